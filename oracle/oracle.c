@@ -1,0 +1,888 @@
+/*
+ * CPU oracle for the eduPIC PIC/MCC time step (arXiv:2103.09642).
+ * TEST INFRASTRUCTURE ONLY -- see oracle.h.
+ *
+ * Each step follows the six-step cycle of section 2.1 in the paper's order:
+ *   1. densities   (eqs. for delta n_p, delta n_{p+1}; Algorithm 2)
+ *   2. rho, Poisson, field (discrete Poisson equation, Thomas algorithm,
+ *      field equations incl. the boundary forms; Algorithm 3)
+ *   3-4. field interpolation and leapfrog push (Algorithm 4)
+ *   5. absorbing walls (Algorithm 5)
+ *   6. Monte Carlo collisions (eq. for P_coll, process selection, COM
+ *      kinematics, Euler-angle rotation; Algorithm 6)
+ * Ions are pushed, wall-checked and collided only on steps with
+ * step % N_SUB == 0 (ion subcycling, section 2.1 and Algorithm 6); between
+ * ion steps the last ion density is kept.
+ *
+ * Readings where the paper is silent or ambiguous are listed with the
+ * code that takes them; they are the same readings the GPU library takes.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Physical constants: CODATA 2018 (the paper does not list its values). */
+static const double E_CHARGE = 1.602176634e-19;   /* C    */
+static const double E_MASS = 9.1093837015e-31;    /* kg   */
+static const double K_BOLTZMANN = 1.380649e-23;  /* J/K  */
+static const double EPSILON0 = 8.8541878128e-12;  /* F/m  */
+static const double AMU = 1.66053906660e-27;      /* kg   */
+#define AR_MASS (39.948 * AMU)
+#define MU_ARAR (AR_MASS / 2.0)                  /* reduced mass Ar+ + Ar */
+#define MU_EAR (E_MASS * AR_MASS / (E_MASS + AR_MASS)) /* reduced mass e + Ar */
+#define EV_TO_J E_CHARGE
+static const double PI_D = 3.14159265358979323846;
+static const double TWO_PI_D = 6.28318530717958647692;
+static const double TWO32 = 4294967296.0; /* fixed-point unit of one particle */
+
+/* Fixed-point scales of the per-step diagnostic sums. */
+static const double DIAG_JS = 1024.0;    /* c * vbar_x          [m/s]  */
+static const double DIAG_WS = 1048576.0; /* c                          */
+static const double DIAG_ES = 1048576.0; /* c * energy          [eV]   */
+
+static char g_err[256];
+const char *orc_error(void) { return g_err; }
+static void set_err(const char *m) { snprintf(g_err, sizeof g_err, "%s", m); }
+
+typedef struct {
+  double *x, *vx, *vy, *vz;
+  uint64_t *uid;
+  int64_t n, cap;
+} parts;
+
+struct orc_sim {
+  orc_case c;
+  int32_t ng, nbins;
+  double L, dx, inv_dx, dt_e, dt_i, dv, factor_w, factor_e, factor_i;
+  double gas_n, sigma_a, de_cs, thr_exc, thr_ion, w_ion;
+  double *sig_el, *sig_exc, *sig_ion, *sig_iso, *sig_back;
+  double *nsig_e, *nsig_i; /* n * sigma_tot, per bin (section 3.2) */
+  parts e, i;
+  int64_t step;
+  int64_t *cnt_e, *cnt_i_cur; /* fixed-point densities of this step     */
+  double *ne, *ni, *rho, *phi, *efield;
+  int64_t counts[ORC_C_N];
+  /* diagnostics */
+  int64_t diag_steps, diag_ion_steps;
+  double *sum_ne, *sum_ni;
+  int64_t *eepf;
+  int64_t *acc_je, *acc_ji, *acc_w, *acc_e; /* per step, fixed point    */
+  double *sum_je, *sum_ji, *sum_w, *sum_e;  /* time sums                */
+};
+
+/* ---------------------------------------------------------------------------
+ * Random numbers.  Philox4x32-10 as defined by Salmon, Moraes, Dror & Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two
+ * 32x32->64 multiplies with the Weyl key schedule.  The paper uses a
+ * sequential Mersenne Twister (section 3.3); a counter-based generator keyed
+ * by (particle id, step) gives every particle its own reproducible stream,
+ * which is what lets a parallel implementation draw the very same numbers.
+ * ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ x1 ^ k0;
+    uint32_t n2 = hi0 ^ x3 ^ k1;
+    x0 = n0;
+    x1 = lo1;
+    x2 = n2;
+    x3 = lo0;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+/* Counter = (uid_lo, uid_hi, step, species<<24 | purpose<<8 | call);
+ * key = (seed_lo, seed_hi).  Each pair of output words gives one uniform in
+ * [0,1) with 53 random bits. */
+void orc_uniform2(uint64_t seed, uint64_t uid, uint32_t step, uint32_t species,
+                  uint32_t purpose, uint32_t call, double out[2]) {
+  uint32_t ctr[4] = {(uint32_t)uid, (uint32_t)(uid >> 32), step,
+                     (species << 24) | (purpose << 8) | call};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  uint64_t a = ((uint64_t)w[0] << 32) | w[1];
+  uint64_t b = ((uint64_t)w[2] << 32) | w[3];
+  out[0] = (double)(a >> 11) * (1.0 / 9007199254740992.0);
+  out[1] = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Two standard normal samples by the Box-Muller transform from two uniforms;
+ * 1-u keeps the logarithm's argument in (0,1]. */
+static void box_muller(const double u[2], double z[2]) {
+  double r = sqrt(-2.0 * log(1.0 - u[0]));
+  z[0] = r * cos(TWO_PI_D * u[1]);
+  z[1] = r * sin(TWO_PI_D * u[1]);
+}
+
+/* Three normals for (uid, step, species, purpose) from calls 1 and 2. */
+static void normals3(uint64_t seed, uint64_t uid, uint32_t step, uint32_t species,
+                     uint32_t purpose, uint32_t first_call, double z[3]) {
+  double u[2], a[2], b[2];
+  orc_uniform2(seed, uid, step, species, purpose, first_call, u);
+  box_muller(u, a);
+  orc_uniform2(seed, uid, step, species, purpose, first_call + 1, u);
+  box_muller(u, b);
+  z[0] = a[0];
+  z[1] = a[1];
+  z[2] = b[0];
+}
+
+/* splitmix64 finaliser (Steele, Lea & Flood, OOPSLA 2014). */
+uint64_t orc_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Identity of a particle born in an ionization at `step`: a hash of the
+ * parent's identity, the step and the kind (1 = ejected electron, 2 = new
+ * ion), so it does not depend on the order in which births happen. */
+uint64_t orc_child_uid(uint64_t parent, int64_t step, uint64_t kind) {
+  return orc_mix64(orc_mix64(parent) ^ ((uint64_t)step * 0x9E3779B97F4A7C15ull) ^ kind);
+}
+
+/* ---------------------------------------------------------------------------
+ * Particle arrays
+ * ------------------------------------------------------------------------- */
+static int parts_reserve(parts *p, int64_t need) {
+  if (need <= p->cap) return 0;
+  int64_t cap = p->cap ? p->cap : 1024;
+  while (cap < need) cap *= 2;
+  double *nx = realloc(p->x, (size_t)cap * sizeof(double));
+  if (!nx) return -1;
+  p->x = nx;
+  double *nvx = realloc(p->vx, (size_t)cap * sizeof(double));
+  if (!nvx) return -1;
+  p->vx = nvx;
+  double *nvy = realloc(p->vy, (size_t)cap * sizeof(double));
+  if (!nvy) return -1;
+  p->vy = nvy;
+  double *nvz = realloc(p->vz, (size_t)cap * sizeof(double));
+  if (!nvz) return -1;
+  p->vz = nvz;
+  uint64_t *nu = realloc(p->uid, (size_t)cap * sizeof(uint64_t));
+  if (!nu) return -1;
+  p->uid = nu;
+  p->cap = cap;
+  return 0;
+}
+
+static void parts_free(parts *p) {
+  free(p->x);
+  free(p->vx);
+  free(p->vy);
+  free(p->vz);
+  free(p->uid);
+  memset(p, 0, sizeof *p);
+}
+
+static void parts_append(parts *p, double x, double vx, double vy, double vz, uint64_t uid) {
+  if (parts_reserve(p, p->n + 1) != 0) {
+    fprintf(stderr, "oracle: out of memory\n");
+    abort();
+  }
+  p->x[p->n] = x;
+  p->vx[p->n] = vx;
+  p->vy[p->n] = vy;
+  p->vz[p->n] = vz;
+  p->uid[p->n] = uid;
+  p->n++;
+}
+
+/* ---------------------------------------------------------------------------
+ * Step 1: charge assignment (eqs. for delta n_p and delta n_{p+1}, Alg. 2).
+ * Each particle carries 2^32 fixed-point units split linearly between the
+ * two nodes that enclose it, so sums are exact integers and independent of
+ * summation order.  p = int(x/dx), clamped to N_g-2 so that x = L puts its
+ * whole weight on the last node.  The split truncates f*2^32 toward zero
+ * (f >= 0) and is capped at 2^32.
+ * ------------------------------------------------------------------------- */
+void orc_deposit(const double *x, int64_t n, int32_t ng, double inv_dx, int64_t *cnt) {
+  for (int64_t k = 0; k < n; ++k) {
+    double c0 = x[k] * inv_dx;
+    int p = (int)c0;
+    if (p > ng - 2) p = ng - 2;
+    double f = c0 - (double)p;
+    int64_t r = (int64_t)(f * TWO32);
+    if (r > (int64_t)4294967296LL) r = (int64_t)4294967296LL;
+    cnt[p] += (int64_t)4294967296LL - r;
+    cnt[p + 1] += r;
+  }
+}
+
+/* Densities on the grid: counts times W/(A dx) / 2^32; the two edge nodes
+ * own half cells, so they are doubled (Algorithm 2). */
+static void density_from_counts(const orc_sim *s, const int64_t *cnt, double *n) {
+  const double scale = s->factor_w / TWO32;
+  for (int p = 0; p < s->ng; ++p) n[p] = (double)cnt[p] * scale;
+  n[0] *= 2.0;
+  n[s->ng - 1] *= 2.0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Step 2: the discrete Poisson equation (-phi_{p-1}+2phi_p-phi_{p+1})/dx^2 =
+ * rho_p/eps0 with phi_0 = V(t), phi_{N_g-1} = 0, solved by the Thomas
+ * algorithm for the constant tridiagonal matrix (Algorithm 3).  With
+ * r_1 = 1/2 and r_p = 1/(2 - r_{p-1}) the forward sweep is
+ * y_p = (d_p + y_{p-1}) r_p and the back substitution phi_p = y_p + r_p phi_{p+1}.
+ * ------------------------------------------------------------------------- */
+void orc_poisson(int32_t ng, double dx, const double *rho, double v_left, double *phi) {
+  const int m = ng - 2; /* interior unknowns 1..m */
+  phi[0] = v_left;
+  phi[ng - 1] = 0.0;
+  if (m <= 0) return;
+  double *r = malloc((size_t)(m + 1) * sizeof(double));
+  double *y = malloc((size_t)(m + 1) * sizeof(double));
+  const double k = dx * dx / EPSILON0;
+  r[1] = 0.5;
+  for (int p = 2; p <= m; ++p) r[p] = 1.0 / (2.0 - r[p - 1]);
+  double prev = 0.0;
+  for (int p = 1; p <= m; ++p) {
+    double d = rho[p] * k;
+    if (p == 1) d = d + v_left;
+    y[p] = (d + prev) * r[p];
+    prev = y[p];
+  }
+  phi[m] = y[m];
+  for (int p = m - 1; p >= 1; --p) phi[p] = y[p] + r[p] * phi[p + 1];
+  free(r);
+  free(y);
+}
+
+/* Field on the grid: centred difference inside, and the boundary forms that
+ * add the half-cell charge (field equations of section 2.1.2). */
+void orc_efield(int32_t ng, double dx, const double *phi, const double *rho, double *efield) {
+  for (int p = 1; p < ng - 1; ++p) efield[p] = (phi[p - 1] - phi[p + 1]) / (2.0 * dx);
+  efield[0] = (phi[0] - phi[1]) / dx - rho[0] * dx / (2.0 * EPSILON0);
+  efield[ng - 1] = (phi[ng - 2] - phi[ng - 1]) / dx + rho[ng - 1] * dx / (2.0 * EPSILON0);
+}
+
+/* Driving voltage at the powered electrode at t_s = step*dt_e: a sum of
+ * harmonics V_k sin(2 pi f_k t + phi_k).  The paper's cosine is phi = pi/2. */
+double orc_voltage(const orc_sim *s, int64_t step) {
+  const double t = (double)step * s->dt_e;
+  double v = 0.0;
+  for (int k = 0; k < s->c.n_harm; ++k)
+    v += s->c.v_amp[k] * sin(TWO_PI_D * s->c.freq_hz[k] * t + s->c.phase_rad[k]);
+  return v;
+}
+
+/* ---------------------------------------------------------------------------
+ * Collisions (section 2.1.6).
+ * ------------------------------------------------------------------------- */
+
+/* Energy bin: min(int(E/DE_CS + 0.5), CS_RANGES-1) (Algorithm 6). */
+static int energy_bin(const orc_sim *s, double energy_ev) {
+  double t = energy_ev / s->de_cs + 0.5;
+  if (t >= (double)(s->nbins - 1)) return s->nbins - 1;
+  return (int)t;
+}
+
+/* v1' = w + m2/(m1+m2) g' R(theta,phi) (cos chi, sin chi cos eta, sin chi sin eta),
+ * with the Euler angles of g taken from its components: cos theta = g_x/g,
+ * sin theta = sqrt(g_y^2+g_z^2)/g, cos phi = g_y/g_yz, sin phi = g_z/g_yz,
+ * and phi = 0 when g points along x.  The three components are written out
+ * as in the final post-collision velocity equation. */
+void orc_scatter(const double g[3], double gmag, double gnew, double f2,
+                 double cos_chi, double sin_chi, double eta, const double w[3],
+                 double out[3]) {
+  double cos_theta, sin_theta, cos_phi, sin_phi;
+  if (gmag > 0.0) {
+    double gyz = sqrt(g[1] * g[1] + g[2] * g[2]);
+    cos_theta = g[0] / gmag;
+    sin_theta = gyz / gmag;
+    if (gyz > 0.0) {
+      cos_phi = g[1] / gyz;
+      sin_phi = g[2] / gyz;
+    } else {
+      cos_phi = 1.0;
+      sin_phi = 0.0;
+    }
+  } else {
+    cos_theta = 1.0;
+    sin_theta = 0.0;
+    cos_phi = 1.0;
+    sin_phi = 0.0;
+  }
+  const double cos_eta = cos(eta), sin_eta = sin(eta);
+  const double a = f2 * gnew;
+  out[0] = w[0] + a * (cos_theta * cos_chi - sin_theta * sin_chi * cos_eta);
+  out[1] = w[1] + a * (sin_theta * cos_phi * cos_chi + cos_theta * cos_phi * sin_chi * cos_eta -
+                       sin_phi * sin_chi * sin_eta);
+  out[2] = w[2] + a * (sin_theta * sin_phi * cos_chi + cos_theta * sin_phi * sin_chi * cos_eta +
+                       cos_phi * sin_chi * sin_eta);
+}
+
+/* e- + Ar with the atom at rest (cold gas): g = v, w = m_e/(m_e+M) v.
+ * Process by partitioning [0,1) as elastic | excitation | ionization.
+ * Elastic: g' = g, cos chi = 1 - 2R, eta = 2 pi R (isotropic).
+ * Excitation: mu g'^2/2 = mu g^2/2 - eps_exc.
+ * Ionization: E' = mu g^2/2 - eps_ion (COM energy), eps_e = w tan[R atan(E'/2w)],
+ * eps_s = E' - eps_e; cos chi_{s,e} = sqrt(eps_{s,e}/E') and eta_e = eta_s + pi;
+ * the ejected electron is scattered like the projectile about the same w.
+ * A negative remaining energy (cannot happen with tables that are zero at
+ * and below threshold) is clamped to zero and reported as an anomaly. */
+int orc_collide_electron(const orc_sim *s, const double v[3], int idx,
+                         double r_proc, double r_chi, double r_eta, double r_share,
+                         double vout[3], double vej[3], int *anomaly) {
+  const double f1 = E_MASS / (E_MASS + AR_MASS);
+  const double f2 = AR_MASS / (E_MASS + AR_MASS);
+  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double g = sqrt(v2);
+  const double w[3] = {f1 * v[0], f1 * v[1], f1 * v[2]};
+  const double s_el = s->sig_el[idx], s_exc = s->sig_exc[idx], s_ion = s->sig_ion[idx];
+  const double st = s_el + s_exc + s_ion;
+  int proc;
+  *anomaly = 0;
+  if (!(st > 0.0) || r_proc < s_el / st)
+    proc = 0;
+  else if (r_proc < (s_el + s_exc) / st)
+    proc = 1;
+  else
+    proc = 2;
+  const double eta = TWO_PI_D * r_eta;
+  if (proc == 0 || proc == 1) {
+    double gnew = g;
+    if (proc == 1) {
+      double ec = 0.5 * MU_EAR * v2 - s->thr_exc * EV_TO_J;
+      if (ec < 0.0) {
+        ec = 0.0;
+        *anomaly = 1;
+      }
+      gnew = sqrt(2.0 * ec / MU_EAR);
+    }
+    const double cos_chi = 1.0 - 2.0 * r_chi;
+    const double sin_chi = sqrt(1.0 - cos_chi * cos_chi);
+    orc_scatter(v, g, gnew, f2, cos_chi, sin_chi, eta, w, vout);
+    return proc;
+  }
+  double e_ev = 0.5 * MU_EAR * v2 / EV_TO_J - s->thr_ion;
+  if (e_ev < 0.0) {
+    e_ev = 0.0;
+    *anomaly = 1;
+  }
+  const double e_ej = s->w_ion * tan(r_share * atan(e_ev / (2.0 * s->w_ion)));
+  const double e_sc = e_ev - e_ej;
+  const double g_sc = sqrt(2.0 * e_sc * EV_TO_J / MU_EAR);
+  const double g_ej = sqrt(2.0 * e_ej * EV_TO_J / MU_EAR);
+  double cs_sc, sn_sc, cs_ej, sn_ej;
+  if (s->c.flags & ORC_IONIZ_ANGLE_LITERAL) {
+    const double chi_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 0.0;
+    const double chi_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 0.0;
+    cs_sc = cos(chi_sc);
+    sn_sc = sin(chi_sc);
+    cs_ej = cos(chi_ej);
+    sn_ej = sin(chi_ej);
+  } else {
+    cs_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 1.0;
+    cs_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 1.0;
+    sn_sc = sqrt(1.0 - cs_sc * cs_sc);
+    sn_ej = sqrt(1.0 - cs_ej * cs_ej);
+  }
+  orc_scatter(v, g, g_sc, f2, cs_sc, sn_sc, eta, w, vout);
+  orc_scatter(v, g, g_ej, f2, cs_ej, sn_ej, eta + PI_D, w, vej);
+  return 2;
+}
+
+/* Ar+ + Ar with a thermal target va: g = v - va, w = (v + va)/2 (equal masses),
+ * isotropic (cos chi = 1 - 2R) or backward (chi = pi) by partitioning [0,1)
+ * as iso | back; |g'| = |g| (elastic). */
+int orc_collide_ion(const orc_sim *s, const double v[3], const double va[3], int idx,
+                    double r_proc, double r_chi, double r_eta, double vout[3]) {
+  const double g3[3] = {v[0] - va[0], v[1] - va[1], v[2] - va[2]};
+  const double g2 = g3[0] * g3[0] + g3[1] * g3[1] + g3[2] * g3[2];
+  const double g = sqrt(g2);
+  const double w[3] = {0.5 * (v[0] + va[0]), 0.5 * (v[1] + va[1]), 0.5 * (v[2] + va[2])};
+  const double s_iso = s->sig_iso[idx], s_back = s->sig_back[idx];
+  double cos_chi, sin_chi;
+  int proc;
+  if (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) {
+    proc = 0;
+    cos_chi = 1.0 - 2.0 * r_chi;
+    sin_chi = sqrt(1.0 - cos_chi * cos_chi);
+  } else {
+    proc = 1;
+    cos_chi = -1.0;
+    sin_chi = 0.0;
+  }
+  orc_scatter(g3, g, g, 0.5, cos_chi, sin_chi, TWO_PI_D * r_eta, w, vout);
+  return proc;
+}
+
+/* ---------------------------------------------------------------------------
+ * Case set-up
+ * ------------------------------------------------------------------------- */
+static double *dup_table(const double *src, int n) {
+  double *d = malloc((size_t)n * sizeof(double));
+  if (d && src) memcpy(d, src, (size_t)n * sizeof(double));
+  if (d && !src) memset(d, 0, (size_t)n * sizeof(double));
+  return d;
+}
+
+orc_sim *orc_new(const orc_case *c, const orc_xsec *xs) {
+  if (!c || !xs) return set_err("null argument"), NULL;
+  if (c->n_grid < 2) return set_err("n_grid must be >= 2"), NULL;
+  if (c->ion_subcycle < 1) return set_err("ion_subcycle must be >= 1"), NULL;
+  if (!(c->dt_e > 0.0)) return set_err("dt_e must be > 0"), NULL;
+  if (!(c->gap_m > 0.0)) return set_err("gap must be > 0"), NULL;
+  if (!(c->area_m2 > 0.0)) return set_err("area must be > 0"), NULL;
+  if (c->n_harm < 0 || c->n_harm > 4) return set_err("n_harm must be 0..4"), NULL;
+  if (xs->n_bins < 1 || !(xs->de_ev > 0.0)) return set_err("bad cross-section table"), NULL;
+  if ((c->flags & ORC_DIAG_EEPF) && (c->n_eepf < 1 || !(c->de_eepf_ev > 0.0)))
+    return set_err("bad EEPF binning"), NULL;
+  orc_sim *s = calloc(1, sizeof *s);
+  if (!s) return set_err("out of memory"), NULL;
+  s->c = *c;
+  s->ng = c->n_grid;
+  s->nbins = xs->n_bins;
+  s->L = c->gap_m;
+  s->dx = s->L / (double)(s->ng - 1);
+  s->inv_dx = 1.0 / s->dx;
+  s->dt_e = c->dt_e;
+  s->dt_i = (double)c->ion_subcycle * c->dt_e;
+  s->dv = c->area_m2 * s->dx;
+  s->factor_w = c->weight / s->dv;
+  s->factor_e = s->dt_e / E_MASS * E_CHARGE;
+  s->factor_i = s->dt_i / AR_MASS * E_CHARGE;
+  s->gas_n = c->pressure_pa / (K_BOLTZMANN * c->gas_temp_k);
+  s->sigma_a = sqrt(K_BOLTZMANN * c->gas_temp_k / AR_MASS);
+  s->de_cs = xs->de_ev;
+  s->thr_exc = xs->e_exc_thr_ev;
+  s->thr_ion = xs->e_ion_thr_ev;
+  s->w_ion = xs->w_ioniz_ev;
+  const int nb = s->nbins, ng = s->ng;
+  s->sig_el = dup_table(xs->e_el, nb);
+  s->sig_exc = dup_table(xs->e_exc, nb);
+  s->sig_ion = dup_table(xs->e_ion, nb);
+  s->sig_iso = dup_table(xs->i_iso, nb);
+  s->sig_back = dup_table(xs->i_back, nb);
+  s->nsig_e = malloc((size_t)nb * sizeof(double));
+  s->nsig_i = malloc((size_t)nb * sizeof(double));
+  /* n sigma_tot per bin (calc_total_cross_sections, section 3.2). */
+  for (int k = 0; k < nb; ++k) {
+    s->nsig_e[k] = s->gas_n * (s->sig_el[k] + s->sig_exc[k] + s->sig_ion[k]);
+    s->nsig_i[k] = s->gas_n * (s->sig_iso[k] + s->sig_back[k]);
+  }
+  s->cnt_e = calloc((size_t)ng, sizeof(int64_t));
+  s->cnt_i_cur = calloc((size_t)ng, sizeof(int64_t));
+  s->ne = calloc((size_t)ng, sizeof(double));
+  s->ni = calloc((size_t)ng, sizeof(double));
+  s->rho = calloc((size_t)ng, sizeof(double));
+  s->phi = calloc((size_t)ng, sizeof(double));
+  s->efield = calloc((size_t)ng, sizeof(double));
+  s->sum_ne = calloc((size_t)ng, sizeof(double));
+  s->sum_ni = calloc((size_t)ng, sizeof(double));
+  s->acc_je = calloc((size_t)ng, sizeof(int64_t));
+  s->acc_ji = calloc((size_t)ng, sizeof(int64_t));
+  s->acc_w = calloc((size_t)ng, sizeof(int64_t));
+  s->acc_e = calloc((size_t)ng, sizeof(int64_t));
+  s->sum_je = calloc((size_t)ng, sizeof(double));
+  s->sum_ji = calloc((size_t)ng, sizeof(double));
+  s->sum_w = calloc((size_t)ng, sizeof(double));
+  s->sum_e = calloc((size_t)ng, sizeof(double));
+  s->eepf = calloc((size_t)(c->n_eepf > 0 ? c->n_eepf : 1), sizeof(int64_t));
+  return s;
+}
+
+void orc_free(orc_sim *s) {
+  if (!s) return;
+  parts_free(&s->e);
+  parts_free(&s->i);
+  double *dbl[] = {s->sig_el, s->sig_exc, s->sig_ion, s->sig_iso, s->sig_back, s->nsig_e,
+                   s->nsig_i, s->ne, s->ni, s->rho, s->phi, s->efield, s->sum_ne, s->sum_ni,
+                   s->sum_je, s->sum_ji, s->sum_w, s->sum_e};
+  for (size_t k = 0; k < sizeof dbl / sizeof dbl[0]; ++k) free(dbl[k]);
+  free(s->cnt_e);
+  free(s->cnt_i_cur);
+  free(s->acc_je);
+  free(s->acc_ji);
+  free(s->acc_w);
+  free(s->acc_e);
+  free(s->eepf);
+  free(s);
+}
+
+static void redeposit_ions(orc_sim *s) {
+  memset(s->cnt_i_cur, 0, (size_t)s->ng * sizeof(int64_t));
+  orc_deposit(s->i.x, s->i.n, s->ng, s->inv_dx, s->cnt_i_cur);
+}
+
+/* Initial particles (Algorithm 1, init): uniform random positions in [0,L)
+ * and, as the workloads ask, Maxwellian velocities (k T_e for electrons, the
+ * ion temperature for Ar+), taken as the half-step velocities v(-dt/2). */
+int orc_seed(orc_sim *s) {
+  const double sig_e = sqrt(s->c.te_init_ev * EV_TO_J / E_MASS);
+  const double sig_i = sqrt(K_BOLTZMANN * s->c.ti_init_k / AR_MASS);
+  parts *sp[2] = {&s->e, &s->i};
+  const int64_t nn[2] = {s->c.n_init_e, s->c.n_init_i};
+  const double sg[2] = {sig_e, sig_i};
+  for (int sp_i = 0; sp_i < 2; ++sp_i) {
+    parts *p = sp[sp_i];
+    p->n = 0;
+    if (parts_reserve(p, nn[sp_i] > 0 ? nn[sp_i] : 1) != 0) return set_err("out of memory"), -1;
+    for (int64_t k = 0; k < nn[sp_i]; ++k) {
+      double u[2], z[3];
+      orc_uniform2(s->c.seed, (uint64_t)k, 0u, (uint32_t)sp_i, 1u, 0u, u);
+      normals3(s->c.seed, (uint64_t)k, 0u, (uint32_t)sp_i, 1u, 1u, z);
+      parts_append(p, s->L * u[0], sg[sp_i] * z[0], sg[sp_i] * z[1], sg[sp_i] * z[2],
+                   (uint64_t)k);
+    }
+  }
+  s->step = 0;
+  redeposit_ions(s);
+  return 0;
+}
+
+int orc_set_state(orc_sim *s, int species, const double *x, const double *vx,
+                  const double *vy, const double *vz, const uint64_t *uid, int64_t n,
+                  int64_t step) {
+  parts *p = species == 0 ? &s->e : &s->i;
+  if (parts_reserve(p, n > 0 ? n : 1) != 0) return set_err("out of memory"), -1;
+  for (int64_t k = 0; k < n; ++k) {
+    p->x[k] = x[k];
+    p->vx[k] = vx[k];
+    p->vy[k] = vy[k];
+    p->vz[k] = vz[k];
+    p->uid[k] = uid[k];
+  }
+  p->n = n;
+  s->step = step;
+  /* Reading: the ion density held until the next ion step is the one of the
+   * ions as given. */
+  if (species == 1) redeposit_ions(s);
+  return 0;
+}
+
+int64_t orc_get_state(const orc_sim *s, int species, double *x, double *vx, double *vy,
+                      double *vz, uint64_t *uid, int64_t cap) {
+  const parts *p = species == 0 ? &s->e : &s->i;
+  int64_t m = p->n < cap ? p->n : cap;
+  for (int64_t k = 0; k < m; ++k) {
+    if (x) x[k] = p->x[k];
+    if (vx) vx[k] = p->vx[k];
+    if (vy) vy[k] = p->vy[k];
+    if (vz) vz[k] = p->vz[k];
+    if (uid) uid[k] = p->uid[k];
+  }
+  return p->n;
+}
+
+/* ---------------------------------------------------------------------------
+ * Steps 3-4: interpolate E to the particle (eq. for E_j) and leapfrog
+ * (eqs. for v(t+dt/2) and x(t+dt)), Algorithm 4.  In measurement mode the
+ * velocity at integer time, the mean of the old and new half-step velocities,
+ * is used with the old position (section 3.6).
+ * ------------------------------------------------------------------------- */
+static void push(orc_sim *s, parts *p, int is_ion) {
+  const int ng = s->ng;
+  const double inv_dx = s->inv_dx, *E = s->efield;
+  const double dt = is_ion ? s->dt_i : s->dt_e;
+  const uint32_t fl = s->c.flags;
+  const double x_lo = 0.45 * s->L, x_hi = 0.55 * s->L;
+  for (int64_t k = 0; k < p->n; ++k) {
+    const double x = p->x[k];
+    const double c0 = x * inv_dx;
+    int q = (int)c0;
+    if (q > ng - 2) q = ng - 2;
+    const double c1 = (double)(q + 1) - c0;
+    const double c2 = c0 - (double)q;
+    const double ex = c1 * E[q] + c2 * E[q + 1];
+    const double vx_old = p->vx[k];
+    double vx_new;
+    if (is_ion)
+      vx_new = vx_old + ex * s->factor_i;
+    else
+      vx_new = vx_old - ex * s->factor_e;
+    p->vx[k] = vx_new;
+    p->x[k] = x + vx_new * dt;
+    if (!(fl & (ORC_DIAG_CURRENT | ORC_DIAG_MEANE | ORC_DIAG_EEPF))) continue;
+    const double vbar = 0.5 * (vx_old + vx_new);
+    if (fl & ORC_DIAG_CURRENT) {
+      int64_t *acc = is_ion ? s->acc_ji : s->acc_je;
+      acc[q] += (int64_t)(c1 * vbar * DIAG_JS);
+      acc[q + 1] += (int64_t)(c2 * vbar * DIAG_JS);
+    }
+    if (is_ion || !(fl & (ORC_DIAG_MEANE | ORC_DIAG_EEPF))) continue;
+    const double vy = p->vy[k], vz = p->vz[k];
+    const double en = 0.5 * E_MASS * (vbar * vbar + vy * vy + vz * vz) / EV_TO_J;
+    if (fl & ORC_DIAG_MEANE) {
+      s->acc_w[q] += (int64_t)(c1 * DIAG_WS);
+      s->acc_w[q + 1] += (int64_t)(c2 * DIAG_WS);
+      s->acc_e[q] += (int64_t)(c1 * en * DIAG_ES);
+      s->acc_e[q + 1] += (int64_t)(c2 * en * DIAG_ES);
+    }
+    if ((fl & ORC_DIAG_EEPF) && x >= x_lo && x <= x_hi) {
+      const double t = en / s->c.de_eepf_ev;
+      if (t < (double)s->c.n_eepf) s->eepf[(int)t]++;
+    }
+  }
+}
+
+/* Step 5: absorbing electrodes; removal by moving the last particle into the
+ * hole (Algorithm 5).  x < 0: powered electrode, x > L: grounded. */
+static void walls(orc_sim *s, parts *p, int is_ion) {
+  int64_t k = 0;
+  while (k < p->n) {
+    const double x = p->x[k];
+    int out = 0;
+    if (x < 0.0) {
+      s->counts[is_ion ? ORC_C_ABS_I_POW : ORC_C_ABS_E_POW]++;
+      out = 1;
+    }
+    if (x > s->L) {
+      s->counts[is_ion ? ORC_C_ABS_I_GND : ORC_C_ABS_E_GND]++;
+      out = 1;
+    }
+    if (out) {
+      const int64_t last = p->n - 1;
+      p->x[k] = p->x[last];
+      p->vx[k] = p->vx[last];
+      p->vy[k] = p->vy[last];
+      p->vz[k] = p->vz[last];
+      p->uid[k] = p->uid[last];
+      p->n--;
+    } else {
+      ++k;
+    }
+  }
+}
+
+/* Step 6 for one electron (Algorithm 6): P = 1 - exp(-n sigma_tot(E) v dt),
+ * collide iff R < P. */
+static void electron_mcc(orc_sim *s, int64_t k) {
+  parts *p = &s->e;
+  const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
+  const double v2 = vx * vx + vy * vy + vz * vz;
+  const double v = sqrt(v2);
+  const double energy = 0.5 * E_MASS * v2 / EV_TO_J;
+  const int idx = energy_bin(s, energy);
+  const double nu = s->nsig_e[idx] * v;
+  const double p_coll = 1.0 - exp(-nu * s->dt_e);
+  const uint64_t uid = p->uid[k];
+  const uint32_t st = (uint32_t)s->step;
+  double r0[2];
+  orc_uniform2(s->c.seed, uid, st, 0u, 0u, 0u, r0);
+  if (!(r0[0] < p_coll)) return;
+  double r1[2], r2[2];
+  orc_uniform2(s->c.seed, uid, st, 0u, 0u, 1u, r1);
+  orc_uniform2(s->c.seed, uid, st, 0u, 0u, 2u, r2);
+  const double vin[3] = {vx, vy, vz};
+  double vout[3], vej[3];
+  int anomaly = 0;
+  const int proc = orc_collide_electron(s, vin, idx, r0[1], r1[0], r1[1], r2[0], vout, vej, &anomaly);
+  p->vx[k] = vout[0];
+  p->vy[k] = vout[1];
+  p->vz[k] = vout[2];
+  s->counts[ORC_C_COLL_E]++;
+  s->counts[ORC_C_ANOMALY] += anomaly;
+  if (proc == 2) {
+    const double x = p->x[k];
+    const uint64_t uid_e = orc_child_uid(uid, s->step, 1);
+    const uint64_t uid_i = orc_child_uid(uid, s->step, 2);
+    parts_append(&s->e, x, vej[0], vej[1], vej[2], uid_e);
+    /* Reading: the new ion takes a thermal velocity of the gas. */
+    double z[3];
+    normals3(s->c.seed, uid_i, st, 1u, 2u, 1u, z);
+    parts_append(&s->i, x, s->sigma_a * z[0], s->sigma_a * z[1], s->sigma_a * z[2], uid_i);
+    s->counts[ORC_C_IONIZ]++;
+  }
+}
+
+/* Step 6 for one ion on an ion step: draw the target from the gas Maxwellian
+ * first, then P from the COM energy mu g^2/2 (Algorithm 6). */
+static void ion_mcc(orc_sim *s, int64_t k) {
+  parts *p = &s->i;
+  const uint64_t uid = p->uid[k];
+  const uint32_t st = (uint32_t)s->step;
+  double z[3];
+  normals3(s->c.seed, uid, st, 1u, 0u, 0u, z);
+  const double va[3] = {s->sigma_a * z[0], s->sigma_a * z[1], s->sigma_a * z[2]};
+  const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
+  const double gx = vx - va[0], gy = vy - va[1], gz = vz - va[2];
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  const double g = sqrt(g2);
+  const double energy = 0.5 * MU_ARAR * g2 / EV_TO_J;
+  const int idx = energy_bin(s, energy);
+  const double nu = s->nsig_i[idx] * g;
+  const double p_coll = 1.0 - exp(-nu * s->dt_i);
+  double r2[2];
+  orc_uniform2(s->c.seed, uid, st, 1u, 0u, 2u, r2);
+  if (!(r2[0] < p_coll)) return;
+  double r3[2];
+  orc_uniform2(s->c.seed, uid, st, 1u, 0u, 3u, r3);
+  const double vin[3] = {vx, vy, vz};
+  double vout[3];
+  orc_collide_ion(s, vin, va, idx, r2[1], r3[0], r3[1], vout);
+  p->vx[k] = vout[0];
+  p->vy[k] = vout[1];
+  p->vz[k] = vout[2];
+  s->counts[ORC_C_COLL_I]++;
+}
+
+static void one_step(orc_sim *s) {
+  const int ng = s->ng;
+  const int ion_step = (s->step % s->c.ion_subcycle) == 0;
+  const uint32_t fl = s->c.flags;
+  /* 1. densities */
+  memset(s->cnt_e, 0, (size_t)ng * sizeof(int64_t));
+  orc_deposit(s->e.x, s->e.n, ng, s->inv_dx, s->cnt_e);
+  if (ion_step) redeposit_ions(s);
+  density_from_counts(s, s->cnt_e, s->ne);
+  density_from_counts(s, s->cnt_i_cur, s->ni);
+  /* 2. charge, potential, field */
+  for (int p = 0; p < ng; ++p) s->rho[p] = E_CHARGE * (s->ni[p] - s->ne[p]);
+  orc_poisson(ng, s->dx, s->rho, orc_voltage(s, s->step), s->phi);
+  orc_efield(ng, s->dx, s->phi, s->rho, s->efield);
+  if (fl & ORC_DIAG_DENSITY)
+    for (int p = 0; p < ng; ++p) {
+      s->sum_ne[p] += s->ne[p];
+      s->sum_ni[p] += s->ni[p];
+    }
+  /* 3-4. push */
+  push(s, &s->e, 0);
+  if (ion_step) push(s, &s->i, 1);
+  /* 5. walls */
+  walls(s, &s->e, 0);
+  if (ion_step) walls(s, &s->i, 1);
+  /* 6. collisions, for the particles present when the loops start (reading:
+   * particles born in this step act from the next step on). */
+  const int64_t ne_loop = s->e.n, ni_loop = s->i.n;
+  for (int64_t k = 0; k < ne_loop; ++k) electron_mcc(s, k);
+  if (ion_step)
+    for (int64_t k = 0; k < ni_loop; ++k) ion_mcc(s, k);
+  /* fold this step's fixed-point diagnostic sums into the time sums */
+  if (fl & ORC_DIAG_CURRENT) {
+    for (int p = 0; p < ng; ++p) {
+      s->sum_je[p] += (double)s->acc_je[p];
+      s->acc_je[p] = 0;
+    }
+    if (ion_step)
+      for (int p = 0; p < ng; ++p) {
+        s->sum_ji[p] += (double)s->acc_ji[p];
+        s->acc_ji[p] = 0;
+      }
+  }
+  if (fl & ORC_DIAG_MEANE)
+    for (int p = 0; p < ng; ++p) {
+      s->sum_w[p] += (double)s->acc_w[p];
+      s->sum_e[p] += (double)s->acc_e[p];
+      s->acc_w[p] = 0;
+      s->acc_e[p] = 0;
+    }
+  s->diag_steps++;
+  if (ion_step) s->diag_ion_steps++;
+  s->step++;
+}
+
+int orc_step(orc_sim *s, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) one_step(s);
+  return 0;
+}
+
+int64_t orc_step_index(const orc_sim *s) { return s->step; }
+
+void orc_counts(const orc_sim *s, int64_t out[ORC_C_N]) {
+  for (int k = 0; k < ORC_C_N; ++k) out[k] = s->counts[k];
+}
+
+void orc_deposit_state(const orc_sim *s, int64_t *cnt_e, int64_t *cnt_i) {
+  memset(cnt_e, 0, (size_t)s->ng * sizeof(int64_t));
+  orc_deposit(s->e.x, s->e.n, s->ng, s->inv_dx, cnt_e);
+  if (s->step % s->c.ion_subcycle == 0) {
+    memset(cnt_i, 0, (size_t)s->ng * sizeof(int64_t));
+    orc_deposit(s->i.x, s->i.n, s->ng, s->inv_dx, cnt_i);
+  } else {
+    memcpy(cnt_i, s->cnt_i_cur, (size_t)s->ng * sizeof(int64_t));
+  }
+}
+
+void orc_fields(const orc_sim *s, double *rho, double *phi, double *efield) {
+  for (int p = 0; p < s->ng; ++p) {
+    if (rho) rho[p] = s->rho[p];
+    if (phi) phi[p] = s->phi[p];
+    if (efield) efield[p] = s->efield[p];
+  }
+}
+
+void orc_read_density(const orc_sim *s, double *ne, double *ni) {
+  const double n = s->diag_steps > 0 ? (double)s->diag_steps : 1.0;
+  for (int p = 0; p < s->ng; ++p) {
+    ne[p] = s->sum_ne[p] / n;
+    ni[p] = s->sum_ni[p] / n;
+  }
+}
+
+/* EEPF normalised so that sum_i f_i sqrt(eps_i) de = 1, eps_i = (i+1/2) de. */
+void orc_read_eepf(const orc_sim *s, double *f, int64_t *counts) {
+  const int nb = s->c.n_eepf;
+  const double de = s->c.de_eepf_ev;
+  double tot = 0.0;
+  for (int k = 0; k < nb; ++k) tot += (double)s->eepf[k];
+  for (int k = 0; k < nb; ++k) {
+    if (counts) counts[k] = s->eepf[k];
+    if (f) f[k] = tot > 0.0 ? (double)s->eepf[k] / (tot * de * sqrt(((double)k + 0.5) * de)) : 0.0;
+  }
+}
+
+/* Current densities j = q n vbar [A/m^2], time averaged (ions over ion steps). */
+void orc_read_currents(const orc_sim *s, double *je, double *ji) {
+  const double ns = s->diag_steps > 0 ? (double)s->diag_steps : 1.0;
+  const double ni = s->diag_ion_steps > 0 ? (double)s->diag_ion_steps : 1.0;
+  for (int p = 0; p < s->ng; ++p) {
+    const double edge = (p == 0 || p == s->ng - 1) ? 2.0 : 1.0;
+    je[p] = edge * (-E_CHARGE * s->factor_w) * (s->sum_je[p] / DIAG_JS) / ns;
+    ji[p] = edge * (E_CHARGE * s->factor_w) * (s->sum_ji[p] / DIAG_JS) / ni;
+  }
+}
+
+void orc_read_mean_energy(const orc_sim *s, double *mee) {
+  for (int p = 0; p < s->ng; ++p)
+    mee[p] = s->sum_w[p] > 0.0 ? (s->sum_e[p] / DIAG_ES) / (s->sum_w[p] / DIAG_WS) : 0.0;
+}
+
+void orc_reset_diag(orc_sim *s) {
+  const size_t ng = (size_t)s->ng;
+  s->diag_steps = 0;
+  s->diag_ion_steps = 0;
+  memset(s->sum_ne, 0, ng * sizeof(double));
+  memset(s->sum_ni, 0, ng * sizeof(double));
+  memset(s->sum_je, 0, ng * sizeof(double));
+  memset(s->sum_ji, 0, ng * sizeof(double));
+  memset(s->sum_w, 0, ng * sizeof(double));
+  memset(s->sum_e, 0, ng * sizeof(double));
+  memset(s->eepf, 0, (size_t)(s->c.n_eepf > 0 ? s->c.n_eepf : 1) * sizeof(int64_t));
+}
+
+void orc_constants(const orc_sim *s, double out[8]) {
+  out[0] = s->dx;
+  out[1] = s->dt_i;
+  out[2] = s->factor_w;
+  out[3] = s->factor_e;
+  out[4] = s->factor_i;
+  out[5] = s->gas_n;
+  out[6] = s->sigma_a;
+  out[7] = orc_voltage(s, 0);
+}
+
+void orc_nsig_tot(const orc_sim *s, double *nsig_e, double *nsig_i) {
+  for (int k = 0; k < s->nbins; ++k) {
+    if (nsig_e) nsig_e[k] = s->nsig_e[k];
+    if (nsig_i) nsig_i[k] = s->nsig_i[k];
+  }
+}

@@ -1,0 +1,132 @@
+"""Pins for the oracle's grid work: charge assignment, Poisson solve, field."""
+import numpy as np
+import pytest
+
+EPS0 = 8.8541878128e-12
+TWO32 = 2**32
+
+
+def test_deposit_conserves_charge_exactly(orc):
+    """Every particle contributes exactly 2^32 fixed-point units."""
+    rng = np.random.default_rng(1)
+    L, ng = 0.025, 400
+    x = rng.uniform(0, L, 100_000)
+    x[:3] = [0.0, L, L / 2]
+    cnt = orc.deposit(x, ng, 1.0 / (L / (ng - 1)))
+    assert cnt.sum() == x.size * TWO32
+    assert np.all(cnt >= 0)
+
+
+def test_deposit_node_and_midpoint_values(orc):
+    """With dx a power of two the cases are exact: a particle on node p puts
+    2^32 on p, one at a cell centre splits 2^31 / 2^31, x = L (clamped index)
+    puts everything on the last node (charge-assignment equations)."""
+    ng = 257
+    inv_dx = 256.0  # L = 1, dx = 1/256
+    for p in (0, 5, 100, 255):
+        c = orc.deposit(np.array([p / 256.0]), ng, inv_dx)
+        assert c[p] == TWO32 and c.sum() == TWO32
+        c = orc.deposit(np.array([(p + 0.5) / 256.0]), ng, inv_dx)
+        assert c[p] == TWO32 // 2 and c[p + 1] == TWO32 // 2
+        c = orc.deposit(np.array([(p + 0.25) / 256.0]), ng, inv_dx)
+        assert c[p] == 3 * TWO32 // 4 and c[p + 1] == TWO32 // 4
+    c = orc.deposit(np.array([1.0]), ng, inv_dx)
+    assert c[ng - 1] == TWO32 and c.sum() == TWO32
+
+
+def test_deposit_matches_floating_point_assignment_within_bound(orc):
+    """The paper's floating-point weights (p+1-x/dx) and (x/dx-p) times 2^32
+    differ from the fixed-point counts by less than one unit per particle."""
+    rng = np.random.default_rng(2)
+    L, ng, n = 0.03, 123, 50_000
+    dx = L / (ng - 1)
+    x = rng.uniform(0, L, n)
+    cnt = orc.deposit(x, ng, 1.0 / dx)
+    c0 = x / dx
+    p = np.minimum(c0.astype(np.int64), ng - 2)
+    ref = np.zeros(ng)
+    np.add.at(ref, p, (p + 1 - c0) * TWO32)
+    np.add.at(ref, p + 1, (c0 - p) * TWO32)
+    per_node = np.bincount(p, minlength=ng) + np.bincount(p + 1, minlength=ng)
+    assert np.all(np.abs(cnt - ref) <= per_node + 1e-6 * np.abs(ref))
+
+
+def test_deposit_order_independent(orc):
+    """Integer sums: any permutation of the particles gives the same bits."""
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 0.02, 20_000)
+    a = orc.deposit(x, 301, 300 / 0.02)
+    b = orc.deposit(rng.permutation(x), 301, 300 / 0.02)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("ng", [3, 4, 17, 400, 1000])
+def test_poisson_uniform_charge_gives_parabola(orc, ng):
+    """Uniform rho with both electrodes at 0 V: the 3-point Laplacian is exact
+    on quadratics, so phi = rho x (L - x) / (2 eps0) at the nodes, and the
+    field (centred and boundary forms) is E = (rho/eps0)(x - L/2) exactly."""
+    L, rho0 = 0.025, 1.3e-4
+    dx = L / (ng - 1)
+    rho = np.full(ng, rho0)
+    phi = orc.poisson(ng, dx, rho, 0.0)
+    xn = np.arange(ng) * dx
+    exact = rho0 * xn * (L - xn) / (2 * EPS0)
+    scale = np.abs(exact).max()
+    assert np.max(np.abs(phi - exact)) <= 1e-12 * scale
+    E = orc.efield(ng, dx, phi, rho)
+    Ex = (rho0 / EPS0) * (xn - L / 2)
+    assert np.max(np.abs(E - Ex)) <= 1e-11 * np.abs(Ex).max()
+
+
+def test_poisson_no_charge_is_linear(orc):
+    """rho = 0: phi falls linearly from V at x=0 to 0 at x=L, E = V/L."""
+    ng, L, V = 400, 0.025, 250.0
+    dx = L / (ng - 1)
+    phi = orc.poisson(ng, dx, np.zeros(ng), V)
+    assert phi[0] == V and phi[-1] == 0.0
+    assert np.max(np.abs(phi - V * (1 - np.arange(ng) / (ng - 1)))) <= 1e-12 * V
+    E = orc.efield(ng, dx, phi, np.zeros(ng))
+    assert np.max(np.abs(E - V / L)) <= 1e-10 * V / L
+
+
+def test_discrete_gauss_law(orc):
+    """E_{N-1} - E_0 = (dx/eps0)[rho_0/2 + sum interior rho + rho_{N-1}/2]:
+    the sum of the discrete Poisson equations telescopes, and the boundary
+    field forms add the half-cell charges."""
+    rng = np.random.default_rng(4)
+    ng, L = 500, 0.025
+    dx = L / (ng - 1)
+    rho = rng.normal(0, 1e-4, ng)
+    phi = orc.poisson(ng, dx, rho, 123.0)
+    E = orc.efield(ng, dx, phi, rho)
+    lhs = E[-1] - E[0]
+    rhs = dx / EPS0 * (rho[0] / 2 + rho[1:-1].sum() + rho[-1] / 2)
+    assert abs(lhs - rhs) <= 1e-9 * (np.abs(E).max())
+
+
+@pytest.mark.parametrize("ng", [3, 5, 12, 60])
+def test_poisson_matches_dense_solve(orc, ng):
+    """Small grids against numpy.linalg.solve of the tridiagonal system."""
+    rng = np.random.default_rng(ng)
+    L, V = 0.02, -37.5
+    dx = L / (ng - 1)
+    rho = rng.normal(0, 2e-4, ng)
+    phi = orc.poisson(ng, dx, rho, V)
+    m = ng - 2
+    A = 2 * np.eye(m) - np.eye(m, k=1) - np.eye(m, k=-1)
+    b = rho[1:-1] * dx * dx / EPS0
+    b[0] += V
+    ref = np.linalg.solve(A, b)
+    assert phi[0] == V and phi[-1] == 0.0
+    assert np.max(np.abs(phi[1:-1] - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_two_node_grid(orc):
+    """N_g = 2: no unknowns; E from the boundary forms only."""
+    dx = 0.01
+    rho = np.array([1e-5, -2e-5])
+    phi = orc.poisson(2, dx, rho, 10.0)
+    assert list(phi) == [10.0, 0.0]
+    E = orc.efield(2, dx, phi, rho)
+    assert E[0] == pytest.approx(10.0 / dx - 1e-5 * dx / (2 * EPS0), rel=1e-15)
+    assert E[1] == pytest.approx(10.0 / dx + -2e-5 * dx / (2 * EPS0), rel=1e-15)

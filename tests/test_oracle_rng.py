@@ -1,0 +1,72 @@
+"""Pins for the oracle's random numbers (counter-based Philox4x32-10)."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "rocrand_philox_ref")
+    subprocess.run([hipcc, "-O1", "--offload-arch=gfx950", os.path.join(HERE, "rocrand_philox_ref.cpp"),
+                    "-o", exe], check=True, capture_output=True)
+    return exe
+
+
+def test_philox_matches_rocrand_library(orc, rocrand_ref):
+    """The oracle's Philox4x32-10 equals rocRAND's ten-round block function
+    (an independent implementation of the SC'11 definition) on random and
+    extreme counters/keys."""
+    rng = np.random.default_rng(7)
+    rows = [[0] * 6, [0xFFFFFFFF] * 6, [1, 0, 0, 0, 0, 0], [0, 0, 0, 0, 1, 0]]
+    rows += rng.integers(0, 2**32, size=(2000, 6), dtype=np.uint64).tolist()
+    inp = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_ref], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = [list(map(int, line.split())) for line in out.strip().splitlines()]
+    assert len(ref) == len(rows)
+    for r, exp in zip(rows, ref):
+        assert orc.philox(r[:4], r[4:]) == exp, r
+
+
+def test_uniforms_are_uniform_and_53_bit(orc):
+    """Uniform draws lie in [0,1), are multiples of 2^-53, and pass a
+    chi-square test on 64 bins over 2e5 draws (both words of a call)."""
+    u = np.array([orc.uniform2(1, uid, 5, 0, 0, 0) for uid in range(100_000)]).ravel()
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert np.all(np.floor(u * 2.0**53) == u * 2.0**53)
+    h, _ = np.histogram(u, bins=64, range=(0, 1))
+    chi2 = ((h - u.size / 64) ** 2 / (u.size / 64)).sum()
+    assert stats.chi2.sf(chi2, 63) > 1e-4
+    # consecutive calls / steps / species are different streams
+    a = orc.uniform2(1, 3, 5, 0, 0, 0)
+    assert not np.array_equal(a, orc.uniform2(1, 3, 5, 0, 0, 1))
+    assert not np.array_equal(a, orc.uniform2(1, 3, 6, 0, 0, 0))
+    assert not np.array_equal(a, orc.uniform2(1, 3, 5, 1, 0, 0))
+    assert not np.array_equal(a, orc.uniform2(2, 3, 5, 0, 0, 0))
+
+
+def test_uniform_word_layout(orc):
+    """u = ((w0<<32 | w1) >> 11) 2^-53 with counter (uid_lo, uid_hi, step,
+    species<<24|purpose<<8|call) and key (seed_lo, seed_hi)."""
+    seed, uid, step, sp, pu, call = 0x123456789ABCDEF0, 0xFEDCBA9876543210, 77, 1, 2, 3
+    w = orc.philox([uid & 0xFFFFFFFF, uid >> 32, step, (sp << 24) | (pu << 8) | call],
+                   [seed & 0xFFFFFFFF, seed >> 32])
+    exp0 = ((w[0] << 32 | w[1]) >> 11) * 2.0**-53
+    exp1 = ((w[2] << 32 | w[3]) >> 11) * 2.0**-53
+    assert list(orc.uniform2(seed, uid, step, sp, pu, call)) == [exp0, exp1]
+
+
+def test_child_uids_distinct(orc):
+    """Identities of newborns are distinct from each other and the parents."""
+    parents = range(20000)
+    kids = {orc.child_uid(p, s, k) for p in parents for s in (0, 1) for k in (1, 2)}
+    assert len(kids) == 4 * len(parents)
+    assert not kids & set(parents)
