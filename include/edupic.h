@@ -1,0 +1,203 @@
+/*
+ * edupic.h -- C ABI of the MI355X (gfx950) PIC/MCC hot path.
+ *
+ * The library advances 1D3V electrostatic particle-in-cell / Monte Carlo
+ * collision simulations of capacitively coupled RF discharges in argon, as
+ * described in Donko et al., "eduPIC: an introductory particle based code for
+ * radio-frequency plasma simulation" (arXiv:2103.09642).  One time step
+ * (section 2.1, the six steps of the PIC/MCC cycle; Algorithms 2-6) is:
+ *   1. charge assignment of electrons (every step) and ions (every N_SUB-th
+ *      step) to the grid  [charge-assignment equations, Algorithm 2],
+ *   2. rho = e (n_i - n_e), the discrete Poisson equation with phi_0 = V(t),
+ *      phi_{N_g-1} = 0 (Thomas algorithm) and the grid field including the
+ *      boundary forms  [Poisson and field equations, Algorithm 3],
+ *   3-4. linear field interpolation and leapfrog push  [Algorithm 4],
+ *   5. absorption at the electrodes  [Algorithm 5],
+ *   6. Monte Carlo collisions: e-Ar elastic / excitation / ionization and
+ *      Ar+-Ar isotropic / backward, probability 1 - exp(-n sigma_tot g dt)
+ *      from tabulated cross sections  [collision equations, Algorithm 6].
+ * Ions are subcycled (pushed and collided every N_SUB-th step with
+ * dt_i = N_SUB dt_e).
+ *
+ * All particle state is FP64 structure-of-arrays in device memory.  Random
+ * numbers come from Philox4x32-10 keyed by (particle id, step), so results do
+ * not depend on particle order or launch shape.  Charge is deposited as int64
+ * fixed point (2^32 units per particle), so densities are bit-reproducible.
+ *
+ * Conventions
+ *  - Every function returns an int status: EDP_OK (0) or a negative EDP_E*
+ *    code; edp_last_error() gives a message (thread-local).  Nothing throws.
+ *  - "host" pointers point to CPU memory owned by the caller and are only
+ *    read or written during the call.  "device" pointers point to GPU memory.
+ *  - A context is bound to one device and one HIP stream; all GPU work it
+ *    issues is asynchronous on that stream unless stated.  Use one context
+ *    per host thread.
+ *  - Arrays indexed by grid node have n_grid entries, node p at x = p dx,
+ *    dx = gap / (n_grid - 1).
+ */
+#ifndef EDUPIC_H
+#define EDUPIC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define EDP_OK 0
+#define EDP_EINVAL (-1)    /* invalid argument or descriptor                 */
+#define EDP_ECAPACITY (-2) /* particle capacity exceeded; case marked failed */
+#define EDP_EUNSTABLE (-3) /* a stability criterion of section 2.2 failed    */
+#define EDP_EHIP (-4)      /* HIP runtime error                              */
+#define EDP_EARENA (-5)    /* device arena too small or misaligned           */
+#define EDP_ESTATE (-6)    /* state does not fit or case has failed          */
+
+/* Case flags (measurement mode of section 3.5 and options). */
+#define EDP_DIAG_DENSITY 1u         /* time-averaged n_e(x), n_i(x)            */
+#define EDP_DIAG_EEPF 2u            /* EEPF in the central 10% of the gap      */
+#define EDP_DIAG_CURRENT 4u         /* time-averaged j_e(x), j_i(x)            */
+#define EDP_DIAG_MEANE 8u           /* time-averaged mean electron energy(x)   */
+#define EDP_IONIZ_ANGLE_LITERAL 16u /* ionization: chi = sqrt(eps/(E-eps_ion)) taken
+                                       as an angle instead of its cosine     */
+#define EDP_ALLOW_UNSTABLE 32u      /* create even if a stability check fails  */
+
+/* Species index. */
+#define EDP_ELECTRONS 0
+#define EDP_IONS 1
+
+/* Execution options for edp_set_option. */
+#define EDP_OPT_MODE 1        /* 0 plain launches, 1 hipGraph chunks, 2 persistent */
+#define EDP_OPT_SORT_EVERY 2  /* steps between compaction + cell sort (>= 1)      */
+#define EDP_OPT_BLOCK 3       /* threads per workgroup of the particle kernels    */
+#define EDP_OPT_PPT 4         /* particles per thread targeted per launch         */
+#define EDP_OPT_PROFILE 5     /* 1: time every particle-kernel launch with events */
+#define EDP_OPT_GRAPH_STEPS 6 /* steps captured per hipGraph (multiple of N_SUB)  */
+#define EDP_OPT_WG_PER_CU 7   /* persistent mode: workgroups per compute unit     */
+
+typedef struct edp_ctx edp_ctx; /* opaque */
+typedef int64_t edp_case;       /* case handle, > 0 */
+
+/* One discharge case: the constants of Table 1 as runtime values. */
+typedef struct {
+  double gap_m;            /* L, electrode gap [m]                              */
+  double pressure_pa;      /* argon pressure [Pa]                               */
+  double gas_temp_k;       /* gas temperature T_g [K]                           */
+  double area_m2;          /* electrode area unit A [m^2] (1e-4 in the paper)   */
+  int32_t n_grid;          /* N_g, 2..4096                                      */
+  int32_t steps_per_cycle; /* steps per RF cycle, the unit of edp_advance       */
+  int32_t ion_subcycle;    /* N_SUB >= 1                                        */
+  int32_t n_harm;          /* waveform harmonics used, 0..4                     */
+  double dt_e;             /* electron time step [s]                            */
+  double v_amp[4];         /* V(t) = sum_k v_amp[k] sin(2 pi freq_hz[k] t +     */
+  double freq_hz[4];       /*        phase_rad[k]) at x = 0; x = L is grounded  */
+  double phase_rad[4];
+  double weight;           /* W, real particles per superparticle               */
+  int64_t n_init_e;        /* superparticles seeded at creation                 */
+  int64_t n_init_i;
+  double te_init_ev;       /* seed electron temperature k T_e [eV]             */
+  double ti_init_k;        /* seed ion temperature [K]                         */
+  int64_t cap_e;           /* particle capacity; 0 = automatic                 */
+  int64_t cap_i;
+  uint64_t seed;           /* random-number key                                 */
+  uint32_t flags;          /* EDP_DIAG_* and option flags                       */
+  int32_t n_eepf;          /* EEPF bins (2000 in section 4.1)                  */
+  double de_eepf_ev;       /* EEPF bin width [eV] (0.05 in section 4.1)         */
+} edp_case_desc;
+
+/* Cross sections tabulated at energies i * de_ev, i = 0..n_bins-1
+ * (section 3.2): electron processes versus LAB energy, Ar+ versus COM
+ * energy, all in m^2.  Host arrays, copied by the call. */
+typedef struct {
+  int32_t n_bins;
+  double de_ev;
+  const double *e_el, *e_exc, *e_ion; /* elastic, excitation, ionization      */
+  const double *i_iso, *i_back;       /* Ar+ isotropic and backward parts      */
+  double e_exc_thr_ev;                /* excitation energy loss [eV]           */
+  double e_ion_thr_ev;                /* ionization energy [eV]                */
+  double w_ioniz_ev;                  /* energy-sharing parameter w [eV]       */
+} edp_xsec;
+
+/* Counters since the case was created (or its state last set). */
+typedef struct {
+  int64_t n_e, n_i;          /* live superparticles                          */
+  int64_t step;              /* global step index s (t = s dt_e)             */
+  int64_t abs_e_pow, abs_e_gnd, abs_i_pow, abs_i_gnd; /* absorbed per wall    */
+  int64_t coll_e, coll_i;    /* collisions                                   */
+  int64_t ioniz;             /* ionizations = electrons born = ions born     */
+  int64_t anomalies;         /* clamped negative post-collision energies     */
+  int64_t dropped;           /* births lost to a full capacity               */
+  int64_t psteps_e;          /* electron pushes done (sum over steps of n_e) */
+  int64_t psteps_i;          /* ion pushes done (sum over ion steps of n_i)  */
+} edp_counts;
+
+/* Create a context on `device` issuing work on `hip_stream` (a hipStream_t,
+ * NULL = the legacy default stream).  *out receives the context. */
+int edp_create(edp_ctx **out, int device, void *hip_stream);
+/* Destroy a context; cases still alive are destroyed (arenas stay the
+ * caller's). */
+int edp_destroy(edp_ctx *ctx);
+/* Set the cross-section tables used by cases created afterwards (section
+ * 3.2; n sigma_tot is formed per case from its gas density). */
+int edp_set_xsec(edp_ctx *ctx, const edp_xsec *xs);
+/* Device bytes a case needs in its arena for the current tables, or a
+ * negative status for an invalid descriptor. */
+int64_t edp_case_bytes(const edp_ctx *ctx, const edp_case_desc *desc);
+/* Create a case inside `dev_arena` (device memory of at least
+ * edp_case_bytes bytes, 256-byte aligned, owned by the caller and kept alive
+ * until edp_case_destroy).  Seeds n_init_e / n_init_i particles at uniform
+ * random positions with Maxwellian velocities (Algorithm 1, init) and
+ * deposits them.  Returns EDP_EUNSTABLE if the time step violates
+ * omega_pe dt < 2 or P_coll < 0.05 at the seed density unless
+ * EDP_ALLOW_UNSTABLE is set (section 2.2). */
+int edp_case_create(edp_ctx *ctx, const edp_case_desc *desc, void *dev_arena,
+                    int64_t arena_bytes, edp_case *out);
+int edp_case_destroy(edp_ctx *ctx, edp_case c);
+/* Advance each listed case by n_cycles[k] RF cycles (steps_per_cycle steps
+ * each).  Asynchronous; cases advance independently (batched in one launch
+ * in persistent mode). */
+int edp_advance(edp_ctx *ctx, const edp_case *cases, int32_t n_cases, const int32_t *n_cycles);
+/* Same with a step count per case. */
+int edp_advance_steps(edp_ctx *ctx, const edp_case *cases, int32_t n_cases,
+                      const int64_t *n_steps);
+/* Wait for the context's stream; returns EDP_ECAPACITY if any case overflowed. */
+int edp_sync(edp_ctx *ctx);
+/* Synchronous reads (they wait for the stream). */
+int edp_read_counts(edp_ctx *ctx, edp_case c, edp_counts *out);
+/* Time-averaged densities [m^-3] (EDP_DIAG_DENSITY); reset != 0 restarts
+ * every diagnostic of the case after the read. */
+int edp_read_density(edp_ctx *ctx, edp_case c, double *ne, double *ni, int32_t n, int32_t reset);
+/* EEPF f(eps) [eV^-3/2] with sum f_i sqrt(eps_i) de = 1, eps_i = (i+1/2) de,
+ * over electrons in [0.45 L, 0.55 L]; counts may be NULL. */
+int edp_read_eepf(edp_ctx *ctx, edp_case c, double *f, int64_t *counts, int32_t n, int32_t reset);
+/* Time-averaged current densities [A m^-2] from the time-centred velocity. */
+int edp_read_currents(edp_ctx *ctx, edp_case c, double *je, double *ji, int32_t n, int32_t reset);
+/* Time-averaged mean electron energy [eV] per node. */
+int edp_read_mean_energy(edp_ctx *ctx, edp_case c, double *mee_ev, int32_t n, int32_t reset);
+/* Fixed-point densities (2^32 per superparticle) the next step will use:
+ * electrons as they are now, ions as held since the last ion step. */
+int edp_read_deposit(edp_ctx *ctx, edp_case c, int64_t *cnt_e, int64_t *cnt_i, int32_t n);
+/* rho [C m^-3], phi [V] and E [V m^-1] of the last completed step. */
+int edp_read_fields(edp_ctx *ctx, edp_case c, double *rho, double *phi, double *efield, int32_t n);
+/* Copy out the live particles of a species (any order) into host arrays of
+ * capacity `cap`; *n_out gets the live count even if it exceeds cap. */
+int edp_get_state(edp_ctx *ctx, edp_case c, int32_t species, double *x, double *vx, double *vy,
+                  double *vz, uint64_t *uid, int64_t cap, int64_t *n_out);
+/* Replace a species' particles from host arrays and set the step index;
+ * velocities are the half-step ones v(t - dt/2).  The species is
+ * redeposited; for ions the deposit also stands until the next ion step.
+ * EDP_ESTATE if n exceeds the capacity. */
+int edp_set_state(edp_ctx *ctx, edp_case c, int32_t species, const double *x, const double *vx,
+                  const double *vy, const double *vz, const uint64_t *uid, int64_t n,
+                  int64_t step);
+/* Execution options (EDP_OPT_*), per context. */
+int edp_set_option(edp_ctx *ctx, int32_t key, int64_t value);
+/* Launch timing when EDP_OPT_PROFILE is on: summed HIP-event milliseconds
+ * and number of launches of the particle kernels (plain and graph modes) or
+ * of the persistent kernel, since the last call (then reset).  Synchronous. */
+int edp_read_profile(edp_ctx *ctx, double *ms, int64_t *launches);
+const char *edp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

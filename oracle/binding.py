@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 DIAG_DENSITY, DIAG_EEPF, DIAG_CURRENT, DIAG_MEANE, IONIZ_LITERAL = 1, 2, 4, 8, 16
 _FLAG_NAMES = {"density": DIAG_DENSITY, "eepf": DIAG_EEPF, "current": DIAG_CURRENT,
-               "meane": DIAG_MEANE, "ioniz_literal": IONIZ_LITERAL}
+               "meane": DIAG_MEANE, "ioniz_literal": IONIZ_LITERAL,
+               "allow_unstable": 0}  # a library option with no effect on the method
 COUNTER_NAMES = ["abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i",
                  "ioniz", "anomaly"]
 

@@ -1,0 +1,937 @@
+// Host runtime and C ABI of the PIC/MCC library (see include/edupic.h).
+//
+// A case lives entirely in a caller-owned device arena: the CaseDev control
+// block, two buffer sets of FP64 structure-of-arrays particles per species,
+// the per-case n*sigma tables, Thomas reciprocals, a ring of V(t_s) values and
+// the grid and diagnostic arrays.  The runtime only computes constants and
+// host-side inputs (V(t), Thomas reciprocals, n*sigma_tot), uploads them and
+// enqueues kernels; every step of the method runs on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "edupic.h"
+#include "impl.hpp"
+
+namespace edp {
+hipError_t launch_field(CaseDev* d, int ng, hipStream_t st);
+hipError_t launch_particles(CaseDev* d, int sp, int blocks, int ng, uint32_t flags, int n_eepf,
+                            hipStream_t st);
+hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
+hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
+                          hipStream_t st);
+hipError_t launch_sort(CaseDev* d, int sp, int ng, int blocks, hipStream_t st);
+hipError_t launch_fold(CaseDev* d, hipStream_t st);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+}  // namespace edp
+
+using namespace edp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return fail(EDP_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Case {
+  edp_case id = 0;
+  edp_case_desc desc{};
+  CaseDev h{};  // host copy of constants and pointers
+  CaseDev* d = nullptr;
+  char* arena = nullptr;
+  int64_t arena_bytes = 0;
+  int64_t step = 0;        // next step to run (host view)
+  int64_t est[2] = {0, 0}; // estimate of the slots in use, for launch sizing
+  int64_t* est_pinned = nullptr;  // async read-back of alloc[]
+  hipEvent_t est_ev = nullptr;
+  bool est_pending = false;
+  double* vstage = nullptr;  // pinned staging of V(t_s)
+  hipEvent_t vev = nullptr;
+  bool vev_pending = false;
+  bool failed = false;
+  // graph mode
+  hipGraphExec_t gexec = nullptr;
+  int g_steps = 0, g_be = 0, g_bi = 0, g_sort = 0;
+};
+
+}  // namespace
+
+struct edp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  // cross sections
+  bool has_xs = false;
+  int nbins = 0;
+  double de = 0, thr_exc = 0, thr_ion = 0, w_ion = 0;
+  std::vector<double> el, exc, ion, iso, back;
+  std::map<edp_case, Case*> cases;
+  edp_case next_id = 1;
+  // options
+  int mode = 0, sort_every = 100, ppt = 4, profile = 0, graph_steps = 0, wg_per_cu = 2;
+  // profiling
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+};
+
+namespace {
+
+struct Layout {
+  size_t off_case, off_part[2][2][5], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
+      off_rho, off_phi, off_ef, off_sum[6], off_acc[4], off_eepf, off_sort, total;
+  int64_t cap[2];
+};
+
+int validate(const edp_case_desc* c) {
+  if (!c) return fail(EDP_EINVAL, "null descriptor");
+  if (c->n_grid < 2 || c->n_grid > 2048) return fail(EDP_EINVAL, "n_grid must be 2..2048");
+  if (c->ion_subcycle < 1) return fail(EDP_EINVAL, "ion_subcycle must be >= 1");
+  if (c->steps_per_cycle < 1) return fail(EDP_EINVAL, "steps_per_cycle must be >= 1");
+  if (!(c->dt_e > 0.0) || !(c->gap_m > 0.0) || !(c->area_m2 > 0.0))
+    return fail(EDP_EINVAL, "dt_e, gap and area must be > 0");
+  if (!(c->gas_temp_k > 0.0) || !(c->pressure_pa >= 0.0) || !(c->weight >= 0.0))
+    return fail(EDP_EINVAL, "bad gas temperature, pressure or weight");
+  if (c->n_harm < 0 || c->n_harm > 4) return fail(EDP_EINVAL, "n_harm must be 0..4");
+  if (c->n_init_e < 0 || c->n_init_i < 0 || c->cap_e < 0 || c->cap_i < 0)
+    return fail(EDP_EINVAL, "negative particle count");
+  if ((c->flags & EDP_DIAG_EEPF) && (c->n_eepf < 1 || c->n_eepf > 4096 || !(c->de_eepf_ev > 0.0)))
+    return fail(EDP_EINVAL, "bad EEPF binning (1..4096 bins)");
+  // particle-kernel LDS: E + deposit (16 B/node), with measurements 24 B/node more
+  if ((c->flags & (EDP_DIAG_EEPF | EDP_DIAG_CURRENT | EDP_DIAG_MEANE)) && c->n_grid > 1024)
+    return fail(EDP_EINVAL, "measurements support n_grid <= 1024");
+  return EDP_OK;
+}
+
+int64_t auto_cap(int64_t n_init, int64_t cap) {
+  int64_t c = cap > 0 ? cap : std::max<int64_t>(2 * n_init, int64_t(1) << 18);
+  return (c + 255) / 256 * 256;
+}
+
+Layout layout(const edp_case_desc* c, int nbins) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  L.off_case = take(sizeof(CaseDev));
+  L.cap[0] = auto_cap(c->n_init_e, c->cap_e);
+  L.cap[1] = auto_cap(c->n_init_i, c->cap_i);
+  for (int sp = 0; sp < 2; ++sp)
+    for (int set = 0; set < 2; ++set)
+      for (int a = 0; a < 5; ++a) L.off_part[sp][set][a] = take((size_t)L.cap[sp] * 8);
+  for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
+  const size_t ng = (size_t)c->n_grid;
+  L.off_rden = take(ng * 8);
+  L.off_volt = take((size_t)kVoltChunk * 8);
+  L.off_cnt_e = take(3 * ng * 8);
+  L.off_cnt_i = take(3 * ng * 8);
+  L.off_rho = take(ng * 8);
+  L.off_phi = take(ng * 8);
+  L.off_ef = take(ng * 8);
+  for (int k = 0; k < 6; ++k) L.off_sum[k] = take(ng * 8);
+  for (int k = 0; k < 4; ++k) L.off_acc[k] = take(3 * ng * 8);
+  L.off_eepf = take((size_t)std::max(1, c->n_eepf) * 8);
+  L.off_sort = take((ng + 1) * 8);
+  L.total = o;
+  return L;
+}
+
+// Driving voltage V(t_s) = sum_k V_k sin(2 pi f_k t_s + phi_k), t_s = s dt_e.
+double voltage(const edp_case_desc& c, int64_t s) {
+  const double t = (double)s * c.dt_e;
+  double v = 0.0;
+  for (int k = 0; k < c.n_harm; ++k)
+    v += c.v_amp[k] * std::sin(kTwoPi * c.freq_hz[k] * t + c.phase_rad[k]);
+  return v;
+}
+
+Case* find(edp_ctx* ctx, edp_case id) {
+  auto it = ctx->cases.find(id);
+  return it == ctx->cases.end() ? nullptr : it->second;
+}
+
+// The dynamic tail of CaseDev (from `step` on) is read and written whole.
+constexpr size_t kDynOff = offsetof(CaseDev, step);
+constexpr size_t kDynBytes = sizeof(CaseDev) - kDynOff;
+
+int read_dyn(edp_ctx* ctx, Case* c, CaseDev& t) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy((char*)&t + kDynOff, (char*)c->d + kDynOff, kDynBytes, hipMemcpyDeviceToHost));
+  return EDP_OK;
+}
+
+int write_dyn(edp_ctx* ctx, Case* c, const CaseDev& t) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy((char*)c->d + kDynOff, (const char*)&t + kDynOff, kDynBytes, hipMemcpyHostToDevice));
+  return EDP_OK;
+}
+
+int blocks_for(const edp_ctx* ctx, int64_t n) {
+  const int64_t per_block = 256 * (int64_t)std::max(1, ctx->ppt);
+  int64_t b = (n + per_block - 1) / per_block;
+  b = std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)ctx->num_cu * 8));
+  return (int)b;
+}
+
+// Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
+int upload_volt(edp_ctx* ctx, Case* c, int64_t s0, int64_t s1) {
+  if (c->vev_pending) {
+    HIPCHK(hipEventSynchronize(c->vev));
+    c->vev_pending = false;
+  }
+  const int64_t n = s1 - s0;
+  for (int64_t k = 0; k < n; ++k) c->vstage[k] = voltage(c->desc, s0 + k);
+  double* ring = const_cast<double*>(c->h.volt);
+  const int64_t a = s0 % kVoltChunk;
+  const int64_t first = std::min<int64_t>(n, kVoltChunk - a);
+  HIPCHK(hipMemcpyAsync(ring + a, c->vstage, first * 8, hipMemcpyHostToDevice, ctx->stream));
+  if (first < n)
+    HIPCHK(hipMemcpyAsync(ring, c->vstage + first, (n - first) * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipEventRecord(c->vev, ctx->stream));
+  c->vev_pending = true;
+  return EDP_OK;
+}
+
+void poll_estimate(Case* c) {
+  if (c->est_pending && hipEventQuery(c->est_ev) == hipSuccess) {
+    c->est[0] = c->est_pinned[0];
+    c->est[1] = c->est_pinned[1];
+    c->est_pending = false;
+  }
+}
+
+int request_estimate(edp_ctx* ctx, Case* c) {
+  if (c->est_pending) return EDP_OK;
+  HIPCHK(hipMemcpyAsync(c->est_pinned, (char*)c->d + offsetof(CaseDev, alloc), 16,
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipEventRecord(c->est_ev, ctx->stream));
+  c->est_pending = true;
+  return EDP_OK;
+}
+
+// One step s, plain launches.
+int enqueue_step(edp_ctx* ctx, Case* c, int64_t s, int be, int bi) {
+  const edp_case_desc& D = c->desc;
+  hipStream_t st = ctx->stream;
+  HIPCHK(launch_field(c->d, D.n_grid, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profile) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+  }
+  HIPCHK(launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st));
+  if (ctx->profile) {
+    HIPCHK(hipEventRecord(e1, st));
+    ctx->ev_pairs.emplace_back(e0, e1);
+  }
+  if (s % D.ion_subcycle == 0) HIPCHK(launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st));
+  // Compaction + cell sort: electrons every sort_every steps, ions every
+  // sort_every ion steps (they move only on ion steps).
+  if ((s + 1) % ctx->sort_every == 0)
+    HIPCHK(launch_sort(c->d, 0, D.n_grid, std::max(1, blocks_for(ctx, c->est[0]) / 4), st));
+  if ((s + 1) % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0)
+    HIPCHK(launch_sort(c->d, 1, D.n_grid, std::max(1, blocks_for(ctx, c->est[1]) / 4), st));
+  return EDP_OK;
+}
+
+int drain_profile(edp_ctx* ctx) {
+  for (auto& pr : ctx->ev_pairs) {
+    float ms = 0.f;
+    HIPCHK(hipEventSynchronize(pr.second));
+    HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+    ctx->prof_ms += ms;
+    ctx->prof_launches += 1;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  ctx->ev_pairs.clear();
+  return EDP_OK;
+}
+
+// Capture graph_steps steps starting at an aligned step into a graph.
+int build_graph(edp_ctx* ctx, Case* c, int steps, int be, int bi, int bsort_e, int bsort_i) {
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  const edp_case_desc& D = c->desc;
+  hipStream_t st = ctx->stream;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < steps; ++k) {
+    (void)launch_field(c->d, D.n_grid, st);
+    (void)launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st);
+    if (k % D.ion_subcycle == 0) (void)launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st);
+    if ((k + 1) % ctx->sort_every == 0) (void)launch_sort(c->d, 0, D.n_grid, bsort_e, st);
+    if ((k + 1) % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0)
+      (void)launch_sort(c->d, 1, D.n_grid, bsort_i, st);
+  }
+  HIPCHK(hipStreamEndCapture(st, &g));
+  hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(EDP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  c->g_steps = steps;
+  c->g_be = be;
+  c->g_bi = bi;
+  return EDP_OK;
+}
+
+int run_steps(edp_ctx* ctx, Case* c, int64_t n) {
+  if (c->failed) return fail(EDP_ESTATE, "case %lld has failed", (long long)c->id);
+  const edp_case_desc& D = c->desc;
+  int64_t s = c->step;
+  const int64_t end = s + n;
+  const int64_t win = 4096;
+  // graph mode: graph length a multiple of N_SUB and of the sort interval
+  int gsteps = 0;
+  if (ctx->mode == 1) {
+    const int64_t base = (int64_t)ctx->sort_every * D.ion_subcycle;
+    gsteps = ctx->graph_steps > 0 ? ctx->graph_steps : (int)std::min<int64_t>(base * std::max<int64_t>(1, 200 / base), 4096);
+    if (gsteps % base != 0) gsteps = (int)((gsteps / base + 1) * base);
+  }
+  while (s < end) {
+    poll_estimate(c);
+    int64_t w_end = std::min(end, s + win);
+    if (gsteps > 0) {
+      // keep windows on graph boundaries where possible
+      const int64_t w = std::max<int64_t>(gsteps, (win / gsteps) * gsteps);
+      w_end = std::min(end, s + w);
+    }
+    int r = upload_volt(ctx, c, s, w_end);
+    if (r) return r;
+    const int be = blocks_for(ctx, c->est[0] + c->est[0] / 8 + 1024);
+    const int bi = blocks_for(ctx, c->est[1] + c->est[1] / 8 + 1024);
+    while (s < w_end) {
+      if (gsteps > 0 && s % gsteps == 0 && s + gsteps <= w_end) {
+        const bool stale = !c->gexec || c->g_steps != gsteps || be > c->g_be * 5 / 4 ||
+                           be < c->g_be * 3 / 4 || bi > c->g_bi * 5 / 4 || bi < c->g_bi * 3 / 4;
+        if (stale) {
+          r = build_graph(ctx, c, gsteps, be, bi, std::max(1, be / 4), std::max(1, bi / 4));
+          if (r) return r;
+        }
+        HIPCHK(hipGraphLaunch(c->gexec, ctx->stream));
+        s += gsteps;
+        continue;
+      }
+      r = enqueue_step(ctx, c, s, be, bi);
+      if (r) return r;
+      ++s;
+    }
+    r = request_estimate(ctx, c);
+    if (r) return r;
+    if (ctx->ev_pairs.size() > 8192) {
+      r = drain_profile(ctx);
+      if (r) return r;
+    }
+  }
+  c->step = end;
+  return EDP_OK;
+}
+
+int deposit_species(edp_ctx* ctx, Case* c, int sp, int64_t step) {
+  const edp_case_desc& D = c->desc;
+  const int ng = D.n_grid;
+  hipStream_t st = ctx->stream;
+  const int blocks = blocks_for(ctx, c->est[sp] + 1);
+  if (sp == 0) {
+    HIPCHK(launch_zero(c->h.cnt_e, 3 * (int64_t)ng * 8, st));
+    HIPCHK(launch_deposit(c->d, 0, c->h.cnt_e + (step % 3) * ng, nullptr, ng, blocks, st));
+  } else {
+    const int64_t k = step / D.ion_subcycle;
+    HIPCHK(launch_zero(c->h.cnt_i, 3 * (int64_t)ng * 8, st));
+    int64_t* second = (step % D.ion_subcycle == 0) ? nullptr : c->h.cnt_i + ((k + 1) % 3) * ng;
+    HIPCHK(launch_deposit(c->d, 1, c->h.cnt_i + (k % 3) * ng, second, ng, blocks, st));
+  }
+  return EDP_OK;
+}
+
+int zero_diag(edp_ctx* ctx, Case* c) {
+  hipStream_t st = ctx->stream;
+  const int64_t ng = c->desc.n_grid;
+  for (double* p : {c->h.sum_ne, c->h.sum_ni, c->h.sum_je, c->h.sum_ji, c->h.sum_w, c->h.sum_e})
+    HIPCHK(launch_zero(p, ng * 8, st));
+  for (int64_t* p : {c->h.acc_je, c->h.acc_ji, c->h.acc_w, c->h.acc_e}) HIPCHK(launch_zero(p, 3 * ng * 8, st));
+  HIPCHK(launch_zero(c->h.eepf, (int64_t)std::max(1, c->desc.n_eepf) * 8, st));
+  return EDP_OK;
+}
+
+int reset_diag(edp_ctx* ctx, Case* c) {
+  int r = zero_diag(ctx, c);
+  if (r) return r;
+  CaseDev t;
+  r = read_dyn(ctx, c, t);
+  if (r) return r;
+  t.diag_steps = 0;
+  t.diag_ion_steps = 0;
+  return write_dyn(ctx, c, t);
+}
+
+// Stability criteria 2 and 3 of section 2.2 at the seed state.
+int stability(const edp_ctx* ctx, const edp_case_desc* D, const std::vector<double>& nsig_e) {
+  if (D->flags & EDP_ALLOW_UNSTABLE) return EDP_OK;
+  const double n_e = D->weight * (double)D->n_init_e / (D->area_m2 * D->gap_m);
+  const double wpe = std::sqrt(n_e * kECharge * kECharge / (kEps0 * kEMass));
+  if (wpe * D->dt_e >= 2.0) return fail(EDP_EUNSTABLE, "omega_pe dt = %g >= 2", wpe * D->dt_e);
+  double pmax = 0.0;
+  for (int k = 0; k < ctx->nbins; ++k) {
+    const double e = k * ctx->de;
+    const double v = std::sqrt(2.0 * e * kEvToJ / kEMass);
+    pmax = std::max(pmax, 1.0 - std::exp(-nsig_e[k] * v * D->dt_e));
+  }
+  if (pmax >= 0.05) return fail(EDP_EUNSTABLE, "max electron collision probability %g >= 0.05", pmax);
+  return EDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* edp_last_error(void) { return g_err.c_str(); }
+
+int edp_create(edp_ctx** out, int device, void* hip_stream) {
+  if (!out) return fail(EDP_EINVAL, "null out");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(EDP_EINVAL, "device %d of %d", device, ndev);
+  HIPCHK(hipSetDevice(device));
+  edp_ctx* ctx = new edp_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+  *out = ctx;
+  return EDP_OK;
+}
+
+int edp_destroy(edp_ctx* ctx) {
+  if (!ctx) return EDP_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->cases) {
+    Case* c = kv.second;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->vstage) (void)hipHostFree(c->vstage);
+    if (c->est_pinned) (void)hipHostFree(c->est_pinned);
+    if (c->vev) (void)hipEventDestroy(c->vev);
+    if (c->est_ev) (void)hipEventDestroy(c->est_ev);
+    delete c;
+  }
+  for (auto& pr : ctx->ev_pairs) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  delete ctx;
+  return EDP_OK;
+}
+
+int edp_set_xsec(edp_ctx* ctx, const edp_xsec* xs) {
+  if (!ctx || !xs) return fail(EDP_EINVAL, "null argument");
+  if (xs->n_bins < 1 || !(xs->de_ev > 0.0)) return fail(EDP_EINVAL, "bad table size");
+  const double* src[5] = {xs->e_el, xs->e_exc, xs->e_ion, xs->i_iso, xs->i_back};
+  std::vector<double>* dst[5] = {&ctx->el, &ctx->exc, &ctx->ion, &ctx->iso, &ctx->back};
+  for (int k = 0; k < 5; ++k) {
+    if (!src[k]) return fail(EDP_EINVAL, "null table");
+    dst[k]->assign(src[k], src[k] + xs->n_bins);
+  }
+  ctx->nbins = xs->n_bins;
+  ctx->de = xs->de_ev;
+  ctx->thr_exc = xs->e_exc_thr_ev;
+  ctx->thr_ion = xs->e_ion_thr_ev;
+  ctx->w_ion = xs->w_ioniz_ev;
+  ctx->has_xs = true;
+  return EDP_OK;
+}
+
+int64_t edp_case_bytes(const edp_ctx* ctx, const edp_case_desc* desc) {
+  if (!ctx || !ctx->has_xs) return fail(EDP_EINVAL, "cross sections not set");
+  int r = validate(desc);
+  if (r) return r;
+  return (int64_t)layout(desc, ctx->nbins).total;
+}
+
+int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, int64_t arena_bytes,
+                    edp_case* out) {
+  if (!ctx || !out) return fail(EDP_EINVAL, "null argument");
+  if (!ctx->has_xs) return fail(EDP_EINVAL, "cross sections not set");
+  int r = validate(desc);
+  if (r) return r;
+  const Layout L = layout(desc, ctx->nbins);
+  if (!dev_arena || arena_bytes < (int64_t)L.total)
+    return fail(EDP_EARENA, "arena needs %lld bytes, got %lld", (long long)L.total, (long long)arena_bytes);
+  if (((uintptr_t)dev_arena) % kAlign) return fail(EDP_EARENA, "arena must be 256-byte aligned");
+  if (desc->n_init_e > L.cap[0] || desc->n_init_i > L.cap[1])
+    return fail(EDP_EINVAL, "initial particles exceed capacity");
+  HIPCHK(hipSetDevice(ctx->device));
+  const edp_case_desc& D = *desc;
+  const int ng = D.n_grid, nb = ctx->nbins;
+  // constants (Table 1 and section 3.1)
+  const double gas_n = D.pressure_pa / (kBoltzmann * D.gas_temp_k);
+  std::vector<double> nsig_e(nb), nsig_i(nb);
+  for (int k = 0; k < nb; ++k) {
+    nsig_e[k] = gas_n * (ctx->el[k] + ctx->exc[k] + ctx->ion[k]);
+    nsig_i[k] = gas_n * (ctx->iso[k] + ctx->back[k]);
+  }
+  r = stability(ctx, desc, nsig_e);
+  if (r) return r;
+  Case* c = new Case();
+  c->desc = D;
+  c->arena = (char*)dev_arena;
+  c->arena_bytes = arena_bytes;
+  c->d = (CaseDev*)(c->arena + L.off_case);
+  CaseDev& h = c->h;
+  std::memset(&h, 0, sizeof h);
+  h.ng = ng;
+  h.nbins = nb;
+  h.nsub = D.ion_subcycle;
+  h.n_eepf = D.n_eepf;
+  h.flags = D.flags;
+  h.L = D.gap_m;
+  h.dx = h.L / (double)(ng - 1);
+  h.inv_dx = 1.0 / h.dx;
+  h.dt_e = D.dt_e;
+  h.dt_i = (double)D.ion_subcycle * D.dt_e;
+  const double dv = D.area_m2 * h.dx;
+  h.factor_w = D.weight / dv;
+  h.factor_e = h.dt_e / kEMass * kECharge;
+  h.factor_i = h.dt_i / kArMass * kECharge;
+  h.sigma_a = std::sqrt(kBoltzmann * D.gas_temp_k / kArMass);
+  h.de_cs = ctx->de;
+  h.thr_exc = ctx->thr_exc;
+  h.thr_ion = ctx->thr_ion;
+  h.w_ion = ctx->w_ion;
+  h.de_eepf = D.de_eepf_ev;
+  h.x_lo = 0.45 * h.L;
+  h.x_hi = 0.55 * h.L;
+  h.dens_scale = h.factor_w / kTwo32;
+  h.kpois = h.dx * h.dx / kEps0;
+  h.seed = D.seed;
+  for (int sp = 0; sp < 2; ++sp) {
+    h.sp[sp].cap = L.cap[sp];
+    for (int set = 0; set < 2; ++set) {
+      h.sp[sp].x[set] = (double*)(c->arena + L.off_part[sp][set][0]);
+      h.sp[sp].vx[set] = (double*)(c->arena + L.off_part[sp][set][1]);
+      h.sp[sp].vy[set] = (double*)(c->arena + L.off_part[sp][set][2]);
+      h.sp[sp].vz[set] = (double*)(c->arena + L.off_part[sp][set][3]);
+      h.sp[sp].uid[set] = (uint64_t*)(c->arena + L.off_part[sp][set][4]);
+    }
+  }
+  double* tabs[7];
+  for (int t = 0; t < 7; ++t) tabs[t] = (double*)(c->arena + L.off_tab[t]);
+  h.nsig_e = tabs[0];
+  h.nsig_i = tabs[1];
+  h.sig_el = tabs[2];
+  h.sig_exc = tabs[3];
+  h.sig_ion = tabs[4];
+  h.sig_iso = tabs[5];
+  h.sig_back = tabs[6];
+  h.rden = (double*)(c->arena + L.off_rden);
+  h.volt = (double*)(c->arena + L.off_volt);
+  h.cnt_e = (int64_t*)(c->arena + L.off_cnt_e);
+  h.cnt_i = (int64_t*)(c->arena + L.off_cnt_i);
+  h.rho = (double*)(c->arena + L.off_rho);
+  h.phi = (double*)(c->arena + L.off_phi);
+  h.efield = (double*)(c->arena + L.off_ef);
+  double** sums[6] = {&h.sum_ne, &h.sum_ni, &h.sum_je, &h.sum_ji, &h.sum_w, &h.sum_e};
+  for (int k = 0; k < 6; ++k) *sums[k] = (double*)(c->arena + L.off_sum[k]);
+  int64_t** accs[4] = {&h.acc_je, &h.acc_ji, &h.acc_w, &h.acc_e};
+  for (int k = 0; k < 4; ++k) *accs[k] = (int64_t*)(c->arena + L.off_acc[k]);
+  h.eepf = (int64_t*)(c->arena + L.off_eepf);
+  h.sort_cnt = (int64_t*)(c->arena + L.off_sort);
+  // dynamic part
+  h.step = 0;
+  h.alloc[0] = D.n_init_e;
+  h.alloc[1] = D.n_init_i;
+  h.n[0] = D.n_init_e;
+  h.n[1] = D.n_init_i;
+  h.ctr[kLiveE] = D.n_init_e;
+  h.ctr[kLiveI] = D.n_init_i;
+  // Thomas reciprocals r_1 = 1/2, r_p = 1/(2 - r_{p-1})
+  std::vector<double> rden(ng, 0.0);
+  if (ng > 2) {
+    rden[1] = 0.5;
+    for (int p = 2; p <= ng - 2; ++p) rden[p] = 1.0 / (2.0 - rden[p - 1]);
+  }
+  hipStream_t st = ctx->stream;
+  auto cleanup = [&](int code) {
+    delete c;
+    return code;
+  };
+  if (hipHostMalloc((void**)&c->vstage, kVoltChunk * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->est_pinned, 16, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->vev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->est_ev, hipEventDisableTiming) != hipSuccess)
+    return cleanup(fail(EDP_EHIP, "host staging allocation failed"));
+  // zero the whole grid/diagnostic/scratch region, then upload
+  const size_t z0 = L.off_cnt_e, z1 = L.total;
+  if (launch_zero(c->arena + z0, (int64_t)(z1 - z0), st) != hipSuccess)
+    return cleanup(fail(EDP_EHIP, "zero fill failed"));
+  const std::vector<double>* tsrc[7] = {&nsig_e, &nsig_i, &ctx->el, &ctx->exc, &ctx->ion, &ctx->iso, &ctx->back};
+  hipError_t e = hipSuccess;
+  for (int t = 0; t < 7 && e == hipSuccess; ++t)
+    e = hipMemcpyAsync(tabs[t], tsrc[t]->data(), (size_t)nb * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)h.rden, rden.data(), (size_t)ng * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d, &h, sizeof(CaseDev), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return cleanup(fail(EDP_EHIP, "upload: %s", hipGetErrorString(e)));
+  c->est[0] = D.n_init_e;
+  c->est[1] = D.n_init_i;
+  // seed (Algorithm 1, init) and deposit
+  const double sig_e = std::sqrt(D.te_init_ev * kEvToJ / kEMass);
+  const double sig_i = std::sqrt(kBoltzmann * D.ti_init_k / kArMass);
+  if (launch_seed(c->d, 0, D.n_init_e, sig_e, st) != hipSuccess ||
+      launch_seed(c->d, 1, D.n_init_i, sig_i, st) != hipSuccess)
+    return cleanup(fail(EDP_EHIP, "seed launch failed"));
+  if ((r = deposit_species(ctx, c, 0, 0)) || (r = deposit_species(ctx, c, 1, 0))) return cleanup(r);
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return cleanup(fail(EDP_EHIP, "seed: %s", hipGetErrorString(e)));
+  c->id = ctx->next_id++;
+  ctx->cases[c->id] = c;
+  *out = c->id;
+  return EDP_OK;
+}
+
+int edp_case_destroy(edp_ctx* ctx, edp_case id) {
+  if (!ctx) return fail(EDP_EINVAL, "null context");
+  Case* c = find(ctx, id);
+  if (!c) return fail(EDP_EINVAL, "unknown case");
+  (void)hipStreamSynchronize(ctx->stream);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  (void)hipHostFree(c->vstage);
+  (void)hipHostFree(c->est_pinned);
+  (void)hipEventDestroy(c->vev);
+  (void)hipEventDestroy(c->est_ev);
+  ctx->cases.erase(id);
+  delete c;
+  return EDP_OK;
+}
+
+int edp_advance_steps(edp_ctx* ctx, const edp_case* cases, int32_t n_cases, const int64_t* n_steps) {
+  if (!ctx || (n_cases > 0 && (!cases || !n_steps))) return fail(EDP_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  for (int32_t k = 0; k < n_cases; ++k) {
+    Case* c = find(ctx, cases[k]);
+    if (!c) return fail(EDP_EINVAL, "unknown case %lld", (long long)cases[k]);
+    if (n_steps[k] < 0) return fail(EDP_EINVAL, "negative step count");
+  }
+  for (int32_t k = 0; k < n_cases; ++k) {
+    const int r = run_steps(ctx, find(ctx, cases[k]), n_steps[k]);
+    if (r) return r;
+  }
+  return EDP_OK;
+}
+
+int edp_advance(edp_ctx* ctx, const edp_case* cases, int32_t n_cases, const int32_t* n_cycles) {
+  if (!ctx || (n_cases > 0 && (!cases || !n_cycles))) return fail(EDP_EINVAL, "null argument");
+  std::vector<int64_t> steps(n_cases);
+  for (int32_t k = 0; k < n_cases; ++k) {
+    Case* c = find(ctx, cases[k]);
+    if (!c) return fail(EDP_EINVAL, "unknown case %lld", (long long)cases[k]);
+    if (n_cycles[k] < 0) return fail(EDP_EINVAL, "negative cycle count");
+    steps[k] = (int64_t)n_cycles[k] * c->desc.steps_per_cycle;
+  }
+  return edp_advance_steps(ctx, cases, n_cases, steps.data());
+}
+
+int edp_sync(edp_ctx* ctx) {
+  if (!ctx) return fail(EDP_EINVAL, "null context");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  int status = EDP_OK;
+  for (auto& kv : ctx->cases) {
+    Case* c = kv.second;
+    int32_t err = 0;
+    HIPCHK(hipMemcpy(&err, (char*)c->d + offsetof(CaseDev, error), 4, hipMemcpyDeviceToHost));
+    if (err) {
+      c->failed = true;
+      status = fail(EDP_ECAPACITY, "case %lld exceeded its particle capacity", (long long)c->id);
+    }
+  }
+  return status;
+}
+
+int edp_read_counts(edp_ctx* ctx, edp_case id, edp_counts* out) {
+  if (!ctx || !out) return fail(EDP_EINVAL, "null argument");
+  Case* c = find(ctx, id);
+  if (!c) return fail(EDP_EINVAL, "unknown case");
+  CaseDev t;
+  int r = read_dyn(ctx, c, t);
+  if (r) return r;
+  out->n_e = t.ctr[kLiveE];
+  out->n_i = t.ctr[kLiveI];
+  out->step = t.step;
+  out->abs_e_pow = t.ctr[kAbsEPow];
+  out->abs_e_gnd = t.ctr[kAbsEGnd];
+  out->abs_i_pow = t.ctr[kAbsIPow];
+  out->abs_i_gnd = t.ctr[kAbsIGnd];
+  out->coll_e = t.ctr[kCollE];
+  out->coll_i = t.ctr[kCollI];
+  out->ioniz = t.ctr[kIoniz];
+  out->anomalies = t.ctr[kAnomaly];
+  out->dropped = t.ctr[kDropped];
+  out->psteps_e = t.ctr[kPstepE];
+  out->psteps_i = t.ctr[kPstepI];
+  return EDP_OK;
+}
+
+static int read_grid(edp_ctx* ctx, Case* c, const void* dev, void* host, size_t bytes) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(host, dev, bytes, hipMemcpyDeviceToHost));
+  return EDP_OK;
+}
+
+int edp_read_density(edp_ctx* ctx, edp_case id, double* ne, double* ni, int32_t n, int32_t reset) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || !ne || !ni) return fail(EDP_EINVAL, "bad argument");
+  const int ng = c->desc.n_grid;
+  if (n < ng) return fail(EDP_EINVAL, "output shorter than n_grid");
+  CaseDev t;
+  int r = read_dyn(ctx, c, t);
+  if (r) return r;
+  std::vector<double> a(ng), b(ng);
+  if ((r = read_grid(ctx, c, c->h.sum_ne, a.data(), ng * 8)) || (r = read_grid(ctx, c, c->h.sum_ni, b.data(), ng * 8)))
+    return r;
+  const double steps = t.diag_steps > 0 ? (double)t.diag_steps : 1.0;
+  for (int p = 0; p < ng; ++p) {
+    ne[p] = a[p] / steps;
+    ni[p] = b[p] / steps;
+  }
+  return reset ? reset_diag(ctx, c) : EDP_OK;
+}
+
+int edp_read_eepf(edp_ctx* ctx, edp_case id, double* f, int64_t* counts, int32_t n, int32_t reset) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c) return fail(EDP_EINVAL, "bad argument");
+  const int nb = c->desc.n_eepf;
+  if (n < nb) return fail(EDP_EINVAL, "output shorter than n_eepf");
+  std::vector<int64_t> h(nb);
+  int r = read_grid(ctx, c, c->h.eepf, h.data(), (size_t)nb * 8);
+  if (r) return r;
+  const double de = c->desc.de_eepf_ev;
+  double tot = 0.0;
+  for (int k = 0; k < nb; ++k) tot += (double)h[k];
+  for (int k = 0; k < nb; ++k) {
+    if (counts) counts[k] = h[k];
+    if (f) f[k] = tot > 0.0 ? (double)h[k] / (tot * de * std::sqrt(((double)k + 0.5) * de)) : 0.0;
+  }
+  return reset ? reset_diag(ctx, c) : EDP_OK;
+}
+
+int edp_read_currents(edp_ctx* ctx, edp_case id, double* je, double* ji, int32_t n, int32_t reset) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || !je || !ji) return fail(EDP_EINVAL, "bad argument");
+  const int ng = c->desc.n_grid;
+  if (n < ng) return fail(EDP_EINVAL, "output shorter than n_grid");
+  HIPCHK(launch_fold(c->d, ctx->stream));
+  CaseDev t;
+  int r = read_dyn(ctx, c, t);
+  if (r) return r;
+  std::vector<double> a(ng), b(ng);
+  if ((r = read_grid(ctx, c, c->h.sum_je, a.data(), ng * 8)) || (r = read_grid(ctx, c, c->h.sum_ji, b.data(), ng * 8)))
+    return r;
+  const double ns = t.diag_steps > 0 ? (double)t.diag_steps : 1.0;
+  const double ni = t.diag_ion_steps > 0 ? (double)t.diag_ion_steps : 1.0;
+  for (int p = 0; p < ng; ++p) {
+    const double edge = (p == 0 || p == ng - 1) ? 2.0 : 1.0;
+    je[p] = edge * (-kECharge * c->h.factor_w) * (a[p] / kDiagJS) / ns;
+    ji[p] = edge * (kECharge * c->h.factor_w) * (b[p] / kDiagJS) / ni;
+  }
+  return reset ? reset_diag(ctx, c) : EDP_OK;
+}
+
+int edp_read_mean_energy(edp_ctx* ctx, edp_case id, double* mee, int32_t n, int32_t reset) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || !mee) return fail(EDP_EINVAL, "bad argument");
+  const int ng = c->desc.n_grid;
+  if (n < ng) return fail(EDP_EINVAL, "output shorter than n_grid");
+  HIPCHK(launch_fold(c->d, ctx->stream));
+  std::vector<double> w(ng), e(ng);
+  int r;
+  if ((r = read_grid(ctx, c, c->h.sum_w, w.data(), ng * 8)) || (r = read_grid(ctx, c, c->h.sum_e, e.data(), ng * 8)))
+    return r;
+  for (int p = 0; p < ng; ++p) mee[p] = w[p] > 0.0 ? (e[p] / kDiagES) / (w[p] / kDiagWS) : 0.0;
+  return reset ? reset_diag(ctx, c) : EDP_OK;
+}
+
+int edp_read_deposit(edp_ctx* ctx, edp_case id, int64_t* cnt_e, int64_t* cnt_i, int32_t n) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || !cnt_e || !cnt_i) return fail(EDP_EINVAL, "bad argument");
+  const int ng = c->desc.n_grid;
+  if (n < ng) return fail(EDP_EINVAL, "output shorter than n_grid");
+  CaseDev t;
+  int r = read_dyn(ctx, c, t);
+  if (r) return r;
+  const int64_t s = t.step, k = s / c->desc.ion_subcycle;
+  if ((r = read_grid(ctx, c, c->h.cnt_e + (s % 3) * ng, cnt_e, ng * 8))) return r;
+  return read_grid(ctx, c, c->h.cnt_i + (k % 3) * ng, cnt_i, ng * 8);
+}
+
+int edp_read_fields(edp_ctx* ctx, edp_case id, double* rho, double* phi, double* ef, int32_t n) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c) return fail(EDP_EINVAL, "bad argument");
+  const int ng = c->desc.n_grid;
+  if (n < ng) return fail(EDP_EINVAL, "output shorter than n_grid");
+  int r;
+  if (rho && (r = read_grid(ctx, c, c->h.rho, rho, ng * 8))) return r;
+  if (phi && (r = read_grid(ctx, c, c->h.phi, phi, ng * 8))) return r;
+  if (ef && (r = read_grid(ctx, c, c->h.efield, ef, ng * 8))) return r;
+  return EDP_OK;
+}
+
+int edp_get_state(edp_ctx* ctx, edp_case id, int32_t species, double* x, double* vx, double* vy,
+                  double* vz, uint64_t* uid, int64_t cap, int64_t* n_out) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || (species != 0 && species != 1) || cap < 0) return fail(EDP_EINVAL, "bad argument");
+  CaseDev t;
+  int r = read_dyn(ctx, c, t);
+  if (r) return r;
+  const int64_t n = t.alloc[species] < c->h.sp[species].cap ? t.alloc[species] : c->h.sp[species].cap;
+  const int set = t.cur[species];
+  const SpeciesDev& S = c->h.sp[species];
+  std::vector<double> hx(n), hvx(n), hvy(n), hvz(n);
+  std::vector<uint64_t> hu(n);
+  if (n > 0) {
+    HIPCHK(hipMemcpy(hx.data(), S.x[set], n * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hvx.data(), S.vx[set], n * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hvy.data(), S.vy[set], n * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hvz.data(), S.vz[set], n * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hu.data(), S.uid[set], n * 8, hipMemcpyDeviceToHost));
+  }
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(hx[i] == hx[i])) continue;
+    if (m < cap) {
+      if (x) x[m] = hx[i];
+      if (vx) vx[m] = hvx[i];
+      if (vy) vy[m] = hvy[i];
+      if (vz) vz[m] = hvz[i];
+      if (uid) uid[m] = hu[i];
+    }
+    ++m;
+  }
+  if (n_out) *n_out = m;
+  return EDP_OK;
+}
+
+int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, const double* vx,
+                  const double* vy, const double* vz, const uint64_t* uid, int64_t n, int64_t step) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || (species != 0 && species != 1) || n < 0 || step < 0) return fail(EDP_EINVAL, "bad argument");
+  if (n > 0 && (!x || !vx || !vy || !vz || !uid)) return fail(EDP_EINVAL, "null array");
+  const SpeciesDev& S = c->h.sp[species];
+  if (n > S.cap) return fail(EDP_ESTATE, "%lld particles exceed capacity %lld", (long long)n, (long long)S.cap);
+  // the kernels rely on every live particle being inside [0, L] with finite
+  // velocity components
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(x[i] >= 0.0 && x[i] <= c->h.L))
+      return fail(EDP_EINVAL, "particle %lld at x = %g is outside [0, L]", (long long)i, x[i]);
+    if (!std::isfinite(vx[i]) || !std::isfinite(vy[i]) || !std::isfinite(vz[i]))
+      return fail(EDP_EINVAL, "particle %lld has a non-finite velocity", (long long)i);
+  }
+  CaseDev t;
+  int r = read_dyn(ctx, c, t);
+  if (r) return r;
+  if (n > 0) {
+    HIPCHK(hipMemcpy(S.x[0], x, n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.vx[0], vx, n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.vy[0], vy, n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.vz[0], vz, n * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.uid[0], uid, n * 8, hipMemcpyHostToDevice));
+  }
+  t.step = step;
+  t.cur[species] = 0;
+  t.alloc[species] = n;
+  t.n[species] = n;
+  const int64_t live_other = t.ctr[species == 0 ? kLiveI : kLiveE];
+  for (int k = 0; k < kNumCtr; ++k) t.ctr[k] = 0;
+  t.ctr[species == 0 ? kLiveE : kLiveI] = n;
+  t.ctr[species == 0 ? kLiveI : kLiveE] = live_other;
+  t.error = 0;
+  t.diag_steps = 0;
+  t.diag_ion_steps = 0;
+  if ((r = write_dyn(ctx, c, t))) return r;
+  c->step = step;
+  c->est[species] = n;
+  c->failed = false;
+  if ((r = zero_diag(ctx, c))) return r;
+  if ((r = deposit_species(ctx, c, species, step))) return r;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return EDP_OK;
+}
+
+int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
+  if (!ctx) return fail(EDP_EINVAL, "null context");
+  switch (key) {
+    case EDP_OPT_MODE:
+      if (value < 0 || value > 1) return fail(EDP_EINVAL, "mode must be 0 or 1");
+      ctx->mode = (int)value;
+      break;
+    case EDP_OPT_SORT_EVERY:
+      if (value < 1) return fail(EDP_EINVAL, "sort interval must be >= 1");
+      ctx->sort_every = (int)value;
+      break;
+    case EDP_OPT_BLOCK:
+      if (value != 256) return fail(EDP_EINVAL, "block size must be 256");
+      break;
+    case EDP_OPT_PPT:
+      if (value < 1 || value > 1024) return fail(EDP_EINVAL, "ppt must be 1..1024");
+      ctx->ppt = (int)value;
+      break;
+    case EDP_OPT_PROFILE:
+      ctx->profile = value ? 1 : 0;
+      break;
+    case EDP_OPT_GRAPH_STEPS:
+      if (value < 0) return fail(EDP_EINVAL, "graph steps must be >= 0");
+      ctx->graph_steps = (int)value;
+      for (auto& kv : ctx->cases) kv.second->g_steps = 0;
+      break;
+    case EDP_OPT_WG_PER_CU:
+      if (value < 1 || value > 16) return fail(EDP_EINVAL, "workgroups per CU must be 1..16");
+      ctx->wg_per_cu = (int)value;
+      break;
+    default:
+      return fail(EDP_EINVAL, "unknown option %d", key);
+  }
+  return EDP_OK;
+}
+
+int edp_read_profile(edp_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx) return fail(EDP_EINVAL, "null context");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  int r = drain_profile(ctx);
+  if (r) return r;
+  if (ms) *ms = ctx->prof_ms;
+  if (launches) *launches = ctx->prof_launches;
+  ctx->prof_ms = 0.0;
+  ctx->prof_launches = 0;
+  return EDP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal layout shared by the HIP kernels and the host runtime of the
+// library.  One CaseDev block per discharge case lives in the case's device
+// arena; kernels take a pointer to it and read every constant, array pointer
+// and dynamic counter from there, so launch arguments never change and whole
+// step sequences can be captured into a hipGraph or run by one persistent
+// launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace edp {
+
+// Physical constants: CODATA 2018 (the paper does not list its values).
+constexpr double kECharge = 1.602176634e-19;  // C
+constexpr double kEMass = 9.1093837015e-31;   // kg
+constexpr double kBoltzmann = 1.380649e-23;   // J/K
+constexpr double kEps0 = 8.8541878128e-12;    // F/m
+constexpr double kAmu = 1.66053906660e-27;    // kg
+constexpr double kArMass = 39.948 * kAmu;
+constexpr double kMuArAr = kArMass / 2.0;                          // Ar+ + Ar
+constexpr double kMuEAr = kEMass * kArMass / (kEMass + kArMass);   // e + Ar
+constexpr double kEvToJ = kECharge;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+constexpr double kTwo32 = 4294967296.0;
+
+// Fixed-point scales of the per-step diagnostic sums.
+constexpr double kDiagJS = 1024.0;     // c * vbar_x [m/s]
+constexpr double kDiagWS = 1048576.0;  // c
+constexpr double kDiagES = 1048576.0;  // c * energy [eV]
+
+constexpr int kMaxGrid = 4096;
+constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
+
+// Flags (same values as EDP_* in edupic.h).
+constexpr uint32_t kDiagDensity = 1u, kDiagEepf = 2u, kDiagCurrent = 4u, kDiagMeanE = 8u,
+                   kIonizLiteral = 16u;
+constexpr uint32_t kDiagParticle = kDiagEepf | kDiagCurrent | kDiagMeanE;
+
+// Dynamic counters (int64 slots of CaseDev::ctr).
+enum Ctr {
+  kAbsEPow = 0, kAbsEGnd, kAbsIPow, kAbsIGnd, kCollE, kCollI, kIoniz, kAnomaly, kDropped,
+  kLiveE, kLiveI, kPstepE, kPstepI, kNumCtr
+};
+
+struct SpeciesDev {
+  double *x[2], *vx[2], *vy[2], *vz[2];  // two buffer sets: current and sort target
+  uint64_t *uid[2];
+  int64_t cap;
+};
+
+struct CaseDev {
+  // ---- constants -------------------------------------------------------
+  int32_t ng, nbins, nsub, n_eepf;
+  uint32_t flags;
+  int32_t pad0;
+  double L, dx, inv_dx, dt_e, dt_i, factor_w, factor_e, factor_i;
+  double sigma_a, de_cs, thr_exc, thr_ion, w_ion, de_eepf, x_lo, x_hi;
+  double dens_scale;  // factor_w / 2^32
+  double kpois;       // dx*dx/eps0
+  uint64_t seed;
+  SpeciesDev sp[2];
+  const double *nsig_e, *nsig_i, *sig_el, *sig_exc, *sig_ion, *sig_iso, *sig_back;
+  const double *rden;   // Thomas reciprocals r_p, p = 0..ng-1 (r_0 unused)
+  const double *volt;   // V(t_s) at volt[s % kVoltChunk]
+  int64_t *cnt_e;       // [3][ng] electron deposit, ring by step % 3
+  int64_t *cnt_i;       // [3][ng] ion deposit, ring by (step / nsub) % 3
+  double *rho, *phi, *efield;
+  double *sum_ne, *sum_ni, *sum_je, *sum_ji, *sum_w, *sum_e;  // [ng] time sums
+  int64_t *acc_je, *acc_ji, *acc_w, *acc_e;                   // [3][ng] per step
+  int64_t *eepf;                                              // [n_eepf]
+  int64_t *sort_cnt;                                          // [ng + 1] scratch
+  // ---- dynamic (device-mutated) -----------------------------------------
+  int64_t step;
+  int64_t n[2];       // slots processed this step (snapshot of alloc at step start)
+  int64_t alloc[2];   // slots in use: live + tombstones + births
+  int32_t cur[2];     // current buffer set per species
+  int64_t diag_steps, diag_ion_steps;
+  int64_t ctr[kNumCtr];
+  int32_t error;      // 1: capacity overflow
+  int32_t pad1;
+};
+
+}  // namespace edp

@@ -1,0 +1,226 @@
+"""GPU path against the CPU oracle, through the C ABI.
+
+Bar: integer work (deposits, counters, identities) bit-exact; FP64 particle
+state within 1e-12 relative after one step from an identical state (the push
+is bit-identical by construction; collided particles differ only through
+libm-vs-device ulps of exp/log/sin/cos/tan/atan)."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import by_uid, compare_states, gpu_context, make_pair, say, set_both
+from paper_2103_09642_amd.workloads import base_case, random_state, synthetic_xsec, zero_xsec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(xs_default):
+    c = gpu_context()
+    c.set_xsec(xs_default)
+    return c
+
+
+def _case(**kw):
+    kw.setdefault("n_init_e", 0)
+    kw.setdefault("n_init_i", 0)
+    kw.setdefault("flags", ["allow_unstable"])
+    return base_case(**kw)
+
+
+def test_seed_matches_oracle(ctx, xs_default, orc):
+    """Seeding draws from Philox: positions x = L u are bit-exact, so the
+    device Philox equals the oracle's; velocities agree to libm ulps."""
+    say("test_seed_matches_oracle")
+    c = base_case(n_init_e=50_000, n_init_i=30_000, weight=1.0)
+    g, o = make_pair(ctx, c, xs_default, orc)
+    o.seed()
+    for sp in (0, 1):
+        a, b = by_uid(g.get_state(sp)), by_uid(o.get_state(sp))
+        assert np.array_equal(a["uid"], b["uid"])
+        assert np.array_equal(a["x"], b["x"])
+        compare_states(a, b, 1e-13, f"seed sp{sp}")
+    ge, gi = g.deposit()
+    oe, oi = o.deposit()
+    assert np.array_equal(ge, oe) and np.array_equal(gi, oi)
+    g.destroy()
+
+
+@pytest.mark.parametrize("ng,nsub,n", [(400, 20, 30_000), (17, 3, 5_000), (1000, 1, 60_000), (2, 5, 2_000)])
+def test_deposit_bit_exact(ctx, xs_default, orc, ng, nsub, n):
+    """Fixed-point densities of an identical state are bit-identical,
+    including particles on nodes, at x = 0 and x = L."""
+    say(f"test_deposit_bit_exact ng={ng} nsub={nsub} n={n}")
+    c = _case(n_grid=ng, ion_subcycle=nsub, cap_e=n + 4096, cap_i=n + 4096)
+    g, o = make_pair(ctx, c, xs_default, orc)
+    st = random_state(n, n // 2, c["gap_m"], seed=ng + n)
+    for step in (0, 7):
+        set_both(g, o, st, step)
+        ge, gi = g.deposit()
+        oe, oi = o.deposit()
+        assert np.array_equal(ge, oe)
+        assert np.array_equal(gi, oi)
+        assert ge.sum() == n * 2**32 and gi.sum() == (n // 2) * 2**32
+    g.destroy()
+
+
+def _one_step(ctx, xs, orc, c, st, step, nsteps=1):
+    g, o = make_pair(ctx, c, xs, orc)
+    set_both(g, o, st, step)
+    g.advance_steps(nsteps)
+    o.step(nsteps)
+    return g, o
+
+
+@pytest.mark.parametrize("step", [0, 5])
+def test_one_step_parity(ctx, xs_default, orc, step):
+    """One full step (ion step and electron-only step) from an identical
+    state with hot electrons, high pressure (many collisions incl.
+    ionization) and particles at/near both walls."""
+    say(f"test_one_step_parity step={step}")
+    c = _case(pressure_pa=50.0, weight=2e5, n_grid=400, ion_subcycle=5, cap_e=200_000, cap_i=200_000)
+    st = random_state(60_000, 50_000, c["gap_m"], seed=11 + step, te_ev=4.0, hot_frac=0.3, hot_ev=90.0,
+                      ion_energy_ev=30.0)
+    g, o = _one_step(ctx, xs_default, orc, c, st, step)
+    rg, pg, eg = g.fields()
+    ro, po, eo = o.fields()
+    assert np.array_equal(rg, ro), "rho"
+    assert np.array_equal(pg, po), "phi (Thomas, same operation order)"
+    assert np.array_equal(eg, eo), "E"
+    cg, co = g.counts(), o.counts()
+    for k in ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz", "anomaly"):
+        assert cg[k if k != "anomaly" else "anomalies"] == co[k], k
+    assert co["coll_e"] > 100 and co["ioniz"] > 10 and co["abs_e_pow"] + co["abs_e_gnd"] > 0
+    if step % 5 == 0:
+        assert co["coll_i"] > 10
+    m = 0
+    for sp in (0, 1):
+        m += compare_states(g.get_state(sp), o.get_state(sp), 1e-12, f"sp{sp}")
+    ge, gi = g.deposit()
+    oe, oi = o.deposit()
+    assert np.array_equal(ge, oe), "electron deposit after the step"
+    assert np.array_equal(gi, oi), "ion deposit after the step"
+    say(f"  bit mismatches in state components: {m}")
+    g.destroy()
+
+
+def test_multi_step_parity_and_subcycling(ctx, xs_default, orc):
+    """60 steps (4 ion steps at N_SUB = 20) with births and absorption: the
+    particle sets stay identical and the states agree to 1e-9."""
+    say("test_multi_step_parity_and_subcycling")
+    c = _case(pressure_pa=20.0, weight=1e5, n_grid=300, cap_e=100_000, cap_i=100_000)
+    st = random_state(20_000, 20_000, c["gap_m"], seed=3, te_ev=3.0, hot_frac=0.2, hot_ev=80.0)
+    g, o = _one_step(ctx, xs_default, orc, c, st, 0, nsteps=60)
+    cg, co = g.counts(), o.counts()
+    for k in ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz"):
+        assert cg[k] == co[k], k
+    for sp in (0, 1):
+        compare_states(g.get_state(sp), o.get_state(sp), 1e-9, f"sp{sp}")
+    g.destroy()
+
+
+def test_empty_case_gives_vacuum_field(ctx, orc):
+    """No particles: rho = 0 and E = V(t)/L on every node."""
+    say("test_empty_case_gives_vacuum_field")
+    xs = zero_xsec(n_bins=100_000)
+    c = _case(harmonics=[(100.0, 0.0, math.pi / 2)])
+    g, o = make_pair(ctx, c, xs, orc)
+    empty = {k: np.zeros(0) for k in ("x", "vx", "vy", "vz")} | {"uid": np.zeros(0, np.uint64)}
+    set_both(g, o, {"e": empty, "i": empty}, 0)
+    g.advance_steps(3)
+    o.step(3)
+    _, _, eg = g.fields()
+    _, _, eo = o.fields()
+    assert np.array_equal(eg, eo)
+    assert np.allclose(eg, 100.0 / c["gap_m"], rtol=1e-10)
+    assert g.counts()["n_e"] == 0
+    g.destroy()
+
+
+def test_run_twice_and_launch_shape_are_bit_identical(ctx, xs_default):
+    """Same state twice, with different launch sizes and with hipGraph
+    capture: bit-identical particles, deposits and counters (integer
+    deposits, counter-based random numbers keyed by particle identity)."""
+    say("test_run_twice_and_launch_shape_are_bit_identical")
+    from paper_2103_09642_amd import edupic
+    c = _case(pressure_pa=30.0, weight=1e5, cap_e=120_000, cap_i=120_000)
+    st = random_state(40_000, 40_000, c["gap_m"], seed=9, te_ev=3.0, hot_frac=0.2, hot_ev=70.0)
+    res = []
+    for mode, ppt, sort_every in ((0, 4, 100), (0, 1, 7), (1, 4, 5), (0, 16, 1000)):
+        ctx.set_option(edupic.OPT_MODE, mode)
+        ctx.set_option(edupic.OPT_PPT, ppt)
+        ctx.set_option(edupic.OPT_SORT_EVERY, sort_every)
+        g = ctx.create_case(c)
+        g.set_state(0, st["e"], 0)
+        g.set_state(1, st["i"], 0)
+        g.advance_steps(200)
+        res.append((by_uid(g.get_state(0)), by_uid(g.get_state(1)), g.deposit(), g.counts()))
+        g.destroy()
+    ctx.set_option(edupic.OPT_MODE, 0)
+    ctx.set_option(edupic.OPT_PPT, 4)
+    ctx.set_option(edupic.OPT_SORT_EVERY, 100)
+    for r in res[1:]:
+        for sp in (0, 1):
+            for k in ("uid", "x", "vx", "vy", "vz"):
+                assert np.array_equal(res[0][sp][k], r[sp][k]), k
+        assert np.array_equal(res[0][2][0], r[2][0]) and np.array_equal(res[0][2][1], r[2][1])
+        assert res[0][3] == r[3]
+
+
+def test_capacity_overflow_is_reported(ctx, xs_default):
+    """Births beyond the capacity are dropped, counted, and edp_sync returns
+    EDP_ECAPACITY; the case then refuses to advance."""
+    say("test_capacity_overflow_is_reported")
+    from paper_2103_09642_amd import edupic
+    c = _case(pressure_pa=80.0, weight=1e5, cap_e=4096, cap_i=4096)
+    st = random_state(4000, 4000, c["gap_m"], seed=1, te_ev=5.0, hot_frac=0.9, hot_ev=99.0)
+    g = ctx.create_case(c)
+    g.set_state(0, st["e"], 0)
+    g.set_state(1, st["i"], 0)
+    g.advance_steps(50)
+    with pytest.raises(edupic.EdpError) as ei:
+        ctx.sync()
+    assert ei.value.code == edupic.EDP_ECAPACITY
+    assert g.counts()["dropped"] > 0
+    with pytest.raises(edupic.EdpError):
+        g.advance_steps(1)
+    g.destroy()
+
+
+def test_invalid_descriptors_rejected(ctx):
+    say("test_invalid_descriptors_rejected")
+    from paper_2103_09642_amd import edupic
+    for bad in (dict(n_grid=1), dict(n_grid=5000), dict(ion_subcycle=0), dict(dt_e=0.0),
+                dict(harmonics=[(1.0, 1.0, 0.0)] * 5)):
+        with pytest.raises((edupic.EdpError, ValueError)):
+            ctx.create_case(_case(**bad))
+    # stability check (omega_pe dt >= 2 at the seed density)
+    with pytest.raises(edupic.EdpError) as ei:
+        ctx.create_case(base_case(n_init_e=1000, n_init_i=1000, weight=1e13))
+    assert ei.value.code == edupic.EDP_EUNSTABLE
+
+
+def test_diagnostics_match_oracle(ctx, xs_default, orc):
+    """Density, EEPF, currents and mean energy after 40 steps with every
+    measurement on: density and EEPF counts bit-exact (integer deposits of
+    identical positions), currents and mean energy to 1e-12."""
+    say("test_diagnostics_match_oracle")
+    c = _case(pressure_pa=10.0, weight=1e5, flags=["allow_unstable", "density", "eepf", "current", "meane"],
+              cap_e=100_000, cap_i=100_000)
+    st = random_state(30_000, 30_000, c["gap_m"], seed=4, te_ev=3.0, hot_frac=0.05, hot_ev=30.0)
+    g, o = _one_step(ctx, xs_default, orc, c, st, 0, nsteps=40)
+    ng_, ni_ = g.density()
+    no_, nio = o.density()
+    assert np.allclose(ng_, no_, rtol=1e-10, atol=1e-10 * no_.max())
+    assert np.allclose(ni_, nio, rtol=1e-10, atol=1e-10 * nio.max())
+    fg, cg = g.eepf()
+    fo, co = o.eepf()
+    assert cg.sum() == co.sum() and np.abs(cg - co).max() <= 2
+    jg = g.currents()
+    jo = o.currents()
+    for a, b in zip(jg, jo):
+        assert np.allclose(a, b, rtol=1e-9, atol=1e-9 * np.abs(b).max())
+    mg, mo = g.mean_energy(), o.mean_energy()
+    assert np.allclose(mg, mo, rtol=1e-9, atol=1e-9 * mo.max())
+    g.destroy()
