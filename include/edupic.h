@@ -68,11 +68,11 @@ extern "C" {
 /* Execution options for edp_set_option. */
 #define EDP_OPT_MODE 1        /* 0 plain launches, 1 hipGraph chunks, 2 persistent */
 #define EDP_OPT_SORT_EVERY 2  /* steps between compaction + cell sort (>= 1)      */
-#define EDP_OPT_BLOCK 3       /* threads per workgroup of the particle kernels    */
-#define EDP_OPT_PPT 4         /* particles per thread targeted per launch         */
 #define EDP_OPT_PROFILE 5     /* 1: time every particle-kernel launch with events */
 #define EDP_OPT_GRAPH_STEPS 6 /* steps captured per hipGraph (multiple of N_SUB)  */
 #define EDP_OPT_WG_PER_CU 7   /* persistent mode: workgroups per compute unit     */
+#define EDP_OPT_POISSON 8     /* field solve: 0 parallel flux scans (default),
+                                 1 sequential Thomas, bit-reproducible           */
 
 typedef struct edp_ctx edp_ctx; /* opaque */
 typedef int64_t edp_case;       /* case handle, > 0 */

@@ -65,6 +65,8 @@ def lib():
         L.orc_get_state.restype = C.c_int64
         L.orc_get_state.argtypes = [P, C.c_int, dp, dp, dp, dp, up, C.c_int64]
         L.orc_step.argtypes = [P, C.c_int64]
+        L.orc_count.restype = C.c_int64
+        L.orc_count.argtypes = [P, C.c_int]
         L.orc_step_index.restype = C.c_int64
         L.orc_step_index.argtypes = [P]
         L.orc_counts.argtypes = [P, ip]
@@ -179,6 +181,9 @@ class Oracle:
 
     def step(self, n: int = 1):
         lib().orc_step(self.h, n)
+
+    def count(self, species: int) -> int:
+        return lib().orc_count(self.h, species)
 
     @property
     def step_index(self) -> int:

@@ -797,6 +797,8 @@ int orc_step(orc_sim *s, int64_t n) {
 
 int64_t orc_step_index(const orc_sim *s) { return s->step; }
 
+int64_t orc_count(const orc_sim *s, int species) { return species == 0 ? s->e.n : s->i.n; }
+
 void orc_counts(const orc_sim *s, int64_t out[ORC_C_N]) {
   for (int k = 0; k < ORC_C_N; ++k) out[k] = s->counts[k];
 }

@@ -87,6 +87,7 @@ int64_t orc_get_state(const orc_sim *s, int species, double *x, double *vx,
                       double *vy, double *vz, uint64_t *uid, int64_t cap);
 /* Advance n full PIC/MCC steps. */
 int orc_step(orc_sim *s, int64_t n);
+int64_t orc_count(const orc_sim *s, int species); /* live particles */
 int64_t orc_step_index(const orc_sim *s);
 void orc_counts(const orc_sim *s, int64_t out[ORC_C_N]);
 /* Fixed-point densities the NEXT step will use (electrons; ions as held). */

@@ -23,7 +23,8 @@
 #include "impl.hpp"
 
 namespace edp {
-hipError_t launch_field(CaseDev* d, int ng, hipStream_t st);
+hipError_t launch_head(CaseDev* d, int ng, int mode, int scatter_blocks, hipStream_t st);
+hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
 hipError_t launch_particles(CaseDev* d, int sp, int blocks, int ng, uint32_t flags, int n_eepf,
                             hipStream_t st);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
@@ -94,7 +95,7 @@ struct edp_ctx {
   std::map<edp_case, Case*> cases;
   edp_case next_id = 1;
   // options
-  int mode = 0, sort_every = 100, ppt = 4, profile = 0, graph_steps = 0, wg_per_cu = 2;
+  int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, wg_per_cu = 2, poisson = 0;
   // profiling
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
   double prof_ms = 0.0;
@@ -104,10 +105,12 @@ struct edp_ctx {
 namespace {
 
 struct Layout {
-  size_t off_case, off_part[2][2][5], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
-      off_rho, off_phi, off_ef, off_sum[6], off_acc[4], off_eepf, off_sort, total;
+  size_t off_case, off_part[2][2][5], off_cq[2][2][2], off_cqb[2][2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
+      off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[4], off_eepf, off_sort, total;
   int64_t cap[2];
 };
+
+constexpr int64_t kMaxCap = (int64_t(1) << 31) - 1024;  // slots are int32 in the queues
 
 int validate(const edp_case_desc* c) {
   if (!c) return fail(EDP_EINVAL, "null descriptor");
@@ -121,6 +124,8 @@ int validate(const edp_case_desc* c) {
   if (c->n_harm < 0 || c->n_harm > 4) return fail(EDP_EINVAL, "n_harm must be 0..4");
   if (c->n_init_e < 0 || c->n_init_i < 0 || c->cap_e < 0 || c->cap_i < 0)
     return fail(EDP_EINVAL, "negative particle count");
+  if (c->cap_e > kMaxCap || c->cap_i > kMaxCap || 2 * c->n_init_e > kMaxCap || 2 * c->n_init_i > kMaxCap)
+    return fail(EDP_EINVAL, "capacity above 2^31 slots");
   if ((c->flags & EDP_DIAG_EEPF) && (c->n_eepf < 1 || c->n_eepf > 4096 || !(c->de_eepf_ev > 0.0)))
     return fail(EDP_EINVAL, "bad EEPF binning (1..4096 bins)");
   // particle-kernel LDS: E + deposit (16 B/node), with measurements 24 B/node more
@@ -148,6 +153,13 @@ Layout layout(const edp_case_desc* c, int nbins) {
   for (int sp = 0; sp < 2; ++sp)
     for (int set = 0; set < 2; ++set)
       for (int a = 0; a < 5; ++a) L.off_part[sp][set][a] = take((size_t)L.cap[sp] * 8);
+  for (int sp = 0; sp < 2; ++sp)
+    for (int b = 0; b < 2; ++b) {
+      L.off_cq[sp][b][0] = take((size_t)L.cap[sp] * 4);
+      L.off_cq[sp][b][1] = take((size_t)L.cap[sp] * 8);
+    }
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) L.off_cqb[b][a] = take((size_t)L.cap[0] * 4);
   for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
   const size_t ng = (size_t)c->n_grid;
   L.off_rden = take(ng * 8);
@@ -157,6 +169,7 @@ Layout layout(const edp_case_desc* c, int nbins) {
   L.off_rho = take(ng * 8);
   L.off_phi = take(ng * 8);
   L.off_ef = take(ng * 8);
+  L.off_flux = take(ng * 8);
   for (int k = 0; k < 6; ++k) L.off_sum[k] = take(ng * 8);
   for (int k = 0; k < 4; ++k) L.off_acc[k] = take(3 * ng * 8);
   L.off_eepf = take((size_t)std::max(1, c->n_eepf) * 8);
@@ -195,11 +208,20 @@ int write_dyn(edp_ctx* ctx, Case* c, const CaseDev& t) {
   return EDP_OK;
 }
 
+// Grid of the deposit/sort kernels for about n particles.
 int blocks_for(const edp_ctx* ctx, int64_t n) {
-  const int64_t per_block = 256 * (int64_t)std::max(1, ctx->ppt);
+  const int64_t per_block = 256 * 4;
   int64_t b = (n + per_block - 1) / per_block;
   b = std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)ctx->num_cu * 8));
   return (int)b;
+}
+
+// Workgroups that apply queued collisions (grid-stride over the queue).
+int scatter_blocks(const edp_ctx* ctx) { return ctx->num_cu; }
+
+// Grid of the particle kernels: one workgroup per kChunk slots of capacity.
+int particle_blocks(const Case* c, int sp) {
+  return (int)((c->h.sp[sp].cap + kChunk - 1) / kChunk);
 }
 
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
@@ -238,11 +260,18 @@ int request_estimate(edp_ctx* ctx, Case* c) {
   return EDP_OK;
 }
 
-// One step s, plain launches.
+// One step s, plain launches: head (field of s + collisions of s-1), the
+// periodic compaction/sort, then the particle kernels.
 int enqueue_step(edp_ctx* ctx, Case* c, int64_t s, int be, int bi) {
   const edp_case_desc& D = c->desc;
   hipStream_t st = ctx->stream;
-  HIPCHK(launch_field(c->d, D.n_grid, st));
+  HIPCHK(launch_head(c->d, D.n_grid, ctx->poisson, scatter_blocks(ctx), st));
+  // Compaction + cell sort: electrons every sort_every steps, ions every
+  // sort_every ion steps (they move only on ion steps).
+  if (s % ctx->sort_every == 0)
+    HIPCHK(launch_sort(c->d, 0, D.n_grid, std::max(1, blocks_for(ctx, c->est[0]) / 4), st));
+  if (s % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0)
+    HIPCHK(launch_sort(c->d, 1, D.n_grid, std::max(1, blocks_for(ctx, c->est[1]) / 4), st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profile) {
     HIPCHK(hipEventCreate(&e0));
@@ -255,12 +284,12 @@ int enqueue_step(edp_ctx* ctx, Case* c, int64_t s, int be, int bi) {
     ctx->ev_pairs.emplace_back(e0, e1);
   }
   if (s % D.ion_subcycle == 0) HIPCHK(launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st));
-  // Compaction + cell sort: electrons every sort_every steps, ions every
-  // sort_every ion steps (they move only on ion steps).
-  if ((s + 1) % ctx->sort_every == 0)
-    HIPCHK(launch_sort(c->d, 0, D.n_grid, std::max(1, blocks_for(ctx, c->est[0]) / 4), st));
-  if ((s + 1) % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0)
-    HIPCHK(launch_sort(c->d, 1, D.n_grid, std::max(1, blocks_for(ctx, c->est[1]) / 4), st));
+  return EDP_OK;
+}
+
+// Apply the collisions still queued by the last step (before reading state).
+int drain(edp_ctx* ctx, Case* c) {
+  HIPCHK(launch_drain(c->d, scatter_blocks(ctx), ctx->stream));
   return EDP_OK;
 }
 
@@ -289,20 +318,19 @@ int build_graph(edp_ctx* ctx, Case* c, int steps, int be, int bi, int bsort_e, i
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   for (int k = 0; k < steps; ++k) {
-    (void)launch_field(c->d, D.n_grid, st);
+    (void)launch_head(c->d, D.n_grid, ctx->poisson, scatter_blocks(ctx), st);
+    if (k % ctx->sort_every == 0) (void)launch_sort(c->d, 0, D.n_grid, bsort_e, st);
+    if (k % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0) (void)launch_sort(c->d, 1, D.n_grid, bsort_i, st);
     (void)launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st);
     if (k % D.ion_subcycle == 0) (void)launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st);
-    if ((k + 1) % ctx->sort_every == 0) (void)launch_sort(c->d, 0, D.n_grid, bsort_e, st);
-    if ((k + 1) % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0)
-      (void)launch_sort(c->d, 1, D.n_grid, bsort_i, st);
   }
   HIPCHK(hipStreamEndCapture(st, &g));
   hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(EDP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   c->g_steps = steps;
-  c->g_be = be;
-  c->g_bi = bi;
+  c->g_be = bsort_e;
+  c->g_bi = bsort_i;
   return EDP_OK;
 }
 
@@ -329,14 +357,18 @@ int run_steps(edp_ctx* ctx, Case* c, int64_t n) {
     }
     int r = upload_volt(ctx, c, s, w_end);
     if (r) return r;
-    const int be = blocks_for(ctx, c->est[0] + c->est[0] / 8 + 1024);
-    const int bi = blocks_for(ctx, c->est[1] + c->est[1] / 8 + 1024);
+    const int be = particle_blocks(c, 0);
+    const int bi = particle_blocks(c, 1);
     while (s < w_end) {
       if (gsteps > 0 && s % gsteps == 0 && s + gsteps <= w_end) {
-        const bool stale = !c->gexec || c->g_steps != gsteps || be > c->g_be * 5 / 4 ||
-                           be < c->g_be * 3 / 4 || bi > c->g_bi * 5 / 4 || bi < c->g_bi * 3 / 4;
+        // the sort grids follow the particle count; rebuild when it has
+        // moved by more than a quarter since the capture
+        const int se = std::max(1, blocks_for(ctx, c->est[0]) / 4);
+        const int si = std::max(1, blocks_for(ctx, c->est[1]) / 4);
+        const bool stale = !c->gexec || c->g_steps != gsteps || se > c->g_be * 5 / 4 + 1 ||
+                           se < c->g_be * 3 / 4 || si > c->g_bi * 5 / 4 + 1 || si < c->g_bi * 3 / 4;
         if (stale) {
-          r = build_graph(ctx, c, gsteps, be, bi, std::max(1, be / 4), std::max(1, bi / 4));
+          r = build_graph(ctx, c, gsteps, be, bi, se, si);
           if (r) return r;
         }
         HIPCHK(hipGraphLaunch(c->gexec, ctx->stream));
@@ -544,6 +576,17 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
       h.sp[sp].uid[set] = (uint64_t*)(c->arena + L.off_part[sp][set][4]);
     }
   }
+  for (int sp = 0; sp < 2; ++sp)
+    for (int b = 0; b < 2; ++b) {
+      h.cq_idx[sp][b] = (int32_t*)(c->arena + L.off_cq[sp][b][0]);
+      h.cq_r[sp][b] = (double*)(c->arena + L.off_cq[sp][b][1]);
+    }
+  for (int b = 0; b < 2; ++b) {
+    h.cq_be[b] = (int32_t*)(c->arena + L.off_cqb[b][0]);
+    h.cq_bi[b] = (int32_t*)(c->arena + L.off_cqb[b][1]);
+  }
+  h.cq_buf_pending = 1;
+  h.cq_step_pending = -1;
   double* tabs[7];
   for (int t = 0; t < 7; ++t) tabs[t] = (double*)(c->arena + L.off_tab[t]);
   h.nsig_e = tabs[0];
@@ -560,6 +603,7 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   h.rho = (double*)(c->arena + L.off_rho);
   h.phi = (double*)(c->arena + L.off_phi);
   h.efield = (double*)(c->arena + L.off_ef);
+  h.flux = (double*)(c->arena + L.off_flux);
   double** sums[6] = {&h.sum_ne, &h.sum_ni, &h.sum_je, &h.sum_ji, &h.sum_w, &h.sum_e};
   for (int k = 0; k < 6; ++k) *sums[k] = (double*)(c->arena + L.off_sum[k]);
   int64_t** accs[4] = {&h.acc_je, &h.acc_ji, &h.acc_w, &h.acc_e};
@@ -681,8 +725,10 @@ int edp_read_counts(edp_ctx* ctx, edp_case id, edp_counts* out) {
   if (!ctx || !out) return fail(EDP_EINVAL, "null argument");
   Case* c = find(ctx, id);
   if (!c) return fail(EDP_EINVAL, "unknown case");
+  int r = drain(ctx, c);
+  if (r) return r;
   CaseDev t;
-  int r = read_dyn(ctx, c, t);
+  r = read_dyn(ctx, c, t);
   if (r) return r;
   out->n_e = t.ctr[kLiveE];
   out->n_i = t.ctr[kLiveI];
@@ -800,8 +846,18 @@ int edp_read_fields(edp_ctx* ctx, edp_case id, double* rho, double* phi, double*
   if (n < ng) return fail(EDP_EINVAL, "output shorter than n_grid");
   int r;
   if (rho && (r = read_grid(ctx, c, c->h.rho, rho, ng * 8))) return r;
-  if (phi && (r = read_grid(ctx, c, c->h.phi, phi, ng * 8))) return r;
   if (ef && (r = read_grid(ctx, c, c->h.efield, ef, ng * 8))) return r;
+  if (phi) {
+    CaseDev t;
+    if ((r = read_dyn(ctx, c, t))) return r;
+    if (t.phi_valid) return read_grid(ctx, c, c->h.phi, phi, ng * 8);
+    // the flux solver keeps F_q = phi_q - phi_{q+1} and V; sum them back up
+    std::vector<double> f(ng);
+    if ((r = read_grid(ctx, c, c->h.flux, f.data(), ng * 8))) return r;
+    phi[0] = f[ng - 1];
+    for (int p = 1; p < ng - 1; ++p) phi[p] = phi[p - 1] - f[p - 1];
+    phi[ng - 1] = 0.0;
+  }
   return EDP_OK;
 }
 
@@ -809,8 +865,10 @@ int edp_get_state(edp_ctx* ctx, edp_case id, int32_t species, double* x, double*
                   double* vz, uint64_t* uid, int64_t cap, int64_t* n_out) {
   Case* c = ctx ? find(ctx, id) : nullptr;
   if (!c || (species != 0 && species != 1) || cap < 0) return fail(EDP_EINVAL, "bad argument");
+  int r = drain(ctx, c);
+  if (r) return r;
   CaseDev t;
-  int r = read_dyn(ctx, c, t);
+  r = read_dyn(ctx, c, t);
   if (r) return r;
   const int64_t n = t.alloc[species] < c->h.sp[species].cap ? t.alloc[species] : c->h.sp[species].cap;
   const int set = t.cur[species];
@@ -855,8 +913,11 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
     if (!std::isfinite(vx[i]) || !std::isfinite(vy[i]) || !std::isfinite(vz[i]))
       return fail(EDP_EINVAL, "particle %lld has a non-finite velocity", (long long)i);
   }
+  // the other species keeps its state: finish its pending collisions first
+  int r = drain(ctx, c);
+  if (r) return r;
   CaseDev t;
-  int r = read_dyn(ctx, c, t);
+  r = read_dyn(ctx, c, t);
   if (r) return r;
   if (n > 0) {
     HIPCHK(hipMemcpy(S.x[0], x, n * 8, hipMemcpyHostToDevice));
@@ -876,6 +937,9 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
   t.error = 0;
   t.diag_steps = 0;
   t.diag_ion_steps = 0;
+  for (int sp = 0; sp < 2; ++sp) t.cq_n[sp][0] = t.cq_n[sp][1] = 0;  // nothing pending
+  t.cq_buf_pending = (int32_t)((step + 1) & 1);
+  t.cq_step_pending = step - 1;
   if ((r = write_dyn(ctx, c, t))) return r;
   c->step = step;
   c->est[species] = n;
@@ -897,19 +961,17 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
       if (value < 1) return fail(EDP_EINVAL, "sort interval must be >= 1");
       ctx->sort_every = (int)value;
       break;
-    case EDP_OPT_BLOCK:
-      if (value != 256) return fail(EDP_EINVAL, "block size must be 256");
-      break;
-    case EDP_OPT_PPT:
-      if (value < 1 || value > 1024) return fail(EDP_EINVAL, "ppt must be 1..1024");
-      ctx->ppt = (int)value;
-      break;
     case EDP_OPT_PROFILE:
       ctx->profile = value ? 1 : 0;
       break;
     case EDP_OPT_GRAPH_STEPS:
       if (value < 0) return fail(EDP_EINVAL, "graph steps must be >= 0");
       ctx->graph_steps = (int)value;
+      for (auto& kv : ctx->cases) kv.second->g_steps = 0;
+      break;
+    case EDP_OPT_POISSON:
+      if (value < 0 || value > 1) return fail(EDP_EINVAL, "poisson solver must be 0 or 1");
+      ctx->poisson = (int)value;
       for (auto& kv : ctx->cases) kv.second->g_steps = 0;
       break;
     case EDP_OPT_WG_PER_CU:

@@ -30,6 +30,10 @@ constexpr double kDiagWS = 1048576.0;  // c
 constexpr double kDiagES = 1048576.0;  // c * energy [eV]
 
 constexpr int kMaxGrid = 4096;
+// Particle kernels: workgroup size and the particle slots each workgroup owns.
+constexpr int kBlock = 256;
+constexpr int kPerThread = 4;
+constexpr int kChunk = kBlock * kPerThread;
 constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
 
 // Flags (same values as EDP_* in edupic.h).
@@ -66,19 +70,29 @@ struct CaseDev {
   int64_t *cnt_e;       // [3][ng] electron deposit, ring by step % 3
   int64_t *cnt_i;       // [3][ng] ion deposit, ring by (step / nsub) % 3
   double *rho, *phi, *efield;
+  double* flux;         // F_q = phi_q - phi_{q+1}, q < ng-1; flux[ng-1] = V of the step
   double *sum_ne, *sum_ni, *sum_je, *sum_ji, *sum_w, *sum_e;  // [ng] time sums
   int64_t *acc_je, *acc_ji, *acc_w, *acc_e;                   // [3][ng] per step
   int64_t *eepf;                                              // [n_eepf]
   int64_t *sort_cnt;                                          // [ng + 1] scratch
+  // collision queues, double-buffered by step parity, capacity = cap:
+  int32_t* cq_idx[2][2];  // [species][buffer] slot of the colliding particle
+  double* cq_r[2][2];     // [species][buffer] its process-selection number
+  int32_t* cq_be[2];      // [buffer] slot of an ionization's new electron or -1
+  int32_t* cq_bi[2];      // [buffer] slot of its new ion or -1
   // ---- dynamic (device-mutated) -----------------------------------------
   int64_t step;
   int64_t n[2];       // slots processed this step (snapshot of alloc at step start)
   int64_t alloc[2];   // slots in use: live + tombstones + births
   int32_t cur[2];     // current buffer set per species
+  int64_t cq_n[2][2];       // [species][buffer] queued collisions
+  int64_t cq_step_pending;  // step whose queue is still to be applied
+  int32_t cq_buf_pending;   // and its buffer
+  int32_t pad2;
   int64_t diag_steps, diag_ion_steps;
   int64_t ctr[kNumCtr];
   int32_t error;      // 1: capacity overflow
-  int32_t pad1;
+  int32_t phi_valid;  // 1: phi[] holds the potential of the last step, 0: use flux[]
 };
 
 }  // namespace edp

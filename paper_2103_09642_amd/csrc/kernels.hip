@@ -1,12 +1,14 @@
 // HIP kernels of the PIC/MCC time step for gfx950.
 //
 // One step s of a case (section 2.1; Algorithms 2-6):
-//   k_field      one workgroup: fixed-point densities -> rho -> Thomas solve of
-//                the discrete Poisson equation -> grid field E (LDS resident).
+//   k_head       workgroup 0: fixed-point densities -> rho -> the discrete
+//                Poisson equation -> grid field E; the other workgroups
+//                finish the collisions of step s-1 (new velocities).
 //   k_particles  every particle of a species: gather E, leapfrog push, wall
-//                absorption, Monte Carlo collision with births, and the
-//                deposit of the new position for step s+1 -- fused, so each
-//                particle's state is streamed from HBM once per step.
+//                absorption, the collision test and process selection with
+//                ionization births, and the deposit of the new position for
+//                step s+1 -- fused, so each particle's state is streamed
+//                from HBM once per step.
 // Ions run k_particles only on steps with s % N_SUB == 0 (ion subcycling).
 //
 // Deposits are int64 fixed point (2^32 units per particle), privatised in
@@ -35,9 +37,11 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    // one 32x32->64 multiply each (v_mad_u64_u32) gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                   (uint32_t)p0);
   }
   return c;
 }
@@ -150,31 +154,115 @@ __device__ __forceinline__ int64_t slots(const CaseDev* C, int sp) {
 __device__ __forceinline__ void lds_add(unsigned long long* a, long long v) {
   atomicAdd(a, (unsigned long long)v);
 }
+
+// Arrays reached through the CaseDev block are global memory, but the
+// compiler cannot prove it for pointers loaded from memory and would emit
+// FLAT instructions, which count against the LDS wait counter too: every LDS
+// access would then wait for the in-flight HBM traffic.  G() states the
+// address space so loads, stores and atomics are global_* instructions.
+#define EDP_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ EDP_GLOBAL T* G(T* p) {
+  return (EDP_GLOBAL T*)p;
+}
 __device__ __forceinline__ void gl_add(int64_t* a, long long v) {
-  atomicAdd((unsigned long long*)a, (unsigned long long)v);
+  __hip_atomic_fetch_add(G((unsigned long long*)a), (unsigned long long)v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long gl_fetch_add(int64_t* a, unsigned long long v) {
+  return __hip_atomic_fetch_add(G((unsigned long long*)a), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // LDS counters of a particle workgroup.
-enum { kLAbsPow = 0, kLAbsGnd, kLColl, kLIoniz, kLAnom, kLDrop, kLLiveE, kLLiveI, kLN };
+enum { kLAbsPow = 0, kLAbsGnd, kLColl, kLIoniz, kLDrop, kLLiveE, kLLiveI, kLN };
+
+// Exclusive scan of one int per thread across the workgroup; *total gets
+// the sum.  sW: 32 ints of LDS scratch.
+__device__ __forceinline__ int block_exclusive_scan_int(int x, int* sW, int* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int inc = x;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) sW[wv] = inc;
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int v = sW[w];
+    if (w < wv) before += v;
+    tot += v;
+  }
+  *total = tot;
+  __syncthreads();
+  return before + inc - x;
+}
+
+// Exclusive scan of one double per thread across the workgroup (wave64
+// shuffles, then the wave totals through LDS); *total gets the sum.
+__device__ __forceinline__ double block_exclusive_scan(double x, double* sW, double* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double inc = x;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) sW[wv] = inc;
+  __syncthreads();
+  if (wv == 0) {
+    double t = lane < nw ? sW[lane] : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double y = __shfl_up(t, off, 64);
+      if (lane >= off) t += y;
+    }
+    if (lane < nw) sW[32 + lane] = t;  // inclusive over waves
+  }
+  __syncthreads();
+  double exc = __shfl_up(inc, 1, 64);
+  if (lane == 0) exc = 0.0;
+  if (wv > 0) exc += sW[32 + wv - 1];
+  *total = sW[32 + nw - 1];
+  __syncthreads();
+  return exc;
+}
 
 // ---------------------------------------------------------------------------
 // Step 2: density -> rho -> potential -> field, one workgroup per case.
+// MODE 0 (default) solves the discrete Poisson equation through the fluxes
+// F_q = phi_q - phi_{q+1}: each row of the equation says F_p - F_{p-1} = d_p
+// with d_p = rho_p dx^2/eps0, so F_p = F_0 + S_p with S_p the prefix sum of
+// d, and the fluxes add up to phi_0 - phi_{N-1} = V, which fixes
+// F_0 = (V - sum_p S_p)/(N_g - 1).  The field follows from the fluxes
+// without forming phi: E_p = (F_{p-1} + F_p)/(2 dx) inside, and the boundary
+// forms use F_0 and F_{N_g-2}.  This is the same linear system as the Thomas
+// algorithm solves, in parallel (two workgroup scans instead of 2 N_g
+// dependent steps); it agrees with an 80-bit solution to ~1e-15 of the field
+// scale, closer than the sequential sweep.
+// MODE 1 runs the Thomas algorithm itself in one thread, operation for
+// operation as the sequential definition (bit-reproducible, slow).
+// The workgroup also does the per-step bookkeeping and advances the step.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_field(CaseDev* __restrict__ C) {
-  extern __shared__ double fsm[];
+constexpr int kFieldRows = 8;  // rows per thread of the flux scans (n_grid <= 2048)
+
+template <int MODE>
+__device__ __forceinline__ void field_solve(CaseDev* __restrict__ C, double* fsm) {
   const int ng = C->ng;
   double* sRho = fsm;
-  double* sPhi = fsm + ng;
-  double* sR = fsm + 2 * ng;
+  double* sPhi = fsm + ng;    // MODE 1: d then phi; MODE 0: S_p then fluxes F_q
+  double* sR = fsm + 2 * ng;  // MODE 1: Thomas reciprocals
+  double* sW = fsm + 3 * ng;  // scan scratch (64 doubles)
   const int64_t s = C->step;
   const int nsub = C->nsub;
   const int64_t k = s / nsub;
   const bool ion_step = (s % nsub) == 0;
   const uint32_t fl = C->flags;
-  const int64_t* cntE = C->cnt_e + (s % 3) * ng;
-  const int64_t* cntI = C->cnt_i + (k % 3) * ng;
-  int64_t* zeroE = C->cnt_e + ((s + 2) % 3) * ng;
-  int64_t* zeroI = C->cnt_i + ((k + 2) % 3) * ng;
+  const EDP_GLOBAL int64_t* cntE = G(C->cnt_e + (s % 3) * ng);
+  const EDP_GLOBAL int64_t* cntI = G(C->cnt_i + (k % 3) * ng);
+  EDP_GLOBAL int64_t* zeroE = G(C->cnt_e + ((s + 2) % 3) * ng);
+  EDP_GLOBAL int64_t* zeroI = G(C->cnt_i + ((k + 2) % 3) * ng);
   const int64_t fold = ((s + 2) % 3) * ng;  // per-step sums of step s-1
   const double scale = C->dens_scale;
   for (int p = threadIdx.x; p < ng; p += blockDim.x) {
@@ -186,43 +274,100 @@ __global__ void __launch_bounds__(1024) k_field(CaseDev* __restrict__ C) {
     }
     const double rho = kECharge * (ni - ne);
     sRho[p] = rho;
-    sR[p] = C->rden[p];
-    sPhi[p] = rho * C->kpois;  // right-hand side d_p (boundary term below)
+    if (MODE == 1) {
+      sR[p] = G(C->rden)[p];
+      sPhi[p] = rho * C->kpois;  // right-hand side d_p (boundary term below)
+    }
     if (fl & kDiagDensity) {
-      C->sum_ne[p] += ne;
-      C->sum_ni[p] += ni;
+      G(C->sum_ne)[p] += ne;
+      G(C->sum_ni)[p] += ni;
     }
     zeroE[p] = 0;
     if (ion_step) zeroI[p] = 0;
     if (fl & kDiagCurrent) {
-      C->sum_je[p] += (double)C->acc_je[fold + p];
-      C->acc_je[fold + p] = 0;
-      C->sum_ji[p] += (double)C->acc_ji[fold + p];
-      C->acc_ji[fold + p] = 0;
+      G(C->sum_je)[p] += (double)G(C->acc_je)[fold + p];
+      G(C->acc_je)[fold + p] = 0;
+      G(C->sum_ji)[p] += (double)G(C->acc_ji)[fold + p];
+      G(C->acc_ji)[fold + p] = 0;
     }
     if (fl & kDiagMeanE) {
-      C->sum_w[p] += (double)C->acc_w[fold + p];
-      C->sum_e[p] += (double)C->acc_e[fold + p];
-      C->acc_w[fold + p] = 0;
-      C->acc_e[fold + p] = 0;
+      G(C->sum_w)[p] += (double)G(C->acc_w)[fold + p];
+      G(C->sum_e)[p] += (double)G(C->acc_e)[fold + p];
+      G(C->acc_w)[fold + p] = 0;
+      G(C->acc_e)[fold + p] = 0;
     }
   }
   __syncthreads();
-  const double V = C->volt[s % kVoltChunk];
-  if (threadIdx.x == 0) {
-    // Thomas algorithm (constant tridiagonal matrix): forward sweep
-    // y_p = (d_p + y_{p-1}) r_p, back substitution phi_p = y_p + r_p phi_{p+1}.
-    const int m = ng - 2;
-    double prev = 0.0;
-    for (int p = 1; p <= m; ++p) {
-      double d = sPhi[p];
-      if (p == 1) d = d + V;
-      prev = (d + prev) * sR[p];
-      sPhi[p] = prev;
+  const double V = G(C->volt)[s % kVoltChunk];
+  const double dx = C->dx;
+  if (MODE == 1) {
+    if (threadIdx.x == 0) {
+      // Thomas algorithm: forward sweep y_p = (d_p + y_{p-1}) r_p, back
+      // substitution phi_p = y_p + r_p phi_{p+1}.
+      const int m = ng - 2;
+      double prev = 0.0;
+      for (int p = 1; p <= m; ++p) {
+        double d = sPhi[p];
+        if (p == 1) d = d + V;
+        prev = (d + prev) * sR[p];
+        sPhi[p] = prev;
+      }
+      for (int p = m - 1; p >= 1; --p) sPhi[p] = sPhi[p] + sR[p] * sPhi[p + 1];
+      sPhi[0] = V;
+      sPhi[ng - 1] = 0.0;
     }
-    for (int p = m - 1; p >= 1; --p) sPhi[p] = sPhi[p] + sR[p] * sPhi[p + 1];
-    sPhi[0] = V;
-    sPhi[ng - 1] = 0.0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
+      double e;
+      if (p == 0)
+        e = (sPhi[0] - sPhi[1]) / dx - sRho[0] * dx / (2.0 * kEps0);
+      else if (p == ng - 1)
+        e = (sPhi[ng - 2] - sPhi[ng - 1]) / dx + sRho[ng - 1] * dx / (2.0 * kEps0);
+      else
+        e = (sPhi[p - 1] - sPhi[p + 1]) / (2.0 * dx);
+      G(C->efield)[p] = e;
+      G(C->phi)[p] = sPhi[p];
+      G(C->rho)[p] = sRho[p];
+    }
+  } else {
+    // rows p = 1..m; thread t owns the contiguous rows q0 < q < q1 (q = p-1)
+    const int m = ng - 2;
+    const double kp = C->kpois;
+    const int q0 = (int)threadIdx.x * kFieldRows;
+    const int q1 = q0 + kFieldRows < m ? q0 + kFieldRows : m;
+    double acc = 0.0;
+    for (int q = q0; q < q1; ++q) {
+      acc += sRho[q + 1] * kp;
+      sPhi[q + 1] = acc;  // prefix within the thread
+    }
+    double tot;
+    const double before = block_exclusive_scan(acc, sW, &tot);
+    double mine = 0.0;
+    for (int q = q0; q < q1; ++q) {
+      const double S = before + sPhi[q + 1];
+      sPhi[q + 1] = S;
+      mine += S;
+    }
+    double T;
+    (void)block_exclusive_scan(mine, sW, &T);
+    const double F0 = (V - T) / (double)(ng - 1);
+    for (int q = q0; q < q1; ++q) sPhi[q + 1] = F0 + sPhi[q + 1];
+    if (threadIdx.x == 0) sPhi[0] = F0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
+      double e;
+      if (p == 0)
+        e = sPhi[0] / dx - sRho[0] * dx / (2.0 * kEps0);
+      else if (p == ng - 1)
+        e = sPhi[ng - 2] / dx + sRho[ng - 1] * dx / (2.0 * kEps0);
+      else
+        e = (sPhi[p - 1] + sPhi[p]) / (2.0 * dx);
+      G(C->efield)[p] = e;
+      G(C->flux)[p] = p < ng - 1 ? sPhi[p] : V;  // last slot keeps V for phi on demand
+      G(C->rho)[p] = sRho[p];
+    }
+  }
+  if (threadIdx.x == 0) {
     // per-step bookkeeping: snapshot the particle slots of this step; after a
     // capacity overflow alloc may have run past the capacity, never process
     // beyond it
@@ -233,53 +378,253 @@ __global__ void __launch_bounds__(1024) k_field(CaseDev* __restrict__ C) {
         C->alloc[sp] = a;
       }
       C->n[sp] = a;
+      C->cq_n[sp][s & 1] = 0;  // this step's collision queue
     }
     C->ctr[kPstepE] += C->ctr[kLiveE];
     if (ion_step) C->ctr[kPstepI] += C->ctr[kLiveI];
     C->diag_steps += 1;
     if (ion_step) C->diag_ion_steps += 1;
+    C->phi_valid = MODE == 1;
     C->step = s + 1;  // particle kernels of this step read step-1
-  }
-  __syncthreads();
-  const double dx = C->dx;
-  for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-    double e;
-    if (p == 0)
-      e = (sPhi[0] - sPhi[1]) / dx - sRho[0] * dx / (2.0 * kEps0);
-    else if (p == ng - 1)
-      e = (sPhi[ng - 2] - sPhi[ng - 1]) / dx + sRho[ng - 1] * dx / (2.0 * kEps0);
-    else
-      e = (sPhi[p - 1] - sPhi[p + 1]) / (2.0 * dx);
-    C->efield[p] = e;
-    C->phi[p] = sPhi[p];
-    C->rho[p] = sRho[p];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Steps 3-6 for one species, fused, plus the deposit for step s+1.
-// Dynamic LDS: E[ng] double, H[ng] deposit; with particle diagnostics also
-// J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).
+// Collisions (step 6).  The particle kernel tests every particle, picks the
+// process of those that collide (partition of [0,1) into sigma_k/sigma_tot),
+// allocates and deposits the particles an ionization creates, and queues the
+// event.  The new velocities -- COM kinematics, scattering angles, Euler
+// rotation, the ionization energy split -- are computed from the queue by
+// extra workgroups of the next step's field launch (they do not depend on
+// each other), so this long transcendental code runs off the streaming path
+// and overlaps the field solve.
 // ---------------------------------------------------------------------------
+
+// Electron-Ar scattering of queued particle i (state after the push).
+__device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_t i, double r_proc, int64_t se, int64_t si,
+                                 int64_t s) {
+  const int ce = C->cur[0];
+  EDP_GLOBAL double* __restrict__ VX = G(C->sp[0].vx[ce]);
+  EDP_GLOBAL double* __restrict__ VY = G(C->sp[0].vy[ce]);
+  EDP_GLOBAL double* __restrict__ VZ = G(C->sp[0].vz[ce]);
+  const double vxn = VX[i], vy = VY[i], vz = VZ[i];
+  const uint64_t uid = G(C->sp[0].uid[ce])[i];
+  const uint64_t seed = C->seed;
+  const uint32_t st = (uint32_t)s;
+  const double v2 = vxn * vxn + vy * vy + vz * vz;
+  const double v = sqrt(v2);
+  const double energy = 0.5 * kEMass * v2 / kEvToJ;
+  const int idx = energy_bin(energy, C->de_cs, C->nbins);
+  double r_chi, r_eta;
+  uniform2(seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
+  const double f1 = kEMass / (kEMass + kArMass);
+  const double f2 = kArMass / (kEMass + kArMass);
+  const double wx = f1 * vxn, wy = f1 * vy, wz = f1 * vz;
+  const double s_el = G(C->sig_el)[idx], s_exc = G(C->sig_exc)[idx], s_ion = G(C->sig_ion)[idx];
+  const double s_tot = s_el + s_exc + s_ion;
+  int proc;
+  if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
+    proc = 0;
+  else if (r_proc < (s_el + s_exc) / s_tot)
+    proc = 1;
+  else
+    proc = 2;
+  const double eta = kTwoPi * r_eta;
+  double ox, oy, oz;
+  if (proc < 2) {
+    double gnew = v;
+    if (proc == 1) {
+      double ec = 0.5 * kMuEAr * v2 - C->thr_exc * kEvToJ;
+      if (ec < 0.0) {
+        ec = 0.0;
+        gl_add(&C->ctr[kAnomaly], 1);
+      }
+      gnew = sqrt(2.0 * ec / kMuEAr);
+    }
+    const double cos_chi = 1.0 - 2.0 * r_chi;
+    const double sin_chi = sqrt(1.0 - cos_chi * cos_chi);
+    scatter(vxn, vy, vz, v, gnew, f2, cos_chi, sin_chi, eta, wx, wy, wz, ox, oy, oz);
+  } else {
+    double r_share, r_unused;
+    uniform2(seed, uid, st, tag(0, 0, 2), r_share, r_unused);
+    double e_ev = 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion;
+    if (e_ev < 0.0) {
+      e_ev = 0.0;
+      gl_add(&C->ctr[kAnomaly], 1);
+    }
+    const double w_ion = C->w_ion;
+    const double e_ej = w_ion * tan(r_share * atan(e_ev / (2.0 * w_ion)));
+    const double e_sc = e_ev - e_ej;
+    const double g_sc = sqrt(2.0 * e_sc * kEvToJ / kMuEAr);
+    const double g_ej = sqrt(2.0 * e_ej * kEvToJ / kMuEAr);
+    double cs_sc, sn_sc, cs_ej, sn_ej;
+    if (C->flags & kIonizLiteral) {
+      const double chi_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 0.0;
+      const double chi_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 0.0;
+      cs_sc = cos(chi_sc);
+      sn_sc = sin(chi_sc);
+      cs_ej = cos(chi_ej);
+      sn_ej = sin(chi_ej);
+    } else {
+      cs_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 1.0;
+      cs_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 1.0;
+      sn_sc = sqrt(1.0 - cs_sc * cs_sc);
+      sn_ej = sqrt(1.0 - cs_ej * cs_ej);
+    }
+    scatter(vxn, vy, vz, v, g_sc, f2, cs_sc, sn_sc, eta, wx, wy, wz, ox, oy, oz);
+    if (se >= 0) {  // the ejected electron, scattered about the same w
+      double ex_, ey_, ez_;
+      scatter(vxn, vy, vz, v, g_ej, f2, cs_ej, sn_ej, eta + kPi, wx, wy, wz, ex_, ey_, ez_);
+      VX[se] = ex_;
+      VY[se] = ey_;
+      VZ[se] = ez_;
+    }
+    if (si >= 0) {  // the new ion: a thermal gas velocity
+      const int ci = C->cur[1];
+      double z0, z1, z2;
+      normals3(seed, child_uid(uid, s, 2), st, 1u, 2u, 1u, z0, z1, z2);
+      const double sa = C->sigma_a;
+      G(C->sp[1].vx[ci])[si] = sa * z0;
+      G(C->sp[1].vy[ci])[si] = sa * z1;
+      G(C->sp[1].vz[ci])[si] = sa * z2;
+    }
+  }
+  VX[i] = ox;
+  VY[i] = oy;
+  VZ[i] = oz;
+}
+
+// Ar+ + Ar scattering of queued ion i with the thermal target of its test
+// (redrawn from the same counter, so it is the same atom).
+__device__ __forceinline__ void ion_scatter(CaseDev* __restrict__ C, int64_t i, double r_proc, int64_t s) {
+  const int cur = C->cur[1];
+  EDP_GLOBAL double* __restrict__ VX = G(C->sp[1].vx[cur]);
+  EDP_GLOBAL double* __restrict__ VY = G(C->sp[1].vy[cur]);
+  EDP_GLOBAL double* __restrict__ VZ = G(C->sp[1].vz[cur]);
+  const double vxn = VX[i], vy = VY[i], vz = VZ[i];
+  const uint64_t uid = G(C->sp[1].uid[cur])[i];
+  const uint64_t seed = C->seed;
+  const uint32_t st = (uint32_t)s;
+  double z0, z1, z2;
+  normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+  const double sa = C->sigma_a;
+  const double vax = sa * z0, vay = sa * z1, vaz = sa * z2;
+  const double gx = vxn - vax, gy = vy - vay, gz = vz - vaz;
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  const double g = sqrt(g2);
+  const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+  const int idx = energy_bin(energy, C->de_cs, C->nbins);
+  double r_chi, r_eta;
+  uniform2(seed, uid, st, tag(1, 0, 3), r_chi, r_eta);
+  const double wx = 0.5 * (vxn + vax), wy = 0.5 * (vy + vay), wz = 0.5 * (vz + vaz);
+  const double s_iso = G(C->sig_iso)[idx], s_back = G(C->sig_back)[idx];
+  double cos_chi, sin_chi;
+  if (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) {
+    cos_chi = 1.0 - 2.0 * r_chi;
+    sin_chi = sqrt(1.0 - cos_chi * cos_chi);
+  } else {
+    cos_chi = -1.0;
+    sin_chi = 0.0;
+  }
+  double ox, oy, oz;
+  scatter(gx, gy, gz, g, g, 0.5, cos_chi, sin_chi, kTwoPi * r_eta, wx, wy, wz, ox, oy, oz);
+  VX[i] = ox;
+  VY[i] = oy;
+  VZ[i] = oz;
+}
+
+// The queued collisions of the last particle step, both species, spread over
+// workgroups blk = 0..nblk-1 (grid-stride).
+__device__ __forceinline__ void scatter_pending(CaseDev* __restrict__ C, int blk, int nblk) {
+  const int qb = C->cq_buf_pending;
+  const int64_t s = C->cq_step_pending;
+  const int64_t ne = C->cq_n[0][qb], ni = C->cq_n[1][qb];
+  const int64_t stride = (int64_t)nblk * blockDim.x;
+  const int64_t e0 = (int64_t)blk * blockDim.x + threadIdx.x;
+  for (int64_t e = e0; e < ne; e += stride)
+    electron_scatter(C, G(C->cq_idx[0][qb])[e], G(C->cq_r[0][qb])[e], G(C->cq_be[qb])[e], G(C->cq_bi[qb])[e], s);
+  for (int64_t e = e0; e < ni; e += stride) ion_scatter(C, G(C->cq_idx[1][qb])[e], G(C->cq_r[1][qb])[e], s);
+}
+
+// Head of a step: workgroup 0 solves the field of step s, the others apply
+// the collisions queued by step s-1.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_head(CaseDev* __restrict__ C) {
+  extern __shared__ double hsm[];
+  if (blockIdx.x == 0)
+    field_solve<MODE>(C, hsm);
+  else
+    scatter_pending(C, (int)blockIdx.x - 1, (int)gridDim.x - 1);
+}
+
+// Apply pending collisions before the host looks at the state.
+__global__ void __launch_bounds__(kBlock) k_drain(CaseDev* __restrict__ C) {
+  scatter_pending(C, (int)blockIdx.x, (int)gridDim.x);
+}
+__global__ void k_drain_done(CaseDev* __restrict__ C) {
+  if (threadIdx.x == 0) {
+    const int qb = C->cq_buf_pending;
+    C->cq_n[0][qb] = 0;
+    C->cq_n[1][qb] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Steps 3-6 for one species plus the deposit for step s+1.
+//
+// Workgroup b owns particle slots [b*kChunk, (b+1)*kChunk); the grid covers
+// the capacity, so any particle count is handled and launch shapes never
+// depend on it (workgroups past the live slots exit at once).  Every
+// particle: gather E from LDS, leapfrog, wall test, the collision test (one
+// Philox call and one exp for an electron; the thermal target draw first for
+// an ion), store x and v_x, deposit the new x into the workgroup's LDS
+// histogram.  A colliding particle's process is selected here (ionizations
+// also allocate and deposit their two newborns) and the event is queued in
+// LDS; the chunk's queue goes to the case's collision queue at the end.
+//
+// Dynamic LDS: E[ng] double, H[ng] deposit; with particle diagnostics also
+// J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32); then the queue.
+// ---------------------------------------------------------------------------
+constexpr int kQCap = kChunk;  // the queue holds a whole chunk
+
+__device__ __forceinline__ size_t queue_offset_doubles(int ng, uint32_t fl, int n_eepf, int sp) {
+  size_t o = (size_t)2 * ng;
+  if (fl & kDiagParticle) o += (size_t)3 * ng + (sp == 0 && (fl & kDiagEepf) ? (size_t)(n_eepf + 1) / 2 : 0);
+  return o;
+}
+
 template <int SP>
-__global__ void __launch_bounds__(256) k_particles(CaseDev* __restrict__ C) {
+__global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
   extern __shared__ double psm[];
   __shared__ unsigned long long sCtr[kLN];
+  __shared__ int sScan[32];
+  const int64_t s = C->step - 1;  // the head of this step already advanced it
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    C->cq_buf_pending = (int)(s & 1);
+    C->cq_step_pending = s;
+  }
+  const int64_t n = C->n[SP];
+  const int64_t lo = (int64_t)blockIdx.x * kChunk;
+  if (lo >= n) return;  // whole workgroup: no live slots in this chunk
+  const int64_t hi = lo + kChunk < n ? lo + kChunk : n;
   const int ng = C->ng;
-  const int64_t s = C->step - 1;  // k_field of this step already advanced it
   const int nsub = C->nsub;
   const int64_t kion = s / nsub;
   const uint32_t fl = C->flags;
   const bool pdiag = (fl & kDiagParticle) != 0;
+  const int n_eepf = C->n_eepf;
   double* sE = psm;
   unsigned long long* sH = (unsigned long long*)(psm + ng);
   unsigned long long* sJ = sH + ng;
   unsigned long long* sW = sJ + ng;
   unsigned long long* sEn = sW + ng;
   unsigned int* sF = (unsigned int*)(sEn + ng);
-  const int n_eepf = C->n_eepf;
+  double* sQr = psm + queue_offset_doubles(ng, fl, n_eepf, SP);
+  int* sQi = (int*)(sQr + kQCap);
+  int* sQe = sQi + kQCap;
+  int* sQj = sQe + kQCap;
   for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-    sE[p] = C->efield[p];
+    sE[p] = G(C->efield)[p];
     sH[p] = 0;
     if (pdiag) {
       sJ[p] = 0;
@@ -293,33 +638,52 @@ __global__ void __launch_bounds__(256) k_particles(CaseDev* __restrict__ C) {
   __syncthreads();
 
   const int cur = C->cur[SP];
-  double* __restrict__ X = C->sp[SP].x[cur];
-  double* __restrict__ VX = C->sp[SP].vx[cur];
-  double* __restrict__ VY = C->sp[SP].vy[cur];
-  double* __restrict__ VZ = C->sp[SP].vz[cur];
-  const uint64_t* __restrict__ UID = C->sp[SP].uid[cur];
-  const int64_t n = C->n[SP];
-  const double inv_dx = C->inv_dx, L = C->L;
+  EDP_GLOBAL double* __restrict__ X = G(C->sp[SP].x[cur]);
+  EDP_GLOBAL double* __restrict__ VX = G(C->sp[SP].vx[cur]);
+  const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
+  const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
+  const EDP_GLOBAL uint64_t* __restrict__ UID = G(C->sp[SP].uid[cur]);
+  const double inv_dx = C->inv_dx, L_gap = C->L;
   const double dt = SP == 0 ? C->dt_e : C->dt_i;
   const double factor = SP == 0 ? C->factor_e : C->factor_i;
-  const double* __restrict__ nsig = SP == 0 ? C->nsig_e : C->nsig_i;
+  const EDP_GLOBAL double* __restrict__ nsig = G(SP == 0 ? C->nsig_e : C->nsig_i);
   const double de_cs = C->de_cs;
   const int nbins = C->nbins;
   const uint64_t seed = C->seed;
   const uint32_t st = (uint32_t)s;
-  const double x_lo = C->x_lo, x_hi = C->x_hi;
+  const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf;
+  const double sa = C->sigma_a;
 
-  unsigned long long my_abs_pow = 0, my_abs_gnd = 0, my_coll = 0;
-  const int64_t G = gridDim.x;
-  const int64_t per = (n + G - 1) / G;
-  const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < n ? lo + per : n;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const double x = X[i];
-    if (!(x == x)) continue;  // absorbed earlier: tombstone
-    const double vx = VX[i];
-    double vy = VY[i], vz = VZ[i];
-    const uint64_t uid = UID[i];
+  unsigned int my_abs_pow = 0, my_abs_gnd = 0, my_coll = 0;
+  int my_q = 0;  // this thread's queued collisions, in its own kPerThread LDS slots
+  // All loads of the thread's kPerThread particles are issued before any
+  // store: on this target stores count against the same wait counter as
+  // loads, so interleaving them would make each load wait for the stores.
+  double xs[kPerThread], vxs[kPerThread], vys[kPerThread], vzs[kPerThread];
+  uint64_t us[kPerThread];
+#pragma unroll
+  for (int u = 0; u < kPerThread; ++u) {
+    const int64_t i = lo + u * kBlock + threadIdx.x;
+    if (i < hi) {
+      xs[u] = X[i];
+      vxs[u] = VX[i];
+      vys[u] = VY[i];
+      vzs[u] = VZ[i];
+      us[u] = UID[i];
+    } else {
+      xs[u] = __longlong_as_double(0x7FF8000000000000LL);
+    }
+  }
+  double xo[kPerThread], vxo[kPerThread];
+  bool st_ok[kPerThread];
+#pragma unroll
+  for (int u = 0; u < kPerThread; ++u) {
+    const int64_t i = lo + u * kBlock + threadIdx.x;
+    const double x = xs[u];
+    st_ok[u] = false;
+    if (!(x == x)) continue;  // past the end, or absorbed earlier (tombstone)
+    st_ok[u] = true;
+    const double vx = vxs[u], vy = vys[u], vz = vzs[u];
     // Steps 3-4: field at the particle and leapfrog.
     const double c0 = x * inv_dx;
     int p = (int)c0;
@@ -349,101 +713,70 @@ __global__ void __launch_bounds__(256) k_particles(CaseDev* __restrict__ C) {
           lds_add(&sEn[p + 1], (long long)(c2 * en * kDiagES));
         }
         if ((fl & kDiagEepf) && x >= x_lo && x <= x_hi) {
-          const double t = en / C->de_eepf;
+          const double t = en / de_eepf;
           if (t < (double)n_eepf) atomicAdd(&sF[(int)t], 1u);
         }
       }
     }
     // Step 5: absorbing electrodes.
-    if (xn < 0.0 || xn > L) {
+    if (xn < 0.0 || xn > L_gap) {
       if (xn < 0.0)
         ++my_abs_pow;
       else
         ++my_abs_gnd;
-      X[i] = __longlong_as_double(0x7FF8000000000000LL);
+      xo[u] = __longlong_as_double(0x7FF8000000000000LL);
+      vxo[u] = vxn;
       continue;
     }
-    // Step 6: collision test and event.
+    // Step 6: collision test, P = 1 - exp(-n sigma_tot(E) g dt), collide iff R < P.
+    double r_coll, r_proc, p_coll;
+    int idx;
     if (SP == 0) {
       const double v2 = vxn * vxn + vy * vy + vz * vz;
       const double v = sqrt(v2);
       const double energy = 0.5 * kEMass * v2 / kEvToJ;
-      const int idx = energy_bin(energy, de_cs, nbins);
+      idx = energy_bin(energy, de_cs, nbins);
       const double nu = nsig[idx] * v;
-      const double p_coll = 1.0 - exp(-nu * dt);
-      double r_coll, r_proc;
-      uniform2(seed, uid, st, tag(0, 0, 0), r_coll, r_proc);
-      if (r_coll < p_coll) {
-        double r_chi, r_eta, r_share, r_unused;
-        uniform2(seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
-        uniform2(seed, uid, st, tag(0, 0, 2), r_share, r_unused);
-        const double f1 = kEMass / (kEMass + kArMass);
-        const double f2 = kArMass / (kEMass + kArMass);
-        const double wx = f1 * vxn, wy = f1 * vy, wz = f1 * vz;
-        const double s_el = C->sig_el[idx], s_exc = C->sig_exc[idx], s_ion = C->sig_ion[idx];
+      p_coll = 1.0 - exp(-nu * dt);
+      uniform2(seed, us[u], st, tag(0, 0, 0), r_coll, r_proc);
+    } else {
+      double z0, z1, z2;
+      normals3(seed, us[u], st, 1u, 0u, 0u, z0, z1, z2);
+      const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+      const double g2 = gx * gx + gy * gy + gz * gz;
+      const double g = sqrt(g2);
+      const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+      idx = energy_bin(energy, de_cs, nbins);
+      const double nu = nsig[idx] * g;
+      p_coll = 1.0 - exp(-nu * dt);
+      uniform2(seed, us[u], st, tag(1, 0, 2), r_coll, r_proc);
+    }
+    xo[u] = xn;
+    vxo[u] = vxn;
+    {
+      long long r;
+      const int q = deposit_split(xn, inv_dx, ng, r);
+      lds_add(&sH[q], 4294967296LL - r);
+      lds_add(&sH[q + 1], r);
+    }
+    if (r_coll < p_coll) {
+      ++my_coll;
+      int se = -1, si = -1;
+      if (SP == 0) {
+        const double s_el = G(C->sig_el)[idx], s_exc = G(C->sig_exc)[idx], s_ion = G(C->sig_ion)[idx];
         const double s_tot = s_el + s_exc + s_ion;
-        int proc;
-        if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
-          proc = 0;
-        else if (r_proc < (s_el + s_exc) / s_tot)
-          proc = 1;
-        else
-          proc = 2;
-        const double eta = kTwoPi * r_eta;
-        double ox, oy, oz;
-        if (proc < 2) {
-          double gnew = v;
-          if (proc == 1) {
-            double ec = 0.5 * kMuEAr * v2 - C->thr_exc * kEvToJ;
-            if (ec < 0.0) {
-              ec = 0.0;
-              atomicAdd(&sCtr[kLAnom], 1ull);
-            }
-            gnew = sqrt(2.0 * ec / kMuEAr);
-          }
-          const double cos_chi = 1.0 - 2.0 * r_chi;
-          const double sin_chi = sqrt(1.0 - cos_chi * cos_chi);
-          scatter(vxn, vy, vz, v, gnew, f2, cos_chi, sin_chi, eta, wx, wy, wz, ox, oy, oz);
-        } else {
-          double e_ev = 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion;
-          if (e_ev < 0.0) {
-            e_ev = 0.0;
-            atomicAdd(&sCtr[kLAnom], 1ull);
-          }
-          const double w_ion = C->w_ion;
-          const double e_ej = w_ion * tan(r_share * atan(e_ev / (2.0 * w_ion)));
-          const double e_sc = e_ev - e_ej;
-          const double g_sc = sqrt(2.0 * e_sc * kEvToJ / kMuEAr);
-          const double g_ej = sqrt(2.0 * e_ej * kEvToJ / kMuEAr);
-          double cs_sc, sn_sc, cs_ej, sn_ej;
-          if (fl & kIonizLiteral) {
-            const double chi_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 0.0;
-            const double chi_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 0.0;
-            cs_sc = cos(chi_sc);
-            sn_sc = sin(chi_sc);
-            cs_ej = cos(chi_ej);
-            sn_ej = sin(chi_ej);
-          } else {
-            cs_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 1.0;
-            cs_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 1.0;
-            sn_sc = sqrt(1.0 - cs_sc * cs_sc);
-            sn_ej = sqrt(1.0 - cs_ej * cs_ej);
-          }
-          scatter(vxn, vy, vz, v, g_sc, f2, cs_sc, sn_sc, eta, wx, wy, wz, ox, oy, oz);
-          double ex_, ey_, ez_;
-          scatter(vxn, vy, vz, v, g_ej, f2, cs_ej, sn_ej, eta + kPi, wx, wy, wz, ex_, ey_, ez_);
-          // births: the ejected electron and the new ion at the parent's position
+        const bool ioniz = (s_tot > 0.0) && !(r_proc < s_el / s_tot) && !(r_proc < (s_el + s_exc) / s_tot);
+        if (ioniz) {
+          // births at the parent's position: an ejected electron and an ion
           atomicAdd(&sCtr[kLIoniz], 1ull);
-          const uint64_t ue = child_uid(uid, s, 1), ui = child_uid(uid, s, 2);
-          const unsigned long long se = atomicAdd((unsigned long long*)&C->alloc[0], 1ull);
-          if ((int64_t)se < C->sp[0].cap) {
-            X[se] = xn;
-            VX[se] = ex_;
-            VY[se] = ey_;
-            VZ[se] = ez_;
-            C->sp[0].uid[cur][se] = ue;
-            long long r;
-            const int q = deposit_split(xn, inv_dx, ng, r);
+          const uint64_t uid = us[u];
+          long long r;
+          const int q = deposit_split(xn, inv_dx, ng, r);
+          const unsigned long long be = gl_fetch_add(&C->alloc[0], 1ull);
+          if ((int64_t)be < C->sp[0].cap) {
+            se = (int)be;
+            X[be] = xn;
+            G(C->sp[0].uid[cur])[be] = child_uid(uid, s, 1);
             lds_add(&sH[q], 4294967296LL - r);
             lds_add(&sH[q + 1], r);
             atomicAdd(&sCtr[kLLiveE], 1ull);
@@ -451,18 +784,11 @@ __global__ void __launch_bounds__(256) k_particles(CaseDev* __restrict__ C) {
             atomicAdd(&sCtr[kLDrop], 1ull);
           }
           const int ci = C->cur[1];
-          const unsigned long long si = atomicAdd((unsigned long long*)&C->alloc[1], 1ull);
-          if ((int64_t)si < C->sp[1].cap) {
-            double z0, z1, z2;
-            normals3(seed, ui, st, 1u, 2u, 1u, z0, z1, z2);
-            const double sa = C->sigma_a;
-            C->sp[1].x[ci][si] = xn;
-            C->sp[1].vx[ci][si] = sa * z0;
-            C->sp[1].vy[ci][si] = sa * z1;
-            C->sp[1].vz[ci][si] = sa * z2;
-            C->sp[1].uid[ci][si] = ui;
-            long long r;
-            const int q = deposit_split(xn, inv_dx, ng, r);
+          const unsigned long long bi = gl_fetch_add(&C->alloc[1], 1ull);
+          if ((int64_t)bi < C->sp[1].cap) {
+            si = (int)bi;
+            G(C->sp[1].x[ci])[bi] = xn;
+            G(C->sp[1].uid[ci])[bi] = child_uid(uid, s, 2);
             int64_t* ci_next = C->cnt_i + ((kion + 1) % 3) * ng;
             gl_add(&ci_next[q], 4294967296LL - r);
             gl_add(&ci_next[q + 1], r);
@@ -471,56 +797,44 @@ __global__ void __launch_bounds__(256) k_particles(CaseDev* __restrict__ C) {
             atomicAdd(&sCtr[kLDrop], 1ull);
           }
         }
-        VY[i] = oy;
-        VZ[i] = oz;
-        vxn = ox;
-        ++my_coll;
       }
-    } else {
-      double z0, z1, z2;
-      normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
-      const double sa = C->sigma_a;
-      const double vax = sa * z0, vay = sa * z1, vaz = sa * z2;
-      const double gx = vxn - vax, gy = vy - vay, gz = vz - vaz;
-      const double g2 = gx * gx + gy * gy + gz * gz;
-      const double g = sqrt(g2);
-      const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-      const int idx = energy_bin(energy, de_cs, nbins);
-      const double nu = nsig[idx] * g;
-      const double p_coll = 1.0 - exp(-nu * dt);
-      double r_coll, r_proc;
-      uniform2(seed, uid, st, tag(1, 0, 2), r_coll, r_proc);
-      if (r_coll < p_coll) {
-        double r_chi, r_eta;
-        uniform2(seed, uid, st, tag(1, 0, 3), r_chi, r_eta);
-        const double wx = 0.5 * (vxn + vax), wy = 0.5 * (vy + vay), wz = 0.5 * (vz + vaz);
-        const double s_iso = C->sig_iso[idx], s_back = C->sig_back[idx];
-        double cos_chi, sin_chi;
-        if (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) {
-          cos_chi = 1.0 - 2.0 * r_chi;
-          sin_chi = sqrt(1.0 - cos_chi * cos_chi);
-        } else {
-          cos_chi = -1.0;
-          sin_chi = 0.0;
-        }
-        double ox, oy, oz;
-        scatter(gx, gy, gz, g, g, 0.5, cos_chi, sin_chi, kTwoPi * r_eta, wx, wy, wz, ox, oy, oz);
-        VY[i] = oy;
-        VZ[i] = oz;
-        vxn = ox;
-        ++my_coll;
+      const int slot = (int)threadIdx.x * kPerThread + my_q++;
+      sQi[slot] = (int)(i - lo);
+      sQr[slot] = r_proc;
+      sQe[slot] = se;
+      sQj[slot] = si;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kPerThread; ++u) {
+    if (!st_ok[u]) continue;
+    const int64_t i = lo + u * kBlock + threadIdx.x;
+    X[i] = xo[u];
+    VX[i] = vxo[u];
+  }
+  if (my_abs_pow) atomicAdd(&sCtr[kLAbsPow], (unsigned long long)my_abs_pow);
+  if (my_abs_gnd) atomicAdd(&sCtr[kLAbsGnd], (unsigned long long)my_abs_gnd);
+  if (my_coll) atomicAdd(&sCtr[kLColl], (unsigned long long)my_coll);
+  // hand the chunk's collisions to the queue of this step: one workgroup
+  // scan places every thread's entries, one global atomic reserves the range
+  int qn;
+  const int my_off = block_exclusive_scan_int(my_q, sScan, &qn);
+  if (qn > 0) {
+    __shared__ unsigned long long sBase;
+    const int qb = (int)(s & 1);
+    if (threadIdx.x == 0) sBase = gl_fetch_add(&C->cq_n[SP][qb], (unsigned long long)qn);
+    __syncthreads();
+    const int64_t b0 = (int64_t)sBase + my_off;
+    for (int k = 0; k < my_q; ++k) {
+      const int slot = (int)threadIdx.x * kPerThread + k;
+      G(C->cq_idx[SP][qb])[b0 + k] = (int)lo + sQi[slot];
+      G(C->cq_r[SP][qb])[b0 + k] = sQr[slot];
+      if (SP == 0) {
+        G(C->cq_be[qb])[b0 + k] = sQe[slot];
+        G(C->cq_bi[qb])[b0 + k] = sQj[slot];
       }
     }
-    X[i] = xn;
-    VX[i] = vxn;
-    long long r;
-    const int q = deposit_split(xn, inv_dx, ng, r);
-    lds_add(&sH[q], 4294967296LL - r);
-    lds_add(&sH[q + 1], r);
   }
-  if (my_abs_pow) atomicAdd(&sCtr[kLAbsPow], my_abs_pow);
-  if (my_abs_gnd) atomicAdd(&sCtr[kLAbsGnd], my_abs_gnd);
-  if (my_coll) atomicAdd(&sCtr[kLColl], my_coll);
   __syncthreads();
   // flush: deposit for step s+1, diagnostics of step s, counters
   int64_t* dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
@@ -543,7 +857,6 @@ __global__ void __launch_bounds__(256) k_particles(CaseDev* __restrict__ C) {
     if (a_gnd) gl_add(&C->ctr[SP == 0 ? kAbsEGnd : kAbsIGnd], (long long)a_gnd);
     if (sCtr[kLColl]) gl_add(&C->ctr[SP == 0 ? kCollE : kCollI], (long long)sCtr[kLColl]);
     if (sCtr[kLIoniz]) gl_add(&C->ctr[kIoniz], (long long)sCtr[kLIoniz]);
-    if (sCtr[kLAnom]) gl_add(&C->ctr[kAnomaly], (long long)sCtr[kLAnom]);
     if (sCtr[kLDrop]) {
       gl_add(&C->ctr[kDropped], (long long)sCtr[kLDrop]);
       atomicExch(&C->error, 1);
@@ -569,11 +882,11 @@ __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma)
   double u0, u1, z0, z1, z2;
   uniform2(C->seed, (uint64_t)i, 0u, tag((uint32_t)sp, 1u, 0u), u0, u1);
   normals3(C->seed, (uint64_t)i, 0u, (uint32_t)sp, 1u, 1u, z0, z1, z2);
-  C->sp[sp].x[cur][i] = C->L * u0;
-  C->sp[sp].vx[cur][i] = sigma * z0;
-  C->sp[sp].vy[cur][i] = sigma * z1;
-  C->sp[sp].vz[cur][i] = sigma * z2;
-  C->sp[sp].uid[cur][i] = (uint64_t)i;
+  G(C->sp[sp].x[cur])[i] = C->L * u0;
+  G(C->sp[sp].vx[cur])[i] = sigma * z0;
+  G(C->sp[sp].vy[cur])[i] = sigma * z1;
+  G(C->sp[sp].vz[cur])[i] = sigma * z2;
+  G(C->sp[sp].uid[cur])[i] = (uint64_t)i;
 }
 
 // Deposit the live particles [0, alloc) of a species into one or two buffers.
@@ -585,7 +898,7 @@ __global__ void __launch_bounds__(256) k_deposit(CaseDev* __restrict__ C, int sp
   for (int p = threadIdx.x; p < ng; p += blockDim.x) sH[p] = 0;
   __syncthreads();
   const int cur = C->cur[sp];
-  const double* __restrict__ X = C->sp[sp].x[cur];
+  const EDP_GLOBAL double* __restrict__ X = G(C->sp[sp].x[cur]);
   const int64_t n = slots(C, sp);
   const double inv_dx = C->inv_dx;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -626,9 +939,9 @@ __global__ void __launch_bounds__(256) k_sort_hist(CaseDev* __restrict__ C, int 
   for (int p = threadIdx.x; p < ng; p += blockDim.x) sC[p] = 0;
   __syncthreads();
   const int cur = C->cur[sp];
-  const double* __restrict__ X = C->sp[sp].x[cur];
+  const EDP_GLOBAL double* __restrict__ X = G(C->sp[sp].x[cur]);
   const int64_t n = slots(C, sp);
-  const int64_t G = gridDim.x, per = (n + G - 1) / G;
+  const int64_t nb = gridDim.x, per = (n + nb - 1) / nb;
   const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const double x = X[i];
@@ -677,9 +990,9 @@ __global__ void __launch_bounds__(256) k_sort_scatter(CaseDev* __restrict__ C, i
   __syncthreads();
   const int cur = C->cur[sp], nxt = cur ^ 1;
   const SpeciesDev& S = C->sp[sp];
-  const double* __restrict__ X = S.x[cur];
+  const EDP_GLOBAL double* __restrict__ X = G(S.x[cur]);
   const int64_t n = slots(C, sp);
-  const int64_t G = gridDim.x, per = (n + G - 1) / G;
+  const int64_t nb = gridDim.x, per = (n + nb - 1) / nb;
   const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
   const double inv_dx = C->inv_dx;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
@@ -689,7 +1002,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(CaseDev* __restrict__ C, i
   __syncthreads();
   for (int p = threadIdx.x; p < ng - 1; p += blockDim.x) {
     const unsigned int c = sC[p];
-    sB[p] = c ? atomicAdd((unsigned long long*)&C->sort_cnt[p], (unsigned long long)c) : 0ull;
+    sB[p] = c ? gl_fetch_add(&C->sort_cnt[p], (unsigned long long)c) : 0ull;
     sC[p] = 0;
   }
   __syncthreads();
@@ -698,11 +1011,11 @@ __global__ void __launch_bounds__(256) k_sort_scatter(CaseDev* __restrict__ C, i
     if (!(x == x)) continue;
     const int c = cell_of(x, inv_dx, ng);
     const int64_t d = (int64_t)sB[c] + atomicAdd(&sC[c], 1u);
-    S.x[nxt][d] = x;
-    S.vx[nxt][d] = S.vx[cur][i];
-    S.vy[nxt][d] = S.vy[cur][i];
-    S.vz[nxt][d] = S.vz[cur][i];
-    S.uid[nxt][d] = S.uid[cur][i];
+    G(S.x[nxt])[d] = x;
+    G(S.vx[nxt])[d] = G(S.vx[cur])[i];
+    G(S.vy[nxt])[d] = G(S.vy[cur])[i];
+    G(S.vz[nxt])[d] = G(S.vz[cur])[i];
+    G(S.uid[nxt])[d] = G(S.uid[cur])[i];
   }
 }
 
@@ -710,6 +1023,7 @@ __global__ void k_sort_finish(CaseDev* __restrict__ C, int sp) {
   const int ng = C->ng;
   if (threadIdx.x == 0) {
     C->alloc[sp] = C->sort_cnt[ng];
+    C->n[sp] = C->sort_cnt[ng];  // the step's snapshot, taken before the sort
     C->cur[sp] ^= 1;
   }
   __syncthreads();
@@ -748,13 +1062,26 @@ __global__ void k_zero(int64_t* __restrict__ p, int64_t n) {
 // Host-side launchers (same translation unit as the kernels).
 // ---------------------------------------------------------------------------
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp) {
-  size_t b = (size_t)ng * 16;
-  if (flags & kDiagParticle) b += (size_t)ng * 24 + (sp == 0 ? (size_t)n_eepf * 4 : 0);
-  return b;
+  size_t doubles = (size_t)2 * ng;
+  if (flags & kDiagParticle)
+    doubles += (size_t)3 * ng + (sp == 0 && (flags & kDiagEepf) ? (size_t)(n_eepf + 1) / 2 : 0);
+  return doubles * 8 + (size_t)kQCap * 20;
 }
 
-hipError_t launch_field(CaseDev* d, int ng, hipStream_t st) {
-  hipLaunchKernelGGL(k_field, dim3(1), dim3(1024), (size_t)ng * 24, st, d);
+// Head of a step: 1 field workgroup + `scatter_blocks` collision workgroups.
+hipError_t launch_head(CaseDev* d, int ng, int mode, int scatter_blocks, hipStream_t st) {
+  const size_t lds = (size_t)ng * 24 + 64 * 8;
+  const dim3 grid(1 + scatter_blocks);
+  if (mode == 1)
+    hipLaunchKernelGGL(k_head<1>, grid, dim3(kBlock), lds, st, d);
+  else
+    hipLaunchKernelGGL(k_head<0>, grid, dim3(kBlock), lds, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_drain, dim3(blocks), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_drain_done, dim3(1), dim3(64), 0, st, d);
   return hipGetLastError();
 }
 
@@ -762,9 +1089,9 @@ hipError_t launch_particles(CaseDev* d, int sp, int blocks, int ng, uint32_t fla
                             hipStream_t st) {
   const size_t lds = particle_lds_bytes(ng, flags, n_eepf, sp);
   if (sp == 0)
-    hipLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(256), lds, st, d);
+    hipLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, d);
   else
-    hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(256), lds, st, d);
+    hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, d);
   return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_common import by_uid, compare_states, gpu_context, make_pair, say, set_both
+from gpu_common import by_uid, compare_states, gpu_context, make_pair, poisson_reference, say, set_both
 from paper_2103_09642_amd.workloads import base_case, random_state, synthetic_xsec, zero_xsec
 
 pytestmark = pytest.mark.gpu
@@ -73,12 +73,24 @@ def _one_step(ctx, xs, orc, c, st, step, nsteps=1):
     return g, o
 
 
+@pytest.fixture
+def poisson(ctx, request):
+    from paper_2103_09642_amd import edupic
+    ctx.set_option(edupic.OPT_POISSON, request.param)
+    yield request.param
+    ctx.set_option(edupic.OPT_POISSON, edupic.POISSON_FLUX)
+
+
+@pytest.mark.parametrize("poisson", [1, 0], indirect=True, ids=["thomas", "flux"])
 @pytest.mark.parametrize("step", [0, 5])
-def test_one_step_parity(ctx, xs_default, orc, step):
+def test_one_step_parity(ctx, xs_default, orc, step, poisson):
     """One full step (ion step and electron-only step) from an identical
     state with hot electrons, high pressure (many collisions incl.
-    ionization) and particles at/near both walls."""
-    say(f"test_one_step_parity step={step}")
+    ionization) and particles at/near both walls.  With the sequential
+    Thomas solve the fields are bit-identical; with the parallel flux solve
+    they agree to 1e-12 of the field scale, and the deposit after the step is
+    compared with the oracle's deposit of the GPU's own positions."""
+    say(f"test_one_step_parity step={step} poisson={poisson}")
     c = _case(pressure_pa=50.0, weight=2e5, n_grid=400, ion_subcycle=5, cap_e=200_000, cap_i=200_000)
     st = random_state(60_000, 50_000, c["gap_m"], seed=11 + step, te_ev=4.0, hot_frac=0.3, hot_ev=90.0,
                       ion_energy_ev=30.0)
@@ -86,8 +98,18 @@ def test_one_step_parity(ctx, xs_default, orc, step):
     rg, pg, eg = g.fields()
     ro, po, eo = o.fields()
     assert np.array_equal(rg, ro), "rho"
-    assert np.array_equal(pg, po), "phi (Thomas, same operation order)"
-    assert np.array_equal(eg, eo), "E"
+    if poisson == 1:
+        assert np.array_equal(pg, po), "phi (Thomas, same operation order)"
+        assert np.array_equal(eg, eo), "E"
+    else:
+        # the flux solve is within 1e-14 of an 80-bit solution; the oracle's
+        # sequential Thomas sweep carries ~1e-13 rounding of its own
+        dx = c["gap_m"] / (c["n_grid"] - 1)
+        v_left = float(pg[0])
+        eref = poisson_reference(rg, dx, v_left)
+        assert float(np.max(np.abs(eg - eref))) <= 1e-14 * float(np.abs(eref).max()), "E vs extended precision"
+        assert np.max(np.abs(eg - eo)) <= 1e-12 * np.abs(eo).max(), "E"
+        assert np.max(np.abs(pg - po)) <= 1e-12 * np.abs(po).max(), "phi"
     cg, co = g.counts(), o.counts()
     for k in ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz", "anomaly"):
         assert cg[k if k != "anomaly" else "anomalies"] == co[k], k
@@ -95,12 +117,24 @@ def test_one_step_parity(ctx, xs_default, orc, step):
     if step % 5 == 0:
         assert co["coll_i"] > 10
     m = 0
+    # a field difference dE moves v_x by dE*factor: judge v_x on the scale of
+    # one step's largest field kick as well
+    kick = {0: np.abs(eo).max() * c["dt_e"] * 1.602176634e-19 / 9.1093837015e-31,
+            1: np.abs(eo).max() * c["dt_e"] * c["ion_subcycle"] * 1.602176634e-19 / (39.948 * 1.66053906660e-27)}
     for sp in (0, 1):
-        m += compare_states(g.get_state(sp), o.get_state(sp), 1e-12, f"sp{sp}")
+        fl = {k: kick[sp] for k in ("vx", "vy", "vz")}  # collisions mix the components
+        m += compare_states(g.get_state(sp), o.get_state(sp), 1e-12, f"sp{sp}", floors=fl if poisson == 0 else None)
     ge, gi = g.deposit()
     oe, oi = o.deposit()
-    assert np.array_equal(ge, oe), "electron deposit after the step"
-    assert np.array_equal(gi, oi), "ion deposit after the step"
+    if poisson == 1:
+        assert np.array_equal(ge, oe), "electron deposit after the step"
+        assert np.array_equal(gi, oi), "ion deposit after the step"
+    else:
+        inv_dx = 1.0 / (c["gap_m"] / (c["n_grid"] - 1))
+        assert np.array_equal(ge, orc.deposit(g.get_state(0)["x"], c["n_grid"], inv_dx))
+        assert int(ge.sum()) == int(oe.sum())  # same electrons
+        # ions: the density held until the next ion step
+        assert np.array_equal(gi, oi)
     say(f"  bit mismatches in state components: {m}")
     g.destroy()
 
@@ -130,16 +164,18 @@ def test_empty_case_gives_vacuum_field(ctx, orc):
     set_both(g, o, {"e": empty, "i": empty}, 0)
     g.advance_steps(3)
     o.step(3)
-    _, _, eg = g.fields()
-    _, _, eo = o.fields()
-    assert np.array_equal(eg, eo)
+    _, pg, eg = g.fields()
+    _, po, eo = o.fields()
+    assert np.allclose(eg, eo, rtol=1e-13)
+    assert np.allclose(pg, po, rtol=0, atol=1e-12 * 100.0)
     assert np.allclose(eg, 100.0 / c["gap_m"], rtol=1e-10)
     assert g.counts()["n_e"] == 0
     g.destroy()
 
 
 def test_run_twice_and_launch_shape_are_bit_identical(ctx, xs_default):
-    """Same state twice, with different launch sizes and with hipGraph
+    """Same state several times, with different compaction/sort intervals
+    (different particle orders and chunk assignments) and with hipGraph
     capture: bit-identical particles, deposits and counters (integer
     deposits, counter-based random numbers keyed by particle identity)."""
     say("test_run_twice_and_launch_shape_are_bit_identical")
@@ -147,9 +183,8 @@ def test_run_twice_and_launch_shape_are_bit_identical(ctx, xs_default):
     c = _case(pressure_pa=30.0, weight=1e5, cap_e=120_000, cap_i=120_000)
     st = random_state(40_000, 40_000, c["gap_m"], seed=9, te_ev=3.0, hot_frac=0.2, hot_ev=70.0)
     res = []
-    for mode, ppt, sort_every in ((0, 4, 100), (0, 1, 7), (1, 4, 5), (0, 16, 1000)):
+    for mode, sort_every in ((0, 100), (0, 7), (1, 5), (0, 1000), (1, 1)):
         ctx.set_option(edupic.OPT_MODE, mode)
-        ctx.set_option(edupic.OPT_PPT, ppt)
         ctx.set_option(edupic.OPT_SORT_EVERY, sort_every)
         g = ctx.create_case(c)
         g.set_state(0, st["e"], 0)
@@ -158,7 +193,6 @@ def test_run_twice_and_launch_shape_are_bit_identical(ctx, xs_default):
         res.append((by_uid(g.get_state(0)), by_uid(g.get_state(1)), g.deposit(), g.counts()))
         g.destroy()
     ctx.set_option(edupic.OPT_MODE, 0)
-    ctx.set_option(edupic.OPT_PPT, 4)
     ctx.set_option(edupic.OPT_SORT_EVERY, 100)
     for r in res[1:]:
         for sp in (0, 1):
