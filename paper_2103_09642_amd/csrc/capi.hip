@@ -105,7 +105,7 @@ struct edp_ctx {
 namespace {
 
 struct Layout {
-  size_t off_case, off_part[2][2][5], off_cq[2][2][2], off_cqb[2][2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
+  size_t off_case, off_part[2][2][5], off_cq[2][2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
       off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[4], off_eepf, off_sort, total;
   int64_t cap[2];
 };
@@ -153,13 +153,11 @@ Layout layout(const edp_case_desc* c, int nbins) {
   for (int sp = 0; sp < 2; ++sp)
     for (int set = 0; set < 2; ++set)
       for (int a = 0; a < 5; ++a) L.off_part[sp][set][a] = take((size_t)L.cap[sp] * 8);
-  for (int sp = 0; sp < 2; ++sp)
-    for (int b = 0; b < 2; ++b) {
-      L.off_cq[sp][b][0] = take((size_t)L.cap[sp] * 4);
-      L.off_cq[sp][b][1] = take((size_t)L.cap[sp] * 8);
-    }
-  for (int b = 0; b < 2; ++b)
-    for (int a = 0; a < 2; ++a) L.off_cqb[b][a] = take((size_t)L.cap[0] * 4);
+  for (int sp = 0; sp < 2; ++sp) {
+    const size_t chunks = (size_t)((L.cap[sp] + kChunk - 1) / kChunk);
+    L.off_cq[sp][0] = take(chunks * kChunk * 4);  // events
+    L.off_cq[sp][1] = take(chunks * 8);           // chunk records
+  }
   for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
   const size_t ng = (size_t)c->n_grid;
   L.off_rden = take(ng * 8);
@@ -576,17 +574,11 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
       h.sp[sp].uid[set] = (uint64_t*)(c->arena + L.off_part[sp][set][4]);
     }
   }
-  for (int sp = 0; sp < 2; ++sp)
-    for (int b = 0; b < 2; ++b) {
-      h.cq_idx[sp][b] = (int32_t*)(c->arena + L.off_cq[sp][b][0]);
-      h.cq_r[sp][b] = (double*)(c->arena + L.off_cq[sp][b][1]);
-    }
-  for (int b = 0; b < 2; ++b) {
-    h.cq_be[b] = (int32_t*)(c->arena + L.off_cqb[b][0]);
-    h.cq_bi[b] = (int32_t*)(c->arena + L.off_cqb[b][1]);
+  for (int sp = 0; sp < 2; ++sp) {
+    h.cq_ent[sp] = (int32_t*)(c->arena + L.off_cq[sp][0]);
+    h.cq_rec[sp] = (int32_t*)(c->arena + L.off_cq[sp][1]);
   }
-  h.cq_buf_pending = 1;
-  h.cq_step_pending = -1;
+  h.q_valid = 0;
   double* tabs[7];
   for (int t = 0; t < 7; ++t) tabs[t] = (double*)(c->arena + L.off_tab[t]);
   h.nsig_e = tabs[0];
@@ -937,9 +929,7 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
   t.error = 0;
   t.diag_steps = 0;
   t.diag_ion_steps = 0;
-  for (int sp = 0; sp < 2; ++sp) t.cq_n[sp][0] = t.cq_n[sp][1] = 0;  // nothing pending
-  t.cq_buf_pending = (int32_t)((step + 1) & 1);
-  t.cq_step_pending = step - 1;
+  t.q_valid = 0;  // nothing pending
   if ((r = write_dyn(ctx, c, t))) return r;
   c->step = step;
   c->est[species] = n;

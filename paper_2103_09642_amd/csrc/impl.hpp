@@ -75,19 +75,26 @@ struct CaseDev {
   int64_t *acc_je, *acc_ji, *acc_w, *acc_e;                   // [3][ng] per step
   int64_t *eepf;                                              // [n_eepf]
   int64_t *sort_cnt;                                          // [ng + 1] scratch
-  // collision queues, double-buffered by step parity, capacity = cap:
-  int32_t* cq_idx[2][2];  // [species][buffer] slot of the colliding particle
-  double* cq_r[2][2];     // [species][buffer] its process-selection number
-  int32_t* cq_be[2];      // [buffer] slot of an ionization's new electron or -1
-  int32_t* cq_bi[2];      // [buffer] slot of its new ion or -1
+  // Collision queue of the last particle step, per species.  Chunk c (slots
+  // [c*kChunk, (c+1)*kChunk)) writes its events to cq_ent[c*kChunk + k] and
+  // its totals to cq_rec[2c] = events | ionizations << 16 and
+  // cq_rec[2c+1] = absorbed at x=0 | absorbed at x=L << 16, so no two
+  // workgroups ever write the same word.  An event is
+  // slot-in-chunk | process << 10 | ionization rank in the chunk << 12.
+  int32_t* cq_ent[2];
+  int32_t* cq_rec[2];
   // ---- dynamic (device-mutated) -----------------------------------------
-  int64_t step;
-  int64_t n[2];       // slots processed this step (snapshot of alloc at step start)
-  int64_t alloc[2];   // slots in use: live + tombstones + births
+  int64_t step;       // next step whose head runs (advanced by the electron kernel)
+  int64_t pstep;      // step of the particle kernels (set by the head)
+  int64_t n[2];       // slots the particle kernels process
+  int64_t alloc[2];   // slots in use: live + tombstones (equal to n between kernels)
   int32_t cur[2];     // current buffer set per species
-  int64_t cq_n[2][2];       // [species][buffer] queued collisions
-  int64_t cq_step_pending;  // step whose queue is still to be applied
-  int32_t cq_buf_pending;   // and its buffer
+  // the pending collision queue: written by the particle kernels of step
+  // q_step, applied by the next head (or a drain)
+  int64_t q_step;
+  int64_t q_base[2];  // slot count of that step: births go to q_base + rank
+  int32_t q_nblk[2];  // chunks that wrote records (0: no events of that species)
+  int32_t q_valid;    // 1 while not yet applied by a drain
   int32_t pad2;
   int64_t diag_steps, diag_ion_steps;
   int64_t ctr[kNumCtr];

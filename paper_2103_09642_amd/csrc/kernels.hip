@@ -174,23 +174,25 @@ __device__ __forceinline__ unsigned long long gl_fetch_add(int64_t* a, unsigned 
 }
 
 // LDS counters of a particle workgroup.
-enum { kLAbsPow = 0, kLAbsGnd, kLColl, kLIoniz, kLDrop, kLLiveE, kLLiveI, kLN };
+enum { kLAbsPow = 0, kLAbsGnd, kLN };
 
-// Exclusive scan of one int per thread across the workgroup; *total gets
-// the sum.  sW: 32 ints of LDS scratch.
-__device__ __forceinline__ int block_exclusive_scan_int(int x, int* sW, int* total) {
+// Exclusive scan of one integer per thread across the workgroup; *total
+// gets the sum.  scratch: 64 int64 of LDS.
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan_t(T x, int64_t* scratch, T* total) {
+  T* sW = (T*)scratch;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int inc = x;
+  T inc = x;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(inc, off, 64);
+    const T y = __shfl_up(inc, off, 64);
     if (lane >= off) inc += y;
   }
   if (lane == 63) sW[wv] = inc;
   __syncthreads();
-  int before = 0, tot = 0;
+  T before = 0, tot = 0;
   for (int w = 0; w < nw; ++w) {
-    const int v = sW[w];
+    const T v = sW[w];
     if (w < wv) before += v;
     tot += v;
   }
@@ -243,7 +245,6 @@ __device__ __forceinline__ double block_exclusive_scan(double x, double* sW, dou
 // scale, closer than the sequential sweep.
 // MODE 1 runs the Thomas algorithm itself in one thread, operation for
 // operation as the sequential definition (bit-reproducible, slow).
-// The workgroup also does the per-step bookkeeping and advances the step.
 // ---------------------------------------------------------------------------
 constexpr int kFieldRows = 8;  // rows per thread of the flux scans (n_grid <= 2048)
 
@@ -367,42 +368,27 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ C, double* fsm
       G(C->rho)[p] = sRho[p];
     }
   }
-  if (threadIdx.x == 0) {
-    // per-step bookkeeping: snapshot the particle slots of this step; after a
-    // capacity overflow alloc may have run past the capacity, never process
-    // beyond it
-    for (int sp = 0; sp < 2; ++sp) {
-      int64_t a = C->alloc[sp];
-      if (a > C->sp[sp].cap) {
-        a = C->sp[sp].cap;
-        C->alloc[sp] = a;
-      }
-      C->n[sp] = a;
-      C->cq_n[sp][s & 1] = 0;  // this step's collision queue
-    }
-    C->ctr[kPstepE] += C->ctr[kLiveE];
-    if (ion_step) C->ctr[kPstepI] += C->ctr[kLiveI];
-    C->diag_steps += 1;
-    if (ion_step) C->diag_ion_steps += 1;
-    C->phi_valid = MODE == 1;
-    C->step = s + 1;  // particle kernels of this step read step-1
-  }
+  if (threadIdx.x == 0) C->phi_valid = MODE == 1;
 }
 
 // ---------------------------------------------------------------------------
 // Collisions (step 6).  The particle kernel tests every particle, picks the
 // process of those that collide (partition of [0,1) into sigma_k/sigma_tot),
-// allocates and deposits the particles an ionization creates, and queues the
-// event.  The new velocities -- COM kinematics, scattering angles, Euler
-// rotation, the ionization energy split -- are computed from the queue by
-// extra workgroups of the next step's field launch (they do not depend on
-// each other), so this long transcendental code runs off the streaming path
-// and overlaps the field solve.
+// deposits the charge of the particles an ionization creates, and queues the
+// event in its chunk's part of the queue.  The new velocities -- COM
+// kinematics, scattering angles, Euler rotation, the ionization energy
+// split -- and the newborns' slots are computed from the queue by extra
+// workgroups of the next step's field launch (they do not depend on each
+// other), so this long transcendental code runs off the streaming path and
+// overlaps the field solve.
 // ---------------------------------------------------------------------------
 
-// Electron-Ar scattering of queued particle i (state after the push).
-__device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_t i, double r_proc, int64_t se, int64_t si,
-                                 int64_t s) {
+// Electron-Ar scattering of queued particle i (state after the push) by
+// process proc (0 elastic, 1 excitation, 2 ionization).  An ionization also
+// writes its newborns: the ejected electron at slot be and the ion at slot
+// bi (-1: dropped at capacity), both at the parent's position.
+__device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_t i, int proc, int64_t be,
+                                                 int64_t bi, int64_t s) {
   const int ce = C->cur[0];
   EDP_GLOBAL double* __restrict__ VX = G(C->sp[0].vx[ce]);
   EDP_GLOBAL double* __restrict__ VY = G(C->sp[0].vy[ce]);
@@ -413,22 +399,11 @@ __device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_
   const uint32_t st = (uint32_t)s;
   const double v2 = vxn * vxn + vy * vy + vz * vz;
   const double v = sqrt(v2);
-  const double energy = 0.5 * kEMass * v2 / kEvToJ;
-  const int idx = energy_bin(energy, C->de_cs, C->nbins);
   double r_chi, r_eta;
   uniform2(seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
   const double f1 = kEMass / (kEMass + kArMass);
   const double f2 = kArMass / (kEMass + kArMass);
   const double wx = f1 * vxn, wy = f1 * vy, wz = f1 * vz;
-  const double s_el = G(C->sig_el)[idx], s_exc = G(C->sig_exc)[idx], s_ion = G(C->sig_ion)[idx];
-  const double s_tot = s_el + s_exc + s_ion;
-  int proc;
-  if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
-    proc = 0;
-  else if (r_proc < (s_el + s_exc) / s_tot)
-    proc = 1;
-  else
-    proc = 2;
   const double eta = kTwoPi * r_eta;
   double ox, oy, oz;
   if (proc < 2) {
@@ -472,21 +447,29 @@ __device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_
       sn_ej = sqrt(1.0 - cs_ej * cs_ej);
     }
     scatter(vxn, vy, vz, v, g_sc, f2, cs_sc, sn_sc, eta, wx, wy, wz, ox, oy, oz);
-    if (se >= 0) {  // the ejected electron, scattered about the same w
-      double ex_, ey_, ez_;
-      scatter(vxn, vy, vz, v, g_ej, f2, cs_ej, sn_ej, eta + kPi, wx, wy, wz, ex_, ey_, ez_);
-      VX[se] = ex_;
-      VY[se] = ey_;
-      VZ[se] = ez_;
-    }
-    if (si >= 0) {  // the new ion: a thermal gas velocity
-      const int ci = C->cur[1];
-      double z0, z1, z2;
-      normals3(seed, child_uid(uid, s, 2), st, 1u, 2u, 1u, z0, z1, z2);
-      const double sa = C->sigma_a;
-      G(C->sp[1].vx[ci])[si] = sa * z0;
-      G(C->sp[1].vy[ci])[si] = sa * z1;
-      G(C->sp[1].vz[ci])[si] = sa * z2;
+    if (be >= 0 || bi >= 0) {
+      const double x = G(C->sp[0].x[ce])[i];
+      if (be >= 0) {  // the ejected electron, scattered about the same w
+        double ex_, ey_, ez_;
+        scatter(vxn, vy, vz, v, g_ej, f2, cs_ej, sn_ej, eta + kPi, wx, wy, wz, ex_, ey_, ez_);
+        G(C->sp[0].x[ce])[be] = x;
+        VX[be] = ex_;
+        VY[be] = ey_;
+        VZ[be] = ez_;
+        G(C->sp[0].uid[ce])[be] = child_uid(uid, s, 1);
+      }
+      if (bi >= 0) {  // the new ion: a thermal gas velocity
+        const int ci = C->cur[1];
+        const uint64_t cu = child_uid(uid, s, 2);
+        double z0, z1, z2;
+        normals3(seed, cu, st, 1u, 2u, 1u, z0, z1, z2);
+        const double sa = C->sigma_a;
+        G(C->sp[1].x[ci])[bi] = x;
+        G(C->sp[1].vx[ci])[bi] = sa * z0;
+        G(C->sp[1].vy[ci])[bi] = sa * z1;
+        G(C->sp[1].vz[ci])[bi] = sa * z2;
+        G(C->sp[1].uid[ci])[bi] = cu;
+      }
     }
   }
   VX[i] = ox;
@@ -494,9 +477,9 @@ __device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_
   VZ[i] = oz;
 }
 
-// Ar+ + Ar scattering of queued ion i with the thermal target of its test
-// (redrawn from the same counter, so it is the same atom).
-__device__ __forceinline__ void ion_scatter(CaseDev* __restrict__ C, int64_t i, double r_proc, int64_t s) {
+// Ar+ + Ar scattering of queued ion i (proc 0 isotropic, 1 backward) with the
+// thermal target of its test (redrawn from the same counter: the same atom).
+__device__ __forceinline__ void ion_scatter(CaseDev* __restrict__ C, int64_t i, int proc, int64_t s) {
   const int cur = C->cur[1];
   EDP_GLOBAL double* __restrict__ VX = G(C->sp[1].vx[cur]);
   EDP_GLOBAL double* __restrict__ VY = G(C->sp[1].vy[cur]);
@@ -510,16 +493,12 @@ __device__ __forceinline__ void ion_scatter(CaseDev* __restrict__ C, int64_t i, 
   const double sa = C->sigma_a;
   const double vax = sa * z0, vay = sa * z1, vaz = sa * z2;
   const double gx = vxn - vax, gy = vy - vay, gz = vz - vaz;
-  const double g2 = gx * gx + gy * gy + gz * gz;
-  const double g = sqrt(g2);
-  const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-  const int idx = energy_bin(energy, C->de_cs, C->nbins);
+  const double g = sqrt(gx * gx + gy * gy + gz * gz);
   double r_chi, r_eta;
   uniform2(seed, uid, st, tag(1, 0, 3), r_chi, r_eta);
   const double wx = 0.5 * (vxn + vax), wy = 0.5 * (vy + vay), wz = 0.5 * (vz + vaz);
-  const double s_iso = G(C->sig_iso)[idx], s_back = G(C->sig_back)[idx];
   double cos_chi, sin_chi;
-  if (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) {
+  if (proc == 0) {
     cos_chi = 1.0 - 2.0 * r_chi;
     sin_chi = sqrt(1.0 - cos_chi * cos_chi);
   } else {
@@ -533,40 +512,147 @@ __device__ __forceinline__ void ion_scatter(CaseDev* __restrict__ C, int64_t i, 
   VZ[i] = oz;
 }
 
-// The queued collisions of the last particle step, both species, spread over
-// workgroups blk = 0..nblk-1 (grid-stride).
-__device__ __forceinline__ void scatter_pending(CaseDev* __restrict__ C, int blk, int nblk) {
-  const int qb = C->cq_buf_pending;
-  const int64_t s = C->cq_step_pending;
-  const int64_t ne = C->cq_n[0][qb], ni = C->cq_n[1][qb];
-  const int64_t stride = (int64_t)nblk * blockDim.x;
-  const int64_t e0 = (int64_t)blk * blockDim.x + threadIdx.x;
-  for (int64_t e = e0; e < ne; e += stride)
-    electron_scatter(C, G(C->cq_idx[0][qb])[e], G(C->cq_r[0][qb])[e], G(C->cq_be[qb])[e], G(C->cq_bi[qb])[e], s);
-  for (int64_t e = e0; e < ni; e += stride) ion_scatter(C, G(C->cq_idx[1][qb])[e], G(C->cq_r[1][qb])[e], s);
+// Apply the pending collision queue.  Workgroup blk of nblk takes a
+// contiguous range of chunks of each species; newborns of chunk c go to
+// q_base + (ionizations of chunks < c) + rank, so every workgroup first sums
+// the ionization counts before its range.  No atomics: the slot of every
+// event and newborn follows from the chunk records alone.  Workgroup nblk-1
+// also folds the records into the counters and the slot counts.
+constexpr int kApplyChunks = kBlock;  // chunks per round of a workgroup
+
+__device__ __forceinline__ void apply_queue(CaseDev* __restrict__ C, int blk, int nblk) {
+  __shared__ int sQo[kApplyChunks];       // events before chunk t of the round
+  __shared__ int64_t sZo[kApplyChunks];   // newborn index of chunk t's first ionization
+  __shared__ int64_t sRed[64];
+  const int64_t s = C->q_step;
+  const bool book = blk == nblk - 1;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t nb = C->q_nblk[sp];
+    const EDP_GLOBAL int32_t* __restrict__ rec = G(C->cq_rec[sp]);
+    const EDP_GLOBAL int32_t* __restrict__ ent = G(C->cq_ent[sp]);
+    const int64_t c0 = nb * blk / nblk, c1 = nb * (blk + 1) / nblk;
+    // ionizations of the chunks before this range (electrons only)
+    int64_t zrun = 0;
+    if (sp == 0) {
+      int64_t z = 0;
+      for (int64_t c = threadIdx.x; c < c0; c += blockDim.x) z += rec[2 * c] >> 16;
+      (void)block_exclusive_scan_t<int64_t>(z, sRed, &zrun);
+    }
+    const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
+    const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
+    for (int64_t cb = c0; cb < c1; cb += kApplyChunks) {
+      const int64_t c = cb + threadIdx.x;
+      const int r0 = c < c1 ? rec[2 * c] : 0;
+      const int q = r0 & 0xFFFF, z = r0 >> 16;
+      int qtot;
+      int64_t ztot;
+      const int qo = block_exclusive_scan_t<int>(q, (int64_t*)sRed, &qtot);
+      const int64_t zo = block_exclusive_scan_t<int64_t>((int64_t)z, sRed, &ztot);
+      sQo[threadIdx.x] = qo;
+      sZo[threadIdx.x] = zrun + zo;
+      __syncthreads();
+      const int nc = (int)((c1 - cb) < kApplyChunks ? (c1 - cb) : kApplyChunks);
+      for (int e = threadIdx.x; e < qtot; e += blockDim.x) {
+        // the chunk holding event e: the last t with sQo[t] <= e
+        int lo_t = 0, hi_t = nc - 1;
+        while (lo_t < hi_t) {
+          const int mid = (lo_t + hi_t + 1) >> 1;
+          if (sQo[mid] <= e)
+            lo_t = mid;
+          else
+            hi_t = mid - 1;
+        }
+        const int64_t ch = cb + lo_t;
+        const int code = ent[ch * kChunk + (e - sQo[lo_t])];
+        const int64_t i = ch * kChunk + (code & 1023);
+        const int proc = (code >> 10) & 3;
+        if (sp == 0) {
+          int64_t be = -1, bi = -1;
+          if (proc == 2) {
+            const int64_t k = sZo[lo_t] + (code >> 12);
+            if (base_e + k < cap_e) be = base_e + k;
+            if (base_i + k < cap_i) bi = base_i + k;
+          }
+          electron_scatter(C, i, proc, be, bi, s);
+        } else {
+          ion_scatter(C, i, proc, s);
+        }
+      }
+      zrun += ztot;
+      __syncthreads();
+    }
+  }
+  if (!book) return;
+  // Totals of all chunks: collision, ionization and absorption counters,
+  // newborns placed, slot counts for the next step.
+  int64_t tq[2] = {0, 0}, tz = 0, tap[2] = {0, 0}, tag_[2] = {0, 0};
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t nb = C->q_nblk[sp];
+    const EDP_GLOBAL int32_t* __restrict__ rec = G(C->cq_rec[sp]);
+    int64_t a = 0, b = 0, d = 0, f = 0;
+    for (int64_t c = threadIdx.x; c < nb; c += blockDim.x) {
+      const int r0 = rec[2 * c], r1 = rec[2 * c + 1];
+      a += r0 & 0xFFFF;
+      b += r0 >> 16;
+      d += r1 & 0xFFFF;
+      f += r1 >> 16;
+    }
+    (void)block_exclusive_scan_t<int64_t>(a, sRed, &tq[sp]);
+    (void)block_exclusive_scan_t<int64_t>(d, sRed, &tap[sp]);
+    (void)block_exclusive_scan_t<int64_t>(f, sRed, &tag_[sp]);
+    if (sp == 0) (void)block_exclusive_scan_t<int64_t>(b, sRed, &tz);
+  }
+  if (threadIdx.x == 0) {
+    const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
+    const int64_t room_e = C->sp[0].cap - base_e, room_i = C->sp[1].cap - base_i;
+    const int64_t ok_e = tz < room_e ? tz : (room_e > 0 ? room_e : 0);
+    const int64_t ok_i = tz < room_i ? tz : (room_i > 0 ? room_i : 0);
+    C->alloc[0] = C->n[0] = base_e + ok_e;
+    C->alloc[1] = C->n[1] = base_i + ok_i;
+    C->ctr[kCollE] += tq[0];
+    C->ctr[kCollI] += tq[1];
+    C->ctr[kIoniz] += tz;
+    C->ctr[kAbsEPow] += tap[0];
+    C->ctr[kAbsEGnd] += tag_[0];
+    C->ctr[kAbsIPow] += tap[1];
+    C->ctr[kAbsIGnd] += tag_[1];
+    C->ctr[kLiveE] += ok_e - tap[0] - tag_[0];
+    C->ctr[kLiveI] += ok_i - tap[1] - tag_[1];
+    if (ok_e < tz || ok_i < tz) {
+      C->ctr[kDropped] += (tz - ok_e) + (tz - ok_i);
+      C->error = 1;
+    }
+  }
 }
 
-// Head of a step: workgroup 0 solves the field of step s, the others apply
-// the collisions queued by step s-1.
+// Head of step s: workgroup 0 solves the field, the others apply the queue
+// of step s-1; the last of them also does the step's bookkeeping.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_head(CaseDev* __restrict__ C) {
   extern __shared__ double hsm[];
-  if (blockIdx.x == 0)
+  if (blockIdx.x == 0) {
     field_solve<MODE>(C, hsm);
-  else
-    scatter_pending(C, (int)blockIdx.x - 1, (int)gridDim.x - 1);
+    return;
+  }
+  const int blk = (int)blockIdx.x - 1, nblk = (int)gridDim.x - 1;
+  if (C->q_valid) apply_queue(C, blk, nblk);
+  if (blk == nblk - 1 && threadIdx.x == 0) {
+    const int64_t s = C->step;
+    const bool ion_step = (s % C->nsub) == 0;
+    C->ctr[kPstepE] += C->ctr[kLiveE];
+    if (ion_step) C->ctr[kPstepI] += C->ctr[kLiveI];
+    C->diag_steps += 1;
+    if (ion_step) C->diag_ion_steps += 1;
+    C->pstep = s;
+  }
 }
 
-// Apply pending collisions before the host looks at the state.
+// Apply the pending queue before the host looks at the state.
 __global__ void __launch_bounds__(kBlock) k_drain(CaseDev* __restrict__ C) {
-  scatter_pending(C, (int)blockIdx.x, (int)gridDim.x);
+  if (C->q_valid) apply_queue(C, (int)blockIdx.x, (int)gridDim.x);
 }
 __global__ void k_drain_done(CaseDev* __restrict__ C) {
-  if (threadIdx.x == 0) {
-    const int qb = C->cq_buf_pending;
-    C->cq_n[0][qb] = 0;
-    C->cq_n[1][qb] = 0;
-  }
+  if (threadIdx.x == 0) C->q_valid = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -578,32 +664,35 @@ __global__ void k_drain_done(CaseDev* __restrict__ C) {
 // particle: gather E from LDS, leapfrog, wall test, the collision test (one
 // Philox call and one exp for an electron; the thermal target draw first for
 // an ion), store x and v_x, deposit the new x into the workgroup's LDS
-// histogram.  A colliding particle's process is selected here (ionizations
-// also allocate and deposit their two newborns) and the event is queued in
-// LDS; the chunk's queue goes to the case's collision queue at the end.
+// histogram.  A colliding particle's process is selected here; an
+// ionization deposits its two newborns (same position as the parent: the
+// electron doubles the parent's share, the ion goes to the next ion step's
+// density).  Events are written to the chunk's own part of the queue, with
+// the chunk totals in its record: the kernel has no returning atomics and no
+// two workgroups share a counter.
 //
 // Dynamic LDS: E[ng] double, H[ng] deposit; with particle diagnostics also
-// J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32); then the queue.
+// J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).
 // ---------------------------------------------------------------------------
-constexpr int kQCap = kChunk;  // the queue holds a whole chunk
-
-__device__ __forceinline__ size_t queue_offset_doubles(int ng, uint32_t fl, int n_eepf, int sp) {
-  size_t o = (size_t)2 * ng;
-  if (fl & kDiagParticle) o += (size_t)3 * ng + (sp == 0 && (fl & kDiagEepf) ? (size_t)(n_eepf + 1) / 2 : 0);
-  return o;
-}
-
 template <int SP>
 __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
   extern __shared__ double psm[];
-  __shared__ unsigned long long sCtr[kLN];
-  __shared__ int sScan[32];
-  const int64_t s = C->step - 1;  // the head of this step already advanced it
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    C->cq_buf_pending = (int)(s & 1);
-    C->cq_step_pending = s;
-  }
+  __shared__ unsigned int sCtr[kLN];
+  __shared__ int64_t sScan[64];
+  const int64_t s = C->pstep;
   const int64_t n = C->n[SP];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // this step's queue: read by the next head (or a drain)
+    C->q_step = s;
+    C->q_base[SP] = n;
+    C->q_nblk[SP] = (int32_t)((n + kChunk - 1) / kChunk);
+    if (SP == 0) {
+      C->q_base[1] = C->n[1];
+      C->q_nblk[1] = 0;  // set by the ion kernel on ion steps
+      C->q_valid = 1;
+      C->step = s + 1;
+    }
+  }
   const int64_t lo = (int64_t)blockIdx.x * kChunk;
   if (lo >= n) return;  // whole workgroup: no live slots in this chunk
   const int64_t hi = lo + kChunk < n ? lo + kChunk : n;
@@ -619,10 +708,6 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
   unsigned long long* sW = sJ + ng;
   unsigned long long* sEn = sW + ng;
   unsigned int* sF = (unsigned int*)(sEn + ng);
-  double* sQr = psm + queue_offset_doubles(ng, fl, n_eepf, SP);
-  int* sQi = (int*)(sQr + kQCap);
-  int* sQe = sQi + kQCap;
-  int* sQj = sQe + kQCap;
   for (int p = threadIdx.x; p < ng; p += blockDim.x) {
     sE[p] = G(C->efield)[p];
     sH[p] = 0;
@@ -647,6 +732,10 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
   const double dt = SP == 0 ? C->dt_e : C->dt_i;
   const double factor = SP == 0 ? C->factor_e : C->factor_i;
   const EDP_GLOBAL double* __restrict__ nsig = G(SP == 0 ? C->nsig_e : C->nsig_i);
+  const EDP_GLOBAL double* __restrict__ sig0 = G(SP == 0 ? C->sig_el : C->sig_iso);
+  const EDP_GLOBAL double* __restrict__ sig1 = G(SP == 0 ? C->sig_exc : C->sig_back);
+  const EDP_GLOBAL double* __restrict__ sig2 = G(C->sig_ion);
+  int64_t* const cnt_i_next = C->cnt_i + ((kion + 1) % 3) * ng;
   const double de_cs = C->de_cs;
   const int nbins = C->nbins;
   const uint64_t seed = C->seed;
@@ -654,8 +743,8 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
   const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf;
   const double sa = C->sigma_a;
 
-  unsigned int my_abs_pow = 0, my_abs_gnd = 0, my_coll = 0;
-  int my_q = 0;  // this thread's queued collisions, in its own kPerThread LDS slots
+  unsigned int my_abs_pow = 0, my_abs_gnd = 0;
+  int my_q = 0, my_z = 0;  // this thread's events and ionizations
   // All loads of the thread's kPerThread particles are issued before any
   // store: on this target stores count against the same wait counter as
   // loads, so interleaving them would make each load wait for the stores.
@@ -676,11 +765,12 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
   }
   double xo[kPerThread], vxo[kPerThread];
   bool st_ok[kPerThread];
+  int qe[kPerThread];  // queued event of particle u, or -1
 #pragma unroll
   for (int u = 0; u < kPerThread; ++u) {
-    const int64_t i = lo + u * kBlock + threadIdx.x;
     const double x = xs[u];
     st_ok[u] = false;
+    qe[u] = -1;
     if (!(x == x)) continue;  // past the end, or absorbed earlier (tombstone)
     st_ok[u] = true;
     const double vx = vxs[u], vy = vys[u], vz = vzs[u];
@@ -718,6 +808,8 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
         }
       }
     }
+    xo[u] = xn;
+    vxo[u] = vxn;
     // Step 5: absorbing electrodes.
     if (xn < 0.0 || xn > L_gap) {
       if (xn < 0.0)
@@ -725,7 +817,6 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
       else
         ++my_abs_gnd;
       xo[u] = __longlong_as_double(0x7FF8000000000000LL);
-      vxo[u] = vxn;
       continue;
     }
     // Step 6: collision test, P = 1 - exp(-n sigma_tot(E) g dt), collide iff R < P.
@@ -751,59 +842,35 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
       p_coll = 1.0 - exp(-nu * dt);
       uniform2(seed, us[u], st, tag(1, 0, 2), r_coll, r_proc);
     }
-    xo[u] = xn;
-    vxo[u] = vxn;
-    {
-      long long r;
-      const int q = deposit_split(xn, inv_dx, ng, r);
-      lds_add(&sH[q], 4294967296LL - r);
-      lds_add(&sH[q + 1], r);
-    }
+    long long r;
+    const int q = deposit_split(xn, inv_dx, ng, r);
+    long long mult = 1;  // the parent, plus the newborn electron of an ionization
     if (r_coll < p_coll) {
-      ++my_coll;
-      int se = -1, si = -1;
+      int proc;
       if (SP == 0) {
-        const double s_el = G(C->sig_el)[idx], s_exc = G(C->sig_exc)[idx], s_ion = G(C->sig_ion)[idx];
+        const double s_el = sig0[idx], s_exc = sig1[idx], s_ion = sig2[idx];
         const double s_tot = s_el + s_exc + s_ion;
-        const bool ioniz = (s_tot > 0.0) && !(r_proc < s_el / s_tot) && !(r_proc < (s_el + s_exc) / s_tot);
-        if (ioniz) {
-          // births at the parent's position: an ejected electron and an ion
-          atomicAdd(&sCtr[kLIoniz], 1ull);
-          const uint64_t uid = us[u];
-          long long r;
-          const int q = deposit_split(xn, inv_dx, ng, r);
-          const unsigned long long be = gl_fetch_add(&C->alloc[0], 1ull);
-          if ((int64_t)be < C->sp[0].cap) {
-            se = (int)be;
-            X[be] = xn;
-            G(C->sp[0].uid[cur])[be] = child_uid(uid, s, 1);
-            lds_add(&sH[q], 4294967296LL - r);
-            lds_add(&sH[q + 1], r);
-            atomicAdd(&sCtr[kLLiveE], 1ull);
-          } else {
-            atomicAdd(&sCtr[kLDrop], 1ull);
-          }
-          const int ci = C->cur[1];
-          const unsigned long long bi = gl_fetch_add(&C->alloc[1], 1ull);
-          if ((int64_t)bi < C->sp[1].cap) {
-            si = (int)bi;
-            G(C->sp[1].x[ci])[bi] = xn;
-            G(C->sp[1].uid[ci])[bi] = child_uid(uid, s, 2);
-            int64_t* ci_next = C->cnt_i + ((kion + 1) % 3) * ng;
-            gl_add(&ci_next[q], 4294967296LL - r);
-            gl_add(&ci_next[q + 1], r);
-            atomicAdd(&sCtr[kLLiveI], 1ull);
-          } else {
-            atomicAdd(&sCtr[kLDrop], 1ull);
-          }
+        if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
+          proc = 0;
+        else if (r_proc < (s_el + s_exc) / s_tot)
+          proc = 1;
+        else
+          proc = 2;
+        if (proc == 2) {
+          mult = 2;
+          gl_add(&cnt_i_next[q], 4294967296LL - r);
+          gl_add(&cnt_i_next[q + 1], r);
+          ++my_z;
         }
+      } else {
+        const double s_iso = sig0[idx], s_back = sig1[idx];
+        proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
       }
-      const int slot = (int)threadIdx.x * kPerThread + my_q++;
-      sQi[slot] = (int)(i - lo);
-      sQr[slot] = r_proc;
-      sQe[slot] = se;
-      sQj[slot] = si;
+      qe[u] = (u * kBlock + (int)threadIdx.x) | (proc << 10);
+      ++my_q;
     }
+    lds_add(&sH[q], mult * (4294967296LL - r));
+    lds_add(&sH[q + 1], mult * r);
   }
 #pragma unroll
   for (int u = 0; u < kPerThread; ++u) {
@@ -812,69 +879,44 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
     X[i] = xo[u];
     VX[i] = vxo[u];
   }
-  if (my_abs_pow) atomicAdd(&sCtr[kLAbsPow], (unsigned long long)my_abs_pow);
-  if (my_abs_gnd) atomicAdd(&sCtr[kLAbsGnd], (unsigned long long)my_abs_gnd);
-  if (my_coll) atomicAdd(&sCtr[kLColl], (unsigned long long)my_coll);
-  // hand the chunk's collisions to the queue of this step: one workgroup
-  // scan places every thread's entries, one global atomic reserves the range
-  int qn;
-  const int my_off = block_exclusive_scan_int(my_q, sScan, &qn);
-  if (qn > 0) {
-    __shared__ unsigned long long sBase;
-    const int qb = (int)(s & 1);
-    if (threadIdx.x == 0) sBase = gl_fetch_add(&C->cq_n[SP][qb], (unsigned long long)qn);
-    __syncthreads();
-    const int64_t b0 = (int64_t)sBase + my_off;
-    for (int k = 0; k < my_q; ++k) {
-      const int slot = (int)threadIdx.x * kPerThread + k;
-      G(C->cq_idx[SP][qb])[b0 + k] = (int)lo + sQi[slot];
-      G(C->cq_r[SP][qb])[b0 + k] = sQr[slot];
-      if (SP == 0) {
-        G(C->cq_be[qb])[b0 + k] = sQe[slot];
-        G(C->cq_bi[qb])[b0 + k] = sQj[slot];
-      }
+  if (my_abs_pow) atomicAdd(&sCtr[kLAbsPow], my_abs_pow);
+  if (my_abs_gnd) atomicAdd(&sCtr[kLAbsGnd], my_abs_gnd);
+  // the chunk's events, in thread order; ionizations numbered in the same order
+  int tot;
+  const int off = block_exclusive_scan_t<int>(my_q | (my_z << 16), sScan, &tot);
+  if (my_q) {
+    EDP_GLOBAL int32_t* __restrict__ ent = G(C->cq_ent[SP]) + lo;
+    int qo = off & 0xFFFF, zo = off >> 16;
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+      if (qe[u] < 0) continue;
+      int code = qe[u];
+      if (((code >> 10) & 3) == 2) code |= (zo++) << 12;
+      ent[qo++] = code;
     }
   }
-  __syncthreads();
-  // flush: deposit for step s+1, diagnostics of step s, counters
+  // flush: deposit for step s+1, diagnostics of step s, the chunk record
   int64_t* dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
   for (int q = threadIdx.x; q < ng; q += blockDim.x) {
     const unsigned long long h = sH[q];
     if (h) gl_add(&dst[q], (long long)h);
     if (pdiag) {
-      const int64_t off = (s % 3) * ng + q;
-      if (sJ[q]) gl_add(&(SP == 0 ? C->acc_je : C->acc_ji)[off], (long long)sJ[q]);
-      if (SP == 0 && sW[q]) gl_add(&C->acc_w[off], (long long)sW[q]);
-      if (SP == 0 && sEn[q]) gl_add(&C->acc_e[off], (long long)sEn[q]);
+      const int64_t off3 = (s % 3) * ng + q;
+      if (sJ[q]) gl_add(&(SP == 0 ? C->acc_je : C->acc_ji)[off3], (long long)sJ[q]);
+      if (SP == 0 && sW[q]) gl_add(&C->acc_w[off3], (long long)sW[q]);
+      if (SP == 0 && sEn[q]) gl_add(&C->acc_e[off3], (long long)sEn[q]);
     }
   }
   if (SP == 0 && (fl & kDiagEepf))
     for (int b = threadIdx.x; b < n_eepf; b += blockDim.x)
       if (sF[b]) gl_add(&C->eepf[b], (long long)sF[b]);
   if (threadIdx.x == 0) {
-    const unsigned long long a_pow = sCtr[kLAbsPow], a_gnd = sCtr[kLAbsGnd];
-    if (a_pow) gl_add(&C->ctr[SP == 0 ? kAbsEPow : kAbsIPow], (long long)a_pow);
-    if (a_gnd) gl_add(&C->ctr[SP == 0 ? kAbsEGnd : kAbsIGnd], (long long)a_gnd);
-    if (sCtr[kLColl]) gl_add(&C->ctr[SP == 0 ? kCollE : kCollI], (long long)sCtr[kLColl]);
-    if (sCtr[kLIoniz]) gl_add(&C->ctr[kIoniz], (long long)sCtr[kLIoniz]);
-    if (sCtr[kLDrop]) {
-      gl_add(&C->ctr[kDropped], (long long)sCtr[kLDrop]);
-      atomicExch(&C->error, 1);
-    }
-    const long long dl = -(long long)(a_pow + a_gnd);
-    if (SP == 0) {
-      const long long de = dl + (long long)sCtr[kLLiveE];
-      if (de) gl_add(&C->ctr[kLiveE], de);
-      if (sCtr[kLLiveI]) gl_add(&C->ctr[kLiveI], (long long)sCtr[kLLiveI]);
-    } else if (dl) {
-      gl_add(&C->ctr[kLiveI], dl);
-    }
+    EDP_GLOBAL int32_t* rec = G(C->cq_rec[SP]) + 2 * blockIdx.x;
+    rec[0] = tot;
+    rec[1] = (int)(sCtr[kLAbsPow] | (sCtr[kLAbsGnd] << 16));
   }
 }
 
-// ---------------------------------------------------------------------------
-// Seeding (Algorithm 1, init) and redeposit.
-// ---------------------------------------------------------------------------
 __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -1065,7 +1107,7 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp) {
   size_t doubles = (size_t)2 * ng;
   if (flags & kDiagParticle)
     doubles += (size_t)3 * ng + (sp == 0 && (flags & kDiagEepf) ? (size_t)(n_eepf + 1) / 2 : 0);
-  return doubles * 8 + (size_t)kQCap * 20;
+  return doubles * 8;
 }
 
 // Head of a step: 1 field workgroup + `scatter_blocks` collision workgroups.
