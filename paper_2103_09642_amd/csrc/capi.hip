@@ -114,7 +114,7 @@ constexpr int64_t kMaxCap = (int64_t(1) << 31) - 1024;  // slots are int32 in th
 
 int validate(const edp_case_desc* c) {
   if (!c) return fail(EDP_EINVAL, "null descriptor");
-  if (c->n_grid < 2 || c->n_grid > 2048) return fail(EDP_EINVAL, "n_grid must be 2..2048");
+  if (c->n_grid < 2 || c->n_grid > kMaxNodes) return fail(EDP_EINVAL, "n_grid must be 2..%d", kMaxNodes);
   if (c->ion_subcycle < 1) return fail(EDP_EINVAL, "ion_subcycle must be >= 1");
   if (c->steps_per_cycle < 1) return fail(EDP_EINVAL, "steps_per_cycle must be >= 1");
   if (!(c->dt_e > 0.0) || !(c->gap_m > 0.0) || !(c->area_m2 > 0.0))

@@ -29,11 +29,12 @@ constexpr double kDiagJS = 1024.0;     // c * vbar_x [m/s]
 constexpr double kDiagWS = 1048576.0;  // c
 constexpr double kDiagES = 1048576.0;  // c * energy [eV]
 
-constexpr int kMaxGrid = 4096;
 // Particle kernels: workgroup size and the particle slots each workgroup owns.
 constexpr int kBlock = 256;
 constexpr int kPerThread = 4;
 constexpr int kChunk = kBlock * kPerThread;
+constexpr int kMaxNodes = 2048;                      // largest n_grid accepted
+constexpr int kGridPerThread = kMaxNodes / kBlock;   // grid nodes per thread
 constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
 
 // Flags (same values as EDP_* in edupic.h).

@@ -266,9 +266,21 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ C, double* fsm
   EDP_GLOBAL int64_t* zeroI = G(C->cnt_i + ((k + 2) % 3) * ng);
   const int64_t fold = ((s + 2) % 3) * ng;  // per-step sums of step s-1
   const double scale = C->dens_scale;
-  for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-    double ne = (double)cntE[p] * scale;
-    double ni = (double)cntI[p] * scale;
+  const double V = G(C->volt)[s % kVoltChunk];
+  // every load of the thread's nodes before any store (one memory round trip)
+  int64_t ce[kGridPerThread], ci[kGridPerThread];
+#pragma unroll
+  for (int j = 0; j < kGridPerThread; ++j) {
+    const int p = threadIdx.x + j * kBlock;
+    ce[j] = p < ng ? cntE[p] : 0;
+    ci[j] = p < ng ? cntI[p] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kGridPerThread; ++j) {
+    const int p = threadIdx.x + j * kBlock;
+    if (p >= ng) break;
+    double ne = (double)ce[j] * scale;
+    double ni = (double)ci[j] * scale;
     if (p == 0 || p == ng - 1) {
       ne *= 2.0;
       ni *= 2.0;
@@ -299,7 +311,6 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ C, double* fsm
     }
   }
   __syncthreads();
-  const double V = G(C->volt)[s % kVoltChunk];
   const double dx = C->dx;
   if (MODE == 1) {
     if (threadIdx.x == 0) {
@@ -383,18 +394,37 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ C, double* fsm
 // overlaps the field solve.
 // ---------------------------------------------------------------------------
 
+// Arrays the collision workgroups touch, loaded once per workgroup.
+struct ScatterPtrs {
+  EDP_GLOBAL double *ex, *evx, *evy, *evz, *ix, *ivx, *ivy, *ivz;
+  EDP_GLOBAL uint64_t *euid, *iuid;
+};
+
+__device__ __forceinline__ ScatterPtrs scatter_ptrs(const CaseDev* __restrict__ C) {
+  ScatterPtrs P;
+  const int ce = C->cur[0], ci = C->cur[1];
+  P.ex = G(C->sp[0].x[ce]);
+  P.evx = G(C->sp[0].vx[ce]);
+  P.evy = G(C->sp[0].vy[ce]);
+  P.evz = G(C->sp[0].vz[ce]);
+  P.euid = G(C->sp[0].uid[ce]);
+  P.ix = G(C->sp[1].x[ci]);
+  P.ivx = G(C->sp[1].vx[ci]);
+  P.ivy = G(C->sp[1].vy[ci]);
+  P.ivz = G(C->sp[1].vz[ci]);
+  P.iuid = G(C->sp[1].uid[ci]);
+  return P;
+}
+
 // Electron-Ar scattering of queued particle i (state after the push) by
 // process proc (0 elastic, 1 excitation, 2 ionization).  An ionization also
 // writes its newborns: the ejected electron at slot be and the ion at slot
 // bi (-1: dropped at capacity), both at the parent's position.
-__device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_t i, int proc, int64_t be,
-                                                 int64_t bi, int64_t s) {
-  const int ce = C->cur[0];
-  EDP_GLOBAL double* __restrict__ VX = G(C->sp[0].vx[ce]);
-  EDP_GLOBAL double* __restrict__ VY = G(C->sp[0].vy[ce]);
-  EDP_GLOBAL double* __restrict__ VZ = G(C->sp[0].vz[ce]);
-  const double vxn = VX[i], vy = VY[i], vz = VZ[i];
-  const uint64_t uid = G(C->sp[0].uid[ce])[i];
+__device__ __forceinline__ void electron_scatter(const CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
+                                                 int proc, int64_t be, int64_t bi, int64_t s) {
+  const double vxn = P.evx[i], vy = P.evy[i], vz = P.evz[i];
+  const uint64_t uid = P.euid[i];
+  const double x = proc == 2 ? P.ex[i] : 0.0;
   const uint64_t seed = C->seed;
   const uint32_t st = (uint32_t)s;
   const double v2 = vxn * vxn + vy * vy + vz * vz;
@@ -412,7 +442,7 @@ __device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_
       double ec = 0.5 * kMuEAr * v2 - C->thr_exc * kEvToJ;
       if (ec < 0.0) {
         ec = 0.0;
-        gl_add(&C->ctr[kAnomaly], 1);
+        gl_add(&((CaseDev*)C)->ctr[kAnomaly], 1);
       }
       gnew = sqrt(2.0 * ec / kMuEAr);
     }
@@ -425,7 +455,7 @@ __device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_
     double e_ev = 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion;
     if (e_ev < 0.0) {
       e_ev = 0.0;
-      gl_add(&C->ctr[kAnomaly], 1);
+      gl_add(&((CaseDev*)C)->ctr[kAnomaly], 1);
     }
     const double w_ion = C->w_ion;
     const double e_ej = w_ion * tan(r_share * atan(e_ev / (2.0 * w_ion)));
@@ -447,45 +477,38 @@ __device__ __forceinline__ void electron_scatter(CaseDev* __restrict__ C, int64_
       sn_ej = sqrt(1.0 - cs_ej * cs_ej);
     }
     scatter(vxn, vy, vz, v, g_sc, f2, cs_sc, sn_sc, eta, wx, wy, wz, ox, oy, oz);
-    if (be >= 0 || bi >= 0) {
-      const double x = G(C->sp[0].x[ce])[i];
-      if (be >= 0) {  // the ejected electron, scattered about the same w
-        double ex_, ey_, ez_;
-        scatter(vxn, vy, vz, v, g_ej, f2, cs_ej, sn_ej, eta + kPi, wx, wy, wz, ex_, ey_, ez_);
-        G(C->sp[0].x[ce])[be] = x;
-        VX[be] = ex_;
-        VY[be] = ey_;
-        VZ[be] = ez_;
-        G(C->sp[0].uid[ce])[be] = child_uid(uid, s, 1);
-      }
-      if (bi >= 0) {  // the new ion: a thermal gas velocity
-        const int ci = C->cur[1];
-        const uint64_t cu = child_uid(uid, s, 2);
-        double z0, z1, z2;
-        normals3(seed, cu, st, 1u, 2u, 1u, z0, z1, z2);
-        const double sa = C->sigma_a;
-        G(C->sp[1].x[ci])[bi] = x;
-        G(C->sp[1].vx[ci])[bi] = sa * z0;
-        G(C->sp[1].vy[ci])[bi] = sa * z1;
-        G(C->sp[1].vz[ci])[bi] = sa * z2;
-        G(C->sp[1].uid[ci])[bi] = cu;
-      }
+    if (be >= 0) {  // the ejected electron, scattered about the same w
+      double ex_, ey_, ez_;
+      scatter(vxn, vy, vz, v, g_ej, f2, cs_ej, sn_ej, eta + kPi, wx, wy, wz, ex_, ey_, ez_);
+      P.ex[be] = x;
+      P.evx[be] = ex_;
+      P.evy[be] = ey_;
+      P.evz[be] = ez_;
+      P.euid[be] = child_uid(uid, s, 1);
+    }
+    if (bi >= 0) {  // the new ion: a thermal gas velocity
+      const uint64_t cu = child_uid(uid, s, 2);
+      double z0, z1, z2;
+      normals3(seed, cu, st, 1u, 2u, 1u, z0, z1, z2);
+      const double sa = C->sigma_a;
+      P.ix[bi] = x;
+      P.ivx[bi] = sa * z0;
+      P.ivy[bi] = sa * z1;
+      P.ivz[bi] = sa * z2;
+      P.iuid[bi] = cu;
     }
   }
-  VX[i] = ox;
-  VY[i] = oy;
-  VZ[i] = oz;
+  P.evx[i] = ox;
+  P.evy[i] = oy;
+  P.evz[i] = oz;
 }
 
 // Ar+ + Ar scattering of queued ion i (proc 0 isotropic, 1 backward) with the
 // thermal target of its test (redrawn from the same counter: the same atom).
-__device__ __forceinline__ void ion_scatter(CaseDev* __restrict__ C, int64_t i, int proc, int64_t s) {
-  const int cur = C->cur[1];
-  EDP_GLOBAL double* __restrict__ VX = G(C->sp[1].vx[cur]);
-  EDP_GLOBAL double* __restrict__ VY = G(C->sp[1].vy[cur]);
-  EDP_GLOBAL double* __restrict__ VZ = G(C->sp[1].vz[cur]);
-  const double vxn = VX[i], vy = VY[i], vz = VZ[i];
-  const uint64_t uid = G(C->sp[1].uid[cur])[i];
+__device__ __forceinline__ void ion_scatter(const CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i, int proc,
+                                            int64_t s) {
+  const double vxn = P.ivx[i], vy = P.ivy[i], vz = P.ivz[i];
+  const uint64_t uid = P.iuid[i];
   const uint64_t seed = C->seed;
   const uint32_t st = (uint32_t)s;
   double z0, z1, z2;
@@ -507,89 +530,87 @@ __device__ __forceinline__ void ion_scatter(CaseDev* __restrict__ C, int64_t i, 
   }
   double ox, oy, oz;
   scatter(gx, gy, gz, g, g, 0.5, cos_chi, sin_chi, kTwoPi * r_eta, wx, wy, wz, ox, oy, oz);
-  VX[i] = ox;
-  VY[i] = oy;
-  VZ[i] = oz;
+  P.ivx[i] = ox;
+  P.ivy[i] = oy;
+  P.ivz[i] = oz;
 }
 
 // Apply the pending collision queue.  Workgroup blk of nblk takes a
-// contiguous range of chunks of each species; newborns of chunk c go to
-// q_base + (ionizations of chunks < c) + rank, so every workgroup first sums
-// the ionization counts before its range.  No atomics: the slot of every
-// event and newborn follows from the chunk records alone.  Workgroup nblk-1
-// also folds the records into the counters and the slot counts.
-constexpr int kApplyChunks = kBlock;  // chunks per round of a workgroup
+// contiguous range of chunks of each species; each half-wave (32 lanes)
+// takes one chunk, its record and its first 32 events loaded together.
+// Newborns of chunk c go to q_base + (ionizations of chunks < c) + rank, so
+// the ionization counts before the range are summed with the same loads.
+// No atomics: every slot follows from the chunk records alone.
+constexpr int kHalf = 32;
+constexpr int kApplyChunks = kBlock / kHalf;  // chunks per round of a workgroup
 
-__device__ __forceinline__ void apply_queue(CaseDev* __restrict__ C, int blk, int nblk) {
-  __shared__ int sQo[kApplyChunks];       // events before chunk t of the round
-  __shared__ int64_t sZo[kApplyChunks];   // newborn index of chunk t's first ionization
+__device__ __forceinline__ void apply_queue(const CaseDev* __restrict__ C, int blk, int nblk) {
   __shared__ int64_t sRed[64];
   const int64_t s = C->q_step;
-  const bool book = blk == nblk - 1;
+  const ScatterPtrs P = scatter_ptrs(C);
+  const int hw = (int)threadIdx.x / kHalf, lane = (int)threadIdx.x % kHalf;
+  const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
+  const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t nb = C->q_nblk[sp];
     const EDP_GLOBAL int32_t* __restrict__ rec = G(C->cq_rec[sp]);
     const EDP_GLOBAL int32_t* __restrict__ ent = G(C->cq_ent[sp]);
     const int64_t c0 = nb * blk / nblk, c1 = nb * (blk + 1) / nblk;
-    // ionizations of the chunks before this range (electrons only)
-    int64_t zrun = 0;
-    if (sp == 0) {
-      int64_t z = 0;
-      for (int64_t c = threadIdx.x; c < c0; c += blockDim.x) z += rec[2 * c] >> 16;
-      (void)block_exclusive_scan_t<int64_t>(z, sRed, &zrun);
-    }
-    const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
-    const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
+    int64_t zrun = 0;  // newborns of the chunks before the current round
     for (int64_t cb = c0; cb < c1; cb += kApplyChunks) {
-      const int64_t c = cb + threadIdx.x;
-      const int r0 = c < c1 ? rec[2 * c] : 0;
-      const int q = r0 & 0xFFFF, z = r0 >> 16;
-      int qtot;
-      int64_t ztot;
-      const int qo = block_exclusive_scan_t<int>(q, (int64_t*)sRed, &qtot);
-      const int64_t zo = block_exclusive_scan_t<int64_t>((int64_t)z, sRed, &ztot);
-      sQo[threadIdx.x] = qo;
-      sZo[threadIdx.x] = zrun + zo;
-      __syncthreads();
-      const int nc = (int)((c1 - cb) < kApplyChunks ? (c1 - cb) : kApplyChunks);
-      for (int e = threadIdx.x; e < qtot; e += blockDim.x) {
-        // the chunk holding event e: the last t with sQo[t] <= e
-        int lo_t = 0, hi_t = nc - 1;
-        while (lo_t < hi_t) {
-          const int mid = (lo_t + hi_t + 1) >> 1;
-          if (sQo[mid] <= e)
-            lo_t = mid;
-          else
-            hi_t = mid - 1;
+      const int64_t c = cb + hw;
+      const bool valid = c < c1;
+      const int r0 = valid ? rec[2 * c] : 0;
+      const int code0 = valid ? ent[c * kChunk + lane] : 0;  // in bounds: the region is kChunk long
+      const int q = r0 & 0xFFFF;
+      if (sp == 0) {
+        // high word: ionizations of chunks < c0 (first round), low word: this
+        // round's ionizations of lower half-waves
+        int64_t zpre = 0;
+        if (cb == c0) {
+#pragma unroll 8
+          for (int64_t k = threadIdx.x; k < c0; k += blockDim.x) zpre += rec[2 * k] >> 16;
         }
-        const int64_t ch = cb + lo_t;
-        const int code = ent[ch * kChunk + (e - sQo[lo_t])];
-        const int64_t i = ch * kChunk + (code & 1023);
-        const int proc = (code >> 10) & 3;
-        if (sp == 0) {
+        const int64_t x = (zpre << 32) | (int64_t)(lane == 0 ? (r0 >> 16) : 0);
+        int64_t tot;
+        const int64_t exc = block_exclusive_scan_t<int64_t>(x, sRed, &tot);
+        const int64_t low = __shfl(exc & 0xFFFFFFFFLL, 0, kHalf);  // lane 0 of the half-wave
+        if (cb == c0) zrun = tot >> 32;
+        const int64_t zbase = zrun + low;
+        zrun += tot & 0xFFFFFFFFLL;
+        for (int k = lane; k < q; k += kHalf) {
+          const int code = k < kHalf ? code0 : ent[c * kChunk + k];
+          const int64_t i = c * kChunk + (code & 1023);
+          const int proc = (code >> 10) & 3;
           int64_t be = -1, bi = -1;
           if (proc == 2) {
-            const int64_t k = sZo[lo_t] + (code >> 12);
-            if (base_e + k < cap_e) be = base_e + k;
-            if (base_i + k < cap_i) bi = base_i + k;
+            const int64_t kk = zbase + (code >> 12);
+            if (base_e + kk < cap_e) be = base_e + kk;
+            if (base_i + kk < cap_i) bi = base_i + kk;
           }
-          electron_scatter(C, i, proc, be, bi, s);
-        } else {
-          ion_scatter(C, i, proc, s);
+          electron_scatter(C, P, i, proc, be, bi, s);
+        }
+      } else {
+        for (int k = lane; k < q; k += kHalf) {
+          const int code = k < kHalf ? code0 : ent[c * kChunk + k];
+          ion_scatter(C, P, c * kChunk + (code & 1023), (code >> 10) & 3, s);
         }
       }
-      zrun += ztot;
-      __syncthreads();
     }
   }
-  if (!book) return;
-  // Totals of all chunks: collision, ionization and absorption counters,
-  // newborns placed, slot counts for the next step.
+}
+
+// Totals of the pending queue (one workgroup, beside the apply workgroups):
+// collision, ionization and absorption counters, newborns placed, slot
+// counts for the next step.
+__device__ __forceinline__ void apply_totals(CaseDev* __restrict__ C) {
+  __shared__ int64_t sRed[64];
   int64_t tq[2] = {0, 0}, tz = 0, tap[2] = {0, 0}, tag_[2] = {0, 0};
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t nb = C->q_nblk[sp];
     const EDP_GLOBAL int32_t* __restrict__ rec = G(C->cq_rec[sp]);
     int64_t a = 0, b = 0, d = 0, f = 0;
+#pragma unroll 8
     for (int64_t c = threadIdx.x; c < nb; c += blockDim.x) {
       const int r0 = rec[2 * c], r1 = rec[2 * c + 1];
       a += r0 & 0xFFFF;
@@ -597,10 +618,14 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ C, int blk, in
       d += r1 & 0xFFFF;
       f += r1 >> 16;
     }
-    (void)block_exclusive_scan_t<int64_t>(a, sRed, &tq[sp]);
-    (void)block_exclusive_scan_t<int64_t>(d, sRed, &tap[sp]);
-    (void)block_exclusive_scan_t<int64_t>(f, sRed, &tag_[sp]);
-    if (sp == 0) (void)block_exclusive_scan_t<int64_t>(b, sRed, &tz);
+    // one scan of four 16-bit-safe sums would overflow; pack two per word
+    int64_t t0, t1;
+    (void)block_exclusive_scan_t<int64_t>((a << 32) | b, sRed, &t0);
+    (void)block_exclusive_scan_t<int64_t>((d << 32) | f, sRed, &t1);
+    tq[sp] = t0 >> 32;
+    if (sp == 0) tz = t0 & 0xFFFFFFFFLL;
+    tap[sp] = t1 >> 32;
+    tag_[sp] = t1 & 0xFFFFFFFFLL;
   }
   if (threadIdx.x == 0) {
     const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
@@ -625,8 +650,9 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ C, int blk, in
   }
 }
 
-// Head of step s: workgroup 0 solves the field, the others apply the queue
-// of step s-1; the last of them also does the step's bookkeeping.
+// Head of step s: workgroup 0 solves the field, the middle ones apply the
+// queue of step s-1, the last one folds its totals and does the step's
+// bookkeeping.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_head(CaseDev* __restrict__ C) {
   extern __shared__ double hsm[];
@@ -634,9 +660,14 @@ __global__ void __launch_bounds__(kBlock) k_head(CaseDev* __restrict__ C) {
     field_solve<MODE>(C, hsm);
     return;
   }
-  const int blk = (int)blockIdx.x - 1, nblk = (int)gridDim.x - 1;
-  if (C->q_valid) apply_queue(C, blk, nblk);
-  if (blk == nblk - 1 && threadIdx.x == 0) {
+  const int blk = (int)blockIdx.x - 1, napply = (int)gridDim.x - 2;
+  const bool valid = C->q_valid != 0;
+  if (blk < napply) {
+    if (valid) apply_queue(C, blk, napply);
+    return;
+  }
+  if (valid) apply_totals(C);
+  if (threadIdx.x == 0) {
     const int64_t s = C->step;
     const bool ion_step = (s % C->nsub) == 0;
     C->ctr[kPstepE] += C->ctr[kLiveE];
@@ -647,9 +678,14 @@ __global__ void __launch_bounds__(kBlock) k_head(CaseDev* __restrict__ C) {
   }
 }
 
-// Apply the pending queue before the host looks at the state.
+// Apply the pending queue before the host looks at the state (the last
+// workgroup folds the totals).
 __global__ void __launch_bounds__(kBlock) k_drain(CaseDev* __restrict__ C) {
-  if (C->q_valid) apply_queue(C, (int)blockIdx.x, (int)gridDim.x);
+  if (!C->q_valid) return;
+  if ((int)blockIdx.x < (int)gridDim.x - 1)
+    apply_queue(C, (int)blockIdx.x, (int)gridDim.x - 1);
+  else
+    apply_totals(C);
 }
 __global__ void k_drain_done(CaseDev* __restrict__ C) {
   if (threadIdx.x == 0) C->q_valid = 0;
@@ -708,8 +744,20 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
   unsigned long long* sW = sJ + ng;
   unsigned long long* sEn = sW + ng;
   unsigned int* sF = (unsigned int*)(sEn + ng);
+  {
+    double ev[kGridPerThread];
+#pragma unroll
+    for (int j = 0; j < kGridPerThread; ++j) {
+      const int p = threadIdx.x + j * kBlock;
+      ev[j] = p < ng ? G(C->efield)[p] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kGridPerThread; ++j) {
+      const int p = threadIdx.x + j * kBlock;
+      if (p < ng) sE[p] = ev[j];
+    }
+  }
   for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-    sE[p] = G(C->efield)[p];
     sH[p] = 0;
     if (pdiag) {
       sJ[p] = 0;
@@ -1110,10 +1158,11 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp) {
   return doubles * 8;
 }
 
-// Head of a step: 1 field workgroup + `scatter_blocks` collision workgroups.
+// Head of a step: 1 field workgroup, `scatter_blocks` collision workgroups,
+// 1 totals/bookkeeping workgroup.
 hipError_t launch_head(CaseDev* d, int ng, int mode, int scatter_blocks, hipStream_t st) {
   const size_t lds = (size_t)ng * 24 + 64 * 8;
-  const dim3 grid(1 + scatter_blocks);
+  const dim3 grid(2 + scatter_blocks);
   if (mode == 1)
     hipLaunchKernelGGL(k_head<1>, grid, dim3(kBlock), lds, st, d);
   else
@@ -1122,7 +1171,7 @@ hipError_t launch_head(CaseDev* d, int ng, int mode, int scatter_blocks, hipStre
 }
 
 hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_drain, dim3(blocks), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_drain, dim3(blocks + 1), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_drain_done, dim3(1), dim3(64), 0, st, d);
   return hipGetLastError();
 }
