@@ -26,7 +26,7 @@ namespace edp {
 hipError_t launch_head(CaseDev* d, int ng, int mode, int scatter_blocks, hipStream_t st);
 hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
 hipError_t launch_particles(CaseDev* d, int sp, int blocks, int ng, uint32_t flags, int n_eepf,
-                            hipStream_t st);
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
 hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
                           hipStream_t st);
@@ -274,14 +274,11 @@ int enqueue_step(edp_ctx* ctx, Case* c, int64_t s, int be, int bi) {
   if (ctx->profile) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, st));
   }
-  HIPCHK(launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st));
-  if (ctx->profile) {
-    HIPCHK(hipEventRecord(e1, st));
-    ctx->ev_pairs.emplace_back(e0, e1);
-  }
-  if (s % D.ion_subcycle == 0) HIPCHK(launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st));
+  HIPCHK(launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st, e0, e1));
+  if (ctx->profile) ctx->ev_pairs.emplace_back(e0, e1);
+  if (s % D.ion_subcycle == 0)
+    HIPCHK(launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st, nullptr, nullptr));
   return EDP_OK;
 }
 
@@ -319,8 +316,8 @@ int build_graph(edp_ctx* ctx, Case* c, int steps, int be, int bi, int bsort_e, i
     (void)launch_head(c->d, D.n_grid, ctx->poisson, scatter_blocks(ctx), st);
     if (k % ctx->sort_every == 0) (void)launch_sort(c->d, 0, D.n_grid, bsort_e, st);
     if (k % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0) (void)launch_sort(c->d, 1, D.n_grid, bsort_i, st);
-    (void)launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st);
-    if (k % D.ion_subcycle == 0) (void)launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st);
+    (void)launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st, nullptr, nullptr);
+    if (k % D.ion_subcycle == 0) (void)launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st, nullptr, nullptr);
   }
   HIPCHK(hipStreamEndCapture(st, &g));
   hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);

@@ -21,6 +21,8 @@
 // Every FP64 expression of the push and the collision kinematics is written
 // in the same operation order as its definition, and the library is built
 // with -ffp-contract=off, so no multiply-add is fused.
+#include <hip/hip_ext.h>
+
 #include "impl.hpp"
 
 namespace edp {
@@ -1176,13 +1178,21 @@ hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st) {
   return hipGetLastError();
 }
 
+// With ev0/ev1 the launch records its own start and end (the dispatch's
+// timestamps, not those of separate event packets around it).
 hipError_t launch_particles(CaseDev* d, int sp, int blocks, int ng, uint32_t flags, int n_eepf,
-                            hipStream_t st) {
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const size_t lds = particle_lds_bytes(ng, flags, n_eepf, sp);
-  if (sp == 0)
+  if (ev0) {
+    if (sp == 0)
+      hipExtLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, d);
+    else
+      hipExtLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, d);
+  } else if (sp == 0) {
     hipLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, d);
-  else
+  } else {
     hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, d);
+  }
   return hipGetLastError();
 }
 
