@@ -23,10 +23,11 @@
 #include "impl.hpp"
 
 namespace edp {
-hipError_t launch_head(CaseDev* d, int ng, int mode, int scatter_blocks, hipStream_t st);
+hipError_t launch_head(const BatchDev* b, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st);
 hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
-hipError_t launch_particles(CaseDev* d, int sp, int blocks, int ng, uint32_t flags, int n_eepf,
-                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_particles(const BatchDev* b, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
+                            hipEvent_t ev1);
+size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
 hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
                           hipStream_t st);
@@ -76,9 +77,23 @@ struct Case {
   hipEvent_t vev = nullptr;
   bool vev_pending = false;
   bool failed = false;
-  // graph mode
+};
+
+// The cases of one lockstep run and everything derived from them: the
+// device table the kernels read, grid sizes, and the captured graph.
+struct Batch {
+  std::vector<Case*> cases;
+  BatchDev h{};
+  int parts[2] = {0, 0};  // particle workgroups per species
+  int apply = 0;          // collision workgroups of the head
+  int max_ng = 2;
+  size_t lds[2] = {0, 0};
+  // graph of g_steps steps, valid for these cases at these step phases and
+  // sort grids
   hipGraphExec_t gexec = nullptr;
-  int g_steps = 0, g_be = 0, g_bi = 0, g_sort = 0;
+  int g_steps = 0;
+  std::vector<int64_t> g_phase;
+  std::vector<int> g_sort_e, g_sort_i;
 };
 
 }  // namespace
@@ -96,6 +111,10 @@ struct edp_ctx {
   edp_case next_id = 1;
   // options
   int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, wg_per_cu = 2, poisson = 0;
+  // the batch table (device copy owned by the context) and its run state
+  BatchDev* batch_d = nullptr;
+  Batch batch;
+  bool batch_valid = false;
   // profiling
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
   double prof_ms = 0.0;
@@ -214,12 +233,21 @@ int blocks_for(const edp_ctx* ctx, int64_t n) {
   return (int)b;
 }
 
-// Workgroups that apply queued collisions (grid-stride over the queue).
+// Workgroups that apply queued collisions outside a step (all of them on
+// one case).
 int scatter_blocks(const edp_ctx* ctx) { return ctx->num_cu; }
 
-// Grid of the particle kernels: one workgroup per kChunk slots of capacity.
+// Particle workgroups of one species of a case: one per kChunk slots of
+// capacity, so any particle count is covered and graphs stay valid.
 int particle_blocks(const Case* c, int sp) {
   return (int)((c->h.sp[sp].cap + kChunk - 1) / kChunk);
+}
+
+// Collision workgroups of a case in the head: a half-wave per chunk of the
+// estimated live slots, eight chunks per workgroup, at most one per CU.
+int apply_blocks(const edp_ctx* ctx, const Case* c) {
+  const int64_t chunks = (std::max(c->est[0], c->est[1]) + kChunk - 1) / kChunk;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ctx->num_cu, (chunks + 7) / 8));
 }
 
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
@@ -258,30 +286,6 @@ int request_estimate(edp_ctx* ctx, Case* c) {
   return EDP_OK;
 }
 
-// One step s, plain launches: head (field of s + collisions of s-1), the
-// periodic compaction/sort, then the particle kernels.
-int enqueue_step(edp_ctx* ctx, Case* c, int64_t s, int be, int bi) {
-  const edp_case_desc& D = c->desc;
-  hipStream_t st = ctx->stream;
-  HIPCHK(launch_head(c->d, D.n_grid, ctx->poisson, scatter_blocks(ctx), st));
-  // Compaction + cell sort: electrons every sort_every steps, ions every
-  // sort_every ion steps (they move only on ion steps).
-  if (s % ctx->sort_every == 0)
-    HIPCHK(launch_sort(c->d, 0, D.n_grid, std::max(1, blocks_for(ctx, c->est[0]) / 4), st));
-  if (s % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0)
-    HIPCHK(launch_sort(c->d, 1, D.n_grid, std::max(1, blocks_for(ctx, c->est[1]) / 4), st));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->profile) {
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-  }
-  HIPCHK(launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st, e0, e1));
-  if (ctx->profile) ctx->ev_pairs.emplace_back(e0, e1);
-  if (s % D.ion_subcycle == 0)
-    HIPCHK(launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st, nullptr, nullptr));
-  return EDP_OK;
-}
-
 // Apply the collisions still queued by the last step (before reading state).
 int drain(edp_ctx* ctx, Case* c) {
   HIPCHK(launch_drain(c->d, scatter_blocks(ctx), ctx->stream));
@@ -302,86 +306,194 @@ int drain_profile(edp_ctx* ctx) {
   return EDP_OK;
 }
 
-// Capture graph_steps steps starting at an aligned step into a graph.
-int build_graph(edp_ctx* ctx, Case* c, int steps, int be, int bi, int bsort_e, int bsort_i) {
-  if (c->gexec) {
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
+void drop_graph(edp_ctx* ctx) {
+  if (ctx->batch.gexec) {
+    (void)hipGraphExecDestroy(ctx->batch.gexec);
+    ctx->batch.gexec = nullptr;
   }
-  const edp_case_desc& D = c->desc;
-  hipStream_t st = ctx->stream;
-  hipGraph_t g = nullptr;
-  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < steps; ++k) {
-    (void)launch_head(c->d, D.n_grid, ctx->poisson, scatter_blocks(ctx), st);
-    if (k % ctx->sort_every == 0) (void)launch_sort(c->d, 0, D.n_grid, bsort_e, st);
-    if (k % ((int64_t)ctx->sort_every * D.ion_subcycle) == 0) (void)launch_sort(c->d, 1, D.n_grid, bsort_i, st);
-    (void)launch_particles(c->d, 0, be, D.n_grid, D.flags, D.n_eepf, st, nullptr, nullptr);
-    if (k % D.ion_subcycle == 0) (void)launch_particles(c->d, 1, bi, D.n_grid, D.flags, D.n_eepf, st, nullptr, nullptr);
+  ctx->batch.g_steps = 0;
+}
+
+// Build the batch table for `cs` (in this order) and upload it.  The table
+// is read by kernels still in flight, so the stream is drained first.
+int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
+  Batch& B = ctx->batch;
+  bool same = ctx->batch_valid && B.cases == cs;
+  if (same) {
+    // grids follow the particle estimates; rebuild when they have moved far
+    for (size_t k = 0; k < cs.size() && same; ++k) {
+      const int a = apply_blocks(ctx, cs[k]);
+      const int a0 = B.h.apply_off[k + 1] - B.h.apply_off[k];
+      same = a <= a0 * 5 / 4 + 1 && a >= a0 * 3 / 4;
+    }
   }
-  HIPCHK(hipStreamEndCapture(st, &g));
-  hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return fail(EDP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-  c->g_steps = steps;
-  c->g_be = bsort_e;
-  c->g_bi = bsort_i;
+  if (same) return EDP_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  drop_graph(ctx);
+  B.cases = cs;
+  B.h = BatchDev{};
+  B.h.ncase = (int32_t)cs.size();
+  B.max_ng = 2;
+  B.lds[0] = B.lds[1] = 0;
+  for (int sp = 0; sp < 2; ++sp) B.h.part_off[sp][0] = 0;
+  B.h.apply_off[0] = 0;
+  for (size_t k = 0; k < cs.size(); ++k) {
+    const Case* c = cs[k];
+    const edp_case_desc& D = c->desc;
+    B.h.c[k] = c->d;
+    for (int sp = 0; sp < 2; ++sp) {
+      B.h.part_off[sp][k + 1] = B.h.part_off[sp][k] + particle_blocks(c, sp);
+      B.lds[sp] = std::max(B.lds[sp], particle_lds_bytes(D.n_grid, D.flags, D.n_eepf, sp));
+    }
+    B.h.apply_off[k + 1] = B.h.apply_off[k] + apply_blocks(ctx, c);
+    B.max_ng = std::max(B.max_ng, (int)D.n_grid);
+  }
+  B.parts[0] = B.h.part_off[0][cs.size()];
+  B.parts[1] = B.h.part_off[1][cs.size()];
+  B.apply = B.h.apply_off[cs.size()];
+  HIPCHK(hipMemcpy(ctx->batch_d, &B.h, sizeof(BatchDev), hipMemcpyHostToDevice));
+  ctx->batch_valid = true;
   return EDP_OK;
 }
 
-int run_steps(edp_ctx* ctx, Case* c, int64_t n) {
-  if (c->failed) return fail(EDP_ESTATE, "case %lld has failed", (long long)c->id);
-  const edp_case_desc& D = c->desc;
-  int64_t s = c->step;
-  const int64_t end = s + n;
-  const int64_t win = 4096;
-  // graph mode: graph length a multiple of N_SUB and of the sort interval
-  int gsteps = 0;
-  if (ctx->mode == 1) {
-    const int64_t base = (int64_t)ctx->sort_every * D.ion_subcycle;
-    gsteps = ctx->graph_steps > 0 ? ctx->graph_steps : (int)std::min<int64_t>(base * std::max<int64_t>(1, 200 / base), 4096);
-    if (gsteps % base != 0) gsteps = (int)((gsteps / base + 1) * base);
+// Grid of a case's sort kernels.
+int sort_blocks(const edp_ctx* ctx, const Case* c, int sp) { return std::max(1, blocks_for(ctx, c->est[sp]) / 4); }
+
+// Step j of the current window (case k at step s[k] + j), plain launches:
+// one head for every case (fields of this step, collisions of the last),
+// the compaction/sort of the cases due for it, then one electron launch and,
+// when some case has an ion step, one ion launch.
+int enqueue_batch_step(edp_ctx* ctx, const std::vector<int64_t>& s, int64_t j, bool capture) {
+  Batch& B = ctx->batch;
+  hipStream_t st = ctx->stream;
+  const int nc = (int)B.cases.size();
+  HIPCHK(launch_head(ctx->batch_d, nc, B.apply, B.max_ng, ctx->poisson, st));
+  bool any_ion = false;
+  for (int k = 0; k < nc; ++k) {
+    const Case* c = B.cases[k];
+    const int64_t sk = s[k] + j;
+    const int64_t nsub = c->desc.ion_subcycle;
+    if (sk % ctx->sort_every == 0)
+      HIPCHK(launch_sort(c->d, 0, c->desc.n_grid, capture ? B.g_sort_e[k] : sort_blocks(ctx, c, 0), st));
+    if (sk % ((int64_t)ctx->sort_every * nsub) == 0)
+      HIPCHK(launch_sort(c->d, 1, c->desc.n_grid, capture ? B.g_sort_i[k] : sort_blocks(ctx, c, 1), st));
+    any_ion = any_ion || sk % nsub == 0;
   }
-  while (s < end) {
-    poll_estimate(c);
-    int64_t w_end = std::min(end, s + win);
-    if (gsteps > 0) {
-      // keep windows on graph boundaries where possible
-      const int64_t w = std::max<int64_t>(gsteps, (win / gsteps) * gsteps);
-      w_end = std::min(end, s + w);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profile && !capture) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+  }
+  HIPCHK(launch_particles(ctx->batch_d, 0, B.parts[0], B.lds[0], st, e0, e1));
+  if (e0) ctx->ev_pairs.emplace_back(e0, e1);
+  if (any_ion) HIPCHK(launch_particles(ctx->batch_d, 1, B.parts[1], B.lds[1], st, nullptr, nullptr));
+  return EDP_OK;
+}
+
+// Capture `steps` batch steps from the cases' current steps into a graph.
+int build_graph(edp_ctx* ctx, const std::vector<int64_t>& s, int steps) {
+  Batch& B = ctx->batch;
+  drop_graph(ctx);
+  const int nc = (int)B.cases.size();
+  B.g_sort_e.resize(nc);
+  B.g_sort_i.resize(nc);
+  B.g_phase.resize(nc);
+  for (int k = 0; k < nc; ++k) {
+    B.g_sort_e[k] = sort_blocks(ctx, B.cases[k], 0);
+    B.g_sort_i[k] = sort_blocks(ctx, B.cases[k], 1);
+    B.g_phase[k] = s[k] % steps;
+  }
+  hipStream_t st = ctx->stream;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int r = EDP_OK;
+  for (int j = 0; j < steps && r == EDP_OK; ++j) r = enqueue_batch_step(ctx, s, j, true);
+  const hipError_t ec = hipStreamEndCapture(st, &g);
+  if (r) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (ec != hipSuccess) return fail(EDP_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+  const hipError_t e = hipGraphInstantiate(&B.gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(EDP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  B.g_steps = steps;
+  return EDP_OK;
+}
+
+bool graph_matches(const edp_ctx* ctx, const std::vector<int64_t>& s, int steps) {
+  const Batch& B = ctx->batch;
+  if (!B.gexec || B.g_steps != steps) return false;
+  for (size_t k = 0; k < B.cases.size(); ++k) {
+    if (s[k] % steps != B.g_phase[k]) return false;
+    const int se = sort_blocks(ctx, B.cases[k], 0), si = sort_blocks(ctx, B.cases[k], 1);
+    const int e0 = B.g_sort_e[k], i0 = B.g_sort_i[k];
+    if (se > e0 * 5 / 4 + 1 || se < e0 * 3 / 4 || si > i0 * 5 / 4 + 1 || si < i0 * 3 / 4) return false;
+  }
+  return true;
+}
+
+// Advance cases[k] by n[k] steps, all in lockstep: every launch serves every
+// case that still has steps to go.  Windows of up to 4096 steps; in graph
+// mode, whole graphs of a multiple of sort_every * N_SUB steps.
+int run_batch(edp_ctx* ctx, const std::vector<Case*>& cases, const std::vector<int64_t>& n) {
+  std::vector<int64_t> left(n);
+  for (;;) {
+    std::vector<Case*> act;
+    std::vector<int64_t> s;
+    int64_t w = 4096;
+    int64_t base = 1;
+    for (size_t k = 0; k < cases.size(); ++k) {
+      if (left[k] <= 0) continue;
+      act.push_back(cases[k]);
+      s.push_back(cases[k]->step);
+      w = std::min(w, left[k]);
+      const int64_t p = (int64_t)ctx->sort_every * cases[k]->desc.ion_subcycle;
+      base = std::lcm(base, p);
     }
-    int r = upload_volt(ctx, c, s, w_end);
+    if (act.empty()) break;
+    for (Case* c : act) poll_estimate(c);
+    int r = set_batch(ctx, act);
     if (r) return r;
-    const int be = particle_blocks(c, 0);
-    const int bi = particle_blocks(c, 1);
-    while (s < w_end) {
-      if (gsteps > 0 && s % gsteps == 0 && s + gsteps <= w_end) {
-        // the sort grids follow the particle count; rebuild when it has
-        // moved by more than a quarter since the capture
-        const int se = std::max(1, blocks_for(ctx, c->est[0]) / 4);
-        const int si = std::max(1, blocks_for(ctx, c->est[1]) / 4);
-        const bool stale = !c->gexec || c->g_steps != gsteps || se > c->g_be * 5 / 4 + 1 ||
-                           se < c->g_be * 3 / 4 || si > c->g_bi * 5 / 4 + 1 || si < c->g_bi * 3 / 4;
-        if (stale) {
-          r = build_graph(ctx, c, gsteps, be, bi, se, si);
+    int gsteps = 0;
+    if (ctx->mode == 1 && base <= 4096) {
+      gsteps = ctx->graph_steps > 0 ? ctx->graph_steps : (int)(base * std::max<int64_t>(1, 200 / base));
+      if (gsteps % base != 0) gsteps = (int)((gsteps / base + 1) * base);
+      if (gsteps <= w) w = (w / gsteps) * gsteps; else gsteps = 0;
+    }
+    for (Case* c : act) {
+      r = upload_volt(ctx, c, c->step, c->step + w);
+      if (r) return r;
+    }
+    int64_t j = 0;
+    while (j < w) {
+      if (gsteps > 0) {
+        std::vector<int64_t> sj(s);
+        for (auto& v : sj) v += j;
+        if (!graph_matches(ctx, sj, gsteps)) {
+          r = build_graph(ctx, sj, gsteps);
           if (r) return r;
         }
-        HIPCHK(hipGraphLaunch(c->gexec, ctx->stream));
-        s += gsteps;
+        HIPCHK(hipGraphLaunch(ctx->batch.gexec, ctx->stream));
+        j += gsteps;
         continue;
       }
-      r = enqueue_step(ctx, c, s, be, bi);
+      r = enqueue_batch_step(ctx, s, j, false);
       if (r) return r;
-      ++s;
+      ++j;
     }
-    r = request_estimate(ctx, c);
-    if (r) return r;
+    for (size_t k = 0, a = 0; k < cases.size(); ++k) {
+      if (left[k] <= 0) continue;
+      cases[k]->step += w;
+      left[k] -= w;
+      r = request_estimate(ctx, act[a++]);
+      if (r) return r;
+    }
     if (ctx->ev_pairs.size() > 8192) {
       r = drain_profile(ctx);
       if (r) return r;
     }
   }
-  c->step = end;
   return EDP_OK;
 }
 
@@ -456,6 +568,10 @@ int edp_create(edp_ctx** out, int device, void* hip_stream) {
   ctx->stream = (hipStream_t)hip_stream;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+  if (hipMalloc((void**)&ctx->batch_d, sizeof(BatchDev)) != hipSuccess) {
+    delete ctx;
+    return fail(EDP_EHIP, "hipMalloc of the batch table failed");
+  }
   *out = ctx;
   return EDP_OK;
 }
@@ -463,9 +579,10 @@ int edp_create(edp_ctx** out, int device, void* hip_stream) {
 int edp_destroy(edp_ctx* ctx) {
   if (!ctx) return EDP_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  drop_graph(ctx);
+  if (ctx->batch_d) (void)hipFree(ctx->batch_d);
   for (auto& kv : ctx->cases) {
     Case* c = kv.second;
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->vstage) (void)hipHostFree(c->vstage);
     if (c->est_pinned) (void)hipHostFree(c->est_pinned);
     if (c->vev) (void)hipEventDestroy(c->vev);
@@ -657,7 +774,11 @@ int edp_case_destroy(edp_ctx* ctx, edp_case id) {
   Case* c = find(ctx, id);
   if (!c) return fail(EDP_EINVAL, "unknown case");
   (void)hipStreamSynchronize(ctx->stream);
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (std::find(ctx->batch.cases.begin(), ctx->batch.cases.end(), c) != ctx->batch.cases.end()) {
+    drop_graph(ctx);
+    ctx->batch.cases.clear();
+    ctx->batch_valid = false;
+  }
   (void)hipHostFree(c->vstage);
   (void)hipHostFree(c->est_pinned);
   (void)hipEventDestroy(c->vev);
@@ -675,10 +796,23 @@ int edp_advance_steps(edp_ctx* ctx, const edp_case* cases, int32_t n_cases, cons
     if (!c) return fail(EDP_EINVAL, "unknown case %lld", (long long)cases[k]);
     if (n_steps[k] < 0) return fail(EDP_EINVAL, "negative step count");
   }
+  std::vector<Case*> cs;
+  std::vector<int64_t> n;
+  bool skipped = false;
   for (int32_t k = 0; k < n_cases; ++k) {
-    const int r = run_steps(ctx, find(ctx, cases[k]), n_steps[k]);
-    if (r) return r;
+    Case* c = find(ctx, cases[k]);
+    if (c->failed) {
+      skipped = true;
+      continue;
+    }
+    if (std::find(cs.begin(), cs.end(), c) != cs.end()) return fail(EDP_EINVAL, "case listed twice");
+    cs.push_back(c);
+    n.push_back(n_steps[k]);
   }
+  if ((int)cs.size() > kMaxBatch) return fail(EDP_EINVAL, "more than %d cases in one call", kMaxBatch);
+  const int r = run_batch(ctx, cs, n);
+  if (r) return r;
+  if (skipped) return fail(EDP_ESTATE, "failed cases were not advanced");
   return EDP_OK;
 }
 
@@ -939,6 +1073,8 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
 
 int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
   if (!ctx) return fail(EDP_EINVAL, "null context");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  drop_graph(ctx);  // every option changes what a captured step sequence contains
   switch (key) {
     case EDP_OPT_MODE:
       if (value < 0 || value > 1) return fail(EDP_EINVAL, "mode must be 0 or 1");
@@ -954,12 +1090,10 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
     case EDP_OPT_GRAPH_STEPS:
       if (value < 0) return fail(EDP_EINVAL, "graph steps must be >= 0");
       ctx->graph_steps = (int)value;
-      for (auto& kv : ctx->cases) kv.second->g_steps = 0;
       break;
     case EDP_OPT_POISSON:
       if (value < 0 || value > 1) return fail(EDP_EINVAL, "poisson solver must be 0 or 1");
       ctx->poisson = (int)value;
-      for (auto& kv : ctx->cases) kv.second->g_steps = 0;
       break;
     case EDP_OPT_WG_PER_CU:
       if (value < 1 || value > 16) return fail(EDP_EINVAL, "workgroups per CU must be 1..16");

@@ -103,4 +103,16 @@ struct CaseDev {
   int32_t phi_valid;  // 1: phi[] holds the potential of the last step, 0: use flux[]
 };
 
+// A batch of cases stepped together: every launch advances each case by one
+// step.  Workgroups find their case from the prefix offsets (one range per
+// case, in case order).
+constexpr int kMaxBatch = 256;
+struct BatchDev {
+  int32_t ncase;
+  int32_t pad;
+  CaseDev* c[kMaxBatch];
+  int32_t part_off[2][kMaxBatch + 1];  // particle workgroups per species (chunks of capacity)
+  int32_t apply_off[kMaxBatch + 1];    // collision workgroups of the head
+};
+
 }  // namespace edp

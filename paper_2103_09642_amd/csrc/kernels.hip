@@ -167,6 +167,15 @@ template <class T>
 __device__ __forceinline__ EDP_GLOBAL T* G(T* p) {
   return (EDP_GLOBAL T*)p;
 }
+// A case's constants (and the counters no thread of the running kernel
+// writes) are read through the constant address space: uniform reads then
+// become scalar loads and stay in scalar registers.  Every write goes
+// through the ordinary pointer.
+#define EDP_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const EDP_CONST T* KC(const T* p) {
+  return (const EDP_CONST T*)p;
+}
 __device__ __forceinline__ void gl_add(int64_t* a, long long v) {
   __hip_atomic_fetch_add(G((unsigned long long*)a), (unsigned long long)v, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
@@ -251,7 +260,8 @@ __device__ __forceinline__ double block_exclusive_scan(double x, double* sW, dou
 constexpr int kFieldRows = 8;  // rows per thread of the flux scans (n_grid <= 2048)
 
 template <int MODE>
-__device__ __forceinline__ void field_solve(CaseDev* __restrict__ C, double* fsm) {
+__device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fsm) {
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int ng = C->ng;
   double* sRho = fsm;
   double* sPhi = fsm + ng;    // MODE 1: d then phi; MODE 0: S_p then fluxes F_q
@@ -381,7 +391,7 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ C, double* fsm
       G(C->rho)[p] = sRho[p];
     }
   }
-  if (threadIdx.x == 0) C->phi_valid = MODE == 1;
+  if (threadIdx.x == 0) Cw->phi_valid = MODE == 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -400,10 +410,13 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ C, double* fsm
 struct ScatterPtrs {
   EDP_GLOBAL double *ex, *evx, *evy, *evz, *ix, *ivx, *ivy, *ivz;
   EDP_GLOBAL uint64_t *euid, *iuid;
+  int64_t* anomaly;
 };
 
-__device__ __forceinline__ ScatterPtrs scatter_ptrs(const CaseDev* __restrict__ C) {
+__device__ __forceinline__ ScatterPtrs scatter_ptrs(CaseDev* __restrict__ Cw) {
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   ScatterPtrs P;
+  P.anomaly = &Cw->ctr[kAnomaly];
   const int ce = C->cur[0], ci = C->cur[1];
   P.ex = G(C->sp[0].x[ce]);
   P.evx = G(C->sp[0].vx[ce]);
@@ -422,7 +435,7 @@ __device__ __forceinline__ ScatterPtrs scatter_ptrs(const CaseDev* __restrict__ 
 // process proc (0 elastic, 1 excitation, 2 ionization).  An ionization also
 // writes its newborns: the ejected electron at slot be and the ion at slot
 // bi (-1: dropped at capacity), both at the parent's position.
-__device__ __forceinline__ void electron_scatter(const CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
+__device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
                                                  int proc, int64_t be, int64_t bi, int64_t s) {
   const double vxn = P.evx[i], vy = P.evy[i], vz = P.evz[i];
   const uint64_t uid = P.euid[i];
@@ -444,7 +457,7 @@ __device__ __forceinline__ void electron_scatter(const CaseDev* __restrict__ C, 
       double ec = 0.5 * kMuEAr * v2 - C->thr_exc * kEvToJ;
       if (ec < 0.0) {
         ec = 0.0;
-        gl_add(&((CaseDev*)C)->ctr[kAnomaly], 1);
+        gl_add(P.anomaly, 1);
       }
       gnew = sqrt(2.0 * ec / kMuEAr);
     }
@@ -457,7 +470,7 @@ __device__ __forceinline__ void electron_scatter(const CaseDev* __restrict__ C, 
     double e_ev = 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion;
     if (e_ev < 0.0) {
       e_ev = 0.0;
-      gl_add(&((CaseDev*)C)->ctr[kAnomaly], 1);
+      gl_add(P.anomaly, 1);
     }
     const double w_ion = C->w_ion;
     const double e_ej = w_ion * tan(r_share * atan(e_ev / (2.0 * w_ion)));
@@ -507,7 +520,7 @@ __device__ __forceinline__ void electron_scatter(const CaseDev* __restrict__ C, 
 
 // Ar+ + Ar scattering of queued ion i (proc 0 isotropic, 1 backward) with the
 // thermal target of its test (redrawn from the same counter: the same atom).
-__device__ __forceinline__ void ion_scatter(const CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i, int proc,
+__device__ __forceinline__ void ion_scatter(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i, int proc,
                                             int64_t s) {
   const double vxn = P.ivx[i], vy = P.ivy[i], vz = P.ivz[i];
   const uint64_t uid = P.iuid[i];
@@ -546,10 +559,11 @@ __device__ __forceinline__ void ion_scatter(const CaseDev* __restrict__ C, const
 constexpr int kHalf = 32;
 constexpr int kApplyChunks = kBlock / kHalf;  // chunks per round of a workgroup
 
-__device__ __forceinline__ void apply_queue(const CaseDev* __restrict__ C, int blk, int nblk) {
+__device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, int nblk) {
   __shared__ int64_t sRed[64];
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int64_t s = C->q_step;
-  const ScatterPtrs P = scatter_ptrs(C);
+  const ScatterPtrs P = scatter_ptrs(Cw);
   const int hw = (int)threadIdx.x / kHalf, lane = (int)threadIdx.x % kHalf;
   const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
   const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
@@ -605,8 +619,9 @@ __device__ __forceinline__ void apply_queue(const CaseDev* __restrict__ C, int b
 // Totals of the pending queue (one workgroup, beside the apply workgroups):
 // collision, ionization and absorption counters, newborns placed, slot
 // counts for the next step.
-__device__ __forceinline__ void apply_totals(CaseDev* __restrict__ C) {
+__device__ __forceinline__ void apply_totals(CaseDev* __restrict__ Cw) {
   __shared__ int64_t sRed[64];
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   int64_t tq[2] = {0, 0}, tz = 0, tap[2] = {0, 0}, tag_[2] = {0, 0};
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t nb = C->q_nblk[sp];
@@ -634,41 +649,59 @@ __device__ __forceinline__ void apply_totals(CaseDev* __restrict__ C) {
     const int64_t room_e = C->sp[0].cap - base_e, room_i = C->sp[1].cap - base_i;
     const int64_t ok_e = tz < room_e ? tz : (room_e > 0 ? room_e : 0);
     const int64_t ok_i = tz < room_i ? tz : (room_i > 0 ? room_i : 0);
-    C->alloc[0] = C->n[0] = base_e + ok_e;
-    C->alloc[1] = C->n[1] = base_i + ok_i;
-    C->ctr[kCollE] += tq[0];
-    C->ctr[kCollI] += tq[1];
-    C->ctr[kIoniz] += tz;
-    C->ctr[kAbsEPow] += tap[0];
-    C->ctr[kAbsEGnd] += tag_[0];
-    C->ctr[kAbsIPow] += tap[1];
-    C->ctr[kAbsIGnd] += tag_[1];
-    C->ctr[kLiveE] += ok_e - tap[0] - tag_[0];
-    C->ctr[kLiveI] += ok_i - tap[1] - tag_[1];
+    Cw->alloc[0] = Cw->n[0] = base_e + ok_e;
+    Cw->alloc[1] = Cw->n[1] = base_i + ok_i;
+    Cw->ctr[kCollE] += tq[0];
+    Cw->ctr[kCollI] += tq[1];
+    Cw->ctr[kIoniz] += tz;
+    Cw->ctr[kAbsEPow] += tap[0];
+    Cw->ctr[kAbsEGnd] += tag_[0];
+    Cw->ctr[kAbsIPow] += tap[1];
+    Cw->ctr[kAbsIGnd] += tag_[1];
+    Cw->ctr[kLiveE] += ok_e - tap[0] - tag_[0];
+    Cw->ctr[kLiveI] += ok_i - tap[1] - tag_[1];
     if (ok_e < tz || ok_i < tz) {
-      C->ctr[kDropped] += (tz - ok_e) + (tz - ok_i);
-      C->error = 1;
+      Cw->ctr[kDropped] += (tz - ok_e) + (tz - ok_i);
+      Cw->error = 1;
     }
   }
 }
 
-// Head of step s: workgroup 0 solves the field, the middle ones apply the
-// queue of step s-1, the last one folds its totals and does the step's
+// The case of workgroup `bid` in a list of per-case ranges [off[k], off[k+1]):
+// every thread tests one range (ncase <= kMaxBatch = blockDim), the match is
+// broadcast through LDS.
+__device__ __forceinline__ int find_case(const int32_t* __restrict__ off, int ncase, int bid) {
+  __shared__ int sCase;
+  const int t = threadIdx.x;
+  if (t < ncase && G(off)[t] <= bid && bid < G(off)[t + 1]) sCase = t;
+  __syncthreads();
+  // uniform across the workgroup: keep it (and everything read through the
+  // case pointer) in scalar registers
+  return __builtin_amdgcn_readfirstlane(sCase);
+}
+
+// Head of step s for every case of the batch.  Workgroups [0, ncase) solve
+// the fields, the next apply_off[ncase] apply the queues of step s-1 (a range
+// per case), the last ncase fold each queue's totals and do the step's
 // bookkeeping.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_head(CaseDev* __restrict__ C) {
+__global__ void __launch_bounds__(kBlock) k_head(const BatchDev* __restrict__ B) {
   extern __shared__ double hsm[];
-  if (blockIdx.x == 0) {
-    field_solve<MODE>(C, hsm);
+  const int nc = B->ncase;
+  const int bid = (int)blockIdx.x;
+  if (bid < nc) {
+    field_solve<MODE>(B->c[bid], hsm);
     return;
   }
-  const int blk = (int)blockIdx.x - 1, napply = (int)gridDim.x - 2;
-  const bool valid = C->q_valid != 0;
-  if (blk < napply) {
-    if (valid) apply_queue(C, blk, napply);
+  const int na = B->apply_off[nc];
+  if (bid < nc + na) {
+    const int k = find_case(B->apply_off, nc, bid - nc);
+    CaseDev* C = B->c[k];
+    if (C->q_valid) apply_queue(C, bid - nc - B->apply_off[k], B->apply_off[k + 1] - B->apply_off[k]);
     return;
   }
-  if (valid) apply_totals(C);
+  CaseDev* C = B->c[bid - nc - na];
+  if (C->q_valid) apply_totals(C);
   if (threadIdx.x == 0) {
     const int64_t s = C->step;
     const bool ion_step = (s % C->nsub) == 0;
@@ -713,25 +746,27 @@ __global__ void k_drain_done(CaseDev* __restrict__ C) {
 // J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).
 // ---------------------------------------------------------------------------
 template <int SP>
-__global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
+__device__ __forceinline__ void particles_chunk(CaseDev* __restrict__ Cw, const int64_t chunk) {
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   extern __shared__ double psm[];
   __shared__ unsigned int sCtr[kLN];
   __shared__ int64_t sScan[64];
   const int64_t s = C->pstep;
   const int64_t n = C->n[SP];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (SP == 1 && (s % C->nsub) != 0) return;  // ions move on ion steps only
+  if (chunk == 0 && threadIdx.x == 0) {
     // this step's queue: read by the next head (or a drain)
-    C->q_step = s;
-    C->q_base[SP] = n;
-    C->q_nblk[SP] = (int32_t)((n + kChunk - 1) / kChunk);
+    Cw->q_step = s;
+    Cw->q_base[SP] = n;
+    Cw->q_nblk[SP] = (int32_t)((n + kChunk - 1) / kChunk);
     if (SP == 0) {
-      C->q_base[1] = C->n[1];
-      C->q_nblk[1] = 0;  // set by the ion kernel on ion steps
-      C->q_valid = 1;
-      C->step = s + 1;
+      Cw->q_base[1] = C->n[1];
+      Cw->q_nblk[1] = 0;  // set by the ion kernel on ion steps
+      Cw->q_valid = 1;
+      Cw->step = s + 1;
     }
   }
-  const int64_t lo = (int64_t)blockIdx.x * kChunk;
+  const int64_t lo = chunk * kChunk;
   if (lo >= n) return;  // whole workgroup: no live slots in this chunk
   const int64_t hi = lo + kChunk < n ? lo + kChunk : n;
   const int ng = C->ng;
@@ -961,10 +996,18 @@ __global__ void __launch_bounds__(kBlock) k_particles(CaseDev* __restrict__ C) {
     for (int b = threadIdx.x; b < n_eepf; b += blockDim.x)
       if (sF[b]) gl_add(&C->eepf[b], (long long)sF[b]);
   if (threadIdx.x == 0) {
-    EDP_GLOBAL int32_t* rec = G(C->cq_rec[SP]) + 2 * blockIdx.x;
+    EDP_GLOBAL int32_t* rec = G(C->cq_rec[SP]) + 2 * chunk;
     rec[0] = tot;
     rec[1] = (int)(sCtr[kLAbsPow] | (sCtr[kLAbsGnd] << 16));
   }
+}
+
+// One launch per species covers the chunks of every case of the batch.
+template <int SP>
+__global__ void __launch_bounds__(kBlock) k_particles(const BatchDev* __restrict__ B) {
+  const int bid = (int)blockIdx.x;
+  const int k = find_case(B->part_off[SP], B->ncase, bid);
+  particles_chunk<SP>(B->c[k], (int64_t)(bid - B->part_off[SP][k]));
 }
 
 __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma) {
@@ -1160,15 +1203,16 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp) {
   return doubles * 8;
 }
 
-// Head of a step: 1 field workgroup, `scatter_blocks` collision workgroups,
-// 1 totals/bookkeeping workgroup.
-hipError_t launch_head(CaseDev* d, int ng, int mode, int scatter_blocks, hipStream_t st) {
-  const size_t lds = (size_t)ng * 24 + 64 * 8;
-  const dim3 grid(2 + scatter_blocks);
+// Head of a batch step: ncase field workgroups, `apply_blocks` collision
+// workgroups in total, ncase totals/bookkeeping workgroups.  `max_ng` sizes
+// the field workgroups' LDS.
+hipError_t launch_head(const BatchDev* b, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st) {
+  const size_t lds = (size_t)max_ng * 24 + 64 * 8;
+  const dim3 grid(2 * ncase + apply_blocks);
   if (mode == 1)
-    hipLaunchKernelGGL(k_head<1>, grid, dim3(kBlock), lds, st, d);
+    hipLaunchKernelGGL(k_head<1>, grid, dim3(kBlock), lds, st, b);
   else
-    hipLaunchKernelGGL(k_head<0>, grid, dim3(kBlock), lds, st, d);
+    hipLaunchKernelGGL(k_head<0>, grid, dim3(kBlock), lds, st, b);
   return hipGetLastError();
 }
 
@@ -1178,20 +1222,21 @@ hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st) {
   return hipGetLastError();
 }
 
-// With ev0/ev1 the launch records its own start and end (the dispatch's
-// timestamps, not those of separate event packets around it).
-hipError_t launch_particles(CaseDev* d, int sp, int blocks, int ng, uint32_t flags, int n_eepf,
-                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  const size_t lds = particle_lds_bytes(ng, flags, n_eepf, sp);
+// One species of a batch: `blocks` = the species' total chunk count;
+// `lds` = the largest per-case need.  With ev0/ev1 the launch records its own
+// start and end (the dispatch's timestamps, not those of separate event
+// packets around it).
+hipError_t launch_particles(const BatchDev* b, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
+                            hipEvent_t ev1) {
   if (ev0) {
     if (sp == 0)
-      hipExtLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, d);
+      hipExtLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, b);
     else
-      hipExtLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, d);
+      hipExtLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, b);
   } else if (sp == 0) {
-    hipLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, d);
+    hipLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, b);
   } else {
-    hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, d);
+    hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, b);
   }
   return hipGetLastError();
 }

@@ -1,0 +1,120 @@
+"""Batched execution: several cases advanced by one call, every launch
+serving all of them.  A case's result must not depend on what it is batched
+with: bit-identical to the same case advanced alone (integer deposits,
+random numbers keyed by particle identity and step, per-case sort schedule).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import by_uid, compare_states, gpu_context, say
+from paper_2103_09642_amd.workloads import base_case, random_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(xs_default):
+    c = gpu_context()
+    c.set_xsec(xs_default)
+    return c
+
+
+def _mix():
+    """Four different cases: grids, subcycling, pressures, sizes, gaps."""
+    specs = [
+        dict(n_grid=400, ion_subcycle=20, pressure_pa=20.0, gap_m=0.025, n=30_000, seed=21),
+        dict(n_grid=173, ion_subcycle=5, pressure_pa=60.0, gap_m=0.015, n=8_000, seed=22),
+        dict(n_grid=1000, ion_subcycle=20, pressure_pa=10.0, gap_m=0.04, n=50_000, seed=23),
+        dict(n_grid=2, ion_subcycle=3, pressure_pa=5.0, gap_m=0.02, n=1_000, seed=24),
+    ]
+    out = []
+    for sp in specs:
+        n = sp.pop("n")
+        seed = sp.pop("seed")
+        c = base_case(n_init_e=0, n_init_i=0, weight=1e5, flags=["allow_unstable"], cap_e=4 * n, cap_i=4 * n,
+                      seed=seed, **sp)
+        st = random_state(n, n, c["gap_m"], seed=seed, te_ev=3.0, hot_frac=0.2, hot_ev=80.0)
+        out.append((c, st))
+    return out
+
+
+def _make(ctx, c, st, step0):
+    g = ctx.create_case(c)
+    g.set_state(0, st["e"], step0)
+    g.set_state(1, st["i"], step0)
+    return g
+
+
+def _result(g):
+    return by_uid(g.get_state(0)), by_uid(g.get_state(1)), g.deposit(), g.counts()
+
+
+def _same(a, b, label):
+    for sp in (0, 1):
+        for k in ("uid", "x", "vx", "vy", "vz"):
+            assert np.array_equal(a[sp][k], b[sp][k]), f"{label}: species {sp} {k}"
+    assert np.array_equal(a[2][0], b[2][0]) and np.array_equal(a[2][1], b[2][1]), f"{label}: deposit"
+    assert a[3] == b[3], f"{label}: counters"
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["plain", "graph"])
+def test_batch_equals_alone(ctx, mode):
+    """Different step counts (the batch shrinks as cases finish) and
+    different starting steps (different ion-step and sort phases)."""
+    say(f"test_batch_equals_alone mode={mode}")
+    from paper_2103_09642_amd import edupic
+    ctx.set_option(edupic.OPT_MODE, mode)
+    ctx.set_option(edupic.OPT_SORT_EVERY, 10)
+    mix = _mix()
+    steps = [700, 433, 700, 120]
+    starts = [0, 3, 17, 5]
+    alone = []
+    for (c, st), n, s0 in zip(mix, steps, starts):
+        g = _make(ctx, c, st, s0)
+        g.advance_steps(n)
+        alone.append(_result(g))
+        g.destroy()
+    gs = [_make(ctx, c, st, s0) for (c, st), s0 in zip(mix, starts)]
+    ctx.advance_steps(gs, steps)
+    for k, g in enumerate(gs):
+        r = _result(g)
+        assert r[3]["step"] == starts[k] + steps[k]
+        _same(alone[k], r, f"case {k}")
+        g.destroy()
+    ctx.set_option(edupic.OPT_MODE, 0)
+    ctx.set_option(edupic.OPT_SORT_EVERY, 100)
+
+
+def test_batch_matches_oracle(ctx, xs_default, orc):
+    """Three cases advanced together for 40 steps against three oracle runs:
+    counters exact, states to the one-step bar (with the flux solve's field
+    kick as the velocity floor)."""
+    say("test_batch_matches_oracle")
+    mix = _mix()[:3]
+    gs, os_ = [], []
+    for c, st in mix:
+        gs.append(_make(ctx, c, st, 0))
+        o = orc.Oracle(c, xs_default)
+        o.set_state(0, st["e"], 0)
+        o.set_state(1, st["i"], 0)
+        os_.append(o)
+    ctx.advance_steps(gs, [40, 40, 40])
+    for (c, _), g, o in zip(mix, gs, os_):
+        o.step(40)
+        cg, co = g.counts(), o.counts()
+        for k in ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz"):
+            assert cg[k] == co[k], k
+        for sp in (0, 1):
+            compare_states(g.get_state(sp), o.get_state(sp), 1e-9, f"ng={c['n_grid']} sp{sp}")
+        g.destroy()
+
+
+def test_batch_rejects_duplicates_and_skips_failed(ctx):
+    say("test_batch_rejects_duplicates_and_skips_failed")
+    from paper_2103_09642_amd import edupic
+    c, st = _mix()[1]
+    g = _make(ctx, c, st, 0)
+    with pytest.raises(edupic.EdpError) as ei:
+        ctx.advance_steps([g, g], [1, 1])
+    assert ei.value.code == edupic.EDP_EINVAL
+    g.destroy()
