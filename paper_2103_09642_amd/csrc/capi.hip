@@ -28,6 +28,7 @@ hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
 hipError_t launch_particles(const BatchDev* b, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
                             hipEvent_t ev1);
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp);
+int particle_occupancy(int sp, size_t lds);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
 hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
                           hipStream_t st);
@@ -175,7 +176,7 @@ Layout layout(const edp_case_desc* c, int nbins) {
   for (int sp = 0; sp < 2; ++sp) {
     const size_t chunks = (size_t)((L.cap[sp] + kChunk - 1) / kChunk);
     L.off_cq[sp][0] = take(chunks * kChunk * 4);  // events
-    L.off_cq[sp][1] = take(chunks * 8);           // chunk records
+    L.off_cq[sp][1] = take(chunks * 16);          // chunk records (one word per wave)
   }
   for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
   const size_t ng = (size_t)c->n_grid;
@@ -237,17 +238,14 @@ int blocks_for(const edp_ctx* ctx, int64_t n) {
 // one case).
 int scatter_blocks(const edp_ctx* ctx) { return ctx->num_cu; }
 
-// Particle workgroups of one species of a case: one per kChunk slots of
-// capacity, so any particle count is covered and graphs stay valid.
-int particle_blocks(const Case* c, int sp) {
-  return (int)((c->h.sp[sp].cap + kChunk - 1) / kChunk);
-}
+// Expected chunks of a species of a case (10% headroom over the estimate).
+int64_t est_chunks(const Case* c, int sp) { return (c->est[sp] + c->est[sp] / 10 + kChunk) / kChunk; }
 
-// Collision workgroups of a case in the head: a half-wave per chunk of the
-// estimated live slots, eight chunks per workgroup, at most one per CU.
+// Collision workgroups of a case in the head: 8 lanes per chunk of the
+// estimated live slots, 32 chunks per workgroup, at most one per CU.
 int apply_blocks(const edp_ctx* ctx, const Case* c) {
   const int64_t chunks = (std::max(c->est[0], c->est[1]) + kChunk - 1) / kChunk;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(ctx->num_cu, (chunks + 7) / 8));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ctx->num_cu, (chunks + 31) / 32));
 }
 
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
@@ -314,43 +312,57 @@ void drop_graph(edp_ctx* ctx) {
   ctx->batch.g_steps = 0;
 }
 
-// Build the batch table for `cs` (in this order) and upload it.  The table
-// is read by kernels still in flight, so the stream is drained first.
+// Build the batch table for `cs` (in this order) and upload it.  Particle
+// workgroups: the chip's resident workgroups shared out in proportion to
+// each case's expected chunks, so every workgroup takes about the same
+// number of chunks (any count is still covered: the kernels split the live
+// chunks over whatever workgroups a case has).  The table is read by
+// kernels still in flight, so the stream is drained before it changes;
+// grids are rebuilt only when a case's estimate has moved by a quarter.
 int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   Batch& B = ctx->batch;
+  const size_t nc = cs.size();
+  size_t lds[2] = {0, 0};
+  int max_ng = 2;
+  for (const Case* c : cs) {
+    for (int sp = 0; sp < 2; ++sp)
+      lds[sp] = std::max(lds[sp], particle_lds_bytes(c->desc.n_grid, c->desc.flags, c->desc.n_eepf, sp));
+    max_ng = std::max(max_ng, (int)c->desc.n_grid);
+  }
+  std::vector<int> want[2], want_apply(nc);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t slots = (int64_t)ctx->num_cu * particle_occupancy(sp, lds[sp]);
+    int64_t total = 0;
+    for (const Case* c : cs) total += est_chunks(c, sp);
+    const int64_t per = std::max<int64_t>(1, (total + slots - 1) / slots);
+    want[sp].resize(nc);
+    for (size_t k = 0; k < nc; ++k)
+      want[sp][k] = (int)std::max<int64_t>(1, (est_chunks(cs[k], sp) + per - 1) / per);
+  }
+  for (size_t k = 0; k < nc; ++k) want_apply[k] = apply_blocks(ctx, cs[k]);
+  auto near = [](int a, int a0) { return a <= a0 * 5 / 4 + 1 && a >= a0 * 3 / 4; };
   bool same = ctx->batch_valid && B.cases == cs;
-  if (same) {
-    // grids follow the particle estimates; rebuild when they have moved far
-    for (size_t k = 0; k < cs.size() && same; ++k) {
-      const int a = apply_blocks(ctx, cs[k]);
-      const int a0 = B.h.apply_off[k + 1] - B.h.apply_off[k];
-      same = a <= a0 * 5 / 4 + 1 && a >= a0 * 3 / 4;
-    }
+  for (size_t k = 0; k < nc && same; ++k) {
+    same = near(want_apply[k], B.h.apply_off[k + 1] - B.h.apply_off[k]);
+    for (int sp = 0; sp < 2 && same; ++sp) same = near(want[sp][k], B.h.part_off[sp][k + 1] - B.h.part_off[sp][k]);
   }
   if (same) return EDP_OK;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   drop_graph(ctx);
   B.cases = cs;
   B.h = BatchDev{};
-  B.h.ncase = (int32_t)cs.size();
-  B.max_ng = 2;
-  B.lds[0] = B.lds[1] = 0;
-  for (int sp = 0; sp < 2; ++sp) B.h.part_off[sp][0] = 0;
-  B.h.apply_off[0] = 0;
-  for (size_t k = 0; k < cs.size(); ++k) {
-    const Case* c = cs[k];
-    const edp_case_desc& D = c->desc;
-    B.h.c[k] = c->d;
-    for (int sp = 0; sp < 2; ++sp) {
-      B.h.part_off[sp][k + 1] = B.h.part_off[sp][k] + particle_blocks(c, sp);
-      B.lds[sp] = std::max(B.lds[sp], particle_lds_bytes(D.n_grid, D.flags, D.n_eepf, sp));
-    }
-    B.h.apply_off[k + 1] = B.h.apply_off[k] + apply_blocks(ctx, c);
-    B.max_ng = std::max(B.max_ng, (int)D.n_grid);
+  B.h.ncase = (int32_t)nc;
+  B.max_ng = max_ng;
+  B.lds[0] = lds[0];
+  B.lds[1] = lds[1];
+  for (size_t k = 0; k < nc; ++k) {
+    B.h.c[k] = cs[k]->d;
+    for (int sp = 0; sp < 2; ++sp) B.h.part_off[sp][k + 1] = B.h.part_off[sp][k] + want[sp][k];
+    B.h.apply_off[k + 1] = B.h.apply_off[k] + want_apply[k];
   }
-  B.parts[0] = B.h.part_off[0][cs.size()];
-  B.parts[1] = B.h.part_off[1][cs.size()];
-  B.apply = B.h.apply_off[cs.size()];
+  B.parts[0] = B.h.part_off[0][nc];
+  B.parts[1] = B.h.part_off[1][nc];
+  B.apply = B.h.apply_off[nc];
   HIPCHK(hipMemcpy(ctx->batch_d, &B.h, sizeof(BatchDev), hipMemcpyHostToDevice));
   ctx->batch_valid = true;
   return EDP_OK;

@@ -31,8 +31,7 @@ constexpr double kDiagES = 1048576.0;  // c * energy [eV]
 
 // Particle kernels: workgroup size and the particle slots each workgroup owns.
 constexpr int kBlock = 256;
-constexpr int kPerThread = 4;
-constexpr int kChunk = kBlock * kPerThread;
+constexpr int kChunk = kBlock;  // particle slots per chunk: one per thread of a workgroup
 constexpr int kMaxNodes = 2048;                      // largest n_grid accepted
 constexpr int kGridPerThread = kMaxNodes / kBlock;   // grid nodes per thread
 constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
@@ -76,12 +75,12 @@ struct CaseDev {
   int64_t *acc_je, *acc_ji, *acc_w, *acc_e;                   // [3][ng] per step
   int64_t *eepf;                                              // [n_eepf]
   int64_t *sort_cnt;                                          // [ng + 1] scratch
-  // Collision queue of the last particle step, per species.  Chunk c (slots
-  // [c*kChunk, (c+1)*kChunk)) writes its events to cq_ent[c*kChunk + k] and
-  // its totals to cq_rec[2c] = events | ionizations << 16 and
-  // cq_rec[2c+1] = absorbed at x=0 | absorbed at x=L << 16, so no two
-  // workgroups ever write the same word.  An event is
-  // slot-in-chunk | process << 10 | ionization rank in the chunk << 12.
+  // Collision queue of the last particle step, per species.  Wave w of chunk
+  // c (slots [c*kChunk, (c+1)*kChunk), 64 per wave) writes its events to
+  // cq_ent[c*kChunk + 64w + k] and its totals to cq_rec[4c + w] =
+  // events | ionizations << 7 | absorbed at x=0 << 14 | absorbed at x=L << 21,
+  // so no two waves ever write the same word.  An event is
+  // slot-in-chunk | process << 10 | ionization rank in the wave << 12.
   int32_t* cq_ent[2];
   int32_t* cq_rec[2];
   // ---- dynamic (device-mutated) -----------------------------------------

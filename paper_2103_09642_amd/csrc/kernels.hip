@@ -184,8 +184,6 @@ __device__ __forceinline__ unsigned long long gl_fetch_add(int64_t* a, unsigned 
   return __hip_atomic_fetch_add(G((unsigned long long*)a), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// LDS counters of a particle workgroup.
-enum { kLAbsPow = 0, kLAbsGnd, kLN };
 
 // Exclusive scan of one integer per thread across the workgroup; *total
 // gets the sum.  scratch: 64 int64 of LDS.
@@ -551,51 +549,69 @@ __device__ __forceinline__ void ion_scatter(const EDP_CONST CaseDev* __restrict_
 }
 
 // Apply the pending collision queue.  Workgroup blk of nblk takes a
-// contiguous range of chunks of each species; each half-wave (32 lanes)
-// takes one chunk, its record and its first 32 events loaded together.
-// Newborns of chunk c go to q_base + (ionizations of chunks < c) + rank, so
-// the ionization counts before the range are summed with the same loads.
-// No atomics: every slot follows from the chunk records alone.
-constexpr int kHalf = 32;
-constexpr int kApplyChunks = kBlock / kHalf;  // chunks per round of a workgroup
+// contiguous range of chunks of each species; a group of 8 lanes takes one
+// chunk: its four wave records and the first two events of each wave's part
+// of the queue are loaded together, lane l working through the events of
+// wave l/2.  Newborns of chunk c go to q_base + (ionizations of chunks < c)
+// + (ionizations of lower waves of c) + rank, so the ionization counts
+// before the range are summed with the same loads.  No atomics: every slot
+// follows from the records alone.
+constexpr int kApplyLanes = 8;
+typedef int rec4 __attribute__((ext_vector_type(4)));  // the four wave records of a chunk
+constexpr int kApplyChunks = kBlock / kApplyLanes;  // chunks per round of a workgroup
+
+__device__ __forceinline__ int rec_q(int r) { return r & 127; }
+__device__ __forceinline__ int rec_z(int r) { return (r >> 7) & 127; }
+__device__ __forceinline__ int rec_ap(int r) { return (r >> 14) & 127; }
+__device__ __forceinline__ int rec_ag(int r) { return (r >> 21) & 127; }
+__device__ __forceinline__ int rec_pick(const rec4 r, int w) { return w == 0 ? r.x : w == 1 ? r.y : w == 2 ? r.z : r.w; }
 
 __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, int nblk) {
   __shared__ int64_t sRed[64];
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int64_t s = C->q_step;
   const ScatterPtrs P = scatter_ptrs(Cw);
-  const int hw = (int)threadIdx.x / kHalf, lane = (int)threadIdx.x % kHalf;
+  const int grp = (int)threadIdx.x / kApplyLanes, l = (int)threadIdx.x % kApplyLanes;
+  const int wv = l / 2, jj = l % 2;  // this lane's wave part of the chunk and first entry
   const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
   const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t nb = C->q_nblk[sp];
-    const EDP_GLOBAL int32_t* __restrict__ rec = G(C->cq_rec[sp]);
+    const EDP_GLOBAL rec4* __restrict__ rec = (const EDP_GLOBAL rec4*)G(C->cq_rec[sp]);
     const EDP_GLOBAL int32_t* __restrict__ ent = G(C->cq_ent[sp]);
     const int64_t c0 = nb * blk / nblk, c1 = nb * (blk + 1) / nblk;
     int64_t zrun = 0;  // newborns of the chunks before the current round
     for (int64_t cb = c0; cb < c1; cb += kApplyChunks) {
-      const int64_t c = cb + hw;
+      const int64_t c = cb + grp;
       const bool valid = c < c1;
-      const int r0 = valid ? rec[2 * c] : 0;
-      const int code0 = valid ? ent[c * kChunk + lane] : 0;  // in bounds: the region is kChunk long
-      const int q = r0 & 0xFFFF;
+      rec4 r4 = {0, 0, 0, 0};
+      if (valid) r4 = rec[c];
+      const int64_t e0 = c * kChunk + wv * 64;
+      const int code0 = valid ? ent[e0 + jj] : 0;  // in bounds: each wave part is 64 long
+      const int qw = rec_q(rec_pick(r4, wv));
       if (sp == 0) {
         // high word: ionizations of chunks < c0 (first round), low word: this
-        // round's ionizations of lower half-waves
+        // round's ionizations of lower groups
         int64_t zpre = 0;
         if (cb == c0) {
 #pragma unroll 8
-          for (int64_t k = threadIdx.x; k < c0; k += blockDim.x) zpre += rec[2 * k] >> 16;
+          for (int64_t k = threadIdx.x; k < c0; k += blockDim.x) {
+            const rec4 t = rec[k];
+            zpre += rec_z(t.x) + rec_z(t.y) + rec_z(t.z) + rec_z(t.w);
+          }
         }
-        const int64_t x = (zpre << 32) | (int64_t)(lane == 0 ? (r0 >> 16) : 0);
+        const int zc = rec_z(r4.x) + rec_z(r4.y) + rec_z(r4.z) + rec_z(r4.w);
+        const int64_t x = (zpre << 32) | (int64_t)(l == 0 ? zc : 0);
         int64_t tot;
         const int64_t exc = block_exclusive_scan_t<int64_t>(x, sRed, &tot);
-        const int64_t low = __shfl(exc & 0xFFFFFFFFLL, 0, kHalf);  // lane 0 of the half-wave
+        const int64_t low = __shfl(exc & 0xFFFFFFFFLL, 0, kApplyLanes);  // lane 0 of the group
         if (cb == c0) zrun = tot >> 32;
-        const int64_t zbase = zrun + low;
+        // ionizations of the lower waves of this chunk
+        const int zw = (wv > 0 ? rec_z(r4.x) : 0) + (wv > 1 ? rec_z(r4.y) : 0) + (wv > 2 ? rec_z(r4.z) : 0);
+        const int64_t zbase = zrun + low + zw;
         zrun += tot & 0xFFFFFFFFLL;
-        for (int k = lane; k < q; k += kHalf) {
-          const int code = k < kHalf ? code0 : ent[c * kChunk + k];
+        for (int k = jj; k < qw; k += 2) {
+          const int code = k == jj ? code0 : ent[e0 + k];
           const int64_t i = c * kChunk + (code & 1023);
           const int proc = (code >> 10) & 3;
           int64_t be = -1, bi = -1;
@@ -607,8 +623,8 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
           electron_scatter(C, P, i, proc, be, bi, s);
         }
       } else {
-        for (int k = lane; k < q; k += kHalf) {
-          const int code = k < kHalf ? code0 : ent[c * kChunk + k];
+        for (int k = jj; k < qw; k += 2) {
+          const int code = k == jj ? code0 : ent[e0 + k];
           ion_scatter(C, P, c * kChunk + (code & 1023), (code >> 10) & 3, s);
         }
       }
@@ -625,17 +641,17 @@ __device__ __forceinline__ void apply_totals(CaseDev* __restrict__ Cw) {
   int64_t tq[2] = {0, 0}, tz = 0, tap[2] = {0, 0}, tag_[2] = {0, 0};
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t nb = C->q_nblk[sp];
-    const EDP_GLOBAL int32_t* __restrict__ rec = G(C->cq_rec[sp]);
+    const EDP_GLOBAL rec4* __restrict__ rec = (const EDP_GLOBAL rec4*)G(C->cq_rec[sp]);
     int64_t a = 0, b = 0, d = 0, f = 0;
 #pragma unroll 8
     for (int64_t c = threadIdx.x; c < nb; c += blockDim.x) {
-      const int r0 = rec[2 * c], r1 = rec[2 * c + 1];
-      a += r0 & 0xFFFF;
-      b += r0 >> 16;
-      d += r1 & 0xFFFF;
-      f += r1 >> 16;
+      const rec4 t = rec[c];
+      a += rec_q(t.x) + rec_q(t.y) + rec_q(t.z) + rec_q(t.w);
+      b += rec_z(t.x) + rec_z(t.y) + rec_z(t.z) + rec_z(t.w);
+      d += rec_ap(t.x) + rec_ap(t.y) + rec_ap(t.z) + rec_ap(t.w);
+      f += rec_ag(t.x) + rec_ag(t.y) + rec_ag(t.z) + rec_ag(t.w);
     }
-    // one scan of four 16-bit-safe sums would overflow; pack two per word
+    // two sums per scan word (each total fits in 32 bits)
     int64_t t0, t1;
     (void)block_exclusive_scan_t<int64_t>((a << 32) | b, sRed, &t0);
     (void)block_exclusive_scan_t<int64_t>((d << 32) | f, sRed, &t1);
@@ -729,36 +745,50 @@ __global__ void k_drain_done(CaseDev* __restrict__ C) {
 // ---------------------------------------------------------------------------
 // Steps 3-6 for one species plus the deposit for step s+1.
 //
-// Workgroup b owns particle slots [b*kChunk, (b+1)*kChunk); the grid covers
-// the capacity, so any particle count is handled and launch shapes never
-// depend on it (workgroups past the live slots exit at once).  Every
-// particle: gather E from LDS, leapfrog, wall test, the collision test (one
-// Philox call and one exp for an electron; the thermal target draw first for
-// an ion), store x and v_x, deposit the new x into the workgroup's LDS
-// histogram.  A colliding particle's process is selected here; an
-// ionization deposits its two newborns (same position as the parent: the
-// electron doubles the parent's share, the ion goes to the next ion step's
-// density).  Events are written to the chunk's own part of the queue, with
-// the chunk totals in its record: the kernel has no returning atomics and no
-// two workgroups share a counter.
+// A case's particle slots are cut into chunks of kChunk = 256 slots; wave w
+// of a workgroup owns slots [c*256 + 64w, c*256 + 64w + 64) of chunk c, one
+// per lane.  The case gets a fixed number of workgroups (sized from the
+// occupancy and the expected particle count); workgroup j takes the
+// contiguous chunk range [j*per, (j+1)*per) with per computed from the live
+// slot count at run time, so the launch shape never depends on the count,
+// every workgroup does the same amount of work, and E is loaded and the
+// deposit flushed once per workgroup.
+//
+// Every particle: gather E from LDS, leapfrog, wall test, the collision test
+// (one Philox call and one exp for an electron; the thermal target draw
+// first for an ion), store x and v_x, deposit the new x into the
+// workgroup's LDS histogram.  A colliding particle's process is selected
+// here; an ionization deposits its two newborns (same position as the
+// parent: the electron doubles the parent's share, the ion goes to the next
+// ion step's density).  Each wave compacts its events with a ballot into
+// its own 64-entry part of the chunk's queue and writes one record word:
+// events | ionizations << 7 | absorbed at x=0 << 14 | absorbed at x=L << 21.
+// Waves never synchronise inside the loop; the kernel has no returning
+// atomics and no two waves share a counter.
 //
 // Dynamic LDS: E[ng] double, H[ng] deposit; with particle diagnostics also
 // J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).
 // ---------------------------------------------------------------------------
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+  // set bits of mask below this lane
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 template <int SP>
-__device__ __forceinline__ void particles_chunk(CaseDev* __restrict__ Cw, const int64_t chunk) {
+__device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const int j, const int nwg) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   extern __shared__ double psm[];
-  __shared__ unsigned int sCtr[kLN];
-  __shared__ int64_t sScan[64];
   const int64_t s = C->pstep;
   const int64_t n = C->n[SP];
   if (SP == 1 && (s % C->nsub) != 0) return;  // ions move on ion steps only
-  if (chunk == 0 && threadIdx.x == 0) {
+  const int64_t nch = (n + kChunk - 1) / kChunk;
+  if (j == 0 && threadIdx.x == 0) {
     // this step's queue: read by the next head (or a drain)
     Cw->q_step = s;
     Cw->q_base[SP] = n;
-    Cw->q_nblk[SP] = (int32_t)((n + kChunk - 1) / kChunk);
+    Cw->q_nblk[SP] = (int32_t)nch;
     if (SP == 0) {
       Cw->q_base[1] = C->n[1];
       Cw->q_nblk[1] = 0;  // set by the ion kernel on ion steps
@@ -766,9 +796,10 @@ __device__ __forceinline__ void particles_chunk(CaseDev* __restrict__ Cw, const 
       Cw->step = s + 1;
     }
   }
-  const int64_t lo = chunk * kChunk;
-  if (lo >= n) return;  // whole workgroup: no live slots in this chunk
-  const int64_t hi = lo + kChunk < n ? lo + kChunk : n;
+  const int64_t per = (nch + nwg - 1) / nwg;
+  const int64_t c_lo = (int64_t)j * per;
+  const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
+  if (c_lo >= c_hi) return;  // whole workgroup: nothing to do this step
   const int ng = C->ng;
   const int nsub = C->nsub;
   const int64_t kion = s / nsub;
@@ -784,14 +815,14 @@ __device__ __forceinline__ void particles_chunk(CaseDev* __restrict__ Cw, const 
   {
     double ev[kGridPerThread];
 #pragma unroll
-    for (int j = 0; j < kGridPerThread; ++j) {
-      const int p = threadIdx.x + j * kBlock;
-      ev[j] = p < ng ? G(C->efield)[p] : 0.0;
+    for (int q = 0; q < kGridPerThread; ++q) {
+      const int p = threadIdx.x + q * kBlock;
+      ev[q] = p < ng ? G(C->efield)[p] : 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < kGridPerThread; ++j) {
-      const int p = threadIdx.x + j * kBlock;
-      if (p < ng) sE[p] = ev[j];
+    for (int q = 0; q < kGridPerThread; ++q) {
+      const int p = threadIdx.x + q * kBlock;
+      if (p < ng) sE[p] = ev[q];
     }
   }
   for (int p = threadIdx.x; p < ng; p += blockDim.x) {
@@ -804,7 +835,6 @@ __device__ __forceinline__ void particles_chunk(CaseDev* __restrict__ Cw, const 
   }
   if (SP == 0 && (fl & kDiagEepf))
     for (int b = threadIdx.x; b < n_eepf; b += blockDim.x) sF[b] = 0;
-  if (threadIdx.x < kLN) sCtr[threadIdx.x] = 0;
   __syncthreads();
 
   const int cur = C->cur[SP];
@@ -813,6 +843,8 @@ __device__ __forceinline__ void particles_chunk(CaseDev* __restrict__ Cw, const 
   const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
   const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
   const EDP_GLOBAL uint64_t* __restrict__ UID = G(C->sp[SP].uid[cur]);
+  EDP_GLOBAL int32_t* __restrict__ ENT = G(C->cq_ent[SP]);
+  EDP_GLOBAL int32_t* __restrict__ REC = G(C->cq_rec[SP]);
   const double inv_dx = C->inv_dx, L_gap = C->L;
   const double dt = SP == 0 ? C->dt_e : C->dt_i;
   const double factor = SP == 0 ? C->factor_e : C->factor_i;
@@ -827,160 +859,133 @@ __device__ __forceinline__ void particles_chunk(CaseDev* __restrict__ Cw, const 
   const uint32_t st = (uint32_t)s;
   const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf;
   const double sa = C->sigma_a;
+  const int w = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
 
-  unsigned int my_abs_pow = 0, my_abs_gnd = 0;
-  int my_q = 0, my_z = 0;  // this thread's events and ionizations
-  // All loads of the thread's kPerThread particles are issued before any
-  // store: on this target stores count against the same wait counter as
-  // loads, so interleaving them would make each load wait for the stores.
-  double xs[kPerThread], vxs[kPerThread], vys[kPerThread], vzs[kPerThread];
-  uint64_t us[kPerThread];
-#pragma unroll
-  for (int u = 0; u < kPerThread; ++u) {
-    const int64_t i = lo + u * kBlock + threadIdx.x;
-    if (i < hi) {
-      xs[u] = X[i];
-      vxs[u] = VX[i];
-      vys[u] = VY[i];
-      vzs[u] = VZ[i];
-      us[u] = UID[i];
-    } else {
-      xs[u] = __longlong_as_double(0x7FF8000000000000LL);
+  for (int64_t c = c_lo; c < c_hi; ++c) {
+    const int slot = w * kWave + lane;  // slot in the chunk
+    const int64_t i = c * kChunk + slot;
+    double x = __longlong_as_double(0x7FF8000000000000LL), vx = 0.0, vy = 0.0, vz = 0.0;
+    uint64_t uid = 0;
+    if (i < n) {
+      x = X[i];
+      vx = VX[i];
+      vy = VY[i];
+      vz = VZ[i];
+      uid = UID[i];
     }
-  }
-  double xo[kPerThread], vxo[kPerThread];
-  bool st_ok[kPerThread];
-  int qe[kPerThread];  // queued event of particle u, or -1
-#pragma unroll
-  for (int u = 0; u < kPerThread; ++u) {
-    const double x = xs[u];
-    st_ok[u] = false;
-    qe[u] = -1;
-    if (!(x == x)) continue;  // past the end, or absorbed earlier (tombstone)
-    st_ok[u] = true;
-    const double vx = vxs[u], vy = vys[u], vz = vzs[u];
-    // Steps 3-4: field at the particle and leapfrog.
-    const double c0 = x * inv_dx;
-    int p = (int)c0;
-    p = p > ng - 2 ? ng - 2 : (p < 0 ? 0 : p);
-    const double c1 = (double)(p + 1) - c0;
-    const double c2 = c0 - (double)p;
-    const double ex = c1 * sE[p] + c2 * sE[p + 1];
-    double vxn;
-    if (SP == 0)
-      vxn = vx - ex * factor;
-    else
-      vxn = vx + ex * factor;
-    const double xn = x + vxn * dt;
-    if (pdiag) {
-      // measurement at integer time: old position, mean of the half-step velocities
-      const double vbar = 0.5 * (vx + vxn);
-      if (fl & kDiagCurrent) {
-        lds_add(&sJ[p], (long long)(c1 * vbar * kDiagJS));
-        lds_add(&sJ[p + 1], (long long)(c2 * vbar * kDiagJS));
-      }
-      if (SP == 0 && (fl & (kDiagMeanE | kDiagEepf))) {
-        const double en = 0.5 * kEMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
-        if (fl & kDiagMeanE) {
-          lds_add(&sW[p], (long long)(c1 * kDiagWS));
-          lds_add(&sW[p + 1], (long long)(c2 * kDiagWS));
-          lds_add(&sEn[p], (long long)(c1 * en * kDiagES));
-          lds_add(&sEn[p + 1], (long long)(c2 * en * kDiagES));
-        }
-        if ((fl & kDiagEepf) && x >= x_lo && x <= x_hi) {
-          const double t = en / de_eepf;
-          if (t < (double)n_eepf) atomicAdd(&sF[(int)t], 1u);
-        }
-      }
-    }
-    xo[u] = xn;
-    vxo[u] = vxn;
-    // Step 5: absorbing electrodes.
-    if (xn < 0.0 || xn > L_gap) {
-      if (xn < 0.0)
-        ++my_abs_pow;
+    bool live = x == x;  // past the end, or absorbed earlier (tombstone)
+    bool abs_pow = false, abs_gnd = false, coll = false, ioniz = false;
+    int proc = 0;
+    double xn = 0.0, vxn = 0.0;
+    if (live) {
+      // Steps 3-4: field at the particle and leapfrog.
+      const double c0 = x * inv_dx;
+      int p = (int)c0;
+      p = p > ng - 2 ? ng - 2 : (p < 0 ? 0 : p);
+      const double c1 = (double)(p + 1) - c0;
+      const double c2 = c0 - (double)p;
+      const double ex = c1 * sE[p] + c2 * sE[p + 1];
+      if (SP == 0)
+        vxn = vx - ex * factor;
       else
-        ++my_abs_gnd;
-      xo[u] = __longlong_as_double(0x7FF8000000000000LL);
-      continue;
-    }
-    // Step 6: collision test, P = 1 - exp(-n sigma_tot(E) g dt), collide iff R < P.
-    double r_coll, r_proc, p_coll;
-    int idx;
-    if (SP == 0) {
-      const double v2 = vxn * vxn + vy * vy + vz * vz;
-      const double v = sqrt(v2);
-      const double energy = 0.5 * kEMass * v2 / kEvToJ;
-      idx = energy_bin(energy, de_cs, nbins);
-      const double nu = nsig[idx] * v;
-      p_coll = 1.0 - exp(-nu * dt);
-      uniform2(seed, us[u], st, tag(0, 0, 0), r_coll, r_proc);
-    } else {
-      double z0, z1, z2;
-      normals3(seed, us[u], st, 1u, 0u, 0u, z0, z1, z2);
-      const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
-      const double g2 = gx * gx + gy * gy + gz * gz;
-      const double g = sqrt(g2);
-      const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-      idx = energy_bin(energy, de_cs, nbins);
-      const double nu = nsig[idx] * g;
-      p_coll = 1.0 - exp(-nu * dt);
-      uniform2(seed, us[u], st, tag(1, 0, 2), r_coll, r_proc);
-    }
-    long long r;
-    const int q = deposit_split(xn, inv_dx, ng, r);
-    long long mult = 1;  // the parent, plus the newborn electron of an ionization
-    if (r_coll < p_coll) {
-      int proc;
-      if (SP == 0) {
-        const double s_el = sig0[idx], s_exc = sig1[idx], s_ion = sig2[idx];
-        const double s_tot = s_el + s_exc + s_ion;
-        if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
-          proc = 0;
-        else if (r_proc < (s_el + s_exc) / s_tot)
-          proc = 1;
-        else
-          proc = 2;
-        if (proc == 2) {
-          mult = 2;
-          gl_add(&cnt_i_next[q], 4294967296LL - r);
-          gl_add(&cnt_i_next[q + 1], r);
-          ++my_z;
+        vxn = vx + ex * factor;
+      xn = x + vxn * dt;
+      if (pdiag) {
+        // measurement at integer time: old position, mean of the half-step velocities
+        const double vbar = 0.5 * (vx + vxn);
+        if (fl & kDiagCurrent) {
+          lds_add(&sJ[p], (long long)(c1 * vbar * kDiagJS));
+          lds_add(&sJ[p + 1], (long long)(c2 * vbar * kDiagJS));
         }
-      } else {
-        const double s_iso = sig0[idx], s_back = sig1[idx];
-        proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
+        if (SP == 0 && (fl & (kDiagMeanE | kDiagEepf))) {
+          const double en = 0.5 * kEMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
+          if (fl & kDiagMeanE) {
+            lds_add(&sW[p], (long long)(c1 * kDiagWS));
+            lds_add(&sW[p + 1], (long long)(c2 * kDiagWS));
+            lds_add(&sEn[p], (long long)(c1 * en * kDiagES));
+            lds_add(&sEn[p + 1], (long long)(c2 * en * kDiagES));
+          }
+          if ((fl & kDiagEepf) && x >= x_lo && x <= x_hi) {
+            const double t = en / de_eepf;
+            if (t < (double)n_eepf) atomicAdd(&sF[(int)t], 1u);
+          }
+        }
       }
-      qe[u] = (u * kBlock + (int)threadIdx.x) | (proc << 10);
-      ++my_q;
+      // Step 5: absorbing electrodes.
+      abs_pow = xn < 0.0;
+      abs_gnd = xn > L_gap;
+      if (abs_pow || abs_gnd) {
+        live = false;
+      } else {
+        // Step 6: collision test, P = 1 - exp(-n sigma_tot(E) g dt), collide iff R < P.
+        double r_coll, r_proc, p_coll;
+        int idx;
+        if (SP == 0) {
+          const double v2 = vxn * vxn + vy * vy + vz * vz;
+          const double v = sqrt(v2);
+          const double energy = 0.5 * kEMass * v2 / kEvToJ;
+          idx = energy_bin(energy, de_cs, nbins);
+          const double nu = nsig[idx] * v;
+          p_coll = 1.0 - exp(-nu * dt);
+          uniform2(seed, uid, st, tag(0, 0, 0), r_coll, r_proc);
+        } else {
+          double z0, z1, z2;
+          normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+          const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+          const double g2 = gx * gx + gy * gy + gz * gz;
+          const double g = sqrt(g2);
+          const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+          idx = energy_bin(energy, de_cs, nbins);
+          const double nu = nsig[idx] * g;
+          p_coll = 1.0 - exp(-nu * dt);
+          uniform2(seed, uid, st, tag(1, 0, 2), r_coll, r_proc);
+        }
+        long long r;
+        const int q = deposit_split(xn, inv_dx, ng, r);
+        coll = r_coll < p_coll;
+        if (coll) {
+          if (SP == 0) {
+            const double s_el = sig0[idx], s_exc = sig1[idx], s_ion = sig2[idx];
+            const double s_tot = s_el + s_exc + s_ion;
+            if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
+              proc = 0;
+            else if (r_proc < (s_el + s_exc) / s_tot)
+              proc = 1;
+            else
+              proc = 2;
+            if (proc == 2) {
+              ioniz = true;
+              gl_add(&cnt_i_next[q], 4294967296LL - r);
+              gl_add(&cnt_i_next[q + 1], r);
+            }
+          } else {
+            const double s_iso = sig0[idx], s_back = sig1[idx];
+            proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
+          }
+        }
+        // the parent, plus the newborn electron of an ionization
+        const long long mult = ioniz ? 2 : 1;
+        lds_add(&sH[q], mult * (4294967296LL - r));
+        lds_add(&sH[q + 1], mult * r);
+      }
     }
-    lds_add(&sH[q], mult * (4294967296LL - r));
-    lds_add(&sH[q + 1], mult * r);
-  }
-#pragma unroll
-  for (int u = 0; u < kPerThread; ++u) {
-    if (!st_ok[u]) continue;
-    const int64_t i = lo + u * kBlock + threadIdx.x;
-    X[i] = xo[u];
-    VX[i] = vxo[u];
-  }
-  if (my_abs_pow) atomicAdd(&sCtr[kLAbsPow], my_abs_pow);
-  if (my_abs_gnd) atomicAdd(&sCtr[kLAbsGnd], my_abs_gnd);
-  // the chunk's events, in thread order; ionizations numbered in the same order
-  int tot;
-  const int off = block_exclusive_scan_t<int>(my_q | (my_z << 16), sScan, &tot);
-  if (my_q) {
-    EDP_GLOBAL int32_t* __restrict__ ent = G(C->cq_ent[SP]) + lo;
-    int qo = off & 0xFFFF, zo = off >> 16;
-#pragma unroll
-    for (int u = 0; u < kPerThread; ++u) {
-      if (qe[u] < 0) continue;
-      int code = qe[u];
-      if (((code >> 10) & 3) == 2) code |= (zo++) << 12;
-      ent[qo++] = code;
+    if (i < n && x == x) {
+      X[i] = live ? xn : __longlong_as_double(0x7FF8000000000000LL);
+      VX[i] = vxn;
     }
+    // the wave's events, in lane order; ionizations numbered in the same order
+    const uint64_t m_coll = __ballot(coll);
+    const uint64_t m_ion = __ballot(ioniz);
+    if (coll) {
+      const int code = slot | (proc << 10) | (lane_rank(m_ion) << 12);
+      ENT[c * kChunk + w * kWave + lane_rank(m_coll)] = code;
+    }
+    const uint64_t m_ap = __ballot(abs_pow), m_ag = __ballot(abs_gnd);
+    if (lane == 0)
+      REC[c * 4 + w] = __popcll(m_coll) | (__popcll(m_ion) << 7) | (__popcll(m_ap) << 14) | (__popcll(m_ag) << 21);
   }
-  // flush: deposit for step s+1, diagnostics of step s, the chunk record
+  __syncthreads();
+  // flush: deposit for step s+1 and diagnostics of step s
   int64_t* dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
   for (int q = threadIdx.x; q < ng; q += blockDim.x) {
     const unsigned long long h = sH[q];
@@ -995,11 +1000,6 @@ __device__ __forceinline__ void particles_chunk(CaseDev* __restrict__ Cw, const 
   if (SP == 0 && (fl & kDiagEepf))
     for (int b = threadIdx.x; b < n_eepf; b += blockDim.x)
       if (sF[b]) gl_add(&C->eepf[b], (long long)sF[b]);
-  if (threadIdx.x == 0) {
-    EDP_GLOBAL int32_t* rec = G(C->cq_rec[SP]) + 2 * chunk;
-    rec[0] = tot;
-    rec[1] = (int)(sCtr[kLAbsPow] | (sCtr[kLAbsGnd] << 16));
-  }
 }
 
 // One launch per species covers the chunks of every case of the batch.
@@ -1007,7 +1007,8 @@ template <int SP>
 __global__ void __launch_bounds__(kBlock) k_particles(const BatchDev* __restrict__ B) {
   const int bid = (int)blockIdx.x;
   const int k = find_case(B->part_off[SP], B->ncase, bid);
-  particles_chunk<SP>(B->c[k], (int64_t)(bid - B->part_off[SP][k]));
+  const int j0 = B->part_off[SP][k];
+  particles_block<SP>(B->c[k], bid - j0, B->part_off[SP][k + 1] - j0);
 }
 
 __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma) {
@@ -1239,6 +1240,15 @@ hipError_t launch_particles(const BatchDev* b, int sp, int blocks, size_t lds, h
     hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, b);
   }
   return hipGetLastError();
+}
+
+// Resident workgroups per CU of a species' particle kernel with `lds` bytes
+// of dynamic LDS.
+int particle_occupancy(int sp, size_t lds) {
+  int nb = 0;
+  const hipError_t e = sp == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<0>, kBlock, lds)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<1>, kBlock, lds);
+  return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
