@@ -125,7 +125,7 @@ struct edp_ctx {
 namespace {
 
 struct Layout {
-  size_t off_case, off_part[2][2][5], off_cq[2][2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
+  size_t off_case, off_part[2][2][5], off_cq[2][2], off_qwg[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
       off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[4], off_eepf, off_sort, total;
   int64_t cap[2];
 };
@@ -178,6 +178,7 @@ Layout layout(const edp_case_desc* c, int nbins) {
     L.off_cq[sp][0] = take(chunks * kChunk * 4);  // events
     L.off_cq[sp][1] = take(chunks * 16);          // chunk records (one word per wave)
   }
+  for (int sp = 0; sp < 2; ++sp) L.off_qwg[sp] = take((size_t)kMaxPartWG * 16);
   for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
   const size_t ng = (size_t)c->n_grid;
   L.off_rden = take(ng * 8);
@@ -236,7 +237,7 @@ int blocks_for(const edp_ctx* ctx, int64_t n) {
 
 // Workgroups that apply queued collisions outside a step (all of them on
 // one case).
-int scatter_blocks(const edp_ctx* ctx) { return ctx->num_cu; }
+int scatter_blocks(const edp_ctx* ctx) { return std::min(ctx->num_cu, kMaxApply); }
 
 // Expected chunks of a species of a case (10% headroom over the estimate).
 int64_t est_chunks(const Case* c, int sp) { return (c->est[sp] + c->est[sp] / 10 + kChunk) / kChunk; }
@@ -245,7 +246,7 @@ int64_t est_chunks(const Case* c, int sp) { return (c->est[sp] + c->est[sp] / 10
 // estimated live slots, 32 chunks per workgroup, at most one per CU.
 int apply_blocks(const edp_ctx* ctx, const Case* c) {
   const int64_t chunks = (std::max(c->est[0], c->est[1]) + kChunk - 1) / kChunk;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(ctx->num_cu, (chunks + 31) / 32));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(ctx->num_cu, kMaxApply), (chunks + 31) / 32));
 }
 
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
@@ -337,7 +338,7 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
     const int64_t per = std::max<int64_t>(1, (total + slots - 1) / slots);
     want[sp].resize(nc);
     for (size_t k = 0; k < nc; ++k)
-      want[sp][k] = (int)std::max<int64_t>(1, (est_chunks(cs[k], sp) + per - 1) / per);
+      want[sp][k] = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxPartWG, (est_chunks(cs[k], sp) + per - 1) / per));
   }
   for (size_t k = 0; k < nc; ++k) want_apply[k] = apply_blocks(ctx, cs[k]);
   auto near = [](int a, int a0) { return a <= a0 * 5 / 4 + 1 && a >= a0 * 3 / 4; };
@@ -704,6 +705,7 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
     h.cq_ent[sp] = (int32_t*)(c->arena + L.off_cq[sp][0]);
     h.cq_rec[sp] = (int32_t*)(c->arena + L.off_cq[sp][1]);
   }
+  for (int sp = 0; sp < 2; ++sp) h.q_wg[sp] = (int32_t*)(c->arena + L.off_qwg[sp]);
   h.q_valid = 0;
   double* tabs[7];
   for (int t = 0; t < 7; ++t) tabs[t] = (double*)(c->arena + L.off_tab[t]);

@@ -32,6 +32,8 @@ constexpr double kDiagES = 1048576.0;  // c * energy [eV]
 // Particle kernels: workgroup size and the particle slots each workgroup owns.
 constexpr int kBlock = 256;
 constexpr int kChunk = kBlock;  // particle slots per chunk: one per thread of a workgroup
+constexpr int kMaxApply = 1024;   // collision workgroups per case and application
+constexpr int kMaxPartWG = 8192;  // particle workgroups per case and species
 constexpr int kMaxNodes = 2048;                      // largest n_grid accepted
 constexpr int kGridPerThread = kMaxNodes / kBlock;   // grid nodes per thread
 constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
@@ -83,6 +85,9 @@ struct CaseDev {
   // slot-in-chunk | process << 10 | ionization rank in the wave << 12.
   int32_t* cq_ent[2];
   int32_t* cq_rec[2];
+  // per particle workgroup and species: the totals of its chunk range,
+  // {events, ionizations, absorbed at x=0, absorbed at x=L}
+  int32_t* q_wg[2];  // [kMaxPartWG][4]
   // ---- dynamic (device-mutated) -----------------------------------------
   int64_t step;       // next step whose head runs (advanced by the electron kernel)
   int64_t pstep;      // step of the particle kernels (set by the head)
@@ -93,6 +98,7 @@ struct CaseDev {
   // q_step, applied by the next head (or a drain)
   int64_t q_step;
   int64_t q_base[2];  // slot count of that step: births go to q_base + rank
+  int64_t q_per[2];   // chunks per particle workgroup in that step
   int32_t q_nblk[2];  // chunks that wrote records (0: no events of that species)
   int32_t q_valid;    // 1 while not yet applied by a drain
   int32_t pad2;

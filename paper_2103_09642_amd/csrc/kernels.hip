@@ -210,36 +210,6 @@ __device__ __forceinline__ T block_exclusive_scan_t(T x, int64_t* scratch, T* to
   return before + inc - x;
 }
 
-// Exclusive scan of one double per thread across the workgroup (wave64
-// shuffles, then the wave totals through LDS); *total gets the sum.
-__device__ __forceinline__ double block_exclusive_scan(double x, double* sW, double* total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double inc = x;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double y = __shfl_up(inc, off, 64);
-    if (lane >= off) inc += y;
-  }
-  if (lane == 63) sW[wv] = inc;
-  __syncthreads();
-  if (wv == 0) {
-    double t = lane < nw ? sW[lane] : 0.0;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const double y = __shfl_up(t, off, 64);
-      if (lane >= off) t += y;
-    }
-    if (lane < nw) sW[32 + lane] = t;  // inclusive over waves
-  }
-  __syncthreads();
-  double exc = __shfl_up(inc, 1, 64);
-  if (lane == 0) exc = 0.0;
-  if (wv > 0) exc += sW[32 + wv - 1];
-  *total = sW[32 + nw - 1];
-  __syncthreads();
-  return exc;
-}
-
 // ---------------------------------------------------------------------------
 // Step 2: density -> rho -> potential -> field, one workgroup per case.
 // MODE 0 (default) solves the discrete Poisson equation through the fluxes
@@ -249,13 +219,13 @@ __device__ __forceinline__ double block_exclusive_scan(double x, double* sW, dou
 // F_0 = (V - sum_p S_p)/(N_g - 1).  The field follows from the fluxes
 // without forming phi: E_p = (F_{p-1} + F_p)/(2 dx) inside, and the boundary
 // forms use F_0 and F_{N_g-2}.  This is the same linear system as the Thomas
-// algorithm solves, in parallel (two workgroup scans instead of 2 N_g
-// dependent steps); it agrees with an 80-bit solution to ~1e-15 of the field
-// scale, closer than the sequential sweep.
+// algorithm solves, in parallel (two wave scans instead of 2 N_g dependent
+// steps); it agrees with an 80-bit solution to ~1e-15 of the field scale,
+// closer than the sequential sweep.
 // MODE 1 runs the Thomas algorithm itself in one thread, operation for
 // operation as the sequential definition (bit-reproducible, slow).
 // ---------------------------------------------------------------------------
-constexpr int kFieldRows = 8;  // rows per thread of the flux scans (n_grid <= 2048)
+constexpr int kWave = 64;
 
 template <int MODE>
 __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fsm) {
@@ -352,29 +322,40 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       G(C->rho)[p] = sRho[p];
     }
   } else {
-    // rows p = 1..m; thread t owns the contiguous rows q0 < q < q1 (q = p-1)
-    const int m = ng - 2;
-    const double kp = C->kpois;
-    const int q0 = (int)threadIdx.x * kFieldRows;
-    const int q1 = q0 + kFieldRows < m ? q0 + kFieldRows : m;
-    double acc = 0.0;
-    for (int q = q0; q < q1; ++q) {
-      acc += sRho[q + 1] * kp;
-      sPhi[q + 1] = acc;  // prefix within the thread
+    // One wave does the two scans (no workgroup barriers in between): lane l
+    // owns the contiguous rows q0 <= q < q1 of the m = N_g - 2 interior rows
+    // (row q is node q+1), and sPhi[q+1] becomes F_{q+1}.
+    if (threadIdx.x < kWave) {
+      const int lane = (int)threadIdx.x;
+      const int m = ng - 2;
+      const double kp = C->kpois;
+      const int R = (m + kWave - 1) / kWave;
+      const int q0 = lane * R < m ? lane * R : m;
+      const int q1 = q0 + R < m ? q0 + R : m;
+      double acc = 0.0;
+      for (int q = q0; q < q1; ++q) {
+        acc += sRho[q + 1] * kp;
+        sPhi[q + 1] = acc;  // prefix within the lane
+      }
+      double inc = acc;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const double y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+      }
+      const double before = inc - acc;
+      double mine = 0.0;
+      for (int q = q0; q < q1; ++q) {
+        const double S = before + sPhi[q + 1];
+        sPhi[q + 1] = S;
+        mine += S;
+      }
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
+      const double F0 = (V - mine) / (double)(ng - 1);
+      for (int q = q0; q < q1; ++q) sPhi[q + 1] = F0 + sPhi[q + 1];
+      if (lane == 0) sPhi[0] = F0;
     }
-    double tot;
-    const double before = block_exclusive_scan(acc, sW, &tot);
-    double mine = 0.0;
-    for (int q = q0; q < q1; ++q) {
-      const double S = before + sPhi[q + 1];
-      sPhi[q + 1] = S;
-      mine += S;
-    }
-    double T;
-    (void)block_exclusive_scan(mine, sW, &T);
-    const double F0 = (V - T) / (double)(ng - 1);
-    for (int q = q0; q < q1; ++q) sPhi[q + 1] = F0 + sPhi[q + 1];
-    if (threadIdx.x == 0) sPhi[0] = F0;
     __syncthreads();
     for (int p = threadIdx.x; p < ng; p += blockDim.x) {
       double e;
@@ -389,7 +370,10 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       G(C->rho)[p] = sRho[p];
     }
   }
-  if (threadIdx.x == 0) Cw->phi_valid = MODE == 1;
+  if (threadIdx.x == 0) {
+    Cw->phi_valid = MODE == 1;
+    Cw->pstep = s;  // the particle kernels of this step read it
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -594,8 +578,13 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
         // round's ionizations of lower groups
         int64_t zpre = 0;
         if (cb == c0) {
-#pragma unroll 8
-          for (int64_t k = threadIdx.x; k < c0; k += blockDim.x) {
+          // whole particle workgroups before c0, then the chunks of the one holding c0
+          const int64_t per = C->q_per[0];
+          const int64_t jw = c0 / per;
+          const EDP_GLOBAL rec4* wg = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
+#pragma unroll 4
+          for (int64_t k = threadIdx.x; k < jw; k += blockDim.x) zpre += wg[k].y;
+          for (int64_t k = jw * per + threadIdx.x; k < c0; k += blockDim.x) {
             const rec4 t = rec[k];
             zpre += rec_z(t.x) + rec_z(t.y) + rec_z(t.z) + rec_z(t.w);
           }
@@ -632,52 +621,54 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
   }
 }
 
-// Totals of the pending queue (one workgroup, beside the apply workgroups):
-// collision, ionization and absorption counters, newborns placed, slot
-// counts for the next step.
-__device__ __forceinline__ void apply_totals(CaseDev* __restrict__ Cw) {
+// Add the totals of the last particle step to the counters and place its
+// newborns (one workgroup): the particle workgroups' records give collisions,
+// ionizations and absorptions; the newborns occupy q_base + [0, ionizations)
+// up to the capacity.
+__device__ __forceinline__ void fold_queue(CaseDev* __restrict__ Cw) {
   __shared__ int64_t sRed[64];
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
-  int64_t tq[2] = {0, 0}, tz = 0, tap[2] = {0, 0}, tag_[2] = {0, 0};
+  int64_t v[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
   for (int sp = 0; sp < 2; ++sp) {
-    const int64_t nb = C->q_nblk[sp];
-    const EDP_GLOBAL rec4* __restrict__ rec = (const EDP_GLOBAL rec4*)G(C->cq_rec[sp]);
-    int64_t a = 0, b = 0, d = 0, f = 0;
-#pragma unroll 8
-    for (int64_t c = threadIdx.x; c < nb; c += blockDim.x) {
-      const rec4 t = rec[c];
-      a += rec_q(t.x) + rec_q(t.y) + rec_q(t.z) + rec_q(t.w);
-      b += rec_z(t.x) + rec_z(t.y) + rec_z(t.z) + rec_z(t.w);
-      d += rec_ap(t.x) + rec_ap(t.y) + rec_ap(t.z) + rec_ap(t.w);
-      f += rec_ag(t.x) + rec_ag(t.y) + rec_ag(t.z) + rec_ag(t.w);
+    const int64_t per = C->q_per[sp];
+    const int64_t nwg = per > 0 ? (C->q_nblk[sp] + per - 1) / per : 0;
+    const EDP_GLOBAL rec4* wg = (const EDP_GLOBAL rec4*)G(C->q_wg[sp]);
+#pragma unroll 4
+    for (int64_t k = threadIdx.x; k < nwg; k += blockDim.x) {
+      const rec4 t = wg[k];
+      v[sp][0] += t.x;
+      v[sp][1] += t.y;
+      v[sp][2] += t.z;
+      v[sp][3] += t.w;
     }
-    // two sums per scan word (each total fits in 32 bits)
-    int64_t t0, t1;
-    (void)block_exclusive_scan_t<int64_t>((a << 32) | b, sRed, &t0);
-    (void)block_exclusive_scan_t<int64_t>((d << 32) | f, sRed, &t1);
-    tq[sp] = t0 >> 32;
-    if (sp == 0) tz = t0 & 0xFFFFFFFFLL;
-    tap[sp] = t1 >> 32;
-    tag_[sp] = t1 & 0xFFFFFFFFLL;
   }
+  // two sums per scan word (each total is at most the slot count, < 2^31)
+  int64_t t[4];
+  (void)block_exclusive_scan_t<int64_t>((v[0][0] << 32) | v[0][1], sRed, &t[0]);
+  (void)block_exclusive_scan_t<int64_t>((v[0][2] << 32) | v[0][3], sRed, &t[1]);
+  (void)block_exclusive_scan_t<int64_t>((v[1][0] << 32) | v[1][2], sRed, &t[2]);
+  (void)block_exclusive_scan_t<int64_t>(v[1][3], sRed, &t[3]);
   if (threadIdx.x == 0) {
+    const int64_t coll_e = t[0] >> 32, z = t[0] & 0xFFFFFFFFLL;
+    const int64_t ap_e = t[1] >> 32, ag_e = t[1] & 0xFFFFFFFFLL;
+    const int64_t coll_i = t[2] >> 32, ap_i = t[2] & 0xFFFFFFFFLL, ag_i = t[3];
     const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
     const int64_t room_e = C->sp[0].cap - base_e, room_i = C->sp[1].cap - base_i;
-    const int64_t ok_e = tz < room_e ? tz : (room_e > 0 ? room_e : 0);
-    const int64_t ok_i = tz < room_i ? tz : (room_i > 0 ? room_i : 0);
+    const int64_t ok_e = z < room_e ? z : (room_e > 0 ? room_e : 0);
+    const int64_t ok_i = z < room_i ? z : (room_i > 0 ? room_i : 0);
     Cw->alloc[0] = Cw->n[0] = base_e + ok_e;
     Cw->alloc[1] = Cw->n[1] = base_i + ok_i;
-    Cw->ctr[kCollE] += tq[0];
-    Cw->ctr[kCollI] += tq[1];
-    Cw->ctr[kIoniz] += tz;
-    Cw->ctr[kAbsEPow] += tap[0];
-    Cw->ctr[kAbsEGnd] += tag_[0];
-    Cw->ctr[kAbsIPow] += tap[1];
-    Cw->ctr[kAbsIGnd] += tag_[1];
-    Cw->ctr[kLiveE] += ok_e - tap[0] - tag_[0];
-    Cw->ctr[kLiveI] += ok_i - tap[1] - tag_[1];
-    if (ok_e < tz || ok_i < tz) {
-      Cw->ctr[kDropped] += (tz - ok_e) + (tz - ok_i);
+    Cw->ctr[kCollE] += coll_e;
+    Cw->ctr[kCollI] += coll_i;
+    Cw->ctr[kIoniz] += z;
+    Cw->ctr[kAbsEPow] += ap_e;
+    Cw->ctr[kAbsEGnd] += ag_e;
+    Cw->ctr[kAbsIPow] += ap_i;
+    Cw->ctr[kAbsIGnd] += ag_i;
+    Cw->ctr[kLiveE] += ok_e - ap_e - ag_e;
+    Cw->ctr[kLiveI] += ok_i - ap_i - ag_i;
+    if (ok_e < z || ok_i < z) {
+      Cw->ctr[kDropped] += (z - ok_e) + (z - ok_i);
       Cw->error = 1;
     }
   }
@@ -698,8 +689,8 @@ __device__ __forceinline__ int find_case(const int32_t* __restrict__ off, int nc
 
 // Head of step s for every case of the batch.  Workgroups [0, ncase) solve
 // the fields, the next apply_off[ncase] apply the queues of step s-1 (a range
-// per case), the last ncase fold each queue's totals and do the step's
-// bookkeeping.
+// per case), the last ncase fold each queue's totals into the counters and
+// do the step's bookkeeping.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_head(const BatchDev* __restrict__ B) {
   extern __shared__ double hsm[];
@@ -717,7 +708,7 @@ __global__ void __launch_bounds__(kBlock) k_head(const BatchDev* __restrict__ B)
     return;
   }
   CaseDev* C = B->c[bid - nc - na];
-  if (C->q_valid) apply_totals(C);
+  if (C->q_valid) fold_queue(C);
   if (threadIdx.x == 0) {
     const int64_t s = C->step;
     const bool ion_step = (s % C->nsub) == 0;
@@ -725,20 +716,17 @@ __global__ void __launch_bounds__(kBlock) k_head(const BatchDev* __restrict__ B)
     if (ion_step) C->ctr[kPstepI] += C->ctr[kLiveI];
     C->diag_steps += 1;
     if (ion_step) C->diag_ion_steps += 1;
-    C->pstep = s;
   }
 }
 
 // Apply the pending queue before the host looks at the state (the last
 // workgroup folds the totals).
 __global__ void __launch_bounds__(kBlock) k_drain(CaseDev* __restrict__ C) {
-  if (!C->q_valid) return;
-  if ((int)blockIdx.x < (int)gridDim.x - 1)
-    apply_queue(C, (int)blockIdx.x, (int)gridDim.x - 1);
-  else
-    apply_totals(C);
+  if (C->q_valid) apply_queue(C, (int)blockIdx.x, (int)gridDim.x);
 }
-__global__ void k_drain_done(CaseDev* __restrict__ C) {
+__global__ void __launch_bounds__(kBlock) k_drain_done(CaseDev* __restrict__ C) {
+  if (C->q_valid) fold_queue(C);
+  __syncthreads();
   if (threadIdx.x == 0) C->q_valid = 0;
 }
 
@@ -769,8 +757,6 @@ __global__ void k_drain_done(CaseDev* __restrict__ C) {
 // Dynamic LDS: E[ng] double, H[ng] deposit; with particle diagnostics also
 // J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).
 // ---------------------------------------------------------------------------
-constexpr int kWave = 64;
-
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
   // set bits of mask below this lane
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -797,6 +783,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     }
   }
   const int64_t per = (nch + nwg - 1) / nwg;
+  if (j == 0 && threadIdx.x == 0) Cw->q_per[SP] = per;
   const int64_t c_lo = (int64_t)j * per;
   const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
   if (c_lo >= c_hi) return;  // whole workgroup: nothing to do this step
@@ -860,6 +847,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf;
   const double sa = C->sigma_a;
   const int w = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
+  int tq = 0, tz = 0, tap = 0, tag_ = 0;  // this wave's totals over the workgroup's chunks
 
   for (int64_t c = c_lo; c < c_hi; ++c) {
     const int slot = w * kWave + lane;  // slot in the chunk
@@ -981,10 +969,17 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       ENT[c * kChunk + w * kWave + lane_rank(m_coll)] = code;
     }
     const uint64_t m_ap = __ballot(abs_pow), m_ag = __ballot(abs_gnd);
+    tq += __popcll(m_coll);
+    tz += __popcll(m_ion);
+    tap += __popcll(m_ap);
+    tag_ += __popcll(m_ag);
     if (lane == 0)
       REC[c * 4 + w] = __popcll(m_coll) | (__popcll(m_ion) << 7) | (__popcll(m_ap) << 14) | (__popcll(m_ag) << 21);
   }
+  __shared__ rec4 sT[kBlock / kWave];
+  if (lane == 0) sT[w] = rec4{tq, tz, tap, tag_};
   __syncthreads();
+  if (threadIdx.x == 0) ((EDP_GLOBAL rec4*)G(Cw->q_wg[SP]))[j] = sT[0] + sT[1] + sT[2] + sT[3];
   // flush: deposit for step s+1 and diagnostics of step s
   int64_t* dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
   for (int q = threadIdx.x; q < ng; q += blockDim.x) {
@@ -1205,8 +1200,8 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp) {
 }
 
 // Head of a batch step: ncase field workgroups, `apply_blocks` collision
-// workgroups in total, ncase totals/bookkeeping workgroups.  `max_ng` sizes
-// the field workgroups' LDS.
+// workgroups in total and ncase totals workgroups.  `max_ng` sizes the field
+// workgroups' LDS.
 hipError_t launch_head(const BatchDev* b, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st) {
   const size_t lds = (size_t)max_ng * 24 + 64 * 8;
   const dim3 grid(2 * ncase + apply_blocks);
@@ -1218,8 +1213,8 @@ hipError_t launch_head(const BatchDev* b, int ncase, int apply_blocks, int max_n
 }
 
 hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_drain, dim3(blocks + 1), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(k_drain_done, dim3(1), dim3(64), 0, st, d);
+  hipLaunchKernelGGL(k_drain, dim3(blocks), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_drain_done, dim3(1), dim3(kBlock), 0, st, d);
   return hipGetLastError();
 }
 
