@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 DIAG_DENSITY, DIAG_EEPF, DIAG_CURRENT, DIAG_MEANE, IONIZ_LITERAL = 1, 2, 4, 8, 16
+NULL_COLLISION = 64
 _FLAG_NAMES = {"density": DIAG_DENSITY, "eepf": DIAG_EEPF, "current": DIAG_CURRENT,
-               "meane": DIAG_MEANE, "ioniz_literal": IONIZ_LITERAL,
+               "meane": DIAG_MEANE, "ioniz_literal": IONIZ_LITERAL, "null_collision": NULL_COLLISION,
                "allow_unstable": 0}  # a library option with no effect on the method
 COUNTER_NAMES = ["abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i",
                  "ioniz", "anomaly"]
@@ -81,6 +82,9 @@ def lib():
         L.orc_voltage.restype = C.c_double
         L.orc_voltage.argtypes = [P, C.c_int64]
         L.orc_nsig_tot.argtypes = [P, dp, dp]
+        L.orc_null_params.argtypes = [P, dp]
+        L.orc_nu_star.restype = C.c_double
+        L.orc_nu_star.argtypes = [dp, C.c_int32, C.c_double, C.c_double]
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                         C.POINTER(C.c_uint32)]
         L.orc_uniform2.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -245,6 +249,11 @@ class Oracle:
         lib().orc_nsig_tot(self.h, dptr(a), dptr(b))
         return a, b
 
+    def null_params(self) -> Dict[str, float]:
+        out = np.zeros(4)
+        lib().orc_null_params(self.h, dptr(out))
+        return {"nu_star_e": out[0], "nu_star_i": out[1], "p_null_e": out[2], "p_null_i": out[3]}
+
     def collide_electron(self, v, idx, r_proc, r_chi, r_eta, r_share):
         vin = np.ascontiguousarray(v, dtype=np.float64)
         vo, ve = np.zeros(3), np.zeros(3)
@@ -310,3 +319,8 @@ def scatter(g, gmag, gnew, f2, cos_chi, sin_chi, eta, w):
 
 def child_uid(parent: int, step: int, kind: int) -> int:
     return int(lib().orc_child_uid(parent, step, kind))
+
+
+def nu_star(nsig: np.ndarray, de_ev: float, mass: float) -> float:
+    a = np.ascontiguousarray(nsig, dtype=np.float64)
+    return lib().orc_nu_star(dptr(a), a.size, de_ev, mass)

@@ -60,6 +60,8 @@ struct orc_sim {
   double gas_n, sigma_a, de_cs, thr_exc, thr_ion, w_ion;
   double *sig_el, *sig_exc, *sig_ion, *sig_iso, *sig_back;
   double *nsig_e, *nsig_i; /* n * sigma_tot, per bin (section 3.2) */
+  double nu_star_e, nu_star_i; /* null-collision maximum frequencies      */
+  double p_null_e, p_null_i;   /* 1 - exp(-nu* dt) for each species      */
   parts e, i;
   int64_t step;
   int64_t *cnt_e, *cnt_i_cur; /* fixed-point densities of this step     */
@@ -338,24 +340,35 @@ void orc_scatter(const double g[3], double gmag, double gnew, double f2,
  * the ejected electron is scattered like the projectile about the same w.
  * A negative remaining energy (cannot happen with tables that are zero at
  * and below threshold) is clamped to zero and reported as an anomaly. */
+static int electron_kinematics(const orc_sim *s, const double v[3], int proc, double r_chi,
+                               double r_eta, double r_share, double vout[3], double vej[3],
+                               int *anomaly);
+
 int orc_collide_electron(const orc_sim *s, const double v[3], int idx,
                          double r_proc, double r_chi, double r_eta, double r_share,
                          double vout[3], double vej[3], int *anomaly) {
-  const double f1 = E_MASS / (E_MASS + AR_MASS);
-  const double f2 = AR_MASS / (E_MASS + AR_MASS);
-  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-  const double g = sqrt(v2);
-  const double w[3] = {f1 * v[0], f1 * v[1], f1 * v[2]};
   const double s_el = s->sig_el[idx], s_exc = s->sig_exc[idx], s_ion = s->sig_ion[idx];
   const double st = s_el + s_exc + s_ion;
   int proc;
-  *anomaly = 0;
   if (!(st > 0.0) || r_proc < s_el / st)
     proc = 0;
   else if (r_proc < (s_el + s_exc) / st)
     proc = 1;
   else
     proc = 2;
+  return electron_kinematics(s, v, proc, r_chi, r_eta, r_share, vout, vej, anomaly);
+}
+
+/* The new velocities of an electron collision whose process is chosen. */
+static int electron_kinematics(const orc_sim *s, const double v[3], int proc, double r_chi,
+                               double r_eta, double r_share, double vout[3], double vej[3],
+                               int *anomaly) {
+  const double f1 = E_MASS / (E_MASS + AR_MASS);
+  const double f2 = AR_MASS / (E_MASS + AR_MASS);
+  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double g = sqrt(v2);
+  const double w[3] = {f1 * v[0], f1 * v[1], f1 * v[2]};
+  *anomaly = 0;
   const double eta = TWO_PI_D * r_eta;
   if (proc == 0 || proc == 1) {
     double gnew = g;
@@ -403,31 +416,52 @@ int orc_collide_electron(const orc_sim *s, const double v[3], int idx,
 /* Ar+ + Ar with a thermal target va: g = v - va, w = (v + va)/2 (equal masses),
  * isotropic (cos chi = 1 - 2R) or backward (chi = pi) by partitioning [0,1)
  * as iso | back; |g'| = |g| (elastic). */
-int orc_collide_ion(const orc_sim *s, const double v[3], const double va[3], int idx,
-                    double r_proc, double r_chi, double r_eta, double vout[3]) {
+/* The new velocity of an ion collision whose process is chosen. */
+static void ion_kinematics(const double v[3], const double va[3], int proc, double r_chi,
+                           double r_eta, double vout[3]) {
   const double g3[3] = {v[0] - va[0], v[1] - va[1], v[2] - va[2]};
   const double g2 = g3[0] * g3[0] + g3[1] * g3[1] + g3[2] * g3[2];
   const double g = sqrt(g2);
   const double w[3] = {0.5 * (v[0] + va[0]), 0.5 * (v[1] + va[1]), 0.5 * (v[2] + va[2])};
-  const double s_iso = s->sig_iso[idx], s_back = s->sig_back[idx];
   double cos_chi, sin_chi;
-  int proc;
-  if (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) {
-    proc = 0;
+  if (proc == 0) {
     cos_chi = 1.0 - 2.0 * r_chi;
     sin_chi = sqrt(1.0 - cos_chi * cos_chi);
   } else {
-    proc = 1;
     cos_chi = -1.0;
     sin_chi = 0.0;
   }
   orc_scatter(g3, g, g, 0.5, cos_chi, sin_chi, TWO_PI_D * r_eta, w, vout);
+}
+
+int orc_collide_ion(const orc_sim *s, const double v[3], const double va[3], int idx,
+                    double r_proc, double r_chi, double r_eta, double vout[3]) {
+  const double s_iso = s->sig_iso[idx], s_back = s->sig_back[idx];
+  const int proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
+  ion_kinematics(v, va, proc, r_chi, r_eta, vout);
   return proc;
 }
 
 /* ---------------------------------------------------------------------------
  * Case set-up
  * ------------------------------------------------------------------------- */
+/* Null-collision maximum frequency (section 2.1.6, the null-collision
+ * method): nu* = max over the table of n sigma_tot(E) g(E), with g taken at
+ * the upper end of every bin's energy range (bin i holds the energies that
+ * round to i de) and, for the last bin, which also holds every energy beyond
+ * the table, at four times the table's range.  mass is the electron mass
+ * (LAB energy) or the Ar+ + Ar reduced mass (COM energy). */
+double orc_nu_star(const double *nsig, int32_t nb, double de_ev, double mass) {
+  double m = 0.0;
+  for (int32_t i = 0; i < nb; ++i) {
+    const double e_hi = (i == nb - 1) ? 4.0 * (double)nb * de_ev : ((double)i + 0.5) * de_ev;
+    const double g = sqrt(2.0 * e_hi * EV_TO_J / mass);
+    const double nu = nsig[i] * g;
+    if (nu > m) m = nu;
+  }
+  return m;
+}
+
 static double *dup_table(const double *src, int n) {
   double *d = malloc((size_t)n * sizeof(double));
   if (d && src) memcpy(d, src, (size_t)n * sizeof(double));
@@ -479,6 +513,10 @@ orc_sim *orc_new(const orc_case *c, const orc_xsec *xs) {
     s->nsig_e[k] = s->gas_n * (s->sig_el[k] + s->sig_exc[k] + s->sig_ion[k]);
     s->nsig_i[k] = s->gas_n * (s->sig_iso[k] + s->sig_back[k]);
   }
+  s->nu_star_e = orc_nu_star(s->nsig_e, nb, s->de_cs, E_MASS);
+  s->nu_star_i = orc_nu_star(s->nsig_i, nb, s->de_cs, MU_ARAR);
+  s->p_null_e = 1.0 - exp(-s->nu_star_e * s->dt_e);
+  s->p_null_i = 1.0 - exp(-s->nu_star_i * s->dt_i);
   s->cnt_e = calloc((size_t)ng, sizeof(int64_t));
   s->cnt_i_cur = calloc((size_t)ng, sizeof(int64_t));
   s->ne = calloc((size_t)ng, sizeof(double));
@@ -704,6 +742,96 @@ static void electron_mcc(orc_sim *s, int64_t k) {
   }
 }
 
+/* Step 6 for one electron with null-collision selection (section 2.1.6 and
+ * the suggested extension of section 5): a candidate with probability
+ * P* = 1 - exp(-nu* dt) (R_coll < P*), then process k with probability
+ * nu_k(E)/nu* from R_proc nu* against the cumulative nu_el, nu_exc, nu_ion
+ * (nu_k = (n sigma_k) v); the remainder is the null process, which leaves
+ * the particle unchanged.  nu_tot > nu* (an energy beyond the bound) is an
+ * anomaly; the candidate then always collides. */
+static void electron_mcc_null(orc_sim *s, int64_t k) {
+  parts *p = &s->e;
+  const uint64_t uid = p->uid[k];
+  const uint32_t st = (uint32_t)s->step;
+  double r0[2];
+  orc_uniform2(s->c.seed, uid, st, 0u, 0u, 0u, r0);
+  if (!(r0[0] < s->p_null_e)) return;
+  const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
+  const double v2 = vx * vx + vy * vy + vz * vz;
+  const double v = sqrt(v2);
+  const double energy = 0.5 * E_MASS * v2 / EV_TO_J;
+  const int idx = energy_bin(s, energy);
+  const double nu_el = (s->gas_n * s->sig_el[idx]) * v;
+  const double nu_exc = (s->gas_n * s->sig_exc[idx]) * v;
+  const double nu_ion = (s->gas_n * s->sig_ion[idx]) * v;
+  const double c1 = nu_el, c2 = c1 + nu_exc, c3 = c2 + nu_ion;
+  if (c3 > s->nu_star_e) s->counts[ORC_C_ANOMALY]++;
+  const double t = r0[1] * s->nu_star_e;
+  const int proc = t < c1 ? 0 : (t < c2 ? 1 : (t < c3 ? 2 : -1));
+  if (proc < 0) return; /* null collision */
+  double r1[2], r2[2];
+  orc_uniform2(s->c.seed, uid, st, 0u, 0u, 1u, r1);
+  orc_uniform2(s->c.seed, uid, st, 0u, 0u, 2u, r2);
+  const double vin[3] = {vx, vy, vz};
+  double vout[3], vej[3];
+  int anomaly = 0;
+  electron_kinematics(s, vin, proc, r1[0], r1[1], r2[0], vout, vej, &anomaly);
+  p->vx[k] = vout[0];
+  p->vy[k] = vout[1];
+  p->vz[k] = vout[2];
+  s->counts[ORC_C_COLL_E]++;
+  s->counts[ORC_C_ANOMALY] += anomaly;
+  if (proc == 2) {
+    const double x = p->x[k];
+    const uint64_t uid_e = orc_child_uid(uid, s->step, 1);
+    const uint64_t uid_i = orc_child_uid(uid, s->step, 2);
+    parts_append(&s->e, x, vej[0], vej[1], vej[2], uid_e);
+    double z[3];
+    normals3(s->c.seed, uid_i, st, 1u, 2u, 1u, z);
+    parts_append(&s->i, x, s->sigma_a * z[0], s->sigma_a * z[1], s->sigma_a * z[2], uid_i);
+    s->counts[ORC_C_IONIZ]++;
+  }
+}
+
+/* Step 6 for one ion with null-collision selection: candidate with
+ * probability P* (R_coll < P*); the target atom is drawn for candidates
+ * only (the same counter as in the direct method, so the same atom), then
+ * isotropic / backward / null from R_proc nu* against nu_iso, nu_iso +
+ * nu_back with nu_k = (n sigma_k) g. */
+static void ion_mcc_null(orc_sim *s, int64_t k) {
+  parts *p = &s->i;
+  const uint64_t uid = p->uid[k];
+  const uint32_t st = (uint32_t)s->step;
+  double r2[2];
+  orc_uniform2(s->c.seed, uid, st, 1u, 0u, 2u, r2);
+  if (!(r2[0] < s->p_null_i)) return;
+  double z[3];
+  normals3(s->c.seed, uid, st, 1u, 0u, 0u, z);
+  const double va[3] = {s->sigma_a * z[0], s->sigma_a * z[1], s->sigma_a * z[2]};
+  const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
+  const double gx = vx - va[0], gy = vy - va[1], gz = vz - va[2];
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  const double g = sqrt(g2);
+  const double energy = 0.5 * MU_ARAR * g2 / EV_TO_J;
+  const int idx = energy_bin(s, energy);
+  const double nu_iso = (s->gas_n * s->sig_iso[idx]) * g;
+  const double nu_back = (s->gas_n * s->sig_back[idx]) * g;
+  const double c1 = nu_iso, c2 = c1 + nu_back;
+  if (c2 > s->nu_star_i) s->counts[ORC_C_ANOMALY]++;
+  const double t = r2[1] * s->nu_star_i;
+  const int proc = t < c1 ? 0 : (t < c2 ? 1 : -1);
+  if (proc < 0) return;
+  double r3[2];
+  orc_uniform2(s->c.seed, uid, st, 1u, 0u, 3u, r3);
+  const double vin[3] = {vx, vy, vz};
+  double vout[3];
+  ion_kinematics(vin, va, proc, r3[0], r3[1], vout);
+  p->vx[k] = vout[0];
+  p->vy[k] = vout[1];
+  p->vz[k] = vout[2];
+  s->counts[ORC_C_COLL_I]++;
+}
+
 /* Step 6 for one ion on an ion step: draw the target from the gas Maxwellian
  * first, then P from the COM energy mu g^2/2 (Algorithm 6). */
 static void ion_mcc(orc_sim *s, int64_t k) {
@@ -763,9 +891,20 @@ static void one_step(orc_sim *s) {
   /* 6. collisions, for the particles present when the loops start (reading:
    * particles born in this step act from the next step on). */
   const int64_t ne_loop = s->e.n, ni_loop = s->i.n;
-  for (int64_t k = 0; k < ne_loop; ++k) electron_mcc(s, k);
+  const int null_coll = (s->c.flags & ORC_NULL_COLLISION) != 0;
+  for (int64_t k = 0; k < ne_loop; ++k) {
+    if (null_coll)
+      electron_mcc_null(s, k);
+    else
+      electron_mcc(s, k);
+  }
   if (ion_step)
-    for (int64_t k = 0; k < ni_loop; ++k) ion_mcc(s, k);
+    for (int64_t k = 0; k < ni_loop; ++k) {
+      if (null_coll)
+        ion_mcc_null(s, k);
+      else
+        ion_mcc(s, k);
+    }
   /* fold this step's fixed-point diagnostic sums into the time sums */
   if (fl & ORC_DIAG_CURRENT) {
     for (int p = 0; p < ng; ++p) {
@@ -887,4 +1026,11 @@ void orc_nsig_tot(const orc_sim *s, double *nsig_e, double *nsig_i) {
     if (nsig_e) nsig_e[k] = s->nsig_e[k];
     if (nsig_i) nsig_i[k] = s->nsig_i[k];
   }
+}
+
+void orc_null_params(const orc_sim *s, double out[4]) {
+  out[0] = s->nu_star_e;
+  out[1] = s->nu_star_i;
+  out[2] = s->p_null_e;
+  out[3] = s->p_null_i;
 }

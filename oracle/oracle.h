@@ -31,6 +31,7 @@ extern "C" {
 #define ORC_DIAG_CURRENT 4u  /* time-averaged j_e(x), j_i(x)                 */
 #define ORC_DIAG_MEANE 8u    /* time-averaged mean electron energy <eps>(x)   */
 #define ORC_IONIZ_ANGLE_LITERAL 16u /* ionization angles: chi = sqrt(..) as radians */
+#define ORC_NULL_COLLISION 64u /* null-collision selection of colliding particles */
 
 /* Counter slots returned by orc_counts(). */
 enum {
@@ -105,6 +106,11 @@ void orc_reset_diag(orc_sim *s);
 void orc_constants(const orc_sim *s, double out[8]);
 double orc_voltage(const orc_sim *s, int64_t step);
 void orc_nsig_tot(const orc_sim *s, double *nsig_e, double *nsig_i);
+/* Null-collision parameters: nu*_e, nu*_i, P*_e, P*_i. */
+void orc_null_params(const orc_sim *s, double out[4]);
+/* nu* = max n sigma_tot(E) g(E) over a table (upper bin edges; the last bin
+ * at four times the table range); mass: electron or Ar+ + Ar reduced mass. */
+double orc_nu_star(const double *nsig, int32_t nb, double de_ev, double mass);
 
 /* Building blocks, exposed for the pin tests -------------------------------- */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
