@@ -71,6 +71,8 @@ def main():
                     help="profiling aid: first copy a device buffer of this size (counter calibration)")
     ap.add_argument("--workload", choices=["large", "batch64"], default="large",
                     help="large: the single 2e6+2e6 case (default); batch64: the 64-case heterogeneous set")
+    ap.add_argument("--null-collision", action="store_true",
+                    help="select colliding particles by the null-collision method")
     ap.add_argument("--sequential", action="store_true",
                     help="batch64 only: advance the cases one after another instead of as one batch")
     args = ap.parse_args()
@@ -87,6 +89,8 @@ def main():
         return bench_batch(args)
 
     case = workloads.config_large()
+    if args.null_collision:
+        case = dict(case, flags=list(case["flags"]) + ["null_collision"])
     xs = workloads.synthetic_xsec()
     ctx = edupic.Context(0)
     ctx.set_xsec(xs)
@@ -180,7 +184,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain large single case: 1000 nodes, 8000 steps/RF cycle, 2e6+2e6 "
                                "seeded uniform 1e15 m^-3, 10 Pa Ar, 250 V 13.56 MHz; step = 1 RF cycle",
-                   "mode": ["plain", "graph"][args.mode], "electrons_live_end": c1["n_e"],
+                   "mode": ["plain", "graph"][args.mode], "collision_selection":
+                       "null collision" if args.null_collision else "direct",
+                   "electrons_live_end": c1["n_e"],
                    "ions_live_end": c1["n_i"], "electron_psteps": pe, "ion_psteps": pi},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -60,6 +60,14 @@ extern "C" {
 #define EDP_IONIZ_ANGLE_LITERAL 16u /* ionization: chi = sqrt(eps/(E-eps_ion)) taken
                                        as an angle instead of its cosine     */
 #define EDP_ALLOW_UNSTABLE 32u      /* create even if a stability check fails  */
+#define EDP_NULL_COLLISION 64u      /* select colliding particles by the
+                                       null-collision method (section 2.1.6):
+                                       candidates with P* = 1 - exp(-nu* dt),
+                                       nu* = max n sigma_tot g over the table
+                                       (bin upper edges, the last bin at four
+                                       times the table range), processes with
+                                       nu_k/nu*, the rest null; same random
+                                       slots as the direct test            */
 
 /* Species index. */
 #define EDP_ELECTRONS 0

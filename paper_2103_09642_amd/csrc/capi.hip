@@ -206,6 +206,21 @@ double voltage(const edp_case_desc& c, int64_t s) {
   return v;
 }
 
+// Null-collision maximum frequency of a table of n sigma_tot: the largest
+// n sigma_tot(E) g(E) with g at the upper end of each bin's energy range
+// (energies round to the nearest bin) and, for the last bin, which also holds
+// every higher energy, at four times the table's range.
+double nu_star(const std::vector<double>& nsig, double de_ev, double mass) {
+  const int nb = (int)nsig.size();
+  double m = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    const double e_hi = i == nb - 1 ? 4.0 * (double)nb * de_ev : ((double)i + 0.5) * de_ev;
+    const double nu = nsig[i] * std::sqrt(2.0 * e_hi * kEvToJ / mass);
+    m = std::max(m, nu);
+  }
+  return m;
+}
+
 Case* find(edp_ctx* ctx, edp_case id) {
   auto it = ctx->cases.find(id);
   return it == ctx->cases.end() ? nullptr : it->second;
@@ -681,6 +696,11 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   h.factor_e = h.dt_e / kEMass * kECharge;
   h.factor_i = h.dt_i / kArMass * kECharge;
   h.sigma_a = std::sqrt(kBoltzmann * D.gas_temp_k / kArMass);
+  h.n_gas = gas_n;
+  h.nu_star_e = nu_star(nsig_e, ctx->de, kEMass);
+  h.nu_star_i = nu_star(nsig_i, ctx->de, kMuArAr);
+  h.p_null_e = 1.0 - std::exp(-h.nu_star_e * h.dt_e);
+  h.p_null_i = 1.0 - std::exp(-h.nu_star_i * h.dt_i);
   h.de_cs = ctx->de;
   h.thr_exc = ctx->thr_exc;
   h.thr_ion = ctx->thr_ion;

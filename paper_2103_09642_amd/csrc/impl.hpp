@@ -40,7 +40,7 @@ constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
 
 // Flags (same values as EDP_* in edupic.h).
 constexpr uint32_t kDiagDensity = 1u, kDiagEepf = 2u, kDiagCurrent = 4u, kDiagMeanE = 8u,
-                   kIonizLiteral = 16u;
+                   kIonizLiteral = 16u, kNullCollision = 64u;
 constexpr uint32_t kDiagParticle = kDiagEepf | kDiagCurrent | kDiagMeanE;
 
 // Dynamic counters (int64 slots of CaseDev::ctr).
@@ -63,6 +63,9 @@ struct CaseDev {
   double L, dx, inv_dx, dt_e, dt_i, factor_w, factor_e, factor_i;
   double sigma_a, de_cs, thr_exc, thr_ion, w_ion, de_eepf, x_lo, x_hi;
   double dens_scale;  // factor_w / 2^32
+  double n_gas;                     // gas density p / (k_B T_g)
+  double nu_star_e, nu_star_i;      // null-collision maximum frequencies
+  double p_null_e, p_null_i;        // 1 - exp(-nu* dt) per species
   double kpois;       // dx*dx/eps0
   uint64_t seed;
   SpeciesDev sp[2];

@@ -846,6 +846,10 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const uint32_t st = (uint32_t)s;
   const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf;
   const double sa = C->sigma_a;
+  const bool null_coll = (fl & kNullCollision) != 0;
+  const double n_gas = C->n_gas;
+  const double nu_star = SP == 0 ? C->nu_star_e : C->nu_star_i;
+  const double p_null = SP == 0 ? C->p_null_e : C->p_null_i;
   const int w = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
   int tq = 0, tz = 0, tap = 0, tag_ = 0;  // this wave's totals over the workgroup's chunks
 
@@ -905,51 +909,86 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       if (abs_pow || abs_gnd) {
         live = false;
       } else {
-        // Step 6: collision test, P = 1 - exp(-n sigma_tot(E) g dt), collide iff R < P.
-        double r_coll, r_proc, p_coll;
-        int idx;
-        if (SP == 0) {
-          const double v2 = vxn * vxn + vy * vy + vz * vz;
-          const double v = sqrt(v2);
-          const double energy = 0.5 * kEMass * v2 / kEvToJ;
-          idx = energy_bin(energy, de_cs, nbins);
-          const double nu = nsig[idx] * v;
-          p_coll = 1.0 - exp(-nu * dt);
-          uniform2(seed, uid, st, tag(0, 0, 0), r_coll, r_proc);
-        } else {
-          double z0, z1, z2;
-          normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
-          const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
-          const double g2 = gx * gx + gy * gy + gz * gz;
-          const double g = sqrt(g2);
-          const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-          idx = energy_bin(energy, de_cs, nbins);
-          const double nu = nsig[idx] * g;
-          p_coll = 1.0 - exp(-nu * dt);
-          uniform2(seed, uid, st, tag(1, 0, 2), r_coll, r_proc);
-        }
+        // Step 6: collision test.  Direct: P = 1 - exp(-n sigma_tot(E) g dt),
+        // collide iff R < P, process by sigma_k/sigma_tot.  Null collision:
+        // candidate iff R < P* (no table work for the others), process by
+        // R nu* against the cumulative nu_k = (n sigma_k) g, the rest null.
+        double r_coll, r_proc;
+        int idx = 0;
         long long r;
         const int q = deposit_split(xn, inv_dx, ng, r);
-        coll = r_coll < p_coll;
-        if (coll) {
-          if (SP == 0) {
-            const double s_el = sig0[idx], s_exc = sig1[idx], s_ion = sig2[idx];
-            const double s_tot = s_el + s_exc + s_ion;
-            if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
-              proc = 0;
-            else if (r_proc < (s_el + s_exc) / s_tot)
-              proc = 1;
-            else
-              proc = 2;
-            if (proc == 2) {
-              ioniz = true;
-              gl_add(&cnt_i_next[q], 4294967296LL - r);
-              gl_add(&cnt_i_next[q + 1], r);
+        if (null_coll) {
+          uniform2(seed, uid, st, SP == 0 ? tag(0, 0, 0) : tag(1, 0, 2), r_coll, r_proc);
+          if (r_coll < p_null) {
+            double g, c1, c2, c3;
+            if (SP == 0) {
+              const double v2 = vxn * vxn + vy * vy + vz * vz;
+              g = sqrt(v2);
+              const double energy = 0.5 * kEMass * v2 / kEvToJ;
+              idx = energy_bin(energy, de_cs, nbins);
+              c1 = (n_gas * sig0[idx]) * g;
+              c2 = c1 + (n_gas * sig1[idx]) * g;
+              c3 = c2 + (n_gas * sig2[idx]) * g;
+            } else {
+              double z0, z1, z2;
+              normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+              const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+              const double g2 = gx * gx + gy * gy + gz * gz;
+              g = sqrt(g2);
+              const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+              idx = energy_bin(energy, de_cs, nbins);
+              c1 = (n_gas * sig0[idx]) * g;
+              c2 = c1 + (n_gas * sig1[idx]) * g;
+              c3 = c2;
             }
-          } else {
-            const double s_iso = sig0[idx], s_back = sig1[idx];
-            proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
+            if (c3 > nu_star) gl_add(&Cw->ctr[kAnomaly], 1);
+            const double t = r_proc * nu_star;
+            proc = t < c1 ? 0 : (t < c2 ? 1 : (SP == 0 && t < c3 ? 2 : -1));
+            coll = proc >= 0;
           }
+        } else {
+          double p_coll;
+          if (SP == 0) {
+            const double v2 = vxn * vxn + vy * vy + vz * vz;
+            const double v = sqrt(v2);
+            const double energy = 0.5 * kEMass * v2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            const double nu = nsig[idx] * v;
+            p_coll = 1.0 - exp(-nu * dt);
+            uniform2(seed, uid, st, tag(0, 0, 0), r_coll, r_proc);
+          } else {
+            double z0, z1, z2;
+            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+            const double g2 = gx * gx + gy * gy + gz * gz;
+            const double g = sqrt(g2);
+            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            const double nu = nsig[idx] * g;
+            p_coll = 1.0 - exp(-nu * dt);
+            uniform2(seed, uid, st, tag(1, 0, 2), r_coll, r_proc);
+          }
+          coll = r_coll < p_coll;
+          if (coll) {
+            if (SP == 0) {
+              const double s_el = sig0[idx], s_exc = sig1[idx], s_ion = sig2[idx];
+              const double s_tot = s_el + s_exc + s_ion;
+              if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
+                proc = 0;
+              else if (r_proc < (s_el + s_exc) / s_tot)
+                proc = 1;
+              else
+                proc = 2;
+            } else {
+              const double s_iso = sig0[idx], s_back = sig1[idx];
+              proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
+            }
+          }
+        }
+        if (SP == 0 && coll && proc == 2) {
+          ioniz = true;
+          gl_add(&cnt_i_next[q], 4294967296LL - r);
+          gl_add(&cnt_i_next[q + 1], r);
         }
         // the parent, plus the newborn electron of an ionization
         const long long mult = ioniz ? 2 : 1;

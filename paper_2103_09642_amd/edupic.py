@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libedupic.so")
 
 EDP_OK, EDP_EINVAL, EDP_ECAPACITY, EDP_EUNSTABLE, EDP_EHIP, EDP_EARENA, EDP_ESTATE = 0, -1, -2, -3, -4, -5, -6
 DIAG_DENSITY, DIAG_EEPF, DIAG_CURRENT, DIAG_MEANE, IONIZ_ANGLE_LITERAL, ALLOW_UNSTABLE = 1, 2, 4, 8, 16, 32
+NULL_COLLISION = 64
 OPT_MODE, OPT_SORT_EVERY, OPT_PROFILE, OPT_GRAPH_STEPS, OPT_WG_PER_CU = 1, 2, 5, 6, 7
 OPT_POISSON = 8
 POISSON_FLUX, POISSON_THOMAS = 0, 1
@@ -24,7 +25,7 @@ MODE_PLAIN, MODE_GRAPH, MODE_PERSISTENT = 0, 1, 2
 ELECTRONS, IONS = 0, 1
 _FLAG_NAMES = {"density": DIAG_DENSITY, "eepf": DIAG_EEPF, "current": DIAG_CURRENT,
                "meane": DIAG_MEANE, "ioniz_literal": IONIZ_ANGLE_LITERAL,
-               "allow_unstable": ALLOW_UNSTABLE}
+               "allow_unstable": ALLOW_UNSTABLE, "null_collision": NULL_COLLISION}
 
 
 class EdpError(RuntimeError):

@@ -386,3 +386,45 @@ def test_long_run_statistics_match_oracle(ctx, xs_default, orc):
         tol = max(0.03, 3.0 * spread)
         rel = abs(gpu[k] - o1[k]) / abs(o1[k])
         assert rel <= tol, f"{k}: gpu {gpu[k]} oracle {o1[k]} (rel {rel:.3g} > {tol:.3g})"
+
+
+# ---------------------------------------------------------------------------
+# Null-collision selection (section 2.1.6): same random slots as the direct
+# test, so the GPU and the oracle make the same decisions.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("step", [0, 5])
+def test_null_collision_one_step_parity(ctx, xs_default, orc, step):
+    say(f"test_null_collision_one_step_parity step={step}")
+    c = _case(pressure_pa=50.0, weight=2e5, n_grid=400, ion_subcycle=5, cap_e=200_000, cap_i=200_000,
+              flags=["allow_unstable", "null_collision"])
+    st = random_state(60_000, 50_000, c["gap_m"], seed=31 + step, te_ev=4.0, hot_frac=0.3, hot_ev=90.0,
+                      ion_energy_ev=30.0)
+    g, o = _one_step(ctx, xs_default, orc, c, st, step)
+    cg, co = g.counts(), o.counts()
+    for k in ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz", "anomaly"):
+        assert cg[k if k != "anomaly" else "anomalies"] == co[k], k
+    assert co["coll_e"] > 100 and co["ioniz"] > 10
+    if step % 5 == 0:
+        assert co["coll_i"] > 10
+    _, _, eo = o.fields()
+    kick = {0: np.abs(eo).max() * c["dt_e"] * 1.602176634e-19 / 9.1093837015e-31,
+            1: np.abs(eo).max() * c["dt_e"] * c["ion_subcycle"] * 1.602176634e-19 / (39.948 * 1.66053906660e-27)}
+    for sp in (0, 1):
+        compare_states(g.get_state(sp), o.get_state(sp), 1e-12, f"null sp{sp}",
+                       floors={k: kick[sp] for k in ("vx", "vy", "vz")})
+    g.destroy()
+
+
+def test_null_collision_multi_step_parity(ctx, xs_default, orc):
+    say("test_null_collision_multi_step_parity")
+    c = _case(pressure_pa=20.0, weight=1e5, n_grid=300, cap_e=100_000, cap_i=100_000,
+              flags=["allow_unstable", "null_collision"])
+    st = random_state(20_000, 20_000, c["gap_m"], seed=33, te_ev=3.0, hot_frac=0.2, hot_ev=80.0)
+    g, o = _one_step(ctx, xs_default, orc, c, st, 0, nsteps=60)
+    cg, co = g.counts(), o.counts()
+    for k in ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz"):
+        assert cg[k] == co[k], k
+    for sp in (0, 1):
+        compare_states(g.get_state(sp), o.get_state(sp), 1e-9, f"null sp{sp}")
+    g.destroy()
