@@ -16,10 +16,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 DIAG_DENSITY, DIAG_EEPF, DIAG_CURRENT, DIAG_MEANE, IONIZ_LITERAL = 1, 2, 4, 8, 16
-NULL_COLLISION = 64
+NULL_COLLISION, DIAG_XT, DIAG_IFED = 64, 128, 256
 _FLAG_NAMES = {"density": DIAG_DENSITY, "eepf": DIAG_EEPF, "current": DIAG_CURRENT,
                "meane": DIAG_MEANE, "ioniz_literal": IONIZ_LITERAL, "null_collision": NULL_COLLISION,
+               "xt": DIAG_XT, "ifed": DIAG_IFED,
                "allow_unstable": 0}  # a library option with no effect on the method
+XT_NAMES = ["pot", "efield", "ne", "ni", "je", "ji", "powere", "poweri", "meanee", "meanei", "ioniz"]
+INFO_NAMES = ["mean_e", "ne_max", "debye", "dx_debye", "wpe_dt", "pmax_e", "pmax_i", "cfl_ev",
+              "power_e", "power_i", "flux_i_pow", "flux_i_gnd", "ei_pow", "ei_gnd", "fail"]
 COUNTER_NAMES = ["abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i",
                  "ioniz", "anomaly"]
 
@@ -32,7 +36,8 @@ class OrcCase(C.Structure):
                 ("phase_rad", C.c_double * 4), ("weight", C.c_double),
                 ("n_init_e", C.c_int64), ("n_init_i", C.c_int64), ("te_init_ev", C.c_double),
                 ("ti_init_k", C.c_double), ("seed", C.c_uint64), ("flags", C.c_uint32),
-                ("n_eepf", C.c_int32), ("de_eepf_ev", C.c_double)]
+                ("n_eepf", C.c_int32), ("de_eepf_ev", C.c_double),
+                ("n_xt_bin", C.c_int32), ("n_ifed", C.c_int32), ("de_ifed_ev", C.c_double)]
 
 
 class OrcXsec(C.Structure):
@@ -78,6 +83,13 @@ def lib():
         L.orc_read_currents.argtypes = [P, dp, dp]
         L.orc_read_mean_energy.argtypes = [P, dp]
         L.orc_reset_diag.argtypes = [P]
+        L.orc_n_xt.restype = C.c_int32
+        L.orc_n_xt.argtypes = [P]
+        L.orc_read_xt.argtypes = [P, C.c_int, dp]
+        L.orc_xt_steps.argtypes = [P, ip, ip]
+        L.orc_read_ifed.argtypes = [P, dp, dp, ip]
+        L.orc_info.argtypes = [P, dp]
+        L.orc_plasma_params.argtypes = [C.c_double, C.c_double, dp]
         L.orc_constants.argtypes = [P, dp]
         L.orc_voltage.restype = C.c_double
         L.orc_voltage.argtypes = [P, C.c_int64]
@@ -138,6 +150,8 @@ def make_case(c: Dict) -> OrcCase:
         fl |= _FLAG_NAMES[name]
     d.flags = fl
     d.n_eepf, d.de_eepf_ev = c["n_eepf"], c["de_eepf_ev"]
+    d.n_xt_bin = c.get("n_xt_bin", 20)
+    d.n_ifed, d.de_ifed_ev = c.get("n_ifed", 200), c.get("de_ifed_ev", 1.0)
     return d
 
 
@@ -234,6 +248,35 @@ class Oracle:
     def reset_diag(self):
         lib().orc_reset_diag(self.h)
 
+    @property
+    def n_xt(self) -> int:
+        return lib().orc_n_xt(self.h)
+
+    def xt(self, name: str) -> np.ndarray:
+        """xt array `name` (one of XT_NAMES) as [n_xt, n_grid]."""
+        out = np.zeros((max(self.n_xt, 1), self.ng))
+        lib().orc_read_xt(self.h, XT_NAMES.index(name), dptr(out))
+        return out[: self.n_xt]
+
+    def xt_steps(self):
+        n = max(self.n_xt, 1)
+        a, b = np.zeros(n, dtype=np.int64), np.zeros(n, dtype=np.int64)
+        lib().orc_xt_steps(self.h, iptr(a), iptr(b))
+        return a[: self.n_xt], b[: self.n_xt]
+
+    def ifed(self):
+        """(F_powered, F_grounded, counts[2, n_ifed + 1])."""
+        nb = self.case.get("n_ifed", 200)
+        fp, fg = np.zeros(nb), np.zeros(nb)
+        c = np.zeros(2 * (nb + 1), dtype=np.int64)
+        lib().orc_read_ifed(self.h, dptr(fp), dptr(fg), iptr(c))
+        return fp, fg, c.reshape(2, nb + 1)
+
+    def info(self) -> Dict[str, float]:
+        out = np.zeros(len(INFO_NAMES))
+        lib().orc_info(self.h, dptr(out))
+        return dict(zip(INFO_NAMES, (float(v) for v in out)))
+
     def constants(self) -> Dict[str, float]:
         a = np.zeros(8)
         lib().orc_constants(self.h, dptr(a))
@@ -319,6 +362,13 @@ def scatter(g, gmag, gnew, f2, cos_chi, sin_chi, eta, w):
 
 def child_uid(parent: int, step: int, kind: int) -> int:
     return int(lib().orc_child_uid(parent, step, kind))
+
+
+def plasma_params(n_e: float, te_ev: float):
+    """(Debye length [m], electron plasma frequency [rad/s])."""
+    out = np.zeros(2)
+    lib().orc_plasma_params(n_e, te_ev, dptr(out))
+    return float(out[0]), float(out[1])
 
 
 def nu_star(nsig: np.ndarray, de_ev: float, mass: float) -> float:

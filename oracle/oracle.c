@@ -42,6 +42,7 @@ static const double TWO32 = 4294967296.0; /* fixed-point unit of one particle */
 static const double DIAG_JS = 1024.0;    /* c * vbar_x          [m/s]  */
 static const double DIAG_WS = 1048576.0; /* c                          */
 static const double DIAG_ES = 1048576.0; /* c * energy          [eV]   */
+static const double DIAG_IZS = 4294967296.0; /* c * nu_ion dt_e        */
 
 static char g_err[256];
 const char *orc_error(void) { return g_err; }
@@ -73,6 +74,15 @@ struct orc_sim {
   int64_t *eepf;
   int64_t *acc_je, *acc_ji, *acc_w, *acc_e; /* per step, fixed point    */
   double *sum_je, *sum_ji, *sum_w, *sum_e;  /* time sums                */
+  /* xt arrays and IFEDF (section 3.5) */
+  int32_t n_xt;
+  int64_t *acc_wi, *acc_ei, *acc_iz; /* per step: ion weight and energy,
+                                        electron ionization probability   */
+  double *x_pot, *x_ef, *x_ne, *x_ni;       /* [n_xt][ng] sums of the grid values */
+  double *x_je, *x_ji, *x_pe, *x_pi;        /* sums of acc, acc * E              */
+  double *x_we, *x_ee, *x_wi, *x_ei, *x_iz; /* sums of acc                       */
+  int64_t *x_steps, *x_ion_steps;           /* [n_xt] steps per bin              */
+  int64_t *ifed;                            /* [2][n_ifed + 1]                   */
 };
 
 /* ---------------------------------------------------------------------------
@@ -480,6 +490,11 @@ orc_sim *orc_new(const orc_case *c, const orc_xsec *xs) {
   if (xs->n_bins < 1 || !(xs->de_ev > 0.0)) return set_err("bad cross-section table"), NULL;
   if ((c->flags & ORC_DIAG_EEPF) && (c->n_eepf < 1 || !(c->de_eepf_ev > 0.0)))
     return set_err("bad EEPF binning"), NULL;
+  if ((c->flags & ORC_DIAG_XT) &&
+      (c->n_xt_bin < 1 || c->steps_per_cycle < 1 || c->steps_per_cycle % c->n_xt_bin != 0))
+    return set_err("N_BIN must divide the steps per cycle"), NULL;
+  if ((c->flags & ORC_DIAG_IFED) && (c->n_ifed < 1 || !(c->de_ifed_ev > 0.0)))
+    return set_err("bad IFEDF binning"), NULL;
   orc_sim *s = calloc(1, sizeof *s);
   if (!s) return set_err("out of memory"), NULL;
   s->c = *c;
@@ -535,6 +550,17 @@ orc_sim *orc_new(const orc_case *c, const orc_xsec *xs) {
   s->sum_w = calloc((size_t)ng, sizeof(double));
   s->sum_e = calloc((size_t)ng, sizeof(double));
   s->eepf = calloc((size_t)(c->n_eepf > 0 ? c->n_eepf : 1), sizeof(int64_t));
+  s->acc_wi = calloc((size_t)ng, sizeof(int64_t));
+  s->acc_ei = calloc((size_t)ng, sizeof(int64_t));
+  s->acc_iz = calloc((size_t)ng, sizeof(int64_t));
+  s->n_xt = (c->flags & ORC_DIAG_XT) ? c->steps_per_cycle / c->n_xt_bin : 1;
+  const size_t nx = (size_t)s->n_xt * (size_t)ng;
+  double **xt[] = {&s->x_pot, &s->x_ef, &s->x_ne, &s->x_ni, &s->x_je, &s->x_ji, &s->x_pe,
+                   &s->x_pi, &s->x_we, &s->x_ee, &s->x_wi, &s->x_ei, &s->x_iz};
+  for (size_t k = 0; k < sizeof xt / sizeof xt[0]; ++k) *xt[k] = calloc(nx, sizeof(double));
+  s->x_steps = calloc((size_t)s->n_xt, sizeof(int64_t));
+  s->x_ion_steps = calloc((size_t)s->n_xt, sizeof(int64_t));
+  s->ifed = calloc(2 * (size_t)((c->flags & ORC_DIAG_IFED) ? c->n_ifed + 1 : 1), sizeof(int64_t));
   return s;
 }
 
@@ -544,7 +570,9 @@ void orc_free(orc_sim *s) {
   parts_free(&s->i);
   double *dbl[] = {s->sig_el, s->sig_exc, s->sig_ion, s->sig_iso, s->sig_back, s->nsig_e,
                    s->nsig_i, s->ne, s->ni, s->rho, s->phi, s->efield, s->sum_ne, s->sum_ni,
-                   s->sum_je, s->sum_ji, s->sum_w, s->sum_e};
+                   s->sum_je, s->sum_ji, s->sum_w, s->sum_e, s->x_pot, s->x_ef, s->x_ne,
+                   s->x_ni, s->x_je, s->x_ji, s->x_pe, s->x_pi, s->x_we, s->x_ee,
+                   s->x_wi, s->x_ei, s->x_iz};
   for (size_t k = 0; k < sizeof dbl / sizeof dbl[0]; ++k) free(dbl[k]);
   free(s->cnt_e);
   free(s->cnt_i_cur);
@@ -553,6 +581,12 @@ void orc_free(orc_sim *s) {
   free(s->acc_w);
   free(s->acc_e);
   free(s->eepf);
+  free(s->acc_wi);
+  free(s->acc_ei);
+  free(s->acc_iz);
+  free(s->x_steps);
+  free(s->x_ion_steps);
+  free(s->ifed);
   free(s);
 }
 
@@ -625,7 +659,10 @@ int64_t orc_get_state(const orc_sim *s, int species, double *x, double *vx, doub
  * Steps 3-4: interpolate E to the particle (eq. for E_j) and leapfrog
  * (eqs. for v(t+dt/2) and x(t+dt)), Algorithm 4.  In measurement mode the
  * velocity at integer time, the mean of the old and new half-step velocities,
- * is used with the old position (section 3.6).
+ * is used with the old position (section 3.6).  With the xt arrays the
+ * ionization rate is measured there too, as the expected rate
+ * n sigma_ion(eps) |v| of each electron at that velocity (reading: the paper
+ * measures it where the particles move, with the time-centred velocities).
  * ------------------------------------------------------------------------- */
 static void push(orc_sim *s, parts *p, int is_ion) {
   const int ng = s->ng;
@@ -649,17 +686,34 @@ static void push(orc_sim *s, parts *p, int is_ion) {
       vx_new = vx_old - ex * s->factor_e;
     p->vx[k] = vx_new;
     p->x[k] = x + vx_new * dt;
-    if (!(fl & (ORC_DIAG_CURRENT | ORC_DIAG_MEANE | ORC_DIAG_EEPF))) continue;
+    if (!(fl & (ORC_DIAG_CURRENT | ORC_DIAG_MEANE | ORC_DIAG_EEPF | ORC_DIAG_XT))) continue;
     const double vbar = 0.5 * (vx_old + vx_new);
-    if (fl & ORC_DIAG_CURRENT) {
+    const int xt = (fl & ORC_DIAG_XT) != 0;
+    if (fl & (ORC_DIAG_CURRENT | ORC_DIAG_XT)) {
       int64_t *acc = is_ion ? s->acc_ji : s->acc_je;
       acc[q] += (int64_t)(c1 * vbar * DIAG_JS);
       acc[q + 1] += (int64_t)(c2 * vbar * DIAG_JS);
     }
-    if (is_ion || !(fl & (ORC_DIAG_MEANE | ORC_DIAG_EEPF))) continue;
     const double vy = p->vy[k], vz = p->vz[k];
+    if (is_ion) {
+      if (xt) {
+        const double en_i = 0.5 * AR_MASS * (vbar * vbar + vy * vy + vz * vz) / EV_TO_J;
+        s->acc_wi[q] += (int64_t)(c1 * DIAG_WS);
+        s->acc_wi[q + 1] += (int64_t)(c2 * DIAG_WS);
+        s->acc_ei[q] += (int64_t)(c1 * en_i * DIAG_ES);
+        s->acc_ei[q + 1] += (int64_t)(c2 * en_i * DIAG_ES);
+      }
+      continue;
+    }
+    if (!(fl & (ORC_DIAG_MEANE | ORC_DIAG_EEPF | ORC_DIAG_XT))) continue;
     const double en = 0.5 * E_MASS * (vbar * vbar + vy * vy + vz * vz) / EV_TO_J;
-    if (fl & ORC_DIAG_MEANE) {
+    if (xt) {
+      const double vmag = sqrt(vbar * vbar + vy * vy + vz * vz);
+      const double pdt = (s->gas_n * s->sig_ion[energy_bin(s, en)]) * vmag * s->dt_e;
+      s->acc_iz[q] += (int64_t)(c1 * pdt * DIAG_IZS);
+      s->acc_iz[q + 1] += (int64_t)(c2 * pdt * DIAG_IZS);
+    }
+    if (fl & (ORC_DIAG_MEANE | ORC_DIAG_XT)) {
       s->acc_w[q] += (int64_t)(c1 * DIAG_WS);
       s->acc_w[q + 1] += (int64_t)(c2 * DIAG_WS);
       s->acc_e[q] += (int64_t)(c1 * en * DIAG_ES);
@@ -673,8 +727,11 @@ static void push(orc_sim *s, parts *p, int is_ion) {
 }
 
 /* Step 5: absorbing electrodes; removal by moving the last particle into the
- * hole (Algorithm 5).  x < 0: powered electrode, x > L: grounded. */
+ * hole (Algorithm 5).  x < 0: powered electrode, x > L: grounded.  An
+ * absorbed ion adds its impact energy M v^2 / 2, from the half-step velocity
+ * that carried it out, to its electrode's IFEDF (Algorithm 5, ions). */
 static void walls(orc_sim *s, parts *p, int is_ion) {
+  const int ifed = is_ion && (s->c.flags & ORC_DIAG_IFED);
   int64_t k = 0;
   while (k < p->n) {
     const double x = p->x[k];
@@ -685,7 +742,15 @@ static void walls(orc_sim *s, parts *p, int is_ion) {
     }
     if (x > s->L) {
       s->counts[is_ion ? ORC_C_ABS_I_GND : ORC_C_ABS_E_GND]++;
-      out = 1;
+      out = 2;
+    }
+    if (out && ifed) {
+      const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
+      const double en = 0.5 * AR_MASS * (vx * vx + vy * vy + vz * vz) / EV_TO_J;
+      const double t = en / s->c.de_ifed_ev;
+      const int nb = s->c.n_ifed;
+      const int b = t < (double)nb ? (int)t : nb;
+      s->ifed[(out - 1) * (nb + 1) + b]++;
     }
     if (out) {
       const int64_t last = p->n - 1;
@@ -867,6 +932,10 @@ static void one_step(orc_sim *s) {
   const int ng = s->ng;
   const int ion_step = (s->step % s->c.ion_subcycle) == 0;
   const uint32_t fl = s->c.flags;
+  const int xt = (fl & ORC_DIAG_XT) != 0;
+  /* xt time bin of this step: N_BIN consecutive steps of the RF period */
+  const size_t row =
+      xt ? (size_t)((s->step % s->c.steps_per_cycle) / s->c.n_xt_bin) * (size_t)ng : 0;
   /* 1. densities */
   memset(s->cnt_e, 0, (size_t)ng * sizeof(int64_t));
   orc_deposit(s->e.x, s->e.n, ng, s->inv_dx, s->cnt_e);
@@ -882,6 +951,16 @@ static void one_step(orc_sim *s) {
       s->sum_ne[p] += s->ne[p];
       s->sum_ni[p] += s->ni[p];
     }
+  if (xt) {
+    for (int p = 0; p < ng; ++p) {
+      s->x_pot[row + p] += s->phi[p];
+      s->x_ef[row + p] += s->efield[p];
+      s->x_ne[row + p] += s->ne[p];
+      s->x_ni[row + p] += s->ni[p];
+    }
+    s->x_steps[row / (size_t)ng]++;
+    if (ion_step) s->x_ion_steps[row / (size_t)ng]++;
+  }
   /* 3-4. push */
   push(s, &s->e, 0);
   if (ion_step) push(s, &s->i, 1);
@@ -905,25 +984,43 @@ static void one_step(orc_sim *s) {
       else
         ion_mcc(s, k);
     }
-  /* fold this step's fixed-point diagnostic sums into the time sums */
-  if (fl & ORC_DIAG_CURRENT) {
+  /* fold this step's fixed-point diagnostic sums into the time sums and
+   * the xt arrays; the power density is j E at the nodes with the field of
+   * this step (section 3.5) */
+  if (xt)
     for (int p = 0; p < ng; ++p) {
-      s->sum_je[p] += (double)s->acc_je[p];
-      s->acc_je[p] = 0;
-    }
-    if (ion_step)
-      for (int p = 0; p < ng; ++p) {
-        s->sum_ji[p] += (double)s->acc_ji[p];
-        s->acc_ji[p] = 0;
+      const double je = (double)s->acc_je[p];
+      s->x_je[row + p] += je;
+      s->x_pe[row + p] += je * s->efield[p];
+      s->x_we[row + p] += (double)s->acc_w[p];
+      s->x_ee[row + p] += (double)s->acc_e[p];
+      s->x_iz[row + p] += (double)s->acc_iz[p];
+      if (ion_step) {
+        const double ji = (double)s->acc_ji[p];
+        s->x_ji[row + p] += ji;
+        s->x_pi[row + p] += ji * s->efield[p];
+        s->x_wi[row + p] += (double)s->acc_wi[p];
+        s->x_ei[row + p] += (double)s->acc_ei[p];
       }
+    }
+  if (fl & ORC_DIAG_CURRENT) {
+    for (int p = 0; p < ng; ++p) s->sum_je[p] += (double)s->acc_je[p];
+    if (ion_step)
+      for (int p = 0; p < ng; ++p) s->sum_ji[p] += (double)s->acc_ji[p];
   }
   if (fl & ORC_DIAG_MEANE)
     for (int p = 0; p < ng; ++p) {
       s->sum_w[p] += (double)s->acc_w[p];
       s->sum_e[p] += (double)s->acc_e[p];
-      s->acc_w[p] = 0;
-      s->acc_e[p] = 0;
     }
+  int64_t *accs[] = {s->acc_je, s->acc_w, s->acc_e, s->acc_iz};
+  for (size_t a = 0; a < sizeof accs / sizeof accs[0]; ++a)
+    memset(accs[a], 0, (size_t)ng * sizeof(int64_t));
+  if (ion_step) {
+    int64_t *acci[] = {s->acc_ji, s->acc_wi, s->acc_ei};
+    for (size_t a = 0; a < sizeof acci / sizeof acci[0]; ++a)
+      memset(acci[a], 0, (size_t)ng * sizeof(int64_t));
+  }
   s->diag_steps++;
   if (ion_step) s->diag_ion_steps++;
   s->step++;
@@ -1008,6 +1105,164 @@ void orc_reset_diag(orc_sim *s) {
   memset(s->sum_w, 0, ng * sizeof(double));
   memset(s->sum_e, 0, ng * sizeof(double));
   memset(s->eepf, 0, (size_t)(s->c.n_eepf > 0 ? s->c.n_eepf : 1) * sizeof(int64_t));
+  const size_t nx = (size_t)s->n_xt * ng;
+  double *xt[] = {s->x_pot, s->x_ef, s->x_ne, s->x_ni, s->x_je, s->x_ji, s->x_pe,
+                  s->x_pi, s->x_we, s->x_ee, s->x_wi, s->x_ei, s->x_iz};
+  for (size_t k = 0; k < sizeof xt / sizeof xt[0]; ++k) memset(xt[k], 0, nx * sizeof(double));
+  memset(s->x_steps, 0, (size_t)s->n_xt * sizeof(int64_t));
+  memset(s->x_ion_steps, 0, (size_t)s->n_xt * sizeof(int64_t));
+  memset(s->ifed, 0,
+         2 * (size_t)((s->c.flags & ORC_DIAG_IFED) ? s->c.n_ifed + 1 : 1) * sizeof(int64_t));
+}
+
+int32_t orc_n_xt(const orc_sim *s) { return (s->c.flags & ORC_DIAG_XT) ? s->n_xt : 0; }
+
+void orc_xt_steps(const orc_sim *s, int64_t *steps, int64_t *ion_steps) {
+  for (int t = 0; t < s->n_xt; ++t) {
+    if (steps) steps[t] = s->x_steps[t];
+    if (ion_steps) ion_steps[t] = s->x_ion_steps[t];
+  }
+}
+
+/* Cell means of the xt sums in SI units (eV for the mean energies):
+ * current density j = q n vbar and power density j E from the time-centred
+ * velocities, ionization rate n_e-weighted n sigma_ion |v| [m^-3 s^-1].
+ * Edge nodes carry half a cell, so their particle sums count double (as in
+ * the densities). */
+void orc_read_xt(const orc_sim *s, int q, double *out) {
+  const int ng = s->ng;
+  const double fw = s->factor_w;
+  for (int t = 0; t < s->n_xt; ++t) {
+    const double ns = (double)s->x_steps[t], ni = (double)s->x_ion_steps[t];
+    for (int p = 0; p < ng; ++p) {
+      const size_t k = (size_t)t * ng + p;
+      const double edge = (p == 0 || p == ng - 1) ? 2.0 : 1.0;
+      double v = 0.0;
+      switch (q) {
+        case ORC_XT_POT: v = ns > 0 ? s->x_pot[k] / ns : 0.0; break;
+        case ORC_XT_EFIELD: v = ns > 0 ? s->x_ef[k] / ns : 0.0; break;
+        case ORC_XT_NE: v = ns > 0 ? s->x_ne[k] / ns : 0.0; break;
+        case ORC_XT_NI: v = ns > 0 ? s->x_ni[k] / ns : 0.0; break;
+        case ORC_XT_JE:
+          v = ns > 0 ? edge * (-E_CHARGE * fw) * (s->x_je[k] / DIAG_JS) / ns : 0.0;
+          break;
+        case ORC_XT_JI:
+          v = ni > 0 ? edge * (E_CHARGE * fw) * (s->x_ji[k] / DIAG_JS) / ni : 0.0;
+          break;
+        case ORC_XT_POWERE:
+          v = ns > 0 ? edge * (-E_CHARGE * fw) * (s->x_pe[k] / DIAG_JS) / ns : 0.0;
+          break;
+        case ORC_XT_POWERI:
+          v = ni > 0 ? edge * (E_CHARGE * fw) * (s->x_pi[k] / DIAG_JS) / ni : 0.0;
+          break;
+        case ORC_XT_MEANEE:
+          v = s->x_we[k] > 0 ? (s->x_ee[k] / DIAG_ES) / (s->x_we[k] / DIAG_WS) : 0.0;
+          break;
+        case ORC_XT_MEANEI:
+          v = s->x_wi[k] > 0 ? (s->x_ei[k] / DIAG_ES) / (s->x_wi[k] / DIAG_WS) : 0.0;
+          break;
+        case ORC_XT_IONIZ:
+          v = ns > 0 ? edge * fw * (s->x_iz[k] / DIAG_IZS) / s->dt_e / ns : 0.0;
+          break;
+        default: break;
+      }
+      out[k] = v;
+    }
+  }
+}
+
+void orc_read_ifed(const orc_sim *s, double *f_pow, double *f_gnd, int64_t *counts) {
+  const int nb = s->c.n_ifed;
+  if (!(s->c.flags & ORC_DIAG_IFED) || nb < 1) return;
+  double *f[2] = {f_pow, f_gnd};
+  for (int side = 0; side < 2; ++side) {
+    const int64_t *h = s->ifed + (size_t)side * (nb + 1);
+    double tot = 0.0;
+    for (int k = 0; k < nb; ++k) tot += (double)h[k];
+    for (int k = 0; k <= nb; ++k)
+      if (counts) counts[(size_t)side * (nb + 1) + k] = h[k];
+    if (f[side])
+      for (int k = 0; k < nb; ++k)
+        f[side][k] = tot > 0.0 ? (double)h[k] / (tot * s->c.de_ifed_ev) : 0.0;
+  }
+}
+
+void orc_plasma_params(double n_e, double te_ev, double out[2]) {
+  out[0] = sqrt(EPSILON0 * te_ev * EV_TO_J / (n_e * E_CHARGE * E_CHARGE));
+  out[1] = sqrt(n_e * E_CHARGE * E_CHARGE / (EPSILON0 * E_MASS));
+}
+
+/* Run report (section 3.5): the accuracy and stability criteria 1-4 of
+ * section 2.2 evaluated on the measured state, the power absorbed by each
+ * species and the ion fluxes and mean impact energies at the electrodes.
+ * Readings: lambda_D and omega_pe take the peak of the time-averaged
+ * electron density and T_e = (2/3) of the mean electron energy over the
+ * gap; the largest collision probabilities are the null-collision bounds
+ * P* (the maximum of n sigma_tot g over the tables); the CFL energy is the
+ * electron energy that moves one cell per step; the power is the space
+ * (trapezoid) and time mean of the xt power density.  Quantities whose
+ * diagnostics are off read 0. */
+void orc_info(const orc_sim *s, double out[ORC_INFO_N]) {
+  const int ng = s->ng;
+  for (int k = 0; k < ORC_INFO_N; ++k) out[k] = 0.0;
+  const double nst = s->diag_steps > 0 ? (double)s->diag_steps : 1.0;
+  double ne_max = 0.0, sw = 0.0, se = 0.0;
+  for (int p = 0; p < ng; ++p) {
+    const double ne = s->sum_ne[p] / nst;
+    if (ne > ne_max) ne_max = ne;
+    sw += s->sum_w[p];
+    se += s->sum_e[p];
+  }
+  const double mean_e = sw > 0.0 ? (se / DIAG_ES) / (sw / DIAG_WS) : 0.0;
+  out[ORC_INFO_MEAN_E] = mean_e;
+  out[ORC_INFO_NE_MAX] = ne_max;
+  int fail = 0;
+  if (ne_max > 0.0 && mean_e > 0.0) {
+    double pp[2];
+    orc_plasma_params(ne_max, 2.0 / 3.0 * mean_e, pp);
+    out[ORC_INFO_DEBYE] = pp[0];
+    out[ORC_INFO_DX_DEBYE] = s->dx / pp[0];
+    out[ORC_INFO_WPE_DT] = pp[1] * s->dt_e;
+    if (!(out[ORC_INFO_DX_DEBYE] < 1.0)) fail |= 1;
+    if (!(out[ORC_INFO_WPE_DT] < 2.0)) fail |= 2;
+  }
+  out[ORC_INFO_PMAX_E] = s->p_null_e;
+  out[ORC_INFO_PMAX_I] = s->p_null_i;
+  if (!(s->p_null_e < 0.05) || !(s->p_null_i < 0.05)) fail |= 4;
+  const double vc = s->dx / s->dt_e;
+  out[ORC_INFO_CFL_EV] = 0.5 * E_MASS * vc * vc / EV_TO_J;
+  if (s->c.flags & ORC_DIAG_XT) {
+    /* trapezoid weight 1/2 at the edges cancels their doubling */
+    double pe = 0.0, pi = 0.0, ns = 0.0, ni = 0.0;
+    for (int t = 0; t < s->n_xt; ++t) {
+      ns += (double)s->x_steps[t];
+      ni += (double)s->x_ion_steps[t];
+      for (int p = 0; p < ng; ++p) {
+        pe += s->x_pe[(size_t)t * ng + p];
+        pi += s->x_pi[(size_t)t * ng + p];
+      }
+    }
+    const double fw = s->factor_w;
+    if (ns > 0) out[ORC_INFO_POWER_E] = (-E_CHARGE * fw) * (pe / DIAG_JS) / ((double)(ng - 1) * ns);
+    if (ni > 0) out[ORC_INFO_POWER_I] = (E_CHARGE * fw) * (pi / DIAG_JS) / ((double)(ng - 1) * ni);
+  }
+  if (s->c.flags & ORC_DIAG_IFED) {
+    const int nb = s->c.n_ifed;
+    const double tspan = (double)s->diag_steps * s->dt_e;
+    for (int side = 0; side < 2; ++side) {
+      const int64_t *h = s->ifed + (size_t)side * (nb + 1);
+      double all = 0.0, in = 0.0, en = 0.0;
+      for (int k = 0; k <= nb; ++k) all += (double)h[k];
+      for (int k = 0; k < nb; ++k) {
+        in += (double)h[k];
+        en += (double)h[k] * ((double)k + 0.5) * s->c.de_ifed_ev;
+      }
+      if (tspan > 0) out[side ? ORC_INFO_FLUX_I_GND : ORC_INFO_FLUX_I_POW] =
+          all * s->c.weight / (s->c.area_m2 * tspan);
+      if (in > 0) out[side ? ORC_INFO_EI_GND : ORC_INFO_EI_POW] = en / in;
+    }
+  }
+  out[ORC_INFO_FAIL] = (double)fail;
 }
 
 void orc_constants(const orc_sim *s, double out[8]) {

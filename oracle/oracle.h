@@ -32,6 +32,35 @@ extern "C" {
 #define ORC_DIAG_MEANE 8u    /* time-averaged mean electron energy <eps>(x)   */
 #define ORC_IONIZ_ANGLE_LITERAL 16u /* ionization angles: chi = sqrt(..) as radians */
 #define ORC_NULL_COLLISION 64u /* null-collision selection of colliding particles */
+#define ORC_DIAG_XT 128u     /* spatio-temporal (xt) arrays of section 3.5    */
+#define ORC_DIAG_IFED 256u   /* ion flux-energy distribution at each electrode */
+
+/* Quantities of the xt arrays (section 3.5), read as [n_xt][n_grid]. */
+enum {
+  ORC_XT_POT = 0, ORC_XT_EFIELD, ORC_XT_NE, ORC_XT_NI, ORC_XT_JE, ORC_XT_JI,
+  ORC_XT_POWERE, ORC_XT_POWERI, ORC_XT_MEANEE, ORC_XT_MEANEI, ORC_XT_IONIZ, ORC_XT_N
+};
+
+/* Slots of orc_info(): the run report of section 3.5 with the accuracy and
+ * stability criteria of section 2.2. */
+enum {
+  ORC_INFO_MEAN_E = 0,   /* mean electron energy over the gap [eV]           */
+  ORC_INFO_NE_MAX,       /* peak of the time-averaged electron density      */
+  ORC_INFO_DEBYE,        /* Debye length with T_e = 2/3 <eps>, n = peak [m] */
+  ORC_INFO_DX_DEBYE,     /* dx / lambda_D (criterion 1: < 1)                */
+  ORC_INFO_WPE_DT,       /* omega_pe dt_e (criterion 2: < 2)                */
+  ORC_INFO_PMAX_E,       /* largest electron collision probability per step */
+  ORC_INFO_PMAX_I,       /* largest ion collision probability per ion step  */
+  ORC_INFO_CFL_EV,       /* electron energy that crosses one cell per step  */
+  ORC_INFO_POWER_E,      /* space-time mean of j_e E [W m^-3]               */
+  ORC_INFO_POWER_I,      /* space-time mean of j_i E [W m^-3]               */
+  ORC_INFO_FLUX_I_POW,   /* ion flux to the powered electrode [m^-2 s^-1]   */
+  ORC_INFO_FLUX_I_GND,   /* ion flux to the grounded electrode              */
+  ORC_INFO_EI_POW,       /* mean ion impact energy, powered electrode [eV]  */
+  ORC_INFO_EI_GND,       /* mean ion impact energy, grounded electrode      */
+  ORC_INFO_FAIL,         /* bits: 1 criterion 1, 2 criterion 2, 4 criterion 3 */
+  ORC_INFO_N
+};
 
 /* Counter slots returned by orc_counts(). */
 enum {
@@ -59,6 +88,9 @@ typedef struct {
   uint32_t flags;      /* ORC_* flags                                       */
   int32_t n_eepf;      /* EEPF bins                                         */
   double de_eepf_ev;   /* EEPF bin width [eV]                              */
+  int32_t n_xt_bin;    /* N_BIN: steps per xt time bin (divides N_t)       */
+  int32_t n_ifed;      /* IFEDF bins                                        */
+  double de_ifed_ev;   /* IFEDF bin width [eV]                             */
 } orc_case;
 
 /* Tabulated cross sections (section 3.2): bin i <-> energy i*de_ev. */
@@ -101,6 +133,20 @@ void orc_read_eepf(const orc_sim *s, double *f, int64_t *counts);
 void orc_read_currents(const orc_sim *s, double *je, double *ji);
 void orc_read_mean_energy(const orc_sim *s, double *mee);
 void orc_reset_diag(orc_sim *s);
+/* xt arrays: time bin t holds the steps s with (s mod N_t) / N_BIN = t;
+ * each cell is the mean over the steps of its bin since the last reset (ion
+ * quantities over the ion steps).  out: [n_xt][n_grid], n_xt = N_t / N_BIN. */
+int32_t orc_n_xt(const orc_sim *s);
+void orc_read_xt(const orc_sim *s, int q, double *out);
+void orc_xt_steps(const orc_sim *s, int64_t *steps, int64_t *ion_steps);
+/* IFEDF per electrode, sum_k F_k de = 1 over the in-range bins; counts:
+ * [2][n_ifed + 1] (powered, grounded; the last bin counts impacts beyond the
+ * range).  Any output may be NULL. */
+void orc_read_ifed(const orc_sim *s, double *f_pow, double *f_gnd, int64_t *counts);
+void orc_info(const orc_sim *s, double out[ORC_INFO_N]);
+/* Debye length [m] and electron plasma frequency [rad/s] for a density
+ * [m^-3] and an electron temperature [eV]. */
+void orc_plasma_params(double n_e, double te_ev, double out[2]);
 /* Derived per-case constants (for tests): dx, dt_i, factor_w, factor_e,
  * factor_i, gas density, V at step 0. */
 void orc_constants(const orc_sim *s, double out[8]);

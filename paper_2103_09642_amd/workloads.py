@@ -77,6 +77,8 @@ def base_case(**kw) -> Dict:
         "weight": 3.5e5, "n_init_e": 1000, "n_init_i": 1000,
         "te_init_ev": 2.0, "ti_init_k": 350.0, "seed": 1,
         "flags": [], "n_eepf": 2000, "de_eepf_ev": 0.05,
+        # measurement mode: N_BIN steps per xt bin, IFEDF 200 x 1 eV (section 4.1)
+        "n_xt_bin": 20, "n_ifed": 200, "de_ifed_ev": 1.0,
     }
     c.update(kw)
     return c
