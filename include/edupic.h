@@ -68,6 +68,47 @@ extern "C" {
                                        times the table range), processes with
                                        nu_k/nu*, the rest null; same random
                                        slots as the direct test            */
+#define EDP_DIAG_XT 128u            /* spatio-temporal (xt) arrays of section
+                                       3.5: N_t / n_xt_bin time bins per RF
+                                       period, read by edp_read_xt          */
+#define EDP_DIAG_IFED 256u          /* ion flux-energy distribution at each
+                                       electrode (section 3.5, Algorithm 5) */
+
+/* Quantities of edp_read_xt (the xt files of section 3.5). */
+#define EDP_XT_POT 0      /* potential [V]                                     */
+#define EDP_XT_EFIELD 1   /* electric field [V m^-1]                           */
+#define EDP_XT_NE 2       /* electron density [m^-3]                           */
+#define EDP_XT_NI 3       /* ion density [m^-3]                                */
+#define EDP_XT_JE 4       /* electron current density [A m^-2]                 */
+#define EDP_XT_JI 5       /* ion current density [A m^-2]                      */
+#define EDP_XT_POWERE 6   /* electron power density j_e E [W m^-3]             */
+#define EDP_XT_POWERI 7   /* ion power density j_i E [W m^-3]                  */
+#define EDP_XT_MEANEE 8   /* mean electron energy [eV]                         */
+#define EDP_XT_MEANEI 9   /* mean ion energy [eV]                              */
+#define EDP_XT_IONIZ 10   /* ionization rate [m^-3 s^-1]                       */
+#define EDP_XT_N 11
+
+/* Slots of edp_read_info: the run report of section 3.5 with the accuracy
+ * and stability criteria of section 2.2 on the measured state. */
+#define EDP_INFO_MEAN_E 0     /* mean electron energy over the gap [eV]        */
+#define EDP_INFO_NE_MAX 1     /* peak time-averaged electron density [m^-3]    */
+#define EDP_INFO_DEBYE 2      /* Debye length, T_e = 2/3 <eps>, peak density   */
+#define EDP_INFO_DX_DEBYE 3   /* dx / lambda_D (criterion 1: < 1)              */
+#define EDP_INFO_WPE_DT 4     /* omega_pe dt_e (criterion 2: < 2)              */
+#define EDP_INFO_PMAX_E 5     /* largest electron collision probability per
+                                 step over the tables (criterion 3: < 0.05)   */
+#define EDP_INFO_PMAX_I 6     /* same for ions per ion step                    */
+#define EDP_INFO_CFL_EV 7     /* electron energy crossing one cell per step
+                                 (criterion 4: the EEPF must be negligible
+                                 above it) [eV]                                */
+#define EDP_INFO_POWER_E 8    /* space-time mean of j_e E [W m^-3]             */
+#define EDP_INFO_POWER_I 9    /* space-time mean of j_i E [W m^-3]             */
+#define EDP_INFO_FLUX_I_POW 10 /* ion flux to the powered electrode [m^-2 s^-1] */
+#define EDP_INFO_FLUX_I_GND 11 /* ion flux to the grounded electrode          */
+#define EDP_INFO_EI_POW 12    /* mean ion impact energy, powered [eV]          */
+#define EDP_INFO_EI_GND 13    /* mean ion impact energy, grounded [eV]         */
+#define EDP_INFO_FAIL 14      /* failed criteria: 1 (bit 0), 2 (bit 1), 3 (bit 2) */
+#define EDP_INFO_N 15
 
 /* Species index. */
 #define EDP_ELECTRONS 0
@@ -110,6 +151,9 @@ typedef struct {
   uint32_t flags;          /* EDP_DIAG_* and option flags                       */
   int32_t n_eepf;          /* EEPF bins (2000 in section 4.1)                  */
   double de_eepf_ev;       /* EEPF bin width [eV] (0.05 in section 4.1)         */
+  int32_t n_xt_bin;        /* N_BIN: steps per xt time bin, divides steps_per_cycle */
+  int32_t n_ifed;          /* IFEDF bins per electrode, 1..4096 (200)          */
+  double de_ifed_ev;       /* IFEDF bin width [eV] (1)                         */
 } edp_case_desc;
 
 /* Cross sections tabulated at energies i * de_ev, i = 0..n_bins-1
@@ -181,6 +225,29 @@ int edp_read_eepf(edp_ctx *ctx, edp_case c, double *f, int64_t *counts, int32_t 
 int edp_read_currents(edp_ctx *ctx, edp_case c, double *je, double *ji, int32_t n, int32_t reset);
 /* Time-averaged mean electron energy [eV] per node. */
 int edp_read_mean_energy(edp_ctx *ctx, edp_case c, double *mee_ev, int32_t n, int32_t reset);
+/* xt array `quantity` (EDP_XT_*) as out[t * n_grid + p] for time bin
+ * t = (s mod steps_per_cycle) / n_xt_bin: the mean over the steps s of the
+ * bin since the last reset (ion quantities over its ion steps; the mean
+ * energies as weight-averaged ratios).  n: capacity of out in doubles, at
+ * least n_xt * n_grid with n_xt = steps_per_cycle / n_xt_bin.  EDP_EINVAL if
+ * the case has no EDP_DIAG_XT.  Synchronous. */
+int edp_read_xt(edp_ctx *ctx, edp_case c, int32_t quantity, double *out, int64_t n);
+/* Steps and ion steps accumulated per xt bin (either pointer may be NULL). */
+int edp_read_xt_steps(edp_ctx *ctx, edp_case c, int64_t *steps, int64_t *ion_steps, int32_t n);
+/* IFEDF of the ions absorbed at the powered and grounded electrode, each
+ * normalised to sum_k F_k de_ifed = 1 over its n_ifed bins (energy M v^2 / 2
+ * of the half-step velocity that carried the ion out); counts (may be NULL)
+ * receives [2][n_ifed + 1] impacts, the last bin of each side holding those
+ * beyond the range.  n: length of f_pow and f_gnd (>= n_ifed). */
+int edp_read_ifed(edp_ctx *ctx, edp_case c, double *f_pow, double *f_gnd, int64_t *counts, int32_t n);
+/* Run report (EDP_INFO_* slots; n >= EDP_INFO_N): the criteria of section 2.2
+ * from the time-averaged density and mean energy (EDP_DIAG_DENSITY and
+ * EDP_DIAG_MEANE), the absorbed power (EDP_DIAG_XT) and the electrode ion
+ * fluxes and impact energies (EDP_DIAG_IFED); slots whose diagnostics are off
+ * read 0. */
+int edp_read_info(edp_ctx *ctx, edp_case c, double *out, int32_t n);
+/* Restart every diagnostic of the case (time sums, xt arrays, EEPF, IFEDF). */
+int edp_reset_diag(edp_ctx *ctx, edp_case c);
 /* Fixed-point densities (2^32 per superparticle) the next step will use:
  * electrons as they are now, ions as held since the last ion step. */
 int edp_read_deposit(edp_ctx *ctx, edp_case c, int64_t *cnt_e, int64_t *cnt_i, int32_t n);

@@ -27,7 +27,7 @@ hipError_t launch_head(const BatchDev* b, int ncase, int apply_blocks, int max_n
 hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
 hipError_t launch_particles(const BatchDev* b, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
                             hipEvent_t ev1);
-size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp);
+size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp);
 int particle_occupancy(int sp, size_t lds);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
 hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
@@ -126,7 +126,8 @@ namespace {
 
 struct Layout {
   size_t off_case, off_part[2][2][5], off_cq[2][2], off_qwg[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
-      off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[4], off_eepf, off_sort, total;
+      off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[7], off_eepf, off_xt, off_xtcnt, off_ifed, off_sort,
+      total;
   int64_t cap[2];
 };
 
@@ -148,9 +149,18 @@ int validate(const edp_case_desc* c) {
     return fail(EDP_EINVAL, "capacity above 2^31 slots");
   if ((c->flags & EDP_DIAG_EEPF) && (c->n_eepf < 1 || c->n_eepf > 4096 || !(c->de_eepf_ev > 0.0)))
     return fail(EDP_EINVAL, "bad EEPF binning (1..4096 bins)");
-  // particle-kernel LDS: E + deposit (16 B/node), with measurements 24 B/node more
-  if ((c->flags & (EDP_DIAG_EEPF | EDP_DIAG_CURRENT | EDP_DIAG_MEANE)) && c->n_grid > 1024)
-    return fail(EDP_EINVAL, "measurements support n_grid <= 1024");
+  if ((c->flags & EDP_DIAG_XT) &&
+      (c->n_xt_bin < 1 || c->steps_per_cycle % c->n_xt_bin != 0 || c->steps_per_cycle / c->n_xt_bin > 100000))
+    return fail(EDP_EINVAL, "n_xt_bin must divide steps_per_cycle (at most 100000 time bins)");
+  if ((c->flags & EDP_DIAG_IFED) && (c->n_ifed < 1 || c->n_ifed > 4096 || !(c->de_ifed_ev > 0.0)))
+    return fail(EDP_EINVAL, "bad IFEDF binning (1..4096 bins)");
+  // particle-kernel LDS: E + deposit (16 B/node), with measurements 24-32 B/node
+  // more and the EEPF / IFEDF histograms
+  const uint32_t meas = EDP_DIAG_EEPF | EDP_DIAG_CURRENT | EDP_DIAG_MEANE | EDP_DIAG_XT | EDP_DIAG_IFED;
+  if ((c->flags & meas) && c->n_grid > 1024) return fail(EDP_EINVAL, "measurements support n_grid <= 1024");
+  for (int sp = 0; sp < 2; ++sp)
+    if (particle_lds_bytes(c->n_grid, c->flags, c->n_eepf, c->n_ifed, sp) > 65536 - 1024)
+      return fail(EDP_EINVAL, "measurement histograms and grid exceed the workgroup's LDS");
   return EDP_OK;
 }
 
@@ -190,8 +200,12 @@ Layout layout(const edp_case_desc* c, int nbins) {
   L.off_ef = take(ng * 8);
   L.off_flux = take(ng * 8);
   for (int k = 0; k < 6; ++k) L.off_sum[k] = take(ng * 8);
-  for (int k = 0; k < 4; ++k) L.off_acc[k] = take(3 * ng * 8);
+  for (int k = 0; k < 7; ++k) L.off_acc[k] = take(3 * ng * 8);
   L.off_eepf = take((size_t)std::max(1, c->n_eepf) * 8);
+  const size_t n_xt = (c->flags & EDP_DIAG_XT) ? (size_t)(c->steps_per_cycle / c->n_xt_bin) : 0;
+  L.off_xt = take(std::max<size_t>(1, (size_t)kNumXt * n_xt * ng) * 8);
+  L.off_xtcnt = take(std::max<size_t>(1, 2 * n_xt) * 8);
+  L.off_ifed = take(2 * (size_t)((c->flags & EDP_DIAG_IFED) ? c->n_ifed + 1 : 1) * 8);
   L.off_sort = take((ng + 1) * 8);
   L.total = o;
   return L;
@@ -342,7 +356,7 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   int max_ng = 2;
   for (const Case* c : cs) {
     for (int sp = 0; sp < 2; ++sp)
-      lds[sp] = std::max(lds[sp], particle_lds_bytes(c->desc.n_grid, c->desc.flags, c->desc.n_eepf, sp));
+      lds[sp] = std::max(lds[sp], particle_lds_bytes(c->desc.n_grid, c->desc.flags, c->desc.n_eepf, c->desc.n_ifed, sp));
     max_ng = std::max(max_ng, (int)c->desc.n_grid);
   }
   std::vector<int> want[2], want_apply(nc);
@@ -547,8 +561,14 @@ int zero_diag(edp_ctx* ctx, Case* c) {
   const int64_t ng = c->desc.n_grid;
   for (double* p : {c->h.sum_ne, c->h.sum_ni, c->h.sum_je, c->h.sum_ji, c->h.sum_w, c->h.sum_e})
     HIPCHK(launch_zero(p, ng * 8, st));
-  for (int64_t* p : {c->h.acc_je, c->h.acc_ji, c->h.acc_w, c->h.acc_e}) HIPCHK(launch_zero(p, 3 * ng * 8, st));
+  for (int64_t* p : {c->h.acc_je, c->h.acc_ji, c->h.acc_w, c->h.acc_e, c->h.acc_wi, c->h.acc_ei, c->h.acc_iz})
+    HIPCHK(launch_zero(p, 3 * ng * 8, st));
   HIPCHK(launch_zero(c->h.eepf, (int64_t)std::max(1, c->desc.n_eepf) * 8, st));
+  if (c->h.n_xt > 0) {
+    HIPCHK(launch_zero(c->h.xt, (int64_t)kNumXt * c->h.n_xt * ng * 8, st));
+    HIPCHK(launch_zero(c->h.xt_cnt, (int64_t)2 * c->h.n_xt * 8, st));
+  }
+  if (c->h.n_ifed > 0) HIPCHK(launch_zero(c->h.ifed, (int64_t)2 * (c->h.n_ifed + 1) * 8, st));
   return EDP_OK;
 }
 
@@ -686,6 +706,11 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   h.nsub = D.ion_subcycle;
   h.n_eepf = D.n_eepf;
   h.flags = D.flags;
+  h.nt = D.steps_per_cycle;
+  h.n_xt_bin = (D.flags & EDP_DIAG_XT) ? D.n_xt_bin : 1;
+  h.n_xt = (D.flags & EDP_DIAG_XT) ? D.steps_per_cycle / D.n_xt_bin : 0;
+  h.n_ifed = (D.flags & EDP_DIAG_IFED) ? D.n_ifed : 0;
+  h.de_ifed = (D.flags & EDP_DIAG_IFED) ? D.de_ifed_ev : 1.0;
   h.L = D.gap_m;
   h.dx = h.L / (double)(ng - 1);
   h.inv_dx = 1.0 / h.dx;
@@ -746,9 +771,12 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   h.flux = (double*)(c->arena + L.off_flux);
   double** sums[6] = {&h.sum_ne, &h.sum_ni, &h.sum_je, &h.sum_ji, &h.sum_w, &h.sum_e};
   for (int k = 0; k < 6; ++k) *sums[k] = (double*)(c->arena + L.off_sum[k]);
-  int64_t** accs[4] = {&h.acc_je, &h.acc_ji, &h.acc_w, &h.acc_e};
-  for (int k = 0; k < 4; ++k) *accs[k] = (int64_t*)(c->arena + L.off_acc[k]);
+  int64_t** accs[7] = {&h.acc_je, &h.acc_ji, &h.acc_w, &h.acc_e, &h.acc_wi, &h.acc_ei, &h.acc_iz};
+  for (int k = 0; k < 7; ++k) *accs[k] = (int64_t*)(c->arena + L.off_acc[k]);
   h.eepf = (int64_t*)(c->arena + L.off_eepf);
+  h.xt = (double*)(c->arena + L.off_xt);
+  h.xt_cnt = (int64_t*)(c->arena + L.off_xtcnt);
+  h.ifed = (int64_t*)(c->arena + L.off_ifed);
   h.sort_cnt = (int64_t*)(c->arena + L.off_sort);
   // dynamic part
   h.step = 0;
@@ -981,6 +1009,208 @@ int edp_read_mean_energy(edp_ctx* ctx, edp_case id, double* mee, int32_t n, int3
     return r;
   for (int p = 0; p < ng; ++p) mee[p] = w[p] > 0.0 ? (e[p] / kDiagES) / (w[p] / kDiagWS) : 0.0;
   return reset ? reset_diag(ctx, c) : EDP_OK;
+}
+
+int edp_read_xt_steps(edp_ctx* ctx, edp_case id, int64_t* steps, int64_t* ion_steps, int32_t n) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c) return fail(EDP_EINVAL, "bad argument");
+  if (!(c->desc.flags & EDP_DIAG_XT)) return fail(EDP_EINVAL, "the xt arrays are off for this case");
+  const int nx = c->h.n_xt;
+  if (n < nx) return fail(EDP_EINVAL, "output shorter than the number of xt bins");
+  std::vector<int64_t> cnt(2 * (size_t)nx);
+  int r = read_grid(ctx, c, c->h.xt_cnt, cnt.data(), cnt.size() * 8);
+  if (r) return r;
+  for (int t = 0; t < nx; ++t) {
+    if (steps) steps[t] = cnt[t];
+    if (ion_steps) ion_steps[t] = cnt[nx + t];
+  }
+  return EDP_OK;
+}
+
+// Cell means of the xt sums, in the units of the time-averaged reads.
+int edp_read_xt(edp_ctx* ctx, edp_case id, int32_t q, double* out, int64_t n) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || !out || q < 0 || q >= EDP_XT_N) return fail(EDP_EINVAL, "bad argument");
+  if (!(c->desc.flags & EDP_DIAG_XT)) return fail(EDP_EINVAL, "the xt arrays are off for this case");
+  const int ng = c->desc.n_grid, nx = c->h.n_xt;
+  const size_t cells = (size_t)nx * ng;
+  if (n < (int64_t)cells) return fail(EDP_EINVAL, "output shorter than n_xt * n_grid");
+  HIPCHK(launch_fold(c->d, ctx->stream));
+  std::vector<int64_t> cnt(2 * (size_t)nx);
+  int r = read_grid(ctx, c, c->h.xt_cnt, cnt.data(), cnt.size() * 8);
+  if (r) return r;
+  auto plane = [&](int k, std::vector<double>& v) {
+    v.resize(cells);
+    return read_grid(ctx, c, c->h.xt + (size_t)k * cells, v.data(), cells * 8);
+  };
+  std::vector<double> a, b;
+  const double fw = c->h.factor_w;
+  switch (q) {
+    case EDP_XT_POT: r = plane(kXtFlux, a); break;
+    case EDP_XT_EFIELD: r = plane(kXtEf, a); break;
+    case EDP_XT_NE: r = plane(kXtNe, a); break;
+    case EDP_XT_NI: r = plane(kXtNi, a); break;
+    case EDP_XT_JE: r = plane(kXtJe, a); break;
+    case EDP_XT_JI: r = plane(kXtJi, a); break;
+    case EDP_XT_POWERE: r = plane(kXtPe, a); break;
+    case EDP_XT_POWERI: r = plane(kXtPi, a); break;
+    case EDP_XT_MEANEE: r = plane(kXtWe, a) ? 1 : plane(kXtEe, b); break;
+    case EDP_XT_MEANEI: r = plane(kXtWi, a) ? 1 : plane(kXtEi, b); break;
+    default: r = plane(kXtIz, a); break;
+  }
+  if (r) return r < 0 ? r : fail(EDP_EHIP, "xt read failed");
+  for (int t = 0; t < nx; ++t) {
+    const double ns = (double)cnt[t], ni = (double)cnt[nx + t];
+    const double* A = a.data() + (size_t)t * ng;
+    double* o = out + (size_t)t * ng;
+    if (q == EDP_XT_POT) {
+      // phi_p = V - sum_{q<p} F_q, summed over the bin's steps
+      double phi = A[ng - 1];
+      for (int p = 0; p < ng; ++p) {
+        o[p] = ns > 0 ? (p == ng - 1 ? 0.0 : phi / ns) : 0.0;
+        if (p < ng - 1) phi = phi - A[p];
+      }
+      continue;
+    }
+    for (int p = 0; p < ng; ++p) {
+      const double edge = (p == 0 || p == ng - 1) ? 2.0 : 1.0;
+      double v = 0.0;
+      switch (q) {
+        case EDP_XT_EFIELD:
+        case EDP_XT_NE:
+        case EDP_XT_NI: v = ns > 0 ? A[p] / ns : 0.0; break;
+        case EDP_XT_JE:
+        case EDP_XT_POWERE: v = ns > 0 ? edge * (-kECharge * fw) * (A[p] / kDiagJS) / ns : 0.0; break;
+        case EDP_XT_JI:
+        case EDP_XT_POWERI: v = ni > 0 ? edge * (kECharge * fw) * (A[p] / kDiagJS) / ni : 0.0; break;
+        case EDP_XT_MEANEE:
+        case EDP_XT_MEANEI: {
+          const double* B = b.data() + (size_t)t * ng;
+          v = A[p] > 0 ? (B[p] / kDiagES) / (A[p] / kDiagWS) : 0.0;
+          break;
+        }
+        default: v = ns > 0 ? edge * fw * (A[p] / kDiagIZS) / c->h.dt_e / ns : 0.0; break;
+      }
+      o[p] = v;
+    }
+  }
+  return EDP_OK;
+}
+
+int edp_read_ifed(edp_ctx* ctx, edp_case id, double* f_pow, double* f_gnd, int64_t* counts, int32_t n) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c) return fail(EDP_EINVAL, "bad argument");
+  if (!(c->desc.flags & EDP_DIAG_IFED)) return fail(EDP_EINVAL, "the IFEDF is off for this case");
+  const int nb = c->h.n_ifed;
+  if (n < nb) return fail(EDP_EINVAL, "output shorter than n_ifed");
+  std::vector<int64_t> h(2 * (size_t)(nb + 1));
+  int r = read_grid(ctx, c, c->h.ifed, h.data(), h.size() * 8);
+  if (r) return r;
+  double* f[2] = {f_pow, f_gnd};
+  for (int side = 0; side < 2; ++side) {
+    const int64_t* H = h.data() + (size_t)side * (nb + 1);
+    double tot = 0.0;
+    for (int k = 0; k < nb; ++k) tot += (double)H[k];
+    if (counts)
+      for (int k = 0; k <= nb; ++k) counts[(size_t)side * (nb + 1) + k] = H[k];
+    if (f[side])
+      for (int k = 0; k < nb; ++k) f[side][k] = tot > 0.0 ? (double)H[k] / (tot * c->h.de_ifed) : 0.0;
+  }
+  return EDP_OK;
+}
+
+int edp_read_info(edp_ctx* ctx, edp_case id, double* out, int32_t n) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || !out) return fail(EDP_EINVAL, "bad argument");
+  if (n < EDP_INFO_N) return fail(EDP_EINVAL, "output shorter than EDP_INFO_N");
+  const int ng = c->desc.n_grid;
+  const uint32_t fl = c->desc.flags;
+  HIPCHK(launch_fold(c->d, ctx->stream));
+  CaseDev t;
+  int r = read_dyn(ctx, c, t);
+  if (r) return r;
+  for (int k = 0; k < EDP_INFO_N; ++k) out[k] = 0.0;
+  std::vector<double> ne(ng), w(ng), e(ng);
+  if ((r = read_grid(ctx, c, c->h.sum_ne, ne.data(), ng * 8)) || (r = read_grid(ctx, c, c->h.sum_w, w.data(), ng * 8)) ||
+      (r = read_grid(ctx, c, c->h.sum_e, e.data(), ng * 8)))
+    return r;
+  const double nst = t.diag_steps > 0 ? (double)t.diag_steps : 1.0;
+  double ne_max = 0.0, sw = 0.0, se = 0.0;
+  for (int p = 0; p < ng; ++p) {
+    ne_max = std::max(ne_max, ne[p] / nst);
+    sw += w[p];
+    se += e[p];
+  }
+  const double mean_e = sw > 0.0 ? (se / kDiagES) / (sw / kDiagWS) : 0.0;
+  out[EDP_INFO_MEAN_E] = mean_e;
+  out[EDP_INFO_NE_MAX] = ne_max;
+  int bad = 0;
+  if (ne_max > 0.0 && mean_e > 0.0) {
+    // criterion 1 with T_e = 2/3 <eps>, criterion 2 at the peak density
+    const double te = 2.0 / 3.0 * mean_e;
+    const double lam = std::sqrt(kEps0 * te * kEvToJ / (ne_max * kECharge * kECharge));
+    const double wpe = std::sqrt(ne_max * kECharge * kECharge / (kEps0 * kEMass));
+    out[EDP_INFO_DEBYE] = lam;
+    out[EDP_INFO_DX_DEBYE] = c->h.dx / lam;
+    out[EDP_INFO_WPE_DT] = wpe * c->h.dt_e;
+    if (!(out[EDP_INFO_DX_DEBYE] < 1.0)) bad |= 1;
+    if (!(out[EDP_INFO_WPE_DT] < 2.0)) bad |= 2;
+  }
+  // criterion 3: the largest collision probabilities over the tables
+  out[EDP_INFO_PMAX_E] = c->h.p_null_e;
+  out[EDP_INFO_PMAX_I] = c->h.p_null_i;
+  if (!(c->h.p_null_e < 0.05) || !(c->h.p_null_i < 0.05)) bad |= 4;
+  // criterion 4: the electron energy that crosses one cell per step
+  const double vc = c->h.dx / c->h.dt_e;
+  out[EDP_INFO_CFL_EV] = 0.5 * kEMass * vc * vc / kEvToJ;
+  if (fl & EDP_DIAG_XT) {
+    const int nx = c->h.n_xt;
+    const size_t cells = (size_t)nx * ng;
+    std::vector<int64_t> cnt(2 * (size_t)nx);
+    std::vector<double> pe(cells), pi(cells);
+    if ((r = read_grid(ctx, c, c->h.xt_cnt, cnt.data(), cnt.size() * 8)) ||
+        (r = read_grid(ctx, c, c->h.xt + (size_t)kXtPe * cells, pe.data(), cells * 8)) ||
+        (r = read_grid(ctx, c, c->h.xt + (size_t)kXtPi * cells, pi.data(), cells * 8)))
+      return r;
+    // trapezoid mean over x: the edge weight 1/2 cancels the edge doubling
+    double spe = 0.0, spi = 0.0, ns = 0.0, ni = 0.0;
+    for (int k = 0; k < nx; ++k) {
+      ns += (double)cnt[k];
+      ni += (double)cnt[nx + k];
+      for (int p = 0; p < ng; ++p) {
+        spe += pe[(size_t)k * ng + p];
+        spi += pi[(size_t)k * ng + p];
+      }
+    }
+    const double fw = c->h.factor_w;
+    if (ns > 0) out[EDP_INFO_POWER_E] = (-kECharge * fw) * (spe / kDiagJS) / ((double)(ng - 1) * ns);
+    if (ni > 0) out[EDP_INFO_POWER_I] = (kECharge * fw) * (spi / kDiagJS) / ((double)(ng - 1) * ni);
+  }
+  if (fl & EDP_DIAG_IFED) {
+    const int nb = c->h.n_ifed;
+    std::vector<int64_t> h(2 * (size_t)(nb + 1));
+    if ((r = read_grid(ctx, c, c->h.ifed, h.data(), h.size() * 8))) return r;
+    const double tspan = (double)t.diag_steps * c->h.dt_e;
+    for (int side = 0; side < 2; ++side) {
+      const int64_t* H = h.data() + (size_t)side * (nb + 1);
+      double all = 0.0, in = 0.0, en = 0.0;
+      for (int k = 0; k <= nb; ++k) all += (double)H[k];
+      for (int k = 0; k < nb; ++k) {
+        in += (double)H[k];
+        en += (double)H[k] * ((double)k + 0.5) * c->h.de_ifed;
+      }
+      if (tspan > 0) out[side ? EDP_INFO_FLUX_I_GND : EDP_INFO_FLUX_I_POW] = all * c->desc.weight / (c->desc.area_m2 * tspan);
+      if (in > 0) out[side ? EDP_INFO_EI_GND : EDP_INFO_EI_POW] = en / in;
+    }
+  }
+  out[EDP_INFO_FAIL] = (double)bad;
+  return EDP_OK;
+}
+
+int edp_reset_diag(edp_ctx* ctx, edp_case id) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c) return fail(EDP_EINVAL, "bad argument");
+  return reset_diag(ctx, c);  // also clears the pending per-step sums
 }
 
 int edp_read_deposit(edp_ctx* ctx, edp_case id, int64_t* cnt_e, int64_t* cnt_i, int32_t n) {

@@ -28,6 +28,7 @@ constexpr double kTwo32 = 4294967296.0;
 constexpr double kDiagJS = 1024.0;     // c * vbar_x [m/s]
 constexpr double kDiagWS = 1048576.0;  // c
 constexpr double kDiagES = 1048576.0;  // c * energy [eV]
+constexpr double kDiagIZS = 4294967296.0;  // c * nu_ion dt_e
 
 // Particle kernels: workgroup size and the particle slots each workgroup owns.
 constexpr int kBlock = 256;
@@ -40,8 +41,16 @@ constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
 
 // Flags (same values as EDP_* in edupic.h).
 constexpr uint32_t kDiagDensity = 1u, kDiagEepf = 2u, kDiagCurrent = 4u, kDiagMeanE = 8u,
-                   kIonizLiteral = 16u, kNullCollision = 64u;
-constexpr uint32_t kDiagParticle = kDiagEepf | kDiagCurrent | kDiagMeanE;
+                   kIonizLiteral = 16u, kNullCollision = 64u, kDiagXT = 128u, kDiagIfed = 256u;
+constexpr uint32_t kDiagParticle = kDiagEepf | kDiagCurrent | kDiagMeanE | kDiagXT | kDiagIfed;
+
+// Sums of the xt arrays, each [n_xt][ng] (time bin major).  kXtFlux holds
+// sum F_q for q < ng-1 and sum V in slot ng-1, from which the potential is
+// rebuilt as phi_p = V - sum_{q<p} F_q.
+enum XtSum {
+  kXtFlux = 0, kXtEf, kXtNe, kXtNi, kXtJe, kXtJi, kXtPe, kXtPi, kXtWe, kXtEe, kXtWi, kXtEi, kXtIz,
+  kNumXt
+};
 
 // Dynamic counters (int64 slots of CaseDev::ctr).
 enum Ctr {
@@ -59,7 +68,12 @@ struct CaseDev {
   // ---- constants -------------------------------------------------------
   int32_t ng, nbins, nsub, n_eepf;
   uint32_t flags;
+  int32_t nt;         // steps per RF period
+  int32_t n_xt_bin;   // steps per xt time bin
+  int32_t n_xt;       // xt time bins (nt / n_xt_bin)
+  int32_t n_ifed;     // IFEDF bins per electrode (plus one beyond the range)
   int32_t pad0;
+  double de_ifed;
   double L, dx, inv_dx, dt_e, dt_i, factor_w, factor_e, factor_i;
   double sigma_a, de_cs, thr_exc, thr_ion, w_ion, de_eepf, x_lo, x_hi;
   double dens_scale;  // factor_w / 2^32
@@ -78,6 +92,10 @@ struct CaseDev {
   double* flux;         // F_q = phi_q - phi_{q+1}, q < ng-1; flux[ng-1] = V of the step
   double *sum_ne, *sum_ni, *sum_je, *sum_ji, *sum_w, *sum_e;  // [ng] time sums
   int64_t *acc_je, *acc_ji, *acc_w, *acc_e;                   // [3][ng] per step
+  int64_t *acc_wi, *acc_ei, *acc_iz;  // [3][ng] per step: ion weight, ion energy, c nu_ion dt
+  double* xt;                         // [kNumXt][n_xt][ng] sums
+  int64_t* xt_cnt;                    // [2][n_xt]: steps and ion steps per bin
+  int64_t* ifed;                      // [2][n_ifed + 1] impacts per energy bin
   int64_t *eepf;                                              // [n_eepf]
   int64_t *sort_cnt;                                          // [ng + 1] scratch
   // Collision queue of the last particle step, per species.  Wave w of chunk

@@ -227,6 +227,52 @@ __device__ __forceinline__ T block_exclusive_scan_t(T x, int64_t* scratch, T* to
 // ---------------------------------------------------------------------------
 constexpr int kWave = 64;
 
+// Fold the per-step particle sums of one node (ring slot `fold`, the step
+// before the one about to run) into the time sums and, with the xt arrays,
+// into time-bin row `row_prev`; the power density j E takes the field that
+// step used, still in efield[] (it is overwritten later in the same thread).
+__device__ __forceinline__ void fold_particle_sums(const EDP_CONST CaseDev* __restrict__ C, int p,
+                                                   int64_t fold, size_t row_prev, size_t plane) {
+  const uint32_t fl = C->flags;
+  EDP_GLOBAL int64_t* aJe = G(C->acc_je) + fold + p;
+  EDP_GLOBAL int64_t* aJi = G(C->acc_ji) + fold + p;
+  EDP_GLOBAL int64_t* aW = G(C->acc_w) + fold + p;
+  EDP_GLOBAL int64_t* aE = G(C->acc_e) + fold + p;
+  const int64_t je = *aJe, ji = *aJi, w = *aW, e = *aE;
+  if (fl & kDiagCurrent) {
+    G(C->sum_je)[p] += (double)je;
+    G(C->sum_ji)[p] += (double)ji;
+  }
+  if (fl & kDiagMeanE) {
+    G(C->sum_w)[p] += (double)w;
+    G(C->sum_e)[p] += (double)e;
+  }
+  *aJe = 0;
+  *aJi = 0;
+  *aW = 0;
+  *aE = 0;
+  if (fl & kDiagXT) {
+    EDP_GLOBAL int64_t* aWi = G(C->acc_wi) + fold + p;
+    EDP_GLOBAL int64_t* aEi = G(C->acc_ei) + fold + p;
+    EDP_GLOBAL int64_t* aIz = G(C->acc_iz) + fold + p;
+    const int64_t wi = *aWi, ei = *aEi, iz = *aIz;
+    const double eo = G(C->efield)[p];
+    EDP_GLOBAL double* __restrict__ X = G(C->xt) + row_prev + p;
+    X[kXtJe * plane] += (double)je;
+    X[kXtPe * plane] += (double)je * eo;
+    X[kXtJi * plane] += (double)ji;
+    X[kXtPi * plane] += (double)ji * eo;
+    X[kXtWe * plane] += (double)w;
+    X[kXtEe * plane] += (double)e;
+    X[kXtWi * plane] += (double)wi;
+    X[kXtEi * plane] += (double)ei;
+    X[kXtIz * plane] += (double)iz;
+    *aWi = 0;
+    *aEi = 0;
+    *aIz = 0;
+  }
+}
+
 template <int MODE>
 __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fsm) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
@@ -247,6 +293,14 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
   const int64_t fold = ((s + 2) % 3) * ng;  // per-step sums of step s-1
   const double scale = C->dens_scale;
   const double V = G(C->volt)[s % kVoltChunk];
+  // xt rows: this step's grid values go to its time bin, the particle sums
+  // of step s-1 to the bin of s-1
+  const bool xt = (fl & kDiagXT) != 0;
+  const int64_t nt = C->nt, nxb = C->n_xt_bin;
+  const size_t plane = (size_t)C->n_xt * (size_t)ng;
+  const size_t row = xt ? (size_t)((s % nt) / nxb) * (size_t)ng : 0;
+  const size_t row_prev = xt ? (size_t)(((s + nt - 1) % nt) / nxb) * (size_t)ng : 0;
+  EDP_GLOBAL double* __restrict__ X = G(C->xt);
   // every load of the thread's nodes before any store (one memory round trip)
   int64_t ce[kGridPerThread], ci[kGridPerThread];
 #pragma unroll
@@ -277,17 +331,10 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
     }
     zeroE[p] = 0;
     if (ion_step) zeroI[p] = 0;
-    if (fl & kDiagCurrent) {
-      G(C->sum_je)[p] += (double)G(C->acc_je)[fold + p];
-      G(C->acc_je)[fold + p] = 0;
-      G(C->sum_ji)[p] += (double)G(C->acc_ji)[fold + p];
-      G(C->acc_ji)[fold + p] = 0;
-    }
-    if (fl & kDiagMeanE) {
-      G(C->sum_w)[p] += (double)G(C->acc_w)[fold + p];
-      G(C->sum_e)[p] += (double)G(C->acc_e)[fold + p];
-      G(C->acc_w)[fold + p] = 0;
-      G(C->acc_e)[fold + p] = 0;
+    if (fl & (kDiagCurrent | kDiagMeanE | kDiagXT)) fold_particle_sums(C, p, fold, row_prev, plane);
+    if (xt) {
+      X[kXtNe * plane + row + p] += ne;
+      X[kXtNi * plane + row + p] += ni;
     }
   }
   __syncthreads();
@@ -320,6 +367,10 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       G(C->efield)[p] = e;
       G(C->phi)[p] = sPhi[p];
       G(C->rho)[p] = sRho[p];
+      if (xt) {
+        X[kXtEf * plane + row + p] += e;
+        X[kXtFlux * plane + row + p] += p < ng - 1 ? sPhi[p] - sPhi[p + 1] : V;
+      }
     }
   } else {
     // One wave does the two scans (no workgroup barriers in between): lane l
@@ -366,11 +417,20 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       else
         e = (sPhi[p - 1] + sPhi[p]) / (2.0 * dx);
       G(C->efield)[p] = e;
-      G(C->flux)[p] = p < ng - 1 ? sPhi[p] : V;  // last slot keeps V for phi on demand
+      const double f = p < ng - 1 ? sPhi[p] : V;  // last slot keeps V for phi on demand
+      G(C->flux)[p] = f;
       G(C->rho)[p] = sRho[p];
+      if (xt) {
+        X[kXtEf * plane + row + p] += e;
+        X[kXtFlux * plane + row + p] += f;
+      }
     }
   }
   if (threadIdx.x == 0) {
+    if (xt) {
+      G(C->xt_cnt)[row / ng] += 1;
+      if (ion_step) G(C->xt_cnt)[C->n_xt + row / ng] += 1;
+    }
     Cw->phi_valid = MODE == 1;
     Cw->pstep = s;  // the particle kernels of this step read it
   }
@@ -792,13 +852,18 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const int64_t kion = s / nsub;
   const uint32_t fl = C->flags;
   const bool pdiag = (fl & kDiagParticle) != 0;
+  const bool xt = (fl & kDiagXT) != 0;
   const int n_eepf = C->n_eepf;
+  const int n_ifed = C->n_ifed;
+  // histogram: the EEPF for electrons, the IFEDF of both electrodes for ions
+  const int n_hist = SP == 0 ? ((fl & kDiagEepf) ? n_eepf : 0) : ((fl & kDiagIfed) ? 2 * (n_ifed + 1) : 0);
   double* sE = psm;
   unsigned long long* sH = (unsigned long long*)(psm + ng);
   unsigned long long* sJ = sH + ng;
   unsigned long long* sW = sJ + ng;
   unsigned long long* sEn = sW + ng;
-  unsigned int* sF = (unsigned int*)(sEn + ng);
+  unsigned long long* sIz = sEn + ng;  // electrons with the xt arrays only
+  unsigned int* sF = (unsigned int*)(sIz + (SP == 0 && xt ? ng : 0));
   {
     double ev[kGridPerThread];
 #pragma unroll
@@ -818,10 +883,10 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       sJ[p] = 0;
       sW[p] = 0;
       sEn[p] = 0;
+      if (SP == 0 && xt) sIz[p] = 0;
     }
   }
-  if (SP == 0 && (fl & kDiagEepf))
-    for (int b = threadIdx.x; b < n_eepf; b += blockDim.x) sF[b] = 0;
+  for (int b = threadIdx.x; b < n_hist; b += blockDim.x) sF[b] = 0;
   __syncthreads();
 
   const int cur = C->cur[SP];
@@ -844,7 +909,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const int nbins = C->nbins;
   const uint64_t seed = C->seed;
   const uint32_t st = (uint32_t)s;
-  const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf;
+  const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf, de_ifed = C->de_ifed;
   const double sa = C->sigma_a;
   const bool null_coll = (fl & kNullCollision) != 0;
   const double n_gas = C->n_gas;
@@ -883,15 +948,30 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         vxn = vx + ex * factor;
       xn = x + vxn * dt;
       if (pdiag) {
-        // measurement at integer time: old position, mean of the half-step velocities
+        // measurement at integer time: old position, mean of the half-step
+        // velocities; the ionization rate as the expected n sigma_ion |v|
         const double vbar = 0.5 * (vx + vxn);
-        if (fl & kDiagCurrent) {
+        if (fl & (kDiagCurrent | kDiagXT)) {
           lds_add(&sJ[p], (long long)(c1 * vbar * kDiagJS));
           lds_add(&sJ[p + 1], (long long)(c2 * vbar * kDiagJS));
         }
-        if (SP == 0 && (fl & (kDiagMeanE | kDiagEepf))) {
+        if (SP == 1) {
+          if (xt) {
+            const double en = 0.5 * kArMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
+            lds_add(&sW[p], (long long)(c1 * kDiagWS));
+            lds_add(&sW[p + 1], (long long)(c2 * kDiagWS));
+            lds_add(&sEn[p], (long long)(c1 * en * kDiagES));
+            lds_add(&sEn[p + 1], (long long)(c2 * en * kDiagES));
+          }
+        } else if (fl & (kDiagMeanE | kDiagEepf | kDiagXT)) {
           const double en = 0.5 * kEMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
-          if (fl & kDiagMeanE) {
+          if (xt) {
+            const double vmag = sqrt(vbar * vbar + vy * vy + vz * vz);
+            const double pdt = (n_gas * sig2[energy_bin(en, de_cs, nbins)]) * vmag * dt;
+            lds_add(&sIz[p], (long long)(c1 * pdt * kDiagIZS));
+            lds_add(&sIz[p + 1], (long long)(c2 * pdt * kDiagIZS));
+          }
+          if (fl & (kDiagMeanE | kDiagXT)) {
             lds_add(&sW[p], (long long)(c1 * kDiagWS));
             lds_add(&sW[p + 1], (long long)(c2 * kDiagWS));
             lds_add(&sEn[p], (long long)(c1 * en * kDiagES));
@@ -903,11 +983,18 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
           }
         }
       }
-      // Step 5: absorbing electrodes.
+      // Step 5: absorbing electrodes; an absorbed ion adds its impact energy
+      // to its electrode's IFEDF (bin n_ifed: beyond the range).
       abs_pow = xn < 0.0;
       abs_gnd = xn > L_gap;
       if (abs_pow || abs_gnd) {
         live = false;
+        if (SP == 1 && (fl & kDiagIfed)) {
+          const double en = 0.5 * kArMass * (vxn * vxn + vy * vy + vz * vz) / kEvToJ;
+          const double t = en / de_ifed;
+          const int b = t < (double)n_ifed ? (int)t : n_ifed;
+          atomicAdd(&sF[(abs_gnd ? n_ifed + 1 : 0) + b], 1u);
+        }
       } else {
         // Step 6: collision test.  Direct: P = 1 - exp(-n sigma_tot(E) g dt),
         // collide iff R < P, process by sigma_k/sigma_tot.  Null collision:
@@ -1027,13 +1114,14 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     if (pdiag) {
       const int64_t off3 = (s % 3) * ng + q;
       if (sJ[q]) gl_add(&(SP == 0 ? C->acc_je : C->acc_ji)[off3], (long long)sJ[q]);
-      if (SP == 0 && sW[q]) gl_add(&C->acc_w[off3], (long long)sW[q]);
-      if (SP == 0 && sEn[q]) gl_add(&C->acc_e[off3], (long long)sEn[q]);
+      if (sW[q]) gl_add(&(SP == 0 ? C->acc_w : C->acc_wi)[off3], (long long)sW[q]);
+      if (sEn[q]) gl_add(&(SP == 0 ? C->acc_e : C->acc_ei)[off3], (long long)sEn[q]);
+      if (SP == 0 && xt && sIz[q]) gl_add(&C->acc_iz[off3], (long long)sIz[q]);
     }
   }
-  if (SP == 0 && (fl & kDiagEepf))
-    for (int b = threadIdx.x; b < n_eepf; b += blockDim.x)
-      if (sF[b]) gl_add(&C->eepf[b], (long long)sF[b]);
+  int64_t* hist = SP == 0 ? C->eepf : C->ifed;
+  for (int b = threadIdx.x; b < n_hist; b += blockDim.x)
+    if (sF[b]) gl_add(&hist[b], (long long)sF[b]);
 }
 
 // One launch per species covers the chunks of every case of the batch.
@@ -1201,25 +1289,16 @@ __global__ void k_sort_finish(CaseDev* __restrict__ C, int sp) {
 }
 
 // Fold the pending per-step diagnostic sums of the last completed step.
-__global__ void k_fold_diag(CaseDev* __restrict__ C) {
+__global__ void k_fold_diag(CaseDev* __restrict__ Cw) {
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int ng = C->ng;
-  const int64_t s = C->step;  // next step to run; the pending sums are those of s-1
+  const int64_t s = Cw->step;  // next step to run; the pending sums are those of s-1
   const int64_t off = ((s + 2) % 3) * ng;
-  const uint32_t fl = C->flags;
-  for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-    if (fl & kDiagCurrent) {
-      C->sum_je[p] += (double)C->acc_je[off + p];
-      C->acc_je[off + p] = 0;
-      C->sum_ji[p] += (double)C->acc_ji[off + p];
-      C->acc_ji[off + p] = 0;
-    }
-    if (fl & kDiagMeanE) {
-      C->sum_w[p] += (double)C->acc_w[off + p];
-      C->sum_e[p] += (double)C->acc_e[off + p];
-      C->acc_w[off + p] = 0;
-      C->acc_e[off + p] = 0;
-    }
-  }
+  if (!(C->flags & (kDiagCurrent | kDiagMeanE | kDiagXT))) return;
+  const int64_t nt = C->nt, nxb = C->n_xt_bin;
+  const size_t plane = (size_t)C->n_xt * (size_t)ng;
+  const size_t row_prev = (C->flags & kDiagXT) ? (size_t)(((s + nt - 1) % nt) / nxb) * (size_t)ng : 0;
+  for (int p = threadIdx.x; p < ng; p += blockDim.x) fold_particle_sums(C, p, off, row_prev, plane);
 }
 
 __global__ void k_zero(int64_t* __restrict__ p, int64_t n) {
@@ -1231,10 +1310,14 @@ __global__ void k_zero(int64_t* __restrict__ p, int64_t n) {
 // ---------------------------------------------------------------------------
 // Host-side launchers (same translation unit as the kernels).
 // ---------------------------------------------------------------------------
-size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int sp) {
+size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp) {
   size_t doubles = (size_t)2 * ng;
-  if (flags & kDiagParticle)
-    doubles += (size_t)3 * ng + (sp == 0 && (flags & kDiagEepf) ? (size_t)(n_eepf + 1) / 2 : 0);
+  if (flags & kDiagParticle) {
+    doubles += (size_t)3 * ng + (sp == 0 && (flags & kDiagXT) ? (size_t)ng : 0);
+    const size_t hist = sp == 0 ? ((flags & kDiagEepf) ? (size_t)n_eepf : 0)
+                                : ((flags & kDiagIfed) ? 2 * (size_t)(n_ifed + 1) : 0);
+    doubles += (hist + 1) / 2;
+  }
   return doubles * 8;
 }
 

@@ -17,7 +17,10 @@ LIB_PATH = os.path.join(HERE, "libedupic.so")
 
 EDP_OK, EDP_EINVAL, EDP_ECAPACITY, EDP_EUNSTABLE, EDP_EHIP, EDP_EARENA, EDP_ESTATE = 0, -1, -2, -3, -4, -5, -6
 DIAG_DENSITY, DIAG_EEPF, DIAG_CURRENT, DIAG_MEANE, IONIZ_ANGLE_LITERAL, ALLOW_UNSTABLE = 1, 2, 4, 8, 16, 32
-NULL_COLLISION = 64
+NULL_COLLISION, DIAG_XT, DIAG_IFED = 64, 128, 256
+XT_NAMES = ["pot", "efield", "ne", "ni", "je", "ji", "powere", "poweri", "meanee", "meanei", "ioniz"]
+INFO_NAMES = ["mean_e", "ne_max", "debye", "dx_debye", "wpe_dt", "pmax_e", "pmax_i", "cfl_ev",
+              "power_e", "power_i", "flux_i_pow", "flux_i_gnd", "ei_pow", "ei_gnd", "fail"]
 OPT_MODE, OPT_SORT_EVERY, OPT_PROFILE, OPT_GRAPH_STEPS, OPT_WG_PER_CU = 1, 2, 5, 6, 7
 OPT_POISSON = 8
 POISSON_FLUX, POISSON_THOMAS = 0, 1
@@ -25,7 +28,8 @@ MODE_PLAIN, MODE_GRAPH, MODE_PERSISTENT = 0, 1, 2
 ELECTRONS, IONS = 0, 1
 _FLAG_NAMES = {"density": DIAG_DENSITY, "eepf": DIAG_EEPF, "current": DIAG_CURRENT,
                "meane": DIAG_MEANE, "ioniz_literal": IONIZ_ANGLE_LITERAL,
-               "allow_unstable": ALLOW_UNSTABLE, "null_collision": NULL_COLLISION}
+               "allow_unstable": ALLOW_UNSTABLE, "null_collision": NULL_COLLISION,
+               "xt": DIAG_XT, "ifed": DIAG_IFED}
 
 
 class EdpError(RuntimeError):
@@ -42,7 +46,8 @@ class CaseDesc(C.Structure):
                 ("phase_rad", C.c_double * 4), ("weight", C.c_double), ("n_init_e", C.c_int64),
                 ("n_init_i", C.c_int64), ("te_init_ev", C.c_double), ("ti_init_k", C.c_double),
                 ("cap_e", C.c_int64), ("cap_i", C.c_int64), ("seed", C.c_uint64),
-                ("flags", C.c_uint32), ("n_eepf", C.c_int32), ("de_eepf_ev", C.c_double)]
+                ("flags", C.c_uint32), ("n_eepf", C.c_int32), ("de_eepf_ev", C.c_double),
+                ("n_xt_bin", C.c_int32), ("n_ifed", C.c_int32), ("de_ifed_ev", C.c_double)]
 
 
 class Xsec(C.Structure):
@@ -67,7 +72,8 @@ EXPORTS = ["edp_create", "edp_destroy", "edp_set_xsec", "edp_case_bytes", "edp_c
            "edp_case_destroy", "edp_advance", "edp_advance_steps", "edp_sync", "edp_read_counts",
            "edp_read_density", "edp_read_eepf", "edp_read_currents", "edp_read_mean_energy",
            "edp_read_deposit", "edp_read_fields", "edp_get_state", "edp_set_state",
-           "edp_set_option", "edp_read_profile", "edp_last_error"]
+           "edp_set_option", "edp_read_profile", "edp_last_error", "edp_read_xt",
+           "edp_read_xt_steps", "edp_read_ifed", "edp_read_info", "edp_reset_diag"]
 
 _lib = None
 
@@ -108,6 +114,11 @@ def load() -> C.CDLL:
         "edp_set_option": (C.c_int, [P, I32, I64]),
         "edp_read_profile": (C.c_int, [P, D, I64P]),
         "edp_last_error": (C.c_char_p, []),
+        "edp_read_xt": (C.c_int, [P, I64, I32, D, I64]),
+        "edp_read_xt_steps": (C.c_int, [P, I64, I64P, I64P, I32]),
+        "edp_read_ifed": (C.c_int, [P, I64, D, D, I64P, I32]),
+        "edp_read_info": (C.c_int, [P, I64, D, I32]),
+        "edp_reset_diag": (C.c_int, [P, I64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -154,6 +165,8 @@ def make_desc(c: Dict) -> CaseDesc:
         fl |= _FLAG_NAMES[name]
     d.flags = fl
     d.n_eepf, d.de_eepf_ev = c["n_eepf"], c["de_eepf_ev"]
+    d.n_xt_bin = c.get("n_xt_bin", 20)
+    d.n_ifed, d.de_ifed_ev = c.get("n_ifed", 200), c.get("de_ifed_ev", 1.0)
     return d
 
 
@@ -279,6 +292,39 @@ class Case:
         m = np.zeros(self.ng)
         _chk(load().edp_read_mean_energy(self.ctx.h, self.id, _d(m), self.ng, int(reset)))
         return m
+
+    @property
+    def n_xt(self) -> int:
+        if "xt" not in self.case.get("flags", []):
+            return 0
+        return self.case["steps_per_cycle"] // self.case.get("n_xt_bin", 20)
+
+    def xt(self, name: str) -> np.ndarray:
+        """xt array `name` (one of XT_NAMES) as [n_xt, n_grid]."""
+        out = np.zeros((self.n_xt, self.ng))
+        _chk(load().edp_read_xt(self.ctx.h, self.id, XT_NAMES.index(name), _d(out), out.size))
+        return out
+
+    def xt_steps(self):
+        a, b = np.zeros(self.n_xt, dtype=np.int64), np.zeros(self.n_xt, dtype=np.int64)
+        _chk(load().edp_read_xt_steps(self.ctx.h, self.id, _i(a), _i(b), self.n_xt))
+        return a, b
+
+    def ifed(self):
+        """(F_powered, F_grounded, counts[2, n_ifed + 1])."""
+        nb = self.case.get("n_ifed", 200)
+        fp, fg = np.zeros(nb), np.zeros(nb)
+        c = np.zeros(2 * (nb + 1), dtype=np.int64)
+        _chk(load().edp_read_ifed(self.ctx.h, self.id, _d(fp), _d(fg), _i(c), nb))
+        return fp, fg, c.reshape(2, nb + 1)
+
+    def info(self) -> Dict[str, float]:
+        out = np.zeros(len(INFO_NAMES))
+        _chk(load().edp_read_info(self.ctx.h, self.id, _d(out), out.size))
+        return dict(zip(INFO_NAMES, (float(v) for v in out)))
+
+    def reset_diag(self):
+        _chk(load().edp_reset_diag(self.ctx.h, self.id))
 
     def deposit(self):
         a, b = np.zeros(self.ng, dtype=np.int64), np.zeros(self.ng, dtype=np.int64)
