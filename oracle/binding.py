@@ -25,7 +25,7 @@ XT_NAMES = ["pot", "efield", "ne", "ni", "je", "ji", "powere", "poweri", "meanee
 INFO_NAMES = ["mean_e", "ne_max", "debye", "dx_debye", "wpe_dt", "pmax_e", "pmax_i", "cfl_ev",
               "power_e", "power_i", "flux_i_pow", "flux_i_gnd", "ei_pow", "ei_gnd", "fail"]
 COUNTER_NAMES = ["abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i",
-                 "ioniz", "anomaly"]
+                 "ioniz", "anomaly", "see", "refl"]
 
 
 class OrcCase(C.Structure):
@@ -37,7 +37,8 @@ class OrcCase(C.Structure):
                 ("n_init_e", C.c_int64), ("n_init_i", C.c_int64), ("te_init_ev", C.c_double),
                 ("ti_init_k", C.c_double), ("seed", C.c_uint64), ("flags", C.c_uint32),
                 ("n_eepf", C.c_int32), ("de_eepf_ev", C.c_double),
-                ("n_xt_bin", C.c_int32), ("n_ifed", C.c_int32), ("de_ifed_ev", C.c_double)]
+                ("n_xt_bin", C.c_int32), ("n_ifed", C.c_int32), ("de_ifed_ev", C.c_double),
+                ("gamma_see", C.c_double * 2), ("eta_refl", C.c_double * 2), ("see_te_ev", C.c_double)]
 
 
 class OrcXsec(C.Structure):
@@ -152,6 +153,9 @@ def make_case(c: Dict) -> OrcCase:
     d.n_eepf, d.de_eepf_ev = c["n_eepf"], c["de_eepf_ev"]
     d.n_xt_bin = c.get("n_xt_bin", 20)
     d.n_ifed, d.de_ifed_ev = c.get("n_ifed", 200), c.get("de_ifed_ev", 1.0)
+    d.gamma_see[0], d.gamma_see[1] = c.get("gamma_see", (0.0, 0.0))
+    d.eta_refl[0], d.eta_refl[1] = c.get("eta_refl", (0.0, 0.0))
+    d.see_te_ev = c.get("see_te_ev", 1.0)
     return d
 
 
@@ -208,7 +212,7 @@ class Oracle:
         return lib().orc_step_index(self.h)
 
     def counts(self) -> Dict[str, int]:
-        a = np.zeros(8, dtype=np.int64)
+        a = np.zeros(len(COUNTER_NAMES), dtype=np.int64)
         lib().orc_counts(self.h, iptr(a))
         return dict(zip(COUNTER_NAMES, (int(v) for v in a)))
 

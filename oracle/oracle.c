@@ -83,6 +83,7 @@ struct orc_sim {
   double *x_we, *x_ee, *x_wi, *x_ei, *x_iz; /* sums of acc                       */
   int64_t *x_steps, *x_ion_steps;           /* [n_xt] steps per bin              */
   int64_t *ifed;                            /* [2][n_ifed + 1]                   */
+  parts see_new; /* electrons emitted in this step, added after step 6 */
 };
 
 /* ---------------------------------------------------------------------------
@@ -495,6 +496,12 @@ orc_sim *orc_new(const orc_case *c, const orc_xsec *xs) {
     return set_err("N_BIN must divide the steps per cycle"), NULL;
   if ((c->flags & ORC_DIAG_IFED) && (c->n_ifed < 1 || !(c->de_ifed_ev > 0.0)))
     return set_err("bad IFEDF binning"), NULL;
+  for (int k = 0; k < 2; ++k)
+    if (!(c->gamma_see[k] >= 0.0 && c->gamma_see[k] <= 1.0) ||
+        !(c->eta_refl[k] >= 0.0 && c->eta_refl[k] <= 1.0))
+      return set_err("surface probabilities must be in [0, 1]"), NULL;
+  if ((c->gamma_see[0] > 0.0 || c->gamma_see[1] > 0.0) && !(c->see_te_ev > 0.0))
+    return set_err("secondary electron temperature must be > 0"), NULL;
   orc_sim *s = calloc(1, sizeof *s);
   if (!s) return set_err("out of memory"), NULL;
   s->c = *c;
@@ -568,6 +575,7 @@ void orc_free(orc_sim *s) {
   if (!s) return;
   parts_free(&s->e);
   parts_free(&s->i);
+  parts_free(&s->see_new);
   double *dbl[] = {s->sig_el, s->sig_exc, s->sig_ion, s->sig_iso, s->sig_back, s->nsig_e,
                    s->nsig_i, s->ne, s->ni, s->rho, s->phi, s->efield, s->sum_ne, s->sum_ni,
                    s->sum_je, s->sum_ji, s->sum_w, s->sum_e, s->x_pot, s->x_ef, s->x_ne,
@@ -726,15 +734,71 @@ static void push(orc_sim *s, parts *p, int is_ion) {
   }
 }
 
+/* Surface processes of section 5, drawn from purpose 3 of the particle's
+ * counter at this step.  Electron reflection: with probability eta of the
+ * electrode (R < eta, call 0), the electron is reflected specularly: the
+ * position is mirrored in the electrode and v_x reversed, so the energy is
+ * kept (reading: elastic means specular).  A mirror image outside the gap
+ * (a flight longer than the gap) is absorbed.  Returns 1 if reflected. */
+static int reflect_electron(orc_sim *s, parts *p, int64_t k, int side) {
+  const double eta = s->c.eta_refl[side];
+  if (!(eta > 0.0)) return 0;
+  double r[2];
+  orc_uniform2(s->c.seed, p->uid[k], (uint32_t)s->step, 0u, 3u, 0u, r);
+  if (!(r[0] < eta)) return 0;
+  const double xm = side == 0 ? -p->x[k] : 2.0 * s->L - p->x[k];
+  if (!(xm >= 0.0 && xm <= s->L)) return 0;
+  p->x[k] = xm;
+  p->vx[k] = -p->vx[k];
+  s->counts[ORC_C_REFL]++;
+  return 1;
+}
+
+/* Ion-induced secondary emission: an ion absorbed at electrode `side` emits
+ * an electron if R < gamma (call 0).  Reading: the electron starts on the
+ * electrode surface with the velocity of a thermal flux leaving it at
+ * temperature T_see: the normal component is Rayleigh distributed,
+ * sigma sqrt(-2 ln(1 - u_a)) into the gap, the two tangential ones normal
+ * (Box-Muller of u_b, u_c), sigma = sqrt(k T_see / m); calls 1 -> (u_a, u_b),
+ * 2 -> u_c.  Its identity is the child of the ion with kind 3.  It is added
+ * after the collisions of this step, like the other newborns. */
+static void emit_secondary(orc_sim *s, const parts *p, int64_t k, int side) {
+  const double gamma = s->c.gamma_see[side];
+  if (!(gamma > 0.0)) return;
+  const uint64_t uid = p->uid[k];
+  const uint32_t st = (uint32_t)s->step;
+  double r[2];
+  orc_uniform2(s->c.seed, uid, st, 1u, 3u, 0u, r);
+  if (!(r[0] < gamma)) return;
+  double a[2], b[2];
+  orc_uniform2(s->c.seed, uid, st, 1u, 3u, 1u, a);
+  orc_uniform2(s->c.seed, uid, st, 1u, 3u, 2u, b);
+  const double sig = sqrt(s->c.see_te_ev * EV_TO_J / E_MASS);
+  const double vn = sig * sqrt(-2.0 * log(1.0 - a[0]));
+  const double vt = sig * sqrt(-2.0 * log(1.0 - a[1]));
+  const double vy = vt * cos(TWO_PI_D * b[0]);
+  const double vz = vt * sin(TWO_PI_D * b[0]);
+  if (side == 0)
+    parts_append(&s->see_new, 0.0, vn, vy, vz, orc_child_uid(uid, s->step, 3));
+  else
+    parts_append(&s->see_new, s->L, -vn, vy, vz, orc_child_uid(uid, s->step, 3));
+  s->counts[ORC_C_SEE]++;
+}
+
 /* Step 5: absorbing electrodes; removal by moving the last particle into the
  * hole (Algorithm 5).  x < 0: powered electrode, x > L: grounded.  An
  * absorbed ion adds its impact energy M v^2 / 2, from the half-step velocity
- * that carried it out, to its electrode's IFEDF (Algorithm 5, ions). */
+ * that carried it out, to its electrode's IFEDF (Algorithm 5, ions), and may
+ * emit a secondary electron; an electron may be reflected instead. */
 static void walls(orc_sim *s, parts *p, int is_ion) {
   const int ifed = is_ion && (s->c.flags & ORC_DIAG_IFED);
   int64_t k = 0;
   while (k < p->n) {
     const double x = p->x[k];
+    if (!is_ion && (x < 0.0 || x > s->L) && reflect_electron(s, p, k, x < 0.0 ? 0 : 1)) {
+      ++k;
+      continue;
+    }
     int out = 0;
     if (x < 0.0) {
       s->counts[is_ion ? ORC_C_ABS_I_POW : ORC_C_ABS_E_POW]++;
@@ -744,6 +808,7 @@ static void walls(orc_sim *s, parts *p, int is_ion) {
       s->counts[is_ion ? ORC_C_ABS_I_GND : ORC_C_ABS_E_GND]++;
       out = 2;
     }
+    if (out && is_ion) emit_secondary(s, p, k, out - 1);
     if (out && ifed) {
       const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
       const double en = 0.5 * AR_MASS * (vx * vx + vy * vy + vz * vz) / EV_TO_J;
@@ -984,6 +1049,11 @@ static void one_step(orc_sim *s) {
       else
         ion_mcc(s, k);
     }
+  /* secondary electrons of this step's ion impacts join from the next step */
+  for (int64_t k = 0; k < s->see_new.n; ++k)
+    parts_append(&s->e, s->see_new.x[k], s->see_new.vx[k], s->see_new.vy[k], s->see_new.vz[k],
+                 s->see_new.uid[k]);
+  s->see_new.n = 0;
   /* fold this step's fixed-point diagnostic sums into the time sums and
    * the xt arrays; the power density is j E at the nodes with the field of
    * this step (section 3.5) */

@@ -65,7 +65,10 @@ enum {
 /* Counter slots returned by orc_counts(). */
 enum {
   ORC_C_ABS_E_POW = 0, ORC_C_ABS_E_GND, ORC_C_ABS_I_POW, ORC_C_ABS_I_GND,
-  ORC_C_COLL_E, ORC_C_COLL_I, ORC_C_IONIZ, ORC_C_ANOMALY, ORC_C_N
+  ORC_C_COLL_E, ORC_C_COLL_I, ORC_C_IONIZ, ORC_C_ANOMALY,
+  ORC_C_SEE,  /* electrons emitted by ion impact                         */
+  ORC_C_REFL, /* electrons reflected at an electrode                      */
+  ORC_C_N
 };
 
 /* One discharge case (Table 1 constants, made runtime values). */
@@ -91,6 +94,11 @@ typedef struct {
   int32_t n_xt_bin;    /* N_BIN: steps per xt time bin (divides N_t)       */
   int32_t n_ifed;      /* IFEDF bins                                        */
   double de_ifed_ev;   /* IFEDF bin width [eV]                             */
+  /* Surface processes (section 5), index 0 the powered electrode (x = 0),
+   * 1 the grounded one (x = L); zero turns a process off. */
+  double gamma_see[2]; /* ion-induced secondary electron yield, 0..1        */
+  double eta_refl[2];  /* elastic electron reflection probability, 0..1     */
+  double see_te_ev;    /* temperature of the emitted electrons [eV]        */
 } orc_case;
 
 /* Tabulated cross sections (section 3.2): bin i <-> energy i*de_ev. */

@@ -79,6 +79,8 @@ def base_case(**kw) -> Dict:
         "flags": [], "n_eepf": 2000, "de_eepf_ev": 0.05,
         # measurement mode: N_BIN steps per xt bin, IFEDF 200 x 1 eV (section 4.1)
         "n_xt_bin": 20, "n_ifed": 200, "de_ifed_ev": 1.0,
+        # surface processes (section 5), (powered, grounded); off by default
+        "gamma_see": (0.0, 0.0), "eta_refl": (0.0, 0.0), "see_te_ev": 1.0,
     }
     c.update(kw)
     return c
