@@ -154,6 +154,18 @@ typedef struct {
   int32_t n_xt_bin;        /* N_BIN: steps per xt time bin, divides steps_per_cycle */
   int32_t n_ifed;          /* IFEDF bins per electrode, 1..4096 (200)          */
   double de_ifed_ev;       /* IFEDF bin width [eV] (1)                         */
+  /* Surface processes suggested in section 5, [0] the powered electrode
+   * (x = 0), [1] the grounded one (x = L); 0 turns a process off.  An
+   * electron leaving the gap is reflected specularly (x mirrored in the
+   * electrode, v_x reversed) with probability eta_refl unless the mirror
+   * image lies outside the gap; an absorbed ion emits an electron with
+   * probability gamma_see, placed on the electrode with the velocity of a
+   * thermal flux at see_te_ev (Rayleigh normal component into the gap,
+   * normal tangential ones), taking part from the next step. */
+  double gamma_see[2];     /* ion-induced secondary electron yield, 0..1       */
+  double eta_refl[2];      /* elastic electron reflection probability, 0..1    */
+  double see_te_ev;        /* temperature of the emitted electrons [eV], > 0
+                              when a gamma_see is                            */
 } edp_case_desc;
 
 /* Cross sections tabulated at energies i * de_ev, i = 0..n_bins-1
@@ -180,6 +192,8 @@ typedef struct {
   int64_t dropped;           /* births lost to a full capacity               */
   int64_t psteps_e;          /* electron pushes done (sum over steps of n_e) */
   int64_t psteps_i;          /* ion pushes done (sum over ion steps of n_i)  */
+  int64_t see;               /* secondary electrons emitted by ion impact    */
+  int64_t refl;              /* electrons reflected at an electrode          */
 } edp_counts;
 
 /* Create a context on `device` issuing work on `hip_stream` (a hipStream_t,

@@ -154,6 +154,11 @@ int validate(const edp_case_desc* c) {
     return fail(EDP_EINVAL, "n_xt_bin must divide steps_per_cycle (at most 100000 time bins)");
   if ((c->flags & EDP_DIAG_IFED) && (c->n_ifed < 1 || c->n_ifed > 4096 || !(c->de_ifed_ev > 0.0)))
     return fail(EDP_EINVAL, "bad IFEDF binning (1..4096 bins)");
+  for (int k = 0; k < 2; ++k)
+    if (!(c->gamma_see[k] >= 0.0 && c->gamma_see[k] <= 1.0) || !(c->eta_refl[k] >= 0.0 && c->eta_refl[k] <= 1.0))
+      return fail(EDP_EINVAL, "surface probabilities must be in [0, 1]");
+  if ((c->gamma_see[0] > 0.0 || c->gamma_see[1] > 0.0) && !(c->see_te_ev > 0.0))
+    return fail(EDP_EINVAL, "see_te_ev must be > 0 with secondary emission");
   // particle-kernel LDS: E + deposit (16 B/node), with measurements 24-32 B/node
   // more and the EEPF / IFEDF histograms
   const uint32_t meas = EDP_DIAG_EEPF | EDP_DIAG_CURRENT | EDP_DIAG_MEANE | EDP_DIAG_XT | EDP_DIAG_IFED;
@@ -735,6 +740,13 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   h.x_hi = 0.55 * h.L;
   h.dens_scale = h.factor_w / kTwo32;
   h.kpois = h.dx * h.dx / kEps0;
+  for (int k = 0; k < 2; ++k) {
+    h.gamma_see[k] = D.gamma_see[k];
+    h.eta_refl[k] = D.eta_refl[k];
+  }
+  h.see_on = D.gamma_see[0] > 0.0 || D.gamma_see[1] > 0.0;
+  h.refl_on = D.eta_refl[0] > 0.0 || D.eta_refl[1] > 0.0;
+  h.see_sigma = h.see_on ? std::sqrt(D.see_te_ev * kEvToJ / kEMass) : 0.0;
   h.seed = D.seed;
   for (int sp = 0; sp < 2; ++sp) {
     h.sp[sp].cap = L.cap[sp];
@@ -929,6 +941,8 @@ int edp_read_counts(edp_ctx* ctx, edp_case id, edp_counts* out) {
   out->dropped = t.ctr[kDropped];
   out->psteps_e = t.ctr[kPstepE];
   out->psteps_i = t.ctr[kPstepI];
+  out->see = t.ctr[kSee];
+  out->refl = t.ctr[kRefl];
   return EDP_OK;
 }
 

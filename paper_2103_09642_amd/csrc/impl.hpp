@@ -55,7 +55,7 @@ enum XtSum {
 // Dynamic counters (int64 slots of CaseDev::ctr).
 enum Ctr {
   kAbsEPow = 0, kAbsEGnd, kAbsIPow, kAbsIGnd, kCollE, kCollI, kIoniz, kAnomaly, kDropped,
-  kLiveE, kLiveI, kPstepE, kPstepI, kNumCtr
+  kLiveE, kLiveI, kPstepE, kPstepI, kSee, kRefl, kNumCtr
 };
 
 struct SpeciesDev {
@@ -81,6 +81,11 @@ struct CaseDev {
   double nu_star_e, nu_star_i;      // null-collision maximum frequencies
   double p_null_e, p_null_i;        // 1 - exp(-nu* dt) per species
   double kpois;       // dx*dx/eps0
+  // surface processes, [0] powered electrode (x = 0), [1] grounded (x = L)
+  double gamma_see[2];  // ion-induced secondary electron yield
+  double eta_refl[2];   // elastic electron reflection probability
+  double see_sigma;     // sqrt(k T_see / m_e) of the emitted electrons
+  int32_t see_on, refl_on;
   uint64_t seed;
   SpeciesDev sp[2];
   const double *nsig_e, *nsig_i, *sig_el, *sig_exc, *sig_ion, *sig_iso, *sig_back;

@@ -592,14 +592,38 @@ __device__ __forceinline__ void ion_scatter(const EDP_CONST CaseDev* __restrict_
   P.ivz[i] = oz;
 }
 
+// Secondary electron of queued ion i, absorbed at electrode `side` (0 at
+// x = 0, 1 at x = L): it starts on the surface with the velocity of a thermal
+// flux at T_see -- a Rayleigh normal component into the gap and two normal
+// tangential ones (Box-Muller) -- from purpose 3 of the ion's counter; its
+// identity is the ion's child of kind 3.  be < 0: dropped at capacity.
+__device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
+                                         int side, int64_t be, int64_t s) {
+  if (be < 0) return;
+  const uint64_t uid = P.iuid[i];
+  const uint32_t st = (uint32_t)s;
+  double a0, a1, b0, b1;
+  uniform2(C->seed, uid, st, tag(1, 3, 1), a0, a1);
+  uniform2(C->seed, uid, st, tag(1, 3, 2), b0, b1);
+  const double sig = C->see_sigma;
+  const double vn = sig * sqrt(-2.0 * log(1.0 - a0));
+  const double vt = sig * sqrt(-2.0 * log(1.0 - a1));
+  P.ex[be] = side == 0 ? 0.0 : C->L;
+  P.evx[be] = side == 0 ? vn : -vn;
+  P.evy[be] = vt * cos(kTwoPi * b0);
+  P.evz[be] = vt * sin(kTwoPi * b0);
+  P.euid[be] = child_uid(uid, s, 3);
+}
+
 // Apply the pending collision queue.  Workgroup blk of nblk takes a
 // contiguous range of chunks of each species; a group of 8 lanes takes one
 // chunk: its four wave records and the first two events of each wave's part
 // of the queue are loaded together, lane l working through the events of
 // wave l/2.  Newborns of chunk c go to q_base + (ionizations of chunks < c)
 // + (ionizations of lower waves of c) + rank, so the ionization counts
-// before the range are summed with the same loads.  No atomics: every slot
-// follows from the records alone.
+// before the range are summed with the same loads.  Secondary electrons of
+// ion impacts are births of the ion queue and follow every electron birth of
+// the step.  No atomics: every slot follows from the records alone.
 constexpr int kApplyLanes = 8;
 typedef int rec4 __attribute__((ext_vector_type(4)));  // the four wave records of a chunk
 constexpr int kApplyChunks = kBlock / kApplyLanes;  // chunks per round of a workgroup
@@ -619,6 +643,7 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
   const int wv = l / 2, jj = l % 2;  // this lane's wave part of the chunk and first entry
   const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
   const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
+  const bool see_on = C->see_on != 0;
   for (int sp = 0; sp < 2; ++sp) {
     const int64_t nb = C->q_nblk[sp];
     const EDP_GLOBAL rec4* __restrict__ rec = (const EDP_GLOBAL rec4*)G(C->cq_rec[sp]);
@@ -633,20 +658,28 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
       const int64_t e0 = c * kChunk + wv * 64;
       const int code0 = valid ? ent[e0 + jj] : 0;  // in bounds: each wave part is 64 long
       const int qw = rec_q(rec_pick(r4, wv));
-      if (sp == 0) {
-        // high word: ionizations of chunks < c0 (first round), low word: this
-        // round's ionizations of lower groups
+      int64_t zbase = 0;  // births (of this species' queue) before this lane's wave
+      if (sp == 0 || see_on) {
+        // high word: births of chunks < c0 (first round), low word: this
+        // round's births of lower groups
         int64_t zpre = 0;
         if (cb == c0) {
           // whole particle workgroups before c0, then the chunks of the one holding c0
-          const int64_t per = C->q_per[0];
+          const int64_t per = C->q_per[sp];
           const int64_t jw = c0 / per;
-          const EDP_GLOBAL rec4* wg = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
+          const EDP_GLOBAL rec4* wg = (const EDP_GLOBAL rec4*)G(C->q_wg[sp]);
 #pragma unroll 4
           for (int64_t k = threadIdx.x; k < jw; k += blockDim.x) zpre += wg[k].y;
           for (int64_t k = jw * per + threadIdx.x; k < c0; k += blockDim.x) {
             const rec4 t = rec[k];
             zpre += rec_z(t.x) + rec_z(t.y) + rec_z(t.z) + rec_z(t.w);
+          }
+          if (sp == 1) {
+            // secondaries come after all of the step's ionization births
+            const int64_t pe = C->q_per[0];
+            const int64_t nwe = pe > 0 ? (C->q_nblk[0] + pe - 1) / pe : 0;
+            const EDP_GLOBAL rec4* wge = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
+            for (int64_t k = threadIdx.x; k < nwe; k += blockDim.x) zpre += wge[k].y;
           }
         }
         const int zc = rec_z(r4.x) + rec_z(r4.y) + rec_z(r4.z) + rec_z(r4.w);
@@ -657,8 +690,10 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
         if (cb == c0) zrun = tot >> 32;
         // ionizations of the lower waves of this chunk
         const int zw = (wv > 0 ? rec_z(r4.x) : 0) + (wv > 1 ? rec_z(r4.y) : 0) + (wv > 2 ? rec_z(r4.z) : 0);
-        const int64_t zbase = zrun + low + zw;
+        zbase = zrun + low + zw;
         zrun += tot & 0xFFFFFFFFLL;
+      }
+      if (sp == 0) {
         for (int k = jj; k < qw; k += 2) {
           const int code = k == jj ? code0 : ent[e0 + k];
           const int64_t i = c * kChunk + (code & 1023);
@@ -674,7 +709,14 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
       } else {
         for (int k = jj; k < qw; k += 2) {
           const int code = k == jj ? code0 : ent[e0 + k];
-          ion_scatter(C, P, c * kChunk + (code & 1023), (code >> 10) & 3, s);
+          const int64_t i = c * kChunk + (code & 1023);
+          const int proc = (code >> 10) & 3;
+          if (proc < 2) {
+            ion_scatter(C, P, i, proc, s);
+          } else {  // 2, 3: absorbed at x = 0 / x = L with an emitted electron
+            const int64_t kk = zbase + (code >> 12);
+            see_emit(C, P, i, proc - 2, base_e + kk < cap_e ? base_e + kk : -1, s);
+          }
         }
       }
     }
@@ -683,8 +725,9 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
 
 // Add the totals of the last particle step to the counters and place its
 // newborns (one workgroup): the particle workgroups' records give collisions,
-// ionizations and absorptions; the newborns occupy q_base + [0, ionizations)
-// up to the capacity.
+// births and absorptions; the newborns occupy q_base + [0, births) up to the
+// capacity, births being ionizations plus, for electrons, the secondaries of
+// ion impacts (ion records count those as events and births).
 __device__ __forceinline__ void fold_queue(CaseDev* __restrict__ Cw) {
   __shared__ int64_t sRed[64];
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
@@ -707,28 +750,31 @@ __device__ __forceinline__ void fold_queue(CaseDev* __restrict__ Cw) {
   (void)block_exclusive_scan_t<int64_t>((v[0][0] << 32) | v[0][1], sRed, &t[0]);
   (void)block_exclusive_scan_t<int64_t>((v[0][2] << 32) | v[0][3], sRed, &t[1]);
   (void)block_exclusive_scan_t<int64_t>((v[1][0] << 32) | v[1][2], sRed, &t[2]);
-  (void)block_exclusive_scan_t<int64_t>(v[1][3], sRed, &t[3]);
+  (void)block_exclusive_scan_t<int64_t>((v[1][1] << 32) | v[1][3], sRed, &t[3]);
   if (threadIdx.x == 0) {
     const int64_t coll_e = t[0] >> 32, z = t[0] & 0xFFFFFFFFLL;
     const int64_t ap_e = t[1] >> 32, ag_e = t[1] & 0xFFFFFFFFLL;
-    const int64_t coll_i = t[2] >> 32, ap_i = t[2] & 0xFFFFFFFFLL, ag_i = t[3];
+    const int64_t see = t[3] >> 32, ag_i = t[3] & 0xFFFFFFFFLL;
+    const int64_t coll_i = (t[2] >> 32) - see, ap_i = t[2] & 0xFFFFFFFFLL;
     const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
     const int64_t room_e = C->sp[0].cap - base_e, room_i = C->sp[1].cap - base_i;
-    const int64_t ok_e = z < room_e ? z : (room_e > 0 ? room_e : 0);
+    const int64_t ze = z + see;
+    const int64_t ok_e = ze < room_e ? ze : (room_e > 0 ? room_e : 0);
     const int64_t ok_i = z < room_i ? z : (room_i > 0 ? room_i : 0);
     Cw->alloc[0] = Cw->n[0] = base_e + ok_e;
     Cw->alloc[1] = Cw->n[1] = base_i + ok_i;
     Cw->ctr[kCollE] += coll_e;
     Cw->ctr[kCollI] += coll_i;
     Cw->ctr[kIoniz] += z;
+    Cw->ctr[kSee] += see;
     Cw->ctr[kAbsEPow] += ap_e;
     Cw->ctr[kAbsEGnd] += ag_e;
     Cw->ctr[kAbsIPow] += ap_i;
     Cw->ctr[kAbsIGnd] += ag_i;
     Cw->ctr[kLiveE] += ok_e - ap_e - ag_e;
     Cw->ctr[kLiveI] += ok_i - ap_i - ag_i;
-    if (ok_e < z || ok_i < z) {
-      Cw->ctr[kDropped] += (z - ok_e) + (z - ok_i);
+    if (ok_e < ze || ok_i < z) {
+      Cw->ctr[kDropped] += (ze - ok_e) + (z - ok_i);
       Cw->error = 1;
     }
   }
@@ -912,6 +958,11 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf, de_ifed = C->de_ifed;
   const double sa = C->sigma_a;
   const bool null_coll = (fl & kNullCollision) != 0;
+  // surface processes of this species' electrode hits
+  const bool surf_on = SP == 0 ? C->refl_on != 0 : C->see_on != 0;
+  const double p_surf0 = SP == 0 ? C->eta_refl[0] : C->gamma_see[0];
+  const double p_surf1 = SP == 0 ? C->eta_refl[1] : C->gamma_see[1];
+  int64_t* const cnt_e_next = C->cnt_e + ((s + 1) % 3) * ng;
   const double n_gas = C->n_gas;
   const double nu_star = SP == 0 ? C->nu_star_e : C->nu_star_i;
   const double p_null = SP == 0 ? C->p_null_e : C->p_null_i;
@@ -931,7 +982,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       uid = UID[i];
     }
     bool live = x == x;  // past the end, or absorbed earlier (tombstone)
-    bool abs_pow = false, abs_gnd = false, coll = false, ioniz = false;
+    bool abs_pow = false, abs_gnd = false, coll = false, ioniz = false, surf = false;
     int proc = 0;
     double xn = 0.0, vxn = 0.0;
     if (live) {
@@ -984,9 +1035,36 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         }
       }
       // Step 5: absorbing electrodes; an absorbed ion adds its impact energy
-      // to its electrode's IFEDF (bin n_ifed: beyond the range).
+      // to its electrode's IFEDF (bin n_ifed: beyond the range).  Surface
+      // processes (purpose 3 of the particle's counter): an electron is
+      // reflected specularly with the electrode's probability eta (unless
+      // its mirror image lies outside the gap); an absorbed ion emits an
+      // electron with probability gamma, whose charge goes on the electrode
+      // node of the next step's deposit now and whose slot and velocity the
+      // next head's queue pass writes.
       abs_pow = xn < 0.0;
       abs_gnd = xn > L_gap;
+      if (surf_on && (abs_pow || abs_gnd)) {
+        double r_surf, r_unused;
+        uniform2(seed, uid, st, tag(SP, 3, 0), r_surf, r_unused);
+        if (r_surf < (abs_pow ? p_surf0 : p_surf1)) {
+          if (SP == 0) {
+            const double xm = abs_pow ? -xn : 2.0 * L_gap - xn;
+            if (xm >= 0.0 && xm <= L_gap) {
+              xn = xm;
+              vxn = -vxn;
+              abs_pow = abs_gnd = false;
+              surf = true;
+            }
+          } else {
+            surf = true;
+            long long r;
+            const int q = deposit_split(abs_pow ? 0.0 : L_gap, inv_dx, ng, r);
+            gl_add(&cnt_e_next[q], 4294967296LL - r);
+            if (r) gl_add(&cnt_e_next[q + 1], r);
+          }
+        }
+      }
       if (abs_pow || abs_gnd) {
         live = false;
         if (SP == 1 && (fl & kDiagIfed)) {
@@ -1087,12 +1165,21 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       X[i] = live ? xn : __longlong_as_double(0x7FF8000000000000LL);
       VX[i] = vxn;
     }
-    // the wave's events, in lane order; ionizations numbered in the same order
-    const uint64_t m_coll = __ballot(coll);
-    const uint64_t m_ion = __ballot(ioniz);
-    if (coll) {
+    // the wave's events, in lane order; births numbered in the same order.
+    // An ion's secondary emission is an event of process 2 (x = 0) or 3
+    // (x = L) with one electron birth.
+    const bool see = SP == 1 && surf;
+    if (see) proc = abs_pow ? 2 : 3;
+    const bool ev = coll || see;
+    const uint64_t m_coll = __ballot(ev);
+    const uint64_t m_ion = __ballot(ioniz || see);
+    if (ev) {
       const int code = slot | (proc << 10) | (lane_rank(m_ion) << 12);
       ENT[c * kChunk + w * kWave + lane_rank(m_coll)] = code;
+    }
+    if (SP == 0 && surf_on) {
+      const uint64_t m_refl = __ballot(surf);
+      if (lane == 0 && m_refl) gl_add(&Cw->ctr[kRefl], (long long)__popcll(m_refl));
     }
     const uint64_t m_ap = __ballot(abs_pow), m_ag = __ballot(abs_gnd);
     tq += __popcll(m_coll);

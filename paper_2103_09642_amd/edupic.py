@@ -47,7 +47,8 @@ class CaseDesc(C.Structure):
                 ("n_init_i", C.c_int64), ("te_init_ev", C.c_double), ("ti_init_k", C.c_double),
                 ("cap_e", C.c_int64), ("cap_i", C.c_int64), ("seed", C.c_uint64),
                 ("flags", C.c_uint32), ("n_eepf", C.c_int32), ("de_eepf_ev", C.c_double),
-                ("n_xt_bin", C.c_int32), ("n_ifed", C.c_int32), ("de_ifed_ev", C.c_double)]
+                ("n_xt_bin", C.c_int32), ("n_ifed", C.c_int32), ("de_ifed_ev", C.c_double),
+                ("gamma_see", C.c_double * 2), ("eta_refl", C.c_double * 2), ("see_te_ev", C.c_double)]
 
 
 class Xsec(C.Structure):
@@ -61,7 +62,7 @@ class Xsec(C.Structure):
 class Counts(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_e", "n_i", "step", "abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e",
-        "coll_i", "ioniz", "anomalies", "dropped", "psteps_e", "psteps_i")]
+        "coll_i", "ioniz", "anomalies", "dropped", "psteps_e", "psteps_i", "see", "refl")]
 
     def as_dict(self) -> Dict[str, int]:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -167,6 +168,9 @@ def make_desc(c: Dict) -> CaseDesc:
     d.n_eepf, d.de_eepf_ev = c["n_eepf"], c["de_eepf_ev"]
     d.n_xt_bin = c.get("n_xt_bin", 20)
     d.n_ifed, d.de_ifed_ev = c.get("n_ifed", 200), c.get("de_ifed_ev", 1.0)
+    d.gamma_see[0], d.gamma_see[1] = c.get("gamma_see", (0.0, 0.0))
+    d.eta_refl[0], d.eta_refl[1] = c.get("eta_refl", (0.0, 0.0))
+    d.see_te_ev = c.get("see_te_ev", 1.0)
     return d
 
 
