@@ -166,6 +166,7 @@ typedef struct {
   double eta_refl[2];      /* elastic electron reflection probability, 0..1    */
   double see_te_ev;        /* temperature of the emitted electrons [eV], > 0
                               when a gamma_see is                            */
+  double v_dc;             /* DC offset added to V(t) at x = 0 [V] (a self-bias) */
 } edp_case_desc;
 
 /* Cross sections tabulated at energies i * de_ev, i = 0..n_bins-1
@@ -192,7 +193,8 @@ typedef struct {
   int64_t dropped;           /* births lost to a full capacity               */
   int64_t psteps_e;          /* electron pushes done (sum over steps of n_e) */
   int64_t psteps_i;          /* ion pushes done (sum over ion steps of n_i)  */
-  int64_t see;               /* secondary electrons emitted by ion impact    */
+  int64_t see_pow, see_gnd;  /* secondary electrons emitted by ion impact at
+                                x = 0 and at x = L                           */
   int64_t refl;              /* electrons reflected at an electrode          */
 } edp_counts;
 
@@ -260,6 +262,12 @@ int edp_read_ifed(edp_ctx *ctx, edp_case c, double *f_pow, double *f_gnd, int64_
  * fluxes and impact energies (EDP_DIAG_IFED); slots whose diagnostics are off
  * read 0. */
 int edp_read_info(edp_ctx *ctx, edp_case c, double *out, int32_t n);
+/* Change the driving waveform from the next advance on: the n_harm harmonic
+ * amplitudes (frequencies and phases stay) and the DC offset v_dc.  This is
+ * the actuator of the outer control loops of section 5 (DC self-bias, power
+ * target).  Host amplitudes are copied.  EDP_EINVAL if n_harm differs from
+ * the case's or a value is not finite. */
+int edp_set_voltage(edp_ctx *ctx, edp_case c, const double *v_amp, int32_t n_harm, double v_dc);
 /* Restart every diagnostic of the case (time sums, xt arrays, EEPF, IFEDF). */
 int edp_reset_diag(edp_ctx *ctx, edp_case c);
 /* Fixed-point densities (2^32 per superparticle) the next step will use:

@@ -25,7 +25,7 @@ XT_NAMES = ["pot", "efield", "ne", "ni", "je", "ji", "powere", "poweri", "meanee
 INFO_NAMES = ["mean_e", "ne_max", "debye", "dx_debye", "wpe_dt", "pmax_e", "pmax_i", "cfl_ev",
               "power_e", "power_i", "flux_i_pow", "flux_i_gnd", "ei_pow", "ei_gnd", "fail"]
 COUNTER_NAMES = ["abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i",
-                 "ioniz", "anomaly", "see", "refl"]
+                 "ioniz", "anomaly", "see_pow", "see_gnd", "refl"]
 
 
 class OrcCase(C.Structure):
@@ -38,7 +38,8 @@ class OrcCase(C.Structure):
                 ("ti_init_k", C.c_double), ("seed", C.c_uint64), ("flags", C.c_uint32),
                 ("n_eepf", C.c_int32), ("de_eepf_ev", C.c_double),
                 ("n_xt_bin", C.c_int32), ("n_ifed", C.c_int32), ("de_ifed_ev", C.c_double),
-                ("gamma_see", C.c_double * 2), ("eta_refl", C.c_double * 2), ("see_te_ev", C.c_double)]
+                ("gamma_see", C.c_double * 2), ("eta_refl", C.c_double * 2), ("see_te_ev", C.c_double),
+                ("v_dc", C.c_double)]
 
 
 class OrcXsec(C.Structure):
@@ -94,6 +95,8 @@ def lib():
         L.orc_constants.argtypes = [P, dp]
         L.orc_voltage.restype = C.c_double
         L.orc_voltage.argtypes = [P, C.c_int64]
+        L.orc_set_voltage.restype = C.c_int
+        L.orc_set_voltage.argtypes = [P, dp, C.c_int32, C.c_double]
         L.orc_nsig_tot.argtypes = [P, dp, dp]
         L.orc_null_params.argtypes = [P, dp]
         L.orc_nu_star.restype = C.c_double
@@ -156,6 +159,7 @@ def make_case(c: Dict) -> OrcCase:
     d.gamma_see[0], d.gamma_see[1] = c.get("gamma_see", (0.0, 0.0))
     d.eta_refl[0], d.eta_refl[1] = c.get("eta_refl", (0.0, 0.0))
     d.see_te_ev = c.get("see_te_ev", 1.0)
+    d.v_dc = c.get("v_dc", 0.0)
     return d
 
 
@@ -289,6 +293,11 @@ class Oracle:
 
     def voltage(self, step: int) -> float:
         return lib().orc_voltage(self.h, step)
+
+    def set_voltage(self, v_amp, v_dc: float = 0.0):
+        a = np.ascontiguousarray(v_amp, dtype=np.float64)
+        if lib().orc_set_voltage(self.h, dptr(a) if a.size else None, a.size, float(v_dc)) != 0:
+            raise ValueError("oracle: " + lib().orc_error().decode())
 
     def nsig_tot(self):
         nb = self._arrs[0].size

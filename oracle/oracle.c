@@ -287,13 +287,21 @@ void orc_efield(int32_t ng, double dx, const double *phi, const double *rho, dou
 }
 
 /* Driving voltage at the powered electrode at t_s = step*dt_e: a sum of
- * harmonics V_k sin(2 pi f_k t + phi_k).  The paper's cosine is phi = pi/2. */
+ * harmonics V_k sin(2 pi f_k t + phi_k) plus a DC offset (a self-bias, zero
+ * unless set).  The paper's cosine is phi = pi/2. */
 double orc_voltage(const orc_sim *s, int64_t step) {
   const double t = (double)step * s->dt_e;
   double v = 0.0;
   for (int k = 0; k < s->c.n_harm; ++k)
     v += s->c.v_amp[k] * sin(TWO_PI_D * s->c.freq_hz[k] * t + s->c.phase_rad[k]);
-  return v;
+  return v + s->c.v_dc;
+}
+
+int orc_set_voltage(orc_sim *s, const double *v_amp, int32_t n, double v_dc) {
+  if (n != s->c.n_harm) return set_err("amplitude count differs from n_harm"), -1;
+  for (int k = 0; k < n; ++k) s->c.v_amp[k] = v_amp[k];
+  s->c.v_dc = v_dc;
+  return 0;
 }
 
 /* ---------------------------------------------------------------------------
@@ -782,7 +790,7 @@ static void emit_secondary(orc_sim *s, const parts *p, int64_t k, int side) {
     parts_append(&s->see_new, 0.0, vn, vy, vz, orc_child_uid(uid, s->step, 3));
   else
     parts_append(&s->see_new, s->L, -vn, vy, vz, orc_child_uid(uid, s->step, 3));
-  s->counts[ORC_C_SEE]++;
+  s->counts[side == 0 ? ORC_C_SEE_POW : ORC_C_SEE_GND]++;
 }
 
 /* Step 5: absorbing electrodes; removal by moving the last particle into the

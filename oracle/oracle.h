@@ -66,8 +66,9 @@ enum {
 enum {
   ORC_C_ABS_E_POW = 0, ORC_C_ABS_E_GND, ORC_C_ABS_I_POW, ORC_C_ABS_I_GND,
   ORC_C_COLL_E, ORC_C_COLL_I, ORC_C_IONIZ, ORC_C_ANOMALY,
-  ORC_C_SEE,  /* electrons emitted by ion impact                         */
-  ORC_C_REFL, /* electrons reflected at an electrode                      */
+  ORC_C_SEE_POW, /* electrons emitted by ion impact at x = 0             */
+  ORC_C_SEE_GND, /* ... at x = L                                         */
+  ORC_C_REFL,    /* electrons reflected at an electrode                   */
   ORC_C_N
 };
 
@@ -99,6 +100,7 @@ typedef struct {
   double gamma_see[2]; /* ion-induced secondary electron yield, 0..1        */
   double eta_refl[2];  /* elastic electron reflection probability, 0..1     */
   double see_te_ev;    /* temperature of the emitted electrons [eV]        */
+  double v_dc;         /* DC offset of the powered electrode's voltage [V]   */
 } orc_case;
 
 /* Tabulated cross sections (section 3.2): bin i <-> energy i*de_ev. */
@@ -159,6 +161,9 @@ void orc_plasma_params(double n_e, double te_ev, double out[2]);
  * factor_i, gas density, V at step 0. */
 void orc_constants(const orc_sim *s, double out[8]);
 double orc_voltage(const orc_sim *s, int64_t step);
+/* Replace the harmonic amplitudes (n = n_harm of the case) and the DC offset
+ * from the next step on (the outer control loops of section 5). */
+int orc_set_voltage(orc_sim *s, const double *v_amp, int32_t n, double v_dc);
 void orc_nsig_tot(const orc_sim *s, double *nsig_e, double *nsig_i);
 /* Null-collision parameters: nu*_e, nu*_i, P*_e, P*_i. */
 void orc_null_params(const orc_sim *s, double out[4]);

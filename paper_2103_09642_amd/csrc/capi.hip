@@ -216,13 +216,13 @@ Layout layout(const edp_case_desc* c, int nbins) {
   return L;
 }
 
-// Driving voltage V(t_s) = sum_k V_k sin(2 pi f_k t_s + phi_k), t_s = s dt_e.
+// Driving voltage V(t_s) = sum_k V_k sin(2 pi f_k t_s + phi_k) + V_dc, t_s = s dt_e.
 double voltage(const edp_case_desc& c, int64_t s) {
   const double t = (double)s * c.dt_e;
   double v = 0.0;
   for (int k = 0; k < c.n_harm; ++k)
     v += c.v_amp[k] * std::sin(kTwoPi * c.freq_hz[k] * t + c.phase_rad[k]);
-  return v;
+  return v + c.v_dc;
 }
 
 // Null-collision maximum frequency of a table of n sigma_tot: the largest
@@ -941,7 +941,8 @@ int edp_read_counts(edp_ctx* ctx, edp_case id, edp_counts* out) {
   out->dropped = t.ctr[kDropped];
   out->psteps_e = t.ctr[kPstepE];
   out->psteps_i = t.ctr[kPstepI];
-  out->see = t.ctr[kSee];
+  out->see_pow = t.ctr[kSeePow];
+  out->see_gnd = t.ctr[kSeeGnd];
   out->refl = t.ctr[kRefl];
   return EDP_OK;
 }
@@ -1218,6 +1219,19 @@ int edp_read_info(edp_ctx* ctx, edp_case id, double* out, int32_t n) {
     }
   }
   out[EDP_INFO_FAIL] = (double)bad;
+  return EDP_OK;
+}
+
+int edp_set_voltage(edp_ctx* ctx, edp_case id, const double* v_amp, int32_t n_harm, double v_dc) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c || (n_harm > 0 && !v_amp)) return fail(EDP_EINVAL, "bad argument");
+  if (n_harm != c->desc.n_harm) return fail(EDP_EINVAL, "n_harm %d differs from the case's %d", n_harm, c->desc.n_harm);
+  if (!std::isfinite(v_dc)) return fail(EDP_EINVAL, "v_dc must be finite");
+  for (int k = 0; k < n_harm; ++k)
+    if (!std::isfinite(v_amp[k])) return fail(EDP_EINVAL, "amplitudes must be finite");
+  // the V(t) ring is filled from the descriptor at the start of every advance
+  for (int k = 0; k < n_harm; ++k) c->desc.v_amp[k] = v_amp[k];
+  c->desc.v_dc = v_dc;
   return EDP_OK;
 }
 

@@ -55,7 +55,7 @@ enum XtSum {
 // Dynamic counters (int64 slots of CaseDev::ctr).
 enum Ctr {
   kAbsEPow = 0, kAbsEGnd, kAbsIPow, kAbsIGnd, kCollE, kCollI, kIoniz, kAnomaly, kDropped,
-  kLiveE, kLiveI, kPstepE, kPstepI, kSee, kRefl, kNumCtr
+  kLiveE, kLiveI, kPstepE, kPstepI, kSeePow, kSeeGnd, kRefl, kNumCtr
 };
 
 struct SpeciesDev {

@@ -766,7 +766,6 @@ __device__ __forceinline__ void fold_queue(CaseDev* __restrict__ Cw) {
     Cw->ctr[kCollE] += coll_e;
     Cw->ctr[kCollI] += coll_i;
     Cw->ctr[kIoniz] += z;
-    Cw->ctr[kSee] += see;
     Cw->ctr[kAbsEPow] += ap_e;
     Cw->ctr[kAbsEGnd] += ag_e;
     Cw->ctr[kAbsIPow] += ap_i;
@@ -1177,9 +1176,12 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       const int code = slot | (proc << 10) | (lane_rank(m_ion) << 12);
       ENT[c * kChunk + w * kWave + lane_rank(m_coll)] = code;
     }
-    if (SP == 0 && surf_on) {
-      const uint64_t m_refl = __ballot(surf);
-      if (lane == 0 && m_refl) gl_add(&Cw->ctr[kRefl], (long long)__popcll(m_refl));
+    if (surf_on) {
+      // reflections (electrons) or emissions per electrode (ions)
+      const uint64_t m_s0 = __ballot(surf && (SP == 0 || abs_pow));
+      const uint64_t m_s1 = SP == 1 ? __ballot(surf && abs_gnd) : 0ull;
+      if (lane == 0 && m_s0) gl_add(&Cw->ctr[SP == 0 ? kRefl : kSeePow], (long long)__popcll(m_s0));
+      if (lane == 0 && m_s1) gl_add(&Cw->ctr[kSeeGnd], (long long)__popcll(m_s1));
     }
     const uint64_t m_ap = __ballot(abs_pow), m_ag = __ballot(abs_gnd);
     tq += __popcll(m_coll);

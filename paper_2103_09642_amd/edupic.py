@@ -48,7 +48,8 @@ class CaseDesc(C.Structure):
                 ("cap_e", C.c_int64), ("cap_i", C.c_int64), ("seed", C.c_uint64),
                 ("flags", C.c_uint32), ("n_eepf", C.c_int32), ("de_eepf_ev", C.c_double),
                 ("n_xt_bin", C.c_int32), ("n_ifed", C.c_int32), ("de_ifed_ev", C.c_double),
-                ("gamma_see", C.c_double * 2), ("eta_refl", C.c_double * 2), ("see_te_ev", C.c_double)]
+                ("gamma_see", C.c_double * 2), ("eta_refl", C.c_double * 2), ("see_te_ev", C.c_double),
+                ("v_dc", C.c_double)]
 
 
 class Xsec(C.Structure):
@@ -62,7 +63,7 @@ class Xsec(C.Structure):
 class Counts(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_e", "n_i", "step", "abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e",
-        "coll_i", "ioniz", "anomalies", "dropped", "psteps_e", "psteps_i", "see", "refl")]
+        "coll_i", "ioniz", "anomalies", "dropped", "psteps_e", "psteps_i", "see_pow", "see_gnd", "refl")]
 
     def as_dict(self) -> Dict[str, int]:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -74,7 +75,7 @@ EXPORTS = ["edp_create", "edp_destroy", "edp_set_xsec", "edp_case_bytes", "edp_c
            "edp_read_density", "edp_read_eepf", "edp_read_currents", "edp_read_mean_energy",
            "edp_read_deposit", "edp_read_fields", "edp_get_state", "edp_set_state",
            "edp_set_option", "edp_read_profile", "edp_last_error", "edp_read_xt",
-           "edp_read_xt_steps", "edp_read_ifed", "edp_read_info", "edp_reset_diag"]
+           "edp_read_xt_steps", "edp_read_ifed", "edp_read_info", "edp_reset_diag", "edp_set_voltage"]
 
 _lib = None
 
@@ -120,6 +121,7 @@ def load() -> C.CDLL:
         "edp_read_ifed": (C.c_int, [P, I64, D, D, I64P, I32]),
         "edp_read_info": (C.c_int, [P, I64, D, I32]),
         "edp_reset_diag": (C.c_int, [P, I64]),
+        "edp_set_voltage": (C.c_int, [P, I64, D, I32, C.c_double]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -171,6 +173,7 @@ def make_desc(c: Dict) -> CaseDesc:
     d.gamma_see[0], d.gamma_see[1] = c.get("gamma_see", (0.0, 0.0))
     d.eta_refl[0], d.eta_refl[1] = c.get("eta_refl", (0.0, 0.0))
     d.see_te_ev = c.get("see_te_ev", 1.0)
+    d.v_dc = c.get("v_dc", 0.0)
     return d
 
 
@@ -329,6 +332,12 @@ class Case:
 
     def reset_diag(self):
         _chk(load().edp_reset_diag(self.ctx.h, self.id))
+
+    def set_voltage(self, v_amp, v_dc: float = 0.0):
+        """New harmonic amplitudes (one per harmonic of the case) and DC
+        offset, effective from the next advance."""
+        a = np.ascontiguousarray(v_amp, dtype=np.float64)
+        _chk(load().edp_set_voltage(self.ctx.h, self.id, _d(a) if a.size else None, a.size, float(v_dc)))
 
     def deposit(self):
         a, b = np.zeros(self.ng, dtype=np.int64), np.zeros(self.ng, dtype=np.int64)

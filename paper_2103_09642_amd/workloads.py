@@ -81,6 +81,7 @@ def base_case(**kw) -> Dict:
         "n_xt_bin": 20, "n_ifed": 200, "de_ifed_ev": 1.0,
         # surface processes (section 5), (powered, grounded); off by default
         "gamma_see": (0.0, 0.0), "eta_refl": (0.0, 0.0), "see_te_ev": 1.0,
+        "v_dc": 0.0,  # DC offset of the powered electrode (self-bias) [V]
     }
     c.update(kw)
     return c

@@ -13,7 +13,8 @@ from paper_2103_09642_amd.workloads import base_case, random_state
 pytestmark = pytest.mark.gpu
 
 QE, MAR = 1.602176634e-19, 39.948 * 1.66053906660e-27
-COUNTERS = ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz", "see", "refl")
+COUNTERS = ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz", "see_pow", "see_gnd",
+            "refl")
 
 
 @pytest.fixture(scope="module")
@@ -74,7 +75,7 @@ def test_surface_one_step_parity(ctx, xs_default, orc, step):
             assert cg[k] == co[k], k
         assert co["refl"] > 500
         if step == 0:
-            assert co["see"] > 300
+            assert co["see_pow"] > 300 and co["see_gnd"] > 200
         for sp in (0, 1):
             compare_states(g.get_state(sp), o.get_state(sp), 1e-12, f"sp{sp}")
         ge, gi = g.deposit()
@@ -106,7 +107,7 @@ def test_surface_multi_step_parity(ctx, xs_default, orc, mode):
         cg, co = g.counts(), o.counts()
         for k in COUNTERS:
             assert cg[k] == co[k], k
-        assert co["see"] > 0 and co["refl"] > 0
+        assert co["see_pow"] > 0 and co["see_gnd"] > 0 and co["refl"] > 0
         for sp in (0, 1):
             compare_states(g.get_state(sp), o.get_state(sp), 1e-9, f"sp{sp}")
         g.destroy()

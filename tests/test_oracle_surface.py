@@ -122,7 +122,7 @@ def test_secondary_emission_count_and_placement(orc):
     e, i = _wall_ions(c, n, seed=3)
     o = _run(orc, c, zero_xsec(), e, i)
     cnt = o.counts()
-    assert cnt["abs_i_pow"] == n and cnt["abs_i_gnd"] == n and cnt["see"] == n
+    assert cnt["abs_i_pow"] == n and cnt["abs_i_gnd"] == n and cnt["see_pow"] == n and cnt["see_gnd"] == 0
     st = o.get_state(0)
     new = ~np.isin(st["uid"], e["uid"])
     assert new.sum() == n
@@ -145,7 +145,8 @@ def test_secondary_emission_yield_per_electrode(orc):
     new = ~np.isin(st["uid"], e["uid"])
     at0 = int((st["x"][new] == 0.0).sum())
     atL = int((st["x"][new] == c["gap_m"]).sum())
-    assert at0 == emit[:n].sum() and atL == emit[n:].sum() and o.counts()["see"] == emit.sum()
+    cnt = o.counts()
+    assert at0 == emit[:n].sum() == cnt["see_pow"] and atL == emit[n:].sum() == cnt["see_gnd"]
     for k, p in ((at0, 0.25), (atL, 0.5)):
         assert abs(k - p * n) < 5 * math.sqrt(n * p * (1 - p))
 
@@ -218,10 +219,10 @@ def test_bookkeeping_with_surface_processes(orc, xs_default):
         o.step(1)
         cur = o.counts()
         d = {k: cur[k] - prev[k] for k in cur}
-        assert o.count(0) == ne - d["abs_e_pow"] - d["abs_e_gnd"] + d["ioniz"] + d["see"]
+        assert o.count(0) == ne - d["abs_e_pow"] - d["abs_e_gnd"] + d["ioniz"] + d["see_pow"] + d["see_gnd"]
         assert o.count(1) == ni - d["abs_i_pow"] - d["abs_i_gnd"] + d["ioniz"]
         prev, ne, ni = cur, o.count(0), o.count(1)
-    assert cur["see"] > 0 and cur["refl"] > 0
+    assert cur["see_pow"] > 0 and cur["see_gnd"] > 0 and cur["refl"] > 0
     uids = o.get_state(0)["uid"]
     assert np.unique(uids).size == uids.size
     with pytest.raises(ValueError):
