@@ -115,11 +115,11 @@ extern "C" {
 #define EDP_IONS 1
 
 /* Execution options for edp_set_option. */
-#define EDP_OPT_MODE 1        /* 0 plain launches, 1 hipGraph chunks, 2 persistent */
+#define EDP_OPT_MODE 1        /* 0 plain launches, 1 step windows replayed as
+                                 captured hipGraphs                           */
 #define EDP_OPT_SORT_EVERY 2  /* steps between compaction + cell sort (>= 1)      */
 #define EDP_OPT_PROFILE 5     /* 1: time every particle-kernel launch with events */
 #define EDP_OPT_GRAPH_STEPS 6 /* steps captured per hipGraph (multiple of N_SUB)  */
-#define EDP_OPT_WG_PER_CU 7   /* persistent mode: workgroups per compute unit     */
 #define EDP_OPT_POISSON 8     /* field solve: 0 parallel flux scans (default),
                                  1 sequential Thomas, bit-reproducible           */
 
@@ -221,8 +221,9 @@ int edp_case_create(edp_ctx *ctx, const edp_case_desc *desc, void *dev_arena,
                     int64_t arena_bytes, edp_case *out);
 int edp_case_destroy(edp_ctx *ctx, edp_case c);
 /* Advance each listed case by n_cycles[k] RF cycles (steps_per_cycle steps
- * each).  Asynchronous; cases advance independently (batched in one launch
- * in persistent mode). */
+ * each).  Asynchronous.  The cases advance in lockstep: every kernel launch
+ * serves all cases still running, and a case's results do not depend on the
+ * others in the call. */
 int edp_advance(edp_ctx *ctx, const edp_case *cases, int32_t n_cases, const int32_t *n_cycles);
 /* Same with a step count per case. */
 int edp_advance_steps(edp_ctx *ctx, const edp_case *cases, int32_t n_cases,
@@ -289,8 +290,8 @@ int edp_set_state(edp_ctx *ctx, edp_case c, int32_t species, const double *x, co
 /* Execution options (EDP_OPT_*), per context. */
 int edp_set_option(edp_ctx *ctx, int32_t key, int64_t value);
 /* Launch timing when EDP_OPT_PROFILE is on: summed HIP-event milliseconds
- * and number of launches of the particle kernels (plain and graph modes) or
- * of the persistent kernel, since the last call (then reset).  Synchronous. */
+ * and number of launches of the electron particle kernel in plain mode, since
+ * the last call (then reset).  Synchronous. */
 int edp_read_profile(edp_ctx *ctx, double *ms, int64_t *launches);
 const char *edp_last_error(void);
 

@@ -111,7 +111,7 @@ struct edp_ctx {
   std::map<edp_case, Case*> cases;
   edp_case next_id = 1;
   // options
-  int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, wg_per_cu = 2, poisson = 0;
+  int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, poisson = 0;
   // the batch table (device copy owned by the context) and its run state
   BatchDev* batch_d = nullptr;
   Batch batch;
@@ -1386,10 +1386,6 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
     case EDP_OPT_POISSON:
       if (value < 0 || value > 1) return fail(EDP_EINVAL, "poisson solver must be 0 or 1");
       ctx->poisson = (int)value;
-      break;
-    case EDP_OPT_WG_PER_CU:
-      if (value < 1 || value > 16) return fail(EDP_EINVAL, "workgroups per CU must be 1..16");
-      ctx->wg_per_cu = (int)value;
       break;
     default:
       return fail(EDP_EINVAL, "unknown option %d", key);

@@ -21,10 +21,10 @@ NULL_COLLISION, DIAG_XT, DIAG_IFED = 64, 128, 256
 XT_NAMES = ["pot", "efield", "ne", "ni", "je", "ji", "powere", "poweri", "meanee", "meanei", "ioniz"]
 INFO_NAMES = ["mean_e", "ne_max", "debye", "dx_debye", "wpe_dt", "pmax_e", "pmax_i", "cfl_ev",
               "power_e", "power_i", "flux_i_pow", "flux_i_gnd", "ei_pow", "ei_gnd", "fail"]
-OPT_MODE, OPT_SORT_EVERY, OPT_PROFILE, OPT_GRAPH_STEPS, OPT_WG_PER_CU = 1, 2, 5, 6, 7
+OPT_MODE, OPT_SORT_EVERY, OPT_PROFILE, OPT_GRAPH_STEPS = 1, 2, 5, 6
 OPT_POISSON = 8
 POISSON_FLUX, POISSON_THOMAS = 0, 1
-MODE_PLAIN, MODE_GRAPH, MODE_PERSISTENT = 0, 1, 2
+MODE_PLAIN, MODE_GRAPH = 0, 1
 ELECTRONS, IONS = 0, 1
 _FLAG_NAMES = {"density": DIAG_DENSITY, "eepf": DIAG_EEPF, "current": DIAG_CURRENT,
                "meane": DIAG_MEANE, "ioniz_literal": IONIZ_ANGLE_LITERAL,
