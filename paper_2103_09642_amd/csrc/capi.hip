@@ -125,7 +125,7 @@ struct edp_ctx {
 namespace {
 
 struct Layout {
-  size_t off_case, off_part[2][2][5], off_cq[2][2], off_qwg[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
+  size_t off_case, off_part[2][2][5], off_cq[2], off_qwg[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
       off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[7], off_eepf, off_xt, off_xtcnt, off_ifed, off_sort,
       total;
   int64_t cap[2];
@@ -164,7 +164,7 @@ int validate(const edp_case_desc* c) {
   const uint32_t meas = EDP_DIAG_EEPF | EDP_DIAG_CURRENT | EDP_DIAG_MEANE | EDP_DIAG_XT | EDP_DIAG_IFED;
   if ((c->flags & meas) && c->n_grid > 1024) return fail(EDP_EINVAL, "measurements support n_grid <= 1024");
   for (int sp = 0; sp < 2; ++sp)
-    if (particle_lds_bytes(c->n_grid, c->flags, c->n_eepf, c->n_ifed, sp) > 65536 - 1024)
+    if (particle_lds_bytes(c->n_grid, c->flags, c->n_eepf, c->n_ifed, sp) > 65536 - 8192)
       return fail(EDP_EINVAL, "measurement histograms and grid exceed the workgroup's LDS");
   return EDP_OK;
 }
@@ -190,8 +190,7 @@ Layout layout(const edp_case_desc* c, int nbins) {
       for (int a = 0; a < 5; ++a) L.off_part[sp][set][a] = take((size_t)L.cap[sp] * 8);
   for (int sp = 0; sp < 2; ++sp) {
     const size_t chunks = (size_t)((L.cap[sp] + kChunk - 1) / kChunk);
-    L.off_cq[sp][0] = take(chunks * kChunk * 4);  // events
-    L.off_cq[sp][1] = take(chunks * 16);          // chunk records (one word per wave)
+    L.off_cq[sp] = take(chunks * kChunk * 8);  // events (per-workgroup lists over its chunk range)
   }
   for (int sp = 0; sp < 2; ++sp) L.off_qwg[sp] = take((size_t)kMaxPartWG * 16);
   for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
@@ -731,6 +730,23 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   h.nu_star_i = nu_star(nsig_i, ctx->de, kMuArAr);
   h.p_null_e = 1.0 - std::exp(-h.nu_star_e * h.dt_e);
   h.p_null_i = 1.0 - std::exp(-h.nu_star_i * h.dt_i);
+  {
+    // Candidates of the direct collision test.  nu* bounds n sigma_tot g up
+    // to the energy e_lim its last bin is taken at, up to rounding of the bin
+    // edges; the relative margin covers that and the ulps of exp, so a
+    // particle with R >= p_bound and an energy below e_lim has R >= P.  An
+    // ion's relative speed is at most |v| + |v_a|: each normal of the
+    // generator is r cos or r sin with r <= sqrt(2 * 53 ln 2) < 8.58, so
+    // |v_a|^2 <= (r1^2 + r2^2) sigma_a^2 < (12.2 sigma_a)^2, and
+    // g^2 <= 2 (v^2 + |v_a|^2).
+    const double e_lim = 4.0 * (double)nb * ctx->de;
+    h.p_bound_e = std::min(1.0, (1.0 - std::exp(-h.nu_star_e * h.dt_e)) * (1.0 + 1e-9));
+    h.p_bound_i = std::min(1.0, (1.0 - std::exp(-h.nu_star_i * h.dt_i)) * (1.0 + 1e-9));
+    h.v2_lim_e = 2.0 * e_lim * kEvToJ / kEMass * (1.0 - 1e-12);
+    h.g2_lim_i = 2.0 * e_lim * kEvToJ / kMuArAr * (1.0 - 1e-12);
+    const double amax = 12.2 * h.sigma_a;
+    h.a2_i = amax * amax;
+  }
   h.de_cs = ctx->de;
   h.thr_exc = ctx->thr_exc;
   h.thr_ion = ctx->thr_ion;
@@ -759,8 +775,7 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
     }
   }
   for (int sp = 0; sp < 2; ++sp) {
-    h.cq_ent[sp] = (int32_t*)(c->arena + L.off_cq[sp][0]);
-    h.cq_rec[sp] = (int32_t*)(c->arena + L.off_cq[sp][1]);
+    h.cq_ent[sp] = (int64_t*)(c->arena + L.off_cq[sp]);
   }
   for (int sp = 0; sp < 2; ++sp) h.q_wg[sp] = (int32_t*)(c->arena + L.off_qwg[sp]);
   h.q_valid = 0;

@@ -80,6 +80,11 @@ struct CaseDev {
   double n_gas;                     // gas density p / (k_B T_g)
   double nu_star_e, nu_star_i;      // null-collision maximum frequencies
   double p_null_e, p_null_i;        // 1 - exp(-nu* dt) per species
+  // collision candidates of the direct test: R below p_bound (P* with a
+  // relative margin), or electrons with v^2 > v2_lim_e, ions with
+  // 2 (v^2 + a2_i) > g2_lim_i (a2_i bounds the squared thermal target speed
+  // the generator can give), i.e. beyond the energy range P* covers
+  double p_bound_e, p_bound_i, v2_lim_e, g2_lim_i, a2_i;
   double kpois;       // dx*dx/eps0
   // surface processes, [0] powered electrode (x = 0), [1] grounded (x = L)
   double gamma_see[2];  // ion-induced secondary electron yield
@@ -103,16 +108,12 @@ struct CaseDev {
   int64_t* ifed;                      // [2][n_ifed + 1] impacts per energy bin
   int64_t *eepf;                                              // [n_eepf]
   int64_t *sort_cnt;                                          // [ng + 1] scratch
-  // Collision queue of the last particle step, per species.  Wave w of chunk
-  // c (slots [c*kChunk, (c+1)*kChunk), 64 per wave) writes its events to
-  // cq_ent[c*kChunk + 64w + k] and its totals to cq_rec[4c + w] =
-  // events | ionizations << 7 | absorbed at x=0 << 14 | absorbed at x=L << 21,
-  // so no two waves ever write the same word.  An event is
-  // slot-in-chunk | process << 10 | ionization rank in the wave << 12.
-  int32_t* cq_ent[2];
-  int32_t* cq_rec[2];
-  // per particle workgroup and species: the totals of its chunk range,
-  // {events, ionizations, absorbed at x=0, absorbed at x=L}
+  // Collision queue of the last particle step, per species: particle
+  // workgroup j (chunks [j*per, (j+1)*per)) writes its events to
+  // cq_ent[j*per*kChunk + k], each slot | process << 32 | birth rank << 34,
+  // and its totals to q_wg[j] = {events, births, absorbed at x=0, absorbed
+  // at x=L}.
+  int64_t* cq_ent[2];
   int32_t* q_wg[2];  // [kMaxPartWG][4]
   // ---- dynamic (device-mutated) -----------------------------------------
   int64_t step;       // next step whose head runs (advanced by the electron kernel)

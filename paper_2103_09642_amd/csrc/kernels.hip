@@ -615,24 +615,19 @@ __device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C
   P.euid[be] = child_uid(uid, s, 3);
 }
 
-// Apply the pending collision queue.  Workgroup blk of nblk takes a
-// contiguous range of chunks of each species; a group of 8 lanes takes one
-// chunk: its four wave records and the first two events of each wave's part
-// of the queue are loaded together, lane l working through the events of
-// wave l/2.  Newborns of chunk c go to q_base + (ionizations of chunks < c)
-// + (ionizations of lower waves of c) + rank, so the ionization counts
-// before the range are summed with the same loads.  Secondary electrons of
-// ion impacts are births of the ion queue and follow every electron birth of
-// the step.  No atomics: every slot follows from the records alone.
-constexpr int kApplyLanes = 8;
-typedef int rec4 __attribute__((ext_vector_type(4)));  // the four wave records of a chunk
-constexpr int kApplyChunks = kBlock / kApplyLanes;  // chunks per round of a workgroup
+typedef int rec4 __attribute__((ext_vector_type(4)));  // per-workgroup queue record
 
-__device__ __forceinline__ int rec_q(int r) { return r & 127; }
-__device__ __forceinline__ int rec_z(int r) { return (r >> 7) & 127; }
-__device__ __forceinline__ int rec_ap(int r) { return (r >> 14) & 127; }
-__device__ __forceinline__ int rec_ag(int r) { return (r >> 21) & 127; }
-__device__ __forceinline__ int rec_pick(const rec4 r, int w) { return w == 0 ? r.x : w == 1 ? r.y : w == 2 ? r.z : r.w; }
+// Apply the pending collision queue.  Every particle workgroup of the last
+// step left one event list (in its chunk range of the queue) and a record
+// {events, births, absorbed at x=0, absorbed at x=L}; an event is
+// slot | process << 32 | birth rank in the list << 34.  Workgroup blk of
+// nblk takes a contiguous range of those lists, a group of 8 lanes one list.
+// Newborns of list j go to q_base + (births of the lists before j) + rank;
+// secondary electrons of ion impacts (ion events of process 2, 3) follow
+// every electron birth of the step.  No atomics: every slot follows from the
+// records alone.
+constexpr int kApplyLanes = 8;
+constexpr int kApplyGroups = kBlock / kApplyLanes;  // lists per round of a workgroup
 
 __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, int nblk) {
   __shared__ int64_t sRed[64];
@@ -640,83 +635,60 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
   const int64_t s = C->q_step;
   const ScatterPtrs P = scatter_ptrs(Cw);
   const int grp = (int)threadIdx.x / kApplyLanes, l = (int)threadIdx.x % kApplyLanes;
-  const int wv = l / 2, jj = l % 2;  // this lane's wave part of the chunk and first entry
   const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
   const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
   const bool see_on = C->see_on != 0;
   for (int sp = 0; sp < 2; ++sp) {
-    const int64_t nb = C->q_nblk[sp];
-    const EDP_GLOBAL rec4* __restrict__ rec = (const EDP_GLOBAL rec4*)G(C->cq_rec[sp]);
-    const EDP_GLOBAL int32_t* __restrict__ ent = G(C->cq_ent[sp]);
-    const int64_t c0 = nb * blk / nblk, c1 = nb * (blk + 1) / nblk;
-    int64_t zrun = 0;  // newborns of the chunks before the current round
-    for (int64_t cb = c0; cb < c1; cb += kApplyChunks) {
-      const int64_t c = cb + grp;
-      const bool valid = c < c1;
-      rec4 r4 = {0, 0, 0, 0};
-      if (valid) r4 = rec[c];
-      const int64_t e0 = c * kChunk + wv * 64;
-      const int code0 = valid ? ent[e0 + jj] : 0;  // in bounds: each wave part is 64 long
-      const int qw = rec_q(rec_pick(r4, wv));
-      int64_t zbase = 0;  // births (of this species' queue) before this lane's wave
-      if (sp == 0 || see_on) {
-        // high word: births of chunks < c0 (first round), low word: this
-        // round's births of lower groups
-        int64_t zpre = 0;
-        if (cb == c0) {
-          // whole particle workgroups before c0, then the chunks of the one holding c0
-          const int64_t per = C->q_per[sp];
-          const int64_t jw = c0 / per;
-          const EDP_GLOBAL rec4* wg = (const EDP_GLOBAL rec4*)G(C->q_wg[sp]);
-#pragma unroll 4
-          for (int64_t k = threadIdx.x; k < jw; k += blockDim.x) zpre += wg[k].y;
-          for (int64_t k = jw * per + threadIdx.x; k < c0; k += blockDim.x) {
-            const rec4 t = rec[k];
-            zpre += rec_z(t.x) + rec_z(t.y) + rec_z(t.z) + rec_z(t.w);
-          }
-          if (sp == 1) {
-            // secondaries come after all of the step's ionization births
-            const int64_t pe = C->q_per[0];
-            const int64_t nwe = pe > 0 ? (C->q_nblk[0] + pe - 1) / pe : 0;
-            const EDP_GLOBAL rec4* wge = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
-            for (int64_t k = threadIdx.x; k < nwe; k += blockDim.x) zpre += wge[k].y;
-          }
-        }
-        const int zc = rec_z(r4.x) + rec_z(r4.y) + rec_z(r4.z) + rec_z(r4.w);
-        const int64_t x = (zpre << 32) | (int64_t)(l == 0 ? zc : 0);
-        int64_t tot;
-        const int64_t exc = block_exclusive_scan_t<int64_t>(x, sRed, &tot);
-        const int64_t low = __shfl(exc & 0xFFFFFFFFLL, 0, kApplyLanes);  // lane 0 of the group
-        if (cb == c0) zrun = tot >> 32;
-        // ionizations of the lower waves of this chunk
-        const int zw = (wv > 0 ? rec_z(r4.x) : 0) + (wv > 1 ? rec_z(r4.y) : 0) + (wv > 2 ? rec_z(r4.z) : 0);
-        zbase = zrun + low + zw;
-        zrun += tot & 0xFFFFFFFFLL;
+    const int64_t per = C->q_per[sp];
+    const int64_t nwg = per > 0 ? (C->q_nblk[sp] + per - 1) / per : 0;
+    const int64_t j0 = nwg * blk / nblk, j1 = nwg * (blk + 1) / nblk;
+    if (j0 >= j1) continue;  // uniform
+    const EDP_GLOBAL rec4* __restrict__ wg = (const EDP_GLOBAL rec4*)G(C->q_wg[sp]);
+    const EDP_GLOBAL int64_t* __restrict__ ent = G(C->cq_ent[sp]);
+    const bool births = sp == 0 || see_on;
+    // births of the lists before this range (for ions: after every electron birth)
+    int64_t zrun = 0;
+    if (births) {
+      int64_t zp = 0;
+      for (int64_t k = threadIdx.x; k < j0; k += blockDim.x) zp += wg[k].y;
+      if (sp == 1) {
+        const int64_t pe = C->q_per[0];
+        const int64_t nwe = pe > 0 ? (C->q_nblk[0] + pe - 1) / pe : 0;
+        const EDP_GLOBAL rec4* __restrict__ wge = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
+        for (int64_t k = threadIdx.x; k < nwe; k += blockDim.x) zp += wge[k].y;
       }
-      if (sp == 0) {
-        for (int k = jj; k < qw; k += 2) {
-          const int code = k == jj ? code0 : ent[e0 + k];
-          const int64_t i = c * kChunk + (code & 1023);
-          const int proc = (code >> 10) & 3;
+      (void)block_exclusive_scan_t<int64_t>(zp, sRed, &zrun);
+    }
+    for (int64_t jb = j0; jb < j1; jb += kApplyGroups) {
+      const int64_t jj = jb + grp;
+      const bool valid = jj < j1;
+      rec4 r = {0, 0, 0, 0};
+      if (valid) r = wg[jj];
+      const EDP_GLOBAL int64_t* __restrict__ e = ent + jj * per * kChunk;
+      const int64_t code0 = valid && l < r.x ? e[l] : 0;
+      int64_t zbase = 0;
+      if (births) {
+        int64_t tot;
+        const int64_t exc = block_exclusive_scan_t<int64_t>(l == 0 ? (int64_t)r.y : 0, sRed, &tot);
+        zbase = zrun + __shfl(exc, 0, kApplyLanes);  // births of the lower groups of this round
+        zrun += tot;
+      }
+      for (int k = l; k < r.x; k += kApplyLanes) {
+        const int64_t code = k == l ? code0 : e[k];
+        const int64_t i = code & 0xFFFFFFFFLL;
+        const int proc = (int)((code >> 32) & 3);
+        const int64_t kk = zbase + (code >> 34);
+        if (sp == 0) {
           int64_t be = -1, bi = -1;
           if (proc == 2) {
-            const int64_t kk = zbase + (code >> 12);
             if (base_e + kk < cap_e) be = base_e + kk;
             if (base_i + kk < cap_i) bi = base_i + kk;
           }
           electron_scatter(C, P, i, proc, be, bi, s);
-        }
-      } else {
-        for (int k = jj; k < qw; k += 2) {
-          const int code = k == jj ? code0 : ent[e0 + k];
-          const int64_t i = c * kChunk + (code & 1023);
-          const int proc = (code >> 10) & 3;
-          if (proc < 2) {
-            ion_scatter(C, P, i, proc, s);
-          } else {  // 2, 3: absorbed at x = 0 / x = L with an emitted electron
-            const int64_t kk = zbase + (code >> 12);
-            see_emit(C, P, i, proc - 2, base_e + kk < cap_e ? base_e + kk : -1, s);
-          }
+        } else if (proc < 2) {
+          ion_scatter(C, P, i, proc, s);
+        } else {  // 2, 3: absorbed at x = 0 / x = L with an emitted electron
+          see_emit(C, P, i, proc - 2, base_e + kk < cap_e ? base_e + kk : -1, s);
         }
       }
     }
@@ -847,30 +819,69 @@ __global__ void __launch_bounds__(kBlock) k_drain_done(CaseDev* __restrict__ C) 
 // every workgroup does the same amount of work, and E is loaded and the
 // deposit flushed once per workgroup.
 //
-// Every particle: gather E from LDS, leapfrog, wall test, the collision test
-// (one Philox call and one exp for an electron; the thermal target draw
-// first for an ion), store x and v_x, deposit the new x into the
-// workgroup's LDS histogram.  A colliding particle's process is selected
-// here; an ionization deposits its two newborns (same position as the
-// parent: the electron doubles the parent's share, the ion goes to the next
-// ion step's density).  Each wave compacts its events with a ballot into
-// its own 64-entry part of the chunk's queue and writes one record word:
-// events | ionizations << 7 | absorbed at x=0 << 14 | absorbed at x=L << 21.
-// Waves never synchronise inside the loop; the kernel has no returning
-// atomics and no two waves share a counter.
+// Every particle: gather E from LDS, leapfrog, wall test, deposit the new x
+// into the workgroup's LDS histogram, store x and v_x, and one Philox call
+// for its collision uniform R.  Only R below a bound of the collision
+// probability over the tables (the null-collision P*, with a relative
+// margin for the direct test), or a speed beyond the range that bound
+// covers, can give a collision; such candidates (a few percent) go to the
+// wave's LDS segment and everyone else is done.  The candidates get the
+// exact test -- energy bin, table lookups, exp, for ions the thermal target
+// first -- in dense passes: all of the workgroup's at the end as one list,
+// or a wave's own when its segment fills.  So the table work and the
+// transcendentals run on full waves instead of on every wave with one
+// candidate lane.  An ionization adds its newborns' charge (the electron a
+// second share at the parent's x, the ion to the next ion step's density).
+// Colliders are appended to the workgroup's event list (one LDS atomic per
+// wave) and the workgroup writes one record {events, births, absorbed at
+// x=0, absorbed at x=L}.  There are no global returning atomics and no
+// counter shared between workgroups.
 //
 // Dynamic LDS: E[ng] double, H[ng] deposit; with particle diagnostics also
-// J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).
+// J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).  Static: the
+// candidate segments (4 KiB).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
   // set bits of mask below this lane
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Candidate segment entries per wave of a particle workgroup.
+constexpr int kSeg = 256;
+
+// Event of a particle step: slot | process << 32 | birth rank << 34.
+__device__ __forceinline__ int64_t event_code(int64_t i, int proc, int64_t brank) {
+  return i | ((int64_t)proc << 32) | (brank << 34);
+}
+
+// Append one wave's events (lanes with ev) to its workgroup's list; list
+// positions and birth ranks come from the workgroup's LDS counters, one
+// atomic per wave.  Called by every lane of the wave.
+__device__ __forceinline__ void push_events(bool ev, bool birth, int64_t i, int proc, int* sCnt,
+                                            EDP_GLOBAL int64_t* ent, int lane) {
+  const uint64_t me = __ballot(ev);
+  if (me == 0) return;
+  const uint64_t mb = __ballot(birth);
+  int e0 = 0, b0 = 0;
+  if (lane == 0) {
+    e0 = atomicAdd(&sCnt[0], (int)__popcll(me));
+    if (mb) b0 = atomicAdd(&sCnt[1], (int)__popcll(mb));
+  }
+  e0 = __shfl(e0, 0);
+  b0 = __shfl(b0, 0);
+  if (ev) ent[e0 + lane_rank(me)] = event_code(i, proc, birth ? b0 + lane_rank(mb) : 0);
+}
+
 template <int SP>
 __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const int j, const int nwg) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   extern __shared__ double psm[];
+  // candidate segments (one per wave), their fill, the workgroup's event and
+  // birth counters, the per-wave absorption totals
+  __shared__ int32_t sSeg[kBlock / kWave][kSeg];
+  __shared__ int sNc[kBlock / kWave];
+  __shared__ int sCnt[2];
+  __shared__ int sAbs[kBlock / kWave][2];
   const int64_t s = C->pstep;
   const int64_t n = C->n[SP];
   if (SP == 1 && (s % C->nsub) != 0) return;  // ions move on ion steps only
@@ -932,6 +943,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     }
   }
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x) sF[b] = 0;
+  if (threadIdx.x < 2) sCnt[threadIdx.x] = 0;
   __syncthreads();
 
   const int cur = C->cur[SP];
@@ -940,8 +952,9 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
   const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
   const EDP_GLOBAL uint64_t* __restrict__ UID = G(C->sp[SP].uid[cur]);
-  EDP_GLOBAL int32_t* __restrict__ ENT = G(C->cq_ent[SP]);
-  EDP_GLOBAL int32_t* __restrict__ REC = G(C->cq_rec[SP]);
+  // this workgroup's event list: its chunk range of the queue
+  EDP_GLOBAL int64_t* __restrict__ ENT = G(C->cq_ent[SP]) + c_lo * kChunk;
+  const int64_t base_slot = c_lo * kChunk;
   const double inv_dx = C->inv_dx, L_gap = C->L;
   const double dt = SP == 0 ? C->dt_e : C->dt_i;
   const double factor = SP == 0 ? C->factor_e : C->factor_i;
@@ -965,8 +978,129 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const double n_gas = C->n_gas;
   const double nu_star = SP == 0 ? C->nu_star_e : C->nu_star_i;
   const double p_null = SP == 0 ? C->p_null_e : C->p_null_i;
+  // candidate pre-test: R below this bound, or a speed beyond the bound's range
+  const double p_cand = null_coll ? p_null : (SP == 0 ? C->p_bound_e : C->p_bound_i);
+  const double v2_cand = null_coll ? __builtin_huge_val() : (SP == 0 ? C->v2_lim_e : C->g2_lim_i);
+  const double a2_i = C->a2_i;
+  const uint32_t r_tag = SP == 0 ? tag(0, 0, 0) : tag(1, 0, 2);
   const int w = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
-  int tq = 0, tz = 0, tap = 0, tag_ = 0;  // this wave's totals over the workgroup's chunks
+  int tap = 0, tag_ = 0;  // this wave's absorptions over the workgroup's chunks
+  int ncw = 0;             // entries in this wave's candidate segment
+
+  // Step 6 for candidates, in dense passes: entry k of `count` (k = first,
+  // first + stride, ...; the loop bound is uniform over the participating
+  // waves) is the particle at slot base_slot + list(k).  The exact test
+  // (direct: P = 1 - exp(-n sigma_tot g dt), collide iff R < P, process by
+  // sigma_k / sigma_tot; null collision: process by R nu* against the
+  // cumulative nu_k, the rest null), then an ionization's newborn charge and
+  // the events of the colliders.
+  auto process = [&](const bool wg_list, const int count, const int first, const int stride) {
+    for (int b0 = 0; b0 < count; b0 += stride) {
+      const int k = b0 + first;
+      const bool act = k < count;
+      int64_t i = 0;
+      double xn = 0.0, vxn = 0.0, vy = 0.0, vz = 0.0;
+      uint64_t uid = 0;
+      if (act) {
+        int e;
+        if (wg_list) {  // the workgroup's segments, one after another
+          int kk = k, sg = 0;
+          while (kk >= sNc[sg]) kk -= sNc[sg++];
+          e = sSeg[sg][kk];
+        } else {
+          e = sSeg[w][k];
+        }
+        i = base_slot + e;
+        xn = X[i];
+        vxn = VX[i];
+        vy = VY[i];
+        vz = VZ[i];
+        uid = UID[i];
+      }
+      int proc = -1;
+      if (act) {
+        double r_coll, r_proc;
+        uniform2(seed, uid, st, r_tag, r_coll, r_proc);
+        if (null_coll) {
+          double g, c1, c2, c3;
+          int idx;
+          if (SP == 0) {
+            const double v2 = vxn * vxn + vy * vy + vz * vz;
+            g = sqrt(v2);
+            const double energy = 0.5 * kEMass * v2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            c1 = (n_gas * sig0[idx]) * g;
+            c2 = c1 + (n_gas * sig1[idx]) * g;
+            c3 = c2 + (n_gas * sig2[idx]) * g;
+          } else {
+            double z0, z1, z2;
+            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+            const double g2 = gx * gx + gy * gy + gz * gz;
+            g = sqrt(g2);
+            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            c1 = (n_gas * sig0[idx]) * g;
+            c2 = c1 + (n_gas * sig1[idx]) * g;
+            c3 = c2;
+          }
+          if (c3 > nu_star) gl_add(&Cw->ctr[kAnomaly], 1);
+          const double t = r_proc * nu_star;
+          proc = t < c1 ? 0 : (t < c2 ? 1 : (SP == 0 && t < c3 ? 2 : -1));
+        } else {
+          double p_coll;
+          int idx;
+          if (SP == 0) {
+            const double v2 = vxn * vxn + vy * vy + vz * vz;
+            const double v = sqrt(v2);
+            const double energy = 0.5 * kEMass * v2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            const double nu = nsig[idx] * v;
+            p_coll = 1.0 - exp(-nu * dt);
+          } else {
+            double z0, z1, z2;
+            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+            const double g2 = gx * gx + gy * gy + gz * gz;
+            const double g = sqrt(g2);
+            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            const double nu = nsig[idx] * g;
+            p_coll = 1.0 - exp(-nu * dt);
+          }
+          if (r_coll < p_coll) {
+            if (SP == 0) {
+              const double s_el = sig0[idx], s_exc = sig1[idx], s_ion = sig2[idx];
+              const double s_tot = s_el + s_exc + s_ion;
+              if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
+                proc = 0;
+              else if (r_proc < (s_el + s_exc) / s_tot)
+                proc = 1;
+              else
+                proc = 2;
+            } else {
+              const double s_iso = sig0[idx], s_back = sig1[idx];
+              proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
+            }
+          }
+        }
+      }
+      const bool coll = proc >= 0;
+      const bool ioniz = SP == 0 && proc == 2;
+      if (ioniz) {
+        // the newborns sit at the parent's position: the electron adds a
+        // second share to this step's deposit, the ion goes to the next ion
+        // step's density
+        long long r;
+        const int q = deposit_split(xn, inv_dx, ng, r);
+        lds_add(&sH[q], 4294967296LL - r);
+        lds_add(&sH[q + 1], r);
+        gl_add(&cnt_i_next[q], 4294967296LL - r);
+        gl_add(&cnt_i_next[q + 1], r);
+      }
+      push_events(coll, ioniz, i, proc, sCnt, ENT, lane);
+    }
+  };
 
   for (int64_t c = c_lo; c < c_hi; ++c) {
     const int slot = w * kWave + lane;  // slot in the chunk
@@ -981,8 +1115,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       uid = UID[i];
     }
     bool live = x == x;  // past the end, or absorbed earlier (tombstone)
-    bool abs_pow = false, abs_gnd = false, coll = false, ioniz = false, surf = false;
-    int proc = 0;
+    bool abs_pow = false, abs_gnd = false, surf = false, cand = false;
     double xn = 0.0, vxn = 0.0;
     if (live) {
       // Steps 3-4: field at the particle and leapfrog.
@@ -1073,128 +1206,64 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
           atomicAdd(&sF[(abs_gnd ? n_ifed + 1 : 0) + b], 1u);
         }
       } else {
-        // Step 6: collision test.  Direct: P = 1 - exp(-n sigma_tot(E) g dt),
-        // collide iff R < P, process by sigma_k/sigma_tot.  Null collision:
-        // candidate iff R < P* (no table work for the others), process by
-        // R nu* against the cumulative nu_k = (n sigma_k) g, the rest null.
-        double r_coll, r_proc;
-        int idx = 0;
+        // Step 7 for step s+1: deposit the new position.  Step 6 pre-test:
+        // a particle can collide only if its R is below the bound of
+        // 1 - exp(-nu dt) over the tables (exactly P* for null collisions),
+        // or if it is faster than the range that bound covers; the others
+        // are settled here with no table work, the candidates go to the
+        // wave's segment for the exact test.
         long long r;
         const int q = deposit_split(xn, inv_dx, ng, r);
-        if (null_coll) {
-          uniform2(seed, uid, st, SP == 0 ? tag(0, 0, 0) : tag(1, 0, 2), r_coll, r_proc);
-          if (r_coll < p_null) {
-            double g, c1, c2, c3;
-            if (SP == 0) {
-              const double v2 = vxn * vxn + vy * vy + vz * vz;
-              g = sqrt(v2);
-              const double energy = 0.5 * kEMass * v2 / kEvToJ;
-              idx = energy_bin(energy, de_cs, nbins);
-              c1 = (n_gas * sig0[idx]) * g;
-              c2 = c1 + (n_gas * sig1[idx]) * g;
-              c3 = c2 + (n_gas * sig2[idx]) * g;
-            } else {
-              double z0, z1, z2;
-              normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
-              const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
-              const double g2 = gx * gx + gy * gy + gz * gz;
-              g = sqrt(g2);
-              const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-              idx = energy_bin(energy, de_cs, nbins);
-              c1 = (n_gas * sig0[idx]) * g;
-              c2 = c1 + (n_gas * sig1[idx]) * g;
-              c3 = c2;
-            }
-            if (c3 > nu_star) gl_add(&Cw->ctr[kAnomaly], 1);
-            const double t = r_proc * nu_star;
-            proc = t < c1 ? 0 : (t < c2 ? 1 : (SP == 0 && t < c3 ? 2 : -1));
-            coll = proc >= 0;
-          }
-        } else {
-          double p_coll;
-          if (SP == 0) {
-            const double v2 = vxn * vxn + vy * vy + vz * vz;
-            const double v = sqrt(v2);
-            const double energy = 0.5 * kEMass * v2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            const double nu = nsig[idx] * v;
-            p_coll = 1.0 - exp(-nu * dt);
-            uniform2(seed, uid, st, tag(0, 0, 0), r_coll, r_proc);
-          } else {
-            double z0, z1, z2;
-            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
-            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
-            const double g2 = gx * gx + gy * gy + gz * gz;
-            const double g = sqrt(g2);
-            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            const double nu = nsig[idx] * g;
-            p_coll = 1.0 - exp(-nu * dt);
-            uniform2(seed, uid, st, tag(1, 0, 2), r_coll, r_proc);
-          }
-          coll = r_coll < p_coll;
-          if (coll) {
-            if (SP == 0) {
-              const double s_el = sig0[idx], s_exc = sig1[idx], s_ion = sig2[idx];
-              const double s_tot = s_el + s_exc + s_ion;
-              if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
-                proc = 0;
-              else if (r_proc < (s_el + s_exc) / s_tot)
-                proc = 1;
-              else
-                proc = 2;
-            } else {
-              const double s_iso = sig0[idx], s_back = sig1[idx];
-              proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
-            }
-          }
-        }
-        if (SP == 0 && coll && proc == 2) {
-          ioniz = true;
-          gl_add(&cnt_i_next[q], 4294967296LL - r);
-          gl_add(&cnt_i_next[q + 1], r);
-        }
-        // the parent, plus the newborn electron of an ionization
-        const long long mult = ioniz ? 2 : 1;
-        lds_add(&sH[q], mult * (4294967296LL - r));
-        lds_add(&sH[q + 1], mult * r);
+        lds_add(&sH[q], 4294967296LL - r);
+        lds_add(&sH[q + 1], r);
+        double r_coll, r_proc;
+        uniform2(seed, uid, st, r_tag, r_coll, r_proc);
+        const double v2 = vxn * vxn + vy * vy + vz * vz;
+        cand = r_coll < p_cand || (SP == 0 ? v2 : 2.0 * (v2 + a2_i)) > v2_cand;
       }
     }
     if (i < n && x == x) {
       X[i] = live ? xn : __longlong_as_double(0x7FF8000000000000LL);
       VX[i] = vxn;
     }
-    // the wave's events, in lane order; births numbered in the same order.
-    // An ion's secondary emission is an event of process 2 (x = 0) or 3
-    // (x = L) with one electron birth.
-    const bool see = SP == 1 && surf;
-    if (see) proc = abs_pow ? 2 : 3;
-    const bool ev = coll || see;
-    const uint64_t m_coll = __ballot(ev);
-    const uint64_t m_ion = __ballot(ioniz || see);
-    if (ev) {
-      const int code = slot | (proc << 10) | (lane_rank(m_ion) << 12);
-      ENT[c * kChunk + w * kWave + lane_rank(m_coll)] = code;
-    }
     if (surf_on) {
-      // reflections (electrons) or emissions per electrode (ions)
+      // reflections (electrons) or emissions per electrode (ions); an ion's
+      // secondary emission is an event of process 2 (x = 0) or 3 (x = L)
+      // with one electron birth
       const uint64_t m_s0 = __ballot(surf && (SP == 0 || abs_pow));
       const uint64_t m_s1 = SP == 1 ? __ballot(surf && abs_gnd) : 0ull;
       if (lane == 0 && m_s0) gl_add(&Cw->ctr[SP == 0 ? kRefl : kSeePow], (long long)__popcll(m_s0));
       if (lane == 0 && m_s1) gl_add(&Cw->ctr[kSeeGnd], (long long)__popcll(m_s1));
+      if (SP == 1) push_events(surf, surf, i, abs_pow ? 2 : 3, sCnt, ENT, lane);
     }
-    const uint64_t m_ap = __ballot(abs_pow), m_ag = __ballot(abs_gnd);
-    tq += __popcll(m_coll);
-    tz += __popcll(m_ion);
-    tap += __popcll(m_ap);
-    tag_ += __popcll(m_ag);
-    if (lane == 0)
-      REC[c * 4 + w] = __popcll(m_coll) | (__popcll(m_ion) << 7) | (__popcll(m_ap) << 14) | (__popcll(m_ag) << 21);
+    const uint64_t m_c = __ballot(cand);
+    if (m_c) {
+      if (cand) sSeg[w][ncw + lane_rank(m_c)] = (int32_t)(i - base_slot);
+      ncw += __popcll(m_c);
+      if (ncw > kSeg - kWave) {
+        // a full segment: the wave finishes its own candidates now (the
+        // fence makes the other lanes' stores of x and v_x visible)
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        process(false, ncw, lane, kWave);
+        ncw = 0;
+      }
+    }
+    tap += __popcll(__ballot(abs_pow));
+    tag_ += __popcll(__ballot(abs_gnd));
   }
-  __shared__ rec4 sT[kBlock / kWave];
-  if (lane == 0) sT[w] = rec4{tq, tz, tap, tag_};
+  if (lane == 0) {
+    sNc[w] = ncw;
+    sAbs[w][0] = tap;
+    sAbs[w][1] = tag_;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) ((EDP_GLOBAL rec4*)G(Cw->q_wg[SP]))[j] = sT[0] + sT[1] + sT[2] + sT[3];
+  // the remaining candidates of all waves, as one list over the workgroup
+  process(true, sNc[0] + sNc[1] + sNc[2] + sNc[3], (int)threadIdx.x, kBlock);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    ((EDP_GLOBAL rec4*)G(Cw->q_wg[SP]))[j] =
+        rec4{sCnt[0], sCnt[1], sAbs[0][0] + sAbs[1][0] + sAbs[2][0] + sAbs[3][0],
+             sAbs[0][1] + sAbs[1][1] + sAbs[2][1] + sAbs[3][1]};
   // flush: deposit for step s+1 and diagnostics of step s
   int64_t* dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
   for (int q = threadIdx.x; q < ng; q += blockDim.x) {
