@@ -649,13 +649,16 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
     // births of the lists before this range (for ions: after every electron birth)
     int64_t zrun = 0;
     if (births) {
+      // independent loads (at most kMaxPartWG / kBlock per thread), all in flight together
       int64_t zp = 0;
-      for (int64_t k = threadIdx.x; k < j0; k += blockDim.x) zp += wg[k].y;
+#pragma unroll 8
+      for (int64_t k = threadIdx.x; k < j0; k += kBlock) zp += wg[k].y;
       if (sp == 1) {
         const int64_t pe = C->q_per[0];
         const int64_t nwe = pe > 0 ? (C->q_nblk[0] + pe - 1) / pe : 0;
         const EDP_GLOBAL rec4* __restrict__ wge = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
-        for (int64_t k = threadIdx.x; k < nwe; k += blockDim.x) zp += wge[k].y;
+#pragma unroll 8
+        for (int64_t k = threadIdx.x; k < nwe; k += kBlock) zp += wge[k].y;
       }
       (void)block_exclusive_scan_t<int64_t>(zp, sRed, &zrun);
     }
@@ -663,9 +666,15 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
       const int64_t jj = jb + grp;
       const bool valid = jj < j1;
       rec4 r = {0, 0, 0, 0};
-      if (valid) r = wg[jj];
+      int64_t code0 = 0;
       const EDP_GLOBAL int64_t* __restrict__ e = ent + jj * per * kChunk;
-      const int64_t code0 = valid && l < r.x ? e[l] : 0;
+      if (valid) {
+        // the first event of this lane is loaded with the record, not after
+        // it (a list region holds at least kChunk entries; unused ones are
+        // ignored below)
+        r = wg[jj];
+        code0 = e[l];
+      }
       int64_t zbase = 0;
       if (births) {
         int64_t tot;
