@@ -621,12 +621,12 @@ typedef int rec4 __attribute__((ext_vector_type(4)));  // per-workgroup queue re
 // step left one event list (in its chunk range of the queue) and a record
 // {events, births, absorbed at x=0, absorbed at x=L}; an event is
 // slot | process << 32 | birth rank in the list << 34.  Workgroup blk of
-// nblk takes a contiguous range of those lists, a group of 8 lanes one list.
+// nblk takes a contiguous range of those lists, a group of 16 lanes one list.
 // Newborns of list j go to q_base + (births of the lists before j) + rank;
 // secondary electrons of ion impacts (ion events of process 2, 3) follow
 // every electron birth of the step.  No atomics: every slot follows from the
 // records alone.
-constexpr int kApplyLanes = 8;
+constexpr int kApplyLanes = 16;
 constexpr int kApplyGroups = kBlock / kApplyLanes;  // lists per round of a workgroup
 
 __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, int nblk) {
