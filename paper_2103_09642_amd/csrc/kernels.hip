@@ -1379,26 +1379,16 @@ __global__ void __launch_bounds__(256) k_sort_hist(CaseDev* __restrict__ C, int 
 
 // Exclusive scan of the ng-1 cell counts (one workgroup); total -> sort_cnt[ng].
 __global__ void __launch_bounds__(1024) k_sort_scan(CaseDev* __restrict__ C) {
-  __shared__ int64_t sPart[1024];
+  __shared__ int64_t sRed[64];
   const int m = C->ng - 1;
   const int t = threadIdx.x, T = blockDim.x;
   const int per = (m + T - 1) / T;
-  const int lo = t * per, hi = lo + per < m ? lo + per : m;
+  const int lo = t * per < m ? t * per : m, hi = lo + per < m ? lo + per : m;
   int64_t acc = 0;
   for (int p = lo; p < hi; ++p) acc += C->sort_cnt[p];
-  sPart[t] = acc;
-  __syncthreads();
-  if (t == 0) {
-    int64_t run = 0;
-    for (int j = 0; j < T; ++j) {
-      const int64_t v = sPart[j];
-      sPart[j] = run;
-      run += v;
-    }
-    C->sort_cnt[C->ng] = run;
-  }
-  __syncthreads();
-  int64_t run = sPart[t];
+  int64_t total;
+  int64_t run = block_exclusive_scan_t<int64_t>(acc, sRed, &total);
+  if (t == 0) C->sort_cnt[C->ng] = total;
   for (int p = lo; p < hi; ++p) {
     const int64_t v = C->sort_cnt[p];
     C->sort_cnt[p] = run;
