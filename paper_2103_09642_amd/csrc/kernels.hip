@@ -646,23 +646,9 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
     const EDP_GLOBAL rec4* __restrict__ wg = (const EDP_GLOBAL rec4*)G(C->q_wg[sp]);
     const EDP_GLOBAL int64_t* __restrict__ ent = G(C->cq_ent[sp]);
     const bool births = sp == 0 || see_on;
-    // births of the lists before this range (for ions: after every electron birth)
-    int64_t zrun = 0;
-    if (births) {
-      // independent loads (at most kMaxPartWG / kBlock per thread), all in flight together
-      int64_t zp = 0;
-#pragma unroll 8
-      for (int64_t k = threadIdx.x; k < j0; k += kBlock) zp += wg[k].y;
-      if (sp == 1) {
-        const int64_t pe = C->q_per[0];
-        const int64_t nwe = pe > 0 ? (C->q_nblk[0] + pe - 1) / pe : 0;
-        const EDP_GLOBAL rec4* __restrict__ wge = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
-#pragma unroll 8
-        for (int64_t k = threadIdx.x; k < nwe; k += kBlock) zp += wge[k].y;
-      }
-      (void)block_exclusive_scan_t<int64_t>(zp, sRed, &zrun);
-    }
+    int64_t zrun = 0;  // births before the current round
     for (int64_t jb = j0; jb < j1; jb += kApplyGroups) {
+      const bool first = jb == j0;
       const int64_t jj = jb + grp;
       const bool valid = jj < j1;
       rec4 r = {0, 0, 0, 0};
@@ -677,10 +663,27 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
       }
       int64_t zbase = 0;
       if (births) {
+        // first round: the births of the lists before this range (for ions,
+        // after every electron birth), loads all in flight together and
+        // summed in the same scan as the round's births (low and high word;
+        // both totals stay below 2^31)
+        int64_t zp = 0;
+        if (first) {
+#pragma unroll 8
+          for (int64_t k = threadIdx.x; k < j0; k += kBlock) zp += wg[k].y;
+          if (sp == 1) {
+            const int64_t pe = C->q_per[0];
+            const int64_t nwe = pe > 0 ? (C->q_nblk[0] + pe - 1) / pe : 0;
+            const EDP_GLOBAL rec4* __restrict__ wge = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
+#pragma unroll 8
+            for (int64_t k = threadIdx.x; k < nwe; k += kBlock) zp += wge[k].y;
+          }
+        }
         int64_t tot;
-        const int64_t exc = block_exclusive_scan_t<int64_t>(l == 0 ? (int64_t)r.y : 0, sRed, &tot);
-        zbase = zrun + __shfl(exc, 0, kApplyLanes);  // births of the lower groups of this round
-        zrun += tot;
+        const int64_t exc = block_exclusive_scan_t<int64_t>(((int64_t)(l == 0 ? r.y : 0) << 32) | zp, sRed, &tot);
+        if (first) zrun = tot & 0xFFFFFFFFLL;
+        zbase = zrun + (__shfl(exc, 0, kApplyLanes) >> 32);  // births of the lower groups of this round
+        zrun += tot >> 32;
       }
       for (int k = l; k < r.x; k += kApplyLanes) {
         const int64_t code = k == l ? code0 : e[k];
