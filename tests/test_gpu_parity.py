@@ -428,3 +428,87 @@ def test_null_collision_multi_step_parity(ctx, xs_default, orc):
     for sp in (0, 1):
         compare_states(g.get_state(sp), o.get_state(sp), 1e-9, f"null sp{sp}")
     g.destroy()
+
+
+def _thomas(ctx):
+    from paper_2103_09642_amd import edupic
+    ctx.set_option(edupic.OPT_POISSON, edupic.POISSON_THOMAS)
+
+
+def _flux(ctx):
+    from paper_2103_09642_amd import edupic
+    ctx.set_option(edupic.OPT_POISSON, edupic.POISSON_FLUX)
+
+
+@pytest.mark.parametrize("step", [0, 5])
+def test_every_particle_a_candidate_flushes_segments(ctx, xs_default, orc, step):
+    """Cross sections x30 (ions x1200) at 30 Pa make nearly every particle a
+    collision candidate, and 1.5e6 particles per species give every particle workgroup several
+    chunks: each wave's candidate segment fills and is processed inside the
+    loop, the rest at the workgroup's end.  One step (ion step and
+    electron-only step) against the oracle: counters exact, particles to
+    1e-12, deposits exact (Thomas solve)."""
+    say(f"test_every_particle_a_candidate_flushes_segments step={step}")
+    xs = synthetic_xsec(scale=30.0)
+    xs["i_iso"], xs["i_back"] = xs["i_iso"] * 40.0, xs["i_back"] * 40.0
+    ctx.set_xsec(xs)
+    _thomas(ctx)
+    try:
+        n = 1_500_000
+        c = _case(pressure_pa=30.0, weight=3e4, ion_subcycle=5, cap_e=2 * n, cap_i=2 * n)
+        st = random_state(n, n, c["gap_m"], seed=61 + step, te_ev=3.0, hot_frac=0.05, hot_ev=40.0,
+                          ion_energy_ev=20.0)
+        g, o = make_pair(ctx, c, xs, orc)
+        set_both(g, o, st, step)
+        g.advance_steps(1)
+        o.step(1)
+        cg, co = g.counts(), o.counts()
+        for k in ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz", "anomaly"):
+            assert cg[k if k != "anomaly" else "anomalies"] == co[k], k
+        assert co["coll_e"] > n // 10
+        if step == 0:
+            assert co["coll_i"] > n // 20
+        for sp in (0, 1):
+            compare_states(g.get_state(sp), o.get_state(sp), 1e-12, f"sp{sp}")
+        ge, gi = g.deposit()
+        oe, oi = o.deposit()
+        assert np.array_equal(ge, oe) and np.array_equal(gi, oi)
+        g.destroy()
+    finally:
+        ctx.set_xsec(xs_default)
+        _flux(ctx)
+
+
+def test_energetic_particles_beyond_the_bound_range(ctx, xs_default, orc):
+    """Electrons of 0.5-3 keV and ions of 1-3 keV lie beyond the energy range
+    the collision-probability bound covers (four times the table range), so
+    they are tested exactly whatever their uniform: one ion step against the
+    oracle, counters exact, particles to 1e-12."""
+    say("test_energetic_particles_beyond_the_bound_range")
+    _thomas(ctx)
+    try:
+        c = _case(pressure_pa=50.0, weight=2e5, ion_subcycle=5, cap_e=200_000, cap_i=200_000)
+        st = random_state(40_000, 40_000, c["gap_m"], seed=71, te_ev=3.0)
+        rng = np.random.default_rng(72)
+        for key, mass, lo, hi in (("e", 9.1093837015e-31, 500.0, 3000.0),
+                                  ("i", 39.948 * 1.66053906660e-27, 1000.0, 3000.0)):
+            m = 8000
+            en = rng.uniform(lo, hi, m)
+            d = rng.normal(size=(3, m))
+            d /= np.linalg.norm(d, axis=0)
+            sp_ = np.sqrt(2 * en * 1.602176634e-19 / mass)
+            for k, comp in zip(("vx", "vy", "vz"), d):
+                st[key][k][-m:] = sp_ * comp
+        g, o = make_pair(ctx, c, xs_default, orc)
+        set_both(g, o, st, 0)
+        g.advance_steps(1)
+        o.step(1)
+        cg, co = g.counts(), o.counts()
+        for k in ("abs_e_pow", "abs_e_gnd", "abs_i_pow", "abs_i_gnd", "coll_e", "coll_i", "ioniz", "anomaly"):
+            assert cg[k if k != "anomaly" else "anomalies"] == co[k], k
+        assert co["ioniz"] > 100 and co["coll_i"] > 10
+        for sp in (0, 1):
+            compare_states(g.get_state(sp), o.get_state(sp), 1e-12, f"sp{sp}")
+        g.destroy()
+    finally:
+        _flux(ctx)
