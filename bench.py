@@ -69,7 +69,7 @@ def main():
                     help="profiling aid: time this many PIC steps instead of --steps RF cycles")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="profiling aid: first copy a device buffer of this size (counter calibration)")
-    ap.add_argument("--workload", choices=["large", "batch64"], default="large",
+    ap.add_argument("--workload", choices=["large", "batch64", "dual32"], default="large",
                     help="large: the single 2e6+2e6 case (default); batch64: the 64-case heterogeneous set")
     ap.add_argument("--null-collision", action="store_true",
                     help="select colliding particles by the null-collision method")
@@ -85,7 +85,7 @@ def main():
     import torch
     from paper_2103_09642_amd import edupic, workloads
 
-    if args.workload == "batch64":
+    if args.workload in ("batch64", "dual32"):
         return bench_batch(args)
 
     case = workloads.config_large()
@@ -195,9 +195,12 @@ def main():
 
 
 def bench_batch(args):
-    """64 heterogeneous cases (pressure, voltage, gap, grid, particle count and
-    N_t all differ), each advanced by RF cycles of its own; one batch call
-    per timed region, or one call per case with --sequential."""
+    """batch64: 64 heterogeneous cases (pressure, voltage, gap, grid, particle
+    count and N_t all differ), each advanced by RF cycles of its own.
+    dual32: 32 dual-frequency cases (1.937 + 27.12 MHz, 1e6 per species,
+    1000 nodes), each advanced by one 27.12 MHz period (2000 steps) per
+    benchmark step.  One batch call per timed region, or one call per case
+    with --sequential."""
     import torch
     from paper_2103_09642_amd import edupic, workloads
 
@@ -209,14 +212,28 @@ def bench_batch(args):
     # the high-pressure, high-voltage cases more than double their seeded
     # particle count within a few cycles: room for 8x
     cases = []
-    for k in range(1, 65):
-        c = workloads.config_batch(k, xs)
-        cases.append(ctx.create_case(dict(c, cap_e=8 * c["n_init_e"], cap_i=8 * c["n_init_i"])))
+    dual = args.workload == "dual32"
+    for k in range(1, 33 if dual else 65):
+        if dual:
+            # run as given: the stability report, not the creation check, flags these
+            c = workloads.config_dualfreq(k)
+            c = dict(c, flags=list(c.get("flags", [])) + ["allow_unstable"], cap_e=3 * c["n_init_e"],
+                     cap_i=3 * c["n_init_i"])
+        else:
+            c = workloads.config_batch(k, xs)
+            c = dict(c, cap_e=8 * c["n_init_e"], cap_i=8 * c["n_init_i"])
+        cases.append(ctx.create_case(c))
+    hf_steps = 2000  # one 27.12 MHz period of the dual-frequency cases
 
     def run(cycles):
         if args.sequential:
             for g in cases:
-                g.advance(cycles)
+                if dual:
+                    g.advance_steps(cycles * hf_steps)
+                else:
+                    g.advance(cycles)
+        elif dual:
+            ctx.advance_steps(cases, [cycles * hf_steps] * len(cases))
         else:
             ctx.advance(cases, [cycles] * len(cases))
 
@@ -245,8 +262,11 @@ def bench_batch(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "batched set: 64 heterogeneous cases (5-100 Pa, 100-500 V, 1.5-5 cm, "
-                               "200-1000 nodes, 1e4-5e5 particles per species); step = 1 RF cycle of every case",
+        "config": {"workload": ("batched dual-frequency set: 32 cases (2.5-20 Pa, 100-400 V at 1.937 MHz + "
+                                "50-200 V at 27.12 MHz, 2.5 cm, 1000 nodes, 1e6+1e6 particles each); "
+                                "step = one 27.12 MHz period (2000 PIC steps) of every case") if dual else
+                               ("batched set: 64 heterogeneous cases (5-100 Pa, 100-500 V, 1.5-5 cm, "
+                                "200-1000 nodes, 1e4-5e5 particles per species); step = 1 RF cycle of every case"),
                    "mode": ["plain", "graph"][args.mode],
                    "execution": "sequential" if args.sequential else "one batch",
                    "particle_steps": ps,
