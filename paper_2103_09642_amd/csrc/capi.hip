@@ -28,6 +28,7 @@ hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
 hipError_t launch_particles(const BatchDev* b, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
                             hipEvent_t ev1);
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp);
+size_t particle_static_lds(int sp);
 int particle_occupancy(int sp, size_t lds);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
 hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
@@ -164,7 +165,7 @@ int validate(const edp_case_desc* c) {
   const uint32_t meas = EDP_DIAG_EEPF | EDP_DIAG_CURRENT | EDP_DIAG_MEANE | EDP_DIAG_XT | EDP_DIAG_IFED;
   if ((c->flags & meas) && c->n_grid > 1024) return fail(EDP_EINVAL, "measurements support n_grid <= 1024");
   for (int sp = 0; sp < 2; ++sp)
-    if (particle_lds_bytes(c->n_grid, c->flags, c->n_eepf, c->n_ifed, sp) > 65536 - 8192)
+    if (particle_lds_bytes(c->n_grid, c->flags, c->n_eepf, c->n_ifed, sp) + particle_static_lds(sp) > 65536)
       return fail(EDP_EINVAL, "measurement histograms and grid exceed the workgroup's LDS");
   return EDP_OK;
 }

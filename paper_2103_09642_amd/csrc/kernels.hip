@@ -851,7 +851,8 @@ __global__ void __launch_bounds__(kBlock) k_drain_done(CaseDev* __restrict__ C) 
 //
 // Dynamic LDS: E[ng] double, H[ng] deposit; with particle diagnostics also
 // J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).  Static: the
-// candidate segments (4 KiB).
+// candidate segments (ions 4 KiB of slots; electrons 10 KiB of slots, v^2
+// and uids) and a few counters.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
   // set bits of mask below this lane
@@ -859,7 +860,13 @@ __device__ __forceinline__ int lane_rank(uint64_t mask) {
 }
 
 // Candidate segment entries per wave of a particle workgroup.
-constexpr int kSeg = 256;
+// Candidate segment per wave: ions keep the slot only (their exact test
+// reloads the state); electrons keep the slot, v^2 and uid, which is all
+// their exact test needs, so it reads nothing back from HBM.
+constexpr int kSegI = 256;
+constexpr int kSegE = 128;
+template <int SP>
+constexpr int seg_len() { return SP == 0 ? kSegE : kSegI; }
 
 // Event of a particle step: slot | process << 32 | birth rank << 34.
 __device__ __forceinline__ int64_t event_code(int64_t i, int proc, int64_t brank) {
@@ -888,9 +895,14 @@ template <int SP>
 __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const int j, const int nwg) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   extern __shared__ double psm[];
-  // candidate segments (one per wave), their fill, the workgroup's event and
-  // birth counters, the per-wave absorption totals
+  // candidate segments (one per wave; electrons with v^2 and uid), their
+  // fill, the workgroup's event and birth counters, the per-wave absorption
+  // totals
+  constexpr int kSeg = seg_len<SP>();
+  constexpr int kPay = SP == 0 ? kBlock / kWave : 1;
   __shared__ int32_t sSeg[kBlock / kWave][kSeg];
+  __shared__ double sV2[kPay][SP == 0 ? kSeg : 1];
+  __shared__ uint64_t sUid[kPay][SP == 0 ? kSeg : 1];
   __shared__ int sNc[kBlock / kWave];
   __shared__ int sCnt[2];
   __shared__ int sAbs[kBlock / kWave][2];
@@ -1011,23 +1023,25 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       const int k = b0 + first;
       const bool act = k < count;
       int64_t i = 0;
-      double xn = 0.0, vxn = 0.0, vy = 0.0, vz = 0.0;
+      double xn = 0.0, vxn = 0.0, vy = 0.0, vz = 0.0, v2e = 0.0;
       uint64_t uid = 0;
       if (act) {
-        int e;
+        int sg = w, kk = k;
         if (wg_list) {  // the workgroup's segments, one after another
-          int kk = k, sg = 0;
+          sg = 0;
           while (kk >= sNc[sg]) kk -= sNc[sg++];
-          e = sSeg[sg][kk];
-        } else {
-          e = sSeg[w][k];
         }
-        i = base_slot + e;
-        xn = X[i];
-        vxn = VX[i];
-        vy = VY[i];
-        vz = VZ[i];
-        uid = UID[i];
+        i = base_slot + sSeg[sg][kk];
+        if (SP == 0) {
+          v2e = sV2[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
+          uid = sUid[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
+        } else {
+          xn = X[i];
+          vxn = VX[i];
+          vy = VY[i];
+          vz = VZ[i];
+          uid = UID[i];
+        }
       }
       int proc = -1;
       if (act) {
@@ -1037,7 +1051,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
           double g, c1, c2, c3;
           int idx;
           if (SP == 0) {
-            const double v2 = vxn * vxn + vy * vy + vz * vz;
+            const double v2 = v2e;
             g = sqrt(v2);
             const double energy = 0.5 * kEMass * v2 / kEvToJ;
             idx = energy_bin(energy, de_cs, nbins);
@@ -1063,7 +1077,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
           double p_coll;
           int idx;
           if (SP == 0) {
-            const double v2 = vxn * vxn + vy * vy + vz * vz;
+            const double v2 = v2e;
             const double v = sqrt(v2);
             const double energy = 0.5 * kEMass * v2 / kEvToJ;
             idx = energy_bin(energy, de_cs, nbins);
@@ -1103,8 +1117,10 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         // the newborns sit at the parent's position: the electron adds a
         // second share to this step's deposit, the ion goes to the next ion
         // step's density
+        // (the parent's new x: stored by this workgroup before the fence or
+        // barrier that precedes every dense pass)
         long long r;
-        const int q = deposit_split(xn, inv_dx, ng, r);
+        const int q = deposit_split(X[i], inv_dx, ng, r);
         lds_add(&sH[q], 4294967296LL - r);
         lds_add(&sH[q + 1], r);
         gl_add(&cnt_i_next[q], 4294967296LL - r);
@@ -1128,7 +1144,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     }
     bool live = x == x;  // past the end, or absorbed earlier (tombstone)
     bool abs_pow = false, abs_gnd = false, surf = false, cand = false;
-    double xn = 0.0, vxn = 0.0;
+    double xn = 0.0, vxn = 0.0, v2 = 0.0;
     if (live) {
       // Steps 3-4: field at the particle and leapfrog.
       const double c0 = x * inv_dx;
@@ -1230,7 +1246,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         lds_add(&sH[q + 1], r);
         double r_coll, r_proc;
         uniform2(seed, uid, st, r_tag, r_coll, r_proc);
-        const double v2 = vxn * vxn + vy * vy + vz * vz;
+        v2 = vxn * vxn + vy * vy + vz * vz;
         cand = r_coll < p_cand || (SP == 0 ? v2 : 2.0 * (v2 + a2_i)) > v2_cand;
       }
     }
@@ -1250,7 +1266,14 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     }
     const uint64_t m_c = __ballot(cand);
     if (m_c) {
-      if (cand) sSeg[w][ncw + lane_rank(m_c)] = (int32_t)(i - base_slot);
+      if (cand) {
+        const int at = ncw + lane_rank(m_c);
+        sSeg[w][at] = (int32_t)(i - base_slot);
+        if (SP == 0) {
+          sV2[SP == 0 ? w : 0][SP == 0 ? at : 0] = v2;
+          sUid[SP == 0 ? w : 0][SP == 0 ? at : 0] = uid;
+        }
+      }
       ncw += __popcll(m_c);
       if (ncw > kSeg - kWave) {
         // a full segment: the wave finishes its own candidates now (the
@@ -1470,6 +1493,13 @@ __global__ void k_zero(int64_t* __restrict__ p, int64_t n) {
 // ---------------------------------------------------------------------------
 // Host-side launchers (same translation unit as the kernels).
 // ---------------------------------------------------------------------------
+// Static LDS of a species' particle kernel: the candidate segments with
+// their payload, plus a bound on the small per-wave counters.
+size_t particle_static_lds(int sp) {
+  const size_t waves = kBlock / kWave;
+  return sp == 0 ? waves * kSegE * (4 + 8 + 8) + 256 : waves * kSegI * 4 + 256;
+}
+
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp) {
   size_t doubles = (size_t)2 * ng;
   if (flags & kDiagParticle) {
