@@ -1074,13 +1074,18 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
           const double t = r_proc * nu_star;
           proc = t < c1 ? 0 : (t < c2 ? 1 : (SP == 0 && t < c3 ? 2 : -1));
         } else {
-          double p_coll;
+          double p_coll, s_a, s_b, s_c = 0.0;
           int idx;
           if (SP == 0) {
             const double v2 = v2e;
             const double v = sqrt(v2);
             const double energy = 0.5 * kEMass * v2 / kEvToJ;
             idx = energy_bin(energy, de_cs, nbins);
+            // the process tables with the total (one round trip; idx is a
+            // valid bin whatever the outcome)
+            s_a = sig0[idx];
+            s_b = sig1[idx];
+            s_c = sig2[idx];
             const double nu = nsig[idx] * v;
             p_coll = 1.0 - exp(-nu * dt);
           } else {
@@ -1091,12 +1096,14 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
             const double g = sqrt(g2);
             const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
             idx = energy_bin(energy, de_cs, nbins);
+            s_a = sig0[idx];
+            s_b = sig1[idx];
             const double nu = nsig[idx] * g;
             p_coll = 1.0 - exp(-nu * dt);
           }
           if (r_coll < p_coll) {
             if (SP == 0) {
-              const double s_el = sig0[idx], s_exc = sig1[idx], s_ion = sig2[idx];
+              const double s_el = s_a, s_exc = s_b, s_ion = s_c;
               const double s_tot = s_el + s_exc + s_ion;
               if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
                 proc = 0;
@@ -1105,7 +1112,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
               else
                 proc = 2;
             } else {
-              const double s_iso = sig0[idx], s_back = sig1[idx];
+              const double s_iso = s_a, s_back = s_b;
               proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
             }
           }
