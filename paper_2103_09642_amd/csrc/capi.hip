@@ -23,9 +23,9 @@
 #include "impl.hpp"
 
 namespace edp {
-hipError_t launch_head(const BatchDev* b, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st);
+hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st);
 hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
-hipError_t launch_particles(const BatchDev* b, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
+hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
                             hipEvent_t ev1);
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp);
 size_t particle_static_lds(int sp);
@@ -81,13 +81,24 @@ struct Case {
   bool failed = false;
 };
 
+// Workgroups per case of each batched launch: prefix offsets, one range per
+// case in case order.
+struct BatchTable {
+  int32_t ncase;
+  int32_t part_off[2][kMaxBatch + 1];  // particle workgroups per species
+  int32_t apply_off[kMaxBatch + 1];    // collision workgroups of the head
+};
+
 // The cases of one lockstep run and everything derived from them: the
-// device table the kernels read, grid sizes, and the captured graph.
+// workgroup tables, grid sizes, and the captured graph.
 struct Batch {
   std::vector<Case*> cases;
-  BatchDev h{};
+  BatchTable h{};
   int parts[2] = {0, 0};  // particle workgroups per species
   int apply = 0;          // collision workgroups of the head
+  // roles of the electron, ion and head launches' workgroups in the
+  // context's device table
+  size_t role_off[3] = {0, 0, 0};
   int max_ng = 2;
   size_t lds[2] = {0, 0};
   // graph of g_steps steps, valid for these cases at these step phases and
@@ -113,8 +124,10 @@ struct edp_ctx {
   edp_case next_id = 1;
   // options
   int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, poisson = 0;
-  // the batch table (device copy owned by the context) and its run state
-  BatchDev* batch_d = nullptr;
+  // the workgroup roles of the batch's launches (device table owned by the
+  // context) and the batch's run state
+  BlockRole* roles_d = nullptr;
+  size_t roles_cap = 0;
   Batch batch;
   bool batch_valid = false;
   // profiling
@@ -384,21 +397,42 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   if (same) return EDP_OK;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   drop_graph(ctx);
+  ctx->batch_valid = false;
   B.cases = cs;
-  B.h = BatchDev{};
+  B.h = BatchTable{};
   B.h.ncase = (int32_t)nc;
   B.max_ng = max_ng;
   B.lds[0] = lds[0];
   B.lds[1] = lds[1];
   for (size_t k = 0; k < nc; ++k) {
-    B.h.c[k] = cs[k]->d;
     for (int sp = 0; sp < 2; ++sp) B.h.part_off[sp][k + 1] = B.h.part_off[sp][k] + want[sp][k];
     B.h.apply_off[k + 1] = B.h.apply_off[k] + want_apply[k];
   }
   B.parts[0] = B.h.part_off[0][nc];
   B.parts[1] = B.h.part_off[1][nc];
   B.apply = B.h.apply_off[nc];
-  HIPCHK(hipMemcpy(ctx->batch_d, &B.h, sizeof(BatchDev), hipMemcpyHostToDevice));
+  // roles: electrons, ions, then the head (fields, collisions, totals)
+  std::vector<BlockRole> roles;
+  roles.reserve((size_t)B.parts[0] + B.parts[1] + B.apply + 2 * nc);
+  for (int sp = 0; sp < 2; ++sp) {
+    B.role_off[sp] = roles.size();
+    for (size_t k = 0; k < nc; ++k)
+      for (int j = 0; j < want[sp][k]; ++j) roles.push_back(BlockRole{cs[k]->d, j, want[sp][k]});
+  }
+  B.role_off[2] = roles.size();
+  for (size_t k = 0; k < nc; ++k) roles.push_back(BlockRole{cs[k]->d, 0, 1});
+  for (size_t k = 0; k < nc; ++k)
+    for (int j = 0; j < want_apply[k]; ++j) roles.push_back(BlockRole{cs[k]->d, j, want_apply[k]});
+  for (size_t k = 0; k < nc; ++k) roles.push_back(BlockRole{cs[k]->d, 0, 1});
+  if (roles.size() > ctx->roles_cap) {
+    // no kernel is in flight (drained above)
+    if (ctx->roles_d) HIPCHK(hipFree(ctx->roles_d));
+    ctx->roles_d = nullptr;
+    ctx->roles_cap = 0;
+    HIPCHK(hipMalloc((void**)&ctx->roles_d, roles.size() * sizeof(BlockRole)));
+    ctx->roles_cap = roles.size();
+  }
+  HIPCHK(hipMemcpy(ctx->roles_d, roles.data(), roles.size() * sizeof(BlockRole), hipMemcpyHostToDevice));
   ctx->batch_valid = true;
   return EDP_OK;
 }
@@ -414,7 +448,7 @@ int enqueue_batch_step(edp_ctx* ctx, const std::vector<int64_t>& s, int64_t j, b
   Batch& B = ctx->batch;
   hipStream_t st = ctx->stream;
   const int nc = (int)B.cases.size();
-  HIPCHK(launch_head(ctx->batch_d, nc, B.apply, B.max_ng, ctx->poisson, st));
+  HIPCHK(launch_head(ctx->roles_d + B.role_off[2], nc, B.apply, B.max_ng, ctx->poisson, st));
   bool any_ion = false;
   for (int k = 0; k < nc; ++k) {
     const Case* c = B.cases[k];
@@ -431,9 +465,9 @@ int enqueue_batch_step(edp_ctx* ctx, const std::vector<int64_t>& s, int64_t j, b
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
   }
-  HIPCHK(launch_particles(ctx->batch_d, 0, B.parts[0], B.lds[0], st, e0, e1));
+  HIPCHK(launch_particles(ctx->roles_d + B.role_off[0], 0, B.parts[0], B.lds[0], st, e0, e1));
   if (e0) ctx->ev_pairs.emplace_back(e0, e1);
-  if (any_ion) HIPCHK(launch_particles(ctx->batch_d, 1, B.parts[1], B.lds[1], st, nullptr, nullptr));
+  if (any_ion) HIPCHK(launch_particles(ctx->roles_d + B.role_off[1], 1, B.parts[1], B.lds[1], st, nullptr, nullptr));
   return EDP_OK;
 }
 
@@ -621,10 +655,6 @@ int edp_create(edp_ctx** out, int device, void* hip_stream) {
   ctx->stream = (hipStream_t)hip_stream;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
-  if (hipMalloc((void**)&ctx->batch_d, sizeof(BatchDev)) != hipSuccess) {
-    delete ctx;
-    return fail(EDP_EHIP, "hipMalloc of the batch table failed");
-  }
   *out = ctx;
   return EDP_OK;
 }
@@ -633,7 +663,7 @@ int edp_destroy(edp_ctx* ctx) {
   if (!ctx) return EDP_OK;
   (void)hipStreamSynchronize(ctx->stream);
   drop_graph(ctx);
-  if (ctx->batch_d) (void)hipFree(ctx->batch_d);
+  if (ctx->roles_d) (void)hipFree(ctx->roles_d);
   for (auto& kv : ctx->cases) {
     Case* c = kv.second;
     if (c->vstage) (void)hipHostFree(c->vstage);

@@ -136,15 +136,13 @@ struct CaseDev {
 };
 
 // A batch of cases stepped together: every launch advances each case by one
-// step.  Workgroups find their case from the prefix offsets (one range per
-// case, in case order).
+// step.  Each workgroup of a batched launch reads its role from a table the
+// host builds with the batch -- its case, its index among that case's
+// workgroups of the same kind and their number -- in one scalar load.
 constexpr int kMaxBatch = 256;
-struct BatchDev {
-  int32_t ncase;
-  int32_t pad;
-  CaseDev* c[kMaxBatch];
-  int32_t part_off[2][kMaxBatch + 1];  // particle workgroups per species (chunks of capacity)
-  int32_t apply_off[kMaxBatch + 1];    // collision workgroups of the head
+struct BlockRole {
+  CaseDev* c;
+  int32_t j, n;
 };
 
 }  // namespace edp

@@ -280,7 +280,6 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
   double* sRho = fsm;
   double* sPhi = fsm + ng;    // MODE 1: d then phi; MODE 0: S_p then fluxes F_q
   double* sR = fsm + 2 * ng;  // MODE 1: Thomas reciprocals
-  double* sW = fsm + 3 * ng;  // scan scratch (64 doubles)
   const int64_t s = C->step;
   const int nsub = C->nsub;
   const int64_t k = s / nsub;
@@ -638,8 +637,11 @@ __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, i
   const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
   const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
   const bool see_on = C->see_on != 0;
+  // no pending queue: no lists (a value, not an early exit, so that every
+  // field of the case is loaded in one round trip)
+  const bool valid = C->q_valid != 0;
   for (int sp = 0; sp < 2; ++sp) {
-    const int64_t per = C->q_per[sp];
+    const int64_t per = valid ? C->q_per[sp] : 0;
     const int64_t nwg = per > 0 ? (C->q_nblk[sp] + per - 1) / per : 0;
     const int64_t j0 = nwg * blk / nblk, j1 = nwg * (blk + 1) / nblk;
     if (j0 >= j1) continue;  // uniform
@@ -763,40 +765,24 @@ __device__ __forceinline__ void fold_queue(CaseDev* __restrict__ Cw) {
   }
 }
 
-// The case of workgroup `bid` in a list of per-case ranges [off[k], off[k+1]):
-// every thread tests one range (ncase <= kMaxBatch = blockDim), the match is
-// broadcast through LDS.
-__device__ __forceinline__ int find_case(const int32_t* __restrict__ off, int ncase, int bid) {
-  __shared__ int sCase;
-  const int t = threadIdx.x;
-  if (t < ncase && G(off)[t] <= bid && bid < G(off)[t + 1]) sCase = t;
-  __syncthreads();
-  // uniform across the workgroup: keep it (and everything read through the
-  // case pointer) in scalar registers
-  return __builtin_amdgcn_readfirstlane(sCase);
-}
-
-// Head of step s for every case of the batch.  Workgroups [0, ncase) solve
-// the fields, the next apply_off[ncase] apply the queues of step s-1 (a range
-// per case), the last ncase fold each queue's totals into the counters and
-// do the step's bookkeeping.
+// Head of step s for every case of the batch.  Workgroups [0, nc) solve the
+// fields, the next na apply the queues of step s-1 (a range per case), the
+// last nc fold each queue's totals into the counters and do the step's
+// bookkeeping.  R: one role per workgroup.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_head(const BatchDev* __restrict__ B) {
+__global__ void __launch_bounds__(kBlock) k_head(const BlockRole* __restrict__ R, int nc, int na) {
   extern __shared__ double hsm[];
-  const int nc = B->ncase;
   const int bid = (int)blockIdx.x;
+  const EDP_CONST BlockRole* r = KC(R) + bid;
+  CaseDev* C = r->c;
   if (bid < nc) {
-    field_solve<MODE>(B->c[bid], hsm);
+    field_solve<MODE>(C, hsm);
     return;
   }
-  const int na = B->apply_off[nc];
   if (bid < nc + na) {
-    const int k = find_case(B->apply_off, nc, bid - nc);
-    CaseDev* C = B->c[k];
-    if (C->q_valid) apply_queue(C, bid - nc - B->apply_off[k], B->apply_off[k + 1] - B->apply_off[k]);
+    apply_queue(C, r->j, r->n);
     return;
   }
-  CaseDev* C = B->c[bid - nc - na];
   if (C->q_valid) fold_queue(C);
   if (threadIdx.x == 0) {
     const int64_t s = C->step;
@@ -811,7 +797,7 @@ __global__ void __launch_bounds__(kBlock) k_head(const BatchDev* __restrict__ B)
 // Apply the pending queue before the host looks at the state (the last
 // workgroup folds the totals).
 __global__ void __launch_bounds__(kBlock) k_drain(CaseDev* __restrict__ C) {
-  if (C->q_valid) apply_queue(C, (int)blockIdx.x, (int)gridDim.x);
+  apply_queue(C, (int)blockIdx.x, (int)gridDim.x);
 }
 __global__ void __launch_bounds__(kBlock) k_drain_done(CaseDev* __restrict__ C) {
   if (C->q_valid) fold_queue(C);
@@ -1023,7 +1009,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       const int k = b0 + first;
       const bool act = k < count;
       int64_t i = 0;
-      double xn = 0.0, vxn = 0.0, vy = 0.0, vz = 0.0, v2e = 0.0;
+      double vxn = 0.0, vy = 0.0, vz = 0.0, v2e = 0.0;
       uint64_t uid = 0;
       if (act) {
         int sg = w, kk = k;
@@ -1036,7 +1022,6 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
           v2e = sV2[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
           uid = sUid[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
         } else {
-          xn = X[i];
           vxn = VX[i];
           vy = VY[i];
           vz = VZ[i];
@@ -1326,11 +1311,9 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
 
 // One launch per species covers the chunks of every case of the batch.
 template <int SP>
-__global__ void __launch_bounds__(kBlock) k_particles(const BatchDev* __restrict__ B) {
-  const int bid = (int)blockIdx.x;
-  const int k = find_case(B->part_off[SP], B->ncase, bid);
-  const int j0 = B->part_off[SP][k];
-  particles_block<SP>(B->c[k], bid - j0, B->part_off[SP][k + 1] - j0);
+__global__ void __launch_bounds__(kBlock) k_particles(const BlockRole* __restrict__ R) {
+  const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
+  particles_block<SP>(r->c, r->j, r->n);
 }
 
 __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma) {
@@ -1519,15 +1502,15 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp
 }
 
 // Head of a batch step: ncase field workgroups, `apply_blocks` collision
-// workgroups in total and ncase totals workgroups.  `max_ng` sizes the field
-// workgroups' LDS.
-hipError_t launch_head(const BatchDev* b, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st) {
-  const size_t lds = (size_t)max_ng * 24 + 64 * 8;
+// workgroups in total and ncase totals workgroups, with their roles in this
+// order.  `max_ng` sizes the field workgroups' LDS.
+hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st) {
+  const size_t lds = (size_t)max_ng * 24;
   const dim3 grid(2 * ncase + apply_blocks);
   if (mode == 1)
-    hipLaunchKernelGGL(k_head<1>, grid, dim3(kBlock), lds, st, b);
+    hipLaunchKernelGGL(k_head<1>, grid, dim3(kBlock), lds, st, roles, ncase, apply_blocks);
   else
-    hipLaunchKernelGGL(k_head<0>, grid, dim3(kBlock), lds, st, b);
+    hipLaunchKernelGGL(k_head<0>, grid, dim3(kBlock), lds, st, roles, ncase, apply_blocks);
   return hipGetLastError();
 }
 
@@ -1537,21 +1520,21 @@ hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st) {
   return hipGetLastError();
 }
 
-// One species of a batch: `blocks` = the species' total chunk count;
-// `lds` = the largest per-case need.  With ev0/ev1 the launch records its own
+// One species of a batch: `blocks` workgroups with their roles; `lds` = the
+// largest per-case need.  With ev0/ev1 the launch records its own
 // start and end (the dispatch's timestamps, not those of separate event
 // packets around it).
-hipError_t launch_particles(const BatchDev* b, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
+hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
                             hipEvent_t ev1) {
   if (ev0) {
     if (sp == 0)
-      hipExtLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, b);
+      hipExtLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, roles);
     else
-      hipExtLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, b);
+      hipExtLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, roles);
   } else if (sp == 0) {
-    hipLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, b);
+    hipLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, roles);
   } else {
-    hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, b);
+    hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, roles);
   }
   return hipGetLastError();
 }
