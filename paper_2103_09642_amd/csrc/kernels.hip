@@ -65,8 +65,12 @@ __device__ __forceinline__ void uniform2(uint64_t seed, uint64_t uid, uint32_t s
 // Box-Muller: two standard normals from two uniforms (log argument in (0,1]).
 __device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
   const double r = sqrt(-2.0 * log(1.0 - u0));
-  z0 = r * cos(kTwoPi * u1);
-  z1 = r * sin(kTwoPi * u1);
+  // sincos: one argument reduction for both (the same values as separate
+  // sin and cos calls)
+  double sn, cs;
+  sincos(kTwoPi * u1, &sn, &cs);
+  z0 = r * cs;
+  z1 = r * sn;
 }
 
 // Three normals from calls first_call and first_call+1.
@@ -125,7 +129,8 @@ __device__ __forceinline__ void scatter(double gx, double gy, double gz, double 
     cos_phi = 1.0;
     sin_phi = 0.0;
   }
-  const double cos_eta = cos(eta), sin_eta = sin(eta);
+  double cos_eta, sin_eta;
+  sincos(eta, &sin_eta, &cos_eta);
   const double a = f2 * gnew;
   ox = wx + a * (cos_theta * cos_chi - sin_theta * sin_chi * cos_eta);
   oy = wy + a * (sin_theta * cos_phi * cos_chi + cos_theta * cos_phi * sin_chi * cos_eta -
@@ -522,10 +527,8 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
     if (C->flags & kIonizLiteral) {
       const double chi_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 0.0;
       const double chi_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 0.0;
-      cs_sc = cos(chi_sc);
-      sn_sc = sin(chi_sc);
-      cs_ej = cos(chi_ej);
-      sn_ej = sin(chi_ej);
+      sincos(chi_sc, &sn_sc, &cs_sc);
+      sincos(chi_ej, &sn_ej, &cs_ej);
     } else {
       cs_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 1.0;
       cs_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 1.0;
@@ -609,8 +612,10 @@ __device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C
   const double vt = sig * sqrt(-2.0 * log(1.0 - a1));
   P.ex[be] = side == 0 ? 0.0 : C->L;
   P.evx[be] = side == 0 ? vn : -vn;
-  P.evy[be] = vt * cos(kTwoPi * b0);
-  P.evz[be] = vt * sin(kTwoPi * b0);
+  double sn, cs;
+  sincos(kTwoPi * b0, &sn, &cs);
+  P.evy[be] = vt * cs;
+  P.evz[be] = vt * sn;
   P.euid[be] = child_uid(uid, s, 3);
 }
 
