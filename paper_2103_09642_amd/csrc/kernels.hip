@@ -282,9 +282,14 @@ template <int MODE>
 __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fsm) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int ng = C->ng;
+  // LDS rows padded by one slot per 16 nodes (node p at lp(p)): the flux
+  // scan's lanes own 16-node blocks, which would otherwise fall on the same
+  // banks
+  const int np = ng + (ng >> 4) + 1;
+  auto lp = [](int p) { return p + (p >> 4); };
   double* sRho = fsm;
-  double* sPhi = fsm + ng;    // MODE 1: d then phi; MODE 0: S_p then fluxes F_q
-  double* sR = fsm + 2 * ng;  // MODE 1: Thomas reciprocals
+  double* sPhi = fsm + np;    // MODE 1: d then phi; MODE 0: S_p then fluxes F_q
+  double* sR = fsm + 2 * np;  // MODE 1: Thomas reciprocals
   const int64_t s = C->step;
   const int nsub = C->nsub;
   const int64_t k = s / nsub;
@@ -324,10 +329,10 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       ni *= 2.0;
     }
     const double rho = kECharge * (ni - ne);
-    sRho[p] = rho;
+    sRho[lp(p)] = rho;
     if (MODE == 1) {
-      sR[p] = G(C->rden)[p];
-      sPhi[p] = rho * C->kpois;  // right-hand side d_p (boundary term below)
+      sR[lp(p)] = G(C->rden)[p];
+      sPhi[lp(p)] = rho * C->kpois;  // right-hand side d_p (boundary term below)
     }
     if (fl & kDiagDensity) {
       G(C->sum_ne)[p] += ne;
@@ -350,36 +355,36 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       const int m = ng - 2;
       double prev = 0.0;
       for (int p = 1; p <= m; ++p) {
-        double d = sPhi[p];
+        double d = sPhi[lp(p)];
         if (p == 1) d = d + V;
-        prev = (d + prev) * sR[p];
-        sPhi[p] = prev;
+        prev = (d + prev) * sR[lp(p)];
+        sPhi[lp(p)] = prev;
       }
-      for (int p = m - 1; p >= 1; --p) sPhi[p] = sPhi[p] + sR[p] * sPhi[p + 1];
-      sPhi[0] = V;
-      sPhi[ng - 1] = 0.0;
+      for (int p = m - 1; p >= 1; --p) sPhi[lp(p)] = sPhi[lp(p)] + sR[lp(p)] * sPhi[lp(p + 1)];
+      sPhi[lp(0)] = V;
+      sPhi[lp(ng - 1)] = 0.0;
     }
     __syncthreads();
     for (int p = threadIdx.x; p < ng; p += blockDim.x) {
       double e;
       if (p == 0)
-        e = (sPhi[0] - sPhi[1]) / dx - sRho[0] * dx / (2.0 * kEps0);
+        e = (sPhi[lp(0)] - sPhi[lp(1)]) / dx - sRho[lp(0)] * dx / (2.0 * kEps0);
       else if (p == ng - 1)
-        e = (sPhi[ng - 2] - sPhi[ng - 1]) / dx + sRho[ng - 1] * dx / (2.0 * kEps0);
+        e = (sPhi[lp(ng - 2)] - sPhi[lp(ng - 1)]) / dx + sRho[lp(ng - 1)] * dx / (2.0 * kEps0);
       else
-        e = (sPhi[p - 1] - sPhi[p + 1]) / (2.0 * dx);
+        e = (sPhi[lp(p - 1)] - sPhi[lp(p + 1)]) / (2.0 * dx);
       G(C->efield)[p] = e;
-      G(C->phi)[p] = sPhi[p];
-      G(C->rho)[p] = sRho[p];
+      G(C->phi)[p] = sPhi[lp(p)];
+      G(C->rho)[p] = sRho[lp(p)];
       if (xt) {
         X[kXtEf * plane + row + p] += e;
-        X[kXtFlux * plane + row + p] += p < ng - 1 ? sPhi[p] - sPhi[p + 1] : V;
+        X[kXtFlux * plane + row + p] += p < ng - 1 ? sPhi[lp(p)] - sPhi[lp(p + 1)] : V;
       }
     }
   } else {
     // One wave does the two scans (no workgroup barriers in between): lane l
     // owns the contiguous rows q0 <= q < q1 of the m = N_g - 2 interior rows
-    // (row q is node q+1), and sPhi[q+1] becomes F_{q+1}.
+    // (row q is node q+1), and node q+1's slot becomes F_{q+1}.
     if (threadIdx.x < kWave) {
       const int lane = (int)threadIdx.x;
       const int m = ng - 2;
@@ -389,8 +394,8 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       const int q1 = q0 + R < m ? q0 + R : m;
       double acc = 0.0;
       for (int q = q0; q < q1; ++q) {
-        acc += sRho[q + 1] * kp;
-        sPhi[q + 1] = acc;  // prefix within the lane
+        acc += sRho[lp(q + 1)] * kp;
+        sPhi[lp(q + 1)] = acc;  // prefix within the lane
       }
       double inc = acc;
 #pragma unroll
@@ -401,29 +406,29 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       const double before = inc - acc;
       double mine = 0.0;
       for (int q = q0; q < q1; ++q) {
-        const double S = before + sPhi[q + 1];
-        sPhi[q + 1] = S;
+        const double S = before + sPhi[lp(q + 1)];
+        sPhi[lp(q + 1)] = S;
         mine += S;
       }
 #pragma unroll
       for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
       const double F0 = (V - mine) / (double)(ng - 1);
-      for (int q = q0; q < q1; ++q) sPhi[q + 1] = F0 + sPhi[q + 1];
-      if (lane == 0) sPhi[0] = F0;
+      for (int q = q0; q < q1; ++q) sPhi[lp(q + 1)] = F0 + sPhi[lp(q + 1)];
+      if (lane == 0) sPhi[lp(0)] = F0;
     }
     __syncthreads();
     for (int p = threadIdx.x; p < ng; p += blockDim.x) {
       double e;
       if (p == 0)
-        e = sPhi[0] / dx - sRho[0] * dx / (2.0 * kEps0);
+        e = sPhi[lp(0)] / dx - sRho[lp(0)] * dx / (2.0 * kEps0);
       else if (p == ng - 1)
-        e = sPhi[ng - 2] / dx + sRho[ng - 1] * dx / (2.0 * kEps0);
+        e = sPhi[lp(ng - 2)] / dx + sRho[lp(ng - 1)] * dx / (2.0 * kEps0);
       else
-        e = (sPhi[p - 1] + sPhi[p]) / (2.0 * dx);
+        e = (sPhi[lp(p - 1)] + sPhi[lp(p)]) / (2.0 * dx);
       G(C->efield)[p] = e;
-      const double f = p < ng - 1 ? sPhi[p] : V;  // last slot keeps V for phi on demand
+      const double f = p < ng - 1 ? sPhi[lp(p)] : V;  // last slot keeps V for phi on demand
       G(C->flux)[p] = f;
-      G(C->rho)[p] = sRho[p];
+      G(C->rho)[p] = sRho[lp(p)];
       if (xt) {
         X[kXtEf * plane + row + p] += e;
         X[kXtFlux * plane + row + p] += f;
@@ -1510,7 +1515,7 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp
 // workgroups in total and ncase totals workgroups, with their roles in this
 // order.  `max_ng` sizes the field workgroups' LDS.
 hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st) {
-  const size_t lds = (size_t)max_ng * 24;
+  const size_t lds = (size_t)(max_ng + (max_ng >> 4) + 1) * 24;  // three padded rows
   const dim3 grid(2 * ncase + apply_blocks);
   if (mode == 1)
     hipLaunchKernelGGL(k_head<1>, grid, dim3(kBlock), lds, st, roles, ncase, apply_blocks);
