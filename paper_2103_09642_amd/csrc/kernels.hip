@@ -278,6 +278,9 @@ __device__ __forceinline__ void fold_particle_sums(const EDP_CONST CaseDev* __re
   }
 }
 
+// Interior rows per lane of the flux scan at the largest grid.
+constexpr int kScanRows = (kMaxNodes - 2 + kWave - 1) / kWave;
+
 template <int MODE>
 __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fsm) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
@@ -384,18 +387,24 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
   } else {
     // One wave does the two scans (no workgroup barriers in between): lane l
     // owns the contiguous rows q0 <= q < q1 of the m = N_g - 2 interior rows
-    // (row q is node q+1), and node q+1's slot becomes F_{q+1}.
+    // (row q is node q+1), and node q+1's slot becomes F_{q+1}.  A lane's
+    // rows stay in registers between one batch of LDS loads and one of
+    // stores.
     if (threadIdx.x < kWave) {
       const int lane = (int)threadIdx.x;
       const int m = ng - 2;
       const double kp = C->kpois;
-      const int R = (m + kWave - 1) / kWave;
+      const int R = (m + kWave - 1) / kWave;  // <= kScanRows
       const int q0 = lane * R < m ? lane * R : m;
-      const int q1 = q0 + R < m ? q0 + R : m;
+      const int nq = (q0 + R < m ? q0 + R : m) - q0;
+      double v[kScanRows];
+#pragma unroll
+      for (int t = 0; t < kScanRows; ++t) v[t] = t < nq ? sRho[lp(q0 + t + 1)] : 0.0;
       double acc = 0.0;
-      for (int q = q0; q < q1; ++q) {
-        acc += sRho[lp(q + 1)] * kp;
-        sPhi[lp(q + 1)] = acc;  // prefix within the lane
+#pragma unroll
+      for (int t = 0; t < kScanRows; ++t) {
+        if (t < nq) acc += v[t] * kp;
+        v[t] = acc;  // prefix within the lane
       }
       double inc = acc;
 #pragma unroll
@@ -405,15 +414,16 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
       }
       const double before = inc - acc;
       double mine = 0.0;
-      for (int q = q0; q < q1; ++q) {
-        const double S = before + sPhi[lp(q + 1)];
-        sPhi[lp(q + 1)] = S;
-        mine += S;
-      }
 #pragma unroll
+      for (int t = 0; t < kScanRows; ++t) {
+        v[t] = before + v[t];  // S_q
+        if (t < nq) mine += v[t];
+      }
       for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
       const double F0 = (V - mine) / (double)(ng - 1);
-      for (int q = q0; q < q1; ++q) sPhi[lp(q + 1)] = F0 + sPhi[lp(q + 1)];
+#pragma unroll
+      for (int t = 0; t < kScanRows; ++t)
+        if (t < nq) sPhi[lp(q0 + t + 1)] = F0 + v[t];
       if (lane == 0) sPhi[lp(0)] = F0;
     }
     __syncthreads();
