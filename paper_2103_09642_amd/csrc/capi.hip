@@ -360,6 +360,11 @@ void drop_graph(edp_ctx* ctx) {
   ctx->batch.g_steps = 0;
 }
 
+// Workgroup j of n of case c in a batched launch.
+BlockRole role(const Case* c, int j, int n) {
+  return BlockRole{c->d, c->h.efield, j, n, (int32_t)c->desc.n_grid, 0};
+}
+
 // Build the batch table for `cs` (in this order) and upload it.  Particle
 // workgroups: the chip's resident workgroups shared out in proportion to
 // each case's expected chunks, so every workgroup takes about the same
@@ -417,13 +422,13 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   for (int sp = 0; sp < 2; ++sp) {
     B.role_off[sp] = roles.size();
     for (size_t k = 0; k < nc; ++k)
-      for (int j = 0; j < want[sp][k]; ++j) roles.push_back(BlockRole{cs[k]->d, j, want[sp][k]});
+      for (int j = 0; j < want[sp][k]; ++j) roles.push_back(role(cs[k], j, want[sp][k]));
   }
   B.role_off[2] = roles.size();
-  for (size_t k = 0; k < nc; ++k) roles.push_back(BlockRole{cs[k]->d, 0, 1});
+  for (size_t k = 0; k < nc; ++k) roles.push_back(role(cs[k], 0, 1));
   for (size_t k = 0; k < nc; ++k)
-    for (int j = 0; j < want_apply[k]; ++j) roles.push_back(BlockRole{cs[k]->d, j, want_apply[k]});
-  for (size_t k = 0; k < nc; ++k) roles.push_back(BlockRole{cs[k]->d, 0, 1});
+    for (int j = 0; j < want_apply[k]; ++j) roles.push_back(role(cs[k], j, want_apply[k]));
+  for (size_t k = 0; k < nc; ++k) roles.push_back(role(cs[k], 0, 1));
   if (roles.size() > ctx->roles_cap) {
     // no kernel is in flight (drained above)
     if (ctx->roles_d) HIPCHK(hipFree(ctx->roles_d));

@@ -138,11 +138,15 @@ struct CaseDev {
 // A batch of cases stepped together: every launch advances each case by one
 // step.  Each workgroup of a batched launch reads its role from a table the
 // host builds with the batch -- its case, its index among that case's
-// workgroups of the same kind and their number -- in one scalar load.
+// workgroups of the same kind and their number, and the case's field array
+// and node count, so that a particle workgroup's E loads need not wait for
+// the case block -- in one scalar load.
 constexpr int kMaxBatch = 256;
 struct BlockRole {
   CaseDev* c;
+  const double* efield;
   int32_t j, n;
+  int32_t ng, pad;
 };
 
 }  // namespace edp

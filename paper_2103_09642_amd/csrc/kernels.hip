@@ -898,7 +898,8 @@ __device__ __forceinline__ void push_events(bool ev, bool birth, int64_t i, int 
 }
 
 template <int SP>
-__device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const int j, const int nwg) {
+__device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const double* __restrict__ efield,
+                                                const int ng, const int j, const int nwg) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   extern __shared__ double psm[];
   // candidate segments (one per wave; electrons with v^2 and uid), their
@@ -912,6 +913,23 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   __shared__ int sNc[kBlock / kWave];
   __shared__ int sCnt[2];
   __shared__ int sAbs[kBlock / kWave][2];
+  // E into LDS first: its address and size come with the workgroup's role,
+  // so these loads go out with those of the case block (a workgroup with no
+  // work this step returns below, after the barrier)
+  double* sE = psm;
+  {
+    double ev[kGridPerThread];
+#pragma unroll
+    for (int q = 0; q < kGridPerThread; ++q) {
+      const int p = threadIdx.x + q * kBlock;
+      ev[q] = p < ng ? G(efield)[p] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kGridPerThread; ++q) {
+      const int p = threadIdx.x + q * kBlock;
+      if (p < ng) sE[p] = ev[q];
+    }
+  }
   const int64_t s = C->pstep;
   const int64_t n = C->n[SP];
   if (SP == 1 && (s % C->nsub) != 0) return;  // ions move on ion steps only
@@ -933,7 +951,6 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const int64_t c_lo = (int64_t)j * per;
   const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
   if (c_lo >= c_hi) return;  // whole workgroup: nothing to do this step
-  const int ng = C->ng;
   const int nsub = C->nsub;
   const int64_t kion = s / nsub;
   const uint32_t fl = C->flags;
@@ -943,26 +960,12 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const int n_ifed = C->n_ifed;
   // histogram: the EEPF for electrons, the IFEDF of both electrodes for ions
   const int n_hist = SP == 0 ? ((fl & kDiagEepf) ? n_eepf : 0) : ((fl & kDiagIfed) ? 2 * (n_ifed + 1) : 0);
-  double* sE = psm;
   unsigned long long* sH = (unsigned long long*)(psm + ng);
   unsigned long long* sJ = sH + ng;
   unsigned long long* sW = sJ + ng;
   unsigned long long* sEn = sW + ng;
   unsigned long long* sIz = sEn + ng;  // electrons with the xt arrays only
   unsigned int* sF = (unsigned int*)(sIz + (SP == 0 && xt ? ng : 0));
-  {
-    double ev[kGridPerThread];
-#pragma unroll
-    for (int q = 0; q < kGridPerThread; ++q) {
-      const int p = threadIdx.x + q * kBlock;
-      ev[q] = p < ng ? G(C->efield)[p] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kGridPerThread; ++q) {
-      const int p = threadIdx.x + q * kBlock;
-      if (p < ng) sE[p] = ev[q];
-    }
-  }
   for (int p = threadIdx.x; p < ng; p += blockDim.x) {
     sH[p] = 0;
     if (pdiag) {
@@ -1333,7 +1336,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
 template <int SP>
 __global__ void __launch_bounds__(kBlock) k_particles(const BlockRole* __restrict__ R) {
   const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
-  particles_block<SP>(r->c, r->j, r->n);
+  particles_block<SP>(r->c, r->efield, r->ng, r->j, r->n);
 }
 
 __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma) {
