@@ -33,7 +33,8 @@ int particle_occupancy(int sp, size_t lds);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
 hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
                           hipStream_t st);
-hipError_t launch_sort(CaseDev* d, int sp, int ng, int blocks, hipStream_t st);
+hipError_t launch_sort(const BlockRole* roles, const BlockRole* case_roles, int sp, int blocks, int ncase, int max_ng,
+                       int every, hipStream_t st);
 hipError_t launch_fold(CaseDev* d, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 }  // namespace edp
@@ -87,6 +88,7 @@ struct BatchTable {
   int32_t ncase;
   int32_t part_off[2][kMaxBatch + 1];  // particle workgroups per species
   int32_t apply_off[kMaxBatch + 1];    // collision workgroups of the head
+  int32_t sort_off[2][kMaxBatch + 1];  // sort workgroups per species
 };
 
 // The cases of one lockstep run and everything derived from them: the
@@ -96,9 +98,11 @@ struct Batch {
   BatchTable h{};
   int parts[2] = {0, 0};  // particle workgroups per species
   int apply = 0;          // collision workgroups of the head
-  // roles of the electron, ion and head launches' workgroups in the
-  // context's device table
-  size_t role_off[3] = {0, 0, 0};
+  int sorts[2] = {0, 0};  // sort workgroups per species
+  // roles of the electron, ion, head, electron-sort and ion-sort launches'
+  // workgroups in the context's device table (the head's first ncase roles,
+  // one per case, also serve the per-case sort kernels)
+  size_t role_off[5] = {0, 0, 0, 0, 0};
   int max_ng = 2;
   size_t lds[2] = {0, 0};
   // graph of g_steps steps, valid for these cases at these step phases and
@@ -106,7 +110,6 @@ struct Batch {
   hipGraphExec_t gexec = nullptr;
   int g_steps = 0;
   std::vector<int64_t> g_phase;
-  std::vector<int> g_sort_e, g_sort_i;
 };
 
 }  // namespace
@@ -365,6 +368,9 @@ BlockRole role(const Case* c, int j, int n) {
   return BlockRole{c->d, c->h.efield, j, n, (int32_t)c->desc.n_grid, 0};
 }
 
+// Workgroups of a case's sort histogram and scatter.
+int sort_blocks(const edp_ctx* ctx, const Case* c, int sp) { return std::max(1, blocks_for(ctx, c->est[sp]) / 4); }
+
 // Build the batch table for `cs` (in this order) and upload it.  Particle
 // workgroups: the chip's resident workgroups shared out in proportion to
 // each case's expected chunks, so every workgroup takes about the same
@@ -393,11 +399,15 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
       want[sp][k] = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxPartWG, (est_chunks(cs[k], sp) + per - 1) / per));
   }
   for (size_t k = 0; k < nc; ++k) want_apply[k] = apply_blocks(ctx, cs[k]);
+  std::vector<int> want_sort[2];
+  for (int sp = 0; sp < 2; ++sp)
+    for (size_t k = 0; k < nc; ++k) want_sort[sp].push_back(sort_blocks(ctx, cs[k], sp));
   auto near = [](int a, int a0) { return a <= a0 * 5 / 4 + 1 && a >= a0 * 3 / 4; };
   bool same = ctx->batch_valid && B.cases == cs;
   for (size_t k = 0; k < nc && same; ++k) {
     same = near(want_apply[k], B.h.apply_off[k + 1] - B.h.apply_off[k]);
     for (int sp = 0; sp < 2 && same; ++sp) same = near(want[sp][k], B.h.part_off[sp][k + 1] - B.h.part_off[sp][k]);
+    for (int sp = 0; sp < 2 && same; ++sp) same = near(want_sort[sp][k], B.h.sort_off[sp][k + 1] - B.h.sort_off[sp][k]);
   }
   if (same) return EDP_OK;
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -412,13 +422,16 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   for (size_t k = 0; k < nc; ++k) {
     for (int sp = 0; sp < 2; ++sp) B.h.part_off[sp][k + 1] = B.h.part_off[sp][k] + want[sp][k];
     B.h.apply_off[k + 1] = B.h.apply_off[k] + want_apply[k];
+    for (int sp = 0; sp < 2; ++sp) B.h.sort_off[sp][k + 1] = B.h.sort_off[sp][k] + want_sort[sp][k];
   }
   B.parts[0] = B.h.part_off[0][nc];
   B.parts[1] = B.h.part_off[1][nc];
   B.apply = B.h.apply_off[nc];
+  B.sorts[0] = B.h.sort_off[0][nc];
+  B.sorts[1] = B.h.sort_off[1][nc];
   // roles: electrons, ions, then the head (fields, collisions, totals)
   std::vector<BlockRole> roles;
-  roles.reserve((size_t)B.parts[0] + B.parts[1] + B.apply + 2 * nc);
+  roles.reserve((size_t)B.parts[0] + B.parts[1] + B.apply + 2 * nc + B.sorts[0] + B.sorts[1]);
   for (int sp = 0; sp < 2; ++sp) {
     B.role_off[sp] = roles.size();
     for (size_t k = 0; k < nc; ++k)
@@ -429,6 +442,11 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   for (size_t k = 0; k < nc; ++k)
     for (int j = 0; j < want_apply[k]; ++j) roles.push_back(role(cs[k], j, want_apply[k]));
   for (size_t k = 0; k < nc; ++k) roles.push_back(role(cs[k], 0, 1));
+  for (int sp = 0; sp < 2; ++sp) {
+    B.role_off[3 + sp] = roles.size();
+    for (size_t k = 0; k < nc; ++k)
+      for (int j = 0; j < want_sort[sp][k]; ++j) roles.push_back(role(cs[k], j, want_sort[sp][k]));
+  }
   if (roles.size() > ctx->roles_cap) {
     // no kernel is in flight (drained above)
     if (ctx->roles_d) HIPCHK(hipFree(ctx->roles_d));
@@ -442,9 +460,6 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   return EDP_OK;
 }
 
-// Grid of a case's sort kernels.
-int sort_blocks(const edp_ctx* ctx, const Case* c, int sp) { return std::max(1, blocks_for(ctx, c->est[sp]) / 4); }
-
 // Step j of the current window (case k at step s[k] + j), plain launches:
 // one head for every case (fields of this step, collisions of the last),
 // the compaction/sort of the cases due for it, then one electron launch and,
@@ -454,17 +469,21 @@ int enqueue_batch_step(edp_ctx* ctx, const std::vector<int64_t>& s, int64_t j, b
   hipStream_t st = ctx->stream;
   const int nc = (int)B.cases.size();
   HIPCHK(launch_head(ctx->roles_d + B.role_off[2], nc, B.apply, B.max_ng, ctx->poisson, st));
-  bool any_ion = false;
+  bool any_ion = false, sort_e = false, sort_i = false;
   for (int k = 0; k < nc; ++k) {
-    const Case* c = B.cases[k];
     const int64_t sk = s[k] + j;
-    const int64_t nsub = c->desc.ion_subcycle;
-    if (sk % ctx->sort_every == 0)
-      HIPCHK(launch_sort(c->d, 0, c->desc.n_grid, capture ? B.g_sort_e[k] : sort_blocks(ctx, c, 0), st));
-    if (sk % ((int64_t)ctx->sort_every * nsub) == 0)
-      HIPCHK(launch_sort(c->d, 1, c->desc.n_grid, capture ? B.g_sort_i[k] : sort_blocks(ctx, c, 1), st));
+    const int64_t nsub = B.cases[k]->desc.ion_subcycle;
+    sort_e = sort_e || sk % ctx->sort_every == 0;
+    sort_i = sort_i || sk % ((int64_t)ctx->sort_every * nsub) == 0;
     any_ion = any_ion || sk % nsub == 0;
   }
+  // one set of sort launches per species for the whole batch; the cases that
+  // are not due skip them on the device
+  const BlockRole* case_roles = ctx->roles_d + B.role_off[2];
+  if (sort_e)
+    HIPCHK(launch_sort(ctx->roles_d + B.role_off[3], case_roles, 0, B.sorts[0], nc, B.max_ng, ctx->sort_every, st));
+  if (sort_i)
+    HIPCHK(launch_sort(ctx->roles_d + B.role_off[4], case_roles, 1, B.sorts[1], nc, B.max_ng, ctx->sort_every, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profile && !capture) {
     HIPCHK(hipEventCreate(&e0));
@@ -481,14 +500,8 @@ int build_graph(edp_ctx* ctx, const std::vector<int64_t>& s, int steps) {
   Batch& B = ctx->batch;
   drop_graph(ctx);
   const int nc = (int)B.cases.size();
-  B.g_sort_e.resize(nc);
-  B.g_sort_i.resize(nc);
   B.g_phase.resize(nc);
-  for (int k = 0; k < nc; ++k) {
-    B.g_sort_e[k] = sort_blocks(ctx, B.cases[k], 0);
-    B.g_sort_i[k] = sort_blocks(ctx, B.cases[k], 1);
-    B.g_phase[k] = s[k] % steps;
-  }
+  for (int k = 0; k < nc; ++k) B.g_phase[k] = s[k] % steps;
   hipStream_t st = ctx->stream;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -510,12 +523,8 @@ int build_graph(edp_ctx* ctx, const std::vector<int64_t>& s, int steps) {
 bool graph_matches(const edp_ctx* ctx, const std::vector<int64_t>& s, int steps) {
   const Batch& B = ctx->batch;
   if (!B.gexec || B.g_steps != steps) return false;
-  for (size_t k = 0; k < B.cases.size(); ++k) {
+  for (size_t k = 0; k < B.cases.size(); ++k)
     if (s[k] % steps != B.g_phase[k]) return false;
-    const int se = sort_blocks(ctx, B.cases[k], 0), si = sort_blocks(ctx, B.cases[k], 1);
-    const int e0 = B.g_sort_e[k], i0 = B.g_sort_i[k];
-    if (se > e0 * 5 / 4 + 1 || se < e0 * 3 / 4 || si > i0 * 5 / 4 + 1 || si < i0 * 3 / 4) return false;
-  }
   return true;
 }
 

@@ -1396,8 +1396,22 @@ __device__ __forceinline__ int cell_of(double x, double inv_dx, int ng) {
 
 
 
-__global__ void __launch_bounds__(256) k_sort_hist(CaseDev* __restrict__ C, int sp) {
+// The sort kernels serve a batch: one role per workgroup (a case's sort
+// workgroups, or one per case for the scan and the finish).  A case sorts its
+// electrons at steps that are multiples of `every` and its ions at multiples
+// of every * N_SUB; the workgroups of a case that is not due return at once,
+// so the host launches the four kernels only at steps where some case is due.
+__device__ __forceinline__ bool sort_due(const CaseDev* C, int sp, int every) {
+  const EDP_CONST CaseDev* K = KC(C);
+  const int64_t per = sp == 0 ? (int64_t)every : (int64_t)every * K->nsub;
+  return K->step % per == 0;
+}
+
+__global__ void __launch_bounds__(256) k_sort_hist(const BlockRole* __restrict__ R, int sp, int every) {
   extern __shared__ double hsm[];
+  const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
+  CaseDev* C = r->c;
+  if (!sort_due(C, sp, every)) return;
   unsigned int* sC = (unsigned int*)hsm;
   const int ng = C->ng;
   for (int p = threadIdx.x; p < ng; p += blockDim.x) sC[p] = 0;
@@ -1405,8 +1419,8 @@ __global__ void __launch_bounds__(256) k_sort_hist(CaseDev* __restrict__ C, int 
   const int cur = C->cur[sp];
   const EDP_GLOBAL double* __restrict__ X = G(C->sp[sp].x[cur]);
   const int64_t n = slots(C, sp);
-  const int64_t nb = gridDim.x, per = (n + nb - 1) / nb;
-  const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+  const int64_t nb = r->n, per = (n + nb - 1) / nb;
+  const int64_t lo = (int64_t)r->j * per, hi = lo + per < n ? lo + per : n;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const double x = X[i];
     if (x == x) atomicAdd(&sC[cell_of(x, C->inv_dx, ng)], 1u);
@@ -1417,8 +1431,10 @@ __global__ void __launch_bounds__(256) k_sort_hist(CaseDev* __restrict__ C, int 
 }
 
 // Exclusive scan of the ng-1 cell counts (one workgroup); total -> sort_cnt[ng].
-__global__ void __launch_bounds__(1024) k_sort_scan(CaseDev* __restrict__ C) {
+__global__ void __launch_bounds__(1024) k_sort_scan(const BlockRole* __restrict__ R, int sp, int every) {
   __shared__ int64_t sRed[64];
+  CaseDev* C = (KC(R) + blockIdx.x)->c;
+  if (!sort_due(C, sp, every)) return;
   const int m = C->ng - 1;
   const int t = threadIdx.x, T = blockDim.x;
   const int per = (m + T - 1) / T;
@@ -1435,8 +1451,11 @@ __global__ void __launch_bounds__(1024) k_sort_scan(CaseDev* __restrict__ C) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_sort_scatter(CaseDev* __restrict__ C, int sp) {
+__global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restrict__ R, int sp, int every) {
   extern __shared__ double ssm[];
+  const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
+  CaseDev* C = r->c;
+  if (!sort_due(C, sp, every)) return;
   unsigned int* sC = (unsigned int*)ssm;
   unsigned long long* sB = (unsigned long long*)(ssm + (C->ng + 1) / 2);
   const int ng = C->ng;
@@ -1446,8 +1465,8 @@ __global__ void __launch_bounds__(256) k_sort_scatter(CaseDev* __restrict__ C, i
   const SpeciesDev& S = C->sp[sp];
   const EDP_GLOBAL double* __restrict__ X = G(S.x[cur]);
   const int64_t n = slots(C, sp);
-  const int64_t nb = gridDim.x, per = (n + nb - 1) / nb;
-  const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+  const int64_t nb = r->n, per = (n + nb - 1) / nb;
+  const int64_t lo = (int64_t)r->j * per, hi = lo + per < n ? lo + per : n;
   const double inv_dx = C->inv_dx;
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const double x = X[i];
@@ -1473,7 +1492,9 @@ __global__ void __launch_bounds__(256) k_sort_scatter(CaseDev* __restrict__ C, i
   }
 }
 
-__global__ void k_sort_finish(CaseDev* __restrict__ C, int sp) {
+__global__ void k_sort_finish(const BlockRole* __restrict__ R, int sp, int every) {
+  CaseDev* C = (KC(R) + blockIdx.x)->c;
+  if (!sort_due(C, sp, every)) return;
   const int ng = C->ng;
   if (threadIdx.x == 0) {
     C->alloc[sp] = C->sort_cnt[ng];
@@ -1593,12 +1614,17 @@ hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int 
   return hipGetLastError();
 }
 
-hipError_t launch_sort(CaseDev* d, int sp, int ng, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(256), (size_t)ng * 4, st, d, sp);
-  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, d);
-  const size_t lds = (size_t)((ng + 1) / 2) * 8 + (size_t)ng * 8;
-  hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(256), lds, st, d, sp);
-  hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1024), 0, st, d, sp);
+// Compaction + cell sort of species sp for every case of a batch that is due
+// (see sort_due): `blocks` workgroups with roles `roles` for the histogram
+// and the scatter, one per case (`case_roles`, ncase of them) for the scan
+// and the finish; `max_ng` sizes the LDS.
+hipError_t launch_sort(const BlockRole* roles, const BlockRole* case_roles, int sp, int blocks, int ncase, int max_ng,
+                       int every, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(256), (size_t)max_ng * 4, st, roles, sp, every);
+  hipLaunchKernelGGL(k_sort_scan, dim3(ncase), dim3(1024), 0, st, case_roles, sp, every);
+  const size_t lds = (size_t)((max_ng + 1) / 2) * 8 + (size_t)max_ng * 8;
+  hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(256), lds, st, roles, sp, every);
+  hipLaunchKernelGGL(k_sort_finish, dim3(ncase), dim3(1024), 0, st, case_roles, sp, every);
   return hipGetLastError();
 }
 
