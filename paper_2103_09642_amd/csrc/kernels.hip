@@ -1401,6 +1401,8 @@ __device__ __forceinline__ int cell_of(double x, double inv_dx, int ng) {
 // electrons at steps that are multiples of `every` and its ions at multiples
 // of every * N_SUB; the workgroups of a case that is not due return at once,
 // so the host launches the four kernels only at steps where some case is due.
+constexpr int kSortUnroll = 4;
+
 __device__ __forceinline__ bool sort_due(const CaseDev* C, int sp, int every) {
   const EDP_CONST CaseDev* K = KC(C);
   const int64_t per = sp == 0 ? (int64_t)every : (int64_t)every * K->nsub;
@@ -1421,9 +1423,19 @@ __global__ void __launch_bounds__(256) k_sort_hist(const BlockRole* __restrict__
   const int64_t n = slots(C, sp);
   const int64_t nb = r->n, per = (n + nb - 1) / nb;
   const int64_t lo = (int64_t)r->j * per, hi = lo + per < n ? lo + per : n;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const double x = X[i];
-    if (x == x) atomicAdd(&sC[cell_of(x, C->inv_dx, ng)], 1u);
+  const double inv_dx = C->inv_dx;
+  // kSortUnroll particles per thread and round: their loads are in flight
+  // together
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kSortUnroll * kBlock) {
+    double x[kSortUnroll];
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u) {
+      const int64_t i = i0 + u * kBlock;
+      x[u] = i < hi ? X[i] : __longlong_as_double(0x7FF8000000000000LL);
+    }
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u)
+      if (x[u] == x[u]) atomicAdd(&sC[cell_of(x[u], inv_dx, ng)], 1u);
   }
   __syncthreads();
   for (int p = threadIdx.x; p < ng - 1; p += blockDim.x)
@@ -1468,9 +1480,16 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
   const int64_t nb = r->n, per = (n + nb - 1) / nb;
   const int64_t lo = (int64_t)r->j * per, hi = lo + per < n ? lo + per : n;
   const double inv_dx = C->inv_dx;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const double x = X[i];
-    if (x == x) atomicAdd(&sC[cell_of(x, inv_dx, ng)], 1u);
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kSortUnroll * kBlock) {
+    double x[kSortUnroll];
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u) {
+      const int64_t i = i0 + u * kBlock;
+      x[u] = i < hi ? X[i] : __longlong_as_double(0x7FF8000000000000LL);
+    }
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u)
+      if (x[u] == x[u]) atomicAdd(&sC[cell_of(x[u], inv_dx, ng)], 1u);
   }
   __syncthreads();
   for (int p = threadIdx.x; p < ng - 1; p += blockDim.x) {
@@ -1479,16 +1498,41 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
     sC[p] = 0;
   }
   __syncthreads();
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const double x = X[i];
-    if (!(x == x)) continue;
-    const int c = cell_of(x, inv_dx, ng);
-    const int64_t d = (int64_t)sB[c] + atomicAdd(&sC[c], 1u);
-    G(S.x[nxt])[d] = x;
-    G(S.vx[nxt])[d] = G(S.vx[cur])[i];
-    G(S.vy[nxt])[d] = G(S.vy[cur])[i];
-    G(S.vz[nxt])[d] = G(S.vz[cur])[i];
-    G(S.uid[nxt])[d] = G(S.uid[cur])[i];
+  const EDP_GLOBAL double* __restrict__ VX = G(S.vx[cur]);
+  const EDP_GLOBAL double* __restrict__ VY = G(S.vy[cur]);
+  const EDP_GLOBAL double* __restrict__ VZ = G(S.vz[cur]);
+  const EDP_GLOBAL uint64_t* __restrict__ UID = G(S.uid[cur]);
+  EDP_GLOBAL double* __restrict__ X2 = G(S.x[nxt]);
+  EDP_GLOBAL double* __restrict__ VX2 = G(S.vx[nxt]);
+  EDP_GLOBAL double* __restrict__ VY2 = G(S.vy[nxt]);
+  EDP_GLOBAL double* __restrict__ VZ2 = G(S.vz[nxt]);
+  EDP_GLOBAL uint64_t* __restrict__ UID2 = G(S.uid[nxt]);
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kSortUnroll * kBlock) {
+    double x[kSortUnroll], vx[kSortUnroll], vy[kSortUnroll], vz[kSortUnroll];
+    uint64_t uid[kSortUnroll];
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u) {
+      const int64_t i = i0 + u * kBlock;
+      x[u] = __longlong_as_double(0x7FF8000000000000LL);
+      if (i < hi) {
+        x[u] = X[i];
+        vx[u] = VX[i];
+        vy[u] = VY[i];
+        vz[u] = VZ[i];
+        uid[u] = UID[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSortUnroll; ++u) {
+      if (!(x[u] == x[u])) continue;
+      const int c = cell_of(x[u], inv_dx, ng);
+      const int64_t d = (int64_t)sB[c] + atomicAdd(&sC[c], 1u);
+      X2[d] = x[u];
+      VX2[d] = vx[u];
+      VY2[d] = vy[u];
+      VZ2[d] = vz[u];
+      UID2[d] = uid[u];
+    }
   }
 }
 
