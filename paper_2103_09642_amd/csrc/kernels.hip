@@ -107,36 +107,48 @@ __device__ __forceinline__ int energy_bin(double e_ev, double de, int nbins) {
 // sin chi sin eta) with the Euler angles of g from its components (phi = 0
 // when g is along x); the components follow the final velocity equation of
 // section 2.1.6 term by term.
+struct Frame {
+  double cos_theta, sin_theta, cos_phi, sin_phi;
+};
+__device__ __forceinline__ Frame frame_of(double gx, double gy, double gz, double gmag) {
+  Frame F;
+  if (gmag > 0.0) {
+    const double gyz = sqrt(gy * gy + gz * gz);
+    F.cos_theta = gx / gmag;
+    F.sin_theta = gyz / gmag;
+    if (gyz > 0.0) {
+      F.cos_phi = gy / gyz;
+      F.sin_phi = gz / gyz;
+    } else {
+      F.cos_phi = 1.0;
+      F.sin_phi = 0.0;
+    }
+  } else {
+    F.cos_theta = 1.0;
+    F.sin_theta = 0.0;
+    F.cos_phi = 1.0;
+    F.sin_phi = 0.0;
+  }
+  return F;
+}
+__device__ __forceinline__ void rotate(const Frame& F, double gnew, double f2, double cos_chi, double sin_chi,
+                                       double cos_eta, double sin_eta, double wx, double wy, double wz, double& ox,
+                                       double& oy, double& oz) {
+  const double a = f2 * gnew;
+  ox = wx + a * (F.cos_theta * cos_chi - F.sin_theta * sin_chi * cos_eta);
+  oy = wy + a * (F.sin_theta * F.cos_phi * cos_chi + F.cos_theta * F.cos_phi * sin_chi * cos_eta -
+                 F.sin_phi * sin_chi * sin_eta);
+  oz = wz + a * (F.sin_theta * F.sin_phi * cos_chi + F.cos_theta * F.sin_phi * sin_chi * cos_eta +
+                 F.cos_phi * sin_chi * sin_eta);
+}
 __device__ __forceinline__ void scatter(double gx, double gy, double gz, double gmag, double gnew,
                                         double f2, double cos_chi, double sin_chi, double eta,
                                         double wx, double wy, double wz, double& ox, double& oy,
                                         double& oz) {
-  double cos_theta, sin_theta, cos_phi, sin_phi;
-  if (gmag > 0.0) {
-    const double gyz = sqrt(gy * gy + gz * gz);
-    cos_theta = gx / gmag;
-    sin_theta = gyz / gmag;
-    if (gyz > 0.0) {
-      cos_phi = gy / gyz;
-      sin_phi = gz / gyz;
-    } else {
-      cos_phi = 1.0;
-      sin_phi = 0.0;
-    }
-  } else {
-    cos_theta = 1.0;
-    sin_theta = 0.0;
-    cos_phi = 1.0;
-    sin_phi = 0.0;
-  }
+  const Frame F = frame_of(gx, gy, gz, gmag);
   double cos_eta, sin_eta;
   sincos(eta, &sin_eta, &cos_eta);
-  const double a = f2 * gnew;
-  ox = wx + a * (cos_theta * cos_chi - sin_theta * sin_chi * cos_eta);
-  oy = wy + a * (sin_theta * cos_phi * cos_chi + cos_theta * cos_phi * sin_chi * cos_eta -
-                 sin_phi * sin_chi * sin_eta);
-  oz = wz + a * (sin_theta * sin_phi * cos_chi + cos_theta * sin_phi * sin_chi * cos_eta +
-                 cos_phi * sin_chi * sin_eta);
+  rotate(F, gnew, f2, cos_chi, sin_chi, cos_eta, sin_eta, wx, wy, wz, ox, oy, oz);
 }
 
 // Fixed-point split of one particle between nodes p and p+1 (charge
@@ -526,8 +538,19 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
     const double sin_chi = sqrt(1.0 - cos_chi * cos_chi);
     scatter(vxn, vy, vz, v, gnew, f2, cos_chi, sin_chi, eta, wx, wy, wz, ox, oy, oz);
   } else {
+    // Every draw of the ionization -- the energy share and the new ion's
+    // thermal velocity -- and the frame of g are taken before the dependent
+    // chains, and only the stores are conditional, so that the independent
+    // chains overlap (an ionization is the longest event of the queue).
     double r_share, r_unused;
     uniform2(seed, uid, st, tag(0, 0, 2), r_share, r_unused);
+    const uint64_t cu = child_uid(uid, s, 2);
+    double z0, z1, z2;
+    normals3(seed, cu, st, 1u, 2u, 1u, z0, z1, z2);
+    const Frame F = frame_of(vxn, vy, vz, v);
+    double cos_eta, sin_eta, cos_eta2, sin_eta2;
+    sincos(eta, &sin_eta, &cos_eta);
+    sincos(eta + kPi, &sin_eta2, &cos_eta2);
     double e_ev = 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion;
     if (e_ev < 0.0) {
       e_ev = 0.0;
@@ -550,10 +573,11 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
       sn_sc = sqrt(1.0 - cs_sc * cs_sc);
       sn_ej = sqrt(1.0 - cs_ej * cs_ej);
     }
-    scatter(vxn, vy, vz, v, g_sc, f2, cs_sc, sn_sc, eta, wx, wy, wz, ox, oy, oz);
-    if (be >= 0) {  // the ejected electron, scattered about the same w
-      double ex_, ey_, ez_;
-      scatter(vxn, vy, vz, v, g_ej, f2, cs_ej, sn_ej, eta + kPi, wx, wy, wz, ex_, ey_, ez_);
+    rotate(F, g_sc, f2, cs_sc, sn_sc, cos_eta, sin_eta, wx, wy, wz, ox, oy, oz);
+    // the ejected electron, scattered about the same w
+    double ex_, ey_, ez_;
+    rotate(F, g_ej, f2, cs_ej, sn_ej, cos_eta2, sin_eta2, wx, wy, wz, ex_, ey_, ez_);
+    if (be >= 0) {
       P.ex[be] = x;
       P.evx[be] = ex_;
       P.evy[be] = ey_;
@@ -561,9 +585,6 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
       P.euid[be] = child_uid(uid, s, 1);
     }
     if (bi >= 0) {  // the new ion: a thermal gas velocity
-      const uint64_t cu = child_uid(uid, s, 2);
-      double z0, z1, z2;
-      normals3(seed, cu, st, 1u, 2u, 1u, z0, z1, z2);
       const double sa = C->sigma_a;
       P.ix[bi] = x;
       P.ivx[bi] = sa * z0;
