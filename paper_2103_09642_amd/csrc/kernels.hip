@@ -1017,6 +1017,8 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const EDP_GLOBAL double* __restrict__ sig1 = G(SP == 0 ? C->sig_exc : C->sig_back);
   const EDP_GLOBAL double* __restrict__ sig2 = G(C->sig_ion);
   int64_t* const cnt_i_next = C->cnt_i + ((kion + 1) % 3) * ng;
+  // this species' deposit for step s+1 (next ion step for ions)
+  int64_t* const dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
   const double de_cs = C->de_cs;
   const int nbins = C->nbins;
   const uint64_t seed = C->seed;
@@ -1154,11 +1156,18 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         // second share to this step's deposit, the ion goes to the next ion
         // step's density
         // (the parent's new x: stored by this workgroup before the fence or
-        // barrier that precedes every dense pass)
+        // barrier that precedes every dense pass; the last pass runs after
+        // the histogram's flush and adds the electron's share to global
+        // memory)
         long long r;
         const int q = deposit_split(X[i], inv_dx, ng, r);
-        lds_add(&sH[q], 4294967296LL - r);
-        lds_add(&sH[q + 1], r);
+        if (wg_list) {
+          gl_add(&dst[q], 4294967296LL - r);
+          gl_add(&dst[q + 1], r);
+        } else {
+          lds_add(&sH[q], 4294967296LL - r);
+          lds_add(&sH[q + 1], r);
+        }
         gl_add(&cnt_i_next[q], 4294967296LL - r);
         gl_add(&cnt_i_next[q + 1], r);
       }
@@ -1328,15 +1337,9 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     sAbs[w][1] = tag_;
   }
   __syncthreads();
-  // the remaining candidates of all waves, as one list over the workgroup
-  process(true, sNc[0] + sNc[1] + sNc[2] + sNc[3], (int)threadIdx.x, kBlock);
-  __syncthreads();
-  if (threadIdx.x == 0)
-    ((EDP_GLOBAL rec4*)G(Cw->q_wg[SP]))[j] =
-        rec4{sCnt[0], sCnt[1], sAbs[0][0] + sAbs[1][0] + sAbs[2][0] + sAbs[3][0],
-             sAbs[0][1] + sAbs[1][1] + sAbs[2][1] + sAbs[3][1]};
-  // flush: deposit for step s+1 and diagnostics of step s
-  int64_t* dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
+  // flush first (deposit for step s+1 and diagnostics of step s): the
+  // last candidate pass below adds its newborns' charge to global memory
+  // directly, so the flush's atomics are in flight during its table loads
   for (int q = threadIdx.x; q < ng; q += blockDim.x) {
     const unsigned long long h = sH[q];
     if (h) gl_add(&dst[q], (long long)h);
@@ -1351,6 +1354,13 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   int64_t* hist = SP == 0 ? C->eepf : C->ifed;
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x)
     if (sF[b]) gl_add(&hist[b], (long long)sF[b]);
+  // the remaining candidates of all waves, as one list over the workgroup
+  process(true, sNc[0] + sNc[1] + sNc[2] + sNc[3], (int)threadIdx.x, kBlock);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    ((EDP_GLOBAL rec4*)G(Cw->q_wg[SP]))[j] =
+        rec4{sCnt[0], sCnt[1], sAbs[0][0] + sAbs[1][0] + sAbs[2][0] + sAbs[3][0],
+             sAbs[0][1] + sAbs[1][1] + sAbs[2][1] + sAbs[3][1]};
 }
 
 // One launch per species covers the chunks of every case of the batch.
