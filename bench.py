@@ -65,8 +65,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--sort-every", type=int, default=0,
-                    help="steps between compaction + cell sort (default: 50 for the large case, 100 for the "
-                         "batched sets, the fastest of a measured sweep)")
+                    help="steps between compaction + cell sort (default 0: chosen by the autotuner on the "
+                         "workload's own cases before the warm-up, outside the timed region)")
     ap.add_argument("--pic-steps", type=int, default=0,
                     help="profiling aid: time this many PIC steps instead of --steps RF cycles")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -87,8 +87,6 @@ def main():
     import torch
     from paper_2103_09642_amd import edupic, workloads
 
-    if not args.sort_every:
-        args.sort_every = 50 if args.workload == "large" else 100
     if args.workload in ("batch64", "dual32"):
         return bench_batch(args)
 
@@ -99,7 +97,6 @@ def main():
     ctx = edupic.Context(0)
     ctx.set_xsec(xs)
     ctx.set_option(edupic.OPT_MODE, args.mode)
-    ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every)
     ctx.set_option(edupic.OPT_PROFILE, 0)
     if args.calib_copy_mb:
         a = torch.empty(args.calib_copy_mb << 20, dtype=torch.uint8, device="cuda")
@@ -107,6 +104,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    tuned = choose_sort_interval(args, ctx, [case], lambda cs: ctx.advance(cs, [args.warmup] * len(cs)))
     g = ctx.create_case(case)
     if args.warmup:
         g.advance(args.warmup)
@@ -190,12 +188,37 @@ def main():
                                "seeded uniform 1e15 m^-3, 10 Pa Ar, 250 V 13.56 MHz; step = 1 RF cycle",
                    "mode": ["plain", "graph"][args.mode], "collision_selection":
                        "null collision" if args.null_collision else "direct", "sort_every": args.sort_every,
+                   "sort_tuning": tuned,
                    "electrons_live_end": c1["n_e"],
                    "ions_live_end": c1["n_i"], "electron_psteps": pe, "ion_psteps": pi},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def choose_sort_interval(args, ctx, descs, warm):
+    """The compaction + sort interval: --sort-every if given, else the
+    autotuner's choice, made on copies of the workload's cases (created from
+    the same seeded descriptors, given the same warm-up as the timed cases --
+    `warm(copies)` -- so that the trials see the regime of the timed window,
+    then tuned and destroyed): the timed cases start from exactly the state
+    they have without tuning.  Returns the tuning record for the output."""
+    from paper_2103_09642_amd import edupic, tune
+    if args.sort_every:
+        ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every)
+        return None
+    t0 = time.perf_counter()
+    copies = [ctx.create_case(d) for d in descs]
+    try:
+        warm(copies)
+        k, trials = tune.tune_sort_interval(ctx, copies)
+    finally:
+        for c in copies:
+            c.destroy()
+    args.sort_every = k
+    return {"seconds": round(time.perf_counter() - t0, 2), "on": "warmed-up copies of the workload's cases",
+            "rates": {t.interval: round(t.rate, 1) for t in trials}}
 
 
 def bench_batch(args):
@@ -212,10 +235,9 @@ def bench_batch(args):
     ctx = edupic.Context(0)
     ctx.set_xsec(xs)
     ctx.set_option(edupic.OPT_MODE, args.mode)
-    ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every)
     # the high-pressure, high-voltage cases more than double their seeded
     # particle count within a few cycles: room for 8x
-    cases = []
+    descs = []
     dual = args.workload == "dual32"
     for k in range(1, 33 if dual else 65):
         if dual:
@@ -226,8 +248,16 @@ def bench_batch(args):
         else:
             c = workloads.config_batch(k, xs)
             c = dict(c, cap_e=8 * c["n_init_e"], cap_i=8 * c["n_init_i"])
-        cases.append(ctx.create_case(c))
+        descs.append(c)
     hf_steps = 2000  # one 27.12 MHz period of the dual-frequency cases
+
+    def warm(cs):
+        if dual:
+            ctx.advance_steps(cs, [args.warmup * hf_steps] * len(cs))
+        else:
+            ctx.advance(cs, [args.warmup] * len(cs))
+    tuned = choose_sort_interval(args, ctx, descs, warm)
+    cases = [ctx.create_case(c) for c in descs]
 
     def run(cycles):
         if args.sequential:
@@ -274,6 +304,7 @@ def bench_batch(args):
                    "mode": ["plain", "graph"][args.mode],
                    "execution": "sequential" if args.sequential else "one batch",
                    "sort_every": args.sort_every,
+                   "sort_tuning": tuned,
                    "particle_steps": ps,
                    "particles_live_end": sum(c["n_e"] + c["n_i"] for c in c1)},
         "roofline": None,

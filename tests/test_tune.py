@@ -1,0 +1,96 @@
+"""The sort-interval autotuner's host logic on model batches (no GPU): the
+trial lengths, the choice of the fastest candidate, and its JSON cache."""
+import json
+
+import pytest
+
+from paper_2103_09642_amd import edupic, tune
+
+
+class FakeCtx:
+    def __init__(self):
+        self.options = {}
+
+    def set_option(self, key, value):
+        self.options[key] = value
+
+
+class FakeCase:
+    def __init__(self, n_e, n_grid, nsub):
+        self.case = {"n_grid": n_grid, "ion_subcycle": nsub}
+        self._n = n_e
+
+    def counts(self):
+        return {"n_e": self._n}
+
+
+def model(cost):
+    """A measure function from a per-step cost model: seconds = steps x cost(k)."""
+    calls = []
+
+    def run(ctx, cases, k, steps, warm):
+        calls.append((k, steps, warm))
+        return tune.Trial(k, steps, steps * cost(k), steps * 1000)
+    return run, calls
+
+
+def test_trial_lengths_cover_whole_graph_windows():
+    cases = [FakeCase(2_000_000, 1000, 20)]
+    steps, base = tune.trial_steps(cases, (25, 50, 100, 200))
+    assert base == {25: 500, 50: 1000, 100: 2000, 200: 4000}
+    assert steps == 4000 and all(steps % b == 0 for b in base.values())
+    # subcycles whose windows do not share a short multiple: capped
+    steps, base = tune.trial_steps([FakeCase(1000, 400, 7), FakeCase(1000, 400, 11)], (25, 50, 100, 200))
+    assert base[200] == 200 * 77 and steps == tune.MAX_TRIAL_STEPS
+
+
+def test_picks_the_fastest_and_sets_it():
+    ctx = FakeCtx()
+    # sort cost 70/k per step plus a locality loss growing with k: best at 50
+    run, calls = model(lambda k: 22.0 + 70.0 / k + 0.03 * k)
+    k, trials = tune.tune_sort_interval(ctx, [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
+    assert k == 50 and ctx.options[edupic.OPT_SORT_EVERY] == 50
+    assert [t.interval for t in trials] == [25, 50, 100, 200]
+    # mirrored order, half-length trials pooled per candidate
+    assert [k for k, _, _ in calls] == [25, 50, 100, 200, 200, 100, 50, 25]
+    assert all(st == 2000 for _, st, _ in calls) and all(t.steps == 4000 for t in trials)
+    assert [w for _, _, w in calls[:4]] == [500, 1000, 2000, 4000]
+
+
+def test_mirrored_order_cancels_a_linear_drift():
+    """The throughput falls 5% per trial while the cases evolve, and the
+    intervals themselves make no difference: pooled rates come out equal, so
+    the drift does not pick the interval measured first."""
+    ctx = FakeCtx()
+    n = [0]
+
+    def run(ctx_, cases, k, steps, warm):
+        t = tune.Trial(k, steps, steps * 1.0, int(steps * 1000 * (1.0 - 0.05 * n[0])))
+        n[0] += 1
+        return t
+    k, trials = tune.tune_sort_interval(ctx, [FakeCase(1_000_000, 1000, 20)], measure_fn=run)
+    rates = [t.rate for t in trials]
+    assert max(rates) - min(rates) < 1e-5 * max(rates)  # (integer particle-step counts)
+
+
+def test_cache_answers_the_same_batch_shape(tmp_path):
+    path = str(tmp_path / "tune.json")
+    ctx = FakeCtx()
+    run, calls = model(lambda k: 1.0 + abs(k - 100) * 1e-3)
+    k, trials = tune.tune_sort_interval(ctx, [FakeCase(300_000, 800, 20)] * 3, cache_path=path, measure_fn=run)
+    assert k == 100 and len(trials) == 4 and len(calls) == 8
+    saved = json.load(open(path))
+    (key, entry), = saved.items()
+    assert entry["sort_every"] == 100 and "cases=3" in key
+    ctx2 = FakeCtx()
+    run2, calls2 = model(lambda k: 1.0)
+    k2, trials2 = tune.tune_sort_interval(ctx2, [FakeCase(300_000, 800, 20)] * 3, cache_path=path, measure_fn=run2)
+    assert k2 == 100 and trials2 == [] and calls2 == [] and ctx2.options[edupic.OPT_SORT_EVERY] == 100
+    # another shape is tuned afresh and added
+    tune.tune_sort_interval(FakeCtx(), [FakeCase(300_000, 800, 20)], cache_path=path, measure_fn=run2)
+    assert len(json.load(open(path))) == 2
+
+
+def test_rejects_bad_candidates():
+    with pytest.raises(ValueError):
+        tune.tune_sort_interval(FakeCtx(), [FakeCase(1000, 100, 5)], candidates=(0, 10))
