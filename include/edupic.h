@@ -117,7 +117,10 @@ extern "C" {
 /* Execution options for edp_set_option. */
 #define EDP_OPT_MODE 1        /* 0 plain launches, 1 step windows replayed as
                                  captured hipGraphs                           */
-#define EDP_OPT_SORT_EVERY 2  /* steps between compaction + cell sort (>= 1)      */
+#define EDP_OPT_SORT_EVERY 2  /* steps between compaction + cell sort (>= 1;
+                                 default 100); results do not depend on it,
+                                 speed does: the Python autotuner (tune.py)
+                                 picks it per batch                             */
 #define EDP_OPT_PROFILE 5     /* 1: time every particle-kernel launch with events */
 #define EDP_OPT_GRAPH_STEPS 6 /* steps captured per hipGraph (multiple of N_SUB)  */
 #define EDP_OPT_POISSON 8     /* field solve: 0 parallel flux scans (default),
