@@ -65,8 +65,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--sort-every", type=int, default=0,
-                    help="steps between compaction + cell sort (default 0: chosen by the autotuner on the "
-                         "workload's own cases before the warm-up, outside the timed region)")
+                    help="steps between compaction + cell sort; with --wg-per-cu it fixes the schedule "
+                         "(default 0: the autotuner chooses both on copies of the workload's cases, "
+                         "outside the timed region)")
+    ap.add_argument("--wg-per-cu", type=int, default=-1,
+                    help="particle workgroups per CU (0: all that fit); -1: the autotuner's choice")
     ap.add_argument("--pic-steps", type=int, default=0,
                     help="profiling aid: time this many PIC steps instead of --steps RF cycles")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -104,7 +107,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    tuned = choose_sort_interval(args, ctx, [case], lambda cs: ctx.advance(cs, [args.warmup] * len(cs)))
+    tuned = choose_schedule(args, ctx, [case], lambda cs: ctx.advance(cs, [args.warmup] * len(cs)))
     g = ctx.create_case(case)
     if args.warmup:
         g.advance(args.warmup)
@@ -188,7 +191,7 @@ def main():
                                "seeded uniform 1e15 m^-3, 10 Pa Ar, 250 V 13.56 MHz; step = 1 RF cycle",
                    "mode": ["plain", "graph"][args.mode], "collision_selection":
                        "null collision" if args.null_collision else "direct", "sort_every": args.sort_every,
-                   "sort_tuning": tuned,
+                   "wg_per_cu": args.wg_per_cu, "schedule_tuning": tuned,
                    "electrons_live_end": c1["n_e"],
                    "ions_live_end": c1["n_i"], "electron_psteps": pe, "ion_psteps": pi},
         "roofline": roof,
@@ -197,28 +200,34 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def choose_sort_interval(args, ctx, descs, warm):
-    """The compaction + sort interval: --sort-every if given, else the
-    autotuner's choice, made on copies of the workload's cases (created from
-    the same seeded descriptors, given the same warm-up as the timed cases --
+def choose_schedule(args, ctx, descs, warm):
+    """The compaction + sort interval and the particle workgroups per CU:
+    --sort-every and --wg-per-cu if both are given, else the autotuner's
+    choice, made on copies of the workload's cases (created from the same
+    seeded descriptors, given the same warm-up as the timed cases --
     `warm(copies)` -- so that the trials see the regime of the timed window,
     then tuned and destroyed): the timed cases start from exactly the state
     they have without tuning.  Returns the tuning record for the output."""
     from paper_2103_09642_amd import edupic, tune
-    if args.sort_every:
+    if args.sort_every and args.wg_per_cu >= 0:
         ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every)
+        ctx.set_option(edupic.OPT_PART_WG_PER_CU, args.wg_per_cu)
         return None
     t0 = time.perf_counter()
     copies = [ctx.create_case(d) for d in descs]
     try:
         warm(copies)
-        k, trials = tune.tune_sort_interval(ctx, copies)
+        choice, trials = tune.tune_schedule(ctx, copies,
+                                            candidates=(args.sort_every,) if args.sort_every else
+                                            tune.DEFAULT_CANDIDATES,
+                                            wg_candidates=(args.wg_per_cu,) if args.wg_per_cu >= 0 else
+                                            tune.DEFAULT_WG_CANDIDATES)
     finally:
         for c in copies:
             c.destroy()
-    args.sort_every = k
+    args.sort_every, args.wg_per_cu = choice["sort_every"], choice["part_wg_per_cu"]
     return {"seconds": round(time.perf_counter() - t0, 2), "on": "warmed-up copies of the workload's cases",
-            "rates": {t.interval: round(t.rate, 1) for t in trials}}
+            "rates": {f"sort_every={t.interval},wg_per_cu={t.wg_per_cu}": round(t.rate, 1) for t in trials}}
 
 
 def bench_batch(args):
@@ -256,7 +265,7 @@ def bench_batch(args):
             ctx.advance_steps(cs, [args.warmup * hf_steps] * len(cs))
         else:
             ctx.advance(cs, [args.warmup] * len(cs))
-    tuned = choose_sort_interval(args, ctx, descs, warm)
+    tuned = choose_schedule(args, ctx, descs, warm)
     cases = [ctx.create_case(c) for c in descs]
 
     def run(cycles):
@@ -303,8 +312,8 @@ def bench_batch(args):
                                 "200-1000 nodes, 1e4-5e5 particles per species); step = 1 RF cycle of every case"),
                    "mode": ["plain", "graph"][args.mode],
                    "execution": "sequential" if args.sequential else "one batch",
-                   "sort_every": args.sort_every,
-                   "sort_tuning": tuned,
+                   "sort_every": args.sort_every, "wg_per_cu": args.wg_per_cu,
+                   "schedule_tuning": tuned,
                    "particle_steps": ps,
                    "particles_live_end": sum(c["n_e"] + c["n_i"] for c in c1)},
         "roofline": None,

@@ -127,6 +127,7 @@ struct edp_ctx {
   edp_case next_id = 1;
   // options
   int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, poisson = 0;
+  int part_wg_per_cu = 0;  // 0: every resident slot
   // the workgroup roles of the batch's launches (device table owned by the
   // context) and the batch's run state
   BlockRole* roles_d = nullptr;
@@ -390,7 +391,9 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   }
   std::vector<int> want[2], want_apply(nc);
   for (int sp = 0; sp < 2; ++sp) {
-    const int64_t slots = (int64_t)ctx->num_cu * particle_occupancy(sp, lds[sp]);
+    const int occ = particle_occupancy(sp, lds[sp]);
+    const int per_cu = ctx->part_wg_per_cu > 0 ? std::min(ctx->part_wg_per_cu, occ) : occ;
+    const int64_t slots = (int64_t)ctx->num_cu * per_cu;
     int64_t total = 0;
     for (const Case* c : cs) total += est_chunks(c, sp);
     const int64_t per = std::max<int64_t>(1, (total + slots - 1) / slots);
@@ -1446,6 +1449,11 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
     case EDP_OPT_POISSON:
       if (value < 0 || value > 1) return fail(EDP_EINVAL, "poisson solver must be 0 or 1");
       ctx->poisson = (int)value;
+      break;
+    case EDP_OPT_PART_WG_PER_CU:
+      if (value < 0 || value > 64) return fail(EDP_EINVAL, "workgroups per CU must be 0..64");
+      ctx->part_wg_per_cu = (int)value;
+      ctx->batch_valid = false;  // the grids change: rebuild the batch tables
       break;
     default:
       return fail(EDP_EINVAL, "unknown option %d", key);

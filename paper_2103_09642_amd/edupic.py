@@ -23,6 +23,7 @@ INFO_NAMES = ["mean_e", "ne_max", "debye", "dx_debye", "wpe_dt", "pmax_e", "pmax
               "power_e", "power_i", "flux_i_pow", "flux_i_gnd", "ei_pow", "ei_gnd", "fail"]
 OPT_MODE, OPT_SORT_EVERY, OPT_PROFILE, OPT_GRAPH_STEPS = 1, 2, 5, 6
 OPT_POISSON = 8
+OPT_PART_WG_PER_CU = 9
 POISSON_FLUX, POISSON_THOMAS = 0, 1
 MODE_PLAIN, MODE_GRAPH = 0, 1
 ELECTRONS, IONS = 0, 1

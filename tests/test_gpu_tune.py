@@ -1,7 +1,8 @@
-"""The sort-interval autotuner on library cases: it advances the real cases
-under each candidate interval, so the state it leaves must be the state of
-the same number of steps at any fixed interval, bit for bit (the step does
-not depend on the sort interval)."""
+"""The schedule autotuner on library cases: it advances the real cases under
+each candidate sort interval and workgroup count, so the state it leaves
+must be the state of the same number of steps under any fixed schedule,
+bit for bit (a step depends neither on the sort interval nor on the launch
+shape)."""
 import pytest
 
 from gpu_common import gpu_context, say
@@ -25,16 +26,16 @@ def test_tuning_loses_no_step_and_changes_nothing(ctx):
     ctx.set_option(edupic.OPT_MODE, 1)
     try:
         gs = [_make(ctx, c, st, 0) for c, st in mix]
-        k, trials = tune.tune_sort_interval(ctx, gs, candidates=(5, 10, 40))
-        assert k in (5, 10, 40) and len(trials) == 3 and all(t.rate > 0 for t in trials)
-        assert tune.last_choice(ctx) == k
-        # two half-length trials per candidate, each after its warm-up window
-        total = sum(t.steps for t in trials) + 2 * sum(min(b, tune.MAX_TRIAL_STEPS)
-                                                       for b in tune.trial_steps(gs, (5, 10, 40))[1].values())
-        say(f"chosen {k}; rates {[round(t.rate / 1e9, 2) for t in trials]} G/s; {total} steps")
+        choice, trials = tune.tune_schedule(ctx, gs, candidates=(5, 10, 40), wg_candidates=(0, 2))
+        assert choice["sort_every"] in (5, 10, 40) and choice["part_wg_per_cu"] in (0, 2)
+        assert tune.last_schedule(ctx) == choice
+        assert len(trials) == 5 and all(t.rate > 0 for t in trials)
+        say(f"chosen {choice}; rates {[round(t.rate / 1e9, 2) for t in trials]} G/s")
         tuned = [_result(g) for g in gs]
-        assert all(r[3]["step"] == total for r in tuned)
+        total = tuned[0][3]["step"]
+        assert total > 0 and all(r[3]["step"] == total for r in tuned)
         ctx.set_option(edupic.OPT_SORT_EVERY, 7)
+        ctx.set_option(edupic.OPT_PART_WG_PER_CU, 1)
         for (c, st), r in zip(mix, tuned):
             g = _make(ctx, c, st, 0)
             g.advance_steps(total)
@@ -45,4 +46,12 @@ def test_tuning_loses_no_step_and_changes_nothing(ctx):
     finally:
         ctx.set_option(edupic.OPT_MODE, 0)
         ctx.set_option(edupic.OPT_SORT_EVERY, 100)
+        ctx.set_option(edupic.OPT_PART_WG_PER_CU, 0)
 
+
+def test_workgroup_option_is_validated(ctx):
+    from paper_2103_09642_amd import edupic
+    say("test_workgroup_option_is_validated")
+    for bad in (-1, 65):
+        with pytest.raises(edupic.EdpError):
+            ctx.set_option(edupic.OPT_PART_WG_PER_CU, bad)

@@ -28,9 +28,9 @@ def model(cost):
     """A measure function from a per-step cost model: seconds = steps x cost(k)."""
     calls = []
 
-    def run(ctx, cases, k, steps, warm):
+    def run(ctx, cases, k, steps, warm, wg=0):
         calls.append((k, steps, warm))
-        return tune.Trial(k, steps, steps * cost(k), steps * 1000)
+        return tune.Trial(k, steps, steps * cost(k), steps * 1000, wg)
     return run, calls
 
 
@@ -64,8 +64,8 @@ def test_mirrored_order_cancels_a_linear_drift():
     ctx = FakeCtx()
     n = [0]
 
-    def run(ctx_, cases, k, steps, warm):
-        t = tune.Trial(k, steps, steps * 1.0, int(steps * 1000 * (1.0 - 0.05 * n[0])))
+    def run(ctx_, cases, k, steps, warm, wg=0):
+        t = tune.Trial(k, steps, steps * 1.0, int(steps * 1000 * (1.0 - 0.05 * n[0])), wg)
         n[0] += 1
         return t
     k, trials = tune.tune_sort_interval(ctx, [FakeCase(1_000_000, 1000, 20)], measure_fn=run)
@@ -91,6 +91,32 @@ def test_cache_answers_the_same_batch_shape(tmp_path):
     assert len(json.load(open(path))) == 2
 
 
+def test_schedule_tunes_the_workgroups_at_the_chosen_interval(tmp_path):
+    """Second knob: with the interval fixed at the winner, the workgroups
+    per CU (0: all that fit) are tried in a mirrored order as well."""
+    calls = []
+
+    def run(ctx, cases, k, steps, warm, wg=0):
+        calls.append((k, wg, warm))
+        cost = 22.0 + 70.0 / k + 0.03 * k + {0: 1.0, 4: 0.0, 3: 0.5}[wg]
+        return tune.Trial(k, steps, steps * cost, steps * 1000, wg)
+    ctx = FakeCtx()
+    path = str(tmp_path / "t.json")
+    choice, trials = tune.tune_schedule(ctx, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run)
+    assert choice == {"sort_every": 50, "part_wg_per_cu": 4}
+    assert ctx.options[edupic.OPT_SORT_EVERY] == 50 and ctx.options[edupic.OPT_PART_WG_PER_CU] == 4
+    assert [(k, w) for k, w, _ in calls[8:]] == [(50, 0), (50, 4), (50, 3), (50, 3), (50, 4), (50, 0)]
+    assert all(warm == 1000 for _, _, warm in calls[8:])
+    assert len(trials) == 7
+    entry, = json.load(open(path)).values()
+    assert entry["sort_every"] == 50 and entry["part_wg_per_cu"] == 4
+    ctx2 = FakeCtx()
+    assert tune.tune_schedule(ctx2, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run)[1] == []
+    assert ctx2.options[edupic.OPT_PART_WG_PER_CU] == 4
+
+
 def test_rejects_bad_candidates():
     with pytest.raises(ValueError):
         tune.tune_sort_interval(FakeCtx(), [FakeCase(1000, 100, 5)], candidates=(0, 10))
+    with pytest.raises(ValueError):
+        tune.tune_schedule(FakeCtx(), [FakeCase(1000, 100, 5)], wg_candidates=(4, -1))
