@@ -373,8 +373,9 @@ BlockRole role(const Case* c, int j, int n) {
 int sort_blocks(const edp_ctx* ctx, const Case* c, int sp) { return std::max(1, blocks_for(ctx, c->est[sp]) / 4); }
 
 // Build the batch table for `cs` (in this order) and upload it.  Particle
-// workgroups: the chip's resident workgroups shared out in proportion to
-// each case's expected chunks, so every workgroup takes about the same
+// workgroups: the chip's resident workgroups (at most part_wg_per_cu per CU
+// when that option is set) shared out in proportion to each case's expected
+// chunks, so every workgroup takes about the same
 // number of chunks (any count is still covered: the kernels split the live
 // chunks over whatever workgroups a case has).  The table is read by
 // kernels still in flight, so the stream is drained before it changes;

@@ -851,10 +851,11 @@ __global__ void __launch_bounds__(kBlock) k_drain_done(CaseDev* __restrict__ C) 
 //
 // A case's particle slots are cut into chunks of kChunk = 256 slots; wave w
 // of a workgroup owns slots [c*256 + 64w, c*256 + 64w + 64) of chunk c, one
-// per lane.  The case gets a fixed number of workgroups (sized from the
-// occupancy and the expected particle count); workgroup j takes the
-// contiguous chunk range [j*per, (j+1)*per) with per computed from the live
-// slot count at run time, so the launch shape never depends on the count,
+// per lane.  The case gets a fixed number of workgroups (its share, by
+// expected particle count, of the resident slots the batch uses); workgroup
+// j takes the contiguous chunk range [j*per, (j+1)*per) with per computed
+// from the live slot count at run time, so the launch shape never depends
+// on the count,
 // every workgroup does the same amount of work, and E is loaded and the
 // deposit flushed once per workgroup.
 //
