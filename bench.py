@@ -65,11 +65,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--sort-every", type=int, default=0,
-                    help="steps between compaction + cell sort; with --wg-per-cu it fixes the schedule "
+                    help="steps between compaction + cell sort; with --wg-per-cu and --apply-lanes it "
+                         "fixes the schedule "
                          "(default 0: the autotuner chooses both on copies of the workload's cases, "
                          "outside the timed region)")
     ap.add_argument("--wg-per-cu", type=int, default=-1,
                     help="particle workgroups per CU (0: all that fit); -1: the autotuner's choice")
+    ap.add_argument("--apply-lanes", type=int, default=0,
+                    help="lanes per event list in the head (16, 32, 64); 0: the autotuner's choice")
     ap.add_argument("--pic-steps", type=int, default=0,
                     help="profiling aid: time this many PIC steps instead of --steps RF cycles")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -107,7 +110,8 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    tuned = choose_schedule(args, ctx, [case], lambda cs: ctx.advance(cs, [args.warmup] * len(cs)))
+    mid = args.warmup + args.steps // 2  # the timed window's midpoint, in RF cycles
+    tuned = choose_schedule(args, ctx, [case], lambda cs: ctx.advance(cs, [mid] * len(cs)))
     g = ctx.create_case(case)
     if args.warmup:
         g.advance(args.warmup)
@@ -191,7 +195,7 @@ def main():
                                "seeded uniform 1e15 m^-3, 10 Pa Ar, 250 V 13.56 MHz; step = 1 RF cycle",
                    "mode": ["plain", "graph"][args.mode], "collision_selection":
                        "null collision" if args.null_collision else "direct", "sort_every": args.sort_every,
-                   "wg_per_cu": args.wg_per_cu, "schedule_tuning": tuned,
+                   "wg_per_cu": args.wg_per_cu, "apply_lanes": args.apply_lanes, "schedule_tuning": tuned,
                    "electrons_live_end": c1["n_e"],
                    "ions_live_end": c1["n_i"], "electron_psteps": pe, "ion_psteps": pi},
         "roofline": roof,
@@ -201,17 +205,19 @@ def main():
 
 
 def choose_schedule(args, ctx, descs, warm):
-    """The compaction + sort interval and the particle workgroups per CU:
-    --sort-every and --wg-per-cu if both are given, else the autotuner's
-    choice, made on copies of the workload's cases (created from the same
-    seeded descriptors, given the same warm-up as the timed cases --
-    `warm(copies)` -- so that the trials see the regime of the timed window,
-    then tuned and destroyed): the timed cases start from exactly the state
-    they have without tuning.  Returns the tuning record for the output."""
+    """The compaction + sort interval, the particle workgroups per CU and
+    the lanes per event list: --sort-every, --wg-per-cu and --apply-lanes if
+    all are given, else the autotuner's choice, made on copies of the
+    workload's cases (created from the same seeded descriptors, advanced to
+    the timed window's midpoint -- `warm(copies)` -- then tuned with every
+    trial starting from that state, so that the trials see the regime of the
+    timed window, and destroyed): the timed cases start from exactly the
+    state they have without tuning.  Returns the tuning record."""
     from paper_2103_09642_amd import edupic, tune
-    if args.sort_every and args.wg_per_cu >= 0:
+    if args.sort_every and args.wg_per_cu >= 0 and args.apply_lanes:
         ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, args.wg_per_cu)
+        ctx.set_option(edupic.OPT_APPLY_LANES, args.apply_lanes)
         return None
     t0 = time.perf_counter()
     copies = [ctx.create_case(d) for d in descs]
@@ -221,13 +227,19 @@ def choose_schedule(args, ctx, descs, warm):
                                             candidates=(args.sort_every,) if args.sort_every else
                                             tune.DEFAULT_CANDIDATES,
                                             wg_candidates=(args.wg_per_cu,) if args.wg_per_cu >= 0 else
-                                            tune.DEFAULT_WG_CANDIDATES)
+                                            tune.DEFAULT_WG_CANDIDATES,
+                                            lane_candidates=(args.apply_lanes,) if args.apply_lanes else
+                                            tune.DEFAULT_LANE_CANDIDATES, restore_state=True)
     finally:
         for c in copies:
             c.destroy()
     args.sort_every, args.wg_per_cu = choice["sort_every"], choice["part_wg_per_cu"]
-    return {"seconds": round(time.perf_counter() - t0, 2), "on": "warmed-up copies of the workload's cases",
-            "rates": {f"sort_every={t.interval},wg_per_cu={t.wg_per_cu}": round(t.rate, 1) for t in trials}}
+    args.apply_lanes = choice["apply_lanes"]
+    return {"seconds": round(time.perf_counter() - t0, 2),
+            "on": "copies of the workload's cases advanced to the timed window's midpoint; "
+                  "every trial starts from that state",
+            "trials": [[t.interval, t.wg_per_cu, t.lanes, round(t.rate, 1)] for t in trials],
+            "trial_fields": ["sort_every", "wg_per_cu", "apply_lanes", "particle-steps/s"]}
 
 
 def bench_batch(args):
@@ -260,11 +272,13 @@ def bench_batch(args):
         descs.append(c)
     hf_steps = 2000  # one 27.12 MHz period of the dual-frequency cases
 
+    mid = args.warmup + args.steps // 2  # the timed window's midpoint, in benchmark steps
+
     def warm(cs):
         if dual:
-            ctx.advance_steps(cs, [args.warmup * hf_steps] * len(cs))
+            ctx.advance_steps(cs, [mid * hf_steps] * len(cs))
         else:
-            ctx.advance(cs, [args.warmup] * len(cs))
+            ctx.advance(cs, [mid] * len(cs))
     tuned = choose_schedule(args, ctx, descs, warm)
     cases = [ctx.create_case(c) for c in descs]
 
@@ -312,7 +326,7 @@ def bench_batch(args):
                                 "200-1000 nodes, 1e4-5e5 particles per species); step = 1 RF cycle of every case"),
                    "mode": ["plain", "graph"][args.mode],
                    "execution": "sequential" if args.sequential else "one batch",
-                   "sort_every": args.sort_every, "wg_per_cu": args.wg_per_cu,
+                   "sort_every": args.sort_every, "wg_per_cu": args.wg_per_cu, "apply_lanes": args.apply_lanes,
                    "schedule_tuning": tuned,
                    "particle_steps": ps,
                    "particles_live_end": sum(c["n_e"] + c["n_i"] for c in c1)},

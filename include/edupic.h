@@ -125,6 +125,10 @@ extern "C" {
 #define EDP_OPT_GRAPH_STEPS 6 /* steps captured per hipGraph (multiple of N_SUB)  */
 #define EDP_OPT_POISSON 8     /* field solve: 0 parallel flux scans (default),
                                  1 sequential Thomas, bit-reproducible           */
+#define EDP_OPT_APPLY_LANES 10 /* lanes per event list in the head's collision
+                                 workgroups: 16, 32 or 64 (default); results do
+                                 not depend on it, speed does: the autotuner
+                                 (tune.py) picks it                           */
 #define EDP_OPT_PART_WG_PER_CU 9 /* resident particle workgroups per CU a batch
                                  uses: 0 (default) all that fit, k >= 1 at
                                  most k; results do not depend on it, speed

@@ -23,7 +23,8 @@
 #include "impl.hpp"
 
 namespace edp {
-hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st);
+hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, int lanes,
+                       hipStream_t st);
 hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
 hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
                             hipEvent_t ev1);
@@ -128,6 +129,7 @@ struct edp_ctx {
   // options
   int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, poisson = 0;
   int part_wg_per_cu = 0;  // 0: every resident slot
+  int apply_lanes = 64;    // lanes per event list in the head's collision workgroups
   // the workgroup roles of the batch's launches (device table owned by the
   // context) and the batch's run state
   BlockRole* roles_d = nullptr;
@@ -293,11 +295,15 @@ int scatter_blocks(const edp_ctx* ctx) { return std::min(ctx->num_cu, kMaxApply)
 // Expected chunks of a species of a case (10% headroom over the estimate).
 int64_t est_chunks(const Case* c, int sp) { return (c->est[sp] + c->est[sp] / 10 + kChunk) / kChunk; }
 
-// Collision workgroups of a case in the head: 8 lanes per chunk of the
-// estimated live slots, 32 chunks per workgroup, at most one per CU.
-int apply_blocks(const edp_ctx* ctx, const Case* c) {
+// Collision workgroups of a case in the head: enough for one round, every
+// event list (one per particle workgroup of the case) with a group of `lanes`
+// lanes, and no fewer than one per 32 chunks of the estimated live slots (up
+// to one per CU), so that short lists still spread over the chip.
+int apply_blocks(const edp_ctx* ctx, const Case* c, int lists, int lanes) {
   const int64_t chunks = (std::max(c->est[0], c->est[1]) + kChunk - 1) / kChunk;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(ctx->num_cu, kMaxApply), (chunks + 31) / 32));
+  const int64_t spread = std::min<int64_t>(ctx->num_cu, (chunks + 31) / 32);
+  const int64_t round = (lists + (256 / lanes) - 1) / (256 / lanes);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxApply, std::max(spread, round)));
 }
 
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
@@ -402,7 +408,8 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
     for (size_t k = 0; k < nc; ++k)
       want[sp][k] = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxPartWG, (est_chunks(cs[k], sp) + per - 1) / per));
   }
-  for (size_t k = 0; k < nc; ++k) want_apply[k] = apply_blocks(ctx, cs[k]);
+  for (size_t k = 0; k < nc; ++k)
+    want_apply[k] = apply_blocks(ctx, cs[k], std::max(want[0][k], want[1][k]), ctx->apply_lanes);
   std::vector<int> want_sort[2];
   for (int sp = 0; sp < 2; ++sp)
     for (size_t k = 0; k < nc; ++k) want_sort[sp].push_back(sort_blocks(ctx, cs[k], sp));
@@ -472,7 +479,7 @@ int enqueue_batch_step(edp_ctx* ctx, const std::vector<int64_t>& s, int64_t j, b
   Batch& B = ctx->batch;
   hipStream_t st = ctx->stream;
   const int nc = (int)B.cases.size();
-  HIPCHK(launch_head(ctx->roles_d + B.role_off[2], nc, B.apply, B.max_ng, ctx->poisson, st));
+  HIPCHK(launch_head(ctx->roles_d + B.role_off[2], nc, B.apply, B.max_ng, ctx->poisson, ctx->apply_lanes, st));
   bool any_ion = false, sort_e = false, sort_i = false;
   for (int k = 0; k < nc; ++k) {
     const int64_t sk = s[k] + j;
@@ -1450,6 +1457,11 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
     case EDP_OPT_POISSON:
       if (value < 0 || value > 1) return fail(EDP_EINVAL, "poisson solver must be 0 or 1");
       ctx->poisson = (int)value;
+      break;
+    case EDP_OPT_APPLY_LANES:
+      if (value != 16 && value != 32 && value != 64) return fail(EDP_EINVAL, "lanes per event list must be 16, 32 or 64");
+      ctx->apply_lanes = (int)value;
+      ctx->batch_valid = false;  // the collision workgroup count changes
       break;
     case EDP_OPT_PART_WG_PER_CU:
       if (value < 0 || value > 64) return fail(EDP_EINVAL, "workgroups per CU must be 0..64");

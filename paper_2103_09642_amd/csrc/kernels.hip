@@ -661,15 +661,18 @@ typedef int rec4 __attribute__((ext_vector_type(4)));  // per-workgroup queue re
 // step left one event list (in its chunk range of the queue) and a record
 // {events, births, absorbed at x=0, absorbed at x=L}; an event is
 // slot | process << 32 | birth rank in the list << 34.  Workgroup blk of
-// nblk takes a contiguous range of those lists, a group of 16 lanes one list.
+// nblk takes a contiguous range of those lists, a group of LANES lanes one
+// list (events carry their birth ranks, so any lane can take any event: more
+// lanes per list shorten long lists, fewer serve more lists per workgroup).
 // Newborns of list j go to q_base + (births of the lists before j) + rank;
 // secondary electrons of ion impacts (ion events of process 2, 3) follow
 // every electron birth of the step.  No atomics: every slot follows from the
 // records alone.
-constexpr int kApplyLanes = 16;
-constexpr int kApplyGroups = kBlock / kApplyLanes;  // lists per round of a workgroup
-
+template <int LANES>
 __device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, int nblk) {
+  static_assert(LANES >= 1 && LANES <= kWave && kBlock % LANES == 0, "collision workgroup shape");
+  constexpr int kApplyLanes = LANES;
+  constexpr int kApplyGroups = kBlock / LANES;  // lists per round of a workgroup
   __shared__ int64_t sRed[64];
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int64_t s = C->q_step;
@@ -810,7 +813,7 @@ __device__ __forceinline__ void fold_queue(CaseDev* __restrict__ Cw) {
 // fields, the next na apply the queues of step s-1 (a range per case), the
 // last nc fold each queue's totals into the counters and do the step's
 // bookkeeping.  R: one role per workgroup.
-template <int MODE>
+template <int MODE, int LANES>
 __global__ void __launch_bounds__(kBlock) k_head(const BlockRole* __restrict__ R, int nc, int na) {
   extern __shared__ double hsm[];
   const int bid = (int)blockIdx.x;
@@ -821,7 +824,7 @@ __global__ void __launch_bounds__(kBlock) k_head(const BlockRole* __restrict__ R
     return;
   }
   if (bid < nc + na) {
-    apply_queue(C, r->j, r->n);
+    apply_queue<LANES>(C, r->j, r->n);
     return;
   }
   if (C->q_valid) fold_queue(C);
@@ -838,7 +841,7 @@ __global__ void __launch_bounds__(kBlock) k_head(const BlockRole* __restrict__ R
 // Apply the pending queue before the host looks at the state (the last
 // workgroup folds the totals).
 __global__ void __launch_bounds__(kBlock) k_drain(CaseDev* __restrict__ C) {
-  apply_queue(C, (int)blockIdx.x, (int)gridDim.x);
+  apply_queue<kWave>(C, (int)blockIdx.x, (int)gridDim.x);
 }
 __global__ void __launch_bounds__(kBlock) k_drain_done(CaseDev* __restrict__ C) {
   if (C->q_valid) fold_queue(C);
@@ -1623,14 +1626,23 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp
 
 // Head of a batch step: ncase field workgroups, `apply_blocks` collision
 // workgroups in total and ncase totals workgroups, with their roles in this
-// order.  `max_ng` sizes the field workgroups' LDS.
-hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, hipStream_t st) {
+// order.  `max_ng` sizes the field workgroups' LDS; `lanes` (16, 32, 64) per
+// event list in the collision workgroups.
+hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, int lanes,
+                       hipStream_t st) {
   const size_t lds = (size_t)(max_ng + (max_ng >> 4) + 1) * 24;  // three padded rows
   const dim3 grid(2 * ncase + apply_blocks);
-  if (mode == 1)
-    hipLaunchKernelGGL(k_head<1>, grid, dim3(kBlock), lds, st, roles, ncase, apply_blocks);
-  else
-    hipLaunchKernelGGL(k_head<0>, grid, dim3(kBlock), lds, st, roles, ncase, apply_blocks);
+#define EDP_HEAD(M, LN) hipLaunchKernelGGL((k_head<M, LN>), grid, dim3(kBlock), lds, st, roles, ncase, apply_blocks)
+  switch (lanes * 2 + (mode == 1)) {
+    case 32: EDP_HEAD(0, 16); break;
+    case 33: EDP_HEAD(1, 16); break;
+    case 64: EDP_HEAD(0, 32); break;
+    case 65: EDP_HEAD(1, 32); break;
+    case 128: EDP_HEAD(0, 64); break;
+    case 129: EDP_HEAD(1, 64); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef EDP_HEAD
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 """Autotuner for the batch runtime's schedule: the compaction + cell-sort
-interval and the particle workgroups per CU.
+interval, the particle workgroups per CU and the lanes per event list of the
+head's collision workgroups.
 
 * The sort every K steps trades its own cost (one pass over every particle
   array of the cases due) against the particle kernel's locality: between
@@ -9,19 +10,35 @@ interval and the particle workgroups per CU.
   workgroup slots.  All of them (5 per CU for electrons) hide the most memory
   latency, fewer leave each workgroup more chunks and the memory system less
   contention; which wins depends on the batch.
+* The head applies each particle workgroup's event list with a group of 16,
+  32 or 64 lanes.  Long lists (the batched sets: tens of chunks per
+  workgroup) want 64, the single large case's short lists 16.
 
 The best values depend on the workload -- a single case of 2e6 particles
 per species is fastest near a 50-step interval, the 64-case batched set near
 100-200; the dual-frequency set gains 7% from 4 workgroups per CU where the
-batched set loses 2% -- and nothing in the results depends on either (a step
-is bit-identical across sort intervals and launch shapes).  So the tuner
-advances the real cases under each candidate in turn, losing no step, times
-each trial with the device's own particle-step counters, and keeps the
-fastest: first the sort interval, then the workgroups per CU at that
-interval.  The cases evolve while they are measured (a seeded plasma loses
-or gains particles for many cycles), so the candidates of a knob run in a
-mirrored order (A B C D D C B A) and each one's rate pools its two trials: a
-linear drift of the throughput cancels.  A choice can be cached in a JSON
+batched set loses 2% -- and nothing in the results depends on any of them (a
+step is bit-identical across sort intervals and launch shapes).  So the
+tuner advances the real cases under each candidate in turn, losing no step,
+times each trial with the device's own particle-step counters, and keeps the
+fastest.  The knobs interact (4 workgroups per CU win at one sort interval
+and lose at another), so when the calibration run says that every
+combination fits in JOINT_BUDGET_SECONDS the tuner tries them all;
+otherwise one knob at a time: the sort interval, then the workgroups per
+CU at that interval, then the lanes per list.  The cases evolve while they are measured
+(a seeded plasma loses or gains particles for many cycles), so the
+candidates of a knob run in a mirrored order (A B C D D C B A) and each
+one's rate pools its two trials: a linear drift of the throughput cancels.
+Every trial is a whole number of every candidate's graph window, stretched
+by a first calibration run to at least MIN_TRIAL_SECONDS, and among the
+candidates within MARGIN of the fastest the one nearest the library's
+default wins (so noise-level differences do not move a knob).
+With `restore`, the tuner instead snapshots the cases' state once and
+restores it before every trial and at the end: every trial then starts from
+the same state, so the ranking reflects that state's regime (a joint search
+runs dozens of RF cycles, over which a discharge can change enough to change
+the ranking), and the cases come back unchanged.  A choice can be cached in
+a JSON
 file keyed by the batch's shape (case count, particle count bucket, grid
 size, ion subcycling).
 
@@ -38,7 +55,13 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 DEFAULT_CANDIDATES = (25, 50, 100, 200)  # sort intervals (steps)
 DEFAULT_WG_CANDIDATES = (0, 4, 3)        # particle workgroups per CU (0: all that fit)
+DEFAULT_LANE_CANDIDATES = (64, 16)       # lanes per event list in the head
 MAX_TRIAL_STEPS = 8000
+MAX_TRIAL_STRETCH = 8       # at most this many windows per trial
+MIN_TRIAL_SECONDS = 0.3     # calibration target per trial
+MARGIN = 0.005              # rates this close to the fastest count as a tie
+DEFAULTS = {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 64}
+JOINT_BUDGET_SECONDS = 60.0  # all combinations tried together below this estimate
 _chosen: Dict[int, Dict[str, int]] = {}  # last choice the tuner set, per context object
 
 
@@ -49,6 +72,7 @@ class Trial:
     seconds: float
     particle_steps: int
     wg_per_cu: int = 0   # the particle workgroups per CU of the trial
+    lanes: int = 64      # the lanes per event list of the trial
 
     @property
     def rate(self) -> float:
@@ -94,12 +118,14 @@ def trial_steps(cases: Sequence, candidates: Sequence[int]) -> Tuple[int, Dict[i
     return steps, base
 
 
-def measure(ctx, cases: Sequence, interval: int, steps: int, warm_steps: int, wg_per_cu: int = 0) -> Trial:
+def measure(ctx, cases: Sequence, interval: int, steps: int, warm_steps: int, wg_per_cu: int = 0,
+            lanes: int = 64) -> Trial:
     """Advance `cases` by warm_steps (graph capture, first sort) and then by
     `steps` timed steps with the given schedule."""
     from . import edupic
     ctx.set_option(edupic.OPT_SORT_EVERY, interval)
     ctx.set_option(edupic.OPT_PART_WG_PER_CU, wg_per_cu)
+    ctx.set_option(edupic.OPT_APPLY_LANES, lanes)
     if warm_steps > 0:
         ctx.advance_steps(list(cases), [warm_steps] * len(cases))
     ctx.sync()
@@ -110,7 +136,7 @@ def measure(ctx, cases: Sequence, interval: int, steps: int, warm_steps: int, wg
     t1 = time.perf_counter()
     c1 = [c.counts() for c in cases]
     ps = sum((b["psteps_e"] - a["psteps_e"]) + (b["psteps_i"] - a["psteps_i"]) for a, b in zip(c0, c1))
-    return Trial(interval, steps, t1 - t0, ps, wg_per_cu)
+    return Trial(interval, steps, t1 - t0, ps, wg_per_cu, lanes)
 
 
 def _mirrored(values: Sequence[int], trial: Callable[[int], Trial]) -> List[Trial]:
@@ -120,8 +146,29 @@ def _mirrored(values: Sequence[int], trial: Callable[[int], Trial]) -> List[Tria
     for v in values:
         mine = [t for w, t in runs if w == v]
         out.append(Trial(mine[0].interval, sum(t.steps for t in mine), sum(t.seconds for t in mine),
-                         sum(t.particle_steps for t in mine), mine[0].wg_per_cu))
+                         sum(t.particle_steps for t in mine), mine[0].wg_per_cu, mine[0].lanes))
     return out
+
+
+def _pick(trials: List[Trial], attr: str, default: int, distance: Callable[[int], float]) -> int:
+    """Among the trials within MARGIN of the fastest, the value nearest the
+    library default (the default itself when it is among them): a tie in
+    the evidence keeps the schedule closest to the default."""
+    top = max(t.rate for t in trials)
+    near = [getattr(t, attr) for t in trials if t.rate >= top / (1.0 + MARGIN)]
+    return min(near, key=lambda v: (distance(v), v))
+
+
+def _dist_sort(k):
+    return abs(math.log(k / DEFAULTS["sort_every"]))
+
+
+def _dist_wg(w):
+    return 0.0 if w == 0 else 1.0 / w
+
+
+def _dist_lanes(v):
+    return abs(math.log2(v / DEFAULTS["apply_lanes"]))
 
 
 def _check(candidates, lo, what):
@@ -129,47 +176,100 @@ def _check(candidates, lo, what):
         raise ValueError(f"{what} candidates must be >= {lo}")
 
 
-def _apply(ctx, sort_every: int, wg: int):
+def _apply(ctx, sort_every: int, wg: int, lanes: int):
     from . import edupic
     ctx.set_option(edupic.OPT_SORT_EVERY, sort_every)
     ctx.set_option(edupic.OPT_PART_WG_PER_CU, wg)
-    _chosen[id(ctx)] = {"sort_every": sort_every, "part_wg_per_cu": wg}
+    ctx.set_option(edupic.OPT_APPLY_LANES, lanes)
+    _chosen[id(ctx)] = {"sort_every": sort_every, "part_wg_per_cu": wg, "apply_lanes": lanes}
+
+
+def snapshot(cases: Sequence) -> List:
+    """Each case's particles of both species and its step (host copies)."""
+    return [(c.get_state(0), c.get_state(1), c.counts()["step"]) for c in cases]
+
+
+def restore(cases: Sequence, snap: List):
+    for c, (e, i, step) in zip(cases, snap):
+        c.set_state(0, e, step)
+        c.set_state(1, i, step)
 
 
 def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CANDIDATES,
-                  wg_candidates: Sequence[int] = DEFAULT_WG_CANDIDATES, cache_path: Optional[str] = None,
-                  measure_fn: Optional[Callable[..., Trial]] = None) -> Tuple[Dict[str, int], List[Trial]]:
+                  wg_candidates: Sequence[int] = DEFAULT_WG_CANDIDATES,
+                  lane_candidates: Sequence[int] = DEFAULT_LANE_CANDIDATES, cache_path: Optional[str] = None,
+                  measure_fn: Optional[Callable[..., Trial]] = None,
+                  restore_state: bool = False) -> Tuple[Dict[str, int], List[Trial]]:
     """Pick the fastest sort interval, then the fastest particle workgroups
-    per CU at that interval, and set both on the context.  Returns
-    ({"sort_every", "part_wg_per_cu"}, trials); no trials when the cache
-    answered.  Empty `wg_candidates` leave the workgroups at all that fit."""
+    per CU at that interval, then the fastest lanes per event list, and set
+    them on the context.  Returns ({"sort_every", "part_wg_per_cu",
+    "apply_lanes"}, trials); no trials when the cache answered.  Empty
+    `wg_candidates` leave the workgroups at all that fit, empty
+    `lane_candidates` the lanes at 64.  With restore_state every trial starts
+    from the cases' state at the call, and the cases end in it."""
     _check(candidates, 1, "sort interval")
     if wg_candidates:
         _check(wg_candidates, 0, "workgroup")
-    key = batch_key(cases) + (":wg" if wg_candidates else "")
+    if lane_candidates and any(int(v) not in (16, 32, 64) for v in lane_candidates):
+        raise ValueError("lane candidates must be 16, 32 or 64")
+    key = batch_key(cases) + (":wg" if wg_candidates else "") + (":lanes" if lane_candidates else "")
     cache: Dict[str, Dict] = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
         if key in cache:
             hit = cache[key]
-            _apply(ctx, int(hit["sort_every"]), int(hit.get("part_wg_per_cu", 0)))
+            _apply(ctx, int(hit["sort_every"]), int(hit.get("part_wg_per_cu", 0)), int(hit.get("apply_lanes", 64)))
             return dict(_chosen[id(ctx)]), []
     steps, base = trial_steps(cases, candidates)
-    half = max(1, steps // 2)
-    run = measure_fn or measure
-    trials = _mirrored([int(k) for k in candidates],
-                       lambda k: run(ctx, cases, k, half, min(base[k], MAX_TRIAL_STEPS), 0))
-    best_k = max(trials, key=lambda t: t.rate).interval
-    best_w = 0
-    if wg_candidates:
-        wt = _mirrored([int(w) for w in wg_candidates],
-                       lambda w: run(ctx, cases, best_k, half, min(base[best_k], MAX_TRIAL_STEPS), w))
-        best_w = max(wt, key=lambda t: t.rate).wg_per_cu
-        trials += wt
-    _apply(ctx, best_k, best_w)
+    measure_one = measure_fn or measure
+    snap = snapshot(cases) if restore_state else None
+
+    def run(*a):
+        if snap is not None:
+            restore(cases, snap)
+        return measure_one(*a)
+    # calibration (not counted; also a warm-up): stretch the trials of a fast
+    # batch to MIN_TRIAL_SECONDS, by whole windows
+    k0 = int(candidates[0])
+    cal = run(ctx, cases, k0, steps, min(base[k0], MAX_TRIAL_STEPS), 0, 64)
+    if 0 < cal.seconds < MIN_TRIAL_SECONDS:
+        steps *= min(MAX_TRIAL_STRETCH, math.ceil(MIN_TRIAL_SECONDS / cal.seconds))
+    per_trial = cal.seconds * steps / cal.steps if cal.steps else 0.0
+    ks = [int(k) for k in candidates]
+    ws = [int(w) for w in wg_candidates] or [0]
+    ls = [int(v) for v in lane_candidates] or [64]
+    combos = [(k, w, v) for k in ks for w in ws for v in ls]
+    if len(combos) > 1 and 2 * len(combos) * per_trial <= JOINT_BUDGET_SECONDS:
+        # every combination, in one mirrored sequence; ties go to the
+        # combination nearest the defaults
+        idx = list(range(len(combos)))
+        trials = _mirrored(idx, lambda i: run(ctx, cases, combos[i][0], steps, min(base[combos[i][0]], MAX_TRIAL_STEPS),
+                                              combos[i][1], combos[i][2]))
+        top = max(t.rate for t in trials)
+        near = [t for t in trials if t.rate >= top / (1.0 + MARGIN)]
+        win = min(near, key=lambda t: (_dist_sort(t.interval) + _dist_wg(t.wg_per_cu) + _dist_lanes(t.lanes),
+                                       t.interval, t.wg_per_cu, t.lanes))
+        best_k, best_w, best_l = win.interval, win.wg_per_cu, win.lanes
+    else:
+        trials = _mirrored(ks, lambda k: run(ctx, cases, k, steps, min(base[k], MAX_TRIAL_STEPS), 0, 64))
+        best_k = _pick(trials, "interval", DEFAULTS["sort_every"], _dist_sort)
+        warm = min(base[best_k], MAX_TRIAL_STEPS)
+        best_w = 0
+        if wg_candidates:
+            wt = _mirrored(ws, lambda w: run(ctx, cases, best_k, steps, warm, w, 64))
+            best_w = _pick(wt, "wg_per_cu", DEFAULTS["part_wg_per_cu"], _dist_wg)
+            trials += wt
+        best_l = 64
+        if lane_candidates:
+            lt = _mirrored(ls, lambda v: run(ctx, cases, best_k, steps, warm, best_w, v))
+            best_l = _pick(lt, "lanes", DEFAULTS["apply_lanes"], _dist_lanes)
+            trials += lt
+    if snap is not None:
+        restore(cases, snap)
+    _apply(ctx, best_k, best_w, best_l)
     if cache_path:
-        cache[key] = {"sort_every": best_k, "part_wg_per_cu": best_w,
+        cache[key] = {"sort_every": best_k, "part_wg_per_cu": best_w, "apply_lanes": best_l,
                       "trials": [dict(asdict(t), rate=t.rate) for t in trials]}
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:
@@ -181,6 +281,6 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
 def tune_sort_interval(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CANDIDATES,
                        cache_path: Optional[str] = None,
                        measure_fn: Optional[Callable[..., Trial]] = None) -> Tuple[int, List[Trial]]:
-    """The sort interval alone (the workgroups stay at all that fit)."""
-    choice, trials = tune_schedule(ctx, cases, candidates, (), cache_path, measure_fn)
+    """The sort interval alone (all workgroups that fit, 64 lanes per list)."""
+    choice, trials = tune_schedule(ctx, cases, candidates, (), (), cache_path, measure_fn)
     return choice["sort_every"], trials

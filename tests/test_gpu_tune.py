@@ -26,16 +26,20 @@ def test_tuning_loses_no_step_and_changes_nothing(ctx):
     ctx.set_option(edupic.OPT_MODE, 1)
     try:
         gs = [_make(ctx, c, st, 0) for c, st in mix]
-        choice, trials = tune.tune_schedule(ctx, gs, candidates=(5, 10, 40), wg_candidates=(0, 2))
+        choice, trials = tune.tune_schedule(ctx, gs, candidates=(5, 10, 40), wg_candidates=(0, 2),
+                                            lane_candidates=(64, 16))
         assert choice["sort_every"] in (5, 10, 40) and choice["part_wg_per_cu"] in (0, 2)
+        assert choice["apply_lanes"] in (64, 16)
         assert tune.last_schedule(ctx) == choice
-        assert len(trials) == 5 and all(t.rate > 0 for t in trials)
+        # one knob at a time (3 + 2 + 2) or, for cases this cheap, every combination (3 x 2 x 2)
+        assert len(trials) in (7, 12) and all(t.rate > 0 for t in trials)
         say(f"chosen {choice}; rates {[round(t.rate / 1e9, 2) for t in trials]} G/s")
         tuned = [_result(g) for g in gs]
         total = tuned[0][3]["step"]
         assert total > 0 and all(r[3]["step"] == total for r in tuned)
         ctx.set_option(edupic.OPT_SORT_EVERY, 7)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, 1)
+        ctx.set_option(edupic.OPT_APPLY_LANES, 32)
         for (c, st), r in zip(mix, tuned):
             g = _make(ctx, c, st, 0)
             g.advance_steps(total)
@@ -47,6 +51,36 @@ def test_tuning_loses_no_step_and_changes_nothing(ctx):
         ctx.set_option(edupic.OPT_MODE, 0)
         ctx.set_option(edupic.OPT_SORT_EVERY, 100)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, 0)
+        ctx.set_option(edupic.OPT_APPLY_LANES, 64)
+
+
+def test_tuning_with_restore_leaves_the_cases_unchanged(ctx):
+    """restore_state: every trial starts from the cases' state at the call,
+    and the cases come back to it, bit for bit, at the same step."""
+    say("test_tuning_with_restore_leaves_the_cases_unchanged")
+    from paper_2103_09642_amd import edupic
+    mix = _mix()[:2]
+    ctx.set_option(edupic.OPT_MODE, 1)
+    try:
+        gs = [_make(ctx, c, st, 3) for c, st in mix]
+        for g in gs:
+            g.advance_steps(40)
+        before = [_result(g) for g in gs]
+        choice, trials = tune.tune_schedule(ctx, gs, candidates=(5, 10), wg_candidates=(0, 2),
+                                            lane_candidates=(64, 16), restore_state=True)
+        assert len(trials) in (6, 8) and all(t.rate > 0 for t in trials)
+        for g, b in zip(gs, before):
+            a = _result(g)
+            assert a[3]["step"] == b[3]["step"] == 43
+            for sp in (0, 1):
+                for k in ("uid", "x", "vx", "vy", "vz"):
+                    assert (a[sp][k] == b[sp][k]).all(), (sp, k)
+            g.destroy()
+    finally:
+        ctx.set_option(edupic.OPT_MODE, 0)
+        ctx.set_option(edupic.OPT_SORT_EVERY, 100)
+        ctx.set_option(edupic.OPT_PART_WG_PER_CU, 0)
+        ctx.set_option(edupic.OPT_APPLY_LANES, 64)
 
 
 def test_workgroup_option_is_validated(ctx):
@@ -55,3 +89,6 @@ def test_workgroup_option_is_validated(ctx):
     for bad in (-1, 65):
         with pytest.raises(edupic.EdpError):
             ctx.set_option(edupic.OPT_PART_WG_PER_CU, bad)
+    for bad in (0, 8, 128):
+        with pytest.raises(edupic.EdpError):
+            ctx.set_option(edupic.OPT_APPLY_LANES, bad)

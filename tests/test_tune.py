@@ -28,9 +28,9 @@ def model(cost):
     """A measure function from a per-step cost model: seconds = steps x cost(k)."""
     calls = []
 
-    def run(ctx, cases, k, steps, warm, wg=0):
+    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
         calls.append((k, steps, warm))
-        return tune.Trial(k, steps, steps * cost(k), steps * 1000, wg)
+        return tune.Trial(k, steps, steps * cost(k), steps * 1000, wg, lanes)
     return run, calls
 
 
@@ -51,10 +51,11 @@ def test_picks_the_fastest_and_sets_it():
     k, trials = tune.tune_sort_interval(ctx, [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
     assert k == 50 and ctx.options[edupic.OPT_SORT_EVERY] == 50
     assert [t.interval for t in trials] == [25, 50, 100, 200]
-    # mirrored order, half-length trials pooled per candidate
-    assert [k for k, _, _ in calls] == [25, 50, 100, 200, 200, 100, 50, 25]
-    assert all(st == 2000 for _, st, _ in calls) and all(t.steps == 4000 for t in trials)
-    assert [w for _, _, w in calls[:4]] == [500, 1000, 2000, 4000]
+    # a calibration run, then the mirrored order with whole-window trials
+    # pooled per candidate
+    assert [k for k, _, _ in calls] == [25] + [25, 50, 100, 200, 200, 100, 50, 25]
+    assert all(st == 4000 for _, st, _ in calls) and all(t.steps == 8000 for t in trials)
+    assert [w for _, _, w in calls[1:5]] == [500, 1000, 2000, 4000]
 
 
 def test_mirrored_order_cancels_a_linear_drift():
@@ -64,8 +65,8 @@ def test_mirrored_order_cancels_a_linear_drift():
     ctx = FakeCtx()
     n = [0]
 
-    def run(ctx_, cases, k, steps, warm, wg=0):
-        t = tune.Trial(k, steps, steps * 1.0, int(steps * 1000 * (1.0 - 0.05 * n[0])), wg)
+    def run(ctx_, cases, k, steps, warm, wg=0, lanes=64):
+        t = tune.Trial(k, steps, steps * 1.0, int(steps * 1000 * (1.0 - 0.05 * n[0])), wg, lanes)
         n[0] += 1
         return t
     k, trials = tune.tune_sort_interval(ctx, [FakeCase(1_000_000, 1000, 20)], measure_fn=run)
@@ -78,7 +79,7 @@ def test_cache_answers_the_same_batch_shape(tmp_path):
     ctx = FakeCtx()
     run, calls = model(lambda k: 1.0 + abs(k - 100) * 1e-3)
     k, trials = tune.tune_sort_interval(ctx, [FakeCase(300_000, 800, 20)] * 3, cache_path=path, measure_fn=run)
-    assert k == 100 and len(trials) == 4 and len(calls) == 8
+    assert k == 100 and len(trials) == 4 and len(calls) == 9
     saved = json.load(open(path))
     (key, entry), = saved.items()
     assert entry["sort_every"] == 100 and "cases=3" in key
@@ -96,23 +97,77 @@ def test_schedule_tunes_the_workgroups_at_the_chosen_interval(tmp_path):
     per CU (0: all that fit) are tried in a mirrored order as well."""
     calls = []
 
-    def run(ctx, cases, k, steps, warm, wg=0):
-        calls.append((k, wg, warm))
-        cost = 22.0 + 70.0 / k + 0.03 * k + {0: 1.0, 4: 0.0, 3: 0.5}[wg]
-        return tune.Trial(k, steps, steps * cost, steps * 1000, wg)
+    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+        calls.append((k, wg, lanes, warm))
+        cost = 22.0 + 70.0 / k + 0.03 * k + {0: 1.0, 4: 0.0, 3: 0.5}[wg] + {64: 0.3, 16: 0.0}[lanes]
+        return tune.Trial(k, steps, steps * cost, steps * 1000, wg, lanes)
     ctx = FakeCtx()
     path = str(tmp_path / "t.json")
     choice, trials = tune.tune_schedule(ctx, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run)
-    assert choice == {"sort_every": 50, "part_wg_per_cu": 4}
+    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "apply_lanes": 16}
     assert ctx.options[edupic.OPT_SORT_EVERY] == 50 and ctx.options[edupic.OPT_PART_WG_PER_CU] == 4
-    assert [(k, w) for k, w, _ in calls[8:]] == [(50, 0), (50, 4), (50, 3), (50, 3), (50, 4), (50, 0)]
-    assert all(warm == 1000 for _, _, warm in calls[8:])
-    assert len(trials) == 7
+    assert ctx.options[edupic.OPT_APPLY_LANES] == 16
+    assert [(k, w) for k, w, _, _ in calls[9:15]] == [(50, 0), (50, 4), (50, 3), (50, 3), (50, 4), (50, 0)]
+    assert [(k, w, ln) for k, w, ln, _ in calls[15:]] == [(50, 4, 64), (50, 4, 16), (50, 4, 16), (50, 4, 64)]
+    assert all(warm == 1000 for _, _, _, warm in calls[9:])
+    assert len(trials) == 9
     entry, = json.load(open(path)).values()
-    assert entry["sort_every"] == 50 and entry["part_wg_per_cu"] == 4
+    assert entry["sort_every"] == 50 and entry["part_wg_per_cu"] == 4 and entry["apply_lanes"] == 16
     ctx2 = FakeCtx()
     assert tune.tune_schedule(ctx2, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run)[1] == []
-    assert ctx2.options[edupic.OPT_PART_WG_PER_CU] == 4
+    assert ctx2.options[edupic.OPT_PART_WG_PER_CU] == 4 and ctx2.options[edupic.OPT_APPLY_LANES] == 16
+
+
+def test_short_trials_are_stretched_by_whole_windows():
+    """A fast batch: the calibration run takes 1/10 of MIN_TRIAL_SECONDS, so
+    every trial runs 10 windows of the common length (capped)."""
+    steps_seen = []
+
+    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+        steps_seen.append(steps)
+        return tune.Trial(k, steps, steps * tune.MIN_TRIAL_SECONDS / 40000, steps * 1000, wg, lanes)
+    tune.tune_sort_interval(FakeCtx(), [FakeCase(10_000, 200, 20)], measure_fn=run)
+    assert steps_seen[0] == 4000
+    assert all(st == 4000 * min(10, tune.MAX_TRIAL_STRETCH) for st in steps_seen[1:])
+
+
+def test_a_default_within_the_margin_is_kept():
+    """Noise-level differences do not move a knob off the library default."""
+    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+        gain = 1.0 + (0.002 if wg == 4 else 0.0) + (0.02 if lanes == 16 else 0.0)
+        return tune.Trial(k, steps, steps / gain, steps * 1000, wg, lanes)
+    choice, _ = tune.tune_schedule(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
+    assert choice == {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 16}
+
+
+def test_a_tie_goes_to_the_value_nearest_the_default():
+    """Intervals 25 and 50 within the margin, both well ahead of 100: 50
+    (nearer 100) is kept."""
+    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+        gain = {25: 1.0301, 50: 1.03, 100: 1.0, 200: 0.95}[k]
+        return tune.Trial(k, steps, steps / gain, steps * 1000, wg, lanes)
+    k, _ = tune.tune_sort_interval(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
+    assert k == 50
+
+
+def test_cheap_batches_search_every_combination():
+    """4 workgroups per CU win only together with 16 lanes: one knob at a
+    time would keep (50, all, 64); trials this short fit the joint budget,
+    so every combination is tried and (50, 4, 16) found."""
+    seen = []
+
+    def rate(k, w, lanes):
+        r = {25: 1.0, 50: 1.05, 100: 1.02, 200: 0.97}[k]
+        if w == 4:
+            r *= 1.03 if lanes == 16 else 0.99
+        return r
+
+    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+        seen.append((k, wg, lanes))
+        return tune.Trial(k, steps, steps * 1e-6 / rate(k, wg, lanes), steps, wg, lanes)
+    choice, trials = tune.tune_schedule(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
+    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "apply_lanes": 16}
+    assert len(trials) == 4 * 3 * 2 and len(seen) == 1 + 2 * 24
 
 
 def test_rejects_bad_candidates():
@@ -120,3 +175,5 @@ def test_rejects_bad_candidates():
         tune.tune_sort_interval(FakeCtx(), [FakeCase(1000, 100, 5)], candidates=(0, 10))
     with pytest.raises(ValueError):
         tune.tune_schedule(FakeCtx(), [FakeCase(1000, 100, 5)], wg_candidates=(4, -1))
+    with pytest.raises(ValueError):
+        tune.tune_schedule(FakeCtx(), [FakeCase(1000, 100, 5)], lane_candidates=(64, 8))
