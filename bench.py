@@ -73,6 +73,9 @@ def main():
                     help="particle workgroups per CU (0: all that fit); -1: the autotuner's choice")
     ap.add_argument("--apply-lanes", type=int, default=0,
                     help="lanes per event list in the head (16, 32, 64); 0: the autotuner's choice")
+    ap.add_argument("--groups", type=int, default=0, choices=(0, 1, 2, 3, 4),
+                    help="lockstep groups of a batched advance, each on a stream of its own "
+                         "(batch64/dual32; a single case runs alone); 0: the autotuner's choice")
     ap.add_argument("--pic-steps", type=int, default=0,
                     help="profiling aid: time this many PIC steps instead of --steps RF cycles")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -205,19 +208,23 @@ def main():
 
 
 def choose_schedule(args, ctx, descs, warm):
-    """The compaction + sort interval, the particle workgroups per CU and
-    the lanes per event list: --sort-every, --wg-per-cu and --apply-lanes if
-    all are given, else the autotuner's choice, made on copies of the
+    """The compaction + sort interval, the particle workgroups per CU, the
+    lanes per event list and the lockstep groups: --sort-every, --wg-per-cu,
+    --apply-lanes and --groups if all are given (a single case: the first
+    three), else the autotuner's choice, made on copies of the
     workload's cases (created from the same seeded descriptors, advanced to
     the timed window's midpoint -- `warm(copies)` -- then tuned with every
     trial starting from that state, so that the trials see the regime of the
     timed window, and destroyed): the timed cases start from exactly the
     state they have without tuning.  Returns the tuning record."""
     from paper_2103_09642_amd import edupic, tune
-    if args.sort_every and args.wg_per_cu >= 0 and args.apply_lanes:
+    if len(descs) == 1 and not args.groups:
+        args.groups = tune.DEFAULTS["groups"]  # no effect on a single case
+    if args.sort_every and args.wg_per_cu >= 0 and args.apply_lanes and args.groups:
         ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, args.wg_per_cu)
         ctx.set_option(edupic.OPT_APPLY_LANES, args.apply_lanes)
+        ctx.set_option(edupic.OPT_GROUPS, args.groups)
         return None
     t0 = time.perf_counter()
     copies = [ctx.create_case(d) for d in descs]
@@ -229,17 +236,19 @@ def choose_schedule(args, ctx, descs, warm):
                                             wg_candidates=(args.wg_per_cu,) if args.wg_per_cu >= 0 else
                                             tune.DEFAULT_WG_CANDIDATES,
                                             lane_candidates=(args.apply_lanes,) if args.apply_lanes else
-                                            tune.DEFAULT_LANE_CANDIDATES, restore_state=True)
+                                            tune.DEFAULT_LANE_CANDIDATES, restore_state=True,
+                                            group_candidates=(args.groups,) if args.groups else
+                                            tune.DEFAULT_GROUP_CANDIDATES)
     finally:
         for c in copies:
             c.destroy()
     args.sort_every, args.wg_per_cu = choice["sort_every"], choice["part_wg_per_cu"]
-    args.apply_lanes = choice["apply_lanes"]
+    args.apply_lanes, args.groups = choice["apply_lanes"], choice["groups"]
     return {"seconds": round(time.perf_counter() - t0, 2),
             "on": "copies of the workload's cases advanced to the timed window's midpoint; "
                   "every trial starts from that state",
-            "trials": [[t.interval, t.wg_per_cu, t.lanes, round(t.rate, 1)] for t in trials],
-            "trial_fields": ["sort_every", "wg_per_cu", "apply_lanes", "particle-steps/s"]}
+            "trials": [[t.interval, t.wg_per_cu, t.lanes, t.groups, round(t.rate, 1)] for t in trials],
+            "trial_fields": ["sort_every", "wg_per_cu", "apply_lanes", "groups", "particle-steps/s"]}
 
 
 def bench_batch(args):
@@ -326,6 +335,7 @@ def bench_batch(args):
                                 "200-1000 nodes, 1e4-5e5 particles per species); step = 1 RF cycle of every case"),
                    "mode": ["plain", "graph"][args.mode],
                    "execution": "sequential" if args.sequential else "one batch",
+                   "groups": args.groups,
                    "sort_every": args.sort_every, "wg_per_cu": args.wg_per_cu, "apply_lanes": args.apply_lanes,
                    "schedule_tuning": tuned,
                    "particle_steps": ps,

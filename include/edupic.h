@@ -129,6 +129,18 @@ extern "C" {
                                  workgroups: 16, 32 or 64 (default); results do
                                  not depend on it, speed does: the autotuner
                                  (tune.py) picks it                           */
+#define EDP_OPT_GROUPS 11     /* lockstep groups of a multi-case advance, 1..4
+                                 (default 2; at most one per case, so a
+                                 single case runs alone): the cases are split
+                                 by expected work (particles x steps), group 0
+                                 runs on the context's stream and the others
+                                 on streams the library creates (default
+                                 priority), so that one group's field solve
+                                 and collisions overlap another's particle
+                                 launch; work enqueued later on the context's
+                                 stream is ordered after every group.
+                                 Results do not depend on it, speed does: the
+                                 autotuner (tune.py) picks it */
 #define EDP_OPT_PART_WG_PER_CU 9 /* resident particle workgroups per CU a batch
                                  uses: 0 (default) all that fit, k >= 1 at
                                  most k; results do not depend on it, speed

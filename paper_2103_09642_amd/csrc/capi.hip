@@ -113,6 +113,26 @@ struct Batch {
   std::vector<int64_t> g_phase;
 };
 
+// One lockstep group of cases: its batch tables, its device role table, and
+// the stream its launches go to.  A multi-case advance runs as one group on
+// the caller's stream, or as up to kMaxGroups groups whose launches go to
+// streams of their own, so that one group's latency-bound head overlaps
+// another's streaming particle launch (the groups share nothing; each keeps
+// its own order).
+constexpr int kMaxGroups = 4;
+struct Group {
+  Batch batch;
+  BlockRole* roles_d = nullptr;
+  size_t roles_cap = 0;
+  std::vector<BlockRole> roles_h;  // host copy of the last upload
+  bool valid = false;  // the tables match batch.cases
+  hipStream_t stream = nullptr;  // where this advance enqueues the group's work
+  // groups 1.. : the library's own stream (default priority) and the event
+  // the caller's stream waits on at the end of an advance
+  hipStream_t own = nullptr;
+  hipEvent_t join = nullptr;
+};
+
 }  // namespace
 
 struct edp_ctx {
@@ -130,12 +150,12 @@ struct edp_ctx {
   int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, poisson = 0;
   int part_wg_per_cu = 0;  // 0: every resident slot
   int apply_lanes = 64;    // lanes per event list in the head's collision workgroups
-  // the workgroup roles of the batch's launches (device table owned by the
-  // context) and the batch's run state
-  BlockRole* roles_d = nullptr;
-  size_t roles_cap = 0;
-  Batch batch;
-  bool batch_valid = false;
+  int groups = 2;  // lockstep groups of a multi-case advance (1..kMaxGroups)
+  // the groups' tables and run state; group 0 runs on `stream`, the others
+  // on streams of their own, forked from and joined back into `stream` by an
+  // advance
+  Group grp[kMaxGroups];
+  hipEvent_t fork_ev = nullptr;
   // profiling
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
   double prof_ms = 0.0;
@@ -307,7 +327,7 @@ int apply_blocks(const edp_ctx* ctx, const Case* c, int lists, int lanes) {
 }
 
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
-int upload_volt(edp_ctx* ctx, Case* c, int64_t s0, int64_t s1) {
+int upload_volt(Case* c, int64_t s0, int64_t s1, hipStream_t st) {
   if (c->vev_pending) {
     HIPCHK(hipEventSynchronize(c->vev));
     c->vev_pending = false;
@@ -317,10 +337,9 @@ int upload_volt(edp_ctx* ctx, Case* c, int64_t s0, int64_t s1) {
   double* ring = const_cast<double*>(c->h.volt);
   const int64_t a = s0 % kVoltChunk;
   const int64_t first = std::min<int64_t>(n, kVoltChunk - a);
-  HIPCHK(hipMemcpyAsync(ring + a, c->vstage, first * 8, hipMemcpyHostToDevice, ctx->stream));
-  if (first < n)
-    HIPCHK(hipMemcpyAsync(ring, c->vstage + first, (n - first) * 8, hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipEventRecord(c->vev, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ring + a, c->vstage, first * 8, hipMemcpyHostToDevice, st));
+  if (first < n) HIPCHK(hipMemcpyAsync(ring, c->vstage + first, (n - first) * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(c->vev, st));
   c->vev_pending = true;
   return EDP_OK;
 }
@@ -333,11 +352,10 @@ void poll_estimate(Case* c) {
   }
 }
 
-int request_estimate(edp_ctx* ctx, Case* c) {
+int request_estimate(Case* c, hipStream_t st) {
   if (c->est_pending) return EDP_OK;
-  HIPCHK(hipMemcpyAsync(c->est_pinned, (char*)c->d + offsetof(CaseDev, alloc), 16,
-                        hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipEventRecord(c->est_ev, ctx->stream));
+  HIPCHK(hipMemcpyAsync(c->est_pinned, (char*)c->d + offsetof(CaseDev, alloc), 16, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(c->est_ev, st));
   c->est_pending = true;
   return EDP_OK;
 }
@@ -362,12 +380,35 @@ int drain_profile(edp_ctx* ctx) {
   return EDP_OK;
 }
 
-void drop_graph(edp_ctx* ctx) {
-  if (ctx->batch.gexec) {
-    (void)hipGraphExecDestroy(ctx->batch.gexec);
-    ctx->batch.gexec = nullptr;
+void drop_graph(Group& G) {
+  if (G.batch.gexec) {
+    (void)hipGraphExecDestroy(G.batch.gexec);
+    G.batch.gexec = nullptr;
   }
-  ctx->batch.g_steps = 0;
+  G.batch.g_steps = 0;
+}
+
+void destroy_group_streams(edp_ctx* ctx) {
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  ctx->fork_ev = nullptr;
+  for (Group& G : ctx->grp) {
+    if (G.own) (void)hipStreamDestroy(G.own);
+    if (G.join) (void)hipEventDestroy(G.join);
+    G.own = nullptr;
+    G.join = nullptr;
+  }
+}
+
+// Drain every group's stream and forget their graphs and tables.
+int reset_groups(edp_ctx* ctx) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (Group& G : ctx->grp)
+    if (G.own) HIPCHK(hipStreamSynchronize(G.own));
+  for (Group& G : ctx->grp) {
+    drop_graph(G);
+    G.valid = false;
+  }
+  return EDP_OK;
 }
 
 // Workgroup j of n of case c in a batched launch.
@@ -386,8 +427,8 @@ int sort_blocks(const edp_ctx* ctx, const Case* c, int sp) { return std::max(1, 
 // chunks over whatever workgroups a case has).  The table is read by
 // kernels still in flight, so the stream is drained before it changes;
 // grids are rebuilt only when a case's estimate has moved by a quarter.
-int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
-  Batch& B = ctx->batch;
+int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
+  Batch& B = G.batch;
   const size_t nc = cs.size();
   size_t lds[2] = {0, 0};
   int max_ng = 2;
@@ -414,16 +455,16 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
   for (int sp = 0; sp < 2; ++sp)
     for (size_t k = 0; k < nc; ++k) want_sort[sp].push_back(sort_blocks(ctx, cs[k], sp));
   auto near = [](int a, int a0) { return a <= a0 * 5 / 4 + 1 && a >= a0 * 3 / 4; };
-  bool same = ctx->batch_valid && B.cases == cs;
+  bool same = G.valid && B.cases == cs;
   for (size_t k = 0; k < nc && same; ++k) {
     same = near(want_apply[k], B.h.apply_off[k + 1] - B.h.apply_off[k]);
     for (int sp = 0; sp < 2 && same; ++sp) same = near(want[sp][k], B.h.part_off[sp][k + 1] - B.h.part_off[sp][k]);
     for (int sp = 0; sp < 2 && same; ++sp) same = near(want_sort[sp][k], B.h.sort_off[sp][k + 1] - B.h.sort_off[sp][k]);
   }
   if (same) return EDP_OK;
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  drop_graph(ctx);
-  ctx->batch_valid = false;
+  HIPCHK(hipStreamSynchronize(G.stream));
+  drop_graph(G);
+  G.valid = false;
   B.cases = cs;
   B.h = BatchTable{};
   B.h.ncase = (int32_t)nc;
@@ -458,16 +499,20 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
     for (size_t k = 0; k < nc; ++k)
       for (int j = 0; j < want_sort[sp][k]; ++j) roles.push_back(role(cs[k], j, want_sort[sp][k]));
   }
-  if (roles.size() > ctx->roles_cap) {
-    // no kernel is in flight (drained above)
-    if (ctx->roles_d) HIPCHK(hipFree(ctx->roles_d));
-    ctx->roles_d = nullptr;
-    ctx->roles_cap = 0;
-    HIPCHK(hipMalloc((void**)&ctx->roles_d, roles.size() * sizeof(BlockRole)));
-    ctx->roles_cap = roles.size();
+  if (roles.size() > G.roles_cap) {
+    // no kernel of this group is in flight (drained above)
+    if (G.roles_d) HIPCHK(hipFree(G.roles_d));
+    G.roles_d = nullptr;
+    G.roles_cap = 0;
+    HIPCHK(hipMalloc((void**)&G.roles_d, roles.size() * sizeof(BlockRole)));
+    G.roles_cap = roles.size();
   }
-  HIPCHK(hipMemcpy(ctx->roles_d, roles.data(), roles.size() * sizeof(BlockRole), hipMemcpyHostToDevice));
-  ctx->batch_valid = true;
+  // ordered on the group's own stream (a blocking copy would also wait for
+  // the other group's work when the caller's stream is the null stream)
+  G.roles_h.swap(roles);
+  HIPCHK(hipMemcpyAsync(G.roles_d, G.roles_h.data(), G.roles_h.size() * sizeof(BlockRole), hipMemcpyHostToDevice,
+                        G.stream));
+  G.valid = true;
   return EDP_OK;
 }
 
@@ -475,11 +520,11 @@ int set_batch(edp_ctx* ctx, const std::vector<Case*>& cs) {
 // one head for every case (fields of this step, collisions of the last),
 // the compaction/sort of the cases due for it, then one electron launch and,
 // when some case has an ion step, one ion launch.
-int enqueue_batch_step(edp_ctx* ctx, const std::vector<int64_t>& s, int64_t j, bool capture) {
-  Batch& B = ctx->batch;
-  hipStream_t st = ctx->stream;
+int enqueue_batch_step(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, int64_t j, bool capture) {
+  Batch& B = G.batch;
+  hipStream_t st = G.stream;
   const int nc = (int)B.cases.size();
-  HIPCHK(launch_head(ctx->roles_d + B.role_off[2], nc, B.apply, B.max_ng, ctx->poisson, ctx->apply_lanes, st));
+  HIPCHK(launch_head(G.roles_d + B.role_off[2], nc, B.apply, B.max_ng, ctx->poisson, ctx->apply_lanes, st));
   bool any_ion = false, sort_e = false, sort_i = false;
   for (int k = 0; k < nc; ++k) {
     const int64_t sk = s[k] + j;
@@ -490,34 +535,34 @@ int enqueue_batch_step(edp_ctx* ctx, const std::vector<int64_t>& s, int64_t j, b
   }
   // one set of sort launches per species for the whole batch; the cases that
   // are not due skip them on the device
-  const BlockRole* case_roles = ctx->roles_d + B.role_off[2];
+  const BlockRole* case_roles = G.roles_d + B.role_off[2];
   if (sort_e)
-    HIPCHK(launch_sort(ctx->roles_d + B.role_off[3], case_roles, 0, B.sorts[0], nc, B.max_ng, ctx->sort_every, st));
+    HIPCHK(launch_sort(G.roles_d + B.role_off[3], case_roles, 0, B.sorts[0], nc, B.max_ng, ctx->sort_every, st));
   if (sort_i)
-    HIPCHK(launch_sort(ctx->roles_d + B.role_off[4], case_roles, 1, B.sorts[1], nc, B.max_ng, ctx->sort_every, st));
+    HIPCHK(launch_sort(G.roles_d + B.role_off[4], case_roles, 1, B.sorts[1], nc, B.max_ng, ctx->sort_every, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profile && !capture) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
   }
-  HIPCHK(launch_particles(ctx->roles_d + B.role_off[0], 0, B.parts[0], B.lds[0], st, e0, e1));
+  HIPCHK(launch_particles(G.roles_d + B.role_off[0], 0, B.parts[0], B.lds[0], st, e0, e1));
   if (e0) ctx->ev_pairs.emplace_back(e0, e1);
-  if (any_ion) HIPCHK(launch_particles(ctx->roles_d + B.role_off[1], 1, B.parts[1], B.lds[1], st, nullptr, nullptr));
+  if (any_ion) HIPCHK(launch_particles(G.roles_d + B.role_off[1], 1, B.parts[1], B.lds[1], st, nullptr, nullptr));
   return EDP_OK;
 }
 
 // Capture `steps` batch steps from the cases' current steps into a graph.
-int build_graph(edp_ctx* ctx, const std::vector<int64_t>& s, int steps) {
-  Batch& B = ctx->batch;
-  drop_graph(ctx);
+int build_graph(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, int steps) {
+  Batch& B = G.batch;
+  drop_graph(G);
   const int nc = (int)B.cases.size();
   B.g_phase.resize(nc);
   for (int k = 0; k < nc; ++k) B.g_phase[k] = s[k] % steps;
-  hipStream_t st = ctx->stream;
+  hipStream_t st = G.stream;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   int r = EDP_OK;
-  for (int j = 0; j < steps && r == EDP_OK; ++j) r = enqueue_batch_step(ctx, s, j, true);
+  for (int j = 0; j < steps && r == EDP_OK; ++j) r = enqueue_batch_step(ctx, G, s, j, true);
   const hipError_t ec = hipStreamEndCapture(st, &g);
   if (r) {
     if (g) (void)hipGraphDestroy(g);
@@ -531,76 +576,128 @@ int build_graph(edp_ctx* ctx, const std::vector<int64_t>& s, int steps) {
   return EDP_OK;
 }
 
-bool graph_matches(const edp_ctx* ctx, const std::vector<int64_t>& s, int steps) {
-  const Batch& B = ctx->batch;
+bool graph_matches(const Group& G, const std::vector<int64_t>& s, int steps) {
+  const Batch& B = G.batch;
   if (!B.gexec || B.g_steps != steps) return false;
   for (size_t k = 0; k < B.cases.size(); ++k)
     if (s[k] % steps != B.g_phase[k]) return false;
   return true;
 }
 
-// Advance cases[k] by n[k] steps, all in lockstep: every launch serves every
-// case that still has steps to go.  Windows of up to 4096 steps; in graph
-// mode, whole graphs of a multiple of sort_every * N_SUB steps.
-int run_batch(edp_ctx* ctx, const std::vector<Case*>& cases, const std::vector<int64_t>& n) {
-  std::vector<int64_t> left(n);
-  for (;;) {
-    std::vector<Case*> act;
-    std::vector<int64_t> s;
-    int64_t w = 4096;
-    int64_t base = 1;
-    for (size_t k = 0; k < cases.size(); ++k) {
-      if (left[k] <= 0) continue;
-      act.push_back(cases[k]);
-      s.push_back(cases[k]->step);
-      w = std::min(w, left[k]);
-      const int64_t p = (int64_t)ctx->sort_every * cases[k]->desc.ion_subcycle;
-      base = std::lcm(base, p);
-    }
-    if (act.empty()) break;
-    for (Case* c : act) poll_estimate(c);
-    int r = set_batch(ctx, act);
+// One window (up to 4096 steps) of the cases of group G that still have
+// steps to go, all in lockstep: the group's tables, the voltages, then graph
+// replays (whole graphs of a multiple of sort_every * N_SUB steps) or plain
+// steps on the group's stream.  `done`: no case had steps left.
+int group_window(edp_ctx* ctx, Group& G, const std::vector<Case*>& cases, std::vector<int64_t>& left, bool& done) {
+  std::vector<Case*> act;
+  std::vector<int64_t> s;
+  int64_t w = 4096;
+  int64_t base = 1;
+  for (size_t k = 0; k < cases.size(); ++k) {
+    if (left[k] <= 0) continue;
+    act.push_back(cases[k]);
+    s.push_back(cases[k]->step);
+    w = std::min(w, left[k]);
+    const int64_t p = (int64_t)ctx->sort_every * cases[k]->desc.ion_subcycle;
+    base = std::lcm(base, p);
+  }
+  done = act.empty();
+  if (done) return EDP_OK;
+  for (Case* c : act) poll_estimate(c);
+  int r = set_batch(ctx, G, act);
+  if (r) return r;
+  int gsteps = 0;
+  if (ctx->mode == 1 && base <= 4096) {
+    gsteps = ctx->graph_steps > 0 ? ctx->graph_steps : (int)(base * std::max<int64_t>(1, 200 / base));
+    if (gsteps % base != 0) gsteps = (int)((gsteps / base + 1) * base);
+    if (gsteps <= w) w = (w / gsteps) * gsteps; else gsteps = 0;
+  }
+  for (Case* c : act) {
+    r = upload_volt(c, c->step, c->step + w, G.stream);
     if (r) return r;
-    int gsteps = 0;
-    if (ctx->mode == 1 && base <= 4096) {
-      gsteps = ctx->graph_steps > 0 ? ctx->graph_steps : (int)(base * std::max<int64_t>(1, 200 / base));
-      if (gsteps % base != 0) gsteps = (int)((gsteps / base + 1) * base);
-      if (gsteps <= w) w = (w / gsteps) * gsteps; else gsteps = 0;
-    }
-    for (Case* c : act) {
-      r = upload_volt(ctx, c, c->step, c->step + w);
-      if (r) return r;
-    }
-    int64_t j = 0;
-    while (j < w) {
-      if (gsteps > 0) {
-        std::vector<int64_t> sj(s);
-        for (auto& v : sj) v += j;
-        if (!graph_matches(ctx, sj, gsteps)) {
-          r = build_graph(ctx, sj, gsteps);
-          if (r) return r;
-        }
-        HIPCHK(hipGraphLaunch(ctx->batch.gexec, ctx->stream));
-        j += gsteps;
-        continue;
+  }
+  int64_t j = 0;
+  while (j < w) {
+    if (gsteps > 0) {
+      std::vector<int64_t> sj(s);
+      for (auto& v : sj) v += j;
+      if (!graph_matches(G, sj, gsteps)) {
+        r = build_graph(ctx, G, sj, gsteps);
+        if (r) return r;
       }
-      r = enqueue_batch_step(ctx, s, j, false);
-      if (r) return r;
-      ++j;
+      HIPCHK(hipGraphLaunch(G.batch.gexec, G.stream));
+      j += gsteps;
+      continue;
     }
-    for (size_t k = 0, a = 0; k < cases.size(); ++k) {
-      if (left[k] <= 0) continue;
-      cases[k]->step += w;
-      left[k] -= w;
-      r = request_estimate(ctx, act[a++]);
-      if (r) return r;
-    }
-    if (ctx->ev_pairs.size() > 8192) {
-      r = drain_profile(ctx);
-      if (r) return r;
-    }
+    r = enqueue_batch_step(ctx, G, s, j, false);
+    if (r) return r;
+    ++j;
+  }
+  for (size_t k = 0, a = 0; k < cases.size(); ++k) {
+    if (left[k] <= 0) continue;
+    cases[k]->step += w;
+    left[k] -= w;
+    r = request_estimate(act[a++], G.stream);
+    if (r) return r;
+  }
+  if (ctx->ev_pairs.size() > 8192) {
+    r = drain_profile(ctx);
+    if (r) return r;
   }
   return EDP_OK;
+}
+
+// Advance cases[k] by n[k] steps.  With G groups (the option, at most one
+// per case) the cases are split into G lockstep groups balanced by expected
+// work (particles x steps, largest first onto the least loaded group), each
+// keeping the call's order; the streams of groups 1.. wait for everything
+// enqueued on the caller's stream before they start, windows of the groups
+// are enqueued in turn, and the caller's stream waits for every group at
+// the end, so every later call on it is ordered after all of them.
+int run_batch(edp_ctx* ctx, const std::vector<Case*>& cases, const std::vector<int64_t>& n) {
+  const int ng = (int)std::min<size_t>((size_t)ctx->groups, std::max<size_t>(1, cases.size()));
+  std::vector<Case*> gc[kMaxGroups];
+  std::vector<int64_t> gl[kMaxGroups];
+  if (ng == 1) {
+    gc[0] = cases;
+    gl[0] = n;
+  } else {
+    std::vector<size_t> order(cases.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    auto work = [&](size_t k) { return (double)(cases[k]->est[0] + cases[k]->est[1]) * (double)n[k]; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work(a) > work(b); });
+    double load[kMaxGroups] = {};
+    std::vector<int> in(cases.size());
+    for (size_t k : order) {
+      int g = 0;
+      for (int h = 1; h < ng; ++h)
+        if (load[h] < load[g]) g = h;
+      in[k] = g;
+      load[g] += work(k);
+    }
+    for (size_t k = 0; k < cases.size(); ++k) {
+      gc[in[k]].push_back(cases[k]);
+      gl[in[k]].push_back(n[k]);
+    }
+  }
+  ctx->grp[0].stream = ctx->stream;
+  for (int g = 1; g < kMaxGroups; ++g) ctx->grp[g].stream = ctx->grp[g].own;
+  if (ng > 1) {
+    HIPCHK(hipEventRecord(ctx->fork_ev, ctx->stream));
+    for (int g = 1; g < ng; ++g) HIPCHK(hipStreamWaitEvent(ctx->grp[g].own, ctx->fork_ev, 0));
+  }
+  int r = EDP_OK;
+  bool done[kMaxGroups] = {};
+  for (int g = ng; g < kMaxGroups; ++g) done[g] = true;
+  auto all_done = [&] { return std::all_of(done, done + kMaxGroups, [](bool d) { return d; }); };
+  while (r == EDP_OK && !all_done())
+    for (int g = 0; g < ng && r == EDP_OK; ++g)
+      if (!done[g]) r = group_window(ctx, ctx->grp[g], gc[g], gl[g], done[g]);
+  for (int g = 1; g < ng; ++g) {
+    HIPCHK(hipEventRecord(ctx->grp[g].join, ctx->grp[g].own));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->grp[g].join, 0));
+  }
+  return r;
 }
 
 int deposit_species(edp_ctx* ctx, Case* c, int sp, int64_t step) {
@@ -680,15 +777,26 @@ int edp_create(edp_ctx** out, int device, void* hip_stream) {
   ctx->stream = (hipStream_t)hip_stream;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+  // the other groups' streams (default priority) and the fork/join events
+  bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int g = 1; g < kMaxGroups && ok; ++g)
+    ok = hipStreamCreateWithFlags(&ctx->grp[g].own, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&ctx->grp[g].join, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    destroy_group_streams(ctx);
+    delete ctx;
+    return fail(EDP_EHIP, "creating the groups' streams or events failed");
+  }
   *out = ctx;
   return EDP_OK;
 }
 
 int edp_destroy(edp_ctx* ctx) {
   if (!ctx) return EDP_OK;
-  (void)hipStreamSynchronize(ctx->stream);
-  drop_graph(ctx);
-  if (ctx->roles_d) (void)hipFree(ctx->roles_d);
+  (void)reset_groups(ctx);
+  for (Group& G : ctx->grp)
+    if (G.roles_d) (void)hipFree(G.roles_d);
+  destroy_group_streams(ctx);
   for (auto& kv : ctx->cases) {
     Case* c = kv.second;
     if (c->vstage) (void)hipHostFree(c->vstage);
@@ -919,11 +1027,14 @@ int edp_case_destroy(edp_ctx* ctx, edp_case id) {
   Case* c = find(ctx, id);
   if (!c) return fail(EDP_EINVAL, "unknown case");
   (void)hipStreamSynchronize(ctx->stream);
-  if (std::find(ctx->batch.cases.begin(), ctx->batch.cases.end(), c) != ctx->batch.cases.end()) {
-    drop_graph(ctx);
-    ctx->batch.cases.clear();
-    ctx->batch_valid = false;
-  }
+  for (Group& G : ctx->grp)
+    if (G.own) (void)hipStreamSynchronize(G.own);
+  for (Group& G : ctx->grp)
+    if (std::find(G.batch.cases.begin(), G.batch.cases.end(), c) != G.batch.cases.end()) {
+      drop_graph(G);
+      G.batch.cases.clear();
+      G.valid = false;
+    }
   (void)hipHostFree(c->vstage);
   (void)hipHostFree(c->est_pinned);
   (void)hipEventDestroy(c->vev);
@@ -976,6 +1087,8 @@ int edp_advance(edp_ctx* ctx, const edp_case* cases, int32_t n_cases, const int3
 int edp_sync(edp_ctx* ctx) {
   if (!ctx) return fail(EDP_EINVAL, "null context");
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (Group& G : ctx->grp)
+    if (G.own) HIPCHK(hipStreamSynchronize(G.own));
   int status = EDP_OK;
   for (auto& kv : ctx->cases) {
     Case* c = kv.second;
@@ -1436,8 +1549,12 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
 
 int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
   if (!ctx) return fail(EDP_EINVAL, "null context");
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  drop_graph(ctx);  // every option changes what a captured step sequence contains
+  // every option changes what a captured step sequence contains (and some the
+  // tables): drain both groups and rebuild on the next advance
+  {
+    const int r = reset_groups(ctx);
+    if (r) return r;
+  }
   switch (key) {
     case EDP_OPT_MODE:
       if (value < 0 || value > 1) return fail(EDP_EINVAL, "mode must be 0 or 1");
@@ -1461,12 +1578,15 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
     case EDP_OPT_APPLY_LANES:
       if (value != 16 && value != 32 && value != 64) return fail(EDP_EINVAL, "lanes per event list must be 16, 32 or 64");
       ctx->apply_lanes = (int)value;
-      ctx->batch_valid = false;  // the collision workgroup count changes
       break;
     case EDP_OPT_PART_WG_PER_CU:
       if (value < 0 || value > 64) return fail(EDP_EINVAL, "workgroups per CU must be 0..64");
       ctx->part_wg_per_cu = (int)value;
-      ctx->batch_valid = false;  // the grids change: rebuild the batch tables
+      break;
+    case EDP_OPT_GROUPS:
+      static_assert(kMaxGroups == 4, "the message below names the limit");
+      if (value < 1 || value > kMaxGroups) return fail(EDP_EINVAL, "groups must be 1..4");
+      ctx->groups = (int)value;
       break;
     default:
       return fail(EDP_EINVAL, "unknown option %d", key);

@@ -1,6 +1,7 @@
 """Autotuner for the batch runtime's schedule: the compaction + cell-sort
-interval, the particle workgroups per CU and the lanes per event list of the
-head's collision workgroups.
+interval, the particle workgroups per CU, the lanes per event list of the
+head's collision workgroups and, for a batch of several cases, the number of
+lockstep groups it runs as.
 
 * The sort every K steps trades its own cost (one pass over every particle
   array of the cases due) against the particle kernel's locality: between
@@ -25,7 +26,11 @@ fastest.  The knobs interact (4 workgroups per CU win at one sort interval
 and lose at another), so when the calibration run says that every
 combination fits in JOINT_BUDGET_SECONDS the tuner tries them all;
 otherwise one knob at a time: the sort interval, then the workgroups per
-CU at that interval, then the lanes per list.  The cases evolve while they are measured
+CU at that interval, then the lanes per list.  Last, for a batch of several
+cases, the lockstep groups (each on a stream of its own, one group's head
+overlapping another's particle launch: 2 groups gain 10-26% on the batched
+sets, 3 or 4 a few percent more, depending on the set) at the chosen
+schedule.  The cases evolve while they are measured
 (a seeded plasma loses or gains particles for many cycles), so the
 candidates of a knob run in a mirrored order (A B C D D C B A) and each
 one's rate pools its two trials: a linear drift of the throughput cancels.
@@ -50,17 +55,18 @@ import json
 import math
 import os
 import time
-from dataclasses import asdict, dataclass
+from dataclasses import asdict, dataclass, replace
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 DEFAULT_CANDIDATES = (25, 50, 100, 200)  # sort intervals (steps)
 DEFAULT_WG_CANDIDATES = (0, 4, 3)        # particle workgroups per CU (0: all that fit)
 DEFAULT_LANE_CANDIDATES = (64, 16)       # lanes per event list in the head
+DEFAULT_GROUP_CANDIDATES = (2, 3, 4)     # lockstep groups of a multi-case batch
 MAX_TRIAL_STEPS = 8000
 MAX_TRIAL_STRETCH = 8       # at most this many windows per trial
 MIN_TRIAL_SECONDS = 0.3     # calibration target per trial
 MARGIN = 0.005              # rates this close to the fastest count as a tie
-DEFAULTS = {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 64}
+DEFAULTS = {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 64, "groups": 2}
 JOINT_BUDGET_SECONDS = 60.0  # all combinations tried together below this estimate
 _chosen: Dict[int, Dict[str, int]] = {}  # last choice the tuner set, per context object
 
@@ -73,6 +79,7 @@ class Trial:
     particle_steps: int
     wg_per_cu: int = 0   # the particle workgroups per CU of the trial
     lanes: int = 64      # the lanes per event list of the trial
+    groups: int = 2      # the lockstep groups of the trial (set by the tuner)
 
     @property
     def rate(self) -> float:
@@ -145,8 +152,8 @@ def _mirrored(values: Sequence[int], trial: Callable[[int], Trial]) -> List[Tria
     out = []
     for v in values:
         mine = [t for w, t in runs if w == v]
-        out.append(Trial(mine[0].interval, sum(t.steps for t in mine), sum(t.seconds for t in mine),
-                         sum(t.particle_steps for t in mine), mine[0].wg_per_cu, mine[0].lanes))
+        out.append(replace(mine[0], steps=sum(t.steps for t in mine), seconds=sum(t.seconds for t in mine),
+                           particle_steps=sum(t.particle_steps for t in mine)))
     return out
 
 
@@ -171,17 +178,22 @@ def _dist_lanes(v):
     return abs(math.log2(v / DEFAULTS["apply_lanes"]))
 
 
+def _dist_groups(g):
+    return abs(g - DEFAULTS["groups"])
+
+
 def _check(candidates, lo, what):
     if not candidates or any(int(k) < lo for k in candidates):
         raise ValueError(f"{what} candidates must be >= {lo}")
 
 
-def _apply(ctx, sort_every: int, wg: int, lanes: int):
+def _apply(ctx, sort_every: int, wg: int, lanes: int, groups: int):
     from . import edupic
     ctx.set_option(edupic.OPT_SORT_EVERY, sort_every)
     ctx.set_option(edupic.OPT_PART_WG_PER_CU, wg)
     ctx.set_option(edupic.OPT_APPLY_LANES, lanes)
-    _chosen[id(ctx)] = {"sort_every": sort_every, "part_wg_per_cu": wg, "apply_lanes": lanes}
+    ctx.set_option(edupic.OPT_GROUPS, groups)
+    _chosen[id(ctx)] = {"sort_every": sort_every, "part_wg_per_cu": wg, "apply_lanes": lanes, "groups": groups}
 
 
 def snapshot(cases: Sequence) -> List:
@@ -199,28 +211,43 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
                   wg_candidates: Sequence[int] = DEFAULT_WG_CANDIDATES,
                   lane_candidates: Sequence[int] = DEFAULT_LANE_CANDIDATES, cache_path: Optional[str] = None,
                   measure_fn: Optional[Callable[..., Trial]] = None,
-                  restore_state: bool = False) -> Tuple[Dict[str, int], List[Trial]]:
+                  restore_state: bool = False,
+                  group_candidates: Sequence[int] = DEFAULT_GROUP_CANDIDATES) -> Tuple[Dict[str, int], List[Trial]]:
     """Pick the fastest sort interval, then the fastest particle workgroups
-    per CU at that interval, then the fastest lanes per event list, and set
-    them on the context.  Returns ({"sort_every", "part_wg_per_cu",
-    "apply_lanes"}, trials); no trials when the cache answered.  Empty
+    per CU at that interval, then the fastest lanes per event list, then (a
+    batch of several cases) the fastest lockstep groups, and set them on the
+    context.  Returns ({"sort_every", "part_wg_per_cu", "apply_lanes",
+    "groups"}, trials); no trials when the cache answered.  Empty
     `wg_candidates` leave the workgroups at all that fit, empty
-    `lane_candidates` the lanes at 64.  With restore_state every trial starts
-    from the cases' state at the call, and the cases end in it."""
+    `lane_candidates` the lanes at 64, empty `group_candidates` (or a
+    batch with fewer cases than two of them) the groups at 2.  Every trial
+    before the groups stage runs with 2 groups.  With restore_state every
+    trial starts from the cases' state at the call, and the cases end in
+    it."""
+    from . import edupic
     _check(candidates, 1, "sort interval")
     if wg_candidates:
         _check(wg_candidates, 0, "workgroup")
     if lane_candidates and any(int(v) not in (16, 32, 64) for v in lane_candidates):
         raise ValueError("lane candidates must be 16, 32 or 64")
-    key = batch_key(cases) + (":wg" if wg_candidates else "") + (":lanes" if lane_candidates else "")
+    if group_candidates and any(int(g) not in (1, 2, 3, 4) for g in group_candidates):
+        raise ValueError("group candidates must be 1..4")
+    # more groups than cases run as one group per case: those candidates are
+    # the same as the case count
+    gs = sorted({min(int(g), len(cases)) for g in group_candidates})
+    gs = gs if len(gs) > 1 else []
+    key = (batch_key(cases) + (":wg" if wg_candidates else "") + (":lanes" if lane_candidates else "") +
+           (":groups" if gs else ""))
     cache: Dict[str, Dict] = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
         if key in cache:
             hit = cache[key]
-            _apply(ctx, int(hit["sort_every"]), int(hit.get("part_wg_per_cu", 0)), int(hit.get("apply_lanes", 64)))
+            _apply(ctx, int(hit["sort_every"]), int(hit.get("part_wg_per_cu", 0)), int(hit.get("apply_lanes", 64)),
+                   int(hit.get("groups", DEFAULTS["groups"])))
             return dict(_chosen[id(ctx)]), []
+    ctx.set_option(edupic.OPT_GROUPS, DEFAULTS["groups"])
     steps, base = trial_steps(cases, candidates)
     measure_one = measure_fn or measure
     snap = snapshot(cases) if restore_state else None
@@ -265,11 +292,21 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
             lt = _mirrored(ls, lambda v: run(ctx, cases, best_k, steps, warm, best_w, v))
             best_l = _pick(lt, "lanes", DEFAULTS["apply_lanes"], _dist_lanes)
             trials += lt
+    trials = [replace(t, groups=DEFAULTS["groups"]) for t in trials]
+    best_g = DEFAULTS["groups"]
+    if gs:
+        def group_trial(g):
+            ctx.set_option(edupic.OPT_GROUPS, g)
+            return replace(run(ctx, cases, best_k, steps, min(base[best_k], MAX_TRIAL_STEPS), best_w, best_l),
+                           groups=g)
+        gt = _mirrored(gs, group_trial)
+        best_g = _pick(gt, "groups", DEFAULTS["groups"], _dist_groups)
+        trials += gt
     if snap is not None:
         restore(cases, snap)
-    _apply(ctx, best_k, best_w, best_l)
+    _apply(ctx, best_k, best_w, best_l, best_g)
     if cache_path:
-        cache[key] = {"sort_every": best_k, "part_wg_per_cu": best_w, "apply_lanes": best_l,
+        cache[key] = {"sort_every": best_k, "part_wg_per_cu": best_w, "apply_lanes": best_l, "groups": best_g,
                       "trials": [dict(asdict(t), rate=t.rate) for t in trials]}
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:
@@ -281,6 +318,7 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
 def tune_sort_interval(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CANDIDATES,
                        cache_path: Optional[str] = None,
                        measure_fn: Optional[Callable[..., Trial]] = None) -> Tuple[int, List[Trial]]:
-    """The sort interval alone (all workgroups that fit, 64 lanes per list)."""
-    choice, trials = tune_schedule(ctx, cases, candidates, (), (), cache_path, measure_fn)
+    """The sort interval alone (all workgroups that fit, 64 lanes per list,
+    2 groups)."""
+    choice, trials = tune_schedule(ctx, cases, candidates, (), (), cache_path, measure_fn, group_candidates=())
     return choice["sort_every"], trials

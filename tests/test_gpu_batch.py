@@ -57,14 +57,18 @@ def _same(a, b, label):
     assert a[3] == b[3], f"{label}: counters"
 
 
+@pytest.mark.parametrize("groups", [1, 2, 4])
 @pytest.mark.parametrize("mode", [0, 1], ids=["plain", "graph"])
-def test_batch_equals_alone(ctx, mode):
+def test_batch_equals_alone(ctx, mode, groups):
     """Different step counts (the batch shrinks as cases finish) and
-    different starting steps (different ion-step and sort phases)."""
-    say(f"test_batch_equals_alone mode={mode}")
+    different starting steps (different ion-step and sort phases); in one
+    lockstep group, and split into two or four groups on streams of their
+    own."""
+    say(f"test_batch_equals_alone mode={mode} groups={groups}")
     from paper_2103_09642_amd import edupic
     ctx.set_option(edupic.OPT_MODE, mode)
     ctx.set_option(edupic.OPT_SORT_EVERY, 10)
+    ctx.set_option(edupic.OPT_GROUPS, groups)
     mix = _mix()
     steps = [700, 433, 700, 120]
     starts = [0, 3, 17, 5]
@@ -83,6 +87,10 @@ def test_batch_equals_alone(ctx, mode):
         g.destroy()
     ctx.set_option(edupic.OPT_MODE, 0)
     ctx.set_option(edupic.OPT_SORT_EVERY, 100)
+    ctx.set_option(edupic.OPT_GROUPS, 1)
+    for bad in (0, 5):
+        with pytest.raises(edupic.EdpError):
+            ctx.set_option(edupic.OPT_GROUPS, bad)
 
 
 def test_batch_matches_oracle(ctx, xs_default, orc):

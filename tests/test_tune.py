@@ -103,8 +103,9 @@ def test_schedule_tunes_the_workgroups_at_the_chosen_interval(tmp_path):
         return tune.Trial(k, steps, steps * cost, steps * 1000, wg, lanes)
     ctx = FakeCtx()
     path = str(tmp_path / "t.json")
-    choice, trials = tune.tune_schedule(ctx, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run)
-    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "apply_lanes": 16}
+    choice, trials = tune.tune_schedule(ctx, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run,
+                                        group_candidates=())
+    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "apply_lanes": 16, "groups": 2}
     assert ctx.options[edupic.OPT_SORT_EVERY] == 50 and ctx.options[edupic.OPT_PART_WG_PER_CU] == 4
     assert ctx.options[edupic.OPT_APPLY_LANES] == 16
     assert [(k, w) for k, w, _, _ in calls[9:15]] == [(50, 0), (50, 4), (50, 3), (50, 3), (50, 4), (50, 0)]
@@ -114,7 +115,8 @@ def test_schedule_tunes_the_workgroups_at_the_chosen_interval(tmp_path):
     entry, = json.load(open(path)).values()
     assert entry["sort_every"] == 50 and entry["part_wg_per_cu"] == 4 and entry["apply_lanes"] == 16
     ctx2 = FakeCtx()
-    assert tune.tune_schedule(ctx2, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run)[1] == []
+    assert tune.tune_schedule(ctx2, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run,
+                              group_candidates=())[1] == []
     assert ctx2.options[edupic.OPT_PART_WG_PER_CU] == 4 and ctx2.options[edupic.OPT_APPLY_LANES] == 16
 
 
@@ -137,7 +139,7 @@ def test_a_default_within_the_margin_is_kept():
         gain = 1.0 + (0.002 if wg == 4 else 0.0) + (0.02 if lanes == 16 else 0.0)
         return tune.Trial(k, steps, steps / gain, steps * 1000, wg, lanes)
     choice, _ = tune.tune_schedule(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
-    assert choice == {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 16}
+    assert choice == {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 16, "groups": 2}
 
 
 def test_a_tie_goes_to_the_value_nearest_the_default():
@@ -166,7 +168,7 @@ def test_cheap_batches_search_every_combination():
         seen.append((k, wg, lanes))
         return tune.Trial(k, steps, steps * 1e-6 / rate(k, wg, lanes), steps, wg, lanes)
     choice, trials = tune.tune_schedule(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
-    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "apply_lanes": 16}
+    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "apply_lanes": 16, "groups": 2}
     assert len(trials) == 4 * 3 * 2 and len(seen) == 1 + 2 * 24
 
 
@@ -177,3 +179,34 @@ def test_rejects_bad_candidates():
         tune.tune_schedule(FakeCtx(), [FakeCase(1000, 100, 5)], wg_candidates=(4, -1))
     with pytest.raises(ValueError):
         tune.tune_schedule(FakeCtx(), [FakeCase(1000, 100, 5)], lane_candidates=(64, 8))
+
+
+def test_groups_are_tuned_last_for_a_batch_of_cases(tmp_path):
+    """Last stage, only for several cases: the lockstep groups at the chosen
+    schedule, in a mirrored order, capped at the case count; every earlier
+    trial runs with 2 groups; the choice is set and cached."""
+    calls = []
+
+    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+        g = ctx.options[edupic.OPT_GROUPS]
+        calls.append((k, wg, lanes, g))
+        cost = 22.0 + 70.0 / k + 0.03 * k + {2: 1.0, 3: 0.0, 4: 0.4}[g]
+        return tune.Trial(k, steps, steps * cost, steps * 1000, wg, lanes)
+    ctx = FakeCtx()
+    path = str(tmp_path / "g.json")
+    cases = [FakeCase(300_000, 1000, 20)] * 5
+    choice, trials = tune.tune_schedule(ctx, cases, wg_candidates=(), lane_candidates=(), cache_path=path,
+                                        measure_fn=run)
+    assert choice == {"sort_every": 50, "part_wg_per_cu": 0, "apply_lanes": 64, "groups": 3}
+    assert ctx.options[edupic.OPT_GROUPS] == 3
+    assert all(g == 2 for _, _, _, g in calls[:9])
+    assert [g for _, _, _, g in calls[9:]] == [2, 3, 4, 4, 3, 2]
+    assert all(k == 50 for k, _, _, _ in calls[9:])
+    assert [t.groups for t in trials] == [2] * 4 + [2, 3, 4]
+    assert json.load(open(path))[tune.batch_key(cases) + ":groups"]["groups"] == 3
+    # two cases: 3 and 4 groups are 2 groups, nothing to try
+    calls.clear()
+    choice, trials = tune.tune_schedule(FakeCtx(), cases[:2], wg_candidates=(), lane_candidates=(), measure_fn=run)
+    assert choice["groups"] == 2 and len(trials) == 4 and all(g == 2 for _, _, _, g in calls)
+    with pytest.raises(ValueError):
+        tune.tune_schedule(FakeCtx(), cases, group_candidates=(2, 5), measure_fn=run)
