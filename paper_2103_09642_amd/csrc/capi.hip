@@ -667,13 +667,15 @@ int run_batch(edp_ctx* ctx, const std::vector<Case*>& cases, const std::vector<i
     auto work = [&](size_t k) { return (double)(cases[k]->est[0] + cases[k]->est[1]) * (double)n[k]; };
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work(a) > work(b); });
     double load[kMaxGroups] = {};
+    int count[kMaxGroups] = {};
     std::vector<int> in(cases.size());
     for (size_t k : order) {
-      int g = 0;
+      int g = 0;  // least loaded; on a tie (empty cases) the one with fewest cases
       for (int h = 1; h < ng; ++h)
-        if (load[h] < load[g]) g = h;
+        if (load[h] < load[g] || (load[h] == load[g] && count[h] < count[g])) g = h;
       in[k] = g;
       load[g] += work(k);
+      ++count[g];
     }
     for (size_t k = 0; k < cases.size(); ++k) {
       gc[in[k]].push_back(cases[k]);
@@ -693,9 +695,12 @@ int run_batch(edp_ctx* ctx, const std::vector<Case*>& cases, const std::vector<i
   while (r == EDP_OK && !all_done())
     for (int g = 0; g < ng && r == EDP_OK; ++g)
       if (!done[g]) r = group_window(ctx, ctx->grp[g], gc[g], gl[g], done[g]);
+  // the joins also after a failed window: whatever the groups did enqueue
+  // stays ordered before later work on the caller's stream
   for (int g = 1; g < ng; ++g) {
-    HIPCHK(hipEventRecord(ctx->grp[g].join, ctx->grp[g].own));
-    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->grp[g].join, 0));
+    const hipError_t e = hipEventRecord(ctx->grp[g].join, ctx->grp[g].own);
+    const hipError_t w = e == hipSuccess ? hipStreamWaitEvent(ctx->stream, ctx->grp[g].join, 0) : e;
+    if (w != hipSuccess && r == EDP_OK) r = fail(EDP_EHIP, "joining group %d: %s", g, hipGetErrorString(w));
   }
   return r;
 }

@@ -117,6 +117,32 @@ def test_batch_matches_oracle(ctx, xs_default, orc):
         g.destroy()
 
 
+def test_groups_with_empty_cases(ctx):
+    """Four groups over a batch of empty cases (no expected work, so the
+    split goes by case count) and one populated case: every case reaches its
+    step, and the populated one equals itself advanced alone."""
+    say("test_groups_with_empty_cases")
+    from paper_2103_09642_amd import edupic
+    c, st = _mix()[1]
+    g = _make(ctx, c, st, 0)
+    g.advance_steps(60)
+    alone = _result(g)
+    g.destroy()
+    empty = {"x": np.zeros(0), "vx": np.zeros(0), "vy": np.zeros(0), "vz": np.zeros(0),
+             "uid": np.zeros(0, dtype=np.uint64)}
+    gs = [_make(ctx, c, {"e": empty, "i": empty}, 0) for _ in range(4)] + [_make(ctx, c, st, 0)]
+    ctx.set_option(edupic.OPT_GROUPS, 4)
+    try:
+        ctx.advance_steps(gs, [60] * len(gs))
+        assert all(x.counts()["step"] == 60 for x in gs)
+        assert all(x.counts()["n_e"] == 0 for x in gs[:4])
+        _same(alone, _result(gs[4]), "populated case")
+    finally:
+        ctx.set_option(edupic.OPT_GROUPS, 2)
+        for x in gs:
+            x.destroy()
+
+
 def test_batch_rejects_duplicates_and_skips_failed(ctx):
     say("test_batch_rejects_duplicates_and_skips_failed")
     from paper_2103_09642_amd import edupic
