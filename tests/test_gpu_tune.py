@@ -83,6 +83,35 @@ def test_tuning_with_restore_leaves_the_cases_unchanged(ctx):
         ctx.set_option(edupic.OPT_APPLY_LANES, 64)
 
 
+def test_group_stage_on_library_cases(ctx):
+    """The lockstep-groups stage on three library cases: 1, 2 and 3 groups
+    are tried in a mirrored order at the chosen schedule, the choice is set
+    on the context, and with restore_state the cases come back unchanged."""
+    say("test_group_stage_on_library_cases")
+    from paper_2103_09642_amd import edupic
+    mix = _mix()[:3]
+    ctx.set_option(edupic.OPT_MODE, 1)
+    try:
+        gs = [_make(ctx, c, st, 0) for c, st in mix]
+        before = [_result(g) for g in gs]
+        choice, trials = tune.tune_schedule(ctx, gs, candidates=(10,), wg_candidates=(), lane_candidates=(),
+                                            group_candidates=(1, 2, 3, 4), restore_state=True)
+        assert [t.groups for t in trials] == [2, 1, 2, 3] and all(t.rate > 0 for t in trials)
+        assert choice["groups"] in (1, 2, 3) and tune.last_schedule(ctx) == choice
+        say(f"chosen {choice}; rates {[round(t.rate / 1e9, 2) for t in trials]} G/s")
+        for g, b in zip(gs, before):
+            a = _result(g)
+            assert a[3]["step"] == b[3]["step"] == 0
+            for sp in (0, 1):
+                for k in ("uid", "x", "vx", "vy", "vz"):
+                    assert (a[sp][k] == b[sp][k]).all(), (sp, k)
+            g.destroy()
+    finally:
+        ctx.set_option(edupic.OPT_MODE, 0)
+        ctx.set_option(edupic.OPT_SORT_EVERY, 100)
+        ctx.set_option(edupic.OPT_GROUPS, 2)
+
+
 def test_workgroup_option_is_validated(ctx):
     from paper_2103_09642_amd import edupic
     say("test_workgroup_option_is_validated")
