@@ -222,7 +222,11 @@ typedef struct {
 } edp_counts;
 
 /* Create a context on `device` issuing work on `hip_stream` (a hipStream_t,
- * NULL = the legacy default stream).  *out receives the context. */
+ * NULL = the legacy default stream).  *out receives the context.  The
+ * context also creates and owns three non-blocking streams of default
+ * priority for lockstep groups 1-3 of a multi-case advance (EDP_OPT_GROUPS);
+ * every advance joins them back into `hip_stream`, and edp_destroy destroys
+ * them.  EDP_EHIP if they cannot be created. */
 int edp_create(edp_ctx **out, int device, void *hip_stream);
 /* Destroy a context; cases still alive are destroyed (arenas stay the
  * caller's). */
