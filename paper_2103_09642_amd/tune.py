@@ -79,7 +79,7 @@ class Trial:
     particle_steps: int
     wg_per_cu: int = 0   # the particle workgroups per CU of the trial
     lanes: int = 64      # the lanes per event list of the trial
-    groups: int = 2      # the lockstep groups of the trial (set by the tuner)
+    groups: int = 2      # the lockstep groups the trial ran as (set by the tuner)
 
     @property
     def rate(self) -> float:
@@ -292,7 +292,9 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
             lt = _mirrored(ls, lambda v: run(ctx, cases, best_k, steps, warm, best_w, v))
             best_l = _pick(lt, "lanes", DEFAULTS["apply_lanes"], _dist_lanes)
             trials += lt
-    trials = [replace(t, groups=DEFAULTS["groups"]) for t in trials]
+    # the groups these trials ran as (a batch smaller than the option runs
+    # as one group per case)
+    trials = [replace(t, groups=min(DEFAULTS["groups"], len(cases))) for t in trials]
     best_g = DEFAULTS["groups"]
     if gs:
         def group_trial(g):

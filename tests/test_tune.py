@@ -208,5 +208,8 @@ def test_groups_are_tuned_last_for_a_batch_of_cases(tmp_path):
     calls.clear()
     choice, trials = tune.tune_schedule(FakeCtx(), cases[:2], wg_candidates=(), lane_candidates=(), measure_fn=run)
     assert choice["groups"] == 2 and len(trials) == 4 and all(g == 2 for _, _, _, g in calls)
+    # one case runs alone whatever the option says
+    _, trials = tune.tune_schedule(FakeCtx(), cases[:1], wg_candidates=(), lane_candidates=(), measure_fn=run)
+    assert [t.groups for t in trials] == [1] * 4
     with pytest.raises(ValueError):
         tune.tune_schedule(FakeCtx(), cases, group_candidates=(2, 5), measure_fn=run)
