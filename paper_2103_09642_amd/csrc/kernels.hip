@@ -523,9 +523,16 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
   const double f2 = kArMass / (kEMass + kArMass);
   const double wx = f1 * vxn, wy = f1 * vy, wz = f1 * vz;
   const double eta = kTwoPi * r_eta;
-  double ox, oy, oz;
+  // the frame of g and the azimuth are the same for every process: computed
+  // once, outside the branch, so that a wave holding both an ionization and
+  // other events runs them once (the results are those of the same
+  // operations taken per process)
+  const Frame F = frame_of(vxn, vy, vz, v);
+  double cos_eta, sin_eta;
+  sincos(eta, &sin_eta, &cos_eta);
+  double gnew, cos_chi, sin_chi;
   if (proc < 2) {
-    double gnew = v;
+    gnew = v;
     if (proc == 1) {
       double ec = 0.5 * kMuEAr * v2 - C->thr_exc * kEvToJ;
       if (ec < 0.0) {
@@ -534,22 +541,19 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
       }
       gnew = sqrt(2.0 * ec / kMuEAr);
     }
-    const double cos_chi = 1.0 - 2.0 * r_chi;
-    const double sin_chi = sqrt(1.0 - cos_chi * cos_chi);
-    scatter(vxn, vy, vz, v, gnew, f2, cos_chi, sin_chi, eta, wx, wy, wz, ox, oy, oz);
+    cos_chi = 1.0 - 2.0 * r_chi;
+    sin_chi = sqrt(1.0 - cos_chi * cos_chi);
   } else {
     // Every draw of the ionization -- the energy share and the new ion's
-    // thermal velocity -- and the frame of g are taken before the dependent
-    // chains, and only the stores are conditional, so that the independent
-    // chains overlap (an ionization is the longest event of the queue).
+    // thermal velocity -- is taken before the dependent chains, and only the
+    // stores are conditional, so that the independent chains overlap (an
+    // ionization is the longest event of the queue).
     double r_share, r_unused;
     uniform2(seed, uid, st, tag(0, 0, 2), r_share, r_unused);
     const uint64_t cu = child_uid(uid, s, 2);
     double z0, z1, z2;
     normals3(seed, cu, st, 1u, 2u, 1u, z0, z1, z2);
-    const Frame F = frame_of(vxn, vy, vz, v);
-    double cos_eta, sin_eta, cos_eta2, sin_eta2;
-    sincos(eta, &sin_eta, &cos_eta);
+    double cos_eta2, sin_eta2;
     sincos(eta + kPi, &sin_eta2, &cos_eta2);
     double e_ev = 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion;
     if (e_ev < 0.0) {
@@ -573,8 +577,11 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
       sn_sc = sqrt(1.0 - cs_sc * cs_sc);
       sn_ej = sqrt(1.0 - cs_ej * cs_ej);
     }
-    rotate(F, g_sc, f2, cs_sc, sn_sc, cos_eta, sin_eta, wx, wy, wz, ox, oy, oz);
-    // the ejected electron, scattered about the same w
+    // the scattered electron is rotated below with the other processes; the
+    // ejected one, scattered about the same w, here
+    gnew = g_sc;
+    cos_chi = cs_sc;
+    sin_chi = sn_sc;
     double ex_, ey_, ez_;
     rotate(F, g_ej, f2, cs_ej, sn_ej, cos_eta2, sin_eta2, wx, wy, wz, ex_, ey_, ez_);
     if (be >= 0) {
@@ -593,6 +600,8 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
       P.iuid[bi] = cu;
     }
   }
+  double ox, oy, oz;
+  rotate(F, gnew, f2, cos_chi, sin_chi, cos_eta, sin_eta, wx, wy, wz, ox, oy, oz);
   P.evx[i] = ox;
   P.evy[i] = oy;
   P.evz[i] = oz;

@@ -65,7 +65,7 @@ DEFAULT_GROUP_CANDIDATES = (2, 3, 4)     # lockstep groups of a multi-case batch
 MAX_TRIAL_STEPS = 8000
 MAX_TRIAL_STRETCH = 8       # at most this many windows per trial
 MIN_TRIAL_SECONDS = 0.3     # calibration target per trial
-MARGIN = 0.005              # rates this close to the fastest count as a tie
+MARGIN = 0.002              # rates this close to the fastest count as a tie
 DEFAULTS = {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 64, "groups": 2}
 JOINT_BUDGET_SECONDS = 60.0  # all combinations tried together below this estimate
 _chosen: Dict[int, Dict[str, int]] = {}  # last choice the tuner set, per context object

@@ -136,7 +136,7 @@ def test_short_trials_are_stretched_by_whole_windows():
 def test_a_default_within_the_margin_is_kept():
     """Noise-level differences do not move a knob off the library default."""
     def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
-        gain = 1.0 + (0.002 if wg == 4 else 0.0) + (0.02 if lanes == 16 else 0.0)
+        gain = 1.0 + (0.001 if wg == 4 else 0.0) + (0.02 if lanes == 16 else 0.0)
         return tune.Trial(k, steps, steps / gain, steps * 1000, wg, lanes)
     choice, _ = tune.tune_schedule(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
     assert choice == {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 16, "groups": 2}
