@@ -384,7 +384,10 @@ static int electron_kinematics(const orc_sim *s, const double v[3], int proc, do
                                int *anomaly) {
   const double f1 = E_MASS / (E_MASS + AR_MASS);
   const double f2 = AR_MASS / (E_MASS + AR_MASS);
-  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  /* the electron's squared speed as vx^2 + (vy^2 + vz^2): the paper sums the
+   * three squares with no order, and this one lets a kernel keep the
+   * bracket per particle */
+  const double v2 = v[0] * v[0] + (v[1] * v[1] + v[2] * v[2]);
   const double g = sqrt(v2);
   const double w[3] = {f1 * v[0], f1 * v[1], f1 * v[2]};
   *anomaly = 0;
@@ -844,7 +847,7 @@ static void walls(orc_sim *s, parts *p, int is_ion) {
 static void electron_mcc(orc_sim *s, int64_t k) {
   parts *p = &s->e;
   const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
-  const double v2 = vx * vx + vy * vy + vz * vz;
+  const double v2 = vx * vx + (vy * vy + vz * vz); /* as in electron_kinematics */
   const double v = sqrt(v2);
   const double energy = 0.5 * E_MASS * v2 / EV_TO_J;
   const int idx = energy_bin(s, energy);
@@ -895,7 +898,7 @@ static void electron_mcc_null(orc_sim *s, int64_t k) {
   orc_uniform2(s->c.seed, uid, st, 0u, 0u, 0u, r0);
   if (!(r0[0] < s->p_null_e)) return;
   const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
-  const double v2 = vx * vx + vy * vy + vz * vz;
+  const double v2 = vx * vx + (vy * vy + vz * vz); /* as in electron_kinematics */
   const double v = sqrt(v2);
   const double energy = 0.5 * E_MASS * v2 / EV_TO_J;
   const int idx = energy_bin(s, energy);

@@ -165,7 +165,7 @@ struct edp_ctx {
 namespace {
 
 struct Layout {
-  size_t off_case, off_part[2][2][5], off_cq[2], off_qwg[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
+  size_t off_case, off_part[2][2][5], off_vp2[2], off_cq[2], off_qwg[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
       off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[7], off_eepf, off_xt, off_xtcnt, off_ifed, off_sort,
       total;
   int64_t cap[2];
@@ -228,6 +228,7 @@ Layout layout(const edp_case_desc* c, int nbins) {
   for (int sp = 0; sp < 2; ++sp)
     for (int set = 0; set < 2; ++set)
       for (int a = 0; a < 5; ++a) L.off_part[sp][set][a] = take((size_t)L.cap[sp] * 8);
+  for (int set = 0; set < 2; ++set) L.off_vp2[set] = take((size_t)L.cap[0] * 8);  // electrons only
   for (int sp = 0; sp < 2; ++sp) {
     const size_t chunks = (size_t)((L.cap[sp] + kChunk - 1) / kChunk);
     L.off_cq[sp] = take(chunks * kChunk * 8);  // events (per-workgroup lists over its chunk range)
@@ -941,6 +942,7 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
       h.sp[sp].vy[set] = (double*)(c->arena + L.off_part[sp][set][2]);
       h.sp[sp].vz[set] = (double*)(c->arena + L.off_part[sp][set][3]);
       h.sp[sp].uid[set] = (uint64_t*)(c->arena + L.off_part[sp][set][4]);
+      h.sp[sp].vp2[set] = sp == 0 ? (double*)(c->arena + L.off_vp2[set]) : nullptr;
     }
   }
   for (int sp = 0; sp < 2; ++sp) {
@@ -1529,6 +1531,12 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
     HIPCHK(hipMemcpy(S.vy[0], vy, n * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(S.vz[0], vz, n * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(S.uid[0], uid, n * 8, hipMemcpyHostToDevice));
+    if (species == 0) {
+      // the same products and sum as the kernels' (no contraction)
+      std::vector<double> p2((size_t)n);
+      for (int64_t i = 0; i < n; ++i) p2[i] = vy[i] * vy[i] + vz[i] * vz[i];
+      HIPCHK(hipMemcpy(S.vp2[0], p2.data(), n * 8, hipMemcpyHostToDevice));
+    }
   }
   t.step = step;
   t.cur[species] = 0;

@@ -481,7 +481,7 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
 
 // Arrays the collision workgroups touch, loaded once per workgroup.
 struct ScatterPtrs {
-  EDP_GLOBAL double *ex, *evx, *evy, *evz, *ix, *ivx, *ivy, *ivz;
+  EDP_GLOBAL double *ex, *evx, *evy, *evz, *evp2, *ix, *ivx, *ivy, *ivz;
   EDP_GLOBAL uint64_t *euid, *iuid;
   int64_t* anomaly;
 };
@@ -495,6 +495,7 @@ __device__ __forceinline__ ScatterPtrs scatter_ptrs(CaseDev* __restrict__ Cw) {
   P.evx = G(C->sp[0].vx[ce]);
   P.evy = G(C->sp[0].vy[ce]);
   P.evz = G(C->sp[0].vz[ce]);
+  P.evp2 = G(C->sp[0].vp2[ce]);
   P.euid = G(C->sp[0].uid[ce]);
   P.ix = G(C->sp[1].x[ci]);
   P.ivx = G(C->sp[1].vx[ci]);
@@ -515,7 +516,9 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
   const double x = proc == 2 ? P.ex[i] : 0.0;
   const uint64_t seed = C->seed;
   const uint32_t st = (uint32_t)s;
-  const double v2 = vxn * vxn + vy * vy + vz * vz;
+  // the push's association: vx^2 + (vy^2 + vz^2), the bracket being the
+  // slot's stored vy*vy + vz*vz
+  const double v2 = vxn * vxn + (vy * vy + vz * vz);
   const double v = sqrt(v2);
   double r_chi, r_eta;
   uniform2(seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
@@ -589,6 +592,7 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
       P.evx[be] = ex_;
       P.evy[be] = ey_;
       P.evz[be] = ez_;
+      P.evp2[be] = ey_ * ey_ + ez_ * ez_;
       P.euid[be] = child_uid(uid, s, 1);
     }
     if (bi >= 0) {  // the new ion: a thermal gas velocity
@@ -605,6 +609,7 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
   P.evx[i] = ox;
   P.evy[i] = oy;
   P.evz[i] = oz;
+  P.evp2[i] = oy * oy + oz * oz;
 }
 
 // Ar+ + Ar scattering of queued ion i (proc 0 isotropic, 1 backward) with the
@@ -659,8 +664,10 @@ __device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C
   P.evx[be] = side == 0 ? vn : -vn;
   double sn, cs;
   sincos(kTwoPi * b0, &sn, &cs);
-  P.evy[be] = vt * cs;
-  P.evz[be] = vt * sn;
+  const double vy = vt * cs, vz = vt * sn;
+  P.evy[be] = vy;
+  P.evz[be] = vz;
+  P.evp2[be] = vy * vy + vz * vz;
   P.euid[be] = child_uid(uid, s, 3);
 }
 
@@ -1019,6 +1026,9 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
   const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
   const EDP_GLOBAL uint64_t* __restrict__ UID = G(C->sp[SP].uid[cur]);
+  // electrons: vy*vy + vz*vz per slot, read in place of vy and vz (those
+  // only for the measurement sums)
+  const EDP_GLOBAL double* __restrict__ VP2 = G(C->sp[SP].vp2[cur]);
   // this workgroup's event list: its chunk range of the queue
   EDP_GLOBAL int64_t* __restrict__ ENT = G(C->cq_ent[SP]) + c_lo * kChunk;
   const int64_t base_slot = c_lo * kChunk;
@@ -1191,13 +1201,16 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   for (int64_t c = c_lo; c < c_hi; ++c) {
     const int slot = w * kWave + lane;  // slot in the chunk
     const int64_t i = c * kChunk + slot;
-    double x = __longlong_as_double(0x7FF8000000000000LL), vx = 0.0, vy = 0.0, vz = 0.0;
+    double x = __longlong_as_double(0x7FF8000000000000LL), vx = 0.0, vy = 0.0, vz = 0.0, vp2 = 0.0;
     uint64_t uid = 0;
     if (i < n) {
       x = X[i];
       vx = VX[i];
-      vy = VY[i];
-      vz = VZ[i];
+      if (SP == 1 || pdiag) {
+        vy = VY[i];
+        vz = VZ[i];
+      }
+      if (SP == 0) vp2 = VP2[i];
       uid = UID[i];
     }
     bool live = x == x;  // past the end, or absorbed earlier (tombstone)
@@ -1304,7 +1317,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         lds_add(&sH[q + 1], r);
         double r_coll, r_proc;
         uniform2(seed, uid, st, r_tag, r_coll, r_proc);
-        v2 = vxn * vxn + vy * vy + vz * vz;
+        v2 = SP == 0 ? vxn * vxn + vp2 : vxn * vxn + vy * vy + vz * vz;
         cand = r_coll < p_cand || (SP == 0 ? v2 : 2.0 * (v2 + a2_i)) > v2_cand;
       }
     }
@@ -1391,9 +1404,11 @@ __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma)
   uniform2(C->seed, (uint64_t)i, 0u, tag((uint32_t)sp, 1u, 0u), u0, u1);
   normals3(C->seed, (uint64_t)i, 0u, (uint32_t)sp, 1u, 1u, z0, z1, z2);
   G(C->sp[sp].x[cur])[i] = C->L * u0;
+  const double vy = sigma * z1, vz = sigma * z2;
   G(C->sp[sp].vx[cur])[i] = sigma * z0;
-  G(C->sp[sp].vy[cur])[i] = sigma * z1;
-  G(C->sp[sp].vz[cur])[i] = sigma * z2;
+  G(C->sp[sp].vy[cur])[i] = vy;
+  G(C->sp[sp].vz[cur])[i] = vz;
+  if (sp == 0) G(C->sp[0].vp2[cur])[i] = vy * vy + vz * vz;
   G(C->sp[sp].uid[cur])[i] = (uint64_t)i;
 }
 
@@ -1551,19 +1566,25 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
   EDP_GLOBAL double* __restrict__ VY2 = G(S.vy[nxt]);
   EDP_GLOBAL double* __restrict__ VZ2 = G(S.vz[nxt]);
   EDP_GLOBAL uint64_t* __restrict__ UID2 = G(S.uid[nxt]);
+  // electrons also carry vy*vy + vz*vz
+  const bool p2 = sp == 0;
+  const EDP_GLOBAL double* __restrict__ VP2 = G(S.vp2[cur]);
+  EDP_GLOBAL double* __restrict__ VP22 = G(S.vp2[nxt]);
   for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kSortUnroll * kBlock) {
-    double x[kSortUnroll], vx[kSortUnroll], vy[kSortUnroll], vz[kSortUnroll];
+    double x[kSortUnroll], vx[kSortUnroll], vy[kSortUnroll], vz[kSortUnroll], q2[kSortUnroll];
     uint64_t uid[kSortUnroll];
 #pragma unroll
     for (int u = 0; u < kSortUnroll; ++u) {
       const int64_t i = i0 + u * kBlock;
       x[u] = __longlong_as_double(0x7FF8000000000000LL);
+      q2[u] = 0.0;
       if (i < hi) {
         x[u] = X[i];
         vx[u] = VX[i];
         vy[u] = VY[i];
         vz[u] = VZ[i];
         uid[u] = UID[i];
+        if (p2) q2[u] = VP2[i];
       }
     }
 #pragma unroll
@@ -1576,6 +1597,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
       VY2[d] = vy[u];
       VZ2[d] = vz[u];
       UID2[d] = uid[u];
+      if (p2) VP22[d] = q2[u];
     }
   }
 }
