@@ -1566,25 +1566,23 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
   EDP_GLOBAL double* __restrict__ VY2 = G(S.vy[nxt]);
   EDP_GLOBAL double* __restrict__ VZ2 = G(S.vz[nxt]);
   EDP_GLOBAL uint64_t* __restrict__ UID2 = G(S.uid[nxt]);
-  // electrons also carry vy*vy + vz*vz
+  // electrons also carry vy*vy + vz*vz: formed again from the moved vy and
+  // vz, as every writer forms it, rather than read
   const bool p2 = sp == 0;
-  const EDP_GLOBAL double* __restrict__ VP2 = G(S.vp2[cur]);
   EDP_GLOBAL double* __restrict__ VP22 = G(S.vp2[nxt]);
   for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kSortUnroll * kBlock) {
-    double x[kSortUnroll], vx[kSortUnroll], vy[kSortUnroll], vz[kSortUnroll], q2[kSortUnroll];
+    double x[kSortUnroll], vx[kSortUnroll], vy[kSortUnroll], vz[kSortUnroll];
     uint64_t uid[kSortUnroll];
 #pragma unroll
     for (int u = 0; u < kSortUnroll; ++u) {
       const int64_t i = i0 + u * kBlock;
       x[u] = __longlong_as_double(0x7FF8000000000000LL);
-      q2[u] = 0.0;
       if (i < hi) {
         x[u] = X[i];
         vx[u] = VX[i];
         vy[u] = VY[i];
         vz[u] = VZ[i];
         uid[u] = UID[i];
-        if (p2) q2[u] = VP2[i];
       }
     }
 #pragma unroll
@@ -1597,7 +1595,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
       VY2[d] = vy[u];
       VZ2[d] = vz[u];
       UID2[d] = uid[u];
-      if (p2) VP22[d] = q2[u];
+      if (p2) VP22[d] = vy[u] * vy[u] + vz[u] * vz[u];
     }
   }
 }
