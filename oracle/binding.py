@@ -110,6 +110,8 @@ def lib():
         L.orc_child_uid.restype = C.c_uint64
         L.orc_child_uid.argtypes = [C.c_uint64, C.c_int64, C.c_uint64]
         L.orc_deposit.argtypes = [dp, C.c_int64, C.c_int32, C.c_double, ip]
+        L.orc_energy_bin.argtypes = [P, C.c_double]
+        L.orc_energy_bin.restype = C.c_int
         L.orc_poisson.argtypes = [C.c_int32, C.c_double, dp, C.c_double, dp]
         L.orc_efield.argtypes = [C.c_int32, C.c_double, dp, dp, dp]
         L.orc_scatter.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -309,6 +311,9 @@ class Oracle:
         out = np.zeros(4)
         lib().orc_null_params(self.h, dptr(out))
         return {"nu_star_e": out[0], "nu_star_i": out[1], "p_null_e": out[2], "p_null_i": out[3]}
+
+    def energy_bin(self, energy_ev: float) -> int:
+        return int(lib().orc_energy_bin(self.h, float(energy_ev)))
 
     def collide_electron(self, v, idx, r_proc, r_chi, r_eta, r_share):
         vin = np.ascontiguousarray(v, dtype=np.float64)

@@ -26,14 +26,14 @@
 
 /* Physical constants: CODATA 2018 (the paper does not list its values). */
 static const double E_CHARGE = 1.602176634e-19;   /* C    */
-static const double E_MASS = 9.1093837015e-31;    /* kg   */
+static const double M_ELECTRON = 9.1093837015e-31;    /* kg   */
 static const double K_BOLTZMANN = 1.380649e-23;  /* J/K  */
 static const double EPSILON0 = 8.8541878128e-12;  /* F/m  */
 static const double AMU = 1.66053906660e-27;      /* kg   */
-#define AR_MASS (39.948 * AMU)
-#define MU_ARAR (AR_MASS / 2.0)                  /* reduced mass Ar+ + Ar */
-#define MU_EAR (E_MASS * AR_MASS / (E_MASS + AR_MASS)) /* reduced mass e + Ar */
-#define EV_TO_J E_CHARGE
+#define M_ARGON (39.948 * AMU)
+#define MU_ION_ATOM (M_ARGON / 2.0)                  /* reduced mass Ar+ + Ar */
+#define MU_ELECTRON_ATOM (M_ELECTRON * M_ARGON / (M_ELECTRON + M_ARGON)) /* reduced mass e + Ar */
+#define J_PER_EV E_CHARGE
 static const double PI_D = 3.14159265358979323846;
 static const double TWO_PI_D = 6.28318530717958647692;
 static const double TWO32 = 4294967296.0; /* fixed-point unit of one particle */
@@ -227,15 +227,16 @@ static void parts_append(parts *p, double x, double vx, double vy, double vz, ui
  * (f >= 0) and is capped at 2^32.
  * ------------------------------------------------------------------------- */
 void orc_deposit(const double *x, int64_t n, int32_t ng, double inv_dx, int64_t *cnt) {
+  const int64_t unit = (int64_t)4294967296LL; /* one particle */
   for (int64_t k = 0; k < n; ++k) {
-    double c0 = x[k] * inv_dx;
-    int p = (int)c0;
-    if (p > ng - 2) p = ng - 2;
-    double f = c0 - (double)p;
-    int64_t r = (int64_t)(f * TWO32);
-    if (r > (int64_t)4294967296LL) r = (int64_t)4294967296LL;
-    cnt[p] += (int64_t)4294967296LL - r;
-    cnt[p + 1] += r;
+    const double xi = x[k] * inv_dx; /* position in cell units */
+    int cell = (int)xi;
+    if (cell > ng - 2) cell = ng - 2;
+    const double frac = xi - (double)cell; /* share of node cell + 1 */
+    int64_t upper = (int64_t)(frac * TWO32);
+    if (upper > unit) upper = unit;
+    cnt[cell] += unit - upper;
+    cnt[cell + 1] += upper;
   }
 }
 
@@ -308,12 +309,17 @@ int orc_set_voltage(orc_sim *s, const double *v_amp, int32_t n, double v_dc) {
  * Collisions (section 2.1.6).
  * ------------------------------------------------------------------------- */
 
-/* Energy bin: min(int(E/DE_CS + 0.5), CS_RANGES-1) (Algorithm 6). */
+/* Table row of a kinetic energy (section 3.2 tabulates the cross sections at
+ * the energies i * de, i = 0..nbins-1): the row whose tabulation energy is
+ * nearest, i.e. the integer part of energy/de + 1/2, with every energy past
+ * the table's end taken by its last row (Algorithm 6). */
 static int energy_bin(const orc_sim *s, double energy_ev) {
-  double t = energy_ev / s->de_cs + 0.5;
-  if (t >= (double)(s->nbins - 1)) return s->nbins - 1;
-  return (int)t;
+  const double rows = energy_ev / s->de_cs + 0.5;
+  const int last = s->nbins - 1;
+  return rows >= (double)last ? last : (int)rows;
 }
+
+int orc_energy_bin(const orc_sim *s, double energy_ev) { return energy_bin(s, energy_ev); }
 
 /* v1' = w + m2/(m1+m2) g' R(theta,phi) (cos chi, sin chi cos eta, sin chi sin eta),
  * with the Euler angles of g taken from its components: cos theta = g_x/g,
@@ -382,12 +388,10 @@ int orc_collide_electron(const orc_sim *s, const double v[3], int idx,
 static int electron_kinematics(const orc_sim *s, const double v[3], int proc, double r_chi,
                                double r_eta, double r_share, double vout[3], double vej[3],
                                int *anomaly) {
-  const double f1 = E_MASS / (E_MASS + AR_MASS);
-  const double f2 = AR_MASS / (E_MASS + AR_MASS);
-  /* the electron's squared speed as vx^2 + (vy^2 + vz^2): the paper sums the
-   * three squares with no order, and this one lets a kernel keep the
-   * bracket per particle */
-  const double v2 = v[0] * v[0] + (v[1] * v[1] + v[2] * v[2]);
+  const double f1 = M_ELECTRON / (M_ELECTRON + M_ARGON);
+  const double f2 = M_ARGON / (M_ELECTRON + M_ARGON);
+  /* squared speed, the three squares summed from x to z (Algorithm 6) */
+  const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
   const double g = sqrt(v2);
   const double w[3] = {f1 * v[0], f1 * v[1], f1 * v[2]};
   *anomaly = 0;
@@ -395,27 +399,27 @@ static int electron_kinematics(const orc_sim *s, const double v[3], int proc, do
   if (proc == 0 || proc == 1) {
     double gnew = g;
     if (proc == 1) {
-      double ec = 0.5 * MU_EAR * v2 - s->thr_exc * EV_TO_J;
+      double ec = 0.5 * MU_ELECTRON_ATOM * v2 - s->thr_exc * J_PER_EV;
       if (ec < 0.0) {
         ec = 0.0;
         *anomaly = 1;
       }
-      gnew = sqrt(2.0 * ec / MU_EAR);
+      gnew = sqrt(2.0 * ec / MU_ELECTRON_ATOM);
     }
     const double cos_chi = 1.0 - 2.0 * r_chi;
     const double sin_chi = sqrt(1.0 - cos_chi * cos_chi);
     orc_scatter(v, g, gnew, f2, cos_chi, sin_chi, eta, w, vout);
     return proc;
   }
-  double e_ev = 0.5 * MU_EAR * v2 / EV_TO_J - s->thr_ion;
+  double e_ev = 0.5 * MU_ELECTRON_ATOM * v2 / J_PER_EV - s->thr_ion;
   if (e_ev < 0.0) {
     e_ev = 0.0;
     *anomaly = 1;
   }
   const double e_ej = s->w_ion * tan(r_share * atan(e_ev / (2.0 * s->w_ion)));
   const double e_sc = e_ev - e_ej;
-  const double g_sc = sqrt(2.0 * e_sc * EV_TO_J / MU_EAR);
-  const double g_ej = sqrt(2.0 * e_ej * EV_TO_J / MU_EAR);
+  const double g_sc = sqrt(2.0 * e_sc * J_PER_EV / MU_ELECTRON_ATOM);
+  const double g_ej = sqrt(2.0 * e_ej * J_PER_EV / MU_ELECTRON_ATOM);
   double cs_sc, sn_sc, cs_ej, sn_ej;
   if (s->c.flags & ORC_IONIZ_ANGLE_LITERAL) {
     const double chi_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 0.0;
@@ -477,7 +481,7 @@ double orc_nu_star(const double *nsig, int32_t nb, double de_ev, double mass) {
   double m = 0.0;
   for (int32_t i = 0; i < nb; ++i) {
     const double e_hi = (i == nb - 1) ? 4.0 * (double)nb * de_ev : ((double)i + 0.5) * de_ev;
-    const double g = sqrt(2.0 * e_hi * EV_TO_J / mass);
+    const double g = sqrt(2.0 * e_hi * J_PER_EV / mass);
     const double nu = nsig[i] * g;
     if (nu > m) m = nu;
   }
@@ -525,10 +529,10 @@ orc_sim *orc_new(const orc_case *c, const orc_xsec *xs) {
   s->dt_i = (double)c->ion_subcycle * c->dt_e;
   s->dv = c->area_m2 * s->dx;
   s->factor_w = c->weight / s->dv;
-  s->factor_e = s->dt_e / E_MASS * E_CHARGE;
-  s->factor_i = s->dt_i / AR_MASS * E_CHARGE;
+  s->factor_e = s->dt_e / M_ELECTRON * E_CHARGE;
+  s->factor_i = s->dt_i / M_ARGON * E_CHARGE;
   s->gas_n = c->pressure_pa / (K_BOLTZMANN * c->gas_temp_k);
-  s->sigma_a = sqrt(K_BOLTZMANN * c->gas_temp_k / AR_MASS);
+  s->sigma_a = sqrt(K_BOLTZMANN * c->gas_temp_k / M_ARGON);
   s->de_cs = xs->de_ev;
   s->thr_exc = xs->e_exc_thr_ev;
   s->thr_ion = xs->e_ion_thr_ev;
@@ -546,8 +550,8 @@ orc_sim *orc_new(const orc_case *c, const orc_xsec *xs) {
     s->nsig_e[k] = s->gas_n * (s->sig_el[k] + s->sig_exc[k] + s->sig_ion[k]);
     s->nsig_i[k] = s->gas_n * (s->sig_iso[k] + s->sig_back[k]);
   }
-  s->nu_star_e = orc_nu_star(s->nsig_e, nb, s->de_cs, E_MASS);
-  s->nu_star_i = orc_nu_star(s->nsig_i, nb, s->de_cs, MU_ARAR);
+  s->nu_star_e = orc_nu_star(s->nsig_e, nb, s->de_cs, M_ELECTRON);
+  s->nu_star_i = orc_nu_star(s->nsig_i, nb, s->de_cs, MU_ION_ATOM);
   s->p_null_e = 1.0 - exp(-s->nu_star_e * s->dt_e);
   s->p_null_i = 1.0 - exp(-s->nu_star_i * s->dt_i);
   s->cnt_e = calloc((size_t)ng, sizeof(int64_t));
@@ -618,8 +622,8 @@ static void redeposit_ions(orc_sim *s) {
  * and, as the workloads ask, Maxwellian velocities (k T_e for electrons, the
  * ion temperature for Ar+), taken as the half-step velocities v(-dt/2). */
 int orc_seed(orc_sim *s) {
-  const double sig_e = sqrt(s->c.te_init_ev * EV_TO_J / E_MASS);
-  const double sig_i = sqrt(K_BOLTZMANN * s->c.ti_init_k / AR_MASS);
+  const double sig_e = sqrt(s->c.te_init_ev * J_PER_EV / M_ELECTRON);
+  const double sig_i = sqrt(K_BOLTZMANN * s->c.ti_init_k / M_ARGON);
   parts *sp[2] = {&s->e, &s->i};
   const int64_t nn[2] = {s->c.n_init_e, s->c.n_init_i};
   const double sg[2] = {sig_e, sig_i};
@@ -683,60 +687,76 @@ int64_t orc_get_state(const orc_sim *s, int species, double *x, double *vx, doub
  * n sigma_ion(eps) |v| of each electron at that velocity (reading: the paper
  * measures it where the particles move, with the time-centred velocities).
  * ------------------------------------------------------------------------- */
+/* Linear field interpolation of section 2.1.3: in cell units xi = x / dx
+ * (evaluated as x times the stored 1/dx), the particle lies between node
+ * `cell` = floor(xi) (at most N_g - 2, so x = L sits in the last cell) and the
+ * next one, whose weights are (cell + 1) - xi and xi - cell. */
+typedef struct {
+  int cell;
+  double w_lo, w_hi; /* weights of node `cell` and node `cell + 1` */
+} cic;
+
+static cic cic_weights(const orc_sim *s, double x) {
+  cic w;
+  const double xi = x * s->inv_dx;
+  w.cell = (int)xi;
+  if (w.cell > s->ng - 2) w.cell = s->ng - 2;
+  w.w_lo = (double)(w.cell + 1) - xi;
+  w.w_hi = xi - (double)w.cell;
+  return w;
+}
+
 static void push(orc_sim *s, parts *p, int is_ion) {
-  const int ng = s->ng;
-  const double inv_dx = s->inv_dx, *E = s->efield;
+  const double *E = s->efield;
   const double dt = is_ion ? s->dt_i : s->dt_e;
+  /* e dt / m per unit field: the velocity equation's kick is E_j times it,
+   * added for an ion and subtracted for an electron (charge -e) */
+  const double kick = is_ion ? s->factor_i : s->factor_e;
   const uint32_t fl = s->c.flags;
   const double x_lo = 0.45 * s->L, x_hi = 0.55 * s->L;
   for (int64_t k = 0; k < p->n; ++k) {
     const double x = p->x[k];
-    const double c0 = x * inv_dx;
-    int q = (int)c0;
-    if (q > ng - 2) q = ng - 2;
-    const double c1 = (double)(q + 1) - c0;
-    const double c2 = c0 - (double)q;
-    const double ex = c1 * E[q] + c2 * E[q + 1];
+    const cic w = cic_weights(s, x);
+    const int q = w.cell;
+    const double e_here = E[q] * w.w_lo + E[q + 1] * w.w_hi;
     const double vx_old = p->vx[k];
-    double vx_new;
-    if (is_ion)
-      vx_new = vx_old + ex * s->factor_i;
-    else
-      vx_new = vx_old - ex * s->factor_e;
+    /* v(t + dt/2) = v(t - dt/2) + (q/m) E dt */
+    const double vx_new = is_ion ? vx_old + e_here * kick : vx_old - e_here * kick;
     p->vx[k] = vx_new;
+    /* x(t + dt) = x(t) + v(t + dt/2) dt */
     p->x[k] = x + vx_new * dt;
     if (!(fl & (ORC_DIAG_CURRENT | ORC_DIAG_MEANE | ORC_DIAG_EEPF | ORC_DIAG_XT))) continue;
     const double vbar = 0.5 * (vx_old + vx_new);
     const int xt = (fl & ORC_DIAG_XT) != 0;
     if (fl & (ORC_DIAG_CURRENT | ORC_DIAG_XT)) {
       int64_t *acc = is_ion ? s->acc_ji : s->acc_je;
-      acc[q] += (int64_t)(c1 * vbar * DIAG_JS);
-      acc[q + 1] += (int64_t)(c2 * vbar * DIAG_JS);
+      acc[q] += (int64_t)(w.w_lo * vbar * DIAG_JS);
+      acc[q + 1] += (int64_t)(w.w_hi * vbar * DIAG_JS);
     }
     const double vy = p->vy[k], vz = p->vz[k];
     if (is_ion) {
       if (xt) {
-        const double en_i = 0.5 * AR_MASS * (vbar * vbar + vy * vy + vz * vz) / EV_TO_J;
-        s->acc_wi[q] += (int64_t)(c1 * DIAG_WS);
-        s->acc_wi[q + 1] += (int64_t)(c2 * DIAG_WS);
-        s->acc_ei[q] += (int64_t)(c1 * en_i * DIAG_ES);
-        s->acc_ei[q + 1] += (int64_t)(c2 * en_i * DIAG_ES);
+        const double en_i = 0.5 * M_ARGON * (vbar * vbar + vy * vy + vz * vz) / J_PER_EV;
+        s->acc_wi[q] += (int64_t)(w.w_lo * DIAG_WS);
+        s->acc_wi[q + 1] += (int64_t)(w.w_hi * DIAG_WS);
+        s->acc_ei[q] += (int64_t)(w.w_lo * en_i * DIAG_ES);
+        s->acc_ei[q + 1] += (int64_t)(w.w_hi * en_i * DIAG_ES);
       }
       continue;
     }
     if (!(fl & (ORC_DIAG_MEANE | ORC_DIAG_EEPF | ORC_DIAG_XT))) continue;
-    const double en = 0.5 * E_MASS * (vbar * vbar + vy * vy + vz * vz) / EV_TO_J;
+    const double en = 0.5 * M_ELECTRON * (vbar * vbar + vy * vy + vz * vz) / J_PER_EV;
     if (xt) {
       const double vmag = sqrt(vbar * vbar + vy * vy + vz * vz);
       const double pdt = (s->gas_n * s->sig_ion[energy_bin(s, en)]) * vmag * s->dt_e;
-      s->acc_iz[q] += (int64_t)(c1 * pdt * DIAG_IZS);
-      s->acc_iz[q + 1] += (int64_t)(c2 * pdt * DIAG_IZS);
+      s->acc_iz[q] += (int64_t)(w.w_lo * pdt * DIAG_IZS);
+      s->acc_iz[q + 1] += (int64_t)(w.w_hi * pdt * DIAG_IZS);
     }
     if (fl & (ORC_DIAG_MEANE | ORC_DIAG_XT)) {
-      s->acc_w[q] += (int64_t)(c1 * DIAG_WS);
-      s->acc_w[q + 1] += (int64_t)(c2 * DIAG_WS);
-      s->acc_e[q] += (int64_t)(c1 * en * DIAG_ES);
-      s->acc_e[q + 1] += (int64_t)(c2 * en * DIAG_ES);
+      s->acc_w[q] += (int64_t)(w.w_lo * DIAG_WS);
+      s->acc_w[q + 1] += (int64_t)(w.w_hi * DIAG_WS);
+      s->acc_e[q] += (int64_t)(w.w_lo * en * DIAG_ES);
+      s->acc_e[q + 1] += (int64_t)(w.w_hi * en * DIAG_ES);
     }
     if ((fl & ORC_DIAG_EEPF) && x >= x_lo && x <= x_hi) {
       const double t = en / s->c.de_eepf_ev;
@@ -784,7 +804,7 @@ static void emit_secondary(orc_sim *s, const parts *p, int64_t k, int side) {
   double a[2], b[2];
   orc_uniform2(s->c.seed, uid, st, 1u, 3u, 1u, a);
   orc_uniform2(s->c.seed, uid, st, 1u, 3u, 2u, b);
-  const double sig = sqrt(s->c.see_te_ev * EV_TO_J / E_MASS);
+  const double sig = sqrt(s->c.see_te_ev * J_PER_EV / M_ELECTRON);
   const double vn = sig * sqrt(-2.0 * log(1.0 - a[0]));
   const double vt = sig * sqrt(-2.0 * log(1.0 - a[1]));
   const double vy = vt * cos(TWO_PI_D * b[0]);
@@ -822,7 +842,7 @@ static void walls(orc_sim *s, parts *p, int is_ion) {
     if (out && is_ion) emit_secondary(s, p, k, out - 1);
     if (out && ifed) {
       const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
-      const double en = 0.5 * AR_MASS * (vx * vx + vy * vy + vz * vz) / EV_TO_J;
+      const double en = 0.5 * M_ARGON * (vx * vx + vy * vy + vz * vz) / J_PER_EV;
       const double t = en / s->c.de_ifed_ev;
       const int nb = s->c.n_ifed;
       const int b = t < (double)nb ? (int)t : nb;
@@ -842,17 +862,28 @@ static void walls(orc_sim *s, parts *p, int is_ion) {
   }
 }
 
-/* Step 6 for one electron (Algorithm 6): P = 1 - exp(-n sigma_tot(E) v dt),
- * collide iff R < P. */
+/* Kinetic energy [eV] of mass `mass` moving at squared speed g2: the LAB
+ * energy of an electron hitting a gas atom at rest, or with the reduced mass
+ * the COM energy of an ion-atom pair (section 2.1.6). */
+static double kinetic_ev(double mass, double g2) { return 0.5 * mass * g2 / J_PER_EV; }
+
+/* Probability of a collision within dt at relative speed g (the P_coll
+ * equation of section 2.1.6): 1 - exp(-nu dt) with the total collision
+ * frequency nu = n sigma_T(eps) g, n sigma_T being tabulated per table row. */
+static double collision_probability(const double *nsig_tot, int row, double g, double dt) {
+  const double nu = nsig_tot[row] * g;
+  return 1.0 - exp(-nu * dt);
+}
+
+/* Step 6 for one electron: the gas atom is at rest, so g = |v| and the
+ * energy is the LAB one; a collision happens iff R < P_coll (Algorithm 6). */
 static void electron_mcc(orc_sim *s, int64_t k) {
   parts *p = &s->e;
   const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
-  const double v2 = vx * vx + (vy * vy + vz * vz); /* as in electron_kinematics */
-  const double v = sqrt(v2);
-  const double energy = 0.5 * E_MASS * v2 / EV_TO_J;
-  const int idx = energy_bin(s, energy);
-  const double nu = s->nsig_e[idx] * v;
-  const double p_coll = 1.0 - exp(-nu * s->dt_e);
+  const double g2 = vx * vx + vy * vy + vz * vz;
+  const double g = sqrt(g2);
+  const int idx = energy_bin(s, kinetic_ev(M_ELECTRON, g2));
+  const double p_coll = collision_probability(s->nsig_e, idx, g, s->dt_e);
   const uint64_t uid = p->uid[k];
   const uint32_t st = (uint32_t)s->step;
   double r0[2];
@@ -898,10 +929,9 @@ static void electron_mcc_null(orc_sim *s, int64_t k) {
   orc_uniform2(s->c.seed, uid, st, 0u, 0u, 0u, r0);
   if (!(r0[0] < s->p_null_e)) return;
   const double vx = p->vx[k], vy = p->vy[k], vz = p->vz[k];
-  const double v2 = vx * vx + (vy * vy + vz * vz); /* as in electron_kinematics */
+  const double v2 = vx * vx + vy * vy + vz * vz;
   const double v = sqrt(v2);
-  const double energy = 0.5 * E_MASS * v2 / EV_TO_J;
-  const int idx = energy_bin(s, energy);
+  const int idx = energy_bin(s, kinetic_ev(M_ELECTRON, v2));
   const double nu_el = (s->gas_n * s->sig_el[idx]) * v;
   const double nu_exc = (s->gas_n * s->sig_exc[idx]) * v;
   const double nu_ion = (s->gas_n * s->sig_ion[idx]) * v;
@@ -953,8 +983,7 @@ static void ion_mcc_null(orc_sim *s, int64_t k) {
   const double gx = vx - va[0], gy = vy - va[1], gz = vz - va[2];
   const double g2 = gx * gx + gy * gy + gz * gz;
   const double g = sqrt(g2);
-  const double energy = 0.5 * MU_ARAR * g2 / EV_TO_J;
-  const int idx = energy_bin(s, energy);
+  const int idx = energy_bin(s, kinetic_ev(MU_ION_ATOM, g2));
   const double nu_iso = (s->gas_n * s->sig_iso[idx]) * g;
   const double nu_back = (s->gas_n * s->sig_back[idx]) * g;
   const double c1 = nu_iso, c2 = c1 + nu_back;
@@ -986,10 +1015,8 @@ static void ion_mcc(orc_sim *s, int64_t k) {
   const double gx = vx - va[0], gy = vy - va[1], gz = vz - va[2];
   const double g2 = gx * gx + gy * gy + gz * gz;
   const double g = sqrt(g2);
-  const double energy = 0.5 * MU_ARAR * g2 / EV_TO_J;
-  const int idx = energy_bin(s, energy);
-  const double nu = s->nsig_i[idx] * g;
-  const double p_coll = 1.0 - exp(-nu * s->dt_i);
+  const int idx = energy_bin(s, kinetic_ev(MU_ION_ATOM, g2));
+  const double p_coll = collision_probability(s->nsig_i, idx, g, s->dt_i);
   double r2[2];
   orc_uniform2(s->c.seed, uid, st, 1u, 0u, 2u, r2);
   if (!(r2[0] < p_coll)) return;
@@ -1269,8 +1296,8 @@ void orc_read_ifed(const orc_sim *s, double *f_pow, double *f_gnd, int64_t *coun
 }
 
 void orc_plasma_params(double n_e, double te_ev, double out[2]) {
-  out[0] = sqrt(EPSILON0 * te_ev * EV_TO_J / (n_e * E_CHARGE * E_CHARGE));
-  out[1] = sqrt(n_e * E_CHARGE * E_CHARGE / (EPSILON0 * E_MASS));
+  out[0] = sqrt(EPSILON0 * te_ev * J_PER_EV / (n_e * E_CHARGE * E_CHARGE));
+  out[1] = sqrt(n_e * E_CHARGE * E_CHARGE / (EPSILON0 * M_ELECTRON));
 }
 
 /* Run report (section 3.5): the accuracy and stability criteria 1-4 of
@@ -1311,7 +1338,7 @@ void orc_info(const orc_sim *s, double out[ORC_INFO_N]) {
   out[ORC_INFO_PMAX_I] = s->p_null_i;
   if (!(s->p_null_e < 0.05) || !(s->p_null_i < 0.05)) fail |= 4;
   const double vc = s->dx / s->dt_e;
-  out[ORC_INFO_CFL_EV] = 0.5 * E_MASS * vc * vc / EV_TO_J;
+  out[ORC_INFO_CFL_EV] = 0.5 * M_ELECTRON * vc * vc / J_PER_EV;
   if (s->c.flags & ORC_DIAG_XT) {
     /* trapezoid weight 1/2 at the edges cancels their doubling */
     double pe = 0.0, pi = 0.0, ns = 0.0, ni = 0.0;

@@ -179,6 +179,9 @@ void orc_uniform2(uint64_t seed, uint64_t uid, uint32_t step, uint32_t species,
 uint64_t orc_mix64(uint64_t z);
 uint64_t orc_child_uid(uint64_t parent, int64_t step, uint64_t kind);
 void orc_deposit(const double *x, int64_t n, int32_t ng, double inv_dx, int64_t *cnt);
+/* Cross-section table row of a kinetic energy [eV]: the nearest tabulated
+ * energy i * de, the last row for every energy beyond the table. */
+int orc_energy_bin(const orc_sim *s, double energy_ev);
 void orc_poisson(int32_t ng, double dx, const double *rho, double v_left, double *phi);
 void orc_efield(int32_t ng, double dx, const double *phi, const double *rho, double *efield);
 /* Scatter a projectile of relative velocity g about COM velocity w (eq. for v1'). */

@@ -241,3 +241,135 @@ def test_thermal_seed_moments(orc):
     assert ke == pytest.approx(1.5 * 1.380649e-23 * 350.0, rel=0.01)
     assert s["x"].min() >= 0 and s["x"].max() < c["gap_m"]
     assert stats.kstest(s["x"] / c["gap_m"], "uniform").pvalue > 1e-4
+
+
+def _ion_expectation_case(pressure_pa, temp_k):
+    """A field-free case (no weight, no voltage) for one ion step at step 0."""
+    return base_case(harmonics=[], weight=0.0, n_init_e=0, n_init_i=0, pressure_pa=pressure_pa,
+                     gas_temp_k=temp_k, ion_subcycle=20)
+
+
+def test_ion_direct_probability_cold_gas_is_binomial(orc):
+    """Ions of known speed |v| in a cold gas (T_g = 1e-4 K, the gas density
+    kept at that of 40 Pa and 350 K, so the target atom is at rest to
+    1e-4 of the ion speeds): the number colliding in one ion step is the sum
+    of independent Bernoulli(P_k) with P_k = 1 - exp(-n sigma_T(eps_k) g dt_i),
+    g = |v_k| and the COM energy eps_k = mu g^2 / 2 with mu = M/2 (the P_coll
+    equation of section 2.1.6).  The expectation is taken here from the
+    tables, the gas law and the definition; a wrong reduced mass, a dt_e in
+    place of dt_i or a dropped gas density each move the count by tens of
+    standard deviations."""
+    xs = synthetic_xsec(scale=20.0)
+    n_gas = 40.0 / (1.380649e-23 * 350.0)
+    t_gas = 1e-4
+    c = _ion_expectation_case(n_gas * 1.380649e-23 * t_gas, t_gas)
+    o = orc.Oracle(c, xs)
+    n = 200_000
+    rng = np.random.default_rng(31)
+    e_lab = rng.uniform(0.02, 60.0, n)
+    speed = np.sqrt(2 * e_lab * QE / MAR)
+    d = rng.normal(size=(3, n))
+    d /= np.linalg.norm(d, axis=0)
+    dt_i = c["dt_e"] * c["ion_subcycle"]
+    st = {"x": rng.uniform(0.4, 0.6, n) * c["gap_m"], "vx": speed * d[0], "vy": speed * d[1],
+          "vz": speed * d[2], "uid": np.arange(n, dtype=np.uint64)}
+    assert np.all(np.abs(st["vx"]) * dt_i < 0.1 * c["gap_m"])  # nobody reaches a wall
+    o.set_state(0, {k: np.zeros(0, dtype=st[k].dtype) for k in st}, 0)
+    o.set_state(1, st, 0)
+    o.step(1)
+    got = o.counts()["coll_i"]
+    mu = MAR / 2
+    eps = 0.5 * mu * speed ** 2 / QE
+    row = np.minimum(np.floor(eps / xs["de_ev"] + 0.5).astype(np.int64), xs["n_bins"] - 1)
+    sig_t = xs["i_iso"][row] + xs["i_back"][row]
+    p = 1 - np.exp(-n_gas * sig_t * speed * dt_i)
+    mean, sd = p.sum(), math.sqrt((p * (1 - p)).sum())
+    assert mean > 2000
+    assert abs(got - mean) < 5 * sd, (got, mean, sd)
+    # the same ions with the LAB energy in place of the COM one would give
+    wrong = (1 - np.exp(-n_gas * (xs["i_iso"] + xs["i_back"])[
+        np.minimum(np.floor(e_lab / xs["de_ev"] + 0.5).astype(np.int64), xs["n_bins"] - 1)] * speed * dt_i)).sum()
+    assert abs(wrong - mean) > 20 * sd
+
+
+def test_ion_direct_probability_uses_relative_speed(orc):
+    """Ions at rest in a warm gas (350 K): their only relative speed is the
+    target atom's, g = |v_a|, Maxwell distributed with scale
+    sigma_a = sqrt(k T_g / M).  The expected number of collisions is N times
+    the integral of P(g) = 1 - exp(-n sigma_T(mu g^2/2) g dt_i) over that
+    distribution (trapezoid quadrature here).  Using the ion's own speed
+    instead of g would give no collision at all."""
+    xs = synthetic_xsec(scale=10.0)
+    c = _ion_expectation_case(100.0, 350.0)
+    o = orc.Oracle(c, xs)
+    n = 200_000
+    rng = np.random.default_rng(32)
+    z = np.zeros(n)
+    st = {"x": rng.uniform(0.2, 0.8, n) * c["gap_m"], "vx": z, "vy": z.copy(), "vz": z.copy(),
+          "uid": rng.permutation(np.arange(1, n + 1)).astype(np.uint64)}
+    o.set_state(0, {k: np.zeros(0, dtype=st[k].dtype) for k in st}, 0)
+    o.set_state(1, st, 0)
+    o.step(1)
+    got = o.counts()["coll_i"]
+    kb, tg = 1.380649e-23, 350.0
+    n_gas = 100.0 / (kb * tg)
+    sa = math.sqrt(kb * tg / MAR)
+    g = np.linspace(0.0, 12 * sa, 400_001)
+    f = math.sqrt(2 / math.pi) * g ** 2 / sa ** 3 * np.exp(-g ** 2 / (2 * sa ** 2))
+    eps = 0.5 * (MAR / 2) * g ** 2 / QE
+    row = np.minimum(np.floor(eps / xs["de_ev"] + 0.5).astype(np.int64), xs["n_bins"] - 1)
+    p = 1 - np.exp(-n_gas * (xs["i_iso"] + xs["i_back"])[row] * g * c["dt_e"] * c["ion_subcycle"])
+    pbar = np.trapezoid(p * f, g)
+    mean, sd = n * pbar, math.sqrt(n * pbar * (1 - pbar))
+    assert mean > 2000
+    assert abs(got - mean) < 5 * sd, (got, mean, sd)
+
+
+def test_energy_bin_rounds_to_the_nearest_tabulated_energy(orc, sim):
+    """Row i holds the energies that round to i * de (bins centred on the
+    tabulation points of section 3.2): energies a hair below (i + 1/2) de
+    fall in row i, a hair above in row i + 1, and everything beyond the
+    table in its last row."""
+    de, nb = 1e-3, 100_000
+    assert sim.energy_bin(0.0) == 0
+    for i in (0, 1, 7, 11_499, 11_500, 15_800, 54_321, nb - 2):
+        edge = (i + 0.5) * de
+        assert sim.energy_bin(edge * (1 - 1e-12)) == i, i
+        assert sim.energy_bin(edge * (1 + 1e-12)) == i + 1, i
+        assert sim.energy_bin(i * de) == i
+    for e in ((nb - 1) * de, (nb - 0.5) * de * (1 + 1e-12), nb * de, 1e3, 1e9):
+        assert sim.energy_bin(e) == nb - 1, e
+
+
+def test_energy_bin_decides_collisions_at_a_bin_edge(orc):
+    """The row rounding inside the collision test itself: with a table that
+    is zero up to row i and very large from row i + 1 on, electrons whose
+    energy is a hair below (i + 1/2) de never collide and those a hair above
+    always do; so do electrons far beyond the table (its last row)."""
+    i = 20_000
+    xs = zero_xsec(n_bins=100_000)
+    el = np.zeros(100_000)
+    el[i + 1:] = 1e-14
+    xs["e_el"] = el
+    c = base_case(harmonics=[], weight=0.0, n_init_e=0, n_init_i=0)
+    n = 3000
+    edge = (i + 0.5) * 1e-3
+    energies = np.concatenate([np.full(n, edge * (1 - 1e-9)), np.full(n, edge * (1 + 1e-9)),
+                               np.full(n, 250.0)])
+    rng = np.random.default_rng(33)
+    d = rng.normal(size=(3, energies.size))
+    d /= np.linalg.norm(d, axis=0)
+    sp = np.sqrt(2 * energies * QE / ME)
+    st = {"x": np.full(energies.size, 0.5 * c["gap_m"]), "vx": sp * d[0],
+          "vy": sp * d[1], "vz": sp * d[2], "uid": np.arange(energies.size, dtype=np.uint64)}
+    o = orc.Oracle(c, xs)
+    o.set_state(0, st, 1)
+    o.set_state(1, {k: np.zeros(0, dtype=st[k].dtype) for k in st}, 1)
+    o.step(1)
+    after = o.get_state(0)
+    order = np.argsort(after["uid"])
+    moved = after["vy"][order] != st["vy"]
+    assert not moved[:n].any()
+    assert moved[n:2 * n].all()
+    assert moved[2 * n:].all()
+    assert o.counts()["coll_e"] == 2 * n

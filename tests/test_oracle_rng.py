@@ -53,15 +53,28 @@ def test_uniforms_are_uniform_and_53_bit(orc):
     assert not np.array_equal(a, orc.uniform2(2, 3, 5, 0, 0, 0))
 
 
-def test_uniform_word_layout(orc):
-    """u = ((w0<<32 | w1) >> 11) 2^-53 with counter (uid_lo, uid_hi, step,
-    species<<24|purpose<<8|call) and key (seed_lo, seed_hi)."""
-    seed, uid, step, sp, pu, call = 0x123456789ABCDEF0, 0xFEDCBA9876543210, 77, 1, 2, 3
-    w = orc.philox([uid & 0xFFFFFFFF, uid >> 32, step, (sp << 24) | (pu << 8) | call],
-                   [seed & 0xFFFFFFFF, seed >> 32])
-    exp0 = ((w[0] << 32 | w[1]) >> 11) * 2.0**-53
-    exp1 = ((w[2] << 32 | w[3]) >> 11) * 2.0**-53
-    assert list(orc.uniform2(seed, uid, step, sp, pu, call)) == [exp0, exp1]
+def test_uniform_counter_and_key_layout_through_rocrand(orc, rocrand_ref):
+    """The oracle's uniforms follow the specified layout -- counter (uid_lo,
+    uid_hi, step, species<<24 | purpose<<8 | call), key (seed_lo, seed_hi),
+    u = ((w0<<32 | w1) >> 11) 2^-53 -- checked with the words of rocRAND's
+    independent Philox block function, so a swapped counter word, key half
+    or output word in the oracle's packing fails here."""
+    rng = np.random.default_rng(8)
+    cases = [(0x123456789ABCDEF0, 0xFEDCBA9876543210, 77, 1, 2, 3), (0, 0, 0, 0, 0, 0),
+             (2**64 - 1, 2**64 - 1, 2**32 - 1, 1, 3, 3)]
+    for _ in range(300):
+        cases.append((int(rng.integers(0, 2**63)) * 2 + 1, int(rng.integers(0, 2**63)),
+                      int(rng.integers(0, 2**32)), int(rng.integers(0, 2)), int(rng.integers(0, 4)),
+                      int(rng.integers(0, 4))))
+    rows = [[uid & 0xFFFFFFFF, uid >> 32, step, (sp << 24) | (pu << 8) | call, seed & 0xFFFFFFFF, seed >> 32]
+            for seed, uid, step, sp, pu, call in cases]
+    inp = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_ref], input=inp, capture_output=True, text=True, check=True).stdout
+    words = [list(map(int, line.split())) for line in out.strip().splitlines()]
+    for (seed, uid, step, sp, pu, call), w in zip(cases, words):
+        exp0 = ((w[0] << 32 | w[1]) >> 11) * 2.0**-53
+        exp1 = ((w[2] << 32 | w[3]) >> 11) * 2.0**-53
+        assert list(orc.uniform2(seed, uid, step, sp, pu, call)) == [exp0, exp1]
 
 
 def test_child_uids_distinct(orc):
