@@ -155,7 +155,7 @@ typedef struct {
   double pressure_pa;      /* argon pressure [Pa]                               */
   double gas_temp_k;       /* gas temperature T_g [K]                           */
   double area_m2;          /* electrode area unit A [m^2] (1e-4 in the paper)   */
-  int32_t n_grid;          /* N_g, 2..4096                                      */
+  int32_t n_grid;          /* N_g, 2..2048 (2..1024 with measurement flags)     */
   int32_t steps_per_cycle; /* steps per RF cycle, the unit of edp_advance       */
   int32_t ion_subcycle;    /* N_SUB >= 1                                        */
   int32_t n_harm;          /* waveform harmonics used, 0..4                     */
@@ -247,27 +247,51 @@ int64_t edp_case_bytes(const edp_ctx *ctx, const edp_case_desc *desc);
 int edp_case_create(edp_ctx *ctx, const edp_case_desc *desc, void *dev_arena,
                     int64_t arena_bytes, edp_case *out);
 int edp_case_destroy(edp_ctx *ctx, edp_case c);
-/* Advance each listed case by n_cycles[k] RF cycles (steps_per_cycle steps
- * each).  Asynchronous.  The cases advance in lockstep: every kernel launch
- * serves all cases still running, and a case's results do not depend on the
- * others in the call. */
+/* The cycle loop of Algorithm 1 (a run given arg1 > 0 cycles, each cycle
+ * N_t repetitions of the six-step PIC/MCC cycle of section 2.1, ions every
+ * N_SUB-th step): advance each listed case by n_cycles[k] RF cycles of
+ * steps_per_cycle steps.  cases: host array of n_cases distinct handles of
+ * this context; n_cycles: host array of n_cases counts >= 0 (both read during
+ * the call only).  Asynchronous on the context's stream.  The cases advance
+ * in lockstep groups: every kernel launch serves all cases of a group still
+ * running, and a case's results do not depend on the others in the call.
+ * EDP_EINVAL for a null, unknown, repeated or failed case or a negative count
+ * (nothing is enqueued); EDP_EHIP if a launch fails.  A capacity overflow
+ * during the advance is reported by edp_sync and edp_read_counts. */
 int edp_advance(edp_ctx *ctx, const edp_case *cases, int32_t n_cases, const int32_t *n_cycles);
-/* Same with a step count per case. */
+/* Same as edp_advance with a step count per case (n_steps: host array of
+ * n_cases counts >= 0), for windows that are not whole RF cycles. */
 int edp_advance_steps(edp_ctx *ctx, const edp_case *cases, int32_t n_cases,
                       const int64_t *n_steps);
 /* Wait for the context's stream; returns EDP_ECAPACITY if any case overflowed. */
 int edp_sync(edp_ctx *ctx);
-/* Synchronous reads (they wait for the stream). */
+/* The conv.dat quantities of section 3.5 (superparticle numbers) plus the
+ * collision, absorption and birth counters of section 2.1's steps 5-6.
+ * Synchronous (waits for the stream); *out: caller-owned.  EDP_EINVAL for
+ * an unknown case; EDP_ECAPACITY (with *out still filled) if the case
+ * overflowed its capacity, so its state is no longer physical. */
 int edp_read_counts(edp_ctx *ctx, edp_case c, edp_counts *out);
-/* Time-averaged densities [m^-3] (EDP_DIAG_DENSITY); reset != 0 restarts
- * every diagnostic of the case after the read. */
+/* The measurement mode's time-averaged densities of section 3.5 (the
+ * density.dat file) [m^-3], needs EDP_DIAG_DENSITY.  ne, ni: caller-owned host
+ * arrays of n >= n_grid doubles, node p at x = p dx.  reset != 0 restarts
+ * every diagnostic of the case after the read.  Synchronous.  Without the
+ * flag the arrays read zero.  EDP_EINVAL for an unknown case or a short
+ * array; EDP_ECAPACITY if the case overflowed its capacity (the arrays are
+ * still written, but the state is no longer physical). */
 int edp_read_density(edp_ctx *ctx, edp_case c, double *ne, double *ni, int32_t n, int32_t reset);
-/* EEPF f(eps) [eV^-3/2] with sum f_i sqrt(eps_i) de = 1, eps_i = (i+1/2) de,
- * over electrons in [0.45 L, 0.55 L]; counts may be NULL. */
+/* The EEPF of section 3.5 (eepf.dat): f(eps) [eV^-3/2] with
+ * sum f_i sqrt(eps_i) de = 1, eps_i = (i+1/2) de, over the electrons in
+ * [0.45 L, 0.55 L] from their time-centred velocity (section 3.6); needs
+ * EDP_DIAG_EEPF.  f: host array of n >= n_eepf doubles; counts (may be
+ * NULL): the raw histogram.  Errors as edp_read_density. */
 int edp_read_eepf(edp_ctx *ctx, edp_case c, double *f, int64_t *counts, int32_t n, int32_t reset);
-/* Time-averaged current densities [A m^-2] from the time-centred velocity. */
+/* Time-averaged electron and ion current densities [A m^-2] per node from
+ * the time-centred velocity (sections 3.5-3.6); needs EDP_DIAG_CURRENT.
+ * je, ji: host arrays of n >= n_grid doubles.  Errors as edp_read_density. */
 int edp_read_currents(edp_ctx *ctx, edp_case c, double *je, double *ji, int32_t n, int32_t reset);
-/* Time-averaged mean electron energy [eV] per node. */
+/* Time-averaged mean electron energy [eV] per node (section 3.5), needs
+ * EDP_DIAG_MEANE.  mee_ev: host array of n >= n_grid doubles.  Errors as
+ * edp_read_density. */
 int edp_read_mean_energy(edp_ctx *ctx, edp_case c, double *mee_ev, int32_t n, int32_t reset);
 /* xt array `quantity` (EDP_XT_*) as out[t * n_grid + p] for time bin
  * t = (s mod steps_per_cycle) / n_xt_bin: the mean over the steps s of the
@@ -298,19 +322,33 @@ int edp_read_info(edp_ctx *ctx, edp_case c, double *out, int32_t n);
 int edp_set_voltage(edp_ctx *ctx, edp_case c, const double *v_amp, int32_t n_harm, double v_dc);
 /* Restart every diagnostic of the case (time sums, xt arrays, EEPF, IFEDF). */
 int edp_reset_diag(edp_ctx *ctx, edp_case c);
-/* Fixed-point densities (2^32 per superparticle) the next step will use:
- * electrons as they are now, ions as held since the last ion step. */
+/* The charge assignment of Algorithm 2 (equations for delta n_p and
+ * delta n_{p+1}) in fixed point: each superparticle adds 2^32 units split
+ * between the two enclosing nodes, so the density is cnt * W/(A dx) / 2^32
+ * (edge nodes doubled).  Returns the counts the next step will use:
+ * electrons as they are now, ions as held since the last ion step.  cnt_e,
+ * cnt_i: caller-owned host arrays of n >= n_grid int64.  Synchronous (applies
+ * pending collisions first).  EDP_EINVAL for an unknown case or short
+ * arrays.  Bit-exact: integer sums do not depend on particle order. */
 int edp_read_deposit(edp_ctx *ctx, edp_case c, int64_t *cnt_e, int64_t *cnt_i, int32_t n);
 /* rho [C m^-3], phi [V] and E [V m^-1] of the last completed step. */
 int edp_read_fields(edp_ctx *ctx, edp_case c, double *rho, double *phi, double *efield, int32_t n);
-/* Copy out the live particles of a species (any order) into host arrays of
- * capacity `cap`; *n_out gets the live count even if it exceeds cap. */
+/* The state save of Algorithm 1 (the particle coordinates written to
+ * picdata.bin at the end of a run): copy out the live particles of a species
+ * (EDP_ELECTRONS or EDP_IONS, any order) into caller-owned host arrays of
+ * capacity `cap` (x [m], v [m/s] at the half step t - dt/2, uid); any array
+ * may be NULL to skip it.  *n_out gets the live count even if it exceeds
+ * cap.  Synchronous (applies pending collisions first).  EDP_EINVAL for an
+ * unknown case or species. */
 int edp_get_state(edp_ctx *ctx, edp_case c, int32_t species, double *x, double *vx, double *vy,
                   double *vz, uint64_t *uid, int64_t cap, int64_t *n_out);
-/* Replace a species' particles from host arrays and set the step index;
- * velocities are the half-step ones v(t - dt/2).  The species is
- * redeposited; for ions the deposit also stands until the next ion step.
- * EDP_ESTATE if n exceeds the capacity. */
+/* The state load of Algorithm 1 (a run continuing from picdata.bin): replace
+ * a species' particles from n entries of caller-owned host arrays (copied)
+ * and set the step index; x must lie in [0, L], velocities are the
+ * half-step ones v(t - dt/2) and finite, uids distinct.  Counters and
+ * diagnostics restart; the species is redeposited, for ions the deposit also
+ * stands until the next ion step.  Synchronous.  EDP_ESTATE if n exceeds the
+ * capacity, EDP_EINVAL for a bad argument (nothing is changed then). */
 int edp_set_state(edp_ctx *ctx, edp_case c, int32_t species, const double *x, const double *vx,
                   const double *vy, const double *vz, const uint64_t *uid, int64_t n,
                   int64_t step);

@@ -228,7 +228,7 @@ Layout layout(const edp_case_desc* c, int nbins) {
   for (int sp = 0; sp < 2; ++sp)
     for (int set = 0; set < 2; ++set)
       for (int a = 0; a < 5; ++a) L.off_part[sp][set][a] = take((size_t)L.cap[sp] * 8);
-  for (int set = 0; set < 2; ++set) L.off_vp2[set] = take((size_t)L.cap[0] * 8);  // electrons only
+  for (int set = 0; set < 2; ++set) L.off_vp2[set] = take((size_t)L.cap[0] * 4);  // electrons only (float)
   for (int sp = 0; sp < 2; ++sp) {
     const size_t chunks = (size_t)((L.cap[sp] + kChunk - 1) / kChunk);
     L.off_cq[sp] = take(chunks * kChunk * 8);  // events (per-workgroup lists over its chunk range)
@@ -942,7 +942,7 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
       h.sp[sp].vy[set] = (double*)(c->arena + L.off_part[sp][set][2]);
       h.sp[sp].vz[set] = (double*)(c->arena + L.off_part[sp][set][3]);
       h.sp[sp].uid[set] = (uint64_t*)(c->arena + L.off_part[sp][set][4]);
-      h.sp[sp].vp2[set] = sp == 0 ? (double*)(c->arena + L.off_vp2[set]) : nullptr;
+      h.sp[sp].vp2[set] = sp == 0 ? (float*)(c->arena + L.off_vp2[set]) : nullptr;
     }
   }
   for (int sp = 0; sp < 2; ++sp) {
@@ -1135,7 +1135,31 @@ int edp_read_counts(edp_ctx* ctx, edp_case id, edp_counts* out) {
   out->see_pow = t.ctr[kSeePow];
   out->see_gnd = t.ctr[kSeeGnd];
   out->refl = t.ctr[kRefl];
+  if (t.error) {
+    c->failed = true;
+    return fail(EDP_ECAPACITY, "case %lld exceeded its particle capacity", (long long)c->id);
+  }
   return EDP_OK;
+}
+
+// EDP_ECAPACITY (and the case marked failed) if the case has overflowed its
+// particle capacity, so that results read from it are not mistaken for
+// physical ones; EDP_OK otherwise.  Waits for the stream.
+static int overflow_status(edp_ctx* ctx, Case* c) {
+  int32_t err = 0;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(&err, (char*)c->d + offsetof(CaseDev, error), 4, hipMemcpyDeviceToHost));
+  if (!err) return EDP_OK;
+  c->failed = true;
+  return fail(EDP_ECAPACITY, "case %lld exceeded its particle capacity", (long long)c->id);
+}
+
+// The status of a time-averaged read: the overflow status, with the
+// diagnostics restarted after the read when asked.
+static int after_read(edp_ctx* ctx, Case* c, int32_t reset) {
+  const int st = overflow_status(ctx, c);
+  const int r = reset ? reset_diag(ctx, c) : EDP_OK;
+  return st ? st : r;
 }
 
 static int read_grid(edp_ctx* ctx, Case* c, const void* dev, void* host, size_t bytes) {
@@ -1160,7 +1184,7 @@ int edp_read_density(edp_ctx* ctx, edp_case id, double* ne, double* ni, int32_t 
     ne[p] = a[p] / steps;
     ni[p] = b[p] / steps;
   }
-  return reset ? reset_diag(ctx, c) : EDP_OK;
+  return after_read(ctx, c, reset);
 }
 
 int edp_read_eepf(edp_ctx* ctx, edp_case id, double* f, int64_t* counts, int32_t n, int32_t reset) {
@@ -1178,7 +1202,7 @@ int edp_read_eepf(edp_ctx* ctx, edp_case id, double* f, int64_t* counts, int32_t
     if (counts) counts[k] = h[k];
     if (f) f[k] = tot > 0.0 ? (double)h[k] / (tot * de * std::sqrt(((double)k + 0.5) * de)) : 0.0;
   }
-  return reset ? reset_diag(ctx, c) : EDP_OK;
+  return after_read(ctx, c, reset);
 }
 
 int edp_read_currents(edp_ctx* ctx, edp_case id, double* je, double* ji, int32_t n, int32_t reset) {
@@ -1200,7 +1224,7 @@ int edp_read_currents(edp_ctx* ctx, edp_case id, double* je, double* ji, int32_t
     je[p] = edge * (-kECharge * c->h.factor_w) * (a[p] / kDiagJS) / ns;
     ji[p] = edge * (kECharge * c->h.factor_w) * (b[p] / kDiagJS) / ni;
   }
-  return reset ? reset_diag(ctx, c) : EDP_OK;
+  return after_read(ctx, c, reset);
 }
 
 int edp_read_mean_energy(edp_ctx* ctx, edp_case id, double* mee, int32_t n, int32_t reset) {
@@ -1214,7 +1238,7 @@ int edp_read_mean_energy(edp_ctx* ctx, edp_case id, double* mee, int32_t n, int3
   if ((r = read_grid(ctx, c, c->h.sum_w, w.data(), ng * 8)) || (r = read_grid(ctx, c, c->h.sum_e, e.data(), ng * 8)))
     return r;
   for (int p = 0; p < ng; ++p) mee[p] = w[p] > 0.0 ? (e[p] / kDiagES) / (w[p] / kDiagWS) : 0.0;
-  return reset ? reset_diag(ctx, c) : EDP_OK;
+  return after_read(ctx, c, reset);
 }
 
 int edp_read_xt_steps(edp_ctx* ctx, edp_case id, int64_t* steps, int64_t* ion_steps, int32_t n) {
@@ -1532,10 +1556,10 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
     HIPCHK(hipMemcpy(S.vz[0], vz, n * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(S.uid[0], uid, n * 8, hipMemcpyHostToDevice));
     if (species == 0) {
-      // the same products and sum as the kernels' (no contraction)
-      std::vector<double> p2((size_t)n);
-      for (int64_t i = 0; i < n; ++i) p2[i] = vy[i] * vy[i] + vz[i] * vz[i];
-      HIPCHK(hipMemcpy(S.vp2[0], p2.data(), n * 8, hipMemcpyHostToDevice));
+      // the float bound of vy*vy + vz*vz every kernel writer keeps
+      std::vector<float> p2((size_t)n);
+      for (int64_t i = 0; i < n; ++i) p2[i] = float_above(vy[i] * vy[i] + vz[i] * vz[i]);
+      HIPCHK(hipMemcpy(S.vp2[0], p2.data(), n * 4, hipMemcpyHostToDevice));
     }
   }
   t.step = step;

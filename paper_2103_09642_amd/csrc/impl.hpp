@@ -24,6 +24,14 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
 constexpr double kTwo32 = 4294967296.0;
 
+// The float nearest above a non-negative double: an upper bound that costs
+// half the bytes (+inf past the float range).
+__host__ __device__ inline float float_above(double d) {
+  const float f = (float)d;
+  // next float up when rounding went down (f is then finite and >= 0)
+  return (double)f < d ? __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) + 1u) : f;
+}
+
 // Fixed-point scales of the per-step diagnostic sums.
 constexpr double kDiagJS = 1024.0;     // c * vbar_x [m/s]
 constexpr double kDiagWS = 1048576.0;  // c
@@ -61,10 +69,11 @@ enum Ctr {
 struct SpeciesDev {
   double *x[2], *vx[2], *vy[2], *vz[2];  // two buffer sets: current and sort target
   uint64_t *uid[2];
-  // electrons: vy*vy + vz*vz of the same slot, kept with vy and vz by every
-  // writer, so that the push reads 8 bytes instead of 16 for the speed of
-  // its collision test (ions: null)
-  double* vp2[2];
+  // electrons: an upper bound of vy*vy + vz*vz of the same slot as a float
+  // (the double value rounded up), kept with vy and vz by every writer, so
+  // that the streaming pass reads 4 bytes instead of 16 to rule out the
+  // electrons too fast for its collision pre-test (ions: null)
+  float* vp2[2];
   int64_t cap;
 };
 

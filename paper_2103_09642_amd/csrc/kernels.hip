@@ -97,10 +97,11 @@ __device__ __forceinline__ uint64_t child_uid(uint64_t parent, int64_t step, uin
   return mix64(mix64(parent) ^ ((uint64_t)step * 0x9E3779B97F4A7C15ull) ^ kind);
 }
 
-// Energy bin min(int(E/DE_CS + 0.5), CS_RANGES-1) (Algorithm 6).
+// Cross-section table row of a kinetic energy: the nearest of the tabulated
+// energies i * de (section 3.2), every energy past the end in the last row.
 __device__ __forceinline__ int energy_bin(double e_ev, double de, int nbins) {
-  const double t = e_ev / de + 0.5;
-  return t >= (double)(nbins - 1) ? nbins - 1 : (int)t;
+  const double rows = e_ev / de + 0.5;
+  return rows >= (double)(nbins - 1) ? nbins - 1 : (int)rows;
 }
 
 // Post-collision velocity w + f2 g' R(theta,phi)(cos chi, sin chi cos eta,
@@ -481,7 +482,8 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
 
 // Arrays the collision workgroups touch, loaded once per workgroup.
 struct ScatterPtrs {
-  EDP_GLOBAL double *ex, *evx, *evy, *evz, *evp2, *ix, *ivx, *ivy, *ivz;
+  EDP_GLOBAL double *ex, *evx, *evy, *evz, *ix, *ivx, *ivy, *ivz;
+  EDP_GLOBAL float* evp2;
   EDP_GLOBAL uint64_t *euid, *iuid;
   int64_t* anomaly;
 };
@@ -516,9 +518,8 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
   const double x = proc == 2 ? P.ex[i] : 0.0;
   const uint64_t seed = C->seed;
   const uint32_t st = (uint32_t)s;
-  // the push's association: vx^2 + (vy^2 + vz^2), the bracket being the
-  // slot's stored vy*vy + vz*vz
-  const double v2 = vxn * vxn + (vy * vy + vz * vz);
+  // squared speed, the squares summed from x to z as the collision test does
+  const double v2 = vxn * vxn + vy * vy + vz * vz;
   const double v = sqrt(v2);
   double r_chi, r_eta;
   uniform2(seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
@@ -592,7 +593,7 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
       P.evx[be] = ex_;
       P.evy[be] = ey_;
       P.evz[be] = ez_;
-      P.evp2[be] = ey_ * ey_ + ez_ * ez_;
+      P.evp2[be] = float_above(ey_ * ey_ + ez_ * ez_);
       P.euid[be] = child_uid(uid, s, 1);
     }
     if (bi >= 0) {  // the new ion: a thermal gas velocity
@@ -609,7 +610,7 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
   P.evx[i] = ox;
   P.evy[i] = oy;
   P.evz[i] = oz;
-  P.evp2[i] = oy * oy + oz * oz;
+  P.evp2[i] = float_above(oy * oy + oz * oz);
 }
 
 // Ar+ + Ar scattering of queued ion i (proc 0 isotropic, 1 backward) with the
@@ -667,7 +668,7 @@ __device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C
   const double vy = vt * cs, vz = vt * sn;
   P.evy[be] = vy;
   P.evz[be] = vz;
-  P.evp2[be] = vy * vy + vz * vz;
+  P.evp2[be] = float_above(vy * vy + vz * vz);
   P.euid[be] = child_uid(uid, s, 3);
 }
 
@@ -949,7 +950,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   constexpr int kSeg = seg_len<SP>();
   constexpr int kPay = SP == 0 ? kBlock / kWave : 1;
   __shared__ int32_t sSeg[kBlock / kWave][kSeg];
-  __shared__ double sV2[kPay][SP == 0 ? kSeg : 1];
+  __shared__ double sVx[kPay][SP == 0 ? kSeg : 1];
   __shared__ uint64_t sUid[kPay][SP == 0 ? kSeg : 1];
   __shared__ int sNc[kBlock / kWave];
   __shared__ int sCnt[2];
@@ -1026,15 +1027,16 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
   const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
   const EDP_GLOBAL uint64_t* __restrict__ UID = G(C->sp[SP].uid[cur]);
-  // electrons: vy*vy + vz*vz per slot, read in place of vy and vz (those
-  // only for the measurement sums)
-  const EDP_GLOBAL double* __restrict__ VP2 = G(C->sp[SP].vp2[cur]);
+  // electrons: a float bound of vy*vy + vz*vz per slot, read in place of vy
+  // and vz for the pre-test (those only by the candidates' exact test and the
+  // measurement sums)
+  const EDP_GLOBAL float* __restrict__ VP2 = G(C->sp[SP].vp2[cur]);
   // this workgroup's event list: its chunk range of the queue
   EDP_GLOBAL int64_t* __restrict__ ENT = G(C->cq_ent[SP]) + c_lo * kChunk;
   const int64_t base_slot = c_lo * kChunk;
   const double inv_dx = C->inv_dx, L_gap = C->L;
   const double dt = SP == 0 ? C->dt_e : C->dt_i;
-  const double factor = SP == 0 ? C->factor_e : C->factor_i;
+  const double kick = SP == 0 ? C->factor_e : C->factor_i;
   const EDP_GLOBAL double* __restrict__ nsig = G(SP == 0 ? C->nsig_e : C->nsig_i);
   const EDP_GLOBAL double* __restrict__ sig0 = G(SP == 0 ? C->sig_el : C->sig_iso);
   const EDP_GLOBAL double* __restrict__ sig1 = G(SP == 0 ? C->sig_exc : C->sig_back);
@@ -1078,7 +1080,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       const int k = b0 + first;
       const bool act = k < count;
       int64_t i = 0;
-      double vxn = 0.0, vy = 0.0, vz = 0.0, v2e = 0.0;
+      double vxn = 0.0, vy = 0.0, vz = 0.0;
       uint64_t uid = 0;
       if (act) {
         int sg = w, kk = k;
@@ -1088,14 +1090,16 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         }
         i = base_slot + sSeg[sg][kk];
         if (SP == 0) {
-          v2e = sV2[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
+          // the pushed v_x and the uid from the segment, v_y and v_z (not
+          // changed by the push) from memory
+          vxn = sVx[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
           uid = sUid[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
         } else {
           vxn = VX[i];
-          vy = VY[i];
-          vz = VZ[i];
           uid = UID[i];
         }
+        vy = VY[i];
+        vz = VZ[i];
       }
       int proc = -1;
       if (act) {
@@ -1105,7 +1109,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
           double g, c1, c2, c3;
           int idx;
           if (SP == 0) {
-            const double v2 = v2e;
+            const double v2 = vxn * vxn + vy * vy + vz * vz;
             g = sqrt(v2);
             const double energy = 0.5 * kEMass * v2 / kEvToJ;
             idx = energy_bin(energy, de_cs, nbins);
@@ -1131,7 +1135,8 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
           double p_coll, s_a, s_b, s_c = 0.0;
           int idx;
           if (SP == 0) {
-            const double v2 = v2e;
+            // squared speed summed from x to z (Algorithm 6)
+            const double v2 = vxn * vxn + vy * vy + vz * vz;
             const double v = sqrt(v2);
             const double energy = 0.5 * kEMass * v2 / kEvToJ;
             idx = energy_bin(energy, de_cs, nbins);
@@ -1210,54 +1215,54 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         vy = VY[i];
         vz = VZ[i];
       }
-      if (SP == 0) vp2 = VP2[i];
+      if (SP == 0) vp2 = (double)VP2[i];
       uid = UID[i];
     }
     bool live = x == x;  // past the end, or absorbed earlier (tombstone)
     bool abs_pow = false, abs_gnd = false, surf = false, cand = false;
     double xn = 0.0, vxn = 0.0, v2 = 0.0;
     if (live) {
-      // Steps 3-4: field at the particle and leapfrog.
-      const double c0 = x * inv_dx;
-      int p = (int)c0;
-      p = p > ng - 2 ? ng - 2 : (p < 0 ? 0 : p);
-      const double c1 = (double)(p + 1) - c0;
-      const double c2 = c0 - (double)p;
-      const double ex = c1 * sE[p] + c2 * sE[p + 1];
-      if (SP == 0)
-        vxn = vx - ex * factor;
-      else
-        vxn = vx + ex * factor;
+      // Steps 3-4: linear interpolation of the nodal field (section 2.1.3)
+      // from cell coordinate xi = x/dx, then the leapfrog equations of
+      // section 2.1.4, the kick being e dt/m per unit field (subtracted for
+      // the electron's negative charge).
+      const double xi = x * inv_dx;
+      int cell = (int)xi;
+      cell = cell > ng - 2 ? ng - 2 : (cell < 0 ? 0 : cell);
+      const double w_lo = (double)(cell + 1) - xi;  // weight of node `cell`
+      const double w_hi = xi - (double)cell;        // weight of node `cell + 1`
+      const double e_here = sE[cell] * w_lo + sE[cell + 1] * w_hi;
+      vxn = SP == 0 ? vx - e_here * kick : vx + e_here * kick;
       xn = x + vxn * dt;
       if (pdiag) {
         // measurement at integer time: old position, mean of the half-step
         // velocities; the ionization rate as the expected n sigma_ion |v|
         const double vbar = 0.5 * (vx + vxn);
         if (fl & (kDiagCurrent | kDiagXT)) {
-          lds_add(&sJ[p], (long long)(c1 * vbar * kDiagJS));
-          lds_add(&sJ[p + 1], (long long)(c2 * vbar * kDiagJS));
+          lds_add(&sJ[cell], (long long)(w_lo * vbar * kDiagJS));
+          lds_add(&sJ[cell + 1], (long long)(w_hi * vbar * kDiagJS));
         }
         if (SP == 1) {
           if (xt) {
             const double en = 0.5 * kArMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
-            lds_add(&sW[p], (long long)(c1 * kDiagWS));
-            lds_add(&sW[p + 1], (long long)(c2 * kDiagWS));
-            lds_add(&sEn[p], (long long)(c1 * en * kDiagES));
-            lds_add(&sEn[p + 1], (long long)(c2 * en * kDiagES));
+            lds_add(&sW[cell], (long long)(w_lo * kDiagWS));
+            lds_add(&sW[cell + 1], (long long)(w_hi * kDiagWS));
+            lds_add(&sEn[cell], (long long)(w_lo * en * kDiagES));
+            lds_add(&sEn[cell + 1], (long long)(w_hi * en * kDiagES));
           }
         } else if (fl & (kDiagMeanE | kDiagEepf | kDiagXT)) {
           const double en = 0.5 * kEMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
           if (xt) {
             const double vmag = sqrt(vbar * vbar + vy * vy + vz * vz);
             const double pdt = (n_gas * sig2[energy_bin(en, de_cs, nbins)]) * vmag * dt;
-            lds_add(&sIz[p], (long long)(c1 * pdt * kDiagIZS));
-            lds_add(&sIz[p + 1], (long long)(c2 * pdt * kDiagIZS));
+            lds_add(&sIz[cell], (long long)(w_lo * pdt * kDiagIZS));
+            lds_add(&sIz[cell + 1], (long long)(w_hi * pdt * kDiagIZS));
           }
           if (fl & (kDiagMeanE | kDiagXT)) {
-            lds_add(&sW[p], (long long)(c1 * kDiagWS));
-            lds_add(&sW[p + 1], (long long)(c2 * kDiagWS));
-            lds_add(&sEn[p], (long long)(c1 * en * kDiagES));
-            lds_add(&sEn[p + 1], (long long)(c2 * en * kDiagES));
+            lds_add(&sW[cell], (long long)(w_lo * kDiagWS));
+            lds_add(&sW[cell + 1], (long long)(w_hi * kDiagWS));
+            lds_add(&sEn[cell], (long long)(w_lo * en * kDiagES));
+            lds_add(&sEn[cell + 1], (long long)(w_hi * en * kDiagES));
           }
           if ((fl & kDiagEepf) && x >= x_lo && x <= x_hi) {
             const double t = en / de_eepf;
@@ -1341,7 +1346,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         const int at = ncw + lane_rank(m_c);
         sSeg[w][at] = (int32_t)(i - base_slot);
         if (SP == 0) {
-          sV2[SP == 0 ? w : 0][SP == 0 ? at : 0] = v2;
+          sVx[SP == 0 ? w : 0][SP == 0 ? at : 0] = vxn;
           sUid[SP == 0 ? w : 0][SP == 0 ? at : 0] = uid;
         }
       }
@@ -1408,7 +1413,7 @@ __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma)
   G(C->sp[sp].vx[cur])[i] = sigma * z0;
   G(C->sp[sp].vy[cur])[i] = vy;
   G(C->sp[sp].vz[cur])[i] = vz;
-  if (sp == 0) G(C->sp[0].vp2[cur])[i] = vy * vy + vz * vz;
+  if (sp == 0) G(C->sp[0].vp2[cur])[i] = float_above(vy * vy + vz * vz);
   G(C->sp[sp].uid[cur])[i] = (uint64_t)i;
 }
 
@@ -1569,7 +1574,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
   // electrons also carry vy*vy + vz*vz: formed again from the moved vy and
   // vz, as every writer forms it, rather than read
   const bool p2 = sp == 0;
-  EDP_GLOBAL double* __restrict__ VP22 = G(S.vp2[nxt]);
+  EDP_GLOBAL float* __restrict__ VP22 = G(S.vp2[nxt]);
   for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kSortUnroll * kBlock) {
     double x[kSortUnroll], vx[kSortUnroll], vy[kSortUnroll], vz[kSortUnroll];
     uint64_t uid[kSortUnroll];
@@ -1595,7 +1600,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
       VY2[d] = vy[u];
       VZ2[d] = vz[u];
       UID2[d] = uid[u];
-      if (p2) VP22[d] = vy[u] * vy[u] + vz[u] * vz[u];
+      if (p2) VP22[d] = float_above(vy[u] * vy[u] + vz[u] * vz[u]);
     }
   }
 }

@@ -278,9 +278,15 @@ class Case:
         self.ctx.advance_steps([self], [steps])
 
     def counts(self) -> Dict[str, int]:
+        """Counters; "overflow" is 1 when the case has exceeded its capacity
+        (the library then reports EDP_ECAPACITY with the counters filled)."""
         c = Counts()
-        _chk(load().edp_read_counts(self.ctx.h, self.id, C.byref(c)))
-        return c.as_dict()
+        code = load().edp_read_counts(self.ctx.h, self.id, C.byref(c))
+        if code != EDP_ECAPACITY:
+            _chk(code)
+        d = c.as_dict()
+        d["overflow"] = int(code == EDP_ECAPACITY)
+        return d
 
     def density(self, reset: bool = False):
         ne, ni = np.zeros(self.ng), np.zeros(self.ng)
