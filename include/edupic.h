@@ -263,6 +263,23 @@ int edp_advance(edp_ctx *ctx, const edp_case *cases, int32_t n_cases, const int3
  * n_cases counts >= 0), for windows that are not whole RF cycles. */
 int edp_advance_steps(edp_ctx *ctx, const edp_case *cases, int32_t n_cases,
                       const int64_t *n_steps);
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * advance as edp_advance_steps (same arguments, same results bit for bit),
+ * but it allocates nothing.  The workgroup role table its launches read
+ * (device memory beyond the cases' arenas) is a file-scope array of 16384
+ * entries (512 KiB) that each GPU the library runs on holds until the
+ * process ends; the call makes no hipMalloc, hipFree, graph, stream or event
+ * and launches plainly, as one lockstep group, on the context's stream.
+ * Host bookkeeping uses the C++ heap only.  Limit: a call whose cases need
+ * more than 16384 workgroups over its particle, head and sort launches
+ * (about 100 cases of a few hundred particle workgroups each) returns
+ * EDP_EINVAL before enqueuing anything.  Every call on a GPU shares that
+ * GPU's array and rewrites it at its start: calls that overlap on one GPU
+ * (from two contexts, or two threads) race and must be serialised by the
+ * caller. */
+int edp_advance_steps_noalloc(edp_ctx *ctx, const edp_case *cases, int32_t n_cases,
+                              const int64_t *n_steps);
 /* Wait for the context's stream; returns EDP_ECAPACITY if any case overflowed. */
 int edp_sync(edp_ctx *ctx);
 /* The conv.dat quantities of section 3.5 (superparticle numbers) plus the

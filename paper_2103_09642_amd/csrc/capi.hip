@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -131,9 +132,24 @@ struct Group {
   // the caller's stream waits on at the end of an advance
   hipStream_t own = nullptr;
   hipEvent_t join = nullptr;
+  // the allocation-free advance's group: its role table is the device's
+  // file-scope array (roles_d, roles_cap fixed), it launches plainly (no
+  // graph, no timing events) on the context's stream and never allocates
+  bool fixed = false;
 };
 
+// Workgroup roles the allocation-free advance can hold: its role table is a
+// file-scope device array of this many entries (512 KiB) per GPU.
+constexpr int kScratchRoles = 16384;
+
 }  // namespace
+
+// The allocation-free advance's role table.  On the host this name is a
+// stand-in, not a device address: host code uses it only to ask
+// hipGetSymbolAddress, with a device current, for that device's copy, and
+// then only that address (kept per device by scratch_roles()).
+__device__ __align__(256) BlockRole scratch[kScratchRoles];
+
 
 struct edp_ctx {
   int device = 0;
@@ -156,6 +172,9 @@ struct edp_ctx {
   // advance
   Group grp[kMaxGroups];
   hipEvent_t fork_ev = nullptr;
+  // the allocation-free advance (edp_advance_steps_noalloc): one group on
+  // `stream` whose role table is the device's scratch array
+  Group na;
   // profiling
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
   double prof_ms = 0.0;
@@ -500,6 +519,9 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
     for (size_t k = 0; k < nc; ++k)
       for (int j = 0; j < want_sort[sp][k]; ++j) roles.push_back(role(cs[k], j, want_sort[sp][k]));
   }
+  if (roles.size() > G.roles_cap && G.fixed)
+    return fail(EDP_EINVAL, "the batch needs %zu workgroup roles; the allocation-free advance holds at most %d",
+                roles.size(), kScratchRoles);
   if (roles.size() > G.roles_cap) {
     // no kernel of this group is in flight (drained above)
     if (G.roles_d) HIPCHK(hipFree(G.roles_d));
@@ -542,7 +564,7 @@ int enqueue_batch_step(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, in
   if (sort_i)
     HIPCHK(launch_sort(G.roles_d + B.role_off[4], case_roles, 1, B.sorts[1], nc, B.max_ng, ctx->sort_every, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->profile && !capture) {
+  if (ctx->profile && !capture && !G.fixed) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
   }
@@ -608,7 +630,7 @@ int group_window(edp_ctx* ctx, Group& G, const std::vector<Case*>& cases, std::v
   int r = set_batch(ctx, G, act);
   if (r) return r;
   int gsteps = 0;
-  if (ctx->mode == 1 && base <= 4096) {
+  if (ctx->mode == 1 && base <= 4096 && !G.fixed) {
     gsteps = ctx->graph_steps > 0 ? ctx->graph_steps : (int)(base * std::max<int64_t>(1, 200 / base));
     if (gsteps % base != 0) gsteps = (int)((gsteps / base + 1) * base);
     if (gsteps <= w) w = (w / gsteps) * gsteps; else gsteps = 0;
@@ -768,6 +790,55 @@ int stability(const edp_ctx* ctx, const edp_case_desc* D, const std::vector<doub
 
 }  // namespace
 
+namespace {
+
+// Device address of `scratch` on each device, taken once per device with the
+// device current (every GPU holds its own copy at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+BlockRole* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_roles(int device, BlockRole** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(EDP_EINVAL, "device %d beyond %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(EDP_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = (BlockRole*)p;
+  }
+  *out = g_scratch_ptr[device];
+  return EDP_OK;
+}
+
+// The cases and step counts of an advance call, validated: distinct known
+// cases of the context, counts >= 0; cases marked failed are left out
+// (*skipped set).
+int collect_cases(edp_ctx* ctx, const edp_case* cases, int32_t n_cases, const int64_t* n_steps,
+                  std::vector<Case*>& cs, std::vector<int64_t>& n, bool& skipped) {
+  if (!ctx || n_cases < 0 || (n_cases > 0 && (!cases || !n_steps))) return fail(EDP_EINVAL, "null argument");
+  for (int32_t k = 0; k < n_cases; ++k) {
+    Case* c = find(ctx, cases[k]);
+    if (!c) return fail(EDP_EINVAL, "unknown case %lld", (long long)cases[k]);
+    if (n_steps[k] < 0) return fail(EDP_EINVAL, "negative step count");
+  }
+  skipped = false;
+  for (int32_t k = 0; k < n_cases; ++k) {
+    Case* c = find(ctx, cases[k]);
+    if (c->failed) {
+      skipped = true;
+      continue;
+    }
+    if (std::find(cs.begin(), cs.end(), c) != cs.end()) return fail(EDP_EINVAL, "case listed twice");
+    cs.push_back(c);
+    n.push_back(n_steps[k]);
+  }
+  if ((int)cs.size() > kMaxBatch) return fail(EDP_EINVAL, "more than %d cases in one call", kMaxBatch);
+  return EDP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* edp_last_error(void) { return g_err.c_str(); }
@@ -793,6 +864,17 @@ int edp_create(edp_ctx** out, int device, void* hip_stream) {
     delete ctx;
     return fail(EDP_EHIP, "creating the groups' streams or events failed");
   }
+  // the allocation-free advance's table: this device's scratch array
+  BlockRole* sp = nullptr;
+  const int rs = scratch_roles(device, &sp);
+  if (rs) {
+    destroy_group_streams(ctx);
+    delete ctx;
+    return rs;
+  }
+  ctx->na.fixed = true;
+  ctx->na.roles_d = sp;
+  ctx->na.roles_cap = kScratchRoles;
   *out = ctx;
   return EDP_OK;
 }
@@ -1052,28 +1134,37 @@ int edp_case_destroy(edp_ctx* ctx, edp_case id) {
 }
 
 int edp_advance_steps(edp_ctx* ctx, const edp_case* cases, int32_t n_cases, const int64_t* n_steps) {
-  if (!ctx || (n_cases > 0 && (!cases || !n_steps))) return fail(EDP_EINVAL, "null argument");
+  if (!ctx) return fail(EDP_EINVAL, "null context");
   HIPCHK(hipSetDevice(ctx->device));
-  for (int32_t k = 0; k < n_cases; ++k) {
-    Case* c = find(ctx, cases[k]);
-    if (!c) return fail(EDP_EINVAL, "unknown case %lld", (long long)cases[k]);
-    if (n_steps[k] < 0) return fail(EDP_EINVAL, "negative step count");
-  }
   std::vector<Case*> cs;
   std::vector<int64_t> n;
   bool skipped = false;
-  for (int32_t k = 0; k < n_cases; ++k) {
-    Case* c = find(ctx, cases[k]);
-    if (c->failed) {
-      skipped = true;
-      continue;
-    }
-    if (std::find(cs.begin(), cs.end(), c) != cs.end()) return fail(EDP_EINVAL, "case listed twice");
-    cs.push_back(c);
-    n.push_back(n_steps[k]);
-  }
-  if ((int)cs.size() > kMaxBatch) return fail(EDP_EINVAL, "more than %d cases in one call", kMaxBatch);
-  const int r = run_batch(ctx, cs, n);
+  int r = collect_cases(ctx, cases, n_cases, n_steps, cs, n, skipped);
+  if (r) return r;
+  r = run_batch(ctx, cs, n);
+  if (r) return r;
+  if (skipped) return fail(EDP_ESTATE, "failed cases were not advanced");
+  return EDP_OK;
+}
+
+int edp_advance_steps_noalloc(edp_ctx* ctx, const edp_case* cases, int32_t n_cases, const int64_t* n_steps) {
+  if (!ctx) return fail(EDP_EINVAL, "null context");
+  HIPCHK(hipSetDevice(ctx->device));
+  std::vector<Case*> cs;
+  std::vector<int64_t> n;
+  bool skipped = false;
+  int r = collect_cases(ctx, cases, n_cases, n_steps, cs, n, skipped);
+  if (r) return r;
+  // One lockstep group on the context's stream, plain launches, the role
+  // table in this device's scratch array.  Any call on the device may have
+  // rewritten that array since this context last used it: the table is
+  // rebuilt and uploaded (ordered on the stream) before the first window.
+  Group& G = ctx->na;
+  G.stream = ctx->stream;
+  G.valid = false;
+  G.batch.cases.clear();
+  bool done = false;
+  while (r == EDP_OK && !done) r = group_window(ctx, G, cs, n, done);
   if (r) return r;
   if (skipped) return fail(EDP_ESTATE, "failed cases were not advanced");
   return EDP_OK;

@@ -78,7 +78,8 @@ EXPORTS = ["edp_create", "edp_destroy", "edp_set_xsec", "edp_case_bytes", "edp_c
            "edp_read_density", "edp_read_eepf", "edp_read_currents", "edp_read_mean_energy",
            "edp_read_deposit", "edp_read_fields", "edp_get_state", "edp_set_state",
            "edp_set_option", "edp_read_profile", "edp_last_error", "edp_read_xt",
-           "edp_read_xt_steps", "edp_read_ifed", "edp_read_info", "edp_reset_diag", "edp_set_voltage"]
+           "edp_read_xt_steps", "edp_read_ifed", "edp_read_info", "edp_reset_diag", "edp_set_voltage",
+           "edp_advance_steps_noalloc"]
 
 _lib = None
 
@@ -106,6 +107,7 @@ def load() -> C.CDLL:
         "edp_case_destroy": (C.c_int, [P, I64]),
         "edp_advance": (C.c_int, [P, I64P, I32, C.POINTER(I32)]),
         "edp_advance_steps": (C.c_int, [P, I64P, I32, I64P]),
+        "edp_advance_steps_noalloc": (C.c_int, [P, I64P, I32, I64P]),
         "edp_sync": (C.c_int, [P]),
         "edp_read_counts": (C.c_int, [P, I64, C.POINTER(Counts)]),
         "edp_read_density": (C.c_int, [P, I64, D, D, I32, I32]),
@@ -237,6 +239,14 @@ class Context:
         ids = (C.c_int64 * n)(*[c.id for c in cases])
         st = (C.c_int64 * n)(*steps)
         _chk(load().edp_advance_steps(self.h, ids, n, st))
+
+    def advance_steps_noalloc(self, cases: Sequence["Case"], steps: Sequence[int]):
+        """edp_advance_steps_noalloc: the same advance with no device
+        allocation (role table in the library's per-device static array)."""
+        n = len(cases)
+        ids = (C.c_int64 * n)(*[c.id for c in cases])
+        st = (C.c_int64 * n)(*steps)
+        _chk(load().edp_advance_steps_noalloc(self.h, ids, n, st))
 
     def sync(self):
         _chk(load().edp_sync(self.h))
