@@ -141,6 +141,15 @@ extern "C" {
                                  stream is ordered after every group.
                                  Results do not depend on it, speed does: the
                                  autotuner (tune.py) picks it */
+#define EDP_OPT_SMALL_MAX 12   /* cases with at most this many particle slots
+                                 per species (the library's estimate) run in
+                                 the persistent small-case kernel: one
+                                 workgroup advances one case through a whole
+                                 window of steps in one launch, every case at
+                                 its own pace, on a stream of the context's
+                                 own forked from and joined back into its
+                                 stream; 0 (default) none.  Results do not
+                                 depend on it, speed does */
 #define EDP_OPT_PART_WG_PER_CU 9 /* resident particle workgroups per CU a batch
                                  uses: 0 (default) all that fit, k >= 1 at
                                  most k; results do not depend on it, speed

@@ -38,6 +38,9 @@ hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int 
 hipError_t launch_sort(const BlockRole* roles, const BlockRole* case_roles, int sp, int blocks, int ncase, int max_ng,
                        int every, hipStream_t st);
 hipError_t launch_fold(CaseDev* d, hipStream_t st);
+size_t small_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed);
+size_t small_static_lds();
+hipError_t launch_small(const BlockRole* roles, int ncase, size_t lds, int mode, int sort_every, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 }  // namespace edp
 
@@ -167,6 +170,15 @@ struct edp_ctx {
   int part_wg_per_cu = 0;  // 0: every resident slot
   int apply_lanes = 64;    // lanes per event list in the head's collision workgroups
   int groups = 2;  // lockstep groups of a multi-case advance (1..kMaxGroups)
+  // cases of at most this many slots per species (estimate) run in the
+  // persistent one-workgroup-per-case kernel (0: none)
+  int64_t small_max = 0;
+  // the persistent small cases' stream (default priority) and role table
+  hipStream_t small_stream = nullptr;
+  hipEvent_t small_join = nullptr;
+  BlockRole* small_roles = nullptr;
+  size_t small_cap = 0;
+  std::vector<BlockRole> small_h;
   // the groups' tables and run state; group 0 runs on `stream`, the others
   // on streams of their own, forked from and joined back into `stream` by an
   // advance
@@ -411,6 +423,10 @@ void drop_graph(Group& G) {
 void destroy_group_streams(edp_ctx* ctx) {
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   ctx->fork_ev = nullptr;
+  if (ctx->small_stream) (void)hipStreamDestroy(ctx->small_stream);
+  if (ctx->small_join) (void)hipEventDestroy(ctx->small_join);
+  ctx->small_stream = nullptr;
+  ctx->small_join = nullptr;
   for (Group& G : ctx->grp) {
     if (G.own) (void)hipStreamDestroy(G.own);
     if (G.join) (void)hipEventDestroy(G.join);
@@ -422,6 +438,7 @@ void destroy_group_streams(edp_ctx* ctx) {
 // Drain every group's stream and forget their graphs and tables.
 int reset_groups(edp_ctx* ctx) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->small_stream) HIPCHK(hipStreamSynchronize(ctx->small_stream));
   for (Group& G : ctx->grp)
     if (G.own) HIPCHK(hipStreamSynchronize(G.own));
   for (Group& G : ctx->grp) {
@@ -677,7 +694,100 @@ int group_window(edp_ctx* ctx, Group& G, const std::vector<Case*>& cases, std::v
 // enqueued on the caller's stream before they start, windows of the groups
 // are enqueued in turn, and the caller's stream waits for every group at
 // the end, so every later call on it is ordered after all of them.
-int run_batch(edp_ctx* ctx, const std::vector<Case*>& cases, const std::vector<int64_t>& n) {
+// Whether a case runs in the persistent one-workgroup-per-case kernel: few
+// enough slots (estimate) and its LDS within one workgroup's 64 KiB.
+bool small_case(const edp_ctx* ctx, const Case* c) {
+  if (ctx->small_max <= 0 || std::max(c->est[0], c->est[1]) > ctx->small_max) return false;
+  const edp_case_desc& D = c->desc;
+  return small_lds_bytes(D.n_grid, D.flags, D.n_eepf, D.n_ifed) + small_static_lds() <= 65536;
+}
+
+// The persistent small cases of an advance, on the context's small-case
+// stream (forked from and joined back into the caller's stream): windows of
+// up to 4096 steps, each one launch in which workgroup k runs case k by its
+// own window (the cases do not wait for each other).
+int run_small(edp_ctx* ctx, const std::vector<Case*>& cases, std::vector<int64_t> left) {
+  hipStream_t st = ctx->small_stream;
+  // the previous call's table may still be in flight from host memory
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipEventRecord(ctx->fork_ev, ctx->stream));
+  HIPCHK(hipStreamWaitEvent(st, ctx->fork_ev, 0));
+  size_t lds = 0;
+  for (const Case* c : cases)
+    lds = std::max(lds, small_lds_bytes(c->desc.n_grid, c->desc.flags, c->desc.n_eepf, c->desc.n_ifed));
+  // every window's roles, built up front and uploaded once: window w holds
+  // the cases with steps left, each with min(left, 4096) steps
+  constexpr int64_t kWin = 4096;
+  std::vector<BlockRole>& roles = ctx->small_h;
+  roles.clear();
+  std::vector<size_t> win_off{0};
+  std::vector<int64_t> rem(left);
+  for (;;) {
+    for (size_t k = 0; k < cases.size(); ++k)
+      if (rem[k] > 0) {
+        const int64_t w = std::min(rem[k], kWin);
+        roles.push_back(role(cases[k], (int)w, 1));
+        rem[k] -= w;
+      }
+    if (roles.size() == win_off.back()) break;
+    win_off.push_back(roles.size());
+  }
+  int r = EDP_OK;
+  if (!roles.empty()) {
+    if (roles.size() > ctx->small_cap) {
+      if (ctx->small_roles) HIPCHK(hipFree(ctx->small_roles));
+      ctx->small_roles = nullptr;
+      ctx->small_cap = 0;
+      HIPCHK(hipMalloc((void**)&ctx->small_roles, roles.size() * sizeof(BlockRole)));
+      ctx->small_cap = roles.size();
+    }
+    HIPCHK(hipMemcpyAsync(ctx->small_roles, roles.data(), roles.size() * sizeof(BlockRole), hipMemcpyHostToDevice, st));
+  }
+  for (size_t win = 0; win + 1 < win_off.size() && r == EDP_OK; ++win) {
+    const size_t lo = win_off[win], hi = win_off[win + 1];
+    for (size_t a = lo; a < hi && r == EDP_OK; ++a) {
+      Case* c = nullptr;
+      for (Case* q : cases)
+        if (q->d == roles[a].c) c = q;
+      r = upload_volt(c, c->step, c->step + roles[a].j, st);
+    }
+    if (r) break;
+    HIPCHK(launch_small(ctx->small_roles + lo, (int)(hi - lo), lds, ctx->poisson, ctx->sort_every, st));
+    for (size_t a = lo; a < hi && r == EDP_OK; ++a)
+      for (Case* q : cases)
+        if (q->d == roles[a].c) {
+          q->step += roles[a].j;
+          r = request_estimate(q, st);
+        }
+  }
+  const hipError_t e = hipEventRecord(ctx->small_join, st);
+  const hipError_t w = e == hipSuccess ? hipStreamWaitEvent(ctx->stream, ctx->small_join, 0) : e;
+  if (w != hipSuccess && r == EDP_OK) r = fail(EDP_EHIP, "joining the small cases: %s", hipGetErrorString(w));
+  return r;
+}
+
+int run_lockstep(edp_ctx* ctx, const std::vector<Case*>& cases, const std::vector<int64_t>& n);
+
+int run_batch(edp_ctx* ctx, const std::vector<Case*>& all, const std::vector<int64_t>& all_n) {
+  std::vector<Case*> small, cases;
+  std::vector<int64_t> small_n, n;
+  for (Case* c : all) poll_estimate(c);
+  for (size_t k = 0; k < all.size(); ++k) {
+    if (small_case(ctx, all[k])) {
+      small.push_back(all[k]);
+      small_n.push_back(all_n[k]);
+    } else {
+      cases.push_back(all[k]);
+      n.push_back(all_n[k]);
+    }
+  }
+  int r = EDP_OK;
+  if (!small.empty()) r = run_small(ctx, small, small_n);
+  if (r == EDP_OK && !cases.empty()) r = run_lockstep(ctx, cases, n);
+  return r;
+}
+
+int run_lockstep(edp_ctx* ctx, const std::vector<Case*>& cases, const std::vector<int64_t>& n) {
   const int ng = (int)std::min<size_t>((size_t)ctx->groups, std::max<size_t>(1, cases.size()));
   std::vector<Case*> gc[kMaxGroups];
   std::vector<int64_t> gl[kMaxGroups];
@@ -855,7 +965,9 @@ int edp_create(edp_ctx** out, int device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
   // the other groups' streams (default priority) and the fork/join events
-  bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess;
+  bool ok = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&ctx->small_stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&ctx->small_join, hipEventDisableTiming) == hipSuccess;
   for (int g = 1; g < kMaxGroups && ok; ++g)
     ok = hipStreamCreateWithFlags(&ctx->grp[g].own, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&ctx->grp[g].join, hipEventDisableTiming) == hipSuccess;
@@ -882,8 +994,10 @@ int edp_create(edp_ctx** out, int device, void* hip_stream) {
 int edp_destroy(edp_ctx* ctx) {
   if (!ctx) return EDP_OK;
   (void)reset_groups(ctx);
+  if (ctx->small_stream) (void)hipStreamSynchronize(ctx->small_stream);
   for (Group& G : ctx->grp)
     if (G.roles_d) (void)hipFree(G.roles_d);
+  if (ctx->small_roles) (void)hipFree(ctx->small_roles);
   destroy_group_streams(ctx);
   for (auto& kv : ctx->cases) {
     Case* c = kv.second;
@@ -1715,6 +1829,10 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
       static_assert(kMaxGroups == 4, "the message below names the limit");
       if (value < 1 || value > kMaxGroups) return fail(EDP_EINVAL, "groups must be 1..4");
       ctx->groups = (int)value;
+      break;
+    case EDP_OPT_SMALL_MAX:
+      if (value < 0) return fail(EDP_EINVAL, "small-case limit must be >= 0");
+      ctx->small_max = value;
       break;
     default:
       return fail(EDP_EINVAL, "unknown option %d", key);

@@ -468,6 +468,194 @@ __device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fs
   }
 }
 
+// The same solve for a workgroup that keeps E of step s in its own LDS (sE)
+// instead of handing it to other launches, with the step given: the
+// persistent small-case kernel below, where the step changes inside the
+// launch.  fsm: two padded rows of scratch.  The writer also stores rho, E
+// and the fluxes (or phi) for reads, clears the deposit rings the next steps
+// refill, folds the per-step diagnostics and counts the step.
+template <int MODE>
+__device__ __forceinline__ void field_to_lds(CaseDev* __restrict__ Cw, double* sE, double* fsm, const bool writer,
+                                             const int64_t s) {
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
+  const int ng = C->ng;
+  // LDS rows padded by one slot per 16 nodes (node p at lp(p)): the flux
+  // scan's lanes own 16-node blocks, which would otherwise fall on the same
+  // banks
+  const int np = ng + (ng >> 4) + 1;
+  auto lp = [](int p) { return p + (p >> 4); };
+  double* sRho = fsm;
+  double* sPhi = fsm + np;  // MODE 1: d then phi; MODE 0: S_p then fluxes F_q
+  const int nsub = C->nsub;
+  const int64_t k = s / nsub;
+  const bool ion_step = (s % nsub) == 0;
+  const uint32_t fl = C->flags;
+  const EDP_GLOBAL int64_t* cntE = G(C->cnt_e + (s % 3) * ng);
+  const EDP_GLOBAL int64_t* cntI = G(C->cnt_i + (k % 3) * ng);
+  EDP_GLOBAL int64_t* zeroE = G(C->cnt_e + ((s + 2) % 3) * ng);
+  EDP_GLOBAL int64_t* zeroI = G(C->cnt_i + ((k + 2) % 3) * ng);
+  const int64_t fold = ((s + 2) % 3) * ng;  // per-step sums of step s-1
+  const double scale = C->dens_scale;
+  const double V = G(C->volt)[s % kVoltChunk];
+  // xt rows: this step's grid values go to its time bin, the particle sums
+  // of step s-1 to the bin of s-1
+  const bool xt = writer && (fl & kDiagXT) != 0;
+  const int64_t nt = C->nt, nxb = C->n_xt_bin;
+  const size_t plane = (size_t)C->n_xt * (size_t)ng;
+  const size_t row = xt ? (size_t)((s % nt) / nxb) * (size_t)ng : 0;
+  const size_t row_prev = xt ? (size_t)(((s + nt - 1) % nt) / nxb) * (size_t)ng : 0;
+  EDP_GLOBAL double* __restrict__ X = G(C->xt);
+  // every load of the thread's nodes before any store (one memory round trip)
+  int64_t ce[kGridPerThread], ci[kGridPerThread];
+#pragma unroll
+  for (int j = 0; j < kGridPerThread; ++j) {
+    const int p = threadIdx.x + j * kBlock;
+    ce[j] = p < ng ? cntE[p] : 0;
+    ci[j] = p < ng ? cntI[p] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kGridPerThread; ++j) {
+    const int p = threadIdx.x + j * kBlock;
+    if (p >= ng) break;
+    double ne = (double)ce[j] * scale;
+    double ni = (double)ci[j] * scale;
+    if (p == 0 || p == ng - 1) {
+      ne *= 2.0;
+      ni *= 2.0;
+    }
+    const double rho = kECharge * (ni - ne);
+    sRho[lp(p)] = rho;
+    if (MODE == 1) sPhi[lp(p)] = rho * C->kpois;  // right-hand side d_p (boundary term below)
+    if (writer) {
+      if (fl & kDiagDensity) {
+        G(C->sum_ne)[p] += ne;
+        G(C->sum_ni)[p] += ni;
+      }
+      zeroE[p] = 0;
+      if (ion_step) zeroI[p] = 0;
+      if (fl & (kDiagCurrent | kDiagMeanE | kDiagXT)) fold_particle_sums(C, p, fold, row_prev, plane);
+      if (xt) {
+        X[kXtNe * plane + row + p] += ne;
+        X[kXtNi * plane + row + p] += ni;
+      }
+    }
+  }
+  __syncthreads();
+  const double dx = C->dx;
+  if (MODE == 1) {
+    if (threadIdx.x == 0) {
+      // Thomas algorithm: forward sweep y_p = (d_p + y_{p-1}) r_p, back
+      // substitution phi_p = y_p + r_p phi_{p+1}, with the reciprocals r_p
+      // precomputed on the host
+      const EDP_GLOBAL double* __restrict__ rd = G(C->rden);
+      const int m = ng - 2;
+      double prev = 0.0;
+      for (int p = 1; p <= m; ++p) {
+        double d = sPhi[lp(p)];
+        if (p == 1) d = d + V;
+        prev = (d + prev) * rd[p];
+        sPhi[lp(p)] = prev;
+      }
+      for (int p = m - 1; p >= 1; --p) sPhi[lp(p)] = sPhi[lp(p)] + rd[p] * sPhi[lp(p + 1)];
+      sPhi[lp(0)] = V;
+      sPhi[lp(ng - 1)] = 0.0;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
+      double e;
+      if (p == 0)
+        e = (sPhi[lp(0)] - sPhi[lp(1)]) / dx - sRho[lp(0)] * dx / (2.0 * kEps0);
+      else if (p == ng - 1)
+        e = (sPhi[lp(ng - 2)] - sPhi[lp(ng - 1)]) / dx + sRho[lp(ng - 1)] * dx / (2.0 * kEps0);
+      else
+        e = (sPhi[lp(p - 1)] - sPhi[lp(p + 1)]) / (2.0 * dx);
+      sE[p] = e;
+      if (writer) {
+        G(C->efield)[p] = e;
+        G(C->phi)[p] = sPhi[lp(p)];
+        G(C->rho)[p] = sRho[lp(p)];
+        if (xt) {
+          X[kXtEf * plane + row + p] += e;
+          X[kXtFlux * plane + row + p] += p < ng - 1 ? sPhi[lp(p)] - sPhi[lp(p + 1)] : V;
+        }
+      }
+    }
+  } else {
+    // One wave does the two scans (no workgroup barriers in between): lane l
+    // owns the contiguous rows q0 <= q < q1 of the m = N_g - 2 interior rows
+    // (row q is node q+1), and node q+1's slot becomes F_{q+1}.  A lane's
+    // rows stay in registers between one batch of LDS loads and one of
+    // stores.
+    if (threadIdx.x < kWave) {
+      const int lane = (int)threadIdx.x;
+      const int m = ng - 2;
+      const double kp = C->kpois;
+      const int R = (m + kWave - 1) / kWave;  // <= kScanRows
+      const int q0 = lane * R < m ? lane * R : m;
+      const int nq = (q0 + R < m ? q0 + R : m) - q0;
+      double v[kScanRows];
+#pragma unroll
+      for (int t = 0; t < kScanRows; ++t) v[t] = t < nq ? sRho[lp(q0 + t + 1)] : 0.0;
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < kScanRows; ++t) {
+        if (t < nq) acc += v[t] * kp;
+        v[t] = acc;  // prefix within the lane
+      }
+      double inc = acc;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const double y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+      }
+      const double before = inc - acc;
+      double mine = 0.0;
+#pragma unroll
+      for (int t = 0; t < kScanRows; ++t) {
+        v[t] = before + v[t];  // S_q
+        if (t < nq) mine += v[t];
+      }
+      for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
+      const double F0 = (V - mine) / (double)(ng - 1);
+#pragma unroll
+      for (int t = 0; t < kScanRows; ++t)
+        if (t < nq) sPhi[lp(q0 + t + 1)] = F0 + v[t];
+      if (lane == 0) sPhi[lp(0)] = F0;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
+      double e;
+      if (p == 0)
+        e = sPhi[lp(0)] / dx - sRho[lp(0)] * dx / (2.0 * kEps0);
+      else if (p == ng - 1)
+        e = sPhi[lp(ng - 2)] / dx + sRho[lp(ng - 1)] * dx / (2.0 * kEps0);
+      else
+        e = (sPhi[lp(p - 1)] + sPhi[lp(p)]) / (2.0 * dx);
+      sE[p] = e;
+      if (writer) {
+        G(C->efield)[p] = e;
+        const double f = p < ng - 1 ? sPhi[lp(p)] : V;  // last slot keeps V for phi on demand
+        G(C->flux)[p] = f;
+        G(C->rho)[p] = sRho[lp(p)];
+        if (xt) {
+          X[kXtEf * plane + row + p] += e;
+          X[kXtFlux * plane + row + p] += f;
+        }
+      }
+    }
+  }
+  if (writer && threadIdx.x == 0) {
+    if (xt) {
+      G(C->xt_cnt)[row / ng] += 1;
+      if (ion_step) G(C->xt_cnt)[C->n_xt + row / ng] += 1;
+    }
+    Cw->phi_valid = MODE == 1;
+    Cw->diag_steps += 1;
+    if (ion_step) Cw->diag_ion_steps += 1;
+  }
+  __syncthreads();  // sE complete; fsm free again
+}
+
 // ---------------------------------------------------------------------------
 // Collisions (step 6).  The particle kernel tests every particle, picks the
 // process of those that collide (partition of [0,1) into sigma_k/sigma_tot),
@@ -488,11 +676,11 @@ struct ScatterPtrs {
   int64_t* anomaly;
 };
 
-__device__ __forceinline__ ScatterPtrs scatter_ptrs(CaseDev* __restrict__ Cw) {
+// The arrays of buffer sets ce (electrons) and ci (ions).
+__device__ __forceinline__ ScatterPtrs scatter_ptrs_at(CaseDev* __restrict__ Cw, int ce, int ci) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   ScatterPtrs P;
   P.anomaly = &Cw->ctr[kAnomaly];
-  const int ce = C->cur[0], ci = C->cur[1];
   P.ex = G(C->sp[0].x[ce]);
   P.evx = G(C->sp[0].vx[ce]);
   P.evy = G(C->sp[0].vy[ce]);
@@ -506,16 +694,20 @@ __device__ __forceinline__ ScatterPtrs scatter_ptrs(CaseDev* __restrict__ Cw) {
   P.iuid = G(C->sp[1].uid[ci]);
   return P;
 }
+__device__ __forceinline__ ScatterPtrs scatter_ptrs(CaseDev* __restrict__ Cw) {
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
+  return scatter_ptrs_at(Cw, C->cur[0], C->cur[1]);
+}
 
 // Electron-Ar scattering of queued particle i (state after the push) by
 // process proc (0 elastic, 1 excitation, 2 ionization).  An ionization also
 // writes its newborns: the ejected electron at slot be and the ion at slot
 // bi (-1: dropped at capacity), both at the parent's position.
-__device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
-                                                 int proc, int64_t be, int64_t bi, int64_t s) {
-  const double vxn = P.evx[i], vy = P.evy[i], vz = P.evz[i];
-  const uint64_t uid = P.euid[i];
-  const double x = proc == 2 ? P.ex[i] : 0.0;
+// electron_scatter_at takes the particle's state (velocity after the push,
+// identity, position) from the caller; electron_scatter loads it.
+__device__ __forceinline__ void electron_scatter_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
+                                                    int64_t i, int proc, int64_t be, int64_t bi, int64_t s,
+                                                    double vxn, double vy, double vz, uint64_t uid, double x) {
   const uint64_t seed = C->seed;
   const uint32_t st = (uint32_t)s;
   // squared speed, the squares summed from x to z as the collision test does
@@ -612,13 +804,15 @@ __device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __rest
   P.evz[i] = oz;
   P.evp2[i] = float_above(oy * oy + oz * oz);
 }
+__device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
+                                                 int proc, int64_t be, int64_t bi, int64_t s) {
+  electron_scatter_at(C, P, i, proc, be, bi, s, P.evx[i], P.evy[i], P.evz[i], P.euid[i], proc == 2 ? P.ex[i] : 0.0);
+}
 
 // Ar+ + Ar scattering of queued ion i (proc 0 isotropic, 1 backward) with the
 // thermal target of its test (redrawn from the same counter: the same atom).
-__device__ __forceinline__ void ion_scatter(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i, int proc,
-                                            int64_t s) {
-  const double vxn = P.ivx[i], vy = P.ivy[i], vz = P.ivz[i];
-  const uint64_t uid = P.iuid[i];
+__device__ __forceinline__ void ion_scatter_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
+                                               int proc, int64_t s, double vxn, double vy, double vz, uint64_t uid) {
   const uint64_t seed = C->seed;
   const uint32_t st = (uint32_t)s;
   double z0, z1, z2;
@@ -644,16 +838,19 @@ __device__ __forceinline__ void ion_scatter(const EDP_CONST CaseDev* __restrict_
   P.ivy[i] = oy;
   P.ivz[i] = oz;
 }
+__device__ __forceinline__ void ion_scatter(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i, int proc,
+                                            int64_t s) {
+  ion_scatter_at(C, P, i, proc, s, P.ivx[i], P.ivy[i], P.ivz[i], P.iuid[i]);
+}
 
 // Secondary electron of queued ion i, absorbed at electrode `side` (0 at
 // x = 0, 1 at x = L): it starts on the surface with the velocity of a thermal
 // flux at T_see -- a Rayleigh normal component into the gap and two normal
 // tangential ones (Box-Muller) -- from purpose 3 of the ion's counter; its
 // identity is the ion's child of kind 3.  be < 0: dropped at capacity.
-__device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
-                                         int side, int64_t be, int64_t s) {
+__device__ __forceinline__ void see_emit_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
+                                            uint64_t uid, int side, int64_t be, int64_t s) {
   if (be < 0) return;
-  const uint64_t uid = P.iuid[i];
   const uint32_t st = (uint32_t)s;
   double a0, a1, b0, b1;
   uniform2(C->seed, uid, st, tag(1, 3, 1), a0, a1);
@@ -670,6 +867,11 @@ __device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C
   P.evz[be] = vz;
   P.evp2[be] = float_above(vy * vy + vz * vz);
   P.euid[be] = child_uid(uid, s, 3);
+}
+__device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
+                                         int side, int64_t be, int64_t s) {
+  if (be < 0) return;
+  see_emit_at(C, P, P.iuid[i], side, be, s);
 }
 
 typedef int rec4 __attribute__((ext_vector_type(4)));  // per-workgroup queue record
@@ -1401,6 +1603,593 @@ __global__ void __launch_bounds__(kBlock) k_particles(const BlockRole* __restric
   particles_block<SP>(r->c, r->efield, r->ng, r->j, r->n);
 }
 
+// Cell of a position (the deposit's node p, clamped to N_g - 2).
+__device__ __forceinline__ int cell_of(double x, double inv_dx, int ng) {
+  int p = (int)(x * inv_dx);
+  return p > ng - 2 ? ng - 2 : (p < 0 ? 0 : p);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent small cases: one workgroup advances one case through a whole
+// window of steps inside one launch, and every case of the launch runs at its
+// own pace -- no lockstep with the other cases, no launch between two steps,
+// no wait between workgroups.  Each step is the same method as the lockstep
+// path's and gives the same results bit for bit: the field solve into LDS
+// (steps 1-2), then per species the push, walls, collision test, the
+// colliders' scattering and the newborns (steps 3-6) and the deposit for the
+// next step, then the step's bookkeeping; compaction and cell sort every
+// `sort_every` steps as in the lockstep path.  Meant for cases of a few
+// thousand particles, whose steps are latency-bound: one workgroup per case
+// keeps the chip's other CUs for the other cases.
+//
+// The workgroup owns the case for the launch: the step, the slot counts and
+// the buffer sets live in LDS and are written back at the end (with a
+// pending collision queue of the lockstep path applied first).
+// ---------------------------------------------------------------------------
+
+// Slots for the newborns of a wave from an LDS counter: lanes with `mine`
+// take consecutive slots after base0 (the slot count at the step's start)
+// and the step's births so far; -1 past the capacity.
+__device__ __forceinline__ int64_t take_slot_lds(bool mine, int* births, int64_t base0, int64_t cap, int lane) {
+  const uint64_t m = __ballot(mine);
+  if (m == 0) return -1;
+  int b = 0;
+  if (lane == 0) b = atomicAdd(births, (int)__popcll(m));
+  b = __shfl(b, 0);
+  const int64_t slot = base0 + (int64_t)b + lane_rank(m);
+  return mine && slot < cap ? slot : -1;
+}
+
+// Totals of one species' step in a small case (summed over the waves).
+struct SmallTot {
+  int coll, ioniz, pow, gnd, live;
+};
+
+// Steps 3-6 of species SP for the case of this workgroup at step s: slots
+// [0, n) of buffer set `cur` (the other species' current set `cur_o`), E in
+// sE, `reg` the LDS region for the deposit histogram (and the particle
+// diagnostics), sBirth the step's birth counters (electron slots, ion slots)
+// after the slot counts n_e0, n_i0 at the step's start.
+template <int SP>
+__device__ __forceinline__ SmallTot small_species(CaseDev* __restrict__ Cw, const double* sE, double* reg, int64_t s,
+                                                  int64_t n, int cur, int cur_o, int64_t n_e0, int64_t n_i0,
+                                                  int* sBirth) {
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
+  constexpr int kSeg = seg_len<SP>();
+  constexpr int kPay = SP == 0 ? kBlock / kWave : 1;
+  __shared__ int32_t sSeg[kBlock / kWave][kSeg];
+  __shared__ double sVx[kPay][SP == 0 ? kSeg : 1];
+  __shared__ uint64_t sUid[kPay][SP == 0 ? kSeg : 1];
+  __shared__ int sNc[kBlock / kWave];
+  __shared__ int sTot[kBlock / kWave][5];
+  const int ng = C->ng;
+  const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
+  const int64_t nch = (n + kChunk - 1) / kChunk;
+  const int nsub = C->nsub;
+  const int64_t kion = s / nsub;
+  const uint32_t fl = C->flags;
+  const bool pdiag = (fl & kDiagParticle) != 0;
+  const bool xt = (fl & kDiagXT) != 0;
+  const int n_eepf = C->n_eepf;
+  const int n_ifed = C->n_ifed;
+  const int n_hist = SP == 0 ? ((fl & kDiagEepf) ? n_eepf : 0) : ((fl & kDiagIfed) ? 2 * (n_ifed + 1) : 0);
+  unsigned long long* sH = (unsigned long long*)reg;
+  unsigned long long* sJ = sH + ng;
+  unsigned long long* sW = sJ + ng;
+  unsigned long long* sEn = sW + ng;
+  unsigned long long* sIz = sEn + ng;
+  unsigned int* sF = (unsigned int*)(sIz + (SP == 0 && xt ? ng : 0));
+  for (int p = threadIdx.x; p < ng; p += blockDim.x) {
+    sH[p] = 0;
+    if (pdiag) {
+      sJ[p] = 0;
+      sW[p] = 0;
+      sEn[p] = 0;
+      if (SP == 0 && xt) sIz[p] = 0;
+    }
+  }
+  for (int b = threadIdx.x; b < n_hist; b += blockDim.x) sF[b] = 0;
+  __syncthreads();
+  EDP_GLOBAL double* __restrict__ X = G(C->sp[SP].x[cur]);
+  EDP_GLOBAL double* __restrict__ VX = G(C->sp[SP].vx[cur]);
+  const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
+  const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
+  const EDP_GLOBAL uint64_t* __restrict__ UID = G(C->sp[SP].uid[cur]);
+  const EDP_GLOBAL float* __restrict__ VP2 = G(C->sp[SP].vp2[cur]);
+  const ScatterPtrs P = SP == 0 ? scatter_ptrs_at(Cw, cur, cur_o) : scatter_ptrs_at(Cw, cur_o, cur);
+  const double inv_dx = C->inv_dx, L_gap = C->L;
+  const double dt = SP == 0 ? C->dt_e : C->dt_i;
+  const double kick = SP == 0 ? C->factor_e : C->factor_i;
+  const EDP_GLOBAL double* __restrict__ nsig = G(SP == 0 ? C->nsig_e : C->nsig_i);
+  const EDP_GLOBAL double* __restrict__ sig0 = G(SP == 0 ? C->sig_el : C->sig_iso);
+  const EDP_GLOBAL double* __restrict__ sig1 = G(SP == 0 ? C->sig_exc : C->sig_back);
+  const EDP_GLOBAL double* __restrict__ sig2 = G(C->sig_ion);
+  int64_t* const cnt_i_next = C->cnt_i + ((kion + 1) % 3) * ng;
+  int64_t* const dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
+  int64_t* const cnt_e_next = C->cnt_e + ((s + 1) % 3) * ng;
+  const double de_cs = C->de_cs;
+  const int nbins = C->nbins;
+  const uint64_t seed = C->seed;
+  const uint32_t st = (uint32_t)s;
+  const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf, de_ifed = C->de_ifed;
+  const double sa = C->sigma_a;
+  const bool null_coll = (fl & kNullCollision) != 0;
+  const bool surf_on = SP == 0 ? C->refl_on != 0 : C->see_on != 0;
+  const double p_surf0 = SP == 0 ? C->eta_refl[0] : C->gamma_see[0];
+  const double p_surf1 = SP == 0 ? C->eta_refl[1] : C->gamma_see[1];
+  const double n_gas = C->n_gas;
+  const double nu_star = SP == 0 ? C->nu_star_e : C->nu_star_i;
+  const double p_null = SP == 0 ? C->p_null_e : C->p_null_i;
+  const double p_cand = null_coll ? p_null : (SP == 0 ? C->p_bound_e : C->p_bound_i);
+  const double v2_cand = null_coll ? __builtin_huge_val() : (SP == 0 ? C->v2_lim_e : C->g2_lim_i);
+  const double a2_i = C->a2_i;
+  const uint32_t r_tag = SP == 0 ? tag(0, 0, 0) : tag(1, 0, 2);
+  const int w = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
+  int t_coll = 0, t_ioniz = 0, t_pow = 0, t_gnd = 0, t_live = 0;
+  int ncw = 0;
+
+  // The exact test of the candidates (as in the lockstep path), then at once
+  // the colliders' scattering and an ionization's newborns and their charge.
+  auto process = [&](const bool wg_list, const int count, const int first, const int stride) {
+    for (int b0 = 0; b0 < count; b0 += stride) {
+      const int k = b0 + first;
+      const bool act = k < count;
+      int64_t i = 0;
+      double vxn = 0.0, vy = 0.0, vz = 0.0;
+      uint64_t uid = 0;
+      if (act) {
+        int sg = w, kk = k;
+        if (wg_list) {
+          sg = 0;
+          while (kk >= sNc[sg]) kk -= sNc[sg++];
+        }
+        i = sSeg[sg][kk];
+        if (SP == 0) {
+          vxn = sVx[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
+          uid = sUid[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
+        } else {
+          vxn = VX[i];
+          uid = UID[i];
+        }
+        vy = VY[i];
+        vz = VZ[i];
+      }
+      int proc = -1;
+      if (act) {
+        double r_coll, r_proc;
+        uniform2(seed, uid, st, r_tag, r_coll, r_proc);
+        if (null_coll) {
+          double g, c1, c2, c3;
+          int idx;
+          if (SP == 0) {
+            const double v2 = vxn * vxn + vy * vy + vz * vz;
+            g = sqrt(v2);
+            const double energy = 0.5 * kEMass * v2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            c1 = (n_gas * sig0[idx]) * g;
+            c2 = c1 + (n_gas * sig1[idx]) * g;
+            c3 = c2 + (n_gas * sig2[idx]) * g;
+          } else {
+            double z0, z1, z2;
+            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+            const double g2 = gx * gx + gy * gy + gz * gz;
+            g = sqrt(g2);
+            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            c1 = (n_gas * sig0[idx]) * g;
+            c2 = c1 + (n_gas * sig1[idx]) * g;
+            c3 = c2;
+          }
+          if (c3 > nu_star) gl_add(&Cw->ctr[kAnomaly], 1);
+          const double t = r_proc * nu_star;
+          proc = t < c1 ? 0 : (t < c2 ? 1 : (SP == 0 && t < c3 ? 2 : -1));
+        } else {
+          double p_coll, s_a, s_b, s_c = 0.0;
+          int idx;
+          if (SP == 0) {
+            const double v2 = vxn * vxn + vy * vy + vz * vz;
+            const double v = sqrt(v2);
+            const double energy = 0.5 * kEMass * v2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            s_a = sig0[idx];
+            s_b = sig1[idx];
+            s_c = sig2[idx];
+            const double nu = nsig[idx] * v;
+            p_coll = 1.0 - exp(-nu * dt);
+          } else {
+            double z0, z1, z2;
+            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+            const double g2 = gx * gx + gy * gy + gz * gz;
+            const double g = sqrt(g2);
+            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+            idx = energy_bin(energy, de_cs, nbins);
+            s_a = sig0[idx];
+            s_b = sig1[idx];
+            const double nu = nsig[idx] * g;
+            p_coll = 1.0 - exp(-nu * dt);
+          }
+          if (r_coll < p_coll) {
+            if (SP == 0) {
+              const double s_tot = s_a + s_b + s_c;
+              if (!(s_tot > 0.0) || r_proc < s_a / s_tot)
+                proc = 0;
+              else if (r_proc < (s_a + s_b) / s_tot)
+                proc = 1;
+              else
+                proc = 2;
+            } else {
+              proc = (!(s_a + s_b > 0.0) || r_proc < s_a / (s_a + s_b)) ? 0 : 1;
+            }
+          }
+        }
+      }
+      const bool coll = proc >= 0;
+      t_coll += __popcll(__ballot(coll));
+      if (SP == 0) {
+        const bool ioniz = proc == 2;
+        double xb = 0.0;
+        int64_t be = -1, bi = -1;
+        const uint64_t mi = __ballot(ioniz);
+        if (mi) {
+          t_ioniz += __popcll(mi);
+          be = take_slot_lds(ioniz, &sBirth[0], n_e0, cap_e, lane);
+          bi = take_slot_lds(ioniz, &sBirth[1], n_i0, cap_i, lane);
+          if (ioniz) {
+            xb = X[i];
+            long long r;
+            const int q = deposit_split(xb, inv_dx, ng, r);
+            if (wg_list) {
+              gl_add(&dst[q], 4294967296LL - r);
+              gl_add(&dst[q + 1], r);
+            } else {
+              lds_add(&sH[q], 4294967296LL - r);
+              lds_add(&sH[q + 1], r);
+            }
+            gl_add(&cnt_i_next[q], 4294967296LL - r);
+            gl_add(&cnt_i_next[q + 1], r);
+          }
+        }
+        if (coll) electron_scatter_at(C, P, i, proc, be, bi, s, vxn, vy, vz, uid, xb);
+      } else if (coll) {
+        ion_scatter_at(C, P, i, proc, s, vxn, vy, vz, uid);
+      }
+    }
+  };
+
+  for (int64_t c = 0; c < nch; ++c) {
+    const int slot = w * kWave + lane;
+    const int64_t i = c * kChunk + slot;
+    double x = __longlong_as_double(0x7FF8000000000000LL), vx = 0.0, vy = 0.0, vz = 0.0, vp2 = 0.0;
+    uint64_t uid = 0;
+    if (i < n) {
+      x = X[i];
+      vx = VX[i];
+      if (SP == 1 || pdiag) {
+        vy = VY[i];
+        vz = VZ[i];
+      }
+      if (SP == 0) vp2 = (double)VP2[i];
+      uid = UID[i];
+    }
+    bool live = x == x;
+    t_live += __popcll(__ballot(live));
+    bool abs_pow = false, abs_gnd = false, surf = false, cand = false;
+    double xn = 0.0, vxn = 0.0, v2 = 0.0;
+    if (live) {
+      // steps 3-4: field at the particle (section 2.1.3) and leapfrog
+      // (section 2.1.4), as in the lockstep kernel
+      const double xi = x * inv_dx;
+      int cell = (int)xi;
+      cell = cell > ng - 2 ? ng - 2 : (cell < 0 ? 0 : cell);
+      const double w_lo = (double)(cell + 1) - xi;
+      const double w_hi = xi - (double)cell;
+      const double e_here = sE[cell] * w_lo + sE[cell + 1] * w_hi;
+      vxn = SP == 0 ? vx - e_here * kick : vx + e_here * kick;
+      xn = x + vxn * dt;
+      if (pdiag) {
+        const double vbar = 0.5 * (vx + vxn);
+        if (fl & (kDiagCurrent | kDiagXT)) {
+          lds_add(&sJ[cell], (long long)(w_lo * vbar * kDiagJS));
+          lds_add(&sJ[cell + 1], (long long)(w_hi * vbar * kDiagJS));
+        }
+        if (SP == 1) {
+          if (xt) {
+            const double en = 0.5 * kArMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
+            lds_add(&sW[cell], (long long)(w_lo * kDiagWS));
+            lds_add(&sW[cell + 1], (long long)(w_hi * kDiagWS));
+            lds_add(&sEn[cell], (long long)(w_lo * en * kDiagES));
+            lds_add(&sEn[cell + 1], (long long)(w_hi * en * kDiagES));
+          }
+        } else if (fl & (kDiagMeanE | kDiagEepf | kDiagXT)) {
+          const double en = 0.5 * kEMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
+          if (xt) {
+            const double vmag = sqrt(vbar * vbar + vy * vy + vz * vz);
+            const double pdt = (n_gas * sig2[energy_bin(en, de_cs, nbins)]) * vmag * dt;
+            lds_add(&sIz[cell], (long long)(w_lo * pdt * kDiagIZS));
+            lds_add(&sIz[cell + 1], (long long)(w_hi * pdt * kDiagIZS));
+          }
+          if (fl & (kDiagMeanE | kDiagXT)) {
+            lds_add(&sW[cell], (long long)(w_lo * kDiagWS));
+            lds_add(&sW[cell + 1], (long long)(w_hi * kDiagWS));
+            lds_add(&sEn[cell], (long long)(w_lo * en * kDiagES));
+            lds_add(&sEn[cell + 1], (long long)(w_hi * en * kDiagES));
+          }
+          if ((fl & kDiagEepf) && x >= x_lo && x <= x_hi) {
+            const double t = en / de_eepf;
+            if (t < (double)n_eepf) atomicAdd(&sF[(int)t], 1u);
+          }
+        }
+      }
+      // step 5: walls and surface processes, as in the lockstep kernel
+      abs_pow = xn < 0.0;
+      abs_gnd = xn > L_gap;
+      if (surf_on && (abs_pow || abs_gnd)) {
+        double r_surf, r_unused;
+        uniform2(seed, uid, st, tag(SP, 3, 0), r_surf, r_unused);
+        if (r_surf < (abs_pow ? p_surf0 : p_surf1)) {
+          if (SP == 0) {
+            const double xm = abs_pow ? -xn : 2.0 * L_gap - xn;
+            if (xm >= 0.0 && xm <= L_gap) {
+              xn = xm;
+              vxn = -vxn;
+              abs_pow = abs_gnd = false;
+              surf = true;
+            }
+          } else {
+            surf = true;
+            long long r;
+            const int q = deposit_split(abs_pow ? 0.0 : L_gap, inv_dx, ng, r);
+            gl_add(&cnt_e_next[q], 4294967296LL - r);
+            if (r) gl_add(&cnt_e_next[q + 1], r);
+          }
+        }
+      }
+      if (abs_pow || abs_gnd) {
+        live = false;
+        if (SP == 1 && (fl & kDiagIfed)) {
+          const double en = 0.5 * kArMass * (vxn * vxn + vy * vy + vz * vz) / kEvToJ;
+          const double t = en / de_ifed;
+          const int b = t < (double)n_ifed ? (int)t : n_ifed;
+          atomicAdd(&sF[(abs_gnd ? n_ifed + 1 : 0) + b], 1u);
+        }
+      } else {
+        long long r;
+        const int q = deposit_split(xn, inv_dx, ng, r);
+        lds_add(&sH[q], 4294967296LL - r);
+        lds_add(&sH[q + 1], r);
+        double r_coll, r_proc;
+        uniform2(seed, uid, st, r_tag, r_coll, r_proc);
+        v2 = SP == 0 ? vxn * vxn + vp2 : vxn * vxn + vy * vy + vz * vz;
+        cand = r_coll < p_cand || (SP == 0 ? v2 : 2.0 * (v2 + a2_i)) > v2_cand;
+      }
+    }
+    if (i < n && x == x) {
+      X[i] = live ? xn : __longlong_as_double(0x7FF8000000000000LL);
+      VX[i] = vxn;
+    }
+    if (surf_on) {
+      const uint64_t m_s0 = __ballot(surf && (SP == 0 || abs_pow));
+      const uint64_t m_s1 = SP == 1 ? __ballot(surf && abs_gnd) : 0ull;
+      if (lane == 0 && m_s0) gl_add(&Cw->ctr[SP == 0 ? kRefl : kSeePow], (long long)__popcll(m_s0));
+      if (lane == 0 && m_s1) gl_add(&Cw->ctr[kSeeGnd], (long long)__popcll(m_s1));
+      if (SP == 1 && (m_s0 | m_s1)) {
+        // a secondary electron takes its slot after this step's births so far
+        const int64_t be = take_slot_lds(surf, &sBirth[0], n_e0, cap_e, lane);
+        if (surf) see_emit_at(C, P, uid, abs_pow ? 0 : 1, be, s);
+      }
+    }
+    const uint64_t m_c = __ballot(cand);
+    if (m_c) {
+      if (cand) {
+        const int at = ncw + lane_rank(m_c);
+        sSeg[w][at] = (int32_t)i;
+        if (SP == 0) {
+          sVx[SP == 0 ? w : 0][SP == 0 ? at : 0] = vxn;
+          sUid[SP == 0 ? w : 0][SP == 0 ? at : 0] = uid;
+        }
+      }
+      ncw += __popcll(m_c);
+      if (ncw > kSeg - kWave) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        process(false, ncw, lane, kWave);
+        ncw = 0;
+      }
+    }
+    t_pow += __popcll(__ballot(abs_pow));
+    t_gnd += __popcll(__ballot(abs_gnd));
+  }
+  if (lane == 0) sNc[w] = ncw;
+  __syncthreads();
+  for (int q = threadIdx.x; q < ng; q += blockDim.x) {
+    const unsigned long long h = sH[q];
+    if (h) gl_add(&dst[q], (long long)h);
+    if (pdiag) {
+      const int64_t off3 = (s % 3) * ng + q;
+      if (sJ[q]) gl_add(&(SP == 0 ? C->acc_je : C->acc_ji)[off3], (long long)sJ[q]);
+      if (sW[q]) gl_add(&(SP == 0 ? C->acc_w : C->acc_wi)[off3], (long long)sW[q]);
+      if (sEn[q]) gl_add(&(SP == 0 ? C->acc_e : C->acc_ei)[off3], (long long)sEn[q]);
+      if (SP == 0 && xt && sIz[q]) gl_add(&C->acc_iz[off3], (long long)sIz[q]);
+    }
+  }
+  int64_t* hist = SP == 0 ? C->eepf : C->ifed;
+  for (int b = threadIdx.x; b < n_hist; b += blockDim.x)
+    if (sF[b]) gl_add(&hist[b], (long long)sF[b]);
+  process(true, sNc[0] + sNc[1] + sNc[2] + sNc[3], (int)threadIdx.x, kBlock);
+  if (lane == 0) {
+    sTot[w][0] = t_coll;
+    sTot[w][1] = t_ioniz;
+    sTot[w][2] = t_pow;
+    sTot[w][3] = t_gnd;
+    sTot[w][4] = t_live;
+  }
+  __syncthreads();
+  SmallTot T{0, 0, 0, 0, 0};
+  for (int v = 0; v < kBlock / kWave; ++v) {
+    T.coll += sTot[v][0];
+    T.ioniz += sTot[v][1];
+    T.pow += sTot[v][2];
+    T.gnd += sTot[v][3];
+    T.live += sTot[v][4];
+  }
+  __syncthreads();  // sTot and the segments are free for the next call
+  return T;
+}
+
+// Compaction + counting sort by cell of species sp in one workgroup: the
+// live slots of [0, n) of set `cur` go to the other set, cell by cell (order
+// within a cell arbitrary); returns the live count.  sC: LDS for ng counters.
+__device__ __forceinline__ int64_t small_sort(CaseDev* __restrict__ Cw, int sp, int cur, int64_t n, unsigned int* sC) {
+  __shared__ int64_t sRed[64];
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
+  const int ng = C->ng;
+  const double inv_dx = C->inv_dx;
+  const EDP_CONST SpeciesDev& S = C->sp[sp];
+  const EDP_GLOBAL double* __restrict__ X = G(S.x[cur]);
+  for (int p = threadIdx.x; p < ng; p += blockDim.x) sC[p] = 0;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    const double x = X[i];
+    if (x == x) atomicAdd(&sC[cell_of(x, inv_dx, ng)], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the ng - 1 cell counts, a contiguous range per thread
+  const int m = ng - 1;
+  const int per = (m + kBlock - 1) / kBlock;
+  const int lo = (int)threadIdx.x * per < m ? (int)threadIdx.x * per : m;
+  const int hi = lo + per < m ? lo + per : m;
+  int64_t acc = 0;
+  for (int p = lo; p < hi; ++p) acc += sC[p];
+  int64_t total;
+  int64_t run = block_exclusive_scan_t<int64_t>(acc, sRed, &total);
+  for (int p = lo; p < hi; ++p) {
+    const unsigned int v = sC[p];
+    sC[p] = (unsigned int)run;
+    run += v;
+  }
+  __syncthreads();
+  const int nxt = cur ^ 1;
+  const EDP_GLOBAL double* __restrict__ VX = G(S.vx[cur]);
+  const EDP_GLOBAL double* __restrict__ VY = G(S.vy[cur]);
+  const EDP_GLOBAL double* __restrict__ VZ = G(S.vz[cur]);
+  const EDP_GLOBAL uint64_t* __restrict__ UID = G(S.uid[cur]);
+  EDP_GLOBAL double* __restrict__ X2 = G(S.x[nxt]);
+  EDP_GLOBAL double* __restrict__ VX2 = G(S.vx[nxt]);
+  EDP_GLOBAL double* __restrict__ VY2 = G(S.vy[nxt]);
+  EDP_GLOBAL double* __restrict__ VZ2 = G(S.vz[nxt]);
+  EDP_GLOBAL uint64_t* __restrict__ UID2 = G(S.uid[nxt]);
+  EDP_GLOBAL float* __restrict__ VP22 = sp == 0 ? G(S.vp2[nxt]) : nullptr;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    const double x = X[i];
+    if (!(x == x)) continue;
+    const double vx = VX[i], vy = VY[i], vz = VZ[i];
+    const uint64_t uid = UID[i];
+    const int64_t d = atomicAdd(&sC[cell_of(x, inv_dx, ng)], 1u);
+    X2[d] = x;
+    VX2[d] = vx;
+    VY2[d] = vy;
+    VZ2[d] = vz;
+    UID2[d] = uid;
+    if (sp == 0) VP22[d] = float_above(vy * vy + vz * vz);
+  }
+  __syncthreads();
+  return total;
+}
+
+// Window of steps of the small cases: workgroup b advances the case of role
+// b by role.j steps.  Dynamic LDS: E, then the largest of the field solve's
+// two padded rows, the particle phase's histograms and the sort's counters.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ R, int sort_every) {
+  extern __shared__ double ssm2[];
+  __shared__ int64_t sState[6];  // step, n_e, n_i, cur_e, cur_i, spare
+  __shared__ int sBirth[2];
+  const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
+  CaseDev* Cw = r->c;
+  const int steps = r->j;
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
+  const int ng = C->ng;
+  const int nsub = C->nsub;
+  double* sE = ssm2;
+  double* reg = ssm2 + ng;
+  // a collision queue the lockstep path left pending is applied first
+  if (Cw->q_valid) {
+    apply_queue<kWave>(Cw, 0, 1);
+    __syncthreads();
+    fold_queue(Cw);
+    __syncthreads();
+    if (threadIdx.x == 0) Cw->q_valid = 0;
+  }
+  if (threadIdx.x == 0) {
+    // vector loads (the scalar cache does not see this launch's stores)
+    auto ld = [](const int64_t* a) { return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+    auto ld32 = [](const int32_t* a) { return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+    sState[0] = ld(&Cw->step);
+    sState[1] = ld(&Cw->n[0]);
+    sState[2] = ld(&Cw->n[1]);
+    sState[3] = ld32(&Cw->cur[0]);
+    sState[4] = ld32(&Cw->cur[1]);
+  }
+  __syncthreads();
+  for (int t = 0; t < steps; ++t) {
+    const int64_t s = sState[0];
+    int64_t n_e = sState[1], n_i = sState[2];
+    int cur_e = (int)sState[3], cur_i = (int)sState[4];
+    const bool ion_step = (s % nsub) == 0;
+    // compaction + cell sort on the lockstep path's schedule
+    if (s % sort_every == 0) {
+      n_e = small_sort(Cw, 0, cur_e, n_e, (unsigned int*)ssm2);
+      cur_e ^= 1;
+    }
+    if (s % ((int64_t)sort_every * nsub) == 0) {
+      n_i = small_sort(Cw, 1, cur_i, n_i, (unsigned int*)ssm2);
+      cur_i ^= 1;
+    }
+    if (threadIdx.x < 2) sBirth[threadIdx.x] = 0;
+    // steps 1-2
+    field_to_lds<MODE>(Cw, sE, reg, true, s);
+    const SmallTot te = small_species<0>(Cw, sE, reg, s, n_e, cur_e, cur_i, n_e, n_i, sBirth);
+    SmallTot ti{0, 0, 0, 0, 0};
+    if (ion_step) ti = small_species<1>(Cw, sE, reg, s, n_i, cur_i, cur_e, n_e, n_i, sBirth);
+    if (threadIdx.x == 0) {
+      int64_t* ctr = Cw->ctr;
+      ctr[kCollE] += te.coll;
+      ctr[kIoniz] += te.ioniz;
+      ctr[kAbsEPow] += te.pow;
+      ctr[kAbsEGnd] += te.gnd;
+      ctr[kPstepE] += te.live;
+      ctr[kCollI] += ti.coll;
+      ctr[kAbsIPow] += ti.pow;
+      ctr[kAbsIGnd] += ti.gnd;
+      ctr[kPstepI] += ti.live;
+      const int64_t be = sBirth[0], bi = sBirth[1];
+      const int64_t room_e = C->sp[0].cap - n_e, room_i = C->sp[1].cap - n_i;
+      const int64_t ge = be < room_e ? be : (room_e > 0 ? room_e : 0);
+      const int64_t gi = bi < room_i ? bi : (room_i > 0 ? room_i : 0);
+      ctr[kLiveE] += ge - te.pow - te.gnd;
+      ctr[kLiveI] += gi - ti.pow - ti.gnd;
+      if (ge < be || gi < bi) {
+        ctr[kDropped] += (be - ge) + (bi - gi);
+        Cw->error = 1;
+      }
+      sState[0] = s + 1;
+      sState[1] = n_e + ge;
+      sState[2] = n_i + gi;
+      sState[3] = cur_e;
+      sState[4] = cur_i;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Cw->step = sState[0];
+    Cw->n[0] = Cw->alloc[0] = sState[1];
+    Cw->n[1] = Cw->alloc[1] = sState[2];
+    Cw->cur[0] = (int32_t)sState[3];
+    Cw->cur[1] = (int32_t)sState[4];
+  }
+}
+
 __global__ void k_seed(CaseDev* __restrict__ C, int sp, int64_t n, double sigma) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -1453,10 +2242,6 @@ __global__ void __launch_bounds__(256) k_deposit(CaseDev* __restrict__ C, int sp
 // so the per-workgroup deposit flush stays small).  Order within a cell is
 // arbitrary; results do not depend on it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int cell_of(double x, double inv_dx, int ng) {
-  int p = (int)(x * inv_dx);
-  return p > ng - 2 ? ng - 2 : (p < 0 ? 0 : p);
-}
 
 
 
@@ -1712,6 +2497,29 @@ int particle_occupancy(int sp, size_t lds) {
   const hipError_t e = sp == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<0>, kBlock, lds)
                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<1>, kBlock, lds);
   return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+// Dynamic LDS of the small-case kernel for a case: E, then the largest of
+// the field solve's rows and either species' particle region.
+size_t small_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed) {
+  size_t region = 2 * (size_t)(ng + (ng >> 4) + 1);
+  for (int sp = 0; sp < 2; ++sp) {
+    const size_t r = particle_lds_bytes(ng, flags, n_eepf, n_ifed, sp) / 8 - (size_t)ng;
+    region = region > r ? region : r;
+  }
+  return ((size_t)ng + region) * 8;
+}
+
+size_t small_static_lds() { return particle_static_lds(0) + particle_static_lds(1) + 2048; }
+
+// One window of the small cases: workgroup b runs the case of roles[b] for
+// roles[b].j steps.
+hipError_t launch_small(const BlockRole* roles, int ncase, size_t lds, int mode, int sort_every, hipStream_t st) {
+  if (mode == 1)
+    hipLaunchKernelGGL(k_small<1>, dim3(ncase), dim3(kBlock), lds, st, roles, sort_every);
+  else
+    hipLaunchKernelGGL(k_small<0>, dim3(ncase), dim3(kBlock), lds, st, roles, sort_every);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
