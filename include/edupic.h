@@ -256,6 +256,18 @@ int64_t edp_case_bytes(const edp_ctx *ctx, const edp_case_desc *desc);
 int edp_case_create(edp_ctx *ctx, const edp_case_desc *desc, void *dev_arena,
                     int64_t arena_bytes, edp_case *out);
 int edp_case_destroy(edp_ctx *ctx, edp_case c);
+/* Move a case into a new arena with other particle capacities (0 keeps a
+ * species' capacity): the paper's codes fix the largest particle count at
+ * compile time (section 3.1); a long run whose plasma grows can instead be
+ * given room at a cycle boundary.  dev_arena: device memory of at least
+ * edp_case_bytes for the descriptor with the new capacities, 256-byte
+ * aligned, caller-owned; the old arena returns to the caller when the call
+ * returns.  Particles, counters, deposits, fields and every diagnostic carry
+ * over unchanged, so the run continues bit for bit as it would have.
+ * Synchronous.  EDP_ESTATE if the slots in use exceed a new capacity,
+ * EDP_EARENA for a short or misaligned arena, EDP_EINVAL otherwise. */
+int edp_case_resize(edp_ctx *ctx, edp_case c, int64_t cap_e, int64_t cap_i, void *dev_arena,
+                    int64_t arena_bytes);
 /* The cycle loop of Algorithm 1 (a run given arg1 > 0 cycles, each cycle
  * N_t repetitions of the six-step PIC/MCC cycle of section 2.1, ions every
  * N_SUB-th step): advance each listed case by n_cycles[k] RF cycles of

@@ -287,6 +287,52 @@ Layout layout(const edp_case_desc* c, int nbins) {
   return L;
 }
 
+// The array pointers of a case's control block for an arena laid out as L
+// (the capacities too).
+void set_pointers(CaseDev& h, char* arena, const Layout& L) {
+  for (int sp = 0; sp < 2; ++sp) {
+    h.sp[sp].cap = L.cap[sp];
+    for (int set = 0; set < 2; ++set) {
+      h.sp[sp].x[set] = (double*)(arena + L.off_part[sp][set][0]);
+      h.sp[sp].vx[set] = (double*)(arena + L.off_part[sp][set][1]);
+      h.sp[sp].vy[set] = (double*)(arena + L.off_part[sp][set][2]);
+      h.sp[sp].vz[set] = (double*)(arena + L.off_part[sp][set][3]);
+      h.sp[sp].uid[set] = (uint64_t*)(arena + L.off_part[sp][set][4]);
+      h.sp[sp].vp2[set] = sp == 0 ? (float*)(arena + L.off_vp2[set]) : nullptr;
+    }
+  }
+  for (int sp = 0; sp < 2; ++sp) {
+    h.cq_ent[sp] = (int64_t*)(arena + L.off_cq[sp]);
+  }
+  for (int sp = 0; sp < 2; ++sp) h.q_wg[sp] = (int32_t*)(arena + L.off_qwg[sp]);
+  double* tabs[7];
+  for (int t = 0; t < 7; ++t) tabs[t] = (double*)(arena + L.off_tab[t]);
+  h.nsig_e = tabs[0];
+  h.nsig_i = tabs[1];
+  h.sig_el = tabs[2];
+  h.sig_exc = tabs[3];
+  h.sig_ion = tabs[4];
+  h.sig_iso = tabs[5];
+  h.sig_back = tabs[6];
+  h.rden = (double*)(arena + L.off_rden);
+  h.volt = (double*)(arena + L.off_volt);
+  h.cnt_e = (int64_t*)(arena + L.off_cnt_e);
+  h.cnt_i = (int64_t*)(arena + L.off_cnt_i);
+  h.rho = (double*)(arena + L.off_rho);
+  h.phi = (double*)(arena + L.off_phi);
+  h.efield = (double*)(arena + L.off_ef);
+  h.flux = (double*)(arena + L.off_flux);
+  double** sums[6] = {&h.sum_ne, &h.sum_ni, &h.sum_je, &h.sum_ji, &h.sum_w, &h.sum_e};
+  for (int k = 0; k < 6; ++k) *sums[k] = (double*)(arena + L.off_sum[k]);
+  int64_t** accs[7] = {&h.acc_je, &h.acc_ji, &h.acc_w, &h.acc_e, &h.acc_wi, &h.acc_ei, &h.acc_iz};
+  for (int k = 0; k < 7; ++k) *accs[k] = (int64_t*)(arena + L.off_acc[k]);
+  h.eepf = (int64_t*)(arena + L.off_eepf);
+  h.xt = (double*)(arena + L.off_xt);
+  h.xt_cnt = (int64_t*)(arena + L.off_xtcnt);
+  h.ifed = (int64_t*)(arena + L.off_ifed);
+  h.sort_cnt = (int64_t*)(arena + L.off_sort);
+}
+
 // Driving voltage V(t_s) = sum_k V_k sin(2 pi f_k t_s + phi_k) + V_dc, t_s = s dt_e.
 double voltage(const edp_case_desc& c, int64_t s) {
   const double t = (double)s * c.dt_e;
@@ -1130,48 +1176,9 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   h.refl_on = D.eta_refl[0] > 0.0 || D.eta_refl[1] > 0.0;
   h.see_sigma = h.see_on ? std::sqrt(D.see_te_ev * kEvToJ / kEMass) : 0.0;
   h.seed = D.seed;
-  for (int sp = 0; sp < 2; ++sp) {
-    h.sp[sp].cap = L.cap[sp];
-    for (int set = 0; set < 2; ++set) {
-      h.sp[sp].x[set] = (double*)(c->arena + L.off_part[sp][set][0]);
-      h.sp[sp].vx[set] = (double*)(c->arena + L.off_part[sp][set][1]);
-      h.sp[sp].vy[set] = (double*)(c->arena + L.off_part[sp][set][2]);
-      h.sp[sp].vz[set] = (double*)(c->arena + L.off_part[sp][set][3]);
-      h.sp[sp].uid[set] = (uint64_t*)(c->arena + L.off_part[sp][set][4]);
-      h.sp[sp].vp2[set] = sp == 0 ? (float*)(c->arena + L.off_vp2[set]) : nullptr;
-    }
-  }
-  for (int sp = 0; sp < 2; ++sp) {
-    h.cq_ent[sp] = (int64_t*)(c->arena + L.off_cq[sp]);
-  }
-  for (int sp = 0; sp < 2; ++sp) h.q_wg[sp] = (int32_t*)(c->arena + L.off_qwg[sp]);
-  h.q_valid = 0;
-  double* tabs[7];
-  for (int t = 0; t < 7; ++t) tabs[t] = (double*)(c->arena + L.off_tab[t]);
-  h.nsig_e = tabs[0];
-  h.nsig_i = tabs[1];
-  h.sig_el = tabs[2];
-  h.sig_exc = tabs[3];
-  h.sig_ion = tabs[4];
-  h.sig_iso = tabs[5];
-  h.sig_back = tabs[6];
-  h.rden = (double*)(c->arena + L.off_rden);
-  h.volt = (double*)(c->arena + L.off_volt);
-  h.cnt_e = (int64_t*)(c->arena + L.off_cnt_e);
-  h.cnt_i = (int64_t*)(c->arena + L.off_cnt_i);
-  h.rho = (double*)(c->arena + L.off_rho);
-  h.phi = (double*)(c->arena + L.off_phi);
-  h.efield = (double*)(c->arena + L.off_ef);
-  h.flux = (double*)(c->arena + L.off_flux);
-  double** sums[6] = {&h.sum_ne, &h.sum_ni, &h.sum_je, &h.sum_ji, &h.sum_w, &h.sum_e};
-  for (int k = 0; k < 6; ++k) *sums[k] = (double*)(c->arena + L.off_sum[k]);
-  int64_t** accs[7] = {&h.acc_je, &h.acc_ji, &h.acc_w, &h.acc_e, &h.acc_wi, &h.acc_ei, &h.acc_iz};
-  for (int k = 0; k < 7; ++k) *accs[k] = (int64_t*)(c->arena + L.off_acc[k]);
-  h.eepf = (int64_t*)(c->arena + L.off_eepf);
-  h.xt = (double*)(c->arena + L.off_xt);
-  h.xt_cnt = (int64_t*)(c->arena + L.off_xtcnt);
-  h.ifed = (int64_t*)(c->arena + L.off_ifed);
-  h.sort_cnt = (int64_t*)(c->arena + L.off_sort);
+  set_pointers(h, c->arena, L);
+  double* tabs[7] = {(double*)h.nsig_e, (double*)h.nsig_i, (double*)h.sig_el, (double*)h.sig_exc,
+                     (double*)h.sig_ion, (double*)h.sig_iso, (double*)h.sig_back};
   // dynamic part
   h.step = 0;
   h.alloc[0] = D.n_init_e;
@@ -1222,6 +1229,66 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   c->id = ctx->next_id++;
   ctx->cases[c->id] = c;
   *out = c->id;
+  return EDP_OK;
+}
+
+int edp_case_resize(edp_ctx* ctx, edp_case id, int64_t cap_e, int64_t cap_i, void* dev_arena,
+                    int64_t arena_bytes) {
+  Case* c = ctx ? find(ctx, id) : nullptr;
+  if (!c) return fail(EDP_EINVAL, "unknown case");
+  if (cap_e < 0 || cap_i < 0) return fail(EDP_EINVAL, "negative capacity");
+  edp_case_desc D2 = c->desc;
+  if (cap_e > 0) D2.cap_e = cap_e;
+  if (cap_i > 0) D2.cap_i = cap_i;
+  int r = validate(&D2);
+  if (r) return r;
+  const Layout Lo = layout(&c->desc, ctx->nbins), Ln = layout(&D2, ctx->nbins);
+  if (!dev_arena || arena_bytes < (int64_t)Ln.total)
+    return fail(EDP_EARENA, "arena needs %lld bytes, got %lld", (long long)Ln.total, (long long)arena_bytes);
+  if (((uintptr_t)dev_arena) % kAlign) return fail(EDP_EARENA, "arena must be 256-byte aligned");
+  HIPCHK(hipSetDevice(ctx->device));
+  // the batch tables and graphs hold the old control block's address
+  if ((r = reset_groups(ctx))) return r;
+  if ((r = drain(ctx, c))) return r;  // no collision queue left pending
+  CaseDev t;
+  if ((r = read_dyn(ctx, c, t))) return r;
+  int64_t live[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    live[sp] = std::min(t.alloc[sp], c->h.sp[sp].cap);
+    if (live[sp] > Ln.cap[sp])
+      return fail(EDP_ESTATE, "%lld slots in use exceed the new capacity %lld", (long long)live[sp],
+                  (long long)Ln.cap[sp]);
+  }
+  char* na = (char*)dev_arena;
+  hipStream_t st = ctx->stream;
+  // the slots in use of the current buffer set go to set 0 of the new arena
+  for (int sp = 0; sp < 2; ++sp) {
+    const int cur = t.cur[sp];
+    const size_t n = (size_t)live[sp];
+    if (!n) continue;
+    for (int a = 0; a < 5; ++a)
+      HIPCHK(hipMemcpyAsync(na + Ln.off_part[sp][0][a], c->arena + Lo.off_part[sp][cur][a], n * 8,
+                            hipMemcpyDeviceToDevice, st));
+    if (sp == 0)
+      HIPCHK(hipMemcpyAsync(na + Ln.off_vp2[0], c->arena + Lo.off_vp2[cur], n * 4, hipMemcpyDeviceToDevice, st));
+  }
+  // tables, V(t), deposit rings, fields and every diagnostic: the same
+  // layout after the particle and queue regions
+  const size_t tail = Lo.total - Lo.off_tab[0];
+  if (tail != Ln.total - Ln.off_tab[0]) return fail(EDP_EHIP, "internal: layouts differ beyond the particles");
+  HIPCHK(hipMemcpyAsync(na + Ln.off_tab[0], c->arena + Lo.off_tab[0], tail, hipMemcpyDeviceToDevice, st));
+  CaseDev h = c->h;
+  set_pointers(h, na, Ln);
+  std::memcpy((char*)&h + kDynOff, (const char*)&t + kDynOff, kDynBytes);
+  h.cur[0] = h.cur[1] = 0;
+  CaseDev* nd = (CaseDev*)(na + Ln.off_case);
+  HIPCHK(hipMemcpyAsync(nd, &h, sizeof(CaseDev), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->desc = D2;
+  c->h = h;
+  c->d = nd;
+  c->arena = na;
+  c->arena_bytes = arena_bytes;
   return EDP_OK;
 }
 

@@ -80,7 +80,7 @@ EXPORTS = ["edp_create", "edp_destroy", "edp_set_xsec", "edp_case_bytes", "edp_c
            "edp_read_deposit", "edp_read_fields", "edp_get_state", "edp_set_state",
            "edp_set_option", "edp_read_profile", "edp_last_error", "edp_read_xt",
            "edp_read_xt_steps", "edp_read_ifed", "edp_read_info", "edp_reset_diag", "edp_set_voltage",
-           "edp_advance_steps_noalloc"]
+           "edp_advance_steps_noalloc", "edp_case_resize"]
 
 _lib = None
 
@@ -106,6 +106,7 @@ def load() -> C.CDLL:
         "edp_case_bytes": (I64, [P, C.POINTER(CaseDesc)]),
         "edp_case_create": (C.c_int, [P, C.POINTER(CaseDesc), P, I64, I64P]),
         "edp_case_destroy": (C.c_int, [P, I64]),
+        "edp_case_resize": (C.c_int, [P, I64, I64, I64, P, I64]),
         "edp_advance": (C.c_int, [P, I64P, I32, C.POINTER(I32)]),
         "edp_advance_steps": (C.c_int, [P, I64P, I32, I64P]),
         "edp_advance_steps_noalloc": (C.c_int, [P, I64P, I32, I64P]),
@@ -275,6 +276,30 @@ class Case:
         out = C.c_int64(0)
         _chk(load().edp_case_create(ctx.h, C.byref(d), C.c_void_p(aligned), nbytes, C.byref(out)))
         self.id = out.value
+
+    def resize(self, cap_e: int = 0, cap_i: int = 0):
+        """Move the case into a new arena with other particle capacities (0:
+        keep); the run continues unchanged."""
+        case = dict(self.case)
+        if cap_e:
+            case["cap_e"] = cap_e
+        if cap_i:
+            case["cap_i"] = cap_i
+        d = make_desc(case)
+        nbytes = _chk(load().edp_case_bytes(self.ctx.h, C.byref(d)))
+        torch = self.ctx._torch
+        arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        aligned = (arena.data_ptr() + 255) // 256 * 256
+        _chk(load().edp_case_resize(self.ctx.h, self.id, int(cap_e), int(cap_i), C.c_void_p(aligned), nbytes))
+        self.arena = arena  # the old arena is released here
+        self.case = case
+
+    def capacity(self):
+        """(cap_e, cap_i) as the library rounds them."""
+        def cap(n_init, c):
+            v = c if c > 0 else max(2 * n_init, 1 << 18)
+            return (v + 255) // 256 * 256
+        return cap(self.case["n_init_e"], self.case.get("cap_e", 0)), cap(self.case["n_init_i"], self.case.get("cap_i", 0))
 
     def destroy(self):
         if self.id:
