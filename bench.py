@@ -26,7 +26,8 @@ electron step (read x, vx, vy, vz; write x, vx) times the electrons of a
 launch over its mean duration, from HIP events on the library's stream
 around every electron launch of a window of plain launches that continues
 the same cases after the timed region (one lockstep group, so that no other
-launch shares the chip); `step_frac` is the same 48 bytes per particle-step
+launch shares the chip; `--roof-same-groups` keeps the timed region's
+groups); `step_frac` is the same 48 bytes per particle-step
 over the whole timed region.  `traffic` is the counter-measured HBM bytes per
 launch (committed summary) while the kernel source still matches the one
 profiled.  The CPU baseline runs the single-threaded oracle, one case per
@@ -89,6 +90,9 @@ def main():
                     help="dual32: timed RF cycles of the plain large case reported beside it (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle PIC steps per case for the CPU baseline (0: the workload's default)")
+    ap.add_argument("--roof-same-groups", action="store_true",
+                    help="time the roofline window in the timed region's lockstep groups (their launches "
+                         "overlap, so each shares the chip) instead of one group")
     ap.add_argument("--roof-steps", type=int, default=0,
                     help="PIC steps of the profiled window (plain launches, HIP events per electron launch; "
                          "0: the workload's default)")
@@ -226,14 +230,16 @@ def timed(ctx, cases, run):
     return wall, pe, pi, c1
 
 
-def roofline(ctx, cases, advance_steps, steps, workload, label):
+def roofline(ctx, cases, advance_steps, steps, workload, label, one_group=True):
     """Electron-kernel roofline from HIP events around every electron launch
-    of `steps` PIC steps of plain launches in one lockstep group."""
+    of `steps` PIC steps of plain launches (every case in one lockstep group,
+    so that no other launch shares the chip, or the timed region's groups
+    with one_group=False)."""
     from paper_2103_09642_amd import edupic
     ctx.set_option(edupic.OPT_MODE, 0)
     ctx.set_option(edupic.OPT_PROFILE, 1)
     groups_before = None
-    if len(cases) > 1:
+    if one_group and len(cases) > 1:
         groups_before = ctx_groups(ctx)
         ctx.set_option(edupic.OPT_GROUPS, 1)
     ctx.sync()
@@ -401,8 +407,10 @@ def bench_batch(args):
     roof = None
     if not args.no_profile:
         steps = args.roof_steps or (200 if dual else 400)
-        roof = roofline(ctx, cases, lambda k: ctx.advance_steps(cases, [k] * len(cases)), steps,
-                        args.workload, "all cases in one lockstep group")
+        roof = roofline(ctx, cases, lambda k: ctx.advance_steps(cases, [k] * len(cases)), steps, args.workload,
+                        f"the same cases in the timed region's {ctx_groups(ctx)} lockstep group(s)"
+                        if args.roof_same_groups else "all cases in one lockstep group",
+                        one_group=not args.roof_same_groups)
         if roof:
             roof["step_frac"] = round(BYTES_PER_PSTEP * (pe + pi) / wall / 1e9 / HBM_PEAK_GBS, 4)
     for g in cases:

@@ -32,6 +32,7 @@ hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t l
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp);
 size_t particle_static_lds(int sp);
 int particle_occupancy(int sp, size_t lds);
+int head_occupancy(int max_ng);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
 hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
                           hipStream_t st);
@@ -188,7 +189,8 @@ struct edp_ctx {
   // `stream` whose role table is the device's scratch array
   Group na;
   // profiling
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;  // recorded, not yet read
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;   // created, ready for reuse
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
 };
@@ -393,15 +395,19 @@ int scatter_blocks(const edp_ctx* ctx) { return std::min(ctx->num_cu, kMaxApply)
 // Expected chunks of a species of a case (10% headroom over the estimate).
 int64_t est_chunks(const Case* c, int sp) { return (c->est[sp] + c->est[sp] / 10 + kChunk) / kChunk; }
 
-// Collision workgroups of a case in the head: enough for one round, every
-// event list (one per particle workgroup of the case) with a group of `lanes`
-// lanes, and no fewer than one per 32 chunks of the estimated live slots (up
-// to one per CU), so that short lists still spread over the chip.
-int apply_blocks(const edp_ctx* ctx, const Case* c, int lists, int lanes) {
+// Collision workgroups of a case in the head: at least enough for one round
+// (every event list -- one per particle workgroup of the case -- with a
+// group of `lanes` lanes), up to one per 32 chunks of the estimated live
+// slots (at most one per CU) so that short lists spread over the chip, and
+// never more than the lists: a list is taken by one workgroup, so a
+// workgroup beyond the lists would have nothing to do.  `one_round` gives the
+// fewest that take every list in one round.
+int apply_blocks(const edp_ctx* ctx, const Case* c, int lists, int lanes, bool one_round = false) {
   const int64_t chunks = (std::max(c->est[0], c->est[1]) + kChunk - 1) / kChunk;
   const int64_t spread = std::min<int64_t>(ctx->num_cu, (chunks + 31) / 32);
   const int64_t round = (lists + (256 / lanes) - 1) / (256 / lanes);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxApply, std::max(spread, round)));
+  const int64_t want = one_round ? round : std::min<int64_t>(std::max(spread, round), lists);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxApply, want));
 }
 
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
@@ -451,10 +457,30 @@ int drain_profile(edp_ctx* ctx) {
     HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
     ctx->prof_ms += ms;
     ctx->prof_launches += 1;
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
+    ctx->ev_free.push_back(pr);
   }
   ctx->ev_pairs.clear();
+  return EDP_OK;
+}
+
+// A new timing event pair.  Timing only: no system-scope fence (nothing on
+// the host reads the memory these events order).
+int create_event_pair(hipEvent_t& e0, hipEvent_t& e1) {
+  HIPCHK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  const hipError_t e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(EDP_EHIP, "hipEventCreateWithFlags: %s", hipGetErrorString(e));
+  }
+  return EDP_OK;
+}
+
+// A timing event pair for one electron launch: from the pool, else new.
+int take_event_pair(edp_ctx* ctx, hipEvent_t& e0, hipEvent_t& e1) {
+  if (ctx->ev_free.empty()) return create_event_pair(e0, e1);
+  e0 = ctx->ev_free.back().first;
+  e1 = ctx->ev_free.back().second;
+  ctx->ev_free.pop_back();
   return EDP_OK;
 }
 
@@ -532,8 +558,17 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
     for (size_t k = 0; k < nc; ++k)
       want[sp][k] = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxPartWG, (est_chunks(cs[k], sp) + per - 1) / per));
   }
-  for (size_t k = 0; k < nc; ++k)
+  // the head's workgroups should all be resident at once (a second round of
+  // collision workgroups would wait for the first): if the spread ones do
+  // not fit, each case gets the fewest that take its lists in one round
+  int64_t head_total = 2 * (int64_t)nc;
+  for (size_t k = 0; k < nc; ++k) {
     want_apply[k] = apply_blocks(ctx, cs[k], std::max(want[0][k], want[1][k]), ctx->apply_lanes);
+    head_total += want_apply[k];
+  }
+  if (head_total > (int64_t)ctx->num_cu * head_occupancy(max_ng))
+    for (size_t k = 0; k < nc; ++k)
+      want_apply[k] = apply_blocks(ctx, cs[k], std::max(want[0][k], want[1][k]), ctx->apply_lanes, true);
   std::vector<int> want_sort[2];
   for (int sp = 0; sp < 2; ++sp)
     for (size_t k = 0; k < nc; ++k) want_sort[sp].push_back(sort_blocks(ctx, cs[k], sp));
@@ -628,8 +663,8 @@ int enqueue_batch_step(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, in
     HIPCHK(launch_sort(G.roles_d + B.role_off[4], case_roles, 1, B.sorts[1], nc, B.max_ng, ctx->sort_every, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profile && !capture && !G.fixed) {
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    const int r = take_event_pair(ctx, e0, e1);
+    if (r) return r;
   }
   HIPCHK(launch_particles(G.roles_d + B.role_off[0], 0, B.parts[0], B.lds[0], st, e0, e1));
   if (e0) ctx->ev_pairs.emplace_back(e0, e1);
@@ -1053,10 +1088,11 @@ int edp_destroy(edp_ctx* ctx) {
     if (c->est_ev) (void)hipEventDestroy(c->est_ev);
     delete c;
   }
-  for (auto& pr : ctx->ev_pairs) {
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
-  }
+  for (auto* v : {&ctx->ev_pairs, &ctx->ev_free})
+    for (auto& pr : *v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
   delete ctx;
   return EDP_OK;
 }
@@ -1875,6 +1911,14 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
       break;
     case EDP_OPT_PROFILE:
       ctx->profile = value ? 1 : 0;
+      // create the pairs of a whole window up front, so that the host loop
+      // that enqueues the timed launches creates none
+      for (size_t n = ctx->ev_free.size() + ctx->ev_pairs.size(); ctx->profile && n < 4096; ++n) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const int r = create_event_pair(e0, e1);
+        if (r) return r;
+        ctx->ev_free.emplace_back(e0, e1);
+      }
       break;
     case EDP_OPT_GRAPH_STEPS:
       if (value < 0) return fail(EDP_EINVAL, "graph steps must be >= 0");

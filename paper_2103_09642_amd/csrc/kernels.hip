@@ -1405,21 +1405,36 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     }
   };
 
-  for (int64_t c = c_lo; c < c_hi; ++c) {
-    const int slot = w * kWave + lane;  // slot in the chunk
+  // The state of chunk c + 1 is loaded before chunk c is worked on, so each
+  // wave keeps two chunks' loads in flight (the loop is bound by memory
+  // latency, not by its arithmetic).
+  const int slot = w * kWave + lane;  // slot in the chunk
+  double nx, nvx, nvy, nvz;
+  float nvp2;
+  uint64_t nuid;
+  auto fetch = [&](const int64_t c) {
     const int64_t i = c * kChunk + slot;
-    double x = __longlong_as_double(0x7FF8000000000000LL), vx = 0.0, vy = 0.0, vz = 0.0, vp2 = 0.0;
-    uint64_t uid = 0;
+    nx = __longlong_as_double(0x7FF8000000000000LL);
+    nvx = nvy = nvz = 0.0;
+    nvp2 = 0.0f;
+    nuid = 0;
     if (i < n) {
-      x = X[i];
-      vx = VX[i];
+      nx = X[i];
+      nvx = VX[i];
       if (SP == 1 || pdiag) {
-        vy = VY[i];
-        vz = VZ[i];
+        nvy = VY[i];
+        nvz = VZ[i];
       }
-      if (SP == 0) vp2 = (double)VP2[i];
-      uid = UID[i];
+      if (SP == 0) nvp2 = VP2[i];
+      nuid = UID[i];
     }
+  };
+  fetch(c_lo);
+  for (int64_t c = c_lo; c < c_hi; ++c) {
+    const int64_t i = c * kChunk + slot;
+    const double x = nx, vx = nvx, vy = nvy, vz = nvz, vp2 = (double)nvp2;
+    const uint64_t uid = nuid;
+    if (c + 1 < c_hi) fetch(c + 1);
     bool live = x == x;  // past the end, or absorbed earlier (tombstone)
     bool abs_pow = false, abs_gnd = false, surf = false, cand = false;
     double xn = 0.0, vxn = 0.0, v2 = 0.0;
@@ -2488,6 +2503,14 @@ hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t l
     hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, roles);
   }
   return hipGetLastError();
+}
+
+// Resident workgroups per CU of the head for grids of up to max_ng nodes.
+int head_occupancy(int max_ng) {
+  const size_t lds = (size_t)(max_ng + (max_ng >> 4) + 1) * 24;
+  int nb = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_head<0, 16>, kBlock, lds);
+  return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 // Resident workgroups per CU of a species' particle kernel with `lds` bytes
