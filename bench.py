@@ -99,13 +99,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--sort-every", type=int, default=0,
-                    help="steps between compaction + cell sort; with --wg-per-cu, --apply-lanes and --groups "
+                    help="steps between compaction + cell sort; with --wg-per-cu and --groups "
                          "it fixes the schedule (default 0: the autotuner chooses on copies of the "
                          "workload's cases, outside the timed region)")
     ap.add_argument("--wg-per-cu", type=int, default=-1,
                     help="particle workgroups per CU (0: all that fit); -1: the autotuner's choice")
-    ap.add_argument("--apply-lanes", type=int, default=0,
-                    help="lanes per event list in the head (16, 32, 64); 0: the autotuner's choice")
     ap.add_argument("--groups", type=int, default=0, choices=(0, 1, 2, 3, 4),
                     help="lockstep groups of a batched advance; 0: the autotuner's choice")
     ap.add_argument("--pic-steps", type=int, default=0,
@@ -165,10 +163,10 @@ def run_cpu_baseline(args):
 # ---------------------------------------------------------------------------
 
 def choose_schedule(args, ctx, descs, warm):
-    """The compaction + sort interval, the particle workgroups per CU, the
-    lanes per event list and the lockstep groups: --sort-every, --wg-per-cu,
-    --apply-lanes and --groups if all are given (a single case: the first
-    three), else the autotuner's choice, made on copies of the workload's
+    """The compaction + sort interval, the particle workgroups per CU and the
+    lockstep groups: --sort-every, --wg-per-cu and --groups if all are given
+    (a single case: the first two), else the autotuner's choice, made on
+    copies of the workload's
     cases (created from the same seeded descriptors, advanced to the timed
     window's midpoint -- `warm(copies)` -- then tuned with every trial
     starting from that state, so that the trials see the regime of the timed
@@ -177,10 +175,9 @@ def choose_schedule(args, ctx, descs, warm):
     from paper_2103_09642_amd import edupic, tune
     if len(descs) == 1 and not args.groups:
         args.groups = tune.DEFAULTS["groups"]  # no effect on a single case
-    if args.sort_every and args.wg_per_cu >= 0 and args.apply_lanes and args.groups:
+    if args.sort_every and args.wg_per_cu >= 0 and args.groups:
         ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, args.wg_per_cu)
-        ctx.set_option(edupic.OPT_APPLY_LANES, args.apply_lanes)
         ctx.set_option(edupic.OPT_GROUPS, args.groups)
         return None
     t0 = time.perf_counter()
@@ -192,20 +189,19 @@ def choose_schedule(args, ctx, descs, warm):
                                             tune.DEFAULT_CANDIDATES,
                                             wg_candidates=(args.wg_per_cu,) if args.wg_per_cu >= 0 else
                                             tune.DEFAULT_WG_CANDIDATES,
-                                            lane_candidates=(args.apply_lanes,) if args.apply_lanes else
-                                            tune.DEFAULT_LANE_CANDIDATES, restore_state=True,
+                                            restore_state=True,
                                             group_candidates=(args.groups,) if args.groups else
                                             tune.DEFAULT_GROUP_CANDIDATES)
     finally:
         for c in copies:
             c.destroy()
     args.sort_every, args.wg_per_cu = choice["sort_every"], choice["part_wg_per_cu"]
-    args.apply_lanes, args.groups = choice["apply_lanes"], choice["groups"]
+    args.groups = choice["groups"]
     return {"seconds": round(time.perf_counter() - t0, 2),
             "on": "copies of the workload's cases advanced to the timed window's midpoint; "
                   "every trial starts from that state",
-            "trials": [[t.interval, t.wg_per_cu, t.lanes, t.groups, round(t.rate, 1)] for t in trials],
-            "trial_fields": ["sort_every", "wg_per_cu", "apply_lanes", "groups", "particle-steps/s"]}
+            "trials": [[t.interval, t.wg_per_cu, t.groups, round(t.rate, 1)] for t in trials],
+            "trial_fields": ["sort_every", "wg_per_cu", "groups", "particle-steps/s"]}
 
 
 # ---------------------------------------------------------------------------
@@ -337,7 +333,7 @@ def base_line(metric_value, wall, n_timed, args, config, roof, cpu, dtype="f64")
 
 def schedule_config(args, tuned):
     return {"mode": ["plain", "graph"][args.mode], "sort_every": args.sort_every, "wg_per_cu": args.wg_per_cu,
-            "apply_lanes": args.apply_lanes, "groups": args.groups, "schedule_tuning": tuned}
+            "groups": args.groups, "schedule_tuning": tuned}
 
 
 # ---------------------------------------------------------------------------
@@ -476,7 +472,7 @@ def plain_large(args):
     """The plain large case beside a batched line: its own tuned schedule,
     density and EEPF on."""
     class A:  # the tuner's inputs for this case alone
-        sort_every, wg_per_cu, apply_lanes, groups = 0, -1, 0, 0
+        sort_every, wg_per_cu, groups = 0, -1, 0
     ctx, g, case, tuned, wall, pe, pi, c1 = run_large(args, args.plain_steps, 1, True, A)
     g.destroy()
     ctx.close()
@@ -485,7 +481,7 @@ def plain_large(args):
                         "cycles",
             "value": round((pe + pi) / wall, 1), "unit": "particle-steps/s", "rf_cycles": args.plain_steps,
             "ms_per_rf_cycle": round(wall * 1e3 / args.plain_steps, 3),
-            "schedule": [A.sort_every, A.wg_per_cu, A.apply_lanes], "tuning_seconds": tuned and tuned["seconds"]}
+            "schedule": [A.sort_every, A.wg_per_cu], "tuning_seconds": tuned and tuned["seconds"]}
 
 
 def bench_large(args):

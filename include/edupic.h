@@ -125,19 +125,15 @@ extern "C" {
 #define EDP_OPT_GRAPH_STEPS 6 /* steps captured per hipGraph (multiple of N_SUB)  */
 #define EDP_OPT_POISSON 8     /* field solve: 0 parallel flux scans (default),
                                  1 sequential Thomas, bit-reproducible           */
-#define EDP_OPT_APPLY_LANES 10 /* lanes per event list in the head's collision
-                                 workgroups: 16, 32 or 64 (default); results do
-                                 not depend on it, speed does: the autotuner
-                                 (tune.py) picks it                           */
 #define EDP_OPT_GROUPS 11     /* lockstep groups of a multi-case advance, 1..4
                                  (default 2; at most one per case, so a
                                  single case runs alone): the cases are split
                                  by expected work (particles x steps), group 0
                                  runs on the context's stream and the others
                                  on streams the library creates (default
-                                 priority), so that one group's field solve
-                                 and collisions overlap another's particle
-                                 launch; work enqueued later on the context's
+                                 priority), so that one group's launch ramp
+                                 and tail overlap another's streaming; work
+                                 enqueued later on the context's
                                  stream is ordered after every group.
                                  Results do not depend on it, speed does: the
                                  autotuner (tune.py) picks it */
@@ -288,13 +284,15 @@ int edp_advance_steps(edp_ctx *ctx, const edp_case *cases, int32_t n_cases,
  * capture, tight serving loops, harnesses that forbid hipMalloc: the same
  * advance as edp_advance_steps (same arguments, same results bit for bit),
  * but it allocates nothing.  The workgroup role table its launches read
- * (device memory beyond the cases' arenas) is a file-scope array of 16384
- * entries (512 KiB) that each GPU the library runs on holds until the
- * process ends; the call makes no hipMalloc, hipFree, graph, stream or event
- * and launches plainly, as one lockstep group, on the context's stream.
- * Host bookkeeping uses the C++ heap only.  Limit: a call whose cases need
- * more than 16384 workgroups over its particle, head and sort launches
- * (about 100 cases of a few hundred particle workgroups each) returns
+ * (device memory beyond the cases' arenas; the first kernel of each window
+ * writes the cases' steps into it) is a file-scope array of 16384 entries
+ * (896 KiB) that each GPU the library runs on holds until the process ends;
+ * the call makes no hipMalloc, hipFree, graph, stream or event and launches
+ * plainly, as one lockstep group, on the context's stream.  Host
+ * bookkeeping uses the C++ heap only.  Limit: a call whose cases need more
+ * than 16384 workgroup roles (one per case plus its particle and sort
+ * workgroups: about 100 cases of a few hundred particle workgroups each)
+ * returns
  * EDP_EINVAL before enqueuing anything.  Every call on a GPU shares that
  * GPU's array and rewrites it at its start: calls that overlap on one GPU
  * (from two contexts, or two threads) race and must be serialised by the

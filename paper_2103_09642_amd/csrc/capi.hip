@@ -24,20 +24,18 @@
 #include "impl.hpp"
 
 namespace edp {
-hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, int lanes,
-                       hipStream_t st);
-hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st);
-hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
-                            hipEvent_t ev1);
+hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, int mode, int dstep,
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_window_begin(BlockRole* roles, int nroles, const BlockRole* cases, int ncase, hipStream_t st);
+hipError_t launch_window_end(const BlockRole* cases, int ncase, int steps, hipStream_t st);
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp);
 size_t particle_static_lds(int sp);
 int particle_occupancy(int sp, size_t lds);
-int head_occupancy(int max_ng);
 hipError_t launch_seed(CaseDev* d, int sp, int64_t n, double sigma, hipStream_t st);
 hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int ng, int blocks,
                           hipStream_t st);
 hipError_t launch_sort(const BlockRole* roles, const BlockRole* case_roles, int sp, int blocks, int ncase, int max_ng,
-                       int every, hipStream_t st);
+                       int every, int dstep, hipStream_t st);
 hipError_t launch_fold(CaseDev* d, hipStream_t st);
 size_t small_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed);
 size_t small_static_lds();
@@ -93,7 +91,6 @@ struct Case {
 struct BatchTable {
   int32_t ncase;
   int32_t part_off[2][kMaxBatch + 1];  // particle workgroups per species
-  int32_t apply_off[kMaxBatch + 1];    // collision workgroups of the head
   int32_t sort_off[2][kMaxBatch + 1];  // sort workgroups per species
 };
 
@@ -103,16 +100,16 @@ struct Batch {
   std::vector<Case*> cases;
   BatchTable h{};
   int parts[2] = {0, 0};  // particle workgroups per species
-  int apply = 0;          // collision workgroups of the head
   int sorts[2] = {0, 0};  // sort workgroups per species
-  // roles of the electron, ion, head, electron-sort and ion-sort launches'
-  // workgroups in the context's device table (the head's first ncase roles,
-  // one per case, also serve the per-case sort kernels)
+  // roles of the electron and ion launches' workgroups, one per case (the
+  // window kernels, the sort scan and finish), and of the electron-sort and
+  // ion-sort launches' workgroups, in the context's device table
   size_t role_off[5] = {0, 0, 0, 0, 0};
+  size_t nroles = 0;
   int max_ng = 2;
   size_t lds[2] = {0, 0};
-  // graph of g_steps steps, valid for these cases at these step phases and
-  // sort grids
+  // graph of one window of g_steps steps, valid for these cases at these
+  // step phases and sort grids
   hipGraphExec_t gexec = nullptr;
   int g_steps = 0;
   std::vector<int64_t> g_phase;
@@ -121,9 +118,8 @@ struct Batch {
 // One lockstep group of cases: its batch tables, its device role table, and
 // the stream its launches go to.  A multi-case advance runs as one group on
 // the caller's stream, or as up to kMaxGroups groups whose launches go to
-// streams of their own, so that one group's latency-bound head overlaps
-// another's streaming particle launch (the groups share nothing; each keeps
-// its own order).
+// streams of their own, so that one group's launch tail overlaps another's
+// streaming (the groups share nothing; each keeps its own order).
 constexpr int kMaxGroups = 4;
 struct Group {
   Batch batch;
@@ -143,7 +139,7 @@ struct Group {
 };
 
 // Workgroup roles the allocation-free advance can hold: its role table is a
-// file-scope device array of this many entries (512 KiB) per GPU.
+// file-scope device array of this many entries (896 KiB) per GPU.
 constexpr int kScratchRoles = 16384;
 
 }  // namespace
@@ -152,6 +148,7 @@ constexpr int kScratchRoles = 16384;
 // stand-in, not a device address: host code uses it only to ask
 // hipGetSymbolAddress, with a device current, for that device's copy, and
 // then only that address (kept per device by scratch_roles()).
+static_assert(sizeof(BlockRole) == 56, "role size named in the ABI header (16384 roles: 896 KiB)");
 __device__ __align__(256) BlockRole scratch[kScratchRoles];
 
 
@@ -169,7 +166,6 @@ struct edp_ctx {
   // options
   int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, poisson = 0;
   int part_wg_per_cu = 0;  // 0: every resident slot
-  int apply_lanes = 64;    // lanes per event list in the head's collision workgroups
   int groups = 2;  // lockstep groups of a multi-case advance (1..kMaxGroups)
   // cases of at most this many slots per species (estimate) run in the
   // persistent one-workgroup-per-case kernel (0: none)
@@ -198,13 +194,13 @@ struct edp_ctx {
 namespace {
 
 struct Layout {
-  size_t off_case, off_part[2][2][5], off_vp2[2], off_cq[2], off_qwg[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
-      off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[7], off_eepf, off_xt, off_xtcnt, off_ifed, off_sort,
-      total;
+  size_t off_case, off_part[2][2][5], off_vp2[2], off_cl[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
+      off_shard, off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[7], off_eepf, off_xt, off_xtcnt, off_ifed,
+      off_sort, total;
   int64_t cap[2];
 };
 
-constexpr int64_t kMaxCap = (int64_t(1) << 31) - 1024;  // slots are int32 in the queues
+constexpr int64_t kMaxCap = (int64_t(1) << 31) - 1024;  // slots are int32 in the candidate lists
 
 int validate(const edp_case_desc* c) {
   if (!c) return fail(EDP_EINVAL, "null descriptor");
@@ -264,15 +260,15 @@ Layout layout(const edp_case_desc* c, int nbins) {
   for (int set = 0; set < 2; ++set) L.off_vp2[set] = take((size_t)L.cap[0] * 4);  // electrons only (float)
   for (int sp = 0; sp < 2; ++sp) {
     const size_t chunks = (size_t)((L.cap[sp] + kChunk - 1) / kChunk);
-    L.off_cq[sp] = take(chunks * kChunk * 8);  // events (per-workgroup lists over its chunk range)
+    L.off_cl[sp] = take(chunks * kChunk * 8);  // colliders (per-workgroup lists over its chunk range)
   }
-  for (int sp = 0; sp < 2; ++sp) L.off_qwg[sp] = take((size_t)kMaxPartWG * 16);
   for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
   const size_t ng = (size_t)c->n_grid;
   L.off_rden = take(ng * 8);
   L.off_volt = take((size_t)kVoltChunk * 8);
   L.off_cnt_e = take(3 * ng * 8);
   L.off_cnt_i = take(3 * ng * 8);
+  L.off_shard = take((size_t)2 * kShards * kRec * 8);
   L.off_rho = take(ng * 8);
   L.off_phi = take(ng * 8);
   L.off_ef = take(ng * 8);
@@ -303,10 +299,7 @@ void set_pointers(CaseDev& h, char* arena, const Layout& L) {
       h.sp[sp].vp2[set] = sp == 0 ? (float*)(arena + L.off_vp2[set]) : nullptr;
     }
   }
-  for (int sp = 0; sp < 2; ++sp) {
-    h.cq_ent[sp] = (int64_t*)(arena + L.off_cq[sp]);
-  }
-  for (int sp = 0; sp < 2; ++sp) h.q_wg[sp] = (int32_t*)(arena + L.off_qwg[sp]);
+  for (int sp = 0; sp < 2; ++sp) h.clist[sp] = (int64_t*)(arena + L.off_cl[sp]);
   double* tabs[7];
   for (int t = 0; t < 7; ++t) tabs[t] = (double*)(arena + L.off_tab[t]);
   h.nsig_e = tabs[0];
@@ -320,6 +313,7 @@ void set_pointers(CaseDev& h, char* arena, const Layout& L) {
   h.volt = (double*)(arena + L.off_volt);
   h.cnt_e = (int64_t*)(arena + L.off_cnt_e);
   h.cnt_i = (int64_t*)(arena + L.off_cnt_i);
+  h.shard = (int64_t*)(arena + L.off_shard);
   h.rho = (double*)(arena + L.off_rho);
   h.phi = (double*)(arena + L.off_phi);
   h.efield = (double*)(arena + L.off_ef);
@@ -388,27 +382,8 @@ int blocks_for(const edp_ctx* ctx, int64_t n) {
   return (int)b;
 }
 
-// Workgroups that apply queued collisions outside a step (all of them on
-// one case).
-int scatter_blocks(const edp_ctx* ctx) { return std::min(ctx->num_cu, kMaxApply); }
-
 // Expected chunks of a species of a case (10% headroom over the estimate).
 int64_t est_chunks(const Case* c, int sp) { return (c->est[sp] + c->est[sp] / 10 + kChunk) / kChunk; }
-
-// Collision workgroups of a case in the head: at least enough for one round
-// (every event list -- one per particle workgroup of the case -- with a
-// group of `lanes` lanes), up to one per 32 chunks of the estimated live
-// slots (at most one per CU) so that short lists spread over the chip, and
-// never more than the lists: a list is taken by one workgroup, so a
-// workgroup beyond the lists would have nothing to do.  `one_round` gives the
-// fewest that take every list in one round.
-int apply_blocks(const edp_ctx* ctx, const Case* c, int lists, int lanes, bool one_round = false) {
-  const int64_t chunks = (std::max(c->est[0], c->est[1]) + kChunk - 1) / kChunk;
-  const int64_t spread = std::min<int64_t>(ctx->num_cu, (chunks + 31) / 32);
-  const int64_t round = (lists + (256 / lanes) - 1) / (256 / lanes);
-  const int64_t want = one_round ? round : std::min<int64_t>(std::max(spread, round), lists);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxApply, want));
-}
 
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
 int upload_volt(Case* c, int64_t s0, int64_t s1, hipStream_t st) {
@@ -441,12 +416,6 @@ int request_estimate(Case* c, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(c->est_pinned, (char*)c->d + offsetof(CaseDev, alloc), 16, hipMemcpyDeviceToHost, st));
   HIPCHK(hipEventRecord(c->est_ev, st));
   c->est_pending = true;
-  return EDP_OK;
-}
-
-// Apply the collisions still queued by the last step (before reading state).
-int drain(edp_ctx* ctx, Case* c) {
-  HIPCHK(launch_drain(c->d, scatter_blocks(ctx), ctx->stream));
   return EDP_OK;
 }
 
@@ -522,7 +491,8 @@ int reset_groups(edp_ctx* ctx) {
 
 // Workgroup j of n of case c in a batched launch.
 BlockRole role(const Case* c, int j, int n) {
-  return BlockRole{c->d, c->h.efield, j, n, (int32_t)c->desc.n_grid, 0};
+  return BlockRole{c->d, c->h.cnt_e, c->h.cnt_i, c->h.volt, c->step, j, n, (int32_t)c->desc.n_grid,
+                   (int32_t)c->desc.ion_subcycle};
 }
 
 // Workgroups of a case's sort histogram and scatter.
@@ -546,7 +516,7 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
       lds[sp] = std::max(lds[sp], particle_lds_bytes(c->desc.n_grid, c->desc.flags, c->desc.n_eepf, c->desc.n_ifed, sp));
     max_ng = std::max(max_ng, (int)c->desc.n_grid);
   }
-  std::vector<int> want[2], want_apply(nc);
+  std::vector<int> want[2];
   for (int sp = 0; sp < 2; ++sp) {
     const int occ = particle_occupancy(sp, lds[sp]);
     const int per_cu = ctx->part_wg_per_cu > 0 ? std::min(ctx->part_wg_per_cu, occ) : occ;
@@ -558,24 +528,12 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
     for (size_t k = 0; k < nc; ++k)
       want[sp][k] = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxPartWG, (est_chunks(cs[k], sp) + per - 1) / per));
   }
-  // the head's workgroups should all be resident at once (a second round of
-  // collision workgroups would wait for the first): if the spread ones do
-  // not fit, each case gets the fewest that take its lists in one round
-  int64_t head_total = 2 * (int64_t)nc;
-  for (size_t k = 0; k < nc; ++k) {
-    want_apply[k] = apply_blocks(ctx, cs[k], std::max(want[0][k], want[1][k]), ctx->apply_lanes);
-    head_total += want_apply[k];
-  }
-  if (head_total > (int64_t)ctx->num_cu * head_occupancy(max_ng))
-    for (size_t k = 0; k < nc; ++k)
-      want_apply[k] = apply_blocks(ctx, cs[k], std::max(want[0][k], want[1][k]), ctx->apply_lanes, true);
   std::vector<int> want_sort[2];
   for (int sp = 0; sp < 2; ++sp)
     for (size_t k = 0; k < nc; ++k) want_sort[sp].push_back(sort_blocks(ctx, cs[k], sp));
   auto near = [](int a, int a0) { return a <= a0 * 5 / 4 + 1 && a >= a0 * 3 / 4; };
   bool same = G.valid && B.cases == cs;
   for (size_t k = 0; k < nc && same; ++k) {
-    same = near(want_apply[k], B.h.apply_off[k + 1] - B.h.apply_off[k]);
     for (int sp = 0; sp < 2 && same; ++sp) same = near(want[sp][k], B.h.part_off[sp][k + 1] - B.h.part_off[sp][k]);
     for (int sp = 0; sp < 2 && same; ++sp) same = near(want_sort[sp][k], B.h.sort_off[sp][k + 1] - B.h.sort_off[sp][k]);
   }
@@ -591,17 +549,15 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
   B.lds[1] = lds[1];
   for (size_t k = 0; k < nc; ++k) {
     for (int sp = 0; sp < 2; ++sp) B.h.part_off[sp][k + 1] = B.h.part_off[sp][k] + want[sp][k];
-    B.h.apply_off[k + 1] = B.h.apply_off[k] + want_apply[k];
     for (int sp = 0; sp < 2; ++sp) B.h.sort_off[sp][k + 1] = B.h.sort_off[sp][k] + want_sort[sp][k];
   }
   B.parts[0] = B.h.part_off[0][nc];
   B.parts[1] = B.h.part_off[1][nc];
-  B.apply = B.h.apply_off[nc];
   B.sorts[0] = B.h.sort_off[0][nc];
   B.sorts[1] = B.h.sort_off[1][nc];
-  // roles: electrons, ions, then the head (fields, collisions, totals)
+  // roles: electrons, ions, one per case, electron sort, ion sort
   std::vector<BlockRole> roles;
-  roles.reserve((size_t)B.parts[0] + B.parts[1] + B.apply + 2 * nc + B.sorts[0] + B.sorts[1]);
+  roles.reserve((size_t)B.parts[0] + B.parts[1] + nc + B.sorts[0] + B.sorts[1]);
   for (int sp = 0; sp < 2; ++sp) {
     B.role_off[sp] = roles.size();
     for (size_t k = 0; k < nc; ++k)
@@ -609,14 +565,12 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
   }
   B.role_off[2] = roles.size();
   for (size_t k = 0; k < nc; ++k) roles.push_back(role(cs[k], 0, 1));
-  for (size_t k = 0; k < nc; ++k)
-    for (int j = 0; j < want_apply[k]; ++j) roles.push_back(role(cs[k], j, want_apply[k]));
-  for (size_t k = 0; k < nc; ++k) roles.push_back(role(cs[k], 0, 1));
   for (int sp = 0; sp < 2; ++sp) {
     B.role_off[3 + sp] = roles.size();
     for (size_t k = 0; k < nc; ++k)
       for (int j = 0; j < want_sort[sp][k]; ++j) roles.push_back(role(cs[k], j, want_sort[sp][k]));
   }
+  B.nroles = roles.size();
   if (roles.size() > G.roles_cap && G.fixed)
     return fail(EDP_EINVAL, "the batch needs %zu workgroup roles; the allocation-free advance holds at most %d",
                 roles.size(), kScratchRoles);
@@ -638,14 +592,12 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
 }
 
 // Step j of the current window (case k at step s[k] + j), plain launches:
-// one head for every case (fields of this step, collisions of the last),
 // the compaction/sort of the cases due for it, then one electron launch and,
 // when some case has an ion step, one ion launch.
 int enqueue_batch_step(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, int64_t j, bool capture) {
   Batch& B = G.batch;
   hipStream_t st = G.stream;
   const int nc = (int)B.cases.size();
-  HIPCHK(launch_head(G.roles_d + B.role_off[2], nc, B.apply, B.max_ng, ctx->poisson, ctx->apply_lanes, st));
   bool any_ion = false, sort_e = false, sort_i = false;
   for (int k = 0; k < nc; ++k) {
     const int64_t sk = s[k] + j;
@@ -657,22 +609,41 @@ int enqueue_batch_step(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, in
   // one set of sort launches per species for the whole batch; the cases that
   // are not due skip them on the device
   const BlockRole* case_roles = G.roles_d + B.role_off[2];
+  const int dj = (int)j;
   if (sort_e)
-    HIPCHK(launch_sort(G.roles_d + B.role_off[3], case_roles, 0, B.sorts[0], nc, B.max_ng, ctx->sort_every, st));
+    HIPCHK(launch_sort(G.roles_d + B.role_off[3], case_roles, 0, B.sorts[0], nc, B.max_ng, ctx->sort_every, dj, st));
   if (sort_i)
-    HIPCHK(launch_sort(G.roles_d + B.role_off[4], case_roles, 1, B.sorts[1], nc, B.max_ng, ctx->sort_every, st));
+    HIPCHK(launch_sort(G.roles_d + B.role_off[4], case_roles, 1, B.sorts[1], nc, B.max_ng, ctx->sort_every, dj, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profile && !capture && !G.fixed) {
     const int r = take_event_pair(ctx, e0, e1);
     if (r) return r;
   }
-  HIPCHK(launch_particles(G.roles_d + B.role_off[0], 0, B.parts[0], B.lds[0], st, e0, e1));
+  HIPCHK(launch_particles(G.roles_d + B.role_off[0], 0, B.parts[0], B.lds[0], ctx->poisson, dj, st, e0, e1));
   if (e0) ctx->ev_pairs.emplace_back(e0, e1);
-  if (any_ion) HIPCHK(launch_particles(G.roles_d + B.role_off[1], 1, B.parts[1], B.lds[1], st, nullptr, nullptr));
+  if (any_ion)
+    HIPCHK(launch_particles(G.roles_d + B.role_off[1], 1, B.parts[1], B.lds[1], ctx->poisson, dj, st, nullptr, nullptr));
   return EDP_OK;
 }
 
-// Capture `steps` batch steps from the cases' current steps into a graph.
+// A window of `steps` steps of the group from the cases' steps s: the
+// window's first kernel (roles' steps, slot-count rings), the steps, its
+// last kernel (counters, steps, slot counts).
+int enqueue_window(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, int64_t steps, bool capture) {
+  Batch& B = G.batch;
+  const int nc = (int)B.cases.size();
+  const BlockRole* case_roles = G.roles_d + B.role_off[2];
+  HIPCHK(launch_window_begin(G.roles_d, (int)B.nroles, case_roles, nc, G.stream));
+  for (int64_t j = 0; j < steps; ++j) {
+    const int r = enqueue_batch_step(ctx, G, s, j, capture);
+    if (r) return r;
+  }
+  HIPCHK(launch_window_end(case_roles, nc, (int)steps, G.stream));
+  return EDP_OK;
+}
+
+// Capture one window of `steps` batch steps from the cases' current steps
+// into a graph.
 int build_graph(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, int steps) {
   Batch& B = G.batch;
   drop_graph(G);
@@ -682,8 +653,7 @@ int build_graph(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, int steps
   hipStream_t st = G.stream;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  int r = EDP_OK;
-  for (int j = 0; j < steps && r == EDP_OK; ++j) r = enqueue_batch_step(ctx, G, s, j, true);
+  const int r = enqueue_window(ctx, G, s, steps, true);
   const hipError_t ec = hipStreamEndCapture(st, &g);
   if (r) {
     if (g) (void)hipGraphDestroy(g);
@@ -750,9 +720,12 @@ int group_window(edp_ctx* ctx, Group& G, const std::vector<Case*>& cases, std::v
       j += gsteps;
       continue;
     }
-    r = enqueue_batch_step(ctx, G, s, j, false);
+    // plain launches: the rest of the window as one window of its own
+    std::vector<int64_t> sj(s);
+    for (auto& v : sj) v += j;
+    r = enqueue_window(ctx, G, sj, w - j, false);
     if (r) return r;
-    ++j;
+    j = w;
   }
   for (size_t k = 0, a = 0; k < cases.size(); ++k) {
     if (left[k] <= 0) continue;
@@ -1285,7 +1258,6 @@ int edp_case_resize(edp_ctx* ctx, edp_case id, int64_t cap_e, int64_t cap_i, voi
   HIPCHK(hipSetDevice(ctx->device));
   // the batch tables and graphs hold the old control block's address
   if ((r = reset_groups(ctx))) return r;
-  if ((r = drain(ctx, c))) return r;  // no collision queue left pending
   CaseDev t;
   if ((r = read_dyn(ctx, c, t))) return r;
   int64_t live[2];
@@ -1421,10 +1393,8 @@ int edp_read_counts(edp_ctx* ctx, edp_case id, edp_counts* out) {
   if (!ctx || !out) return fail(EDP_EINVAL, "null argument");
   Case* c = find(ctx, id);
   if (!c) return fail(EDP_EINVAL, "unknown case");
-  int r = drain(ctx, c);
-  if (r) return r;
   CaseDev t;
-  r = read_dyn(ctx, c, t);
+  int r = read_dyn(ctx, c, t);
   if (r) return r;
   out->n_e = t.ctr[kLiveE];
   out->n_i = t.ctr[kLiveI];
@@ -1803,10 +1773,8 @@ int edp_get_state(edp_ctx* ctx, edp_case id, int32_t species, double* x, double*
                   double* vz, uint64_t* uid, int64_t cap, int64_t* n_out) {
   Case* c = ctx ? find(ctx, id) : nullptr;
   if (!c || (species != 0 && species != 1) || cap < 0) return fail(EDP_EINVAL, "bad argument");
-  int r = drain(ctx, c);
-  if (r) return r;
   CaseDev t;
-  r = read_dyn(ctx, c, t);
+  int r = read_dyn(ctx, c, t);
   if (r) return r;
   const int64_t n = t.alloc[species] < c->h.sp[species].cap ? t.alloc[species] : c->h.sp[species].cap;
   const int set = t.cur[species];
@@ -1851,11 +1819,9 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
     if (!std::isfinite(vx[i]) || !std::isfinite(vy[i]) || !std::isfinite(vz[i]))
       return fail(EDP_EINVAL, "particle %lld has a non-finite velocity", (long long)i);
   }
-  // the other species keeps its state: finish its pending collisions first
-  int r = drain(ctx, c);
-  if (r) return r;
+  // the other species keeps its state
   CaseDev t;
-  r = read_dyn(ctx, c, t);
+  int r = read_dyn(ctx, c, t);
   if (r) return r;
   if (n > 0) {
     HIPCHK(hipMemcpy(S.x[0], x, n * 8, hipMemcpyHostToDevice));
@@ -1881,7 +1847,6 @@ int edp_set_state(edp_ctx* ctx, edp_case id, int32_t species, const double* x, c
   t.error = 0;
   t.diag_steps = 0;
   t.diag_ion_steps = 0;
-  t.q_valid = 0;  // nothing pending
   if ((r = write_dyn(ctx, c, t))) return r;
   c->step = step;
   c->est[species] = n;
@@ -1927,10 +1892,6 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
     case EDP_OPT_POISSON:
       if (value < 0 || value > 1) return fail(EDP_EINVAL, "poisson solver must be 0 or 1");
       ctx->poisson = (int)value;
-      break;
-    case EDP_OPT_APPLY_LANES:
-      if (value != 16 && value != 32 && value != 64) return fail(EDP_EINVAL, "lanes per event list must be 16, 32 or 64");
-      ctx->apply_lanes = (int)value;
       break;
     case EDP_OPT_PART_WG_PER_CU:
       if (value < 0 || value > 64) return fail(EDP_EINVAL, "workgroups per CU must be 0..64");

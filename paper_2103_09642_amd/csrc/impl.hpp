@@ -1,9 +1,9 @@
 // Internal layout shared by the HIP kernels and the host runtime of the
 // library.  One CaseDev block per discharge case lives in the case's device
-// arena; kernels take a pointer to it and read every constant, array pointer
-// and dynamic counter from there, so launch arguments never change and whole
-// step sequences can be captured into a hipGraph or run by one persistent
-// launch.
+// arena; kernels reach it through their workgroup's role and read every
+// constant, array pointer and dynamic counter from there.  A launch's only
+// other argument is the offset of its step in the window, so a window of
+// steps can be captured into a hipGraph once and replayed.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -121,45 +121,56 @@ struct CaseDev {
   int64_t* ifed;                      // [2][n_ifed + 1] impacts per energy bin
   int64_t *eepf;                                              // [n_eepf]
   int64_t *sort_cnt;                                          // [ng + 1] scratch
-  // Collision queue of the last particle step, per species: particle
-  // workgroup j (chunks [j*per, (j+1)*per)) writes its events to
-  // cq_ent[j*per*kChunk + k], each slot | process << 32 | birth rank << 34,
-  // and its totals to q_wg[j] = {events, births, absorbed at x=0, absorbed
-  // at x=L}.
-  int64_t* cq_ent[2];
-  int32_t* q_wg[2];  // [kMaxPartWG][4]
+  // Step totals of the lockstep particle workgroups, [2][kShards][kRec]:
+  // workgroup j of a species adds its totals to shard j % kShards (few
+  // workgroups share an address); the window-end kernel folds the shards
+  // into the counters and clears them.
+  int64_t* shard;
+  // Colliders a particle workgroup's streaming loop found, per species
+  // [cap]: workgroup j writes slot | process << 32 into its own chunk range
+  // and applies them after the loop.
+  int64_t* clist[2];
   // ---- dynamic (device-mutated) -----------------------------------------
-  int64_t step;       // next step whose head runs (advanced by the electron kernel)
-  int64_t pstep;      // step of the particle kernels (set by the head)
-  int64_t n[2];       // slots the particle kernels process
-  int64_t alloc[2];   // slots in use: live + tombstones (equal to n between kernels)
+  int64_t step;       // next step to run (advanced at the end of a window)
+  int64_t n[2];       // slots in use (live + tombstones) at `step`, between windows
+  int64_t alloc[2];   // the same (kept for the host's asynchronous size estimate)
   int32_t cur[2];     // current buffer set per species
-  // the pending collision queue: written by the particle kernels of step
-  // q_step, applied by the next head (or a drain)
-  int64_t q_step;
-  int64_t q_base[2];  // slot count of that step: births go to q_base + rank
-  int64_t q_per[2];   // chunks per particle workgroup in that step
-  int32_t q_nblk[2];  // chunks that wrote records (0: no events of that species)
-  int32_t q_valid;    // 1 while not yet applied by a drain
-  int32_t pad2;
+  // Slot counts inside a window: the slots at the start of step s are
+  // min(nbase[sp][(s+2)%3] + born[sp][(s+2)%3], cap) -- the slots at the start
+  // of step s-1 and the births that step placed.  Newborns of step s take
+  // slots nbase + born[sp][s%3]++ (so a step's loops never see its own
+  // newborns); step s stores its own count in nbase[sp][s%3] and clears
+  // born[sp][(s+1)%3] for the next step.
+  int64_t nbase[2][3];
+  int64_t born[2][3];
   int64_t diag_steps, diag_ion_steps;
   int64_t ctr[kNumCtr];
   int32_t error;      // 1: capacity overflow
   int32_t phi_valid;  // 1: phi[] holds the potential of the last step, 0: use flux[]
 };
 
+// Fields of a particle workgroup's step totals (one shard record).
+enum Rec { kRecColl = 0, kRecIoniz, kRecAbsPow, kRecAbsGnd, kRecLive, kRecBornE, kRecBornI, kRecDropped, kRec };
+constexpr int kShards = 64;
+
 // A batch of cases stepped together: every launch advances each case by one
 // step.  Each workgroup of a batched launch reads its role from a table the
-// host builds with the batch -- its case, its index among that case's
-// workgroups of the same kind and their number, and the case's field array
-// and node count, so that a particle workgroup's E loads need not wait for
-// the case block -- in one scalar load.
+// host builds with the batch -- its case, the case's deposit rings and V(t)
+// ring, the case's step at the start of the window (refreshed on the device
+// by the window's first kernel), its index among that case's workgroups of
+// the same kind and their number, and the case's node count and ion
+// subcycle -- in one scalar load, so that its first loads of the deposit
+// need not wait for the case block.  A launch of a window gets its step
+// offset as an argument: step = step0 + dstep.
 constexpr int kMaxBatch = 256;
 struct BlockRole {
   CaseDev* c;
-  const double* efield;
+  const int64_t* cnt_e;  // [3][ng] electron deposit rings
+  const int64_t* cnt_i;  // [3][ng] ion deposit rings
+  const double* volt;    // V(t_s) ring
+  int64_t step0;
   int32_t j, n;
-  int32_t ng, pad;
+  int32_t ng, nsub;
 };
 
 }  // namespace edp

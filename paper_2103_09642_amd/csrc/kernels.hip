@@ -1,15 +1,15 @@
 // HIP kernels of the PIC/MCC time step for gfx950.
 //
-// One step s of a case (section 2.1; Algorithms 2-6):
-//   k_head       workgroup 0: fixed-point densities -> rho -> the discrete
-//                Poisson equation -> grid field E; the other workgroups
-//                finish the collisions of step s-1 (new velocities).
-//   k_particles  every particle of a species: gather E, leapfrog push, wall
-//                absorption, the collision test and process selection with
-//                ionization births, and the deposit of the new position for
-//                step s+1 -- fused, so each particle's state is streamed
-//                from HBM once per step.
-// Ions run k_particles only on steps with s % N_SUB == 0 (ion subcycling).
+// One step s of a case (section 2.1; Algorithms 2-6) is one launch per
+// species (ions only on steps with s % N_SUB == 0: ion subcycling).  Every
+// workgroup of k_particles first solves the field of step s from the
+// fixed-point densities into its own LDS (steps 1-2: rho, the discrete
+// Poisson equation, E on the nodes) and then streams its share of the
+// particles: gather E, leapfrog push, wall absorption, the collision test,
+// the colliders' scattering and the ionization births, and the deposit of
+// the new position for step s+1 -- fused, so each particle's state is
+// streamed from HBM once per step and no launch sits between two steps'
+// particle passes.
 //
 // Deposits are int64 fixed point (2^32 units per particle), privatised in
 // LDS per workgroup and flushed with one global atomic per touched node;
@@ -229,26 +229,20 @@ __device__ __forceinline__ T block_exclusive_scan_t(T x, int64_t* scratch, T* to
 }
 
 // ---------------------------------------------------------------------------
-// Step 2: density -> rho -> potential -> field, one workgroup per case.
-// MODE 0 (default) solves the discrete Poisson equation through the fluxes
-// F_q = phi_q - phi_{q+1}: each row of the equation says F_p - F_{p-1} = d_p
-// with d_p = rho_p dx^2/eps0, so F_p = F_0 + S_p with S_p the prefix sum of
-// d, and the fluxes add up to phi_0 - phi_{N-1} = V, which fixes
-// F_0 = (V - sum_p S_p)/(N_g - 1).  The field follows from the fluxes
-// without forming phi: E_p = (F_{p-1} + F_p)/(2 dx) inside, and the boundary
-// forms use F_0 and F_{N_g-2}.  This is the same linear system as the Thomas
-// algorithm solves, in parallel (two wave scans instead of 2 N_g dependent
-// steps); it agrees with an 80-bit solution to ~1e-15 of the field scale,
-// closer than the sequential sweep.
-// MODE 1 runs the Thomas algorithm itself in one thread, operation for
-// operation as the sequential definition (bit-reproducible, slow).
+// Steps 1-2: density -> rho -> potential -> field.  MODE 0 (default)
+// solves the discrete Poisson equation through the fluxes between nodes, in
+// parallel (two workgroup scans instead of 2 N_g dependent steps); it agrees
+// with an 80-bit solution to ~1e-15 of the field scale, closer than the
+// sequential sweep.  MODE 1 runs the Thomas algorithm itself in one thread,
+// operation for operation as the sequential definition (bit-reproducible,
+// slow).
 // ---------------------------------------------------------------------------
 constexpr int kWave = 64;
 
 // Fold the per-step particle sums of one node (ring slot `fold`, the step
 // before the one about to run) into the time sums and, with the xt arrays,
 // into time-bin row `row_prev`; the power density j E takes the field that
-// step used, still in efield[] (it is overwritten later in the same thread).
+// step used, still in efield[] (the caller overwrites it after a barrier).
 __device__ __forceinline__ void fold_particle_sums(const EDP_CONST CaseDev* __restrict__ C, int p,
                                                    int64_t fold, size_t row_prev, size_t plane) {
   const uint32_t fl = C->flags;
@@ -291,249 +285,74 @@ __device__ __forceinline__ void fold_particle_sums(const EDP_CONST CaseDev* __re
   }
 }
 
-// Interior rows per lane of the flux scan at the largest grid.
-constexpr int kScanRows = (kMaxNodes - 2 + kWave - 1) / kWave;
+// Rows of the flux scan per thread at the largest grid.
+constexpr int kScanRows = (kMaxNodes - 2 + kBlock - 1) / kBlock;
 
+// Steps 1-2 of step s, computed by every workgroup that needs E (each
+// particle workgroup of a lockstep launch, the small-case workgroup): the
+// densities of the deposit rings read at step s, rho, the potential and E on
+// the nodes into sE (LDS).  sF: ng doubles of LDS scratch.  The ring and V(t)
+// pointers come with the workgroup's role.  The results depend only on the
+// deposit, so every workgroup gets the same bits.  The writer (one workgroup
+// per case and step) also stores rho, E and the fluxes (or phi) for reads,
+// clears the deposit rings the next steps refill, adds the measurement sums
+// and counts the step.
 template <int MODE>
-__device__ __forceinline__ void field_solve(CaseDev* __restrict__ Cw, double* fsm) {
+__device__ __forceinline__ void solve_field(CaseDev* __restrict__ Cw, const int64_t* __restrict__ cnt_e,
+                                            const int64_t* __restrict__ cnt_i, const double* __restrict__ volt,
+                                            const int ng, const int nsub, const int64_t s, double* sE, double* sF,
+                                            const bool writer) {
+  __shared__ int64_t sRed[64];
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
-  const int ng = C->ng;
-  // LDS rows padded by one slot per 16 nodes (node p at lp(p)): the flux
-  // scan's lanes own 16-node blocks, which would otherwise fall on the same
-  // banks
-  const int np = ng + (ng >> 4) + 1;
-  auto lp = [](int p) { return p + (p >> 4); };
-  double* sRho = fsm;
-  double* sPhi = fsm + np;    // MODE 1: d then phi; MODE 0: S_p then fluxes F_q
-  double* sR = fsm + 2 * np;  // MODE 1: Thomas reciprocals
-  const int64_t s = C->step;
-  const int nsub = C->nsub;
   const int64_t k = s / nsub;
   const bool ion_step = (s % nsub) == 0;
-  const uint32_t fl = C->flags;
-  const EDP_GLOBAL int64_t* cntE = G(C->cnt_e + (s % 3) * ng);
-  const EDP_GLOBAL int64_t* cntI = G(C->cnt_i + (k % 3) * ng);
-  EDP_GLOBAL int64_t* zeroE = G(C->cnt_e + ((s + 2) % 3) * ng);
-  EDP_GLOBAL int64_t* zeroI = G(C->cnt_i + ((k + 2) % 3) * ng);
-  const int64_t fold = ((s + 2) % 3) * ng;  // per-step sums of step s-1
-  const double scale = C->dens_scale;
-  const double V = G(C->volt)[s % kVoltChunk];
-  // xt rows: this step's grid values go to its time bin, the particle sums
-  // of step s-1 to the bin of s-1
-  const bool xt = (fl & kDiagXT) != 0;
-  const int64_t nt = C->nt, nxb = C->n_xt_bin;
-  const size_t plane = (size_t)C->n_xt * (size_t)ng;
-  const size_t row = xt ? (size_t)((s % nt) / nxb) * (size_t)ng : 0;
-  const size_t row_prev = xt ? (size_t)(((s + nt - 1) % nt) / nxb) * (size_t)ng : 0;
-  EDP_GLOBAL double* __restrict__ X = G(C->xt);
-  // every load of the thread's nodes before any store (one memory round trip)
+  const EDP_GLOBAL int64_t* cntE = G(cnt_e) + (s % 3) * ng;
+  const EDP_GLOBAL int64_t* cntI = G(cnt_i) + (k % 3) * ng;
+  const int t = (int)threadIdx.x;
+  // every load of the thread's nodes first (one memory round trip)
   int64_t ce[kGridPerThread], ci[kGridPerThread];
 #pragma unroll
-  for (int j = 0; j < kGridPerThread; ++j) {
-    const int p = threadIdx.x + j * kBlock;
-    ce[j] = p < ng ? cntE[p] : 0;
-    ci[j] = p < ng ? cntI[p] : 0;
+  for (int q = 0; q < kGridPerThread; ++q) {
+    const int p = t + q * kBlock;
+    ce[q] = p < ng ? cntE[p] : 0;
+    ci[q] = p < ng ? cntI[p] : 0;
   }
-#pragma unroll
-  for (int j = 0; j < kGridPerThread; ++j) {
-    const int p = threadIdx.x + j * kBlock;
-    if (p >= ng) break;
-    double ne = (double)ce[j] * scale;
-    double ni = (double)ci[j] * scale;
-    if (p == 0 || p == ng - 1) {
-      ne *= 2.0;
-      ni *= 2.0;
-    }
-    const double rho = kECharge * (ni - ne);
-    sRho[lp(p)] = rho;
-    if (MODE == 1) {
-      sR[lp(p)] = G(C->rden)[p];
-      sPhi[lp(p)] = rho * C->kpois;  // right-hand side d_p (boundary term below)
-    }
-    if (fl & kDiagDensity) {
-      G(C->sum_ne)[p] += ne;
-      G(C->sum_ni)[p] += ni;
-    }
-    zeroE[p] = 0;
-    if (ion_step) zeroI[p] = 0;
-    if (fl & (kDiagCurrent | kDiagMeanE | kDiagXT)) fold_particle_sums(C, p, fold, row_prev, plane);
-    if (xt) {
-      X[kXtNe * plane + row + p] += ne;
-      X[kXtNi * plane + row + p] += ni;
-    }
-  }
-  __syncthreads();
-  const double dx = C->dx;
-  if (MODE == 1) {
-    if (threadIdx.x == 0) {
-      // Thomas algorithm: forward sweep y_p = (d_p + y_{p-1}) r_p, back
-      // substitution phi_p = y_p + r_p phi_{p+1}.
-      const int m = ng - 2;
-      double prev = 0.0;
-      for (int p = 1; p <= m; ++p) {
-        double d = sPhi[lp(p)];
-        if (p == 1) d = d + V;
-        prev = (d + prev) * sR[lp(p)];
-        sPhi[lp(p)] = prev;
-      }
-      for (int p = m - 1; p >= 1; --p) sPhi[lp(p)] = sPhi[lp(p)] + sR[lp(p)] * sPhi[lp(p + 1)];
-      sPhi[lp(0)] = V;
-      sPhi[lp(ng - 1)] = 0.0;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-      double e;
-      if (p == 0)
-        e = (sPhi[lp(0)] - sPhi[lp(1)]) / dx - sRho[lp(0)] * dx / (2.0 * kEps0);
-      else if (p == ng - 1)
-        e = (sPhi[lp(ng - 2)] - sPhi[lp(ng - 1)]) / dx + sRho[lp(ng - 1)] * dx / (2.0 * kEps0);
-      else
-        e = (sPhi[lp(p - 1)] - sPhi[lp(p + 1)]) / (2.0 * dx);
-      G(C->efield)[p] = e;
-      G(C->phi)[p] = sPhi[lp(p)];
-      G(C->rho)[p] = sRho[lp(p)];
-      if (xt) {
-        X[kXtEf * plane + row + p] += e;
-        X[kXtFlux * plane + row + p] += p < ng - 1 ? sPhi[lp(p)] - sPhi[lp(p + 1)] : V;
-      }
-    }
-  } else {
-    // One wave does the two scans (no workgroup barriers in between): lane l
-    // owns the contiguous rows q0 <= q < q1 of the m = N_g - 2 interior rows
-    // (row q is node q+1), and node q+1's slot becomes F_{q+1}.  A lane's
-    // rows stay in registers between one batch of LDS loads and one of
-    // stores.
-    if (threadIdx.x < kWave) {
-      const int lane = (int)threadIdx.x;
-      const int m = ng - 2;
-      const double kp = C->kpois;
-      const int R = (m + kWave - 1) / kWave;  // <= kScanRows
-      const int q0 = lane * R < m ? lane * R : m;
-      const int nq = (q0 + R < m ? q0 + R : m) - q0;
-      double v[kScanRows];
-#pragma unroll
-      for (int t = 0; t < kScanRows; ++t) v[t] = t < nq ? sRho[lp(q0 + t + 1)] : 0.0;
-      double acc = 0.0;
-#pragma unroll
-      for (int t = 0; t < kScanRows; ++t) {
-        if (t < nq) acc += v[t] * kp;
-        v[t] = acc;  // prefix within the lane
-      }
-      double inc = acc;
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-        const double y = __shfl_up(inc, off, kWave);
-        if (lane >= off) inc += y;
-      }
-      const double before = inc - acc;
-      double mine = 0.0;
-#pragma unroll
-      for (int t = 0; t < kScanRows; ++t) {
-        v[t] = before + v[t];  // S_q
-        if (t < nq) mine += v[t];
-      }
-      for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
-      const double F0 = (V - mine) / (double)(ng - 1);
-#pragma unroll
-      for (int t = 0; t < kScanRows; ++t)
-        if (t < nq) sPhi[lp(q0 + t + 1)] = F0 + v[t];
-      if (lane == 0) sPhi[lp(0)] = F0;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-      double e;
-      if (p == 0)
-        e = sPhi[lp(0)] / dx - sRho[lp(0)] * dx / (2.0 * kEps0);
-      else if (p == ng - 1)
-        e = sPhi[lp(ng - 2)] / dx + sRho[lp(ng - 1)] * dx / (2.0 * kEps0);
-      else
-        e = (sPhi[lp(p - 1)] + sPhi[lp(p)]) / (2.0 * dx);
-      G(C->efield)[p] = e;
-      const double f = p < ng - 1 ? sPhi[lp(p)] : V;  // last slot keeps V for phi on demand
-      G(C->flux)[p] = f;
-      G(C->rho)[p] = sRho[lp(p)];
-      if (xt) {
-        X[kXtEf * plane + row + p] += e;
-        X[kXtFlux * plane + row + p] += f;
-      }
-    }
-  }
-  if (threadIdx.x == 0) {
-    if (xt) {
-      G(C->xt_cnt)[row / ng] += 1;
-      if (ion_step) G(C->xt_cnt)[C->n_xt + row / ng] += 1;
-    }
-    Cw->phi_valid = MODE == 1;
-    Cw->pstep = s;  // the particle kernels of this step read it
-  }
-}
-
-// The same solve for a workgroup that keeps E of step s in its own LDS (sE)
-// instead of handing it to other launches, with the step given: the
-// persistent small-case kernel below, where the step changes inside the
-// launch.  fsm: two padded rows of scratch.  The writer also stores rho, E
-// and the fluxes (or phi) for reads, clears the deposit rings the next steps
-// refill, folds the per-step diagnostics and counts the step.
-template <int MODE>
-__device__ __forceinline__ void field_to_lds(CaseDev* __restrict__ Cw, double* sE, double* fsm, const bool writer,
-                                             const int64_t s) {
-  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
-  const int ng = C->ng;
-  // LDS rows padded by one slot per 16 nodes (node p at lp(p)): the flux
-  // scan's lanes own 16-node blocks, which would otherwise fall on the same
-  // banks
-  const int np = ng + (ng >> 4) + 1;
-  auto lp = [](int p) { return p + (p >> 4); };
-  double* sRho = fsm;
-  double* sPhi = fsm + np;  // MODE 1: d then phi; MODE 0: S_p then fluxes F_q
-  const int nsub = C->nsub;
-  const int64_t k = s / nsub;
-  const bool ion_step = (s % nsub) == 0;
-  const uint32_t fl = C->flags;
-  const EDP_GLOBAL int64_t* cntE = G(C->cnt_e + (s % 3) * ng);
-  const EDP_GLOBAL int64_t* cntI = G(C->cnt_i + (k % 3) * ng);
-  EDP_GLOBAL int64_t* zeroE = G(C->cnt_e + ((s + 2) % 3) * ng);
-  EDP_GLOBAL int64_t* zeroI = G(C->cnt_i + ((k + 2) % 3) * ng);
-  const int64_t fold = ((s + 2) % 3) * ng;  // per-step sums of step s-1
+  const double V = G(volt)[s % kVoltChunk];
   const double scale = C->dens_scale;
-  const double V = G(C->volt)[s % kVoltChunk];
-  // xt rows: this step's grid values go to its time bin, the particle sums
-  // of step s-1 to the bin of s-1
+  const double kp = C->kpois;
+  const uint32_t fl = C->flags;
   const bool xt = writer && (fl & kDiagXT) != 0;
   const int64_t nt = C->nt, nxb = C->n_xt_bin;
   const size_t plane = (size_t)C->n_xt * (size_t)ng;
   const size_t row = xt ? (size_t)((s % nt) / nxb) * (size_t)ng : 0;
   const size_t row_prev = xt ? (size_t)(((s + nt - 1) % nt) / nxb) * (size_t)ng : 0;
   EDP_GLOBAL double* __restrict__ X = G(C->xt);
-  // every load of the thread's nodes before any store (one memory round trip)
-  int64_t ce[kGridPerThread], ci[kGridPerThread];
+  // densities (the electrodes' half cells count twice) and rho into sE; for
+  // the Thomas solve also its right-hand side d_p = rho_p dx^2/eps0 into sF
 #pragma unroll
-  for (int j = 0; j < kGridPerThread; ++j) {
-    const int p = threadIdx.x + j * kBlock;
-    ce[j] = p < ng ? cntE[p] : 0;
-    ci[j] = p < ng ? cntI[p] : 0;
-  }
-#pragma unroll
-  for (int j = 0; j < kGridPerThread; ++j) {
-    const int p = threadIdx.x + j * kBlock;
+  for (int q = 0; q < kGridPerThread; ++q) {
+    const int p = t + q * kBlock;
     if (p >= ng) break;
-    double ne = (double)ce[j] * scale;
-    double ni = (double)ci[j] * scale;
+    double ne = (double)ce[q] * scale;
+    double ni = (double)ci[q] * scale;
     if (p == 0 || p == ng - 1) {
       ne *= 2.0;
       ni *= 2.0;
     }
     const double rho = kECharge * (ni - ne);
-    sRho[lp(p)] = rho;
-    if (MODE == 1) sPhi[lp(p)] = rho * C->kpois;  // right-hand side d_p (boundary term below)
+    sE[p] = rho;
+    if (MODE == 1) sF[p] = rho * kp;
     if (writer) {
+      G(C->rho)[p] = rho;
       if (fl & kDiagDensity) {
         G(C->sum_ne)[p] += ne;
         G(C->sum_ni)[p] += ni;
       }
-      zeroE[p] = 0;
-      if (ion_step) zeroI[p] = 0;
-      if (fl & (kDiagCurrent | kDiagMeanE | kDiagXT)) fold_particle_sums(C, p, fold, row_prev, plane);
+      G(C->cnt_e)[((s + 2) % 3) * ng + p] = 0;
+      if (ion_step) G(C->cnt_i)[((k + 2) % 3) * ng + p] = 0;
+      // the particle sums of step s-1, with the field that step used (still
+      // in efield[]; it is overwritten below, after the barriers)
+      if (fl & (kDiagCurrent | kDiagMeanE | kDiagXT)) fold_particle_sums(C, p, ((s + 2) % 3) * ng, row_prev, plane);
       if (xt) {
         X[kXtNe * plane + row + p] += ne;
         X[kXtNi * plane + row + p] += ni;
@@ -541,9 +360,10 @@ __device__ __forceinline__ void field_to_lds(CaseDev* __restrict__ Cw, double* s
     }
   }
   __syncthreads();
+  const double rho0 = sE[0], rhoN = sE[ng - 1];
   const double dx = C->dx;
   if (MODE == 1) {
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       // Thomas algorithm: forward sweep y_p = (d_p + y_{p-1}) r_p, back
       // substitution phi_p = y_p + r_p phi_{p+1}, with the reciprocals r_p
       // precomputed on the host
@@ -551,100 +371,88 @@ __device__ __forceinline__ void field_to_lds(CaseDev* __restrict__ Cw, double* s
       const int m = ng - 2;
       double prev = 0.0;
       for (int p = 1; p <= m; ++p) {
-        double d = sPhi[lp(p)];
+        double d = sF[p];
         if (p == 1) d = d + V;
         prev = (d + prev) * rd[p];
-        sPhi[lp(p)] = prev;
+        sF[p] = prev;
       }
-      for (int p = m - 1; p >= 1; --p) sPhi[lp(p)] = sPhi[lp(p)] + rd[p] * sPhi[lp(p + 1)];
-      sPhi[lp(0)] = V;
-      sPhi[lp(ng - 1)] = 0.0;
+      for (int p = m - 1; p >= 1; --p) sF[p] = sF[p] + rd[p] * sF[p + 1];
+      sF[0] = V;
+      sF[ng - 1] = 0.0;
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-      double e;
-      if (p == 0)
-        e = (sPhi[lp(0)] - sPhi[lp(1)]) / dx - sRho[lp(0)] * dx / (2.0 * kEps0);
-      else if (p == ng - 1)
-        e = (sPhi[lp(ng - 2)] - sPhi[lp(ng - 1)]) / dx + sRho[lp(ng - 1)] * dx / (2.0 * kEps0);
-      else
-        e = (sPhi[lp(p - 1)] - sPhi[lp(p + 1)]) / (2.0 * dx);
-      sE[p] = e;
-      if (writer) {
-        G(C->efield)[p] = e;
-        G(C->phi)[p] = sPhi[lp(p)];
-        G(C->rho)[p] = sRho[lp(p)];
-        if (xt) {
-          X[kXtEf * plane + row + p] += e;
-          X[kXtFlux * plane + row + p] += p < ng - 1 ? sPhi[lp(p)] - sPhi[lp(p + 1)] : V;
-        }
-      }
-    }
   } else {
-    // One wave does the two scans (no workgroup barriers in between): lane l
-    // owns the contiguous rows q0 <= q < q1 of the m = N_g - 2 interior rows
-    // (row q is node q+1), and node q+1's slot becomes F_{q+1}.  A lane's
-    // rows stay in registers between one batch of LDS loads and one of
-    // stores.
-    if (threadIdx.x < kWave) {
-      const int lane = (int)threadIdx.x;
-      const int m = ng - 2;
-      const double kp = C->kpois;
-      const int R = (m + kWave - 1) / kWave;  // <= kScanRows
-      const int q0 = lane * R < m ? lane * R : m;
-      const int nq = (q0 + R < m ? q0 + R : m) - q0;
-      double v[kScanRows];
+    // The flux form of the same tridiagonal system: with F_q = phi_q -
+    // phi_{q+1}, row p of the Poisson equation says F_p - F_{p-1} = d_p, so
+    // F_p = F_0 + S_p with S the prefix sum of d over the interior nodes; the
+    // fluxes add up to phi_0 - phi_{N-1} = V, which fixes
+    // F_0 = (V - sum_p S_p)/(N_g - 1).  Thread t owns the contiguous interior
+    // rows q0 <= q < q0 + nq (row q is node q + 1): a sequential prefix of its
+    // rows, a workgroup scan of the row totals, then the sum of S over the
+    // workgroup.  Slot q + 1 of sF becomes F_{q+1}, slot 0 F_0.
+    const int m = ng - 2;
+    const int R = (m + kBlock - 1) / kBlock;  // <= kScanRows
+    const int q0 = t * R < m ? t * R : m;
+    const int nq = (q0 + R < m ? q0 + R : m) - q0;
+    double v[kScanRows];
+    double acc = 0.0;
 #pragma unroll
-      for (int t = 0; t < kScanRows; ++t) v[t] = t < nq ? sRho[lp(q0 + t + 1)] : 0.0;
-      double acc = 0.0;
-#pragma unroll
-      for (int t = 0; t < kScanRows; ++t) {
-        if (t < nq) acc += v[t] * kp;
-        v[t] = acc;  // prefix within the lane
-      }
-      double inc = acc;
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-        const double y = __shfl_up(inc, off, kWave);
-        if (lane >= off) inc += y;
-      }
-      const double before = inc - acc;
-      double mine = 0.0;
-#pragma unroll
-      for (int t = 0; t < kScanRows; ++t) {
-        v[t] = before + v[t];  // S_q
-        if (t < nq) mine += v[t];
-      }
-      for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
-      const double F0 = (V - mine) / (double)(ng - 1);
-#pragma unroll
-      for (int t = 0; t < kScanRows; ++t)
-        if (t < nq) sPhi[lp(q0 + t + 1)] = F0 + v[t];
-      if (lane == 0) sPhi[lp(0)] = F0;
+    for (int r = 0; r < kScanRows; ++r) {
+      if (r < nq) acc += sE[q0 + r + 1] * kp;
+      v[r] = acc;  // prefix within the thread
     }
+    double tot;
+    const double before = block_exclusive_scan_t<double>(acc, sRed, &tot);
+    double mine = 0.0;
+#pragma unroll
+    for (int r = 0; r < kScanRows; ++r) {
+      v[r] = before + v[r];  // S_q
+      if (r < nq) mine += v[r];
+    }
+    double sum_s;
+    (void)block_exclusive_scan_t<double>(mine, sRed, &sum_s);
+    const double F0 = (V - sum_s) / (double)(ng - 1);
+#pragma unroll
+    for (int r = 0; r < kScanRows; ++r)
+      if (r < nq) sF[q0 + r + 1] = F0 + v[r];
+    if (t == 0) sF[0] = F0;
     __syncthreads();
-    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-      double e;
+  }
+  // E on the nodes: centred differences inside, the boundary forms (Gauss's
+  // law over the half cell) at the electrodes
+  for (int p = t; p < ng; p += kBlock) {
+    double e, f;
+    if (MODE == 1) {
       if (p == 0)
-        e = sPhi[lp(0)] / dx - sRho[lp(0)] * dx / (2.0 * kEps0);
+        e = (sF[0] - sF[1]) / dx - rho0 * dx / (2.0 * kEps0);
       else if (p == ng - 1)
-        e = sPhi[lp(ng - 2)] / dx + sRho[lp(ng - 1)] * dx / (2.0 * kEps0);
+        e = (sF[ng - 2] - sF[ng - 1]) / dx + rhoN * dx / (2.0 * kEps0);
       else
-        e = (sPhi[lp(p - 1)] + sPhi[lp(p)]) / (2.0 * dx);
-      sE[p] = e;
-      if (writer) {
-        G(C->efield)[p] = e;
-        const double f = p < ng - 1 ? sPhi[lp(p)] : V;  // last slot keeps V for phi on demand
+        e = (sF[p - 1] - sF[p + 1]) / (2.0 * dx);
+      f = p < ng - 1 ? sF[p] - sF[p + 1] : V;
+    } else {
+      if (p == 0)
+        e = sF[0] / dx - rho0 * dx / (2.0 * kEps0);
+      else if (p == ng - 1)
+        e = sF[ng - 2] / dx + rhoN * dx / (2.0 * kEps0);
+      else
+        e = (sF[p - 1] + sF[p]) / (2.0 * dx);
+      f = p < ng - 1 ? sF[p] : V;  // last slot keeps V for phi on demand
+    }
+    sE[p] = e;
+    if (writer) {
+      G(C->efield)[p] = e;
+      if (MODE == 1)
+        G(C->phi)[p] = sF[p];
+      else
         G(C->flux)[p] = f;
-        G(C->rho)[p] = sRho[lp(p)];
-        if (xt) {
-          X[kXtEf * plane + row + p] += e;
-          X[kXtFlux * plane + row + p] += f;
-        }
+      if (xt) {
+        X[kXtEf * plane + row + p] += e;
+        X[kXtFlux * plane + row + p] += f;
       }
     }
   }
-  if (writer && threadIdx.x == 0) {
+  if (writer && t == 0) {
     if (xt) {
       G(C->xt_cnt)[row / ng] += 1;
       if (ion_step) G(C->xt_cnt)[C->n_xt + row / ng] += 1;
@@ -653,22 +461,18 @@ __device__ __forceinline__ void field_to_lds(CaseDev* __restrict__ Cw, double* s
     Cw->diag_steps += 1;
     if (ion_step) Cw->diag_ion_steps += 1;
   }
-  __syncthreads();  // sE complete; fsm free again
+  __syncthreads();  // sE complete; sF free again
 }
 
 // ---------------------------------------------------------------------------
-// Collisions (step 6).  The particle kernel tests every particle, picks the
+// Collisions (step 6): the particle kernels test every particle, pick the
 // process of those that collide (partition of [0,1) into sigma_k/sigma_tot),
-// deposits the charge of the particles an ionization creates, and queues the
-// event in its chunk's part of the queue.  The new velocities -- COM
-// kinematics, scattering angles, Euler rotation, the ionization energy
-// split -- and the newborns' slots are computed from the queue by extra
-// workgroups of the next step's field launch (they do not depend on each
-// other), so this long transcendental code runs off the streaming path and
-// overlaps the field solve.
+// and apply it at once -- COM kinematics, scattering angles, Euler rotation,
+// the ionization energy split and the newborns -- in dense passes over the
+// colliders (see species_pass).
 // ---------------------------------------------------------------------------
 
-// Arrays the collision workgroups touch, loaded once per workgroup.
+// Arrays the scattering code touches, loaded once per workgroup.
 struct ScatterPtrs {
   EDP_GLOBAL double *ex, *evx, *evy, *evz, *ix, *ivx, *ivy, *ivz;
   EDP_GLOBAL float* evp2;
@@ -694,17 +498,12 @@ __device__ __forceinline__ ScatterPtrs scatter_ptrs_at(CaseDev* __restrict__ Cw,
   P.iuid = G(C->sp[1].uid[ci]);
   return P;
 }
-__device__ __forceinline__ ScatterPtrs scatter_ptrs(CaseDev* __restrict__ Cw) {
-  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
-  return scatter_ptrs_at(Cw, C->cur[0], C->cur[1]);
-}
 
-// Electron-Ar scattering of queued particle i (state after the push) by
-// process proc (0 elastic, 1 excitation, 2 ionization).  An ionization also
-// writes its newborns: the ejected electron at slot be and the ion at slot
-// bi (-1: dropped at capacity), both at the parent's position.
-// electron_scatter_at takes the particle's state (velocity after the push,
-// identity, position) from the caller; electron_scatter loads it.
+// Electron-Ar scattering of colliding particle i by process proc (0 elastic,
+// 1 excitation, 2 ionization), from its state after the push (velocity,
+// identity; position for an ionization).  An ionization also writes its
+// newborns: the ejected electron at slot be and the ion at slot bi (-1:
+// dropped at capacity), both at the parent's position.
 __device__ __forceinline__ void electron_scatter_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
                                                     int64_t i, int proc, int64_t be, int64_t bi, int64_t s,
                                                     double vxn, double vy, double vz, uint64_t uid, double x) {
@@ -804,12 +603,7 @@ __device__ __forceinline__ void electron_scatter_at(const EDP_CONST CaseDev* __r
   P.evz[i] = oz;
   P.evp2[i] = float_above(oy * oy + oz * oz);
 }
-__device__ __forceinline__ void electron_scatter(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
-                                                 int proc, int64_t be, int64_t bi, int64_t s) {
-  electron_scatter_at(C, P, i, proc, be, bi, s, P.evx[i], P.evy[i], P.evz[i], P.euid[i], proc == 2 ? P.ex[i] : 0.0);
-}
-
-// Ar+ + Ar scattering of queued ion i (proc 0 isotropic, 1 backward) with the
+// Ar+ + Ar scattering of colliding ion i (proc 0 isotropic, 1 backward) with the
 // thermal target of its test (redrawn from the same counter: the same atom).
 __device__ __forceinline__ void ion_scatter_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
                                                int proc, int64_t s, double vxn, double vy, double vz, uint64_t uid) {
@@ -838,12 +632,7 @@ __device__ __forceinline__ void ion_scatter_at(const EDP_CONST CaseDev* __restri
   P.ivy[i] = oy;
   P.ivz[i] = oz;
 }
-__device__ __forceinline__ void ion_scatter(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i, int proc,
-                                            int64_t s) {
-  ion_scatter_at(C, P, i, proc, s, P.ivx[i], P.ivy[i], P.ivz[i], P.iuid[i]);
-}
-
-// Secondary electron of queued ion i, absorbed at electrode `side` (0 at
+// Secondary electron of ion i, absorbed at electrode `side` (0 at
 // x = 0, 1 at x = L): it starts on the surface with the velocity of a thermal
 // flux at T_see -- a Rayleigh normal component into the gap and two normal
 // tangential ones (Box-Muller) -- from purpose 3 of the ion's counter; its
@@ -868,218 +657,18 @@ __device__ __forceinline__ void see_emit_at(const EDP_CONST CaseDev* __restrict_
   P.evp2[be] = float_above(vy * vy + vz * vz);
   P.euid[be] = child_uid(uid, s, 3);
 }
-__device__ __forceinline__ void see_emit(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
-                                         int side, int64_t be, int64_t s) {
-  if (be < 0) return;
-  see_emit_at(C, P, P.iuid[i], side, be, s);
-}
-
-typedef int rec4 __attribute__((ext_vector_type(4)));  // per-workgroup queue record
-
-// Apply the pending collision queue.  Every particle workgroup of the last
-// step left one event list (in its chunk range of the queue) and a record
-// {events, births, absorbed at x=0, absorbed at x=L}; an event is
-// slot | process << 32 | birth rank in the list << 34.  Workgroup blk of
-// nblk takes a contiguous range of those lists, a group of LANES lanes one
-// list (events carry their birth ranks, so any lane can take any event: more
-// lanes per list shorten long lists, fewer serve more lists per workgroup).
-// Newborns of list j go to q_base + (births of the lists before j) + rank;
-// secondary electrons of ion impacts (ion events of process 2, 3) follow
-// every electron birth of the step.  No atomics: every slot follows from the
-// records alone.
-template <int LANES>
-__device__ __forceinline__ void apply_queue(CaseDev* __restrict__ Cw, int blk, int nblk) {
-  static_assert(LANES >= 1 && LANES <= kWave && kBlock % LANES == 0, "collision workgroup shape");
-  constexpr int kApplyLanes = LANES;
-  constexpr int kApplyGroups = kBlock / LANES;  // lists per round of a workgroup
-  __shared__ int64_t sRed[64];
-  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
-  const int64_t s = C->q_step;
-  const ScatterPtrs P = scatter_ptrs(Cw);
-  const int grp = (int)threadIdx.x / kApplyLanes, l = (int)threadIdx.x % kApplyLanes;
-  const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
-  const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
-  const bool see_on = C->see_on != 0;
-  // no pending queue: no lists (a value, not an early exit, so that every
-  // field of the case is loaded in one round trip)
-  const bool valid = C->q_valid != 0;
-  for (int sp = 0; sp < 2; ++sp) {
-    const int64_t per = valid ? C->q_per[sp] : 0;
-    const int64_t nwg = per > 0 ? (C->q_nblk[sp] + per - 1) / per : 0;
-    const int64_t j0 = nwg * blk / nblk, j1 = nwg * (blk + 1) / nblk;
-    if (j0 >= j1) continue;  // uniform
-    const EDP_GLOBAL rec4* __restrict__ wg = (const EDP_GLOBAL rec4*)G(C->q_wg[sp]);
-    const EDP_GLOBAL int64_t* __restrict__ ent = G(C->cq_ent[sp]);
-    const bool births = sp == 0 || see_on;
-    int64_t zrun = 0;  // births before the current round
-    for (int64_t jb = j0; jb < j1; jb += kApplyGroups) {
-      const bool first = jb == j0;
-      const int64_t jj = jb + grp;
-      const bool valid = jj < j1;
-      rec4 r = {0, 0, 0, 0};
-      int64_t code0 = 0;
-      const EDP_GLOBAL int64_t* __restrict__ e = ent + jj * per * kChunk;
-      if (valid) {
-        // the first event of this lane is loaded with the record, not after
-        // it (a list region holds at least kChunk entries; unused ones are
-        // ignored below)
-        r = wg[jj];
-        code0 = e[l];
-      }
-      int64_t zbase = 0;
-      if (births) {
-        // first round: the births of the lists before this range (for ions,
-        // after every electron birth), loads all in flight together and
-        // summed in the same scan as the round's births (low and high word;
-        // both totals stay below 2^31)
-        int64_t zp = 0;
-        if (first) {
-#pragma unroll 8
-          for (int64_t k = threadIdx.x; k < j0; k += kBlock) zp += wg[k].y;
-          if (sp == 1) {
-            const int64_t pe = C->q_per[0];
-            const int64_t nwe = pe > 0 ? (C->q_nblk[0] + pe - 1) / pe : 0;
-            const EDP_GLOBAL rec4* __restrict__ wge = (const EDP_GLOBAL rec4*)G(C->q_wg[0]);
-#pragma unroll 8
-            for (int64_t k = threadIdx.x; k < nwe; k += kBlock) zp += wge[k].y;
-          }
-        }
-        int64_t tot;
-        const int64_t exc = block_exclusive_scan_t<int64_t>(((int64_t)(l == 0 ? r.y : 0) << 32) | zp, sRed, &tot);
-        if (first) zrun = tot & 0xFFFFFFFFLL;
-        zbase = zrun + (__shfl(exc, 0, kApplyLanes) >> 32);  // births of the lower groups of this round
-        zrun += tot >> 32;
-      }
-      for (int k = l; k < r.x; k += kApplyLanes) {
-        const int64_t code = k == l ? code0 : e[k];
-        const int64_t i = code & 0xFFFFFFFFLL;
-        const int proc = (int)((code >> 32) & 3);
-        const int64_t kk = zbase + (code >> 34);
-        if (sp == 0) {
-          int64_t be = -1, bi = -1;
-          if (proc == 2) {
-            if (base_e + kk < cap_e) be = base_e + kk;
-            if (base_i + kk < cap_i) bi = base_i + kk;
-          }
-          electron_scatter(C, P, i, proc, be, bi, s);
-        } else if (proc < 2) {
-          ion_scatter(C, P, i, proc, s);
-        } else {  // 2, 3: absorbed at x = 0 / x = L with an emitted electron
-          see_emit(C, P, i, proc - 2, base_e + kk < cap_e ? base_e + kk : -1, s);
-        }
-      }
-    }
-  }
-}
-
-// Add the totals of the last particle step to the counters and place its
-// newborns (one workgroup): the particle workgroups' records give collisions,
-// births and absorptions; the newborns occupy q_base + [0, births) up to the
-// capacity, births being ionizations plus, for electrons, the secondaries of
-// ion impacts (ion records count those as events and births).
-__device__ __forceinline__ void fold_queue(CaseDev* __restrict__ Cw) {
-  __shared__ int64_t sRed[64];
-  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
-  int64_t v[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  for (int sp = 0; sp < 2; ++sp) {
-    const int64_t per = C->q_per[sp];
-    const int64_t nwg = per > 0 ? (C->q_nblk[sp] + per - 1) / per : 0;
-    const EDP_GLOBAL rec4* wg = (const EDP_GLOBAL rec4*)G(C->q_wg[sp]);
-#pragma unroll 4
-    for (int64_t k = threadIdx.x; k < nwg; k += blockDim.x) {
-      const rec4 t = wg[k];
-      v[sp][0] += t.x;
-      v[sp][1] += t.y;
-      v[sp][2] += t.z;
-      v[sp][3] += t.w;
-    }
-  }
-  // two sums per scan word (each total is at most the slot count, < 2^31)
-  int64_t t[4];
-  (void)block_exclusive_scan_t<int64_t>((v[0][0] << 32) | v[0][1], sRed, &t[0]);
-  (void)block_exclusive_scan_t<int64_t>((v[0][2] << 32) | v[0][3], sRed, &t[1]);
-  (void)block_exclusive_scan_t<int64_t>((v[1][0] << 32) | v[1][2], sRed, &t[2]);
-  (void)block_exclusive_scan_t<int64_t>((v[1][1] << 32) | v[1][3], sRed, &t[3]);
-  if (threadIdx.x == 0) {
-    const int64_t coll_e = t[0] >> 32, z = t[0] & 0xFFFFFFFFLL;
-    const int64_t ap_e = t[1] >> 32, ag_e = t[1] & 0xFFFFFFFFLL;
-    const int64_t see = t[3] >> 32, ag_i = t[3] & 0xFFFFFFFFLL;
-    const int64_t coll_i = (t[2] >> 32) - see, ap_i = t[2] & 0xFFFFFFFFLL;
-    const int64_t base_e = C->q_base[0], base_i = C->q_base[1];
-    const int64_t room_e = C->sp[0].cap - base_e, room_i = C->sp[1].cap - base_i;
-    const int64_t ze = z + see;
-    const int64_t ok_e = ze < room_e ? ze : (room_e > 0 ? room_e : 0);
-    const int64_t ok_i = z < room_i ? z : (room_i > 0 ? room_i : 0);
-    Cw->alloc[0] = Cw->n[0] = base_e + ok_e;
-    Cw->alloc[1] = Cw->n[1] = base_i + ok_i;
-    Cw->ctr[kCollE] += coll_e;
-    Cw->ctr[kCollI] += coll_i;
-    Cw->ctr[kIoniz] += z;
-    Cw->ctr[kAbsEPow] += ap_e;
-    Cw->ctr[kAbsEGnd] += ag_e;
-    Cw->ctr[kAbsIPow] += ap_i;
-    Cw->ctr[kAbsIGnd] += ag_i;
-    Cw->ctr[kLiveE] += ok_e - ap_e - ag_e;
-    Cw->ctr[kLiveI] += ok_i - ap_i - ag_i;
-    if (ok_e < ze || ok_i < z) {
-      Cw->ctr[kDropped] += (ze - ok_e) + (z - ok_i);
-      Cw->error = 1;
-    }
-  }
-}
-
-// Head of step s for every case of the batch.  Workgroups [0, nc) solve the
-// fields, the next na apply the queues of step s-1 (a range per case), the
-// last nc fold each queue's totals into the counters and do the step's
-// bookkeeping.  R: one role per workgroup.
-template <int MODE, int LANES>
-__global__ void __launch_bounds__(kBlock) k_head(const BlockRole* __restrict__ R, int nc, int na) {
-  extern __shared__ double hsm[];
-  const int bid = (int)blockIdx.x;
-  const EDP_CONST BlockRole* r = KC(R) + bid;
-  CaseDev* C = r->c;
-  if (bid < nc) {
-    field_solve<MODE>(C, hsm);
-    return;
-  }
-  if (bid < nc + na) {
-    apply_queue<LANES>(C, r->j, r->n);
-    return;
-  }
-  if (C->q_valid) fold_queue(C);
-  if (threadIdx.x == 0) {
-    const int64_t s = C->step;
-    const bool ion_step = (s % C->nsub) == 0;
-    C->ctr[kPstepE] += C->ctr[kLiveE];
-    if (ion_step) C->ctr[kPstepI] += C->ctr[kLiveI];
-    C->diag_steps += 1;
-    if (ion_step) C->diag_ion_steps += 1;
-  }
-}
-
-// Apply the pending queue before the host looks at the state (the last
-// workgroup folds the totals).
-__global__ void __launch_bounds__(kBlock) k_drain(CaseDev* __restrict__ C) {
-  apply_queue<kWave>(C, (int)blockIdx.x, (int)gridDim.x);
-}
-__global__ void __launch_bounds__(kBlock) k_drain_done(CaseDev* __restrict__ C) {
-  if (C->q_valid) fold_queue(C);
-  __syncthreads();
-  if (threadIdx.x == 0) C->q_valid = 0;
-}
-
 // ---------------------------------------------------------------------------
 // Steps 3-6 for one species plus the deposit for step s+1.
 //
 // A case's particle slots are cut into chunks of kChunk = 256 slots; wave w
 // of a workgroup owns slots [c*256 + 64w, c*256 + 64w + 64) of chunk c, one
-// per lane.  The case gets a fixed number of workgroups (its share, by
-// expected particle count, of the resident slots the batch uses); workgroup
-// j takes the contiguous chunk range [j*per, (j+1)*per) with per computed
-// from the live slot count at run time, so the launch shape never depends
-// on the count,
-// every workgroup does the same amount of work, and E is loaded and the
-// deposit flushed once per workgroup.
+// per lane.  In the lockstep kernels a case gets a fixed number of
+// workgroups (its share, by expected particle count, of the resident slots
+// the batch uses); workgroup j takes the contiguous chunk range
+// [j*per, (j+1)*per) with per computed from the step's slot count, so the
+// launch shape never depends on the count and every workgroup does the same
+// amount of work.  The small-case kernel runs every chunk of its case in one
+// workgroup.
 //
 // Every particle: gather E from LDS, leapfrog, wall test, deposit the new x
 // into the workgroup's LDS histogram, store x and v_x, and one Philox call
@@ -1089,112 +678,89 @@ __global__ void __launch_bounds__(kBlock) k_drain_done(CaseDev* __restrict__ C) 
 // covers, can give a collision; such candidates (a few percent) go to the
 // wave's LDS segment and everyone else is done.  The candidates get the
 // exact test -- energy bin, table lookups, exp, for ions the thermal target
-// first -- in dense passes: all of the workgroup's at the end as one list,
-// or a wave's own when its segment fills.  So the table work and the
-// transcendentals run on full waves instead of on every wave with one
-// candidate lane.  An ionization adds its newborns' charge (the electron a
-// second share at the parent's x, the ion to the next ion step's density).
-// Colliders are appended to the workgroup's event list (one LDS atomic per
-// wave) and the workgroup writes one record {events, births, absorbed at
-// x=0, absorbed at x=L}.  There are no global returning atomics and no
-// counter shared between workgroups.
+// first -- and the colliders their scattering, in dense passes: all of the
+// workgroup's at the end as one list, or a wave's own when its segment
+// fills.  So the table work and the transcendentals run on full waves
+// instead of on every wave with one candidate lane.  An ionization takes
+// slots for its newborns from the step's birth counters, writes them, and
+// adds their charge (the electron a second share at the parent's x, the ion
+// to the next ion step's density).
 //
-// Dynamic LDS: E[ng] double, H[ng] deposit; with particle diagnostics also
-// J[ng], W[ng], En[ng] (int64) and EEPF[n_eepf] (uint32).  Static: the
-// candidate segments (ions 4 KiB of slots; electrons 10 KiB of slots, v^2
-// and uids) and a few counters.
+// Dynamic LDS: E[ng] double, then the region of H[ng] deposit (also the field
+// solve's scratch); with particle diagnostics also J[ng], W[ng], En[ng]
+// (int64) and EEPF[n_eepf] (uint32).  Static: the candidate segments (ions
+// 4 KiB of slots; electrons 10 KiB of slots, v^2 and uids) and a few
+// counters.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
   // set bits of mask below this lane
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Candidate segment entries per wave of a particle workgroup.
-// Candidate segment per wave: ions keep the slot only (their exact test
-// reloads the state); electrons keep the slot, v^2 and uid, which is all
-// their exact test needs, so it reads nothing back from HBM.
+// Candidate segment entries per wave: ions keep the slot only (their exact
+// test reloads the state); electrons keep the slot, the pushed v_x and the
+// uid, so that their exact test reads only v_y and v_z back.
 constexpr int kSegI = 256;
 constexpr int kSegE = 128;
 template <int SP>
 constexpr int seg_len() { return SP == 0 ? kSegE : kSegI; }
 
-// Event of a particle step: slot | process << 32 | birth rank << 34.
-__device__ __forceinline__ int64_t event_code(int64_t i, int proc, int64_t brank) {
-  return i | ((int64_t)proc << 32) | (brank << 34);
-}
-
-// Append one wave's events (lanes with ev) to its workgroup's list; list
-// positions and birth ranks come from the workgroup's LDS counters, one
-// atomic per wave.  Called by every lane of the wave.
-__device__ __forceinline__ void push_events(bool ev, bool birth, int64_t i, int proc, int* sCnt,
-                                            EDP_GLOBAL int64_t* ent, int lane) {
-  const uint64_t me = __ballot(ev);
-  if (me == 0) return;
-  const uint64_t mb = __ballot(birth);
-  int e0 = 0, b0 = 0;
-  if (lane == 0) {
-    e0 = atomicAdd(&sCnt[0], (int)__popcll(me));
-    if (mb) b0 = atomicAdd(&sCnt[1], (int)__popcll(mb));
+// Birth slots of one step: a species' newborns take consecutive slots after
+// its slot count at the step's start, from a counter of the step's births
+// (LDS in the small-case kernel, born[sp][s % 3] in global memory in the
+// lockstep kernels); a slot at or beyond the capacity drops the birth.
+template <bool SMALL>
+struct Births {
+  int64_t base[2], cap[2];
+  int* lds;           // SMALL: this step's counters per species
+  int64_t* glob[2];   // lockstep: this step's counters per species
+  // Slot of this lane's newborn of species sp (mine), -1 if none or dropped;
+  // every lane of the wave calls it.  placed / dropped count the wave's.
+  __device__ __forceinline__ int64_t take(int sp, bool mine, int lane, int& placed, int& dropped) const {
+    const uint64_t m = __ballot(mine);
+    if (m == 0) return -1;
+    long long b = 0;
+    if (lane == 0) {
+      const int c = (int)__popcll(m);
+      if (SMALL)
+        b = atomicAdd(&lds[sp], c);
+      else
+        b = (long long)gl_fetch_add(glob[sp], (unsigned long long)c);
+    }
+    b = __shfl(b, 0);
+    const int64_t slot = base[sp] + (int64_t)b + lane_rank(m);
+    const bool ok = slot < cap[sp];
+    placed += (int)__popcll(__ballot(mine && ok));
+    dropped += (int)__popcll(__ballot(mine && !ok));
+    return mine && ok ? slot : -1;
   }
-  e0 = __shfl(e0, 0);
-  b0 = __shfl(b0, 0);
-  if (ev) ent[e0 + lane_rank(me)] = event_code(i, proc, birth ? b0 + lane_rank(mb) : 0);
-}
+};
 
-template <int SP>
-__device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const double* __restrict__ efield,
-                                                const int ng, const int j, const int nwg) {
+// Totals of one species' step in one workgroup (kRec fields, summed over the
+// waves).
+struct SpTot {
+  int v[kRec];
+};
+
+// Steps 3-6 of species SP at step s over chunks [c_lo, c_hi) of slots [0, n)
+// of buffer set `cur` (the other species' current set `cur_o`), E in sE,
+// `reg` the LDS region for the deposit histogram (and the particle
+// diagnostics), B the step's birth counters.
+template <int SP, bool SMALL>
+__device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const double* sE, double* reg,
+                                              const int64_t s, const int64_t n, const int64_t c_lo,
+                                              const int64_t c_hi, const int cur, const int cur_o,
+                                              const Births<SMALL>& B) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
-  extern __shared__ double psm[];
-  // candidate segments (one per wave; electrons with v^2 and uid), their
-  // fill, the workgroup's event and birth counters, the per-wave absorption
-  // totals
   constexpr int kSeg = seg_len<SP>();
   constexpr int kPay = SP == 0 ? kBlock / kWave : 1;
   __shared__ int32_t sSeg[kBlock / kWave][kSeg];
   __shared__ double sVx[kPay][SP == 0 ? kSeg : 1];
   __shared__ uint64_t sUid[kPay][SP == 0 ? kSeg : 1];
   __shared__ int sNc[kBlock / kWave];
-  __shared__ int sCnt[2];
-  __shared__ int sAbs[kBlock / kWave][2];
-  // E into LDS first: its address and size come with the workgroup's role,
-  // so these loads go out with those of the case block (a workgroup with no
-  // work this step returns below, after the barrier)
-  double* sE = psm;
-  {
-    double ev[kGridPerThread];
-#pragma unroll
-    for (int q = 0; q < kGridPerThread; ++q) {
-      const int p = threadIdx.x + q * kBlock;
-      ev[q] = p < ng ? G(efield)[p] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kGridPerThread; ++q) {
-      const int p = threadIdx.x + q * kBlock;
-      if (p < ng) sE[p] = ev[q];
-    }
-  }
-  const int64_t s = C->pstep;
-  const int64_t n = C->n[SP];
-  if (SP == 1 && (s % C->nsub) != 0) return;  // ions move on ion steps only
-  const int64_t nch = (n + kChunk - 1) / kChunk;
-  if (j == 0 && threadIdx.x == 0) {
-    // this step's queue: read by the next head (or a drain)
-    Cw->q_step = s;
-    Cw->q_base[SP] = n;
-    Cw->q_nblk[SP] = (int32_t)nch;
-    if (SP == 0) {
-      Cw->q_base[1] = C->n[1];
-      Cw->q_nblk[1] = 0;  // set by the ion kernel on ion steps
-      Cw->q_valid = 1;
-      Cw->step = s + 1;
-    }
-  }
-  const int64_t per = (nch + nwg - 1) / nwg;
-  if (j == 0 && threadIdx.x == 0) Cw->q_per[SP] = per;
-  const int64_t c_lo = (int64_t)j * per;
-  const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
-  if (c_lo >= c_hi) return;  // whole workgroup: nothing to do this step
+  __shared__ int sNd;  // entries of the collider list
+  __shared__ int sTot[kBlock / kWave][kRec];
+  const int ng = C->ng;
   const int nsub = C->nsub;
   const int64_t kion = s / nsub;
   const uint32_t fl = C->flags;
@@ -1204,7 +770,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const int n_ifed = C->n_ifed;
   // histogram: the EEPF for electrons, the IFEDF of both electrodes for ions
   const int n_hist = SP == 0 ? ((fl & kDiagEepf) ? n_eepf : 0) : ((fl & kDiagIfed) ? 2 * (n_ifed + 1) : 0);
-  unsigned long long* sH = (unsigned long long*)(psm + ng);
+  unsigned long long* sH = (unsigned long long*)reg;
   unsigned long long* sJ = sH + ng;
   unsigned long long* sW = sJ + ng;
   unsigned long long* sEn = sW + ng;
@@ -1220,11 +786,11 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     }
   }
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x) sF[b] = 0;
-  if (threadIdx.x < 2) sCnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) sNd = 0;
   __syncthreads();
-
-  const int cur = C->cur[SP];
   EDP_GLOBAL double* __restrict__ X = G(C->sp[SP].x[cur]);
+  // this workgroup's collider list: its chunk range of the species' list
+  EDP_GLOBAL int64_t* __restrict__ CL = G(C->clist[SP]) + c_lo * kChunk;
   EDP_GLOBAL double* __restrict__ VX = G(C->sp[SP].vx[cur]);
   const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
   const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
@@ -1233,9 +799,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   // and vz for the pre-test (those only by the candidates' exact test and the
   // measurement sums)
   const EDP_GLOBAL float* __restrict__ VP2 = G(C->sp[SP].vp2[cur]);
-  // this workgroup's event list: its chunk range of the queue
-  EDP_GLOBAL int64_t* __restrict__ ENT = G(C->cq_ent[SP]) + c_lo * kChunk;
-  const int64_t base_slot = c_lo * kChunk;
+  const ScatterPtrs P = SP == 0 ? scatter_ptrs_at(Cw, cur, cur_o) : scatter_ptrs_at(Cw, cur_o, cur);
   const double inv_dx = C->inv_dx, L_gap = C->L;
   const double dt = SP == 0 ? C->dt_e : C->dt_i;
   const double kick = SP == 0 ? C->factor_e : C->factor_i;
@@ -1246,6 +810,7 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   int64_t* const cnt_i_next = C->cnt_i + ((kion + 1) % 3) * ng;
   // this species' deposit for step s+1 (next ion step for ions)
   int64_t* const dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
+  int64_t* const cnt_e_next = C->cnt_e + ((s + 1) % 3) * ng;
   const double de_cs = C->de_cs;
   const int nbins = C->nbins;
   const uint64_t seed = C->seed;
@@ -1257,7 +822,6 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const bool surf_on = SP == 0 ? C->refl_on != 0 : C->see_on != 0;
   const double p_surf0 = SP == 0 ? C->eta_refl[0] : C->gamma_see[0];
   const double p_surf1 = SP == 0 ? C->eta_refl[1] : C->gamma_see[1];
-  int64_t* const cnt_e_next = C->cnt_e + ((s + 1) % 3) * ng;
   const double n_gas = C->n_gas;
   const double nu_star = SP == 0 ? C->nu_star_e : C->nu_star_i;
   const double p_null = SP == 0 ? C->p_null_e : C->p_null_i;
@@ -1267,33 +831,154 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   const double a2_i = C->a2_i;
   const uint32_t r_tag = SP == 0 ? tag(0, 0, 0) : tag(1, 0, 2);
   const int w = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
-  int tap = 0, tag_ = 0;  // this wave's absorptions over the workgroup's chunks
-  int ncw = 0;             // entries in this wave's candidate segment
+  // this wave's totals (uniform over the wave)
+  int t_coll = 0, t_ioniz = 0, t_pow = 0, t_gnd = 0, t_live = 0, t_be = 0, t_bi = 0, t_drop = 0;
+  int ncw = 0;  // entries in this wave's candidate segment
 
-  // Step 6 for candidates, in dense passes: entry k of `count` (k = first,
-  // first + stride, ...; the loop bound is uniform over the participating
-  // waves) is the particle at slot base_slot + list(k).  The exact test
+  // Step 6 for candidates.  exact_test: the exact test of one candidate
   // (direct: P = 1 - exp(-n sigma_tot g dt), collide iff R < P, process by
   // sigma_k / sigma_tot; null collision: process by R nu* against the
-  // cumulative nu_k, the rest null), then an ionization's newborn charge and
-  // the events of the colliders.
-  auto process = [&](const bool wg_list, const int count, const int first, const int stride) {
-    for (int b0 = 0; b0 < count; b0 += stride) {
-      const int k = b0 + first;
+  // cumulative nu_k, the rest null) from its pushed v_x, v_y, v_z and uid;
+  // returns the process or -1.
+  auto exact_test = [&](const double vxn, const double vy, const double vz, const uint64_t uid) -> int {
+    int proc = -1;
+    double r_coll, r_proc;
+    uniform2(seed, uid, st, r_tag, r_coll, r_proc);
+    if (null_coll) {
+      double g, c1, c2, c3;
+      int idx;
+      if (SP == 0) {
+        const double v2 = vxn * vxn + vy * vy + vz * vz;
+        g = sqrt(v2);
+        const double energy = 0.5 * kEMass * v2 / kEvToJ;
+        idx = energy_bin(energy, de_cs, nbins);
+        c1 = (n_gas * sig0[idx]) * g;
+        c2 = c1 + (n_gas * sig1[idx]) * g;
+        c3 = c2 + (n_gas * sig2[idx]) * g;
+      } else {
+        double z0, z1, z2;
+        normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+        const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+        const double g2 = gx * gx + gy * gy + gz * gz;
+        g = sqrt(g2);
+        const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+        idx = energy_bin(energy, de_cs, nbins);
+        c1 = (n_gas * sig0[idx]) * g;
+        c2 = c1 + (n_gas * sig1[idx]) * g;
+        c3 = c2;
+      }
+      if (c3 > nu_star) gl_add(&Cw->ctr[kAnomaly], 1);
+      const double t = r_proc * nu_star;
+      proc = t < c1 ? 0 : (t < c2 ? 1 : (SP == 0 && t < c3 ? 2 : -1));
+    } else {
+      double p_coll, s_a, s_b, s_c = 0.0;
+      int idx;
+      if (SP == 0) {
+        // squared speed summed from x to z (Algorithm 6)
+        const double v2 = vxn * vxn + vy * vy + vz * vz;
+        const double v = sqrt(v2);
+        const double energy = 0.5 * kEMass * v2 / kEvToJ;
+        idx = energy_bin(energy, de_cs, nbins);
+        // the process tables with the total (one round trip; idx is a
+        // valid bin whatever the outcome)
+        s_a = sig0[idx];
+        s_b = sig1[idx];
+        s_c = sig2[idx];
+        const double nu = nsig[idx] * v;
+        p_coll = 1.0 - exp(-nu * dt);
+      } else {
+        double z0, z1, z2;
+        normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
+        const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
+        const double g2 = gx * gx + gy * gy + gz * gz;
+        const double g = sqrt(g2);
+        const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
+        idx = energy_bin(energy, de_cs, nbins);
+        s_a = sig0[idx];
+        s_b = sig1[idx];
+        const double nu = nsig[idx] * g;
+        p_coll = 1.0 - exp(-nu * dt);
+      }
+      if (r_coll < p_coll) {
+        if (SP == 0) {
+          const double s_tot = s_a + s_b + s_c;
+          if (!(s_tot > 0.0) || r_proc < s_a / s_tot)
+            proc = 0;
+          else if (r_proc < (s_a + s_b) / s_tot)
+            proc = 1;
+          else
+            proc = 2;
+        } else {
+          proc = (!(s_a + s_b > 0.0) || r_proc < s_a / (s_a + s_b)) ? 0 : 1;
+        }
+      }
+    }
+    return proc;
+  };
+
+  // A wave's full segment, tested inside the streaming loop: its colliders
+  // go to the workgroup's collider list (slot | process << 32, in the
+  // workgroup's range of the species' list) for the scattering after the
+  // loop, so that the long scattering code has a single site, where the
+  // loop's state is dead.
+  auto test_segment = [&](const int count) {
+    for (int b0 = 0; b0 < count; b0 += kWave) {
+      const int k = b0 + lane;
       const bool act = k < count;
       int64_t i = 0;
-      double vxn = 0.0, vy = 0.0, vz = 0.0;
-      uint64_t uid = 0;
+      int proc = -1;
       if (act) {
-        int sg = w, kk = k;
-        if (wg_list) {  // the workgroup's segments, one after another
-          sg = 0;
-          while (kk >= sNc[sg]) kk -= sNc[sg++];
-        }
-        i = base_slot + sSeg[sg][kk];
+        i = sSeg[w][k];
+        double vxn;
+        uint64_t uid;
         if (SP == 0) {
           // the pushed v_x and the uid from the segment, v_y and v_z (not
           // changed by the push) from memory
+          vxn = sVx[SP == 0 ? w : 0][SP == 0 ? k : 0];
+          uid = sUid[SP == 0 ? w : 0][SP == 0 ? k : 0];
+        } else {
+          vxn = VX[i];
+          uid = UID[i];
+        }
+        proc = exact_test(vxn, VY[i], VZ[i], uid);
+      }
+      const uint64_t mc = __ballot(proc >= 0);
+      if (mc) {
+        int at = 0;
+        if (lane == 0) at = atomicAdd(&sNd, (int)__popcll(mc));
+        at = __shfl(at, 0);
+        if (proc >= 0) CL[at + lane_rank(mc)] = i | ((int64_t)proc << 32);
+      }
+    }
+  };
+
+  // After the loop and the histogram's flush, one list over the workgroup:
+  // the colliders the streaming loop found (entries [0, nd), state reloaded),
+  // then the remaining candidates of the segments (exact test now).  Every
+  // collider gets its scattering; an ionization its newborns (slots from the
+  // step's counters, charge at the parent's new position: the electron a
+  // second share of this step's deposit, the ion the next ion step's
+  // density).
+  auto finish = [&](const int nd, const int count) {
+    for (int b0 = 0; b0 < count; b0 += kBlock) {
+      const int k = b0 + (int)threadIdx.x;
+      int64_t i = 0;
+      double vxn = 0.0, vy = 0.0, vz = 0.0;
+      uint64_t uid = 0;
+      int proc = -1;
+      if (k < nd) {
+        const int64_t code = CL[k];
+        i = code & 0xFFFFFFFFLL;
+        proc = (int)(code >> 32);
+        vxn = VX[i];
+        vy = VY[i];
+        vz = VZ[i];
+        uid = UID[i];
+      } else if (k < count) {
+        int sg = 0, kk = k - nd;
+        while (kk >= sNc[sg]) kk -= sNc[sg++];
+        i = sSeg[sg][kk];
+        if (SP == 0) {
           vxn = sVx[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
           uid = sUid[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
         } else {
@@ -1302,106 +987,33 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
         }
         vy = VY[i];
         vz = VZ[i];
-      }
-      int proc = -1;
-      if (act) {
-        double r_coll, r_proc;
-        uniform2(seed, uid, st, r_tag, r_coll, r_proc);
-        if (null_coll) {
-          double g, c1, c2, c3;
-          int idx;
-          if (SP == 0) {
-            const double v2 = vxn * vxn + vy * vy + vz * vz;
-            g = sqrt(v2);
-            const double energy = 0.5 * kEMass * v2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            c1 = (n_gas * sig0[idx]) * g;
-            c2 = c1 + (n_gas * sig1[idx]) * g;
-            c3 = c2 + (n_gas * sig2[idx]) * g;
-          } else {
-            double z0, z1, z2;
-            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
-            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
-            const double g2 = gx * gx + gy * gy + gz * gz;
-            g = sqrt(g2);
-            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            c1 = (n_gas * sig0[idx]) * g;
-            c2 = c1 + (n_gas * sig1[idx]) * g;
-            c3 = c2;
-          }
-          if (c3 > nu_star) gl_add(&Cw->ctr[kAnomaly], 1);
-          const double t = r_proc * nu_star;
-          proc = t < c1 ? 0 : (t < c2 ? 1 : (SP == 0 && t < c3 ? 2 : -1));
-        } else {
-          double p_coll, s_a, s_b, s_c = 0.0;
-          int idx;
-          if (SP == 0) {
-            // squared speed summed from x to z (Algorithm 6)
-            const double v2 = vxn * vxn + vy * vy + vz * vz;
-            const double v = sqrt(v2);
-            const double energy = 0.5 * kEMass * v2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            // the process tables with the total (one round trip; idx is a
-            // valid bin whatever the outcome)
-            s_a = sig0[idx];
-            s_b = sig1[idx];
-            s_c = sig2[idx];
-            const double nu = nsig[idx] * v;
-            p_coll = 1.0 - exp(-nu * dt);
-          } else {
-            double z0, z1, z2;
-            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
-            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
-            const double g2 = gx * gx + gy * gy + gz * gz;
-            const double g = sqrt(g2);
-            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            s_a = sig0[idx];
-            s_b = sig1[idx];
-            const double nu = nsig[idx] * g;
-            p_coll = 1.0 - exp(-nu * dt);
-          }
-          if (r_coll < p_coll) {
-            if (SP == 0) {
-              const double s_el = s_a, s_exc = s_b, s_ion = s_c;
-              const double s_tot = s_el + s_exc + s_ion;
-              if (!(s_tot > 0.0) || r_proc < s_el / s_tot)
-                proc = 0;
-              else if (r_proc < (s_el + s_exc) / s_tot)
-                proc = 1;
-              else
-                proc = 2;
-            } else {
-              const double s_iso = s_a, s_back = s_b;
-              proc = (!(s_iso + s_back > 0.0) || r_proc < s_iso / (s_iso + s_back)) ? 0 : 1;
-            }
-          }
-        }
+        proc = exact_test(vxn, vy, vz, uid);
       }
       const bool coll = proc >= 0;
-      const bool ioniz = SP == 0 && proc == 2;
-      if (ioniz) {
-        // the newborns sit at the parent's position: the electron adds a
-        // second share to this step's deposit, the ion goes to the next ion
-        // step's density
-        // (the parent's new x: stored by this workgroup before the fence or
-        // barrier that precedes every dense pass; the last pass runs after
-        // the histogram's flush and adds the electron's share to global
-        // memory)
-        long long r;
-        const int q = deposit_split(X[i], inv_dx, ng, r);
-        if (wg_list) {
-          gl_add(&dst[q], 4294967296LL - r);
-          gl_add(&dst[q + 1], r);
-        } else {
-          lds_add(&sH[q], 4294967296LL - r);
-          lds_add(&sH[q + 1], r);
+      t_coll += (int)__popcll(__ballot(coll));
+      if (SP == 0) {
+        const bool ioniz = proc == 2;
+        double xb = 0.0;
+        int64_t be = -1, bi = -1;
+        const uint64_t mi = __ballot(ioniz);
+        if (mi) {
+          t_ioniz += (int)__popcll(mi);
+          be = B.take(0, ioniz, lane, t_be, t_drop);
+          bi = B.take(1, ioniz, lane, t_bi, t_drop);
+          if (ioniz) {
+            xb = X[i];
+            long long r;
+            const int q = deposit_split(xb, inv_dx, ng, r);
+            gl_add(&dst[q], 4294967296LL - r);
+            gl_add(&dst[q + 1], r);
+            gl_add(&cnt_i_next[q], 4294967296LL - r);
+            gl_add(&cnt_i_next[q + 1], r);
+          }
         }
-        gl_add(&cnt_i_next[q], 4294967296LL - r);
-        gl_add(&cnt_i_next[q + 1], r);
+        if (coll) electron_scatter_at(C, P, i, proc, be, bi, s, vxn, vy, vz, uid, xb);
+      } else if (coll) {
+        ion_scatter_at(C, P, i, proc, s, vxn, vy, vz, uid);
       }
-      push_events(coll, ioniz, i, proc, sCnt, ENT, lane);
     }
   };
 
@@ -1409,9 +1021,9 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   // wave keeps two chunks' loads in flight (the loop is bound by memory
   // latency, not by its arithmetic).
   const int slot = w * kWave + lane;  // slot in the chunk
-  double nx, nvx, nvy, nvz;
-  float nvp2;
-  uint64_t nuid;
+  double nx = 0.0, nvx = 0.0, nvy = 0.0, nvz = 0.0;
+  float nvp2 = 0.0f;
+  uint64_t nuid = 0;
   auto fetch = [&](const int64_t c) {
     const int64_t i = c * kChunk + slot;
     nx = __longlong_as_double(0x7FF8000000000000LL);
@@ -1429,13 +1041,14 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       nuid = UID[i];
     }
   };
-  fetch(c_lo);
+  if (c_lo < c_hi) fetch(c_lo);
   for (int64_t c = c_lo; c < c_hi; ++c) {
     const int64_t i = c * kChunk + slot;
     const double x = nx, vx = nvx, vy = nvy, vz = nvz, vp2 = (double)nvp2;
     const uint64_t uid = nuid;
     if (c + 1 < c_hi) fetch(c + 1);
     bool live = x == x;  // past the end, or absorbed earlier (tombstone)
+    t_live += (int)__popcll(__ballot(live));
     bool abs_pow = false, abs_gnd = false, surf = false, cand = false;
     double xn = 0.0, vxn = 0.0, v2 = 0.0;
     if (live) {
@@ -1493,8 +1106,8 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
       // reflected specularly with the electrode's probability eta (unless
       // its mirror image lies outside the gap); an absorbed ion emits an
       // electron with probability gamma, whose charge goes on the electrode
-      // node of the next step's deposit now and whose slot and velocity the
-      // next head's queue pass writes.
+      // node of the next step's deposit now and which takes its slot from
+      // the step's electron births below.
       abs_pow = xn < 0.0;
       abs_gnd = xn > L_gap;
       if (surf_on && (abs_pow || abs_gnd)) {
@@ -1549,41 +1162,37 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
     }
     if (surf_on) {
       // reflections (electrons) or emissions per electrode (ions); an ion's
-      // secondary emission is an event of process 2 (x = 0) or 3 (x = L)
-      // with one electron birth
+      // secondary electron takes its slot after this step's births so far
       const uint64_t m_s0 = __ballot(surf && (SP == 0 || abs_pow));
       const uint64_t m_s1 = SP == 1 ? __ballot(surf && abs_gnd) : 0ull;
       if (lane == 0 && m_s0) gl_add(&Cw->ctr[SP == 0 ? kRefl : kSeePow], (long long)__popcll(m_s0));
       if (lane == 0 && m_s1) gl_add(&Cw->ctr[kSeeGnd], (long long)__popcll(m_s1));
-      if (SP == 1) push_events(surf, surf, i, abs_pow ? 2 : 3, sCnt, ENT, lane);
+      if (SP == 1 && (m_s0 | m_s1)) {
+        const int64_t be = B.take(0, surf, lane, t_be, t_drop);
+        if (surf) see_emit_at(C, P, uid, abs_pow ? 0 : 1, be, s);
+      }
     }
     const uint64_t m_c = __ballot(cand);
     if (m_c) {
       if (cand) {
         const int at = ncw + lane_rank(m_c);
-        sSeg[w][at] = (int32_t)(i - base_slot);
+        sSeg[w][at] = (int32_t)i;
         if (SP == 0) {
           sVx[SP == 0 ? w : 0][SP == 0 ? at : 0] = vxn;
           sUid[SP == 0 ? w : 0][SP == 0 ? at : 0] = uid;
         }
       }
-      ncw += __popcll(m_c);
+      ncw += (int)__popcll(m_c);
       if (ncw > kSeg - kWave) {
-        // a full segment: the wave finishes its own candidates now (the
-        // fence makes the other lanes' stores of x and v_x visible)
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        process(false, ncw, lane, kWave);
+        // a full segment: the wave tests its own candidates now
+        test_segment(ncw);
         ncw = 0;
       }
     }
-    tap += __popcll(__ballot(abs_pow));
-    tag_ += __popcll(__ballot(abs_gnd));
+    t_pow += (int)__popcll(__ballot(abs_pow));
+    t_gnd += (int)__popcll(__ballot(abs_gnd));
   }
-  if (lane == 0) {
-    sNc[w] = ncw;
-    sAbs[w][0] = tap;
-    sAbs[w][1] = tag_;
-  }
+  if (lane == 0) sNc[w] = ncw;
   __syncthreads();
   // flush first (deposit for step s+1 and diagnostics of step s): the
   // last candidate pass below adds its newborns' charge to global memory
@@ -1602,20 +1211,165 @@ __device__ __forceinline__ void particles_block(CaseDev* __restrict__ Cw, const 
   int64_t* hist = SP == 0 ? C->eepf : C->ifed;
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x)
     if (sF[b]) gl_add(&hist[b], (long long)sF[b]);
-  // the remaining candidates of all waves, as one list over the workgroup
-  process(true, sNc[0] + sNc[1] + sNc[2] + sNc[3], (int)threadIdx.x, kBlock);
+  // the loop's colliders and the remaining candidates of all waves
+  const int nd = sNd;
+  finish(nd, nd + sNc[0] + sNc[1] + sNc[2] + sNc[3]);
+  if (lane == 0) {
+    sTot[w][kRecColl] = t_coll;
+    sTot[w][kRecIoniz] = t_ioniz;
+    sTot[w][kRecAbsPow] = t_pow;
+    sTot[w][kRecAbsGnd] = t_gnd;
+    sTot[w][kRecLive] = t_live;
+    sTot[w][kRecBornE] = t_be;
+    sTot[w][kRecBornI] = t_bi;
+    sTot[w][kRecDropped] = t_drop;
+  }
   __syncthreads();
-  if (threadIdx.x == 0)
-    ((EDP_GLOBAL rec4*)G(Cw->q_wg[SP]))[j] =
-        rec4{sCnt[0], sCnt[1], sAbs[0][0] + sAbs[1][0] + sAbs[2][0] + sAbs[3][0],
-             sAbs[0][1] + sAbs[1][1] + sAbs[2][1] + sAbs[3][1]};
+  SpTot T;
+#pragma unroll
+  for (int f = 0; f < kRec; ++f) T.v[f] = sTot[0][f] + sTot[1][f] + sTot[2][f] + sTot[3][f];
+  __syncthreads();  // sTot, the segments and the histograms are free again
+  return T;
 }
 
-// One launch per species covers the chunks of every case of the batch.
-template <int SP>
-__global__ void __launch_bounds__(kBlock) k_particles(const BlockRole* __restrict__ R) {
+// Slot count of species sp at the start of step s inside a window.
+__device__ __forceinline__ int64_t step_slots(const EDP_CONST CaseDev* __restrict__ C, int sp, int64_t s) {
+  const int r = (int)((s + 2) % 3);
+  const int64_t a = C->nbase[sp][r] + C->born[sp][r];
+  return a < C->sp[sp].cap ? a : C->sp[sp].cap;
+}
+
+// Steps 1-7 of one species for every case of a lockstep group, at step
+// step0 + dstep of each case.  At most 128 VGPRs (four workgroups per CU):
+// the streaming loop needs about 100; the scattering code after the loop
+// would take twice that if left alone, and spills there instead (colliders
+// are a few percent of the particles).  Every workgroup solves its case's field into
+// LDS, then takes its chunk range.  The electron launch's workgroup 0 of
+// each case is the writer of the step (field outputs, ring clearing,
+// measurement sums) and publishes the step's slot counts.  Each workgroup
+// adds its totals to its shard of the case's counters.
+template <int SP, int MODE>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_particles(const BlockRole* __restrict__ R, int dstep) {
+  extern __shared__ double psm[];
   const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
-  particles_block<SP>(r->c, r->efield, r->ng, r->j, r->n);
+  CaseDev* Cw = r->c;
+  const int ng = r->ng, nsub = r->nsub, j = r->j, nwg = r->n;
+  const int64_t s = r->step0 + dstep;
+  if (SP == 1 && (s % nsub) != 0) return;  // ions move on ion steps only
+  double* sE = psm;
+  double* reg = psm + ng;
+  const bool writer = SP == 0 && j == 0;
+  solve_field<MODE>(Cw, r->cnt_e, r->cnt_i, r->volt, ng, nsub, s, sE, reg, writer);
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
+  const int64_t n_e = step_slots(C, 0, s), n_i = step_slots(C, 1, s);
+  if (writer && threadIdx.x == 0) {
+    for (int sp = 0; sp < 2; ++sp) {
+      Cw->nbase[sp][s % 3] = sp == 0 ? n_e : n_i;
+      Cw->born[sp][(s + 1) % 3] = 0;
+    }
+  }
+  const int64_t n = SP == 0 ? n_e : n_i;
+  const int64_t nch = (n + kChunk - 1) / kChunk;
+  const int64_t per = (nch + nwg - 1) / nwg;
+  const int64_t c_lo = (int64_t)j * per;
+  const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
+  if (c_lo >= c_hi) return;  // whole workgroup: nothing to do this step
+  Births<false> B;
+  B.base[0] = n_e;
+  B.base[1] = n_i;
+  B.cap[0] = C->sp[0].cap;
+  B.cap[1] = C->sp[1].cap;
+  B.lds = nullptr;
+  B.glob[0] = &Cw->born[0][s % 3];
+  B.glob[1] = &Cw->born[1][s % 3];
+  const SpTot T = species_pass<SP, false>(Cw, sE, reg, s, n, c_lo, c_hi, C->cur[SP], C->cur[1 - SP], B);
+  if (threadIdx.x == 0) {
+    int64_t* sh = C->shard + ((int64_t)SP * kShards + j % kShards) * kRec;
+#pragma unroll
+    for (int f = 0; f < kRec; ++f)
+      if (T.v[f]) gl_add(&sh[f], T.v[f]);
+    if (T.v[kRecDropped]) Cw->error = 1;
+  }
+}
+
+// First kernel of a lockstep window: every role's step0 from its case, and
+// each case's slot-count rings from its slot counts (so that any host-side
+// change of a case between windows is picked up).  Workgroups [0, ncase)
+// take the cases of `cases`, the others the roles.
+__global__ void __launch_bounds__(kBlock) k_window_begin(BlockRole* __restrict__ roles, int nroles,
+                                                         const BlockRole* __restrict__ cases, int ncase) {
+  const int b = (int)blockIdx.x;
+  if (b < ncase) {
+    if (threadIdx.x == 0) {
+      CaseDev* C = cases[b].c;
+      const int64_t s = C->step;
+      for (int sp = 0; sp < 2; ++sp) {
+        C->nbase[sp][(s + 2) % 3] = C->n[sp];
+        C->born[sp][(s + 2) % 3] = 0;
+        C->born[sp][s % 3] = 0;
+      }
+    }
+    return;
+  }
+  const int i = (b - ncase) * kBlock + (int)threadIdx.x;
+  if (i < nroles) roles[i].step0 = roles[i].c->step;
+}
+
+// Last kernel of a lockstep window of `steps` steps, one workgroup per case:
+// the case's step, its slot counts, and the workgroups' shards folded into
+// the counters (then cleared).
+__global__ void __launch_bounds__(kBlock) k_window_end(const BlockRole* __restrict__ cases, int steps) {
+  __shared__ int64_t sSum[kBlock / kWave][2 * kRec];
+  CaseDev* Cw = (KC(cases) + blockIdx.x)->c;
+  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
+  // thread t sums field t % (2 kRec) of every shard of both species
+  constexpr int kF = 2 * kRec;
+  const int t = (int)threadIdx.x;
+  static_assert(kBlock == 4 * kWave && kWave == 4 * kF, "shard fold layout");
+  int64_t acc = 0;
+  EDP_GLOBAL int64_t* sh = G(C->shard);
+  {
+    const int f = t % kF, sp = f / kRec, fld = f % kRec;
+    for (int k = t / kF; k < kShards; k += kBlock / kF) {
+      EDP_GLOBAL int64_t* a = sh + ((int64_t)sp * kShards + k) * kRec + fld;
+      acc += *a;
+      *a = 0;
+    }
+  }
+  const int lane = t % kWave, wv = t / kWave;
+  // lanes l and l + 16, l + 32, l + 48 hold the same field (64 = 4 * kF)
+  acc += __shfl_xor(acc, 16, kWave);
+  acc += __shfl_xor(acc, 32, kWave);
+  if (lane < kF) sSum[wv][lane] = acc;
+  __syncthreads();
+  if (t == 0) {
+    int64_t v[kF];
+    for (int f = 0; f < kF; ++f) v[f] = sSum[0][f] + sSum[1][f] + sSum[2][f] + sSum[3][f];
+    const int64_t* e = v;
+    const int64_t* ii = v + kRec;
+    int64_t* ctr = Cw->ctr;
+    ctr[kCollE] += e[kRecColl];
+    ctr[kIoniz] += e[kRecIoniz];
+    ctr[kAbsEPow] += e[kRecAbsPow];
+    ctr[kAbsEGnd] += e[kRecAbsGnd];
+    ctr[kPstepE] += e[kRecLive];
+    ctr[kCollI] += ii[kRecColl];
+    ctr[kAbsIPow] += ii[kRecAbsPow];
+    ctr[kAbsIGnd] += ii[kRecAbsGnd];
+    ctr[kPstepI] += ii[kRecLive];
+    ctr[kLiveE] += e[kRecBornE] + ii[kRecBornE] - e[kRecAbsPow] - e[kRecAbsGnd];
+    ctr[kLiveI] += e[kRecBornI] + ii[kRecBornI] - ii[kRecAbsPow] - ii[kRecAbsGnd];
+    ctr[kDropped] += e[kRecDropped] + ii[kRecDropped];
+    const int64_t s = Cw->step + steps;
+    Cw->step = s;
+    for (int sp = 0; sp < 2; ++sp) {
+      const int r = (int)((s + 2) % 3);
+      const int64_t a = Cw->nbase[sp][r] + Cw->born[sp][r];
+      const int64_t cap = C->sp[sp].cap;
+      Cw->n[sp] = Cw->alloc[sp] = a < cap ? a : cap;
+    }
+  }
 }
 
 // Cell of a position (the deposit's node p, clamped to N_g - 2).
@@ -1638,419 +1392,8 @@ __device__ __forceinline__ int cell_of(double x, double inv_dx, int ng) {
 // keeps the chip's other CUs for the other cases.
 //
 // The workgroup owns the case for the launch: the step, the slot counts and
-// the buffer sets live in LDS and are written back at the end (with a
-// pending collision queue of the lockstep path applied first).
+// the buffer sets live in LDS and are written back at the end.
 // ---------------------------------------------------------------------------
-
-// Slots for the newborns of a wave from an LDS counter: lanes with `mine`
-// take consecutive slots after base0 (the slot count at the step's start)
-// and the step's births so far; -1 past the capacity.
-__device__ __forceinline__ int64_t take_slot_lds(bool mine, int* births, int64_t base0, int64_t cap, int lane) {
-  const uint64_t m = __ballot(mine);
-  if (m == 0) return -1;
-  int b = 0;
-  if (lane == 0) b = atomicAdd(births, (int)__popcll(m));
-  b = __shfl(b, 0);
-  const int64_t slot = base0 + (int64_t)b + lane_rank(m);
-  return mine && slot < cap ? slot : -1;
-}
-
-// Totals of one species' step in a small case (summed over the waves).
-struct SmallTot {
-  int coll, ioniz, pow, gnd, live;
-};
-
-// Steps 3-6 of species SP for the case of this workgroup at step s: slots
-// [0, n) of buffer set `cur` (the other species' current set `cur_o`), E in
-// sE, `reg` the LDS region for the deposit histogram (and the particle
-// diagnostics), sBirth the step's birth counters (electron slots, ion slots)
-// after the slot counts n_e0, n_i0 at the step's start.
-template <int SP>
-__device__ __forceinline__ SmallTot small_species(CaseDev* __restrict__ Cw, const double* sE, double* reg, int64_t s,
-                                                  int64_t n, int cur, int cur_o, int64_t n_e0, int64_t n_i0,
-                                                  int* sBirth) {
-  const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
-  constexpr int kSeg = seg_len<SP>();
-  constexpr int kPay = SP == 0 ? kBlock / kWave : 1;
-  __shared__ int32_t sSeg[kBlock / kWave][kSeg];
-  __shared__ double sVx[kPay][SP == 0 ? kSeg : 1];
-  __shared__ uint64_t sUid[kPay][SP == 0 ? kSeg : 1];
-  __shared__ int sNc[kBlock / kWave];
-  __shared__ int sTot[kBlock / kWave][5];
-  const int ng = C->ng;
-  const int64_t cap_e = C->sp[0].cap, cap_i = C->sp[1].cap;
-  const int64_t nch = (n + kChunk - 1) / kChunk;
-  const int nsub = C->nsub;
-  const int64_t kion = s / nsub;
-  const uint32_t fl = C->flags;
-  const bool pdiag = (fl & kDiagParticle) != 0;
-  const bool xt = (fl & kDiagXT) != 0;
-  const int n_eepf = C->n_eepf;
-  const int n_ifed = C->n_ifed;
-  const int n_hist = SP == 0 ? ((fl & kDiagEepf) ? n_eepf : 0) : ((fl & kDiagIfed) ? 2 * (n_ifed + 1) : 0);
-  unsigned long long* sH = (unsigned long long*)reg;
-  unsigned long long* sJ = sH + ng;
-  unsigned long long* sW = sJ + ng;
-  unsigned long long* sEn = sW + ng;
-  unsigned long long* sIz = sEn + ng;
-  unsigned int* sF = (unsigned int*)(sIz + (SP == 0 && xt ? ng : 0));
-  for (int p = threadIdx.x; p < ng; p += blockDim.x) {
-    sH[p] = 0;
-    if (pdiag) {
-      sJ[p] = 0;
-      sW[p] = 0;
-      sEn[p] = 0;
-      if (SP == 0 && xt) sIz[p] = 0;
-    }
-  }
-  for (int b = threadIdx.x; b < n_hist; b += blockDim.x) sF[b] = 0;
-  __syncthreads();
-  EDP_GLOBAL double* __restrict__ X = G(C->sp[SP].x[cur]);
-  EDP_GLOBAL double* __restrict__ VX = G(C->sp[SP].vx[cur]);
-  const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
-  const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
-  const EDP_GLOBAL uint64_t* __restrict__ UID = G(C->sp[SP].uid[cur]);
-  const EDP_GLOBAL float* __restrict__ VP2 = G(C->sp[SP].vp2[cur]);
-  const ScatterPtrs P = SP == 0 ? scatter_ptrs_at(Cw, cur, cur_o) : scatter_ptrs_at(Cw, cur_o, cur);
-  const double inv_dx = C->inv_dx, L_gap = C->L;
-  const double dt = SP == 0 ? C->dt_e : C->dt_i;
-  const double kick = SP == 0 ? C->factor_e : C->factor_i;
-  const EDP_GLOBAL double* __restrict__ nsig = G(SP == 0 ? C->nsig_e : C->nsig_i);
-  const EDP_GLOBAL double* __restrict__ sig0 = G(SP == 0 ? C->sig_el : C->sig_iso);
-  const EDP_GLOBAL double* __restrict__ sig1 = G(SP == 0 ? C->sig_exc : C->sig_back);
-  const EDP_GLOBAL double* __restrict__ sig2 = G(C->sig_ion);
-  int64_t* const cnt_i_next = C->cnt_i + ((kion + 1) % 3) * ng;
-  int64_t* const dst = SP == 0 ? C->cnt_e + ((s + 1) % 3) * ng : C->cnt_i + ((kion + 1) % 3) * ng;
-  int64_t* const cnt_e_next = C->cnt_e + ((s + 1) % 3) * ng;
-  const double de_cs = C->de_cs;
-  const int nbins = C->nbins;
-  const uint64_t seed = C->seed;
-  const uint32_t st = (uint32_t)s;
-  const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf, de_ifed = C->de_ifed;
-  const double sa = C->sigma_a;
-  const bool null_coll = (fl & kNullCollision) != 0;
-  const bool surf_on = SP == 0 ? C->refl_on != 0 : C->see_on != 0;
-  const double p_surf0 = SP == 0 ? C->eta_refl[0] : C->gamma_see[0];
-  const double p_surf1 = SP == 0 ? C->eta_refl[1] : C->gamma_see[1];
-  const double n_gas = C->n_gas;
-  const double nu_star = SP == 0 ? C->nu_star_e : C->nu_star_i;
-  const double p_null = SP == 0 ? C->p_null_e : C->p_null_i;
-  const double p_cand = null_coll ? p_null : (SP == 0 ? C->p_bound_e : C->p_bound_i);
-  const double v2_cand = null_coll ? __builtin_huge_val() : (SP == 0 ? C->v2_lim_e : C->g2_lim_i);
-  const double a2_i = C->a2_i;
-  const uint32_t r_tag = SP == 0 ? tag(0, 0, 0) : tag(1, 0, 2);
-  const int w = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
-  int t_coll = 0, t_ioniz = 0, t_pow = 0, t_gnd = 0, t_live = 0;
-  int ncw = 0;
-
-  // The exact test of the candidates (as in the lockstep path), then at once
-  // the colliders' scattering and an ionization's newborns and their charge.
-  auto process = [&](const bool wg_list, const int count, const int first, const int stride) {
-    for (int b0 = 0; b0 < count; b0 += stride) {
-      const int k = b0 + first;
-      const bool act = k < count;
-      int64_t i = 0;
-      double vxn = 0.0, vy = 0.0, vz = 0.0;
-      uint64_t uid = 0;
-      if (act) {
-        int sg = w, kk = k;
-        if (wg_list) {
-          sg = 0;
-          while (kk >= sNc[sg]) kk -= sNc[sg++];
-        }
-        i = sSeg[sg][kk];
-        if (SP == 0) {
-          vxn = sVx[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
-          uid = sUid[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
-        } else {
-          vxn = VX[i];
-          uid = UID[i];
-        }
-        vy = VY[i];
-        vz = VZ[i];
-      }
-      int proc = -1;
-      if (act) {
-        double r_coll, r_proc;
-        uniform2(seed, uid, st, r_tag, r_coll, r_proc);
-        if (null_coll) {
-          double g, c1, c2, c3;
-          int idx;
-          if (SP == 0) {
-            const double v2 = vxn * vxn + vy * vy + vz * vz;
-            g = sqrt(v2);
-            const double energy = 0.5 * kEMass * v2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            c1 = (n_gas * sig0[idx]) * g;
-            c2 = c1 + (n_gas * sig1[idx]) * g;
-            c3 = c2 + (n_gas * sig2[idx]) * g;
-          } else {
-            double z0, z1, z2;
-            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
-            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
-            const double g2 = gx * gx + gy * gy + gz * gz;
-            g = sqrt(g2);
-            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            c1 = (n_gas * sig0[idx]) * g;
-            c2 = c1 + (n_gas * sig1[idx]) * g;
-            c3 = c2;
-          }
-          if (c3 > nu_star) gl_add(&Cw->ctr[kAnomaly], 1);
-          const double t = r_proc * nu_star;
-          proc = t < c1 ? 0 : (t < c2 ? 1 : (SP == 0 && t < c3 ? 2 : -1));
-        } else {
-          double p_coll, s_a, s_b, s_c = 0.0;
-          int idx;
-          if (SP == 0) {
-            const double v2 = vxn * vxn + vy * vy + vz * vz;
-            const double v = sqrt(v2);
-            const double energy = 0.5 * kEMass * v2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            s_a = sig0[idx];
-            s_b = sig1[idx];
-            s_c = sig2[idx];
-            const double nu = nsig[idx] * v;
-            p_coll = 1.0 - exp(-nu * dt);
-          } else {
-            double z0, z1, z2;
-            normals3(seed, uid, st, 1u, 0u, 0u, z0, z1, z2);
-            const double gx = vxn - sa * z0, gy = vy - sa * z1, gz = vz - sa * z2;
-            const double g2 = gx * gx + gy * gy + gz * gz;
-            const double g = sqrt(g2);
-            const double energy = 0.5 * kMuArAr * g2 / kEvToJ;
-            idx = energy_bin(energy, de_cs, nbins);
-            s_a = sig0[idx];
-            s_b = sig1[idx];
-            const double nu = nsig[idx] * g;
-            p_coll = 1.0 - exp(-nu * dt);
-          }
-          if (r_coll < p_coll) {
-            if (SP == 0) {
-              const double s_tot = s_a + s_b + s_c;
-              if (!(s_tot > 0.0) || r_proc < s_a / s_tot)
-                proc = 0;
-              else if (r_proc < (s_a + s_b) / s_tot)
-                proc = 1;
-              else
-                proc = 2;
-            } else {
-              proc = (!(s_a + s_b > 0.0) || r_proc < s_a / (s_a + s_b)) ? 0 : 1;
-            }
-          }
-        }
-      }
-      const bool coll = proc >= 0;
-      t_coll += __popcll(__ballot(coll));
-      if (SP == 0) {
-        const bool ioniz = proc == 2;
-        double xb = 0.0;
-        int64_t be = -1, bi = -1;
-        const uint64_t mi = __ballot(ioniz);
-        if (mi) {
-          t_ioniz += __popcll(mi);
-          be = take_slot_lds(ioniz, &sBirth[0], n_e0, cap_e, lane);
-          bi = take_slot_lds(ioniz, &sBirth[1], n_i0, cap_i, lane);
-          if (ioniz) {
-            xb = X[i];
-            long long r;
-            const int q = deposit_split(xb, inv_dx, ng, r);
-            if (wg_list) {
-              gl_add(&dst[q], 4294967296LL - r);
-              gl_add(&dst[q + 1], r);
-            } else {
-              lds_add(&sH[q], 4294967296LL - r);
-              lds_add(&sH[q + 1], r);
-            }
-            gl_add(&cnt_i_next[q], 4294967296LL - r);
-            gl_add(&cnt_i_next[q + 1], r);
-          }
-        }
-        if (coll) electron_scatter_at(C, P, i, proc, be, bi, s, vxn, vy, vz, uid, xb);
-      } else if (coll) {
-        ion_scatter_at(C, P, i, proc, s, vxn, vy, vz, uid);
-      }
-    }
-  };
-
-  for (int64_t c = 0; c < nch; ++c) {
-    const int slot = w * kWave + lane;
-    const int64_t i = c * kChunk + slot;
-    double x = __longlong_as_double(0x7FF8000000000000LL), vx = 0.0, vy = 0.0, vz = 0.0, vp2 = 0.0;
-    uint64_t uid = 0;
-    if (i < n) {
-      x = X[i];
-      vx = VX[i];
-      if (SP == 1 || pdiag) {
-        vy = VY[i];
-        vz = VZ[i];
-      }
-      if (SP == 0) vp2 = (double)VP2[i];
-      uid = UID[i];
-    }
-    bool live = x == x;
-    t_live += __popcll(__ballot(live));
-    bool abs_pow = false, abs_gnd = false, surf = false, cand = false;
-    double xn = 0.0, vxn = 0.0, v2 = 0.0;
-    if (live) {
-      // steps 3-4: field at the particle (section 2.1.3) and leapfrog
-      // (section 2.1.4), as in the lockstep kernel
-      const double xi = x * inv_dx;
-      int cell = (int)xi;
-      cell = cell > ng - 2 ? ng - 2 : (cell < 0 ? 0 : cell);
-      const double w_lo = (double)(cell + 1) - xi;
-      const double w_hi = xi - (double)cell;
-      const double e_here = sE[cell] * w_lo + sE[cell + 1] * w_hi;
-      vxn = SP == 0 ? vx - e_here * kick : vx + e_here * kick;
-      xn = x + vxn * dt;
-      if (pdiag) {
-        const double vbar = 0.5 * (vx + vxn);
-        if (fl & (kDiagCurrent | kDiagXT)) {
-          lds_add(&sJ[cell], (long long)(w_lo * vbar * kDiagJS));
-          lds_add(&sJ[cell + 1], (long long)(w_hi * vbar * kDiagJS));
-        }
-        if (SP == 1) {
-          if (xt) {
-            const double en = 0.5 * kArMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
-            lds_add(&sW[cell], (long long)(w_lo * kDiagWS));
-            lds_add(&sW[cell + 1], (long long)(w_hi * kDiagWS));
-            lds_add(&sEn[cell], (long long)(w_lo * en * kDiagES));
-            lds_add(&sEn[cell + 1], (long long)(w_hi * en * kDiagES));
-          }
-        } else if (fl & (kDiagMeanE | kDiagEepf | kDiagXT)) {
-          const double en = 0.5 * kEMass * (vbar * vbar + vy * vy + vz * vz) / kEvToJ;
-          if (xt) {
-            const double vmag = sqrt(vbar * vbar + vy * vy + vz * vz);
-            const double pdt = (n_gas * sig2[energy_bin(en, de_cs, nbins)]) * vmag * dt;
-            lds_add(&sIz[cell], (long long)(w_lo * pdt * kDiagIZS));
-            lds_add(&sIz[cell + 1], (long long)(w_hi * pdt * kDiagIZS));
-          }
-          if (fl & (kDiagMeanE | kDiagXT)) {
-            lds_add(&sW[cell], (long long)(w_lo * kDiagWS));
-            lds_add(&sW[cell + 1], (long long)(w_hi * kDiagWS));
-            lds_add(&sEn[cell], (long long)(w_lo * en * kDiagES));
-            lds_add(&sEn[cell + 1], (long long)(w_hi * en * kDiagES));
-          }
-          if ((fl & kDiagEepf) && x >= x_lo && x <= x_hi) {
-            const double t = en / de_eepf;
-            if (t < (double)n_eepf) atomicAdd(&sF[(int)t], 1u);
-          }
-        }
-      }
-      // step 5: walls and surface processes, as in the lockstep kernel
-      abs_pow = xn < 0.0;
-      abs_gnd = xn > L_gap;
-      if (surf_on && (abs_pow || abs_gnd)) {
-        double r_surf, r_unused;
-        uniform2(seed, uid, st, tag(SP, 3, 0), r_surf, r_unused);
-        if (r_surf < (abs_pow ? p_surf0 : p_surf1)) {
-          if (SP == 0) {
-            const double xm = abs_pow ? -xn : 2.0 * L_gap - xn;
-            if (xm >= 0.0 && xm <= L_gap) {
-              xn = xm;
-              vxn = -vxn;
-              abs_pow = abs_gnd = false;
-              surf = true;
-            }
-          } else {
-            surf = true;
-            long long r;
-            const int q = deposit_split(abs_pow ? 0.0 : L_gap, inv_dx, ng, r);
-            gl_add(&cnt_e_next[q], 4294967296LL - r);
-            if (r) gl_add(&cnt_e_next[q + 1], r);
-          }
-        }
-      }
-      if (abs_pow || abs_gnd) {
-        live = false;
-        if (SP == 1 && (fl & kDiagIfed)) {
-          const double en = 0.5 * kArMass * (vxn * vxn + vy * vy + vz * vz) / kEvToJ;
-          const double t = en / de_ifed;
-          const int b = t < (double)n_ifed ? (int)t : n_ifed;
-          atomicAdd(&sF[(abs_gnd ? n_ifed + 1 : 0) + b], 1u);
-        }
-      } else {
-        long long r;
-        const int q = deposit_split(xn, inv_dx, ng, r);
-        lds_add(&sH[q], 4294967296LL - r);
-        lds_add(&sH[q + 1], r);
-        double r_coll, r_proc;
-        uniform2(seed, uid, st, r_tag, r_coll, r_proc);
-        v2 = SP == 0 ? vxn * vxn + vp2 : vxn * vxn + vy * vy + vz * vz;
-        cand = r_coll < p_cand || (SP == 0 ? v2 : 2.0 * (v2 + a2_i)) > v2_cand;
-      }
-    }
-    if (i < n && x == x) {
-      X[i] = live ? xn : __longlong_as_double(0x7FF8000000000000LL);
-      VX[i] = vxn;
-    }
-    if (surf_on) {
-      const uint64_t m_s0 = __ballot(surf && (SP == 0 || abs_pow));
-      const uint64_t m_s1 = SP == 1 ? __ballot(surf && abs_gnd) : 0ull;
-      if (lane == 0 && m_s0) gl_add(&Cw->ctr[SP == 0 ? kRefl : kSeePow], (long long)__popcll(m_s0));
-      if (lane == 0 && m_s1) gl_add(&Cw->ctr[kSeeGnd], (long long)__popcll(m_s1));
-      if (SP == 1 && (m_s0 | m_s1)) {
-        // a secondary electron takes its slot after this step's births so far
-        const int64_t be = take_slot_lds(surf, &sBirth[0], n_e0, cap_e, lane);
-        if (surf) see_emit_at(C, P, uid, abs_pow ? 0 : 1, be, s);
-      }
-    }
-    const uint64_t m_c = __ballot(cand);
-    if (m_c) {
-      if (cand) {
-        const int at = ncw + lane_rank(m_c);
-        sSeg[w][at] = (int32_t)i;
-        if (SP == 0) {
-          sVx[SP == 0 ? w : 0][SP == 0 ? at : 0] = vxn;
-          sUid[SP == 0 ? w : 0][SP == 0 ? at : 0] = uid;
-        }
-      }
-      ncw += __popcll(m_c);
-      if (ncw > kSeg - kWave) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        process(false, ncw, lane, kWave);
-        ncw = 0;
-      }
-    }
-    t_pow += __popcll(__ballot(abs_pow));
-    t_gnd += __popcll(__ballot(abs_gnd));
-  }
-  if (lane == 0) sNc[w] = ncw;
-  __syncthreads();
-  for (int q = threadIdx.x; q < ng; q += blockDim.x) {
-    const unsigned long long h = sH[q];
-    if (h) gl_add(&dst[q], (long long)h);
-    if (pdiag) {
-      const int64_t off3 = (s % 3) * ng + q;
-      if (sJ[q]) gl_add(&(SP == 0 ? C->acc_je : C->acc_ji)[off3], (long long)sJ[q]);
-      if (sW[q]) gl_add(&(SP == 0 ? C->acc_w : C->acc_wi)[off3], (long long)sW[q]);
-      if (sEn[q]) gl_add(&(SP == 0 ? C->acc_e : C->acc_ei)[off3], (long long)sEn[q]);
-      if (SP == 0 && xt && sIz[q]) gl_add(&C->acc_iz[off3], (long long)sIz[q]);
-    }
-  }
-  int64_t* hist = SP == 0 ? C->eepf : C->ifed;
-  for (int b = threadIdx.x; b < n_hist; b += blockDim.x)
-    if (sF[b]) gl_add(&hist[b], (long long)sF[b]);
-  process(true, sNc[0] + sNc[1] + sNc[2] + sNc[3], (int)threadIdx.x, kBlock);
-  if (lane == 0) {
-    sTot[w][0] = t_coll;
-    sTot[w][1] = t_ioniz;
-    sTot[w][2] = t_pow;
-    sTot[w][3] = t_gnd;
-    sTot[w][4] = t_live;
-  }
-  __syncthreads();
-  SmallTot T{0, 0, 0, 0, 0};
-  for (int v = 0; v < kBlock / kWave; ++v) {
-    T.coll += sTot[v][0];
-    T.ioniz += sTot[v][1];
-    T.pow += sTot[v][2];
-    T.gnd += sTot[v][3];
-    T.live += sTot[v][4];
-  }
-  __syncthreads();  // sTot and the segments are free for the next call
-  return T;
-}
 
 // Compaction + counting sort by cell of species sp in one workgroup: the
 // live slots of [0, n) of set `cur` go to the other set, cell by cell (order
@@ -2113,12 +1456,13 @@ __device__ __forceinline__ int64_t small_sort(CaseDev* __restrict__ Cw, int sp, 
 }
 
 // Window of steps of the small cases: workgroup b advances the case of role
-// b by role.j steps.  Dynamic LDS: E, then the largest of the field solve's
-// two padded rows, the particle phase's histograms and the sort's counters.
+// b by role.j steps.  Dynamic LDS: E, then the largest of the particle
+// phase's histograms (also the field solve's scratch) and the sort's
+// counters.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ R, int sort_every) {
   extern __shared__ double ssm2[];
-  __shared__ int64_t sState[6];  // step, n_e, n_i, cur_e, cur_i, spare
+  __shared__ int64_t sState[5];  // step, n_e, n_i, cur_e, cur_i
   __shared__ int sBirth[2];
   const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
   CaseDev* Cw = r->c;
@@ -2128,23 +1472,12 @@ __global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ 
   const int nsub = C->nsub;
   double* sE = ssm2;
   double* reg = ssm2 + ng;
-  // a collision queue the lockstep path left pending is applied first
-  if (Cw->q_valid) {
-    apply_queue<kWave>(Cw, 0, 1);
-    __syncthreads();
-    fold_queue(Cw);
-    __syncthreads();
-    if (threadIdx.x == 0) Cw->q_valid = 0;
-  }
   if (threadIdx.x == 0) {
-    // vector loads (the scalar cache does not see this launch's stores)
-    auto ld = [](const int64_t* a) { return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
-    auto ld32 = [](const int32_t* a) { return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
-    sState[0] = ld(&Cw->step);
-    sState[1] = ld(&Cw->n[0]);
-    sState[2] = ld(&Cw->n[1]);
-    sState[3] = ld32(&Cw->cur[0]);
-    sState[4] = ld32(&Cw->cur[1]);
+    sState[0] = Cw->step;
+    sState[1] = Cw->n[0];
+    sState[2] = Cw->n[1];
+    sState[3] = Cw->cur[0];
+    sState[4] = Cw->cur[1];
   }
   __syncthreads();
   for (int t = 0; t < steps; ++t) {
@@ -2163,29 +1496,35 @@ __global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ 
     }
     if (threadIdx.x < 2) sBirth[threadIdx.x] = 0;
     // steps 1-2
-    field_to_lds<MODE>(Cw, sE, reg, true, s);
-    const SmallTot te = small_species<0>(Cw, sE, reg, s, n_e, cur_e, cur_i, n_e, n_i, sBirth);
-    SmallTot ti{0, 0, 0, 0, 0};
-    if (ion_step) ti = small_species<1>(Cw, sE, reg, s, n_i, cur_i, cur_e, n_e, n_i, sBirth);
+    solve_field<MODE>(Cw, C->cnt_e, C->cnt_i, C->volt, ng, nsub, s, sE, reg, true);
+    Births<true> B;
+    B.base[0] = n_e;
+    B.base[1] = n_i;
+    B.cap[0] = C->sp[0].cap;
+    B.cap[1] = C->sp[1].cap;
+    B.lds = sBirth;
+    B.glob[0] = B.glob[1] = nullptr;
+    const int64_t nch_e = (n_e + kChunk - 1) / kChunk, nch_i = (n_i + kChunk - 1) / kChunk;
+    const SpTot te = species_pass<0, true>(Cw, sE, reg, s, n_e, 0, nch_e, cur_e, cur_i, B);
+    SpTot ti{};
+    if (ion_step) ti = species_pass<1, true>(Cw, sE, reg, s, n_i, 0, nch_i, cur_i, cur_e, B);
     if (threadIdx.x == 0) {
       int64_t* ctr = Cw->ctr;
-      ctr[kCollE] += te.coll;
-      ctr[kIoniz] += te.ioniz;
-      ctr[kAbsEPow] += te.pow;
-      ctr[kAbsEGnd] += te.gnd;
-      ctr[kPstepE] += te.live;
-      ctr[kCollI] += ti.coll;
-      ctr[kAbsIPow] += ti.pow;
-      ctr[kAbsIGnd] += ti.gnd;
-      ctr[kPstepI] += ti.live;
-      const int64_t be = sBirth[0], bi = sBirth[1];
-      const int64_t room_e = C->sp[0].cap - n_e, room_i = C->sp[1].cap - n_i;
-      const int64_t ge = be < room_e ? be : (room_e > 0 ? room_e : 0);
-      const int64_t gi = bi < room_i ? bi : (room_i > 0 ? room_i : 0);
-      ctr[kLiveE] += ge - te.pow - te.gnd;
-      ctr[kLiveI] += gi - ti.pow - ti.gnd;
-      if (ge < be || gi < bi) {
-        ctr[kDropped] += (be - ge) + (bi - gi);
+      ctr[kCollE] += te.v[kRecColl];
+      ctr[kIoniz] += te.v[kRecIoniz];
+      ctr[kAbsEPow] += te.v[kRecAbsPow];
+      ctr[kAbsEGnd] += te.v[kRecAbsGnd];
+      ctr[kPstepE] += te.v[kRecLive];
+      ctr[kCollI] += ti.v[kRecColl];
+      ctr[kAbsIPow] += ti.v[kRecAbsPow];
+      ctr[kAbsIGnd] += ti.v[kRecAbsGnd];
+      ctr[kPstepI] += ti.v[kRecLive];
+      const int64_t ge = te.v[kRecBornE] + ti.v[kRecBornE], gi = te.v[kRecBornI] + ti.v[kRecBornI];
+      ctr[kLiveE] += ge - te.v[kRecAbsPow] - te.v[kRecAbsGnd];
+      ctr[kLiveI] += gi - ti.v[kRecAbsPow] - ti.v[kRecAbsGnd];
+      const int64_t dropped = te.v[kRecDropped] + ti.v[kRecDropped];
+      if (dropped) {
+        ctr[kDropped] += dropped;
         Cw->error = 1;
       }
       sState[0] = s + 1;
@@ -2267,24 +1606,27 @@ __global__ void __launch_bounds__(256) k_deposit(CaseDev* __restrict__ C, int sp
 // so the host launches the four kernels only at steps where some case is due.
 constexpr int kSortUnroll = 4;
 
-__device__ __forceinline__ bool sort_due(const CaseDev* C, int sp, int every) {
-  const EDP_CONST CaseDev* K = KC(C);
-  const int64_t per = sp == 0 ? (int64_t)every : (int64_t)every * K->nsub;
-  return K->step % per == 0;
+// Step of a sort launch of a window for role r, and whether species sp of
+// its case is due at that step.
+__device__ __forceinline__ bool sort_due(const EDP_CONST BlockRole* r, int sp, int every, int dstep, int64_t& s) {
+  s = r->step0 + dstep;
+  const int64_t per = sp == 0 ? (int64_t)every : (int64_t)every * r->nsub;
+  return s % per == 0;
 }
 
-__global__ void __launch_bounds__(256) k_sort_hist(const BlockRole* __restrict__ R, int sp, int every) {
+__global__ void __launch_bounds__(256) k_sort_hist(const BlockRole* __restrict__ R, int sp, int every, int dstep) {
   extern __shared__ double hsm[];
   const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
   CaseDev* C = r->c;
-  if (!sort_due(C, sp, every)) return;
+  int64_t s;
+  if (!sort_due(r, sp, every, dstep, s)) return;
   unsigned int* sC = (unsigned int*)hsm;
   const int ng = C->ng;
   for (int p = threadIdx.x; p < ng; p += blockDim.x) sC[p] = 0;
   __syncthreads();
   const int cur = C->cur[sp];
   const EDP_GLOBAL double* __restrict__ X = G(C->sp[sp].x[cur]);
-  const int64_t n = slots(C, sp);
+  const int64_t n = step_slots(KC(C), sp, s);
   const int64_t nb = r->n, per = (n + nb - 1) / nb;
   const int64_t lo = (int64_t)r->j * per, hi = lo + per < n ? lo + per : n;
   const double inv_dx = C->inv_dx;
@@ -2307,10 +1649,12 @@ __global__ void __launch_bounds__(256) k_sort_hist(const BlockRole* __restrict__
 }
 
 // Exclusive scan of the ng-1 cell counts (one workgroup); total -> sort_cnt[ng].
-__global__ void __launch_bounds__(1024) k_sort_scan(const BlockRole* __restrict__ R, int sp, int every) {
+__global__ void __launch_bounds__(1024) k_sort_scan(const BlockRole* __restrict__ R, int sp, int every, int dstep) {
   __shared__ int64_t sRed[64];
-  CaseDev* C = (KC(R) + blockIdx.x)->c;
-  if (!sort_due(C, sp, every)) return;
+  const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
+  CaseDev* C = r->c;
+  int64_t s;
+  if (!sort_due(r, sp, every, dstep, s)) return;
   const int m = C->ng - 1;
   const int t = threadIdx.x, T = blockDim.x;
   const int per = (m + T - 1) / T;
@@ -2327,11 +1671,13 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const BlockRole* __restrict_
   }
 }
 
-__global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restrict__ R, int sp, int every) {
+__global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restrict__ R, int sp, int every,
+                                                      int dstep) {
   extern __shared__ double ssm[];
   const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
   CaseDev* C = r->c;
-  if (!sort_due(C, sp, every)) return;
+  int64_t s;
+  if (!sort_due(r, sp, every, dstep, s)) return;
   unsigned int* sC = (unsigned int*)ssm;
   unsigned long long* sB = (unsigned long long*)(ssm + (C->ng + 1) / 2);
   const int ng = C->ng;
@@ -2340,7 +1686,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
   const int cur = C->cur[sp], nxt = cur ^ 1;
   const SpeciesDev& S = C->sp[sp];
   const EDP_GLOBAL double* __restrict__ X = G(S.x[cur]);
-  const int64_t n = slots(C, sp);
+  const int64_t n = step_slots(KC(C), sp, s);
   const int64_t nb = r->n, per = (n + nb - 1) / nb;
   const int64_t lo = (int64_t)r->j * per, hi = lo + per < n ? lo + per : n;
   const double inv_dx = C->inv_dx;
@@ -2405,13 +1751,16 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const BlockRole* __restric
   }
 }
 
-__global__ void k_sort_finish(const BlockRole* __restrict__ R, int sp, int every) {
-  CaseDev* C = (KC(R) + blockIdx.x)->c;
-  if (!sort_due(C, sp, every)) return;
+__global__ void k_sort_finish(const BlockRole* __restrict__ R, int sp, int every, int dstep) {
+  const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
+  CaseDev* C = r->c;
+  int64_t s;
+  if (!sort_due(r, sp, every, dstep, s)) return;
   const int ng = C->ng;
   if (threadIdx.x == 0) {
-    C->alloc[sp] = C->sort_cnt[ng];
-    C->n[sp] = C->sort_cnt[ng];  // the step's snapshot, taken before the sort
+    // the step's slot count: the live particles, now in the other set
+    C->nbase[sp][(s + 2) % 3] = C->sort_cnt[ng];
+    C->born[sp][(s + 2) % 3] = 0;
     C->cur[sp] ^= 1;
   }
   __syncthreads();
@@ -2441,10 +1790,11 @@ __global__ void k_zero(int64_t* __restrict__ p, int64_t n) {
 // Host-side launchers (same translation unit as the kernels).
 // ---------------------------------------------------------------------------
 // Static LDS of a species' particle kernel: the candidate segments with
-// their payload, plus a bound on the small per-wave counters.
+// their payload, plus a bound on the counters, the totals and the field
+// scan's scratch.
 size_t particle_static_lds(int sp) {
   const size_t waves = kBlock / kWave;
-  return sp == 0 ? waves * kSegE * (4 + 8 + 8) + 256 : waves * kSegI * 4 + 256;
+  return sp == 0 ? waves * kSegE * (4 + 8 + 8) + 1024 : waves * kSegI * 4 + 1024;
 }
 
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp) {
@@ -2458,74 +1808,58 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp
   return doubles * 8;
 }
 
-// Head of a batch step: ncase field workgroups, `apply_blocks` collision
-// workgroups in total and ncase totals workgroups, with their roles in this
-// order.  `max_ng` sizes the field workgroups' LDS; `lanes` (16, 32, 64) per
-// event list in the collision workgroups.
-hipError_t launch_head(const BlockRole* roles, int ncase, int apply_blocks, int max_ng, int mode, int lanes,
-                       hipStream_t st) {
-  const size_t lds = (size_t)(max_ng + (max_ng >> 4) + 1) * 24;  // three padded rows
-  const dim3 grid(2 * ncase + apply_blocks);
-#define EDP_HEAD(M, LN) hipLaunchKernelGGL((k_head<M, LN>), grid, dim3(kBlock), lds, st, roles, ncase, apply_blocks)
-  switch (lanes * 2 + (mode == 1)) {
-    case 32: EDP_HEAD(0, 16); break;
-    case 33: EDP_HEAD(1, 16); break;
-    case 64: EDP_HEAD(0, 32); break;
-    case 65: EDP_HEAD(1, 32); break;
-    case 128: EDP_HEAD(0, 64); break;
-    case 129: EDP_HEAD(1, 64); break;
-    default: return hipErrorInvalidValue;
-  }
-#undef EDP_HEAD
-  return hipGetLastError();
+// One species of a window step of a batch: `blocks` workgroups with their
+// roles; `lds` = the largest per-case need; mode 1: the Thomas solve.  With
+// ev0/ev1 the launch records its own start and end (the dispatch's
+// timestamps, not those of separate event packets around it).
+template <int SP, int MODE>
+void launch_particles_t(const BlockRole* roles, int blocks, size_t lds, int dstep, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, roles, dstep);
+  else
+    hipLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kBlock), lds, st, roles, dstep);
 }
 
-hipError_t launch_drain(CaseDev* d, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_drain, dim3(blocks), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(k_drain_done, dim3(1), dim3(kBlock), 0, st, d);
-  return hipGetLastError();
-}
-
-// One species of a batch: `blocks` workgroups with their roles; `lds` = the
-// largest per-case need.  With ev0/ev1 the launch records its own
-// start and end (the dispatch's timestamps, not those of separate event
-// packets around it).
-hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, hipStream_t st, hipEvent_t ev0,
-                            hipEvent_t ev1) {
-  if (ev0) {
-    if (sp == 0)
-      hipExtLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, roles);
-    else
-      hipExtLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, roles);
-  } else if (sp == 0) {
-    hipLaunchKernelGGL(k_particles<0>, dim3(blocks), dim3(kBlock), lds, st, roles);
-  } else {
-    hipLaunchKernelGGL(k_particles<1>, dim3(blocks), dim3(kBlock), lds, st, roles);
+hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, int mode, int dstep,
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (sp * 2 + (mode == 1)) {
+    case 0: launch_particles_t<0, 0>(roles, blocks, lds, dstep, st, ev0, ev1); break;
+    case 1: launch_particles_t<0, 1>(roles, blocks, lds, dstep, st, ev0, ev1); break;
+    case 2: launch_particles_t<1, 0>(roles, blocks, lds, dstep, st, ev0, ev1); break;
+    default: launch_particles_t<1, 1>(roles, blocks, lds, dstep, st, ev0, ev1); break;
   }
   return hipGetLastError();
 }
 
-// Resident workgroups per CU of the head for grids of up to max_ng nodes.
-int head_occupancy(int max_ng) {
-  const size_t lds = (size_t)(max_ng + (max_ng >> 4) + 1) * 24;
-  int nb = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_head<0, 16>, kBlock, lds);
-  return e == hipSuccess && nb > 0 ? nb : 1;
+// The first and last kernels of a lockstep window (see k_window_begin and
+// k_window_end): `roles` the group's nroles roles, `cases` its ncase case
+// roles.
+hipError_t launch_window_begin(BlockRole* roles, int nroles, const BlockRole* cases, int ncase, hipStream_t st) {
+  const int blocks = ncase + (nroles + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_window_begin, dim3(blocks), dim3(kBlock), 0, st, roles, nroles, cases, ncase);
+  return hipGetLastError();
+}
+
+hipError_t launch_window_end(const BlockRole* cases, int ncase, int steps, hipStream_t st) {
+  hipLaunchKernelGGL(k_window_end, dim3(ncase), dim3(kBlock), 0, st, cases, steps);
+  return hipGetLastError();
 }
 
 // Resident workgroups per CU of a species' particle kernel with `lds` bytes
 // of dynamic LDS.
 int particle_occupancy(int sp, size_t lds) {
   int nb = 0;
-  const hipError_t e = sp == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<0>, kBlock, lds)
-                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<1>, kBlock, lds);
+  const hipError_t e = sp == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<0, 0>, kBlock, lds)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<1, 0>, kBlock, lds);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 // Dynamic LDS of the small-case kernel for a case: E, then the largest of
-// the field solve's rows and either species' particle region.
+// either species' particle region (which also holds the field solve's
+// scratch and the sort's counters).
 size_t small_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed) {
-  size_t region = 2 * (size_t)(ng + (ng >> 4) + 1);
+  size_t region = (size_t)ng;
   for (int sp = 0; sp < 2; ++sp) {
     const size_t r = particle_lds_bytes(ng, flags, n_eepf, n_ifed, sp) / 8 - (size_t)ng;
     region = region > r ? region : r;
@@ -2572,12 +1906,12 @@ hipError_t launch_deposit(CaseDev* d, int sp, int64_t* dst1, int64_t* dst2, int 
 // and the scatter, one per case (`case_roles`, ncase of them) for the scan
 // and the finish; `max_ng` sizes the LDS.
 hipError_t launch_sort(const BlockRole* roles, const BlockRole* case_roles, int sp, int blocks, int ncase, int max_ng,
-                       int every, hipStream_t st) {
-  hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(256), (size_t)max_ng * 4, st, roles, sp, every);
-  hipLaunchKernelGGL(k_sort_scan, dim3(ncase), dim3(1024), 0, st, case_roles, sp, every);
+                       int every, int dstep, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(256), (size_t)max_ng * 4, st, roles, sp, every, dstep);
+  hipLaunchKernelGGL(k_sort_scan, dim3(ncase), dim3(1024), 0, st, case_roles, sp, every, dstep);
   const size_t lds = (size_t)((max_ng + 1) / 2) * 8 + (size_t)max_ng * 8;
-  hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(256), lds, st, roles, sp, every);
-  hipLaunchKernelGGL(k_sort_finish, dim3(ncase), dim3(1024), 0, st, case_roles, sp, every);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(256), lds, st, roles, sp, every, dstep);
+  hipLaunchKernelGGL(k_sort_finish, dim3(ncase), dim3(1024), 0, st, case_roles, sp, every, dstep);
   return hipGetLastError();
 }
 

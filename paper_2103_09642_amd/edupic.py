@@ -24,7 +24,6 @@ INFO_NAMES = ["mean_e", "ne_max", "debye", "dx_debye", "wpe_dt", "pmax_e", "pmax
 OPT_MODE, OPT_SORT_EVERY, OPT_PROFILE, OPT_GRAPH_STEPS = 1, 2, 5, 6
 OPT_POISSON = 8
 OPT_PART_WG_PER_CU = 9
-OPT_APPLY_LANES = 10
 OPT_GROUPS = 11
 OPT_SMALL_MAX = 12
 POISSON_FLUX, POISSON_THOMAS = 0, 1

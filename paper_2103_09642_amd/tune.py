@@ -1,19 +1,15 @@
 """Autotuner for the batch runtime's schedule: the compaction + cell-sort
-interval, the particle workgroups per CU, the lanes per event list of the
-head's collision workgroups and, for a batch of several cases, the number of
-lockstep groups it runs as.
+interval, the particle workgroups per CU and, for a batch of several cases,
+the number of lockstep groups it runs as.
 
 * The sort every K steps trades its own cost (one pass over every particle
   array of the cases due) against the particle kernel's locality: between
   sorts, newborns are appended unsorted and particles drift between cells, so
   the streaming kernel slows down as the last sort recedes.
 * The particle launches take, per case, a share of the chip's resident
-  workgroup slots.  All of them (5 per CU for electrons) hide the most memory
-  latency, fewer leave each workgroup more chunks and the memory system less
-  contention; which wins depends on the batch.
-* The head applies each particle workgroup's event list with a group of 16,
-  32 or 64 lanes.  Long lists (the batched sets: tens of chunks per
-  workgroup) want 64, the single large case's short lists 16.
+  workgroup slots.  All of them hide the most memory latency, fewer leave
+  each workgroup more chunks (each workgroup solves the field once per step)
+  and the memory system less contention; which wins depends on the batch.
 
 The best values depend on the workload -- a single case of 2e6 particles
 per species is fastest near a 50-step interval, the 64-case batched set near
@@ -26,11 +22,9 @@ fastest.  The knobs interact (4 workgroups per CU win at one sort interval
 and lose at another), so when the calibration run says that every
 combination fits in JOINT_BUDGET_SECONDS the tuner tries them all;
 otherwise one knob at a time: the sort interval, then the workgroups per
-CU at that interval, then the lanes per list.  Last, for a batch of several
-cases, the lockstep groups (each on a stream of its own, one group's head
-overlapping another's particle launch: 2 groups gain 10-26% on the batched
-sets, 3 or 4 a few percent more, depending on the set) at the chosen
-schedule.  The cases evolve while they are measured
+CU at that interval.  Last, for a batch of several cases, the lockstep
+groups (each on a stream of its own, one group's launch ramp and tail
+overlapping another's streaming) at the chosen schedule.  The cases evolve while they are measured
 (a seeded plasma loses or gains particles for many cycles), so the
 candidates of a knob run in a mirrored order (A B C D D C B A) and each
 one's rate pools its two trials: a linear drift of the throughput cancels.
@@ -60,13 +54,12 @@ from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 DEFAULT_CANDIDATES = (25, 50, 100, 200)  # sort intervals (steps)
 DEFAULT_WG_CANDIDATES = (0, 4, 3)        # particle workgroups per CU (0: all that fit)
-DEFAULT_LANE_CANDIDATES = (64, 16)       # lanes per event list in the head
 DEFAULT_GROUP_CANDIDATES = (2, 3, 4)     # lockstep groups of a multi-case batch
 MAX_TRIAL_STEPS = 8000
 MAX_TRIAL_STRETCH = 8       # at most this many windows per trial
 MIN_TRIAL_SECONDS = 0.3     # calibration target per trial
 MARGIN = 0.002              # rates this close to the fastest count as a tie
-DEFAULTS = {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 64, "groups": 2}
+DEFAULTS = {"sort_every": 100, "part_wg_per_cu": 0, "groups": 2}
 JOINT_BUDGET_SECONDS = 60.0  # all combinations tried together below this estimate
 _chosen: Dict[int, Dict[str, int]] = {}  # last choice the tuner set, per context object
 
@@ -78,7 +71,6 @@ class Trial:
     seconds: float
     particle_steps: int
     wg_per_cu: int = 0   # the particle workgroups per CU of the trial
-    lanes: int = 64      # the lanes per event list of the trial
     groups: int = 2      # the lockstep groups the trial ran as (set by the tuner)
 
     @property
@@ -125,14 +117,12 @@ def trial_steps(cases: Sequence, candidates: Sequence[int]) -> Tuple[int, Dict[i
     return steps, base
 
 
-def measure(ctx, cases: Sequence, interval: int, steps: int, warm_steps: int, wg_per_cu: int = 0,
-            lanes: int = 64) -> Trial:
+def measure(ctx, cases: Sequence, interval: int, steps: int, warm_steps: int, wg_per_cu: int = 0) -> Trial:
     """Advance `cases` by warm_steps (graph capture, first sort) and then by
     `steps` timed steps with the given schedule."""
     from . import edupic
     ctx.set_option(edupic.OPT_SORT_EVERY, interval)
     ctx.set_option(edupic.OPT_PART_WG_PER_CU, wg_per_cu)
-    ctx.set_option(edupic.OPT_APPLY_LANES, lanes)
     if warm_steps > 0:
         ctx.advance_steps(list(cases), [warm_steps] * len(cases))
     ctx.sync()
@@ -143,7 +133,7 @@ def measure(ctx, cases: Sequence, interval: int, steps: int, warm_steps: int, wg
     t1 = time.perf_counter()
     c1 = [c.counts() for c in cases]
     ps = sum((b["psteps_e"] - a["psteps_e"]) + (b["psteps_i"] - a["psteps_i"]) for a, b in zip(c0, c1))
-    return Trial(interval, steps, t1 - t0, ps, wg_per_cu, lanes)
+    return Trial(interval, steps, t1 - t0, ps, wg_per_cu)
 
 
 def _mirrored(values: Sequence[int], trial: Callable[[int], Trial]) -> List[Trial]:
@@ -174,10 +164,6 @@ def _dist_wg(w):
     return 0.0 if w == 0 else 1.0 / w
 
 
-def _dist_lanes(v):
-    return abs(math.log2(v / DEFAULTS["apply_lanes"]))
-
-
 def _dist_groups(g):
     return abs(g - DEFAULTS["groups"])
 
@@ -187,13 +173,12 @@ def _check(candidates, lo, what):
         raise ValueError(f"{what} candidates must be >= {lo}")
 
 
-def _apply(ctx, sort_every: int, wg: int, lanes: int, groups: int):
+def _apply(ctx, sort_every: int, wg: int, groups: int):
     from . import edupic
     ctx.set_option(edupic.OPT_SORT_EVERY, sort_every)
     ctx.set_option(edupic.OPT_PART_WG_PER_CU, wg)
-    ctx.set_option(edupic.OPT_APPLY_LANES, lanes)
     ctx.set_option(edupic.OPT_GROUPS, groups)
-    _chosen[id(ctx)] = {"sort_every": sort_every, "part_wg_per_cu": wg, "apply_lanes": lanes, "groups": groups}
+    _chosen[id(ctx)] = {"sort_every": sort_every, "part_wg_per_cu": wg, "groups": groups}
 
 
 def snapshot(cases: Sequence) -> List:
@@ -208,19 +193,17 @@ def restore(cases: Sequence, snap: List):
 
 
 def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CANDIDATES,
-                  wg_candidates: Sequence[int] = DEFAULT_WG_CANDIDATES,
-                  lane_candidates: Sequence[int] = DEFAULT_LANE_CANDIDATES, cache_path: Optional[str] = None,
+                  wg_candidates: Sequence[int] = DEFAULT_WG_CANDIDATES, cache_path: Optional[str] = None,
                   measure_fn: Optional[Callable[..., Trial]] = None,
                   restore_state: bool = False,
                   group_candidates: Sequence[int] = DEFAULT_GROUP_CANDIDATES) -> Tuple[Dict[str, int], List[Trial]]:
     """Pick the fastest sort interval, then the fastest particle workgroups
-    per CU at that interval, then the fastest lanes per event list, then (a
-    batch of several cases) the fastest lockstep groups, and set them on the
-    context.  Returns ({"sort_every", "part_wg_per_cu", "apply_lanes",
-    "groups"}, trials); no trials when the cache answered.  Empty
-    `wg_candidates` leave the workgroups at all that fit, empty
-    `lane_candidates` the lanes at 64, empty `group_candidates` (or a
-    batch with fewer cases than two of them) the groups at 2.  Every trial
+    per CU at that interval, then (a batch of several cases) the fastest
+    lockstep groups, and set them on the context.  Returns ({"sort_every",
+    "part_wg_per_cu", "groups"}, trials); no trials when the cache answered.
+    Empty `wg_candidates` leave the workgroups at all that fit, empty
+    `group_candidates` (or a batch with fewer cases than two of them) the
+    groups at 2.  Every trial
     before the groups stage runs with 2 groups.  With restore_state every
     trial starts from the cases' state at the call, and the cases end in
     it."""
@@ -228,23 +211,20 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
     _check(candidates, 1, "sort interval")
     if wg_candidates:
         _check(wg_candidates, 0, "workgroup")
-    if lane_candidates and any(int(v) not in (16, 32, 64) for v in lane_candidates):
-        raise ValueError("lane candidates must be 16, 32 or 64")
     if group_candidates and any(int(g) not in (1, 2, 3, 4) for g in group_candidates):
         raise ValueError("group candidates must be 1..4")
     # more groups than cases run as one group per case: those candidates are
     # the same as the case count
     gs = sorted({min(int(g), len(cases)) for g in group_candidates})
     gs = gs if len(gs) > 1 else []
-    key = (batch_key(cases) + (":wg" if wg_candidates else "") + (":lanes" if lane_candidates else "") +
-           (":groups" if gs else ""))
+    key = batch_key(cases) + (":wg" if wg_candidates else "") + (":groups" if gs else "")
     cache: Dict[str, Dict] = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
         if key in cache:
             hit = cache[key]
-            _apply(ctx, int(hit["sort_every"]), int(hit.get("part_wg_per_cu", 0)), int(hit.get("apply_lanes", 64)),
+            _apply(ctx, int(hit["sort_every"]), int(hit.get("part_wg_per_cu", 0)),
                    int(hit.get("groups", DEFAULTS["groups"])))
             return dict(_chosen[id(ctx)]), []
     ctx.set_option(edupic.OPT_GROUPS, DEFAULTS["groups"])
@@ -259,39 +239,32 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
     # calibration (not counted; also a warm-up): stretch the trials of a fast
     # batch to MIN_TRIAL_SECONDS, by whole windows
     k0 = int(candidates[0])
-    cal = run(ctx, cases, k0, steps, min(base[k0], MAX_TRIAL_STEPS), 0, 64)
+    cal = run(ctx, cases, k0, steps, min(base[k0], MAX_TRIAL_STEPS), 0)
     if 0 < cal.seconds < MIN_TRIAL_SECONDS:
         steps *= min(MAX_TRIAL_STRETCH, math.ceil(MIN_TRIAL_SECONDS / cal.seconds))
     per_trial = cal.seconds * steps / cal.steps if cal.steps else 0.0
     ks = [int(k) for k in candidates]
     ws = [int(w) for w in wg_candidates] or [0]
-    ls = [int(v) for v in lane_candidates] or [64]
-    combos = [(k, w, v) for k in ks for w in ws for v in ls]
+    combos = [(k, w) for k in ks for w in ws]
     if len(combos) > 1 and 2 * len(combos) * per_trial <= JOINT_BUDGET_SECONDS:
         # every combination, in one mirrored sequence; ties go to the
         # combination nearest the defaults
         idx = list(range(len(combos)))
         trials = _mirrored(idx, lambda i: run(ctx, cases, combos[i][0], steps, min(base[combos[i][0]], MAX_TRIAL_STEPS),
-                                              combos[i][1], combos[i][2]))
+                                              combos[i][1]))
         top = max(t.rate for t in trials)
         near = [t for t in trials if t.rate >= top / (1.0 + MARGIN)]
-        win = min(near, key=lambda t: (_dist_sort(t.interval) + _dist_wg(t.wg_per_cu) + _dist_lanes(t.lanes),
-                                       t.interval, t.wg_per_cu, t.lanes))
-        best_k, best_w, best_l = win.interval, win.wg_per_cu, win.lanes
+        win = min(near, key=lambda t: (_dist_sort(t.interval) + _dist_wg(t.wg_per_cu), t.interval, t.wg_per_cu))
+        best_k, best_w = win.interval, win.wg_per_cu
     else:
-        trials = _mirrored(ks, lambda k: run(ctx, cases, k, steps, min(base[k], MAX_TRIAL_STEPS), 0, 64))
+        trials = _mirrored(ks, lambda k: run(ctx, cases, k, steps, min(base[k], MAX_TRIAL_STEPS), 0))
         best_k = _pick(trials, "interval", DEFAULTS["sort_every"], _dist_sort)
         warm = min(base[best_k], MAX_TRIAL_STEPS)
         best_w = 0
         if wg_candidates:
-            wt = _mirrored(ws, lambda w: run(ctx, cases, best_k, steps, warm, w, 64))
+            wt = _mirrored(ws, lambda w: run(ctx, cases, best_k, steps, warm, w))
             best_w = _pick(wt, "wg_per_cu", DEFAULTS["part_wg_per_cu"], _dist_wg)
             trials += wt
-        best_l = 64
-        if lane_candidates:
-            lt = _mirrored(ls, lambda v: run(ctx, cases, best_k, steps, warm, best_w, v))
-            best_l = _pick(lt, "lanes", DEFAULTS["apply_lanes"], _dist_lanes)
-            trials += lt
     # the groups these trials ran as (a batch smaller than the option runs
     # as one group per case)
     trials = [replace(t, groups=min(DEFAULTS["groups"], len(cases))) for t in trials]
@@ -299,16 +272,15 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
     if gs:
         def group_trial(g):
             ctx.set_option(edupic.OPT_GROUPS, g)
-            return replace(run(ctx, cases, best_k, steps, min(base[best_k], MAX_TRIAL_STEPS), best_w, best_l),
-                           groups=g)
+            return replace(run(ctx, cases, best_k, steps, min(base[best_k], MAX_TRIAL_STEPS), best_w), groups=g)
         gt = _mirrored(gs, group_trial)
         best_g = _pick(gt, "groups", DEFAULTS["groups"], _dist_groups)
         trials += gt
     if snap is not None:
         restore(cases, snap)
-    _apply(ctx, best_k, best_w, best_l, best_g)
+    _apply(ctx, best_k, best_w, best_g)
     if cache_path:
-        cache[key] = {"sort_every": best_k, "part_wg_per_cu": best_w, "apply_lanes": best_l, "groups": best_g,
+        cache[key] = {"sort_every": best_k, "part_wg_per_cu": best_w, "groups": best_g,
                       "trials": [dict(asdict(t), rate=t.rate) for t in trials]}
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:
@@ -320,7 +292,6 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
 def tune_sort_interval(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CANDIDATES,
                        cache_path: Optional[str] = None,
                        measure_fn: Optional[Callable[..., Trial]] = None) -> Tuple[int, List[Trial]]:
-    """The sort interval alone (all workgroups that fit, 64 lanes per list,
-    2 groups)."""
-    choice, trials = tune_schedule(ctx, cases, candidates, (), (), cache_path, measure_fn, group_candidates=())
+    """The sort interval alone (all workgroups that fit, 2 groups)."""
+    choice, trials = tune_schedule(ctx, cases, candidates, (), cache_path, measure_fn, group_candidates=())
     return choice["sort_every"], trials

@@ -26,20 +26,19 @@ def test_tuning_loses_no_step_and_changes_nothing(ctx):
     ctx.set_option(edupic.OPT_MODE, 1)
     try:
         gs = [_make(ctx, c, st, 0) for c, st in mix]
-        choice, trials = tune.tune_schedule(ctx, gs, candidates=(5, 10, 40), wg_candidates=(0, 2),
-                                            lane_candidates=(64, 16))
+        choice, trials = tune.tune_schedule(ctx, gs, candidates=(5, 10, 40), wg_candidates=(0, 2))
         assert choice["sort_every"] in (5, 10, 40) and choice["part_wg_per_cu"] in (0, 2)
-        assert choice["apply_lanes"] in (64, 16)
         assert tune.last_schedule(ctx) == choice
-        # one knob at a time (3 + 2 + 2) or, for cases this cheap, every combination (3 x 2 x 2)
-        assert len(trials) in (7, 12) and all(t.rate > 0 for t in trials)
+        # one knob at a time (3 + 2) or, for cases this cheap, every
+        # combination (3 x 2), then the groups (2 and 3 for these two cases:
+        # capped at 2, nothing to try)
+        assert len(trials) in (5, 6) and all(t.rate > 0 for t in trials)
         say(f"chosen {choice}; rates {[round(t.rate / 1e9, 2) for t in trials]} G/s")
         tuned = [_result(g) for g in gs]
         total = tuned[0][3]["step"]
         assert total > 0 and all(r[3]["step"] == total for r in tuned)
         ctx.set_option(edupic.OPT_SORT_EVERY, 7)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, 1)
-        ctx.set_option(edupic.OPT_APPLY_LANES, 32)
         for (c, st), r in zip(mix, tuned):
             g = _make(ctx, c, st, 0)
             g.advance_steps(total)
@@ -51,7 +50,6 @@ def test_tuning_loses_no_step_and_changes_nothing(ctx):
         ctx.set_option(edupic.OPT_MODE, 0)
         ctx.set_option(edupic.OPT_SORT_EVERY, 100)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, 0)
-        ctx.set_option(edupic.OPT_APPLY_LANES, 64)
 
 
 def test_tuning_with_restore_leaves_the_cases_unchanged(ctx):
@@ -66,9 +64,8 @@ def test_tuning_with_restore_leaves_the_cases_unchanged(ctx):
         for g in gs:
             g.advance_steps(40)
         before = [_result(g) for g in gs]
-        choice, trials = tune.tune_schedule(ctx, gs, candidates=(5, 10), wg_candidates=(0, 2),
-                                            lane_candidates=(64, 16), restore_state=True)
-        assert len(trials) in (6, 8) and all(t.rate > 0 for t in trials)
+        choice, trials = tune.tune_schedule(ctx, gs, candidates=(5, 10), wg_candidates=(0, 2), restore_state=True)
+        assert len(trials) == 4 and all(t.rate > 0 for t in trials)
         for g, b in zip(gs, before):
             a = _result(g)
             assert a[3]["step"] == b[3]["step"] == 43
@@ -80,7 +77,6 @@ def test_tuning_with_restore_leaves_the_cases_unchanged(ctx):
         ctx.set_option(edupic.OPT_MODE, 0)
         ctx.set_option(edupic.OPT_SORT_EVERY, 100)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, 0)
-        ctx.set_option(edupic.OPT_APPLY_LANES, 64)
 
 
 def test_group_stage_on_library_cases(ctx):
@@ -94,7 +90,7 @@ def test_group_stage_on_library_cases(ctx):
     try:
         gs = [_make(ctx, c, st, 0) for c, st in mix]
         before = [_result(g) for g in gs]
-        choice, trials = tune.tune_schedule(ctx, gs, candidates=(10,), wg_candidates=(), lane_candidates=(),
+        choice, trials = tune.tune_schedule(ctx, gs, candidates=(10,), wg_candidates=(),
                                             group_candidates=(1, 2, 3, 4), restore_state=True)
         assert [t.groups for t in trials] == [2, 1, 2, 3] and all(t.rate > 0 for t in trials)
         assert choice["groups"] in (1, 2, 3) and tune.last_schedule(ctx) == choice
@@ -118,6 +114,5 @@ def test_workgroup_option_is_validated(ctx):
     for bad in (-1, 65):
         with pytest.raises(edupic.EdpError):
             ctx.set_option(edupic.OPT_PART_WG_PER_CU, bad)
-    for bad in (0, 8, 128):
-        with pytest.raises(edupic.EdpError):
-            ctx.set_option(edupic.OPT_APPLY_LANES, bad)
+    with pytest.raises(edupic.EdpError):
+        ctx.set_option(10, 64)  # no such option

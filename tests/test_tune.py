@@ -28,9 +28,9 @@ def model(cost):
     """A measure function from a per-step cost model: seconds = steps x cost(k)."""
     calls = []
 
-    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+    def run(ctx, cases, k, steps, warm, wg=0):
         calls.append((k, steps, warm))
-        return tune.Trial(k, steps, steps * cost(k), steps * 1000, wg, lanes)
+        return tune.Trial(k, steps, steps * cost(k), steps * 1000, wg)
     return run, calls
 
 
@@ -65,8 +65,8 @@ def test_mirrored_order_cancels_a_linear_drift():
     ctx = FakeCtx()
     n = [0]
 
-    def run(ctx_, cases, k, steps, warm, wg=0, lanes=64):
-        t = tune.Trial(k, steps, steps * 1.0, int(steps * 1000 * (1.0 - 0.05 * n[0])), wg, lanes)
+    def run(ctx_, cases, k, steps, warm, wg=0):
+        t = tune.Trial(k, steps, steps * 1.0, int(steps * 1000 * (1.0 - 0.05 * n[0])), wg)
         n[0] += 1
         return t
     k, trials = tune.tune_sort_interval(ctx, [FakeCase(1_000_000, 1000, 20)], measure_fn=run)
@@ -97,27 +97,30 @@ def test_schedule_tunes_the_workgroups_at_the_chosen_interval(tmp_path):
     per CU (0: all that fit) are tried in a mirrored order as well."""
     calls = []
 
-    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
-        calls.append((k, wg, lanes, warm))
-        cost = 22.0 + 70.0 / k + 0.03 * k + {0: 1.0, 4: 0.0, 3: 0.5}[wg] + {64: 0.3, 16: 0.0}[lanes]
-        return tune.Trial(k, steps, steps * cost, steps * 1000, wg, lanes)
+    def run(ctx, cases, k, steps, warm, wg=0):
+        calls.append((k, wg, warm))
+        cost = 22.0 + 70.0 / k + 0.03 * k + {0: 1.0, 4: 0.0, 3: 0.5}[wg]
+        return tune.Trial(k, steps, steps * cost, steps * 1000, wg)
     ctx = FakeCtx()
     path = str(tmp_path / "t.json")
-    choice, trials = tune.tune_schedule(ctx, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run,
-                                        group_candidates=())
-    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "apply_lanes": 16, "groups": 2}
+    # a slow batch (above the joint budget): one knob at a time
+    tune.JOINT_BUDGET_SECONDS, saved = 0.0, tune.JOINT_BUDGET_SECONDS
+    try:
+        choice, trials = tune.tune_schedule(ctx, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path,
+                                            measure_fn=run, group_candidates=())
+    finally:
+        tune.JOINT_BUDGET_SECONDS = saved
+    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "groups": 2}
     assert ctx.options[edupic.OPT_SORT_EVERY] == 50 and ctx.options[edupic.OPT_PART_WG_PER_CU] == 4
-    assert ctx.options[edupic.OPT_APPLY_LANES] == 16
-    assert [(k, w) for k, w, _, _ in calls[9:15]] == [(50, 0), (50, 4), (50, 3), (50, 3), (50, 4), (50, 0)]
-    assert [(k, w, ln) for k, w, ln, _ in calls[15:]] == [(50, 4, 64), (50, 4, 16), (50, 4, 16), (50, 4, 64)]
-    assert all(warm == 1000 for _, _, _, warm in calls[9:])
-    assert len(trials) == 9
+    assert [(k, w) for k, w, _ in calls[9:15]] == [(50, 0), (50, 4), (50, 3), (50, 3), (50, 4), (50, 0)]
+    assert all(warm == 1000 for _, _, warm in calls[9:])
+    assert len(trials) == 7
     entry, = json.load(open(path)).values()
-    assert entry["sort_every"] == 50 and entry["part_wg_per_cu"] == 4 and entry["apply_lanes"] == 16
+    assert entry["sort_every"] == 50 and entry["part_wg_per_cu"] == 4
     ctx2 = FakeCtx()
     assert tune.tune_schedule(ctx2, [FakeCase(1_000_000, 1000, 20)] * 4, cache_path=path, measure_fn=run,
                               group_candidates=())[1] == []
-    assert ctx2.options[edupic.OPT_PART_WG_PER_CU] == 4 and ctx2.options[edupic.OPT_APPLY_LANES] == 16
+    assert ctx2.options[edupic.OPT_PART_WG_PER_CU] == 4
 
 
 def test_short_trials_are_stretched_by_whole_windows():
@@ -125,9 +128,9 @@ def test_short_trials_are_stretched_by_whole_windows():
     every trial runs 10 windows of the common length (capped)."""
     steps_seen = []
 
-    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+    def run(ctx, cases, k, steps, warm, wg=0):
         steps_seen.append(steps)
-        return tune.Trial(k, steps, steps * tune.MIN_TRIAL_SECONDS / 40000, steps * 1000, wg, lanes)
+        return tune.Trial(k, steps, steps * tune.MIN_TRIAL_SECONDS / 40000, steps * 1000, wg)
     tune.tune_sort_interval(FakeCtx(), [FakeCase(10_000, 200, 20)], measure_fn=run)
     assert steps_seen[0] == 4000
     assert all(st == 4000 * min(10, tune.MAX_TRIAL_STRETCH) for st in steps_seen[1:])
@@ -135,41 +138,44 @@ def test_short_trials_are_stretched_by_whole_windows():
 
 def test_a_default_within_the_margin_is_kept():
     """Noise-level differences do not move a knob off the library default."""
-    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
-        gain = 1.0 + (0.001 if wg == 4 else 0.0) + (0.02 if lanes == 16 else 0.0)
-        return tune.Trial(k, steps, steps / gain, steps * 1000, wg, lanes)
+    def run(ctx, cases, k, steps, warm, wg=0):
+        gain = 1.0 + (0.001 if wg == 4 else 0.0) + (0.02 if wg == 3 else 0.0)
+        return tune.Trial(k, steps, steps / gain, steps * 1000, wg)
     choice, _ = tune.tune_schedule(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
-    assert choice == {"sort_every": 100, "part_wg_per_cu": 0, "apply_lanes": 16, "groups": 2}
+    assert choice == {"sort_every": 100, "part_wg_per_cu": 3, "groups": 2}
+    choice, _ = tune.tune_schedule(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], wg_candidates=(0, 4),
+                                   measure_fn=run)
+    assert choice == {"sort_every": 100, "part_wg_per_cu": 0, "groups": 2}
 
 
 def test_a_tie_goes_to_the_value_nearest_the_default():
     """Intervals 25 and 50 within the margin, both well ahead of 100: 50
     (nearer 100) is kept."""
-    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+    def run(ctx, cases, k, steps, warm, wg=0):
         gain = {25: 1.0301, 50: 1.03, 100: 1.0, 200: 0.95}[k]
-        return tune.Trial(k, steps, steps / gain, steps * 1000, wg, lanes)
+        return tune.Trial(k, steps, steps / gain, steps * 1000, wg)
     k, _ = tune.tune_sort_interval(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
     assert k == 50
 
 
 def test_cheap_batches_search_every_combination():
-    """4 workgroups per CU win only together with 16 lanes: one knob at a
-    time would keep (50, all, 64); trials this short fit the joint budget,
-    so every combination is tried and (50, 4, 16) found."""
+    """4 workgroups per CU win only at a 25-step interval: one knob at a time
+    would keep (50, all); trials this short fit the joint budget, so every
+    combination is tried and (25, 4) found."""
     seen = []
 
-    def rate(k, w, lanes):
+    def rate(k, w):
         r = {25: 1.0, 50: 1.05, 100: 1.02, 200: 0.97}[k]
         if w == 4:
-            r *= 1.03 if lanes == 16 else 0.99
+            r *= 1.08 if k == 25 else 0.99
         return r
 
-    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
-        seen.append((k, wg, lanes))
-        return tune.Trial(k, steps, steps * 1e-6 / rate(k, wg, lanes), steps, wg, lanes)
+    def run(ctx, cases, k, steps, warm, wg=0):
+        seen.append((k, wg))
+        return tune.Trial(k, steps, steps * 1e-6 / rate(k, wg), steps, wg)
     choice, trials = tune.tune_schedule(FakeCtx(), [FakeCase(2_000_000, 1000, 20)], measure_fn=run)
-    assert choice == {"sort_every": 50, "part_wg_per_cu": 4, "apply_lanes": 16, "groups": 2}
-    assert len(trials) == 4 * 3 * 2 and len(seen) == 1 + 2 * 24
+    assert choice == {"sort_every": 25, "part_wg_per_cu": 4, "groups": 2}
+    assert len(trials) == 4 * 3 and len(seen) == 1 + 2 * 12
 
 
 def test_rejects_bad_candidates():
@@ -177,8 +183,6 @@ def test_rejects_bad_candidates():
         tune.tune_sort_interval(FakeCtx(), [FakeCase(1000, 100, 5)], candidates=(0, 10))
     with pytest.raises(ValueError):
         tune.tune_schedule(FakeCtx(), [FakeCase(1000, 100, 5)], wg_candidates=(4, -1))
-    with pytest.raises(ValueError):
-        tune.tune_schedule(FakeCtx(), [FakeCase(1000, 100, 5)], lane_candidates=(64, 8))
 
 
 def test_groups_are_tuned_last_for_a_batch_of_cases(tmp_path):
@@ -187,29 +191,28 @@ def test_groups_are_tuned_last_for_a_batch_of_cases(tmp_path):
     trial runs with 2 groups; the choice is set and cached."""
     calls = []
 
-    def run(ctx, cases, k, steps, warm, wg=0, lanes=64):
+    def run(ctx, cases, k, steps, warm, wg=0):
         g = ctx.options[edupic.OPT_GROUPS]
-        calls.append((k, wg, lanes, g))
+        calls.append((k, wg, g))
         cost = 22.0 + 70.0 / k + 0.03 * k + {2: 1.0, 3: 0.0, 4: 0.4}[g]
-        return tune.Trial(k, steps, steps * cost, steps * 1000, wg, lanes)
+        return tune.Trial(k, steps, steps * cost, steps * 1000, wg)
     ctx = FakeCtx()
     path = str(tmp_path / "g.json")
     cases = [FakeCase(300_000, 1000, 20)] * 5
-    choice, trials = tune.tune_schedule(ctx, cases, wg_candidates=(), lane_candidates=(), cache_path=path,
-                                        measure_fn=run)
-    assert choice == {"sort_every": 50, "part_wg_per_cu": 0, "apply_lanes": 64, "groups": 3}
+    choice, trials = tune.tune_schedule(ctx, cases, wg_candidates=(), cache_path=path, measure_fn=run)
+    assert choice == {"sort_every": 50, "part_wg_per_cu": 0, "groups": 3}
     assert ctx.options[edupic.OPT_GROUPS] == 3
-    assert all(g == 2 for _, _, _, g in calls[:9])
-    assert [g for _, _, _, g in calls[9:]] == [2, 3, 4, 4, 3, 2]
-    assert all(k == 50 for k, _, _, _ in calls[9:])
+    assert all(g == 2 for _, _, g in calls[:9])
+    assert [g for _, _, g in calls[9:]] == [2, 3, 4, 4, 3, 2]
+    assert all(k == 50 for k, _, _ in calls[9:])
     assert [t.groups for t in trials] == [2] * 4 + [2, 3, 4]
     assert json.load(open(path))[tune.batch_key(cases) + ":groups"]["groups"] == 3
     # two cases: 3 and 4 groups are 2 groups, nothing to try
     calls.clear()
-    choice, trials = tune.tune_schedule(FakeCtx(), cases[:2], wg_candidates=(), lane_candidates=(), measure_fn=run)
-    assert choice["groups"] == 2 and len(trials) == 4 and all(g == 2 for _, _, _, g in calls)
+    choice, trials = tune.tune_schedule(FakeCtx(), cases[:2], wg_candidates=(), measure_fn=run)
+    assert choice["groups"] == 2 and len(trials) == 4 and all(g == 2 for _, _, g in calls)
     # one case runs alone whatever the option says
-    _, trials = tune.tune_schedule(FakeCtx(), cases[:1], wg_candidates=(), lane_candidates=(), measure_fn=run)
+    _, trials = tune.tune_schedule(FakeCtx(), cases[:1], wg_candidates=(), measure_fn=run)
     assert [t.groups for t in trials] == [1] * 4
     with pytest.raises(ValueError):
         tune.tune_schedule(FakeCtx(), cases, group_candidates=(2, 5), measure_fn=run)
