@@ -126,9 +126,9 @@ struct CaseDev {
   // workgroups share an address); the window-end kernel folds the shards
   // into the counters and clears them.
   int64_t* shard;
-  // Colliders a particle workgroup's streaming loop found, per species
-  // [cap]: workgroup j writes slot | process << 32 into its own chunk range
-  // and applies them after the loop.
+  // Collision candidates a particle workgroup's streaming loop could not
+  // keep in LDS, per species [cap]: workgroup j writes their slots into its
+  // own chunk range and tests them after the loop.
   int64_t* clist[2];
   // ---- dynamic (device-mutated) -----------------------------------------
   int64_t step;       // next step to run (advanced at the end of a window)

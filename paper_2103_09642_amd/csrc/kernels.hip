@@ -288,81 +288,117 @@ __device__ __forceinline__ void fold_particle_sums(const EDP_CONST CaseDev* __re
 // Rows of the flux scan per thread at the largest grid.
 constexpr int kScanRows = (kMaxNodes - 2 + kBlock - 1) / kBlock;
 
+// Per-node duties of a step's writer: rho for reads, the time sums of the
+// densities, the deposit rings the next steps refill cleared, the particle
+// sums of step s-1 folded with the field that step used (still in efield[];
+// it is overwritten after the workgroup's next barrier), the xt rows of the
+// densities.
+struct FieldWriter {
+  const EDP_CONST CaseDev* C;
+  int64_t s, k;
+  int ng;
+  bool ion_step, xt;
+  size_t plane, row, row_prev;
+  __device__ __forceinline__ void node(int p, double ne, double ni, double rho) const {
+    const uint32_t fl = C->flags;
+    G(C->rho)[p] = rho;
+    if (fl & kDiagDensity) {
+      G(C->sum_ne)[p] += ne;
+      G(C->sum_ni)[p] += ni;
+    }
+    G(C->cnt_e)[((s + 2) % 3) * ng + p] = 0;
+    if (ion_step) G(C->cnt_i)[((k + 2) % 3) * ng + p] = 0;
+    if (fl & (kDiagCurrent | kDiagMeanE | kDiagXT)) fold_particle_sums(C, p, ((s + 2) % 3) * ng, row_prev, plane);
+    if (xt) {
+      EDP_GLOBAL double* __restrict__ X = G(C->xt);
+      X[kXtNe * plane + row + p] += ne;
+      X[kXtNi * plane + row + p] += ni;
+    }
+  }
+  // the node's field E and flux f (phi for the Thomas solve: MODE 1)
+  template <int MODE>
+  __device__ __forceinline__ void out(int p, double e, double f, double phi) const {
+    G(C->efield)[p] = e;
+    if (MODE == 1)
+      G(C->phi)[p] = phi;
+    else
+      G(C->flux)[p] = f;
+    if (xt) {
+      EDP_GLOBAL double* __restrict__ X = G(C->xt);
+      X[kXtEf * plane + row + p] += e;
+      X[kXtFlux * plane + row + p] += f;
+    }
+  }
+};
+
 // Steps 1-2 of step s, computed by every workgroup that needs E (each
 // particle workgroup of a lockstep launch, the small-case workgroup): the
 // densities of the deposit rings read at step s, rho, the potential and E on
-// the nodes into sE (LDS).  sF: ng doubles of LDS scratch.  The ring and V(t)
-// pointers come with the workgroup's role.  The results depend only on the
-// deposit, so every workgroup gets the same bits.  The writer (one workgroup
-// per case and step) also stores rho, E and the fluxes (or phi) for reads,
-// clears the deposit rings the next steps refill, adds the measurement sums
-// and counts the step.
+// the nodes into sE (LDS).  sF: ng doubles of LDS scratch (the Thomas
+// solve).  The ring and V(t) pointers come with the workgroup's role.  The
+// results depend only on the deposit, so every workgroup gets the same bits.
+// The writer (one workgroup per case and step) also stores rho, E and the
+// fluxes (or phi) for reads, clears the deposit rings the next steps refill,
+// adds the measurement sums and counts the step.
 template <int MODE>
 __device__ __forceinline__ void solve_field(CaseDev* __restrict__ Cw, const int64_t* __restrict__ cnt_e,
                                             const int64_t* __restrict__ cnt_i, const double* __restrict__ volt,
                                             const int ng, const int nsub, const int64_t s, double* sE, double* sF,
                                             const bool writer) {
-  __shared__ int64_t sRed[64];
+  __shared__ double sWave[2][kBlock / kWave];
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int64_t k = s / nsub;
   const bool ion_step = (s % nsub) == 0;
   const EDP_GLOBAL int64_t* cntE = G(cnt_e) + (s % 3) * ng;
   const EDP_GLOBAL int64_t* cntI = G(cnt_i) + (k % 3) * ng;
   const int t = (int)threadIdx.x;
-  // every load of the thread's nodes first (one memory round trip)
-  int64_t ce[kGridPerThread], ci[kGridPerThread];
-#pragma unroll
-  for (int q = 0; q < kGridPerThread; ++q) {
-    const int p = t + q * kBlock;
-    ce[q] = p < ng ? cntE[p] : 0;
-    ci[q] = p < ng ? cntI[p] : 0;
-  }
+  const int lane = t % kWave, wv = t / kWave;
   const double V = G(volt)[s % kVoltChunk];
   const double scale = C->dens_scale;
   const double kp = C->kpois;
-  const uint32_t fl = C->flags;
-  const bool xt = writer && (fl & kDiagXT) != 0;
+  const double dx = C->dx;
+  FieldWriter W;
+  W.C = C;
+  W.s = s;
+  W.k = k;
+  W.ng = ng;
+  W.ion_step = ion_step;
+  W.xt = writer && (C->flags & kDiagXT) != 0;
   const int64_t nt = C->nt, nxb = C->n_xt_bin;
-  const size_t plane = (size_t)C->n_xt * (size_t)ng;
-  const size_t row = xt ? (size_t)((s % nt) / nxb) * (size_t)ng : 0;
-  const size_t row_prev = xt ? (size_t)(((s + nt - 1) % nt) / nxb) * (size_t)ng : 0;
-  EDP_GLOBAL double* __restrict__ X = G(C->xt);
-  // densities (the electrodes' half cells count twice) and rho into sE; for
-  // the Thomas solve also its right-hand side d_p = rho_p dx^2/eps0 into sF
-#pragma unroll
-  for (int q = 0; q < kGridPerThread; ++q) {
-    const int p = t + q * kBlock;
-    if (p >= ng) break;
-    double ne = (double)ce[q] * scale;
-    double ni = (double)ci[q] * scale;
+  W.plane = (size_t)C->n_xt * (size_t)ng;
+  W.row = W.xt ? (size_t)((s % nt) / nxb) * (size_t)ng : 0;
+  W.row_prev = W.xt ? (size_t)(((s + nt - 1) % nt) / nxb) * (size_t)ng : 0;
+  // densities (the electrodes' half cells count twice) and rho of node p
+  auto dens = [&](int p, int64_t ce, int64_t ci, double& ne, double& ni) {
+    ne = (double)ce * scale;
+    ni = (double)ci * scale;
     if (p == 0 || p == ng - 1) {
       ne *= 2.0;
       ni *= 2.0;
     }
-    const double rho = kECharge * (ni - ne);
-    sE[p] = rho;
-    if (MODE == 1) sF[p] = rho * kp;
-    if (writer) {
-      G(C->rho)[p] = rho;
-      if (fl & kDiagDensity) {
-        G(C->sum_ne)[p] += ne;
-        G(C->sum_ni)[p] += ni;
-      }
-      G(C->cnt_e)[((s + 2) % 3) * ng + p] = 0;
-      if (ion_step) G(C->cnt_i)[((k + 2) % 3) * ng + p] = 0;
-      // the particle sums of step s-1, with the field that step used (still
-      // in efield[]; it is overwritten below, after the barriers)
-      if (fl & (kDiagCurrent | kDiagMeanE | kDiagXT)) fold_particle_sums(C, p, ((s + 2) % 3) * ng, row_prev, plane);
-      if (xt) {
-        X[kXtNe * plane + row + p] += ne;
-        X[kXtNi * plane + row + p] += ni;
-      }
-    }
-  }
-  __syncthreads();
-  const double rho0 = sE[0], rhoN = sE[ng - 1];
-  const double dx = C->dx;
+    return kECharge * (ni - ne);
+  };
   if (MODE == 1) {
+    // node p = t + q kBlock: rho and the right-hand side d_p = rho_p dx^2/eps0
+    int64_t ce[kGridPerThread], ci[kGridPerThread];
+#pragma unroll
+    for (int q = 0; q < kGridPerThread; ++q) {
+      const int p = t + q * kBlock;
+      ce[q] = p < ng ? cntE[p] : 0;
+      ci[q] = p < ng ? cntI[p] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kGridPerThread; ++q) {
+      const int p = t + q * kBlock;
+      if (p >= ng) break;
+      double ne, ni;
+      const double rho = dens(p, ce[q], ci[q], ne, ni);
+      sE[p] = rho;
+      sF[p] = rho * kp;
+      if (writer) W.node(p, ne, ni, rho);
+    }
+    __syncthreads();
+    const double rho0 = sE[0], rhoN = sE[ng - 1];
     if (t == 0) {
       // Thomas algorithm: forward sweep y_p = (d_p + y_{p-1}) r_p, back
       // substitution phi_p = y_p + r_p phi_{p+1}, with the reciprocals r_p
@@ -381,81 +417,113 @@ __device__ __forceinline__ void solve_field(CaseDev* __restrict__ Cw, const int6
       sF[ng - 1] = 0.0;
     }
     __syncthreads();
-  } else {
-    // The flux form of the same tridiagonal system: with F_q = phi_q -
-    // phi_{q+1}, row p of the Poisson equation says F_p - F_{p-1} = d_p, so
-    // F_p = F_0 + S_p with S the prefix sum of d over the interior nodes; the
-    // fluxes add up to phi_0 - phi_{N-1} = V, which fixes
-    // F_0 = (V - sum_p S_p)/(N_g - 1).  Thread t owns the contiguous interior
-    // rows q0 <= q < q0 + nq (row q is node q + 1): a sequential prefix of its
-    // rows, a workgroup scan of the row totals, then the sum of S over the
-    // workgroup.  Slot q + 1 of sF becomes F_{q+1}, slot 0 F_0.
-    const int m = ng - 2;
-    const int R = (m + kBlock - 1) / kBlock;  // <= kScanRows
-    const int q0 = t * R < m ? t * R : m;
-    const int nq = (q0 + R < m ? q0 + R : m) - q0;
-    double v[kScanRows];
-    double acc = 0.0;
-#pragma unroll
-    for (int r = 0; r < kScanRows; ++r) {
-      if (r < nq) acc += sE[q0 + r + 1] * kp;
-      v[r] = acc;  // prefix within the thread
-    }
-    double tot;
-    const double before = block_exclusive_scan_t<double>(acc, sRed, &tot);
-    double mine = 0.0;
-#pragma unroll
-    for (int r = 0; r < kScanRows; ++r) {
-      v[r] = before + v[r];  // S_q
-      if (r < nq) mine += v[r];
-    }
-    double sum_s;
-    (void)block_exclusive_scan_t<double>(mine, sRed, &sum_s);
-    const double F0 = (V - sum_s) / (double)(ng - 1);
-#pragma unroll
-    for (int r = 0; r < kScanRows; ++r)
-      if (r < nq) sF[q0 + r + 1] = F0 + v[r];
-    if (t == 0) sF[0] = F0;
-    __syncthreads();
-  }
-  // E on the nodes: centred differences inside, the boundary forms (Gauss's
-  // law over the half cell) at the electrodes
-  for (int p = t; p < ng; p += kBlock) {
-    double e, f;
-    if (MODE == 1) {
+    for (int p = t; p < ng; p += kBlock) {
+      double e;
       if (p == 0)
         e = (sF[0] - sF[1]) / dx - rho0 * dx / (2.0 * kEps0);
       else if (p == ng - 1)
         e = (sF[ng - 2] - sF[ng - 1]) / dx + rhoN * dx / (2.0 * kEps0);
       else
         e = (sF[p - 1] - sF[p + 1]) / (2.0 * dx);
-      f = p < ng - 1 ? sF[p] - sF[p + 1] : V;
-    } else {
-      if (p == 0)
-        e = sF[0] / dx - rho0 * dx / (2.0 * kEps0);
-      else if (p == ng - 1)
-        e = sF[ng - 2] / dx + rhoN * dx / (2.0 * kEps0);
-      else
-        e = (sF[p - 1] + sF[p]) / (2.0 * dx);
-      f = p < ng - 1 ? sF[p] : V;  // last slot keeps V for phi on demand
+      sE[p] = e;
+      if (writer) W.out<1>(p, e, p < ng - 1 ? sF[p] - sF[p + 1] : V, sF[p]);
     }
-    sE[p] = e;
-    if (writer) {
-      G(C->efield)[p] = e;
-      if (MODE == 1)
-        G(C->phi)[p] = sF[p];
-      else
-        G(C->flux)[p] = f;
-      if (xt) {
-        X[kXtEf * plane + row + p] += e;
-        X[kXtFlux * plane + row + p] += f;
+  } else {
+    // The flux form of the same tridiagonal system: with F_q = phi_q -
+    // phi_{q+1}, row p of the Poisson equation says F_p - F_{p-1} = d_p, so
+    // F_p = F_0 + S_p with S the prefix sum of d over the interior nodes; the
+    // fluxes add up to phi_0 - phi_{N-1} = V, which fixes
+    // F_0 = (V - sum_q S_q)/(N_g - 1), and sum_q S_q = sum_r (m - r) d_r over
+    // the m = N_g - 2 interior rows.  Thread t owns the contiguous rows
+    // q0 <= q < q0 + nq (row q is node q + 1): it loads their densities,
+    // forms its prefix and its share of the weighted sum, and one workgroup
+    // pass (wave scans, one exchange of the wave totals) gives every thread
+    // the rows before its own and the weighted total.  E of its nodes then
+    // follows in registers: E_p = (F_{p-1} + F_p)/(2 dx) inside, the boundary
+    // forms (Gauss's law over the half cell) at the electrodes.
+    const int m = ng - 2;
+    const int R = (m + kBlock - 1) / kBlock;  // <= kScanRows
+    const int q0 = t * R < m ? t * R : m;
+    const int nq = (q0 + R < m ? q0 + R : m) - q0;
+    int64_t ce[kScanRows], ci[kScanRows];
+#pragma unroll
+    for (int r = 0; r < kScanRows; ++r) {
+      ce[r] = r < nq ? cntE[q0 + 1 + r] : 0;
+      ci[r] = r < nq ? cntI[q0 + 1 + r] : 0;
+    }
+    const int64_t ce0 = cntE[0], ci0 = cntI[0], ceN = cntE[ng - 1], ciN = cntI[ng - 1];
+    double v[kScanRows];
+    double acc = 0.0, wsum = 0.0;
+#pragma unroll
+    for (int r = 0; r < kScanRows; ++r) {
+      if (r < nq) {
+        const int p = q0 + 1 + r;
+        double ne, ni;
+        const double rho = dens(p, ce[r], ci[r], ne, ni);
+        if (writer) W.node(p, ne, ni, rho);
+        const double d = rho * kp;
+        acc += d;
+        wsum += d * (double)(m - (q0 + r));
       }
+      v[r] = acc;  // prefix within the thread
+    }
+    double ne0, ni0, neN, niN;
+    const double rho0 = dens(0, ce0, ci0, ne0, ni0);
+    const double rhoN = dens(ng - 1, ceN, ciN, neN, niN);
+    if (writer && t == 0) {
+      W.node(0, ne0, ni0, rho0);
+      W.node(ng - 1, neN, niN, rhoN);
+    }
+    // the workgroup pass: inclusive scan of acc and sum of wsum per wave
+    double inc = acc;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const double y = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += y;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off, kWave);
+    if (lane == kWave - 1) {
+      sWave[0][wv] = inc;
+      sWave[1][wv] = wsum;
+    }
+    __syncthreads();
+    double before = inc - acc, sum_s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kBlock / kWave; ++u) {
+      if (u < wv) before += sWave[0][u];
+      sum_s += sWave[1][u];
+    }
+    const double F0 = (V - sum_s) / (double)(ng - 1);
+    double f_prev = F0 + before;  // F_{q0}: F0 plus the rows before this thread's
+#pragma unroll
+    for (int r = 0; r < kScanRows; ++r) {
+      if (r < nq) {
+        const int p = q0 + 1 + r;
+        const double f = F0 + (before + v[r]);  // F_{q+1} = F_p
+        const double e = (f_prev + f) / (2.0 * dx);
+        sE[p] = e;
+        if (writer) W.out<0>(p, e, f, 0.0);
+        f_prev = f;
+      }
+    }
+    // the electrodes: node 0 by thread 0, node N_g-1 by the owner of the
+    // last row (thread 0 when there are no interior rows)
+    if (t == 0) {
+      const double e = F0 / dx - rho0 * dx / (2.0 * kEps0);
+      sE[0] = e;
+      if (writer) W.out<0>(0, e, F0, 0.0);
+    }
+    if (nq > 0 ? q0 + nq == m : t == 0) {
+      const double e = f_prev / dx + rhoN * dx / (2.0 * kEps0);
+      sE[ng - 1] = e;
+      if (writer) W.out<0>(ng - 1, e, V, 0.0);  // the last flux slot keeps V for phi on demand
     }
   }
   if (writer && t == 0) {
-    if (xt) {
-      G(C->xt_cnt)[row / ng] += 1;
-      if (ion_step) G(C->xt_cnt)[C->n_xt + row / ng] += 1;
+    if (W.xt) {
+      G(C->xt_cnt)[W.row / ng] += 1;
+      if (ion_step) G(C->xt_cnt)[C->n_xt + W.row / ng] += 1;
     }
     Cw->phi_valid = MODE == 1;
     Cw->diag_steps += 1;
@@ -499,35 +567,58 @@ __device__ __forceinline__ ScatterPtrs scatter_ptrs_at(CaseDev* __restrict__ Cw,
   return P;
 }
 
-// Electron-Ar scattering of colliding particle i by process proc (0 elastic,
-// 1 excitation, 2 ionization), from its state after the push (velocity,
-// identity; position for an ionization).  An ionization also writes its
-// newborns: the ejected electron at slot be and the ion at slot bi (-1:
-// dropped at capacity), both at the parent's position.
+// Electron-Ar collisions, from the colliding electron's state after the push
+// (velocity, identity; position for an ionization).  The post-collision
+// velocity is w + f2 g' R(theta,phi)(cos chi, sin chi cos eta, sin chi sin
+// eta) about the centre-of-mass velocity w, with the frame of g from its
+// components and the azimuth eta = 2 pi R_eta; an ionization shares the
+// energy above its threshold between the scattered and the ejected
+// electron, which leaves at the azimuth eta + pi, and creates an ion with a
+// thermal gas velocity.  The three parts are separate functions that
+// recompute what they share from the same inputs (same operations, same
+// bits), so that the scattering code after a particle loop keeps few values
+// alive at once.
+
+// The energy share of an ionization: the COM energy above the threshold
+// [eV] (clamped at 0, counted as an anomaly) and the ejected electron's part
+// e_ej = w tan(R atan(E/(2w))).
+__device__ __forceinline__ void ionization_share(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
+                                                 double v2, uint64_t uid, uint32_t st, double& e_ev, double& e_ej) {
+  double r_share, r_unused;
+  uniform2(C->seed, uid, st, tag(0, 0, 2), r_share, r_unused);
+  e_ev = 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion;
+  if (e_ev < 0.0) e_ev = 0.0;
+  const double w_ion = C->w_ion;
+  e_ej = w_ion * tan(r_share * atan(e_ev / (2.0 * w_ion)));
+}
+
+// Scattering angle of one of the two electrons of an ionization from its
+// energy e and the shared energy e_ev: cos chi = sqrt(e / e_ev) (or, with the
+// literal reading, chi itself).
+__device__ __forceinline__ void ionization_angle(const EDP_CONST CaseDev* __restrict__ C, double e, double e_ev,
+                                                 double& cs, double& sn) {
+  if (C->flags & kIonizLiteral) {
+    const double chi = e_ev > 0.0 ? sqrt(e / e_ev) : 0.0;
+    sincos(chi, &sn, &cs);
+  } else {
+    cs = e_ev > 0.0 ? sqrt(e / e_ev) : 1.0;
+    sn = sqrt(1.0 - cs * cs);
+  }
+}
+
+// The colliding electron i itself, process proc (0 elastic, 1 excitation,
+// 2 ionization): its new velocity.
 __device__ __forceinline__ void electron_scatter_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
-                                                    int64_t i, int proc, int64_t be, int64_t bi, int64_t s,
-                                                    double vxn, double vy, double vz, uint64_t uid, double x) {
-  const uint64_t seed = C->seed;
+                                                    int64_t i, int proc, int64_t s, double vxn, double vy,
+                                                    double vz, uint64_t uid) {
   const uint32_t st = (uint32_t)s;
   // squared speed, the squares summed from x to z as the collision test does
   const double v2 = vxn * vxn + vy * vy + vz * vz;
   const double v = sqrt(v2);
   double r_chi, r_eta;
-  uniform2(seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
-  const double f1 = kEMass / (kEMass + kArMass);
-  const double f2 = kArMass / (kEMass + kArMass);
-  const double wx = f1 * vxn, wy = f1 * vy, wz = f1 * vz;
-  const double eta = kTwoPi * r_eta;
-  // the frame of g and the azimuth are the same for every process: computed
-  // once, outside the branch, so that a wave holding both an ionization and
-  // other events runs them once (the results are those of the same
-  // operations taken per process)
-  const Frame F = frame_of(vxn, vy, vz, v);
-  double cos_eta, sin_eta;
-  sincos(eta, &sin_eta, &cos_eta);
-  double gnew, cos_chi, sin_chi;
+  uniform2(C->seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
+  double gnew = v, cos_chi, sin_chi;
   if (proc < 2) {
-    gnew = v;
     if (proc == 1) {
       double ec = 0.5 * kMuEAr * v2 - C->thr_exc * kEvToJ;
       if (ec < 0.0) {
@@ -539,70 +630,70 @@ __device__ __forceinline__ void electron_scatter_at(const EDP_CONST CaseDev* __r
     cos_chi = 1.0 - 2.0 * r_chi;
     sin_chi = sqrt(1.0 - cos_chi * cos_chi);
   } else {
-    // Every draw of the ionization -- the energy share and the new ion's
-    // thermal velocity -- is taken before the dependent chains, and only the
-    // stores are conditional, so that the independent chains overlap (an
-    // ionization is the longest event of the queue).
-    double r_share, r_unused;
-    uniform2(seed, uid, st, tag(0, 0, 2), r_share, r_unused);
-    const uint64_t cu = child_uid(uid, s, 2);
-    double z0, z1, z2;
-    normals3(seed, cu, st, 1u, 2u, 1u, z0, z1, z2);
-    double cos_eta2, sin_eta2;
-    sincos(eta + kPi, &sin_eta2, &cos_eta2);
-    double e_ev = 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion;
-    if (e_ev < 0.0) {
-      e_ev = 0.0;
-      gl_add(P.anomaly, 1);
-    }
-    const double w_ion = C->w_ion;
-    const double e_ej = w_ion * tan(r_share * atan(e_ev / (2.0 * w_ion)));
+    double e_ev, e_ej;
+    ionization_share(C, P, v2, uid, st, e_ev, e_ej);
+    if (0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion < 0.0) gl_add(P.anomaly, 1);
     const double e_sc = e_ev - e_ej;
-    const double g_sc = sqrt(2.0 * e_sc * kEvToJ / kMuEAr);
-    const double g_ej = sqrt(2.0 * e_ej * kEvToJ / kMuEAr);
-    double cs_sc, sn_sc, cs_ej, sn_ej;
-    if (C->flags & kIonizLiteral) {
-      const double chi_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 0.0;
-      const double chi_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 0.0;
-      sincos(chi_sc, &sn_sc, &cs_sc);
-      sincos(chi_ej, &sn_ej, &cs_ej);
-    } else {
-      cs_sc = e_ev > 0.0 ? sqrt(e_sc / e_ev) : 1.0;
-      cs_ej = e_ev > 0.0 ? sqrt(e_ej / e_ev) : 1.0;
-      sn_sc = sqrt(1.0 - cs_sc * cs_sc);
-      sn_ej = sqrt(1.0 - cs_ej * cs_ej);
-    }
-    // the scattered electron is rotated below with the other processes; the
-    // ejected one, scattered about the same w, here
-    gnew = g_sc;
-    cos_chi = cs_sc;
-    sin_chi = sn_sc;
-    double ex_, ey_, ez_;
-    rotate(F, g_ej, f2, cs_ej, sn_ej, cos_eta2, sin_eta2, wx, wy, wz, ex_, ey_, ez_);
-    if (be >= 0) {
-      P.ex[be] = x;
-      P.evx[be] = ex_;
-      P.evy[be] = ey_;
-      P.evz[be] = ez_;
-      P.evp2[be] = float_above(ey_ * ey_ + ez_ * ez_);
-      P.euid[be] = child_uid(uid, s, 1);
-    }
-    if (bi >= 0) {  // the new ion: a thermal gas velocity
-      const double sa = C->sigma_a;
-      P.ix[bi] = x;
-      P.ivx[bi] = sa * z0;
-      P.ivy[bi] = sa * z1;
-      P.ivz[bi] = sa * z2;
-      P.iuid[bi] = cu;
-    }
+    gnew = sqrt(2.0 * e_sc * kEvToJ / kMuEAr);
+    ionization_angle(C, e_sc, e_ev, cos_chi, sin_chi);
   }
+  const double f1 = kEMass / (kEMass + kArMass);
+  const double f2 = kArMass / (kEMass + kArMass);
+  const Frame F = frame_of(vxn, vy, vz, v);
+  double cos_eta, sin_eta;
+  sincos(kTwoPi * r_eta, &sin_eta, &cos_eta);
   double ox, oy, oz;
-  rotate(F, gnew, f2, cos_chi, sin_chi, cos_eta, sin_eta, wx, wy, wz, ox, oy, oz);
+  rotate(F, gnew, f2, cos_chi, sin_chi, cos_eta, sin_eta, f1 * vxn, f1 * vy, f1 * vz, ox, oy, oz);
   P.evx[i] = ox;
   P.evy[i] = oy;
   P.evz[i] = oz;
   P.evp2[i] = float_above(oy * oy + oz * oz);
 }
+
+// The electron an ionization ejects, at slot be, from the parent's state.
+__device__ __forceinline__ void electron_eject_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
+                                                  int64_t be, int64_t s, double vxn, double vy, double vz,
+                                                  uint64_t uid, double x) {
+  const uint32_t st = (uint32_t)s;
+  const double v2 = vxn * vxn + vy * vy + vz * vz;
+  const double v = sqrt(v2);
+  double e_ev, e_ej;
+  ionization_share(C, P, v2, uid, st, e_ev, e_ej);
+  const double g_ej = sqrt(2.0 * e_ej * kEvToJ / kMuEAr);
+  double cs_ej, sn_ej;
+  ionization_angle(C, e_ej, e_ev, cs_ej, sn_ej);
+  double r_chi, r_eta;
+  uniform2(C->seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
+  const double f1 = kEMass / (kEMass + kArMass);
+  const double f2 = kArMass / (kEMass + kArMass);
+  const Frame F = frame_of(vxn, vy, vz, v);
+  double cos_eta2, sin_eta2;
+  sincos(kTwoPi * r_eta + kPi, &sin_eta2, &cos_eta2);
+  double ex_, ey_, ez_;
+  rotate(F, g_ej, f2, cs_ej, sn_ej, cos_eta2, sin_eta2, f1 * vxn, f1 * vy, f1 * vz, ex_, ey_, ez_);
+  P.ex[be] = x;
+  P.evx[be] = ex_;
+  P.evy[be] = ey_;
+  P.evz[be] = ez_;
+  P.evp2[be] = float_above(ey_ * ey_ + ez_ * ez_);
+  P.euid[be] = child_uid(uid, s, 1);
+}
+
+// The ion an ionization creates, at slot bi at the parent's position: a
+// thermal gas velocity from the newborn's own counter.
+__device__ __forceinline__ void ion_birth_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
+                                             int64_t bi, int64_t s, uint64_t uid, double x) {
+  const uint64_t cu = child_uid(uid, s, 2);
+  double z0, z1, z2;
+  normals3(C->seed, cu, (uint32_t)s, 1u, 2u, 1u, z0, z1, z2);
+  const double sa = C->sigma_a;
+  P.ix[bi] = x;
+  P.ivx[bi] = sa * z0;
+  P.ivy[bi] = sa * z1;
+  P.ivz[bi] = sa * z2;
+  P.iuid[bi] = cu;
+}
+
 // Ar+ + Ar scattering of colliding ion i (proc 0 isotropic, 1 backward) with the
 // thermal target of its test (redrawn from the same counter: the same atom).
 __device__ __forceinline__ void ion_scatter_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P, int64_t i,
@@ -734,6 +825,35 @@ struct Births {
     dropped += (int)__popcll(__ballot(mine && !ok));
     return mine && ok ? slot : -1;
   }
+  // Slots of an ionization's two newborns (an electron and an ion) for the
+  // lanes with `mine`: both counters' atomics go out together.
+  __device__ __forceinline__ void take_pair(bool mine, int lane, int64_t& be, int64_t& bi, int& placed_e,
+                                            int& placed_i, int& dropped) const {
+    const uint64_t m = __ballot(mine);
+    be = bi = -1;
+    if (m == 0) return;
+    long long b0 = 0, b1 = 0;
+    if (lane == 0) {
+      const int c = (int)__popcll(m);
+      if (SMALL) {
+        b0 = atomicAdd(&lds[0], c);
+        b1 = atomicAdd(&lds[1], c);
+      } else {
+        b0 = (long long)gl_fetch_add(glob[0], (unsigned long long)c);
+        b1 = (long long)gl_fetch_add(glob[1], (unsigned long long)c);
+      }
+    }
+    b0 = __shfl(b0, 0);
+    b1 = __shfl(b1, 0);
+    const int r = lane_rank(m);
+    const int64_t se = base[0] + (int64_t)b0 + r, si = base[1] + (int64_t)b1 + r;
+    const bool ok_e = se < cap[0], ok_i = si < cap[1];
+    placed_e += (int)__popcll(__ballot(mine && ok_e));
+    placed_i += (int)__popcll(__ballot(mine && ok_i));
+    dropped += (int)__popcll(__ballot(mine && !ok_e)) + (int)__popcll(__ballot(mine && !ok_i));
+    be = mine && ok_e ? se : -1;
+    bi = mine && ok_i ? si : -1;
+  }
 };
 
 // Totals of one species' step in one workgroup (kRec fields, summed over the
@@ -757,8 +877,6 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   __shared__ int32_t sSeg[kBlock / kWave][kSeg];
   __shared__ double sVx[kPay][SP == 0 ? kSeg : 1];
   __shared__ uint64_t sUid[kPay][SP == 0 ? kSeg : 1];
-  __shared__ int sNc[kBlock / kWave];
-  __shared__ int sNd;  // entries of the collider list
   __shared__ int sTot[kBlock / kWave][kRec];
   const int ng = C->ng;
   const int nsub = C->nsub;
@@ -786,10 +904,10 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
     }
   }
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x) sF[b] = 0;
-  if (threadIdx.x == 0) sNd = 0;
   __syncthreads();
   EDP_GLOBAL double* __restrict__ X = G(C->sp[SP].x[cur]);
-  // this workgroup's collider list: its chunk range of the species' list
+  // this workgroup's overflow lists of candidates: its chunk range of the
+  // species' list, a quarter per wave
   EDP_GLOBAL int64_t* __restrict__ CL = G(C->clist[SP]) + c_lo * kChunk;
   EDP_GLOBAL double* __restrict__ VX = G(C->sp[SP].vx[cur]);
   const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
@@ -916,101 +1034,95 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
     return proc;
   };
 
-  // A wave's full segment, tested inside the streaming loop: its colliders
-  // go to the workgroup's collider list (slot | process << 32, in the
-  // workgroup's range of the species' list) for the scattering after the
-  // loop, so that the long scattering code has a single site, where the
-  // loop's state is dead.
-  auto test_segment = [&](const int count) {
-    for (int b0 = 0; b0 < count; b0 += kWave) {
-      const int k = b0 + lane;
-      const bool act = k < count;
-      int64_t i = 0;
-      int proc = -1;
-      if (act) {
-        i = sSeg[w][k];
-        double vxn;
-        uint64_t uid;
-        if (SP == 0) {
-          // the pushed v_x and the uid from the segment, v_y and v_z (not
-          // changed by the push) from memory
-          vxn = sVx[SP == 0 ? w : 0][SP == 0 ? k : 0];
-          uid = sUid[SP == 0 ? w : 0][SP == 0 ? k : 0];
-        } else {
-          vxn = VX[i];
-          uid = UID[i];
-        }
-        proc = exact_test(vxn, VY[i], VZ[i], uid);
-      }
-      const uint64_t mc = __ballot(proc >= 0);
-      if (mc) {
-        int at = 0;
-        if (lane == 0) at = atomicAdd(&sNd, (int)__popcll(mc));
-        at = __shfl(at, 0);
-        if (proc >= 0) CL[at + lane_rank(mc)] = i | ((int64_t)proc << 32);
-      }
-    }
+  // A wave's full segment inside the streaming loop goes to the wave's
+  // overflow list (its quarter of the workgroup's range of the species'
+  // list, as many entries as the wave has slots) and is tested after the
+  // loop: the loop holds no table or transcendental code, so it keeps few
+  // registers.
+  EDP_GLOBAL int64_t* __restrict__ CLw = CL + (int64_t)w * (c_hi - c_lo) * kWave;
+  int nov = 0;  // entries of this wave's overflow list
+  auto spill_segment = [&](const int count) {
+    for (int k = lane; k < count; k += kWave) CLw[nov + k] = sSeg[w][k];
+    nov += count;
   };
 
-  // After the loop and the histogram's flush, one list over the workgroup:
-  // the colliders the streaming loop found (entries [0, nd), state reloaded),
-  // then the remaining candidates of the segments (exact test now).  Every
-  // collider gets its scattering; an ionization its newborns (slots from the
-  // step's counters, charge at the parent's new position: the electron a
-  // second share of this step's deposit, the ion the next ion step's
-  // density).
-  auto finish = [&](const int nd, const int count) {
-    for (int b0 = 0; b0 < count; b0 += kBlock) {
-      const int k = b0 + (int)threadIdx.x;
+  // After the loop and the histogram's flush, each wave its own list, in
+  // rounds of 64 entries: its overflow list (state reloaded), then what is
+  // left in its segment.  Each round runs the exact test, moves the round's
+  // colliders with their state to the low lanes (one push permutation), and
+  // gives each its scattering; an ionization also gets its newborns (slots
+  // from the step's counters, charge at the parent's new position: the
+  // electron a second share of this step's deposit, the ion the next ion
+  // step's density).  No workgroup barrier: waves finish at their own pace.
+  auto finish = [&]() {
+    const int count = nov + ncw;
+    for (int b0 = 0; b0 < count; b0 += kWave) {
+      const int k = b0 + lane;
       int64_t i = 0;
       double vxn = 0.0, vy = 0.0, vz = 0.0;
       uint64_t uid = 0;
       int proc = -1;
-      if (k < nd) {
-        const int64_t code = CL[k];
-        i = code & 0xFFFFFFFFLL;
-        proc = (int)(code >> 32);
-        vxn = VX[i];
-        vy = VY[i];
-        vz = VZ[i];
-        uid = UID[i];
-      } else if (k < count) {
-        int sg = 0, kk = k - nd;
-        while (kk >= sNc[sg]) kk -= sNc[sg++];
-        i = sSeg[sg][kk];
-        if (SP == 0) {
-          vxn = sVx[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
-          uid = sUid[SP == 0 ? sg : 0][SP == 0 ? kk : 0];
-        } else {
+      if (k < count) {
+        if (k < nov) {
+          i = CLw[k];
           vxn = VX[i];
           uid = UID[i];
+        } else {
+          const int kk = k - nov;
+          i = sSeg[w][kk];
+          if (SP == 0) {
+            // the pushed v_x and the uid from the segment
+            vxn = sVx[SP == 0 ? w : 0][SP == 0 ? kk : 0];
+            uid = sUid[SP == 0 ? w : 0][SP == 0 ? kk : 0];
+          } else {
+            vxn = VX[i];
+            uid = UID[i];
+          }
         }
+        // v_y and v_z are not changed by the push
         vy = VY[i];
         vz = VZ[i];
         proc = exact_test(vxn, vy, vz, uid);
       }
-      const bool coll = proc >= 0;
-      t_coll += (int)__popcll(__ballot(coll));
+      const bool c0 = proc >= 0;
+      const uint64_t mc = __ballot(c0);
+      const int ncol = (int)__popcll(mc);
+      t_coll += ncol;
+      if (ncol == 0) continue;
+      // colliders to lanes [0, ncol), the others after them
+      const int to = 4 * (c0 ? lane_rank(mc) : ncol + lane_rank(~mc));
+      auto push32 = [&](int v) { return __builtin_amdgcn_ds_permute(to, v); };
+      auto push64 = [&](uint64_t v) {
+        return (uint64_t)(uint32_t)push32((int)(uint32_t)v) | ((uint64_t)(uint32_t)push32((int)(v >> 32)) << 32);
+      };
+      i = (int64_t)push64((uint64_t)i);
+      proc = push32(proc);
+      vxn = __longlong_as_double((long long)push64((uint64_t)__double_as_longlong(vxn)));
+      vy = __longlong_as_double((long long)push64((uint64_t)__double_as_longlong(vy)));
+      vz = __longlong_as_double((long long)push64((uint64_t)__double_as_longlong(vz)));
+      uid = push64(uid);
+      const bool coll = lane < ncol;
       if (SP == 0) {
-        const bool ioniz = proc == 2;
-        double xb = 0.0;
-        int64_t be = -1, bi = -1;
+        const bool ioniz = coll && proc == 2;
         const uint64_t mi = __ballot(ioniz);
         if (mi) {
           t_ioniz += (int)__popcll(mi);
-          be = B.take(0, ioniz, lane, t_be, t_drop);
-          bi = B.take(1, ioniz, lane, t_bi, t_drop);
+          // the parent's new position loads while the slots are taken
+          const double xb = ioniz ? X[i] : 0.0;
+          int64_t be, bi;
+          B.take_pair(ioniz, lane, be, bi, t_be, t_bi, t_drop);
           if (ioniz) {
-            xb = X[i];
             long long r;
             const int q = deposit_split(xb, inv_dx, ng, r);
             gl_add(&dst[q], 4294967296LL - r);
             gl_add(&dst[q + 1], r);
             gl_add(&cnt_i_next[q], 4294967296LL - r);
             gl_add(&cnt_i_next[q + 1], r);
+            if (be >= 0) electron_eject_at(C, P, be, s, vxn, vy, vz, uid, xb);
+            if (bi >= 0) ion_birth_at(C, P, bi, s, uid, xb);
           }
         }
-        if (coll) electron_scatter_at(C, P, i, proc, be, bi, s, vxn, vy, vz, uid, xb);
+        if (coll) electron_scatter_at(C, P, i, proc, s, vxn, vy, vz, uid);
       } else if (coll) {
         ion_scatter_at(C, P, i, proc, s, vxn, vy, vz, uid);
       }
@@ -1184,15 +1296,13 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
       }
       ncw += (int)__popcll(m_c);
       if (ncw > kSeg - kWave) {
-        // a full segment: the wave tests its own candidates now
-        test_segment(ncw);
+        spill_segment(ncw);
         ncw = 0;
       }
     }
     t_pow += (int)__popcll(__ballot(abs_pow));
     t_gnd += (int)__popcll(__ballot(abs_gnd));
   }
-  if (lane == 0) sNc[w] = ncw;
   __syncthreads();
   // flush first (deposit for step s+1 and diagnostics of step s): the
   // last candidate pass below adds its newborns' charge to global memory
@@ -1211,9 +1321,8 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   int64_t* hist = SP == 0 ? C->eepf : C->ifed;
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x)
     if (sF[b]) gl_add(&hist[b], (long long)sF[b]);
-  // the loop's colliders and the remaining candidates of all waves
-  const int nd = sNd;
-  finish(nd, nd + sNc[0] + sNc[1] + sNc[2] + sNc[3]);
+  // this wave's overflow list and segment
+  finish();
   if (lane == 0) {
     sTot[w][kRecColl] = t_coll;
     sTot[w][kRecIoniz] = t_ioniz;
@@ -1260,20 +1369,21 @@ k_particles(const BlockRole* __restrict__ R, int dstep) {
   double* sE = psm;
   double* reg = psm + ng;
   const bool writer = SP == 0 && j == 0;
-  solve_field<MODE>(Cw, r->cnt_e, r->cnt_i, r->volt, ng, nsub, s, sE, reg, writer);
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int64_t n_e = step_slots(C, 0, s), n_i = step_slots(C, 1, s);
+  const int64_t n = SP == 0 ? n_e : n_i;
+  const int64_t nch = (n + kChunk - 1) / kChunk;
+  const int64_t per = (nch + nwg - 1) / nwg;
+  const int64_t c_lo = (int64_t)j * per;
+  const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
+  const int cur = C->cur[SP];
+  solve_field<MODE>(Cw, r->cnt_e, r->cnt_i, r->volt, ng, nsub, s, sE, reg, writer);
   if (writer && threadIdx.x == 0) {
     for (int sp = 0; sp < 2; ++sp) {
       Cw->nbase[sp][s % 3] = sp == 0 ? n_e : n_i;
       Cw->born[sp][(s + 1) % 3] = 0;
     }
   }
-  const int64_t n = SP == 0 ? n_e : n_i;
-  const int64_t nch = (n + kChunk - 1) / kChunk;
-  const int64_t per = (nch + nwg - 1) / nwg;
-  const int64_t c_lo = (int64_t)j * per;
-  const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
   if (c_lo >= c_hi) return;  // whole workgroup: nothing to do this step
   Births<false> B;
   B.base[0] = n_e;
@@ -1283,7 +1393,7 @@ k_particles(const BlockRole* __restrict__ R, int dstep) {
   B.lds = nullptr;
   B.glob[0] = &Cw->born[0][s % 3];
   B.glob[1] = &Cw->born[1][s % 3];
-  const SpTot T = species_pass<SP, false>(Cw, sE, reg, s, n, c_lo, c_hi, C->cur[SP], C->cur[1 - SP], B);
+  const SpTot T = species_pass<SP, false>(Cw, sE, reg, s, n, c_lo, c_hi, cur, C->cur[1 - SP], B);
   if (threadIdx.x == 0) {
     int64_t* sh = C->shard + ((int64_t)SP * kShards + j % kShards) * kRec;
 #pragma unroll
@@ -1790,11 +1900,11 @@ __global__ void k_zero(int64_t* __restrict__ p, int64_t n) {
 // Host-side launchers (same translation unit as the kernels).
 // ---------------------------------------------------------------------------
 // Static LDS of a species' particle kernel: the candidate segments with
-// their payload, plus a bound on the counters, the totals and the field
-// scan's scratch.
+// their payload, plus a bound on the counters, the totals, a round's
+// colliders and the field scan's scratch.
 size_t particle_static_lds(int sp) {
   const size_t waves = kBlock / kWave;
-  return sp == 0 ? waves * kSegE * (4 + 8 + 8) + 1024 : waves * kSegI * 4 + 1024;
+  return sp == 0 ? waves * kSegE * (4 + 8 + 8) + 2048 : waves * kSegI * 4 + 2048;
 }
 
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp) {
