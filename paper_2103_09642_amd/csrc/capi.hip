@@ -259,8 +259,8 @@ Layout layout(const edp_case_desc* c, int nbins) {
       for (int a = 0; a < 5; ++a) L.off_part[sp][set][a] = take((size_t)L.cap[sp] * 8);
   for (int set = 0; set < 2; ++set) L.off_vp2[set] = take((size_t)L.cap[0] * 4);  // electrons only (float)
   for (int sp = 0; sp < 2; ++sp) {
-    const size_t chunks = (size_t)((L.cap[sp] + kChunk - 1) / kChunk);
-    L.off_cl[sp] = take(chunks * kChunk * 8);  // candidates (per-workgroup lists over its chunk range)
+    const size_t chunks = (size_t)((L.cap[sp] + kMaxChunk - 1) / kMaxChunk);
+    L.off_cl[sp] = take(chunks * kMaxChunk * 8);  // candidates (per-workgroup lists over its chunk range)
   }
   for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
   const size_t ng = (size_t)c->n_grid;

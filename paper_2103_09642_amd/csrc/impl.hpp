@@ -38,13 +38,21 @@ constexpr double kDiagWS = 1048576.0;  // c
 constexpr double kDiagES = 1048576.0;  // c * energy [eV]
 constexpr double kDiagIZS = 4294967296.0;  // c * nu_ion dt_e
 
-// Particle kernels: workgroup size and the particle slots each workgroup owns.
+// Workgroup size of most kernels, and of the small-case kernel's chunks.
 constexpr int kBlock = 256;
-constexpr int kChunk = kBlock;  // particle slots per chunk: one per thread of a workgroup
+constexpr int kChunk = kBlock;  // slots per chunk of the host's size estimates and the sort
+// Workgroup size of the lockstep particle kernels; a chunk of their
+// streaming loop is one slot per thread.  Candidate lists are sized for the
+// largest chunk.
+#ifndef EDP_PART_BLOCK
+#define EDP_PART_BLOCK 256
+#endif
+constexpr int kPartBlock = EDP_PART_BLOCK;
+constexpr int kMaxChunk = 1024;
+static_assert(kPartBlock % 256 == 0 && kPartBlock <= kMaxChunk, "particle workgroup size");
 constexpr int kMaxApply = 1024;   // collision workgroups per case and application
 constexpr int kMaxPartWG = 8192;  // particle workgroups per case and species
 constexpr int kMaxNodes = 2048;                      // largest n_grid accepted
-constexpr int kGridPerThread = kMaxNodes / kBlock;   // grid nodes per thread
 constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
 
 // Flags (same values as EDP_* in edupic.h).

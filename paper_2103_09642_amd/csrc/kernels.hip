@@ -285,9 +285,6 @@ __device__ __forceinline__ void fold_particle_sums(const EDP_CONST CaseDev* __re
   }
 }
 
-// Rows of the flux scan per thread at the largest grid.
-constexpr int kScanRows = (kMaxNodes - 2 + kBlock - 1) / kBlock;
-
 // Per-node duties of a step's writer: rho for reads, the time sums of the
 // densities, the deposit rings the next steps refill cleared, the particle
 // sums of step s-1 folded with the field that step used (still in efield[];
@@ -340,12 +337,15 @@ struct FieldWriter {
 // The writer (one workgroup per case and step) also stores rho, E and the
 // fluxes (or phi) for reads, clears the deposit rings the next steps refill,
 // adds the measurement sums and counts the step.
-template <int MODE>
+template <int MODE, int NB>
 __device__ __forceinline__ void solve_field(CaseDev* __restrict__ Cw, const int64_t* __restrict__ cnt_e,
                                             const int64_t* __restrict__ cnt_i, const double* __restrict__ volt,
                                             const int ng, const int nsub, const int64_t s, double* sE, double* sF,
                                             const bool writer) {
-  __shared__ double sWave[2][kBlock / kWave];
+  // rows of the flux scan and nodes per thread at the largest grid
+  constexpr int kRows = (kMaxNodes - 2 + NB - 1) / NB;
+  constexpr int kNodes = (kMaxNodes + NB - 1) / NB;
+  __shared__ double sWave[2][NB / kWave];
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int64_t k = s / nsub;
   const bool ion_step = (s % nsub) == 0;
@@ -379,17 +379,17 @@ __device__ __forceinline__ void solve_field(CaseDev* __restrict__ Cw, const int6
     return kECharge * (ni - ne);
   };
   if (MODE == 1) {
-    // node p = t + q kBlock: rho and the right-hand side d_p = rho_p dx^2/eps0
-    int64_t ce[kGridPerThread], ci[kGridPerThread];
+    // node p = t + q NB: rho and the right-hand side d_p = rho_p dx^2/eps0
+    int64_t ce[kNodes], ci[kNodes];
 #pragma unroll
-    for (int q = 0; q < kGridPerThread; ++q) {
-      const int p = t + q * kBlock;
+    for (int q = 0; q < kNodes; ++q) {
+      const int p = t + q * NB;
       ce[q] = p < ng ? cntE[p] : 0;
       ci[q] = p < ng ? cntI[p] : 0;
     }
 #pragma unroll
-    for (int q = 0; q < kGridPerThread; ++q) {
-      const int p = t + q * kBlock;
+    for (int q = 0; q < kNodes; ++q) {
+      const int p = t + q * NB;
       if (p >= ng) break;
       double ne, ni;
       const double rho = dens(p, ce[q], ci[q], ne, ni);
@@ -417,7 +417,7 @@ __device__ __forceinline__ void solve_field(CaseDev* __restrict__ Cw, const int6
       sF[ng - 1] = 0.0;
     }
     __syncthreads();
-    for (int p = t; p < ng; p += kBlock) {
+    for (int p = t; p < ng; p += NB) {
       double e;
       if (p == 0)
         e = (sF[0] - sF[1]) / dx - rho0 * dx / (2.0 * kEps0);
@@ -442,20 +442,20 @@ __device__ __forceinline__ void solve_field(CaseDev* __restrict__ Cw, const int6
     // follows in registers: E_p = (F_{p-1} + F_p)/(2 dx) inside, the boundary
     // forms (Gauss's law over the half cell) at the electrodes.
     const int m = ng - 2;
-    const int R = (m + kBlock - 1) / kBlock;  // <= kScanRows
+    const int R = (m + NB - 1) / NB;  // <= kRows
     const int q0 = t * R < m ? t * R : m;
     const int nq = (q0 + R < m ? q0 + R : m) - q0;
-    int64_t ce[kScanRows], ci[kScanRows];
+    int64_t ce[kRows], ci[kRows];
 #pragma unroll
-    for (int r = 0; r < kScanRows; ++r) {
+    for (int r = 0; r < kRows; ++r) {
       ce[r] = r < nq ? cntE[q0 + 1 + r] : 0;
       ci[r] = r < nq ? cntI[q0 + 1 + r] : 0;
     }
     const int64_t ce0 = cntE[0], ci0 = cntI[0], ceN = cntE[ng - 1], ciN = cntI[ng - 1];
-    double v[kScanRows];
+    double v[kRows];
     double acc = 0.0, wsum = 0.0;
 #pragma unroll
-    for (int r = 0; r < kScanRows; ++r) {
+    for (int r = 0; r < kRows; ++r) {
       if (r < nq) {
         const int p = q0 + 1 + r;
         double ne, ni;
@@ -490,14 +490,14 @@ __device__ __forceinline__ void solve_field(CaseDev* __restrict__ Cw, const int6
     __syncthreads();
     double before = inc - acc, sum_s = 0.0;
 #pragma unroll
-    for (int u = 0; u < kBlock / kWave; ++u) {
+    for (int u = 0; u < NB / kWave; ++u) {
       if (u < wv) before += sWave[0][u];
       sum_s += sWave[1][u];
     }
     const double F0 = (V - sum_s) / (double)(ng - 1);
     double f_prev = F0 + before;  // F_{q0}: F0 plus the rows before this thread's
 #pragma unroll
-    for (int r = 0; r < kScanRows; ++r) {
+    for (int r = 0; r < kRows; ++r) {
       if (r < nq) {
         const int p = q0 + 1 + r;
         const double f = F0 + (before + v[r]);  // F_{q+1} = F_p
@@ -866,18 +866,18 @@ struct SpTot {
 // of buffer set `cur` (the other species' current set `cur_o`), E in sE,
 // `reg` the LDS region for the deposit histogram (and the particle
 // diagnostics), B the step's birth counters.
-template <int SP, bool SMALL>
+template <int SP, bool SMALL, int NB>
 __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const double* sE, double* reg,
                                               const int64_t s, const int64_t n, const int64_t c_lo,
                                               const int64_t c_hi, const int cur, const int cur_o,
                                               const Births<SMALL>& B) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   constexpr int kSeg = seg_len<SP>();
-  constexpr int kPay = SP == 0 ? kBlock / kWave : 1;
-  __shared__ int32_t sSeg[kBlock / kWave][kSeg];
+  constexpr int kPay = SP == 0 ? NB / kWave : 1;
+  __shared__ int32_t sSeg[NB / kWave][kSeg];
   __shared__ double sVx[kPay][SP == 0 ? kSeg : 1];
   __shared__ uint64_t sUid[kPay][SP == 0 ? kSeg : 1];
-  __shared__ int sTot[kBlock / kWave][kRec];
+  __shared__ int sTot[NB / kWave][kRec];
   const int ng = C->ng;
   const int nsub = C->nsub;
   const int64_t kion = s / nsub;
@@ -908,7 +908,7 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   EDP_GLOBAL double* __restrict__ X = G(C->sp[SP].x[cur]);
   // this workgroup's overflow lists of candidates: its chunk range of the
   // species' list, a quarter per wave
-  EDP_GLOBAL int64_t* __restrict__ CL = G(C->clist[SP]) + c_lo * kChunk;
+  EDP_GLOBAL int64_t* __restrict__ CL = G(C->clist[SP]) + c_lo * NB;
   EDP_GLOBAL double* __restrict__ VX = G(C->sp[SP].vx[cur]);
   const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
   const EDP_GLOBAL double* __restrict__ VZ = G(C->sp[SP].vz[cur]);
@@ -1137,7 +1137,7 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   float nvp2 = 0.0f;
   uint64_t nuid = 0;
   auto fetch = [&](const int64_t c) {
-    const int64_t i = c * kChunk + slot;
+    const int64_t i = c * NB + slot;
     nx = __longlong_as_double(0x7FF8000000000000LL);
     nvx = nvy = nvz = 0.0;
     nvp2 = 0.0f;
@@ -1155,7 +1155,7 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   };
   if (c_lo < c_hi) fetch(c_lo);
   for (int64_t c = c_lo; c < c_hi; ++c) {
-    const int64_t i = c * kChunk + slot;
+    const int64_t i = c * NB + slot;
     const double x = nx, vx = nvx, vy = nvy, vz = nvz, vp2 = (double)nvp2;
     const uint64_t uid = nuid;
     if (c + 1 < c_hi) fetch(c + 1);
@@ -1336,7 +1336,10 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   __syncthreads();
   SpTot T;
 #pragma unroll
-  for (int f = 0; f < kRec; ++f) T.v[f] = sTot[0][f] + sTot[1][f] + sTot[2][f] + sTot[3][f];
+  for (int f = 0; f < kRec; ++f) {
+    T.v[f] = 0;
+    for (int u = 0; u < NB / kWave; ++u) T.v[f] += sTot[u][f];
+  }
   __syncthreads();  // sTot, the segments and the histograms are free again
   return T;
 }
@@ -1358,7 +1361,7 @@ __device__ __forceinline__ int64_t step_slots(const EDP_CONST CaseDev* __restric
 // measurement sums) and publishes the step's slot counts.  Each workgroup
 // adds its totals to its shard of the case's counters.
 template <int SP, int MODE>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kPartBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_particles(const BlockRole* __restrict__ R, int dstep) {
   extern __shared__ double psm[];
   const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
@@ -1372,12 +1375,12 @@ k_particles(const BlockRole* __restrict__ R, int dstep) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int64_t n_e = step_slots(C, 0, s), n_i = step_slots(C, 1, s);
   const int64_t n = SP == 0 ? n_e : n_i;
-  const int64_t nch = (n + kChunk - 1) / kChunk;
+  const int64_t nch = (n + kPartBlock - 1) / kPartBlock;
   const int64_t per = (nch + nwg - 1) / nwg;
   const int64_t c_lo = (int64_t)j * per;
   const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
   const int cur = C->cur[SP];
-  solve_field<MODE>(Cw, r->cnt_e, r->cnt_i, r->volt, ng, nsub, s, sE, reg, writer);
+  solve_field<MODE, kPartBlock>(Cw, r->cnt_e, r->cnt_i, r->volt, ng, nsub, s, sE, reg, writer);
   if (writer && threadIdx.x == 0) {
     for (int sp = 0; sp < 2; ++sp) {
       Cw->nbase[sp][s % 3] = sp == 0 ? n_e : n_i;
@@ -1393,7 +1396,7 @@ k_particles(const BlockRole* __restrict__ R, int dstep) {
   B.lds = nullptr;
   B.glob[0] = &Cw->born[0][s % 3];
   B.glob[1] = &Cw->born[1][s % 3];
-  const SpTot T = species_pass<SP, false>(Cw, sE, reg, s, n, c_lo, c_hi, cur, C->cur[1 - SP], B);
+  const SpTot T = species_pass<SP, false, kPartBlock>(Cw, sE, reg, s, n, c_lo, c_hi, cur, C->cur[1 - SP], B);
   if (threadIdx.x == 0) {
     int64_t* sh = C->shard + ((int64_t)SP * kShards + j % kShards) * kRec;
 #pragma unroll
@@ -1606,7 +1609,7 @@ __global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ 
     }
     if (threadIdx.x < 2) sBirth[threadIdx.x] = 0;
     // steps 1-2
-    solve_field<MODE>(Cw, C->cnt_e, C->cnt_i, C->volt, ng, nsub, s, sE, reg, true);
+    solve_field<MODE, kBlock>(Cw, C->cnt_e, C->cnt_i, C->volt, ng, nsub, s, sE, reg, true);
     Births<true> B;
     B.base[0] = n_e;
     B.base[1] = n_i;
@@ -1615,9 +1618,9 @@ __global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ 
     B.lds = sBirth;
     B.glob[0] = B.glob[1] = nullptr;
     const int64_t nch_e = (n_e + kChunk - 1) / kChunk, nch_i = (n_i + kChunk - 1) / kChunk;
-    const SpTot te = species_pass<0, true>(Cw, sE, reg, s, n_e, 0, nch_e, cur_e, cur_i, B);
+    const SpTot te = species_pass<0, true, kBlock>(Cw, sE, reg, s, n_e, 0, nch_e, cur_e, cur_i, B);
     SpTot ti{};
-    if (ion_step) ti = species_pass<1, true>(Cw, sE, reg, s, n_i, 0, nch_i, cur_i, cur_e, B);
+    if (ion_step) ti = species_pass<1, true, kBlock>(Cw, sE, reg, s, n_i, 0, nch_i, cur_i, cur_e, B);
     if (threadIdx.x == 0) {
       int64_t* ctr = Cw->ctr;
       ctr[kCollE] += te.v[kRecColl];
@@ -1903,7 +1906,7 @@ __global__ void k_zero(int64_t* __restrict__ p, int64_t n) {
 // their payload, plus a bound on the counters, the totals, a round's
 // colliders and the field scan's scratch.
 size_t particle_static_lds(int sp) {
-  const size_t waves = kBlock / kWave;
+  const size_t waves = kPartBlock / kWave;
   return sp == 0 ? waves * kSegE * (4 + 8 + 8) + 2048 : waves * kSegI * 4 + 2048;
 }
 
@@ -1926,9 +1929,9 @@ template <int SP, int MODE>
 void launch_particles_t(const BlockRole* roles, int blocks, size_t lds, int dstep, hipStream_t st, hipEvent_t ev0,
                         hipEvent_t ev1) {
   if (ev0)
-    hipExtLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kBlock), lds, st, ev0, ev1, 0, roles, dstep);
+    hipExtLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kPartBlock), lds, st, ev0, ev1, 0, roles, dstep);
   else
-    hipLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kBlock), lds, st, roles, dstep);
+    hipLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kPartBlock), lds, st, roles, dstep);
 }
 
 hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, int mode, int dstep,
@@ -1960,8 +1963,8 @@ hipError_t launch_window_end(const BlockRole* cases, int ncase, int steps, hipSt
 // of dynamic LDS.
 int particle_occupancy(int sp, size_t lds) {
   int nb = 0;
-  const hipError_t e = sp == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<0, 0>, kBlock, lds)
-                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<1, 0>, kBlock, lds);
+  const hipError_t e = sp == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<0, 0>, kPartBlock, lds)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particles<1, 0>, kPartBlock, lds);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
@@ -1977,7 +1980,10 @@ size_t small_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed) {
   return ((size_t)ng + region) * 8;
 }
 
-size_t small_static_lds() { return particle_static_lds(0) + particle_static_lds(1) + 2048; }
+size_t small_static_lds() {
+  const size_t waves = kBlock / kWave;
+  return waves * kSegE * (4 + 8 + 8) + waves * kSegI * 4 + 6144;
+}
 
 // One window of the small cases: workgroup b runs the case of roles[b] for
 // roles[b].j steps.
