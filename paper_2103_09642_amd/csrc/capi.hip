@@ -523,10 +523,31 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
     const int64_t slots = (int64_t)ctx->num_cu * per_cu;
     int64_t total = 0;
     for (const Case* c : cs) total += est_chunks(c, sp);
-    const int64_t per = std::max<int64_t>(1, (total + slots - 1) / slots);
-    want[sp].resize(nc);
-    for (size_t k = 0; k < nc; ++k)
-      want[sp][k] = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxPartWG, (est_chunks(cs[k], sp) + per - 1) / per));
+    // every case at least one workgroup, the slots in proportion to the
+    // chunks (largest remainders first), never more workgroups than chunks
+    // and never more than the slots in all (unless the cases outnumber
+    // them): a workgroup beyond the resident slots would wait for a whole
+    // workgroup to finish and run after it
+    want[sp].assign(nc, 1);
+    std::vector<double> frac(nc, 0.0);
+    int64_t used = 0;
+    for (size_t k = 0; k < nc; ++k) {
+      const int64_t ch = est_chunks(cs[k], sp);
+      const double ideal = (double)ch * (double)slots / (double)std::max<int64_t>(1, total);
+      const int64_t w = std::max<int64_t>(1, std::min<int64_t>({(int64_t)ideal, ch, (int64_t)kMaxPartWG}));
+      want[sp][k] = (int)w;
+      frac[k] = ideal - (double)w;
+      used += w;
+    }
+    std::vector<size_t> order(nc);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return frac[a] > frac[b]; });
+    for (size_t k : order) {
+      if (used >= slots) break;
+      if (frac[k] <= 0.0 || want[sp][k] >= std::min<int64_t>(kMaxPartWG, est_chunks(cs[k], sp))) continue;
+      ++want[sp][k];
+      ++used;
+    }
   }
   std::vector<int> want_sort[2];
   for (int sp = 0; sp < 2; ++sp)
