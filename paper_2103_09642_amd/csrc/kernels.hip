@@ -153,13 +153,13 @@ __device__ __forceinline__ void scatter(double gx, double gy, double gz, double 
 }
 
 // Fixed-point split of one particle between nodes p and p+1 (charge
-// assignment equations): p = int(x/dx) clamped to N_g-2, f*2^32 truncated,
-// capped at 2^32.
+// assignment equations): in cell units xi = x/dx, p = int(xi) clamped to
+// N_g-2, the share of node p+1 (xi - p) 2^32 truncated, capped at 2^32.
 __device__ __forceinline__ int deposit_split(double x, double inv_dx, int ng, long long& r) {
-  const double c0 = x * inv_dx;
-  int p = (int)c0;
+  const double xi = x * inv_dx;
+  int p = (int)xi;
   p = p > ng - 2 ? ng - 2 : (p < 0 ? 0 : p);
-  const double f = c0 - (double)p;
+  const double f = xi - (double)p;
   long long q = (long long)(f * kTwo32);
   r = q > 4294967296LL ? 4294967296LL : q;
   return p;
@@ -1084,13 +1084,13 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
         vz = VZ[i];
         proc = exact_test(vxn, vy, vz, uid);
       }
-      const bool c0 = proc >= 0;
-      const uint64_t mc = __ballot(c0);
+      const bool hit = proc >= 0;
+      const uint64_t mc = __ballot(hit);
       const int ncol = (int)__popcll(mc);
       t_coll += ncol;
       if (ncol == 0) continue;
       // colliders to lanes [0, ncol), the others after them
-      const int to = 4 * (c0 ? lane_rank(mc) : ncol + lane_rank(~mc));
+      const int to = 4 * (hit ? lane_rank(mc) : ncol + lane_rank(~mc));
       auto push32 = [&](int v) { return __builtin_amdgcn_ds_permute(to, v); };
       auto push64 = [&](uint64_t v) {
         return (uint64_t)(uint32_t)push32((int)(uint32_t)v) | ((uint64_t)(uint32_t)push32((int)(v >> 32)) << 32);
