@@ -104,6 +104,9 @@ def main():
                          "workload's cases, outside the timed region)")
     ap.add_argument("--wg-per-cu", type=int, default=-1,
                     help="particle workgroups per CU (0: all that fit); -1: the autotuner's choice")
+    ap.add_argument("--part-skew", type=int, default=-1,
+                    help="per mille: the last dispatch layer's share of a case's chunks below the first's "
+                         "(-1: the library's default)")
     ap.add_argument("--groups", type=int, default=0, choices=(0, 1, 2, 3, 4),
                     help="lockstep groups of a batched advance; 0: the autotuner's choice")
     ap.add_argument("--pic-steps", type=int, default=0,
@@ -368,6 +371,8 @@ def bench_batch(args):
     dual = args.workload == "dual32"
     xs = workloads.synthetic_xsec()
     ctx = edupic.Context(0)
+    if args.part_skew >= 0:
+        ctx.set_option(edupic.OPT_PART_SKEW, args.part_skew)
     ctx.set_xsec(xs)
     ctx.set_option(edupic.OPT_MODE, args.mode)
     descs = batch_descs(args.workload)
@@ -446,6 +451,8 @@ def run_large(args, cycles, warmup, diag, tune_on):
     from paper_2103_09642_amd import edupic, workloads
     case = large_desc(args, diag)
     ctx = edupic.Context(0)
+    if args.part_skew >= 0:
+        ctx.set_option(edupic.OPT_PART_SKEW, args.part_skew)
     ctx.set_xsec(workloads.synthetic_xsec())
     ctx.set_option(edupic.OPT_MODE, args.mode)
     mid = warmup + cycles // 2
@@ -528,6 +535,8 @@ def bench_small(args):
     res = {}
     for path, small_max in (("lockstep", 0), ("persistent", 1 << 30)):
         ctx = edupic.Context(0)
+        if args.part_skew >= 0:
+            ctx.set_option(edupic.OPT_PART_SKEW, args.part_skew)
         ctx.set_xsec(xs)
         ctx.set_option(edupic.OPT_MODE, args.mode)
         ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every or 100)

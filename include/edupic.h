@@ -150,6 +150,16 @@ extern "C" {
                                  uses: 0 (default) all that fit, k >= 1 at
                                  most k; results do not depend on it, speed
                                  does: the autotuner (tune.py) picks it       */
+#define EDP_OPT_PART_SKEW 13   /* per mille, 0..900, or -1 (default):
+                                 a particle launch's workgroups are
+                                 dispatched one per CU in turn, and each
+                                 later layer streams its chunks more slowly;
+                                 layer l of L then takes a share of its
+                                 case's chunks weighted by
+                                 1 - skew l / (L - 1).  -1: 200 (L - 1), at
+                                 most 900, when the launch serves one case,
+                                 else 0.  Results do not depend on it, speed
+                                 does */
 
 typedef struct edp_ctx edp_ctx; /* opaque */
 typedef int64_t edp_case;       /* case handle, > 0 */
@@ -286,7 +296,7 @@ int edp_advance_steps(edp_ctx *ctx, const edp_case *cases, int32_t n_cases,
  * but it allocates nothing.  The workgroup role table its launches read
  * (device memory beyond the cases' arenas; the first kernel of each window
  * writes the cases' steps into it) is a file-scope array of 16384 entries
- * (896 KiB) that each GPU the library runs on holds until the process ends;
+ * (1 MiB) that each GPU the library runs on holds until the process ends;
  * the call makes no hipMalloc, hipFree, graph, stream or event and launches
  * plainly, as one lockstep group, on the context's stream.  Host
  * bookkeeping uses the C++ heap only.  Limit: a call whose cases need more

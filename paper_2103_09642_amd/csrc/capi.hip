@@ -121,6 +121,7 @@ struct Batch {
 // streams of their own, so that one group's launch tail overlaps another's
 // streaming (the groups share nothing; each keeps its own order).
 constexpr int kMaxGroups = 4;
+constexpr int kAutoSkew = -1;  // EDP_OPT_PART_SKEW default
 struct Group {
   Batch batch;
   BlockRole* roles_d = nullptr;
@@ -139,7 +140,7 @@ struct Group {
 };
 
 // Workgroup roles the allocation-free advance can hold: its role table is a
-// file-scope device array of this many entries (896 KiB) per GPU.
+// file-scope device array of this many entries (1 MiB) per GPU.
 constexpr int kScratchRoles = 16384;
 
 }  // namespace
@@ -148,7 +149,7 @@ constexpr int kScratchRoles = 16384;
 // stand-in, not a device address: host code uses it only to ask
 // hipGetSymbolAddress, with a device current, for that device's copy, and
 // then only that address (kept per device by scratch_roles()).
-static_assert(sizeof(BlockRole) == 56, "role size named in the ABI header (16384 roles: 896 KiB)");
+static_assert(sizeof(BlockRole) == 64, "role size named in the ABI header (16384 roles: 1 MiB)");
 __device__ __align__(256) BlockRole scratch[kScratchRoles];
 
 
@@ -166,6 +167,7 @@ struct edp_ctx {
   // options
   int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, poisson = 0;
   int part_wg_per_cu = 0;  // 0: every resident slot
+  int part_skew = kAutoSkew;  // per mille: the last layer's weight below the first's; -1 automatic
   int groups = 2;  // lockstep groups of a multi-case advance (1..kMaxGroups)
   // cases of at most this many slots per species (estimate) run in the
   // persistent one-workgroup-per-case kernel (0: none)
@@ -489,10 +491,66 @@ int reset_groups(edp_ctx* ctx) {
   return EDP_OK;
 }
 
-// Workgroup j of n of case c in a batched launch.
+// Workgroup j of n of case c in a batched launch (an equal share of the
+// case's chunks).
 BlockRole role(const Case* c, int j, int n) {
+  const uint64_t one = 1ull << 31;
   return BlockRole{c->d, c->h.cnt_e, c->h.cnt_i, c->h.volt, c->step, j, n, (int32_t)c->desc.n_grid,
-                   (int32_t)c->desc.ion_subcycle};
+                   (int32_t)c->desc.ion_subcycle, (uint32_t)(one * (uint64_t)j / (uint64_t)n),
+                   (uint32_t)(one * (uint64_t)(j + 1) / (uint64_t)n)};
+}
+
+// Particle roles of one launch: case k's want[k] workgroups, spread over
+// the launch (workgroup j of n at position (j + 1/2)/n of it, cases in order
+// on ties) so that each case has workgroups in every dispatch layer, with
+// their chunk shares.  A launch's workgroups are dispatched one per CU in
+// turn, so block b is in layer b / num_cu; the CUs' wave arbitration favours
+// the older waves, and a later layer streams its chunks more slowly.  With
+// skew a (per mille) layer l of L gets the weight 1 - a l / (L - 1), and
+// each case's chunks are split by the weights of its workgroups.  The
+// automatic skew (a < 0) is 200 (L - 1), at most 900, for a launch of one
+// case: on the large case (2e6 particles per species, four layers) 600-750
+// measured best, 4% above none; a launch of several cases runs without
+// (measured neutral with two lockstep groups, 3% slower with one: cases
+// differ in their cost per chunk more than layers do).
+void particle_roles(std::vector<BlockRole>& roles, const std::vector<Case*>& cs, const std::vector<int>& want,
+                    int num_cu, int skew) {
+  struct Pos {
+    double key;
+    int k, j;
+  };
+  std::vector<Pos> order;
+  for (size_t k = 0; k < cs.size(); ++k)
+    for (int j = 0; j < want[k]; ++j) order.push_back({(j + 0.5) / want[k], (int)k, j});
+  std::stable_sort(order.begin(), order.end(), [](const Pos& a, const Pos& b) { return a.key < b.key; });
+  const size_t off = roles.size();
+  const int nblocks = (int)order.size();
+  std::vector<std::vector<int>> at(cs.size());
+  for (int b = 0; b < nblocks; ++b) {
+    const Pos& p = order[b];
+    roles.push_back(role(cs[p.k], p.j, want[p.k]));
+    at[p.k].push_back(b);  // j increasing with b within a case
+  }
+  const int layers = (nblocks + num_cu - 1) / std::max(1, num_cu);
+  if (skew < 0) skew = cs.size() == 1 ? std::min(900, 200 * (layers - 1)) : 0;
+  auto weight = [&](int b) {
+    if (layers < 2 || skew <= 0) return 1.0;
+    return 1.0 - 1e-3 * skew * (double)(b / num_cu) / (double)(layers - 1);
+  };
+  const double one = (double)(1ull << 31);
+  for (size_t k = 0; k < cs.size(); ++k) {
+    double total = 0.0;
+    for (int b : at[k]) total += weight(b);
+    double acc = 0.0;
+    uint32_t lo = 0;
+    for (size_t j = 0; j < at[k].size(); ++j) {
+      BlockRole& r = roles[off + at[k][j]];
+      acc += weight(at[k][j]);
+      r.f_lo = lo;
+      r.f_hi = j + 1 == at[k].size() ? (uint32_t)(1ull << 31) : (uint32_t)std::min(one, std::floor(acc / total * one));
+      lo = r.f_hi;
+    }
+  }
 }
 
 // Workgroups of a case's sort histogram and scatter.
@@ -581,8 +639,7 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
   roles.reserve((size_t)B.parts[0] + B.parts[1] + nc + B.sorts[0] + B.sorts[1]);
   for (int sp = 0; sp < 2; ++sp) {
     B.role_off[sp] = roles.size();
-    for (size_t k = 0; k < nc; ++k)
-      for (int j = 0; j < want[sp][k]; ++j) roles.push_back(role(cs[k], j, want[sp][k]));
+    particle_roles(roles, cs, want[sp], ctx->num_cu, ctx->part_skew);
   }
   B.role_off[2] = roles.size();
   for (size_t k = 0; k < nc; ++k) roles.push_back(role(cs[k], 0, 1));
@@ -1917,6 +1974,10 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
     case EDP_OPT_PART_WG_PER_CU:
       if (value < 0 || value > 64) return fail(EDP_EINVAL, "workgroups per CU must be 0..64");
       ctx->part_wg_per_cu = (int)value;
+      break;
+    case EDP_OPT_PART_SKEW:
+      if (value < -1 || value > 900) return fail(EDP_EINVAL, "workgroup share skew must be -1..900 (per mille)");
+      ctx->part_skew = (int)value;
       break;
     case EDP_OPT_GROUPS:
       static_assert(kMaxGroups == 4, "the message below names the limit");

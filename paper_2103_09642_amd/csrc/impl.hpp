@@ -167,9 +167,10 @@ constexpr int kShards = 64;
 // ring, the case's step at the start of the window (refreshed on the device
 // by the window's first kernel), its index among that case's workgroups of
 // the same kind and their number, and the case's node count and ion
-// subcycle -- in one scalar load, so that its first loads of the deposit
-// need not wait for the case block.  A launch of a window gets its step
-// offset as an argument: step = step0 + dstep.
+// subcycle, and for a particle workgroup its share of the case's chunks --
+// in one scalar load, so that its first loads of the deposit need not wait
+// for the case block.  A launch of a window gets its step offset as an
+// argument: step = step0 + dstep.
 constexpr int kMaxBatch = 256;
 struct BlockRole {
   CaseDev* c;
@@ -179,6 +180,10 @@ struct BlockRole {
   int64_t step0;
   int32_t j, n;
   int32_t ng, nsub;
+  // particle workgroups: chunks [nch*f_lo, nch*f_hi) / 2^31 of the case's nch
+  // chunks of a step (consecutive workgroups share their bounds, the first
+  // starts at 0 and the last ends at 2^31)
+  uint32_t f_lo, f_hi;
 };
 
 }  // namespace edp

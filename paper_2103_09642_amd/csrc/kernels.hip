@@ -606,11 +606,15 @@ __device__ __forceinline__ void ionization_angle(const EDP_CONST CaseDev* __rest
   }
 }
 
-// The colliding electron i itself, process proc (0 elastic, 1 excitation,
-// 2 ionization): its new velocity.
-__device__ __forceinline__ void electron_scatter_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
-                                                    int64_t i, int proc, int64_t s, double vxn, double vy,
-                                                    double vz, uint64_t uid) {
+// An outgoing electron of a collision: the colliding electron itself
+// (process proc: 0 elastic, 1 excitation, 2 ionization) or, with `eject`,
+// the electron its ionization ejects (proc 2), from the parent's pushed
+// velocity and identity.  Both take the frame of g and the draws of the
+// parent's counter; the ejected one leaves with the other share of the
+// energy at the azimuth eta + pi.  Returns the new velocity.
+__device__ __forceinline__ void electron_outgoing(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
+                                                  bool eject, int proc, int64_t s, double vxn, double vy,
+                                                  double vz, uint64_t uid, double& ox, double& oy, double& oz) {
   const uint32_t st = (uint32_t)s;
   // squared speed, the squares summed from x to z as the collision test does
   const double v2 = vxn * vxn + vy * vy + vz * vz;
@@ -632,51 +636,26 @@ __device__ __forceinline__ void electron_scatter_at(const EDP_CONST CaseDev* __r
   } else {
     double e_ev, e_ej;
     ionization_share(C, P, v2, uid, st, e_ev, e_ej);
-    if (0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion < 0.0) gl_add(P.anomaly, 1);
-    const double e_sc = e_ev - e_ej;
-    gnew = sqrt(2.0 * e_sc * kEvToJ / kMuEAr);
-    ionization_angle(C, e_sc, e_ev, cos_chi, sin_chi);
+    if (!eject && 0.5 * kMuEAr * v2 / kEvToJ - C->thr_ion < 0.0) gl_add(P.anomaly, 1);
+    const double e_out = eject ? e_ej : e_ev - e_ej;
+    gnew = sqrt(2.0 * e_out * kEvToJ / kMuEAr);
+    ionization_angle(C, e_out, e_ev, cos_chi, sin_chi);
   }
   const double f1 = kEMass / (kEMass + kArMass);
   const double f2 = kArMass / (kEMass + kArMass);
   const Frame F = frame_of(vxn, vy, vz, v);
   double cos_eta, sin_eta;
-  sincos(kTwoPi * r_eta, &sin_eta, &cos_eta);
-  double ox, oy, oz;
+  const double eta = kTwoPi * r_eta;
+  sincos(eject ? eta + kPi : eta, &sin_eta, &cos_eta);
   rotate(F, gnew, f2, cos_chi, sin_chi, cos_eta, sin_eta, f1 * vxn, f1 * vy, f1 * vz, ox, oy, oz);
+}
+
+// Stores of an electron's velocity (and the float bound of vy^2 + vz^2).
+__device__ __forceinline__ void store_electron_v(const ScatterPtrs& P, int64_t i, double ox, double oy, double oz) {
   P.evx[i] = ox;
   P.evy[i] = oy;
   P.evz[i] = oz;
   P.evp2[i] = float_above(oy * oy + oz * oz);
-}
-
-// The electron an ionization ejects, at slot be, from the parent's state.
-__device__ __forceinline__ void electron_eject_at(const EDP_CONST CaseDev* __restrict__ C, const ScatterPtrs& P,
-                                                  int64_t be, int64_t s, double vxn, double vy, double vz,
-                                                  uint64_t uid, double x) {
-  const uint32_t st = (uint32_t)s;
-  const double v2 = vxn * vxn + vy * vy + vz * vz;
-  const double v = sqrt(v2);
-  double e_ev, e_ej;
-  ionization_share(C, P, v2, uid, st, e_ev, e_ej);
-  const double g_ej = sqrt(2.0 * e_ej * kEvToJ / kMuEAr);
-  double cs_ej, sn_ej;
-  ionization_angle(C, e_ej, e_ev, cs_ej, sn_ej);
-  double r_chi, r_eta;
-  uniform2(C->seed, uid, st, tag(0, 0, 1), r_chi, r_eta);
-  const double f1 = kEMass / (kEMass + kArMass);
-  const double f2 = kArMass / (kEMass + kArMass);
-  const Frame F = frame_of(vxn, vy, vz, v);
-  double cos_eta2, sin_eta2;
-  sincos(kTwoPi * r_eta + kPi, &sin_eta2, &cos_eta2);
-  double ex_, ey_, ez_;
-  rotate(F, g_ej, f2, cs_ej, sn_ej, cos_eta2, sin_eta2, f1 * vxn, f1 * vy, f1 * vz, ex_, ey_, ez_);
-  P.ex[be] = x;
-  P.evx[be] = ex_;
-  P.evy[be] = ey_;
-  P.evz[be] = ez_;
-  P.evp2[be] = float_above(ey_ * ey_ + ez_ * ez_);
-  P.euid[be] = child_uid(uid, s, 1);
 }
 
 // The ion an ionization creates, at slot bi at the parent's position: a
@@ -751,15 +730,16 @@ __device__ __forceinline__ void see_emit_at(const EDP_CONST CaseDev* __restrict_
 // ---------------------------------------------------------------------------
 // Steps 3-6 for one species plus the deposit for step s+1.
 //
-// A case's particle slots are cut into chunks of kChunk = 256 slots; wave w
-// of a workgroup owns slots [c*256 + 64w, c*256 + 64w + 64) of chunk c, one
-// per lane.  In the lockstep kernels a case gets a fixed number of
-// workgroups (its share, by expected particle count, of the resident slots
-// the batch uses); workgroup j takes the contiguous chunk range
-// [j*per, (j+1)*per) with per computed from the step's slot count, so the
-// launch shape never depends on the count and every workgroup does the same
-// amount of work.  The small-case kernel runs every chunk of its case in one
-// workgroup.
+// A case's particle slots are cut into chunks of NB slots (the workgroup
+// size).  In the lockstep kernels a case gets a fixed number of workgroups
+// (its share, by expected particle count, of the resident slots the batch
+// uses); each takes a contiguous range of the step's chunks by the share
+// its role gives it (the later a workgroup is dispatched, the smaller its
+// share, when the host weights them so), so the launch shape never depends
+// on the count.  The small-case kernel runs every chunk of its case
+// in one workgroup.  Inside a workgroup the range is worked in slices of 64
+// slots, one per lane: wave w takes slices w, w + W, w + 2W, ... of its
+// workgroup's W waves.
 //
 // Every particle: gather E from LDS, leapfrog, wall test, deposit the new x
 // into the workgroup's LDS histogram, store x and v_x, and one Philox call
@@ -769,9 +749,10 @@ __device__ __forceinline__ void see_emit_at(const EDP_CONST CaseDev* __restrict_
 // covers, can give a collision; such candidates (a few percent) go to the
 // wave's LDS segment and everyone else is done.  The candidates get the
 // exact test -- energy bin, table lookups, exp, for ions the thermal target
-// first -- and the colliders their scattering, in dense passes: all of the
-// workgroup's at the end as one list, or a wave's own when its segment
-// fills.  So the table work and the transcendentals run on full waves
+// first -- and the colliders their scattering, in dense passes after the
+// loop: each wave its own segment, then the workgroup's overflow list (the
+// segments that filled during the loop), 64 entries per pass from an LDS
+// counter.  So the table work and the transcendentals run on full waves
 // instead of on every wave with one candidate lane.  An ionization takes
 // slots for its newborns from the step's birth counters, writes them, and
 // adds their charge (the electron a second share at the parent's x, the ion
@@ -825,34 +806,25 @@ struct Births {
     dropped += (int)__popcll(__ballot(mine && !ok));
     return mine && ok ? slot : -1;
   }
-  // Slots of an ionization's two newborns (an electron and an ion) for the
-  // lanes with `mine`: both counters' atomics go out together.
-  __device__ __forceinline__ void take_pair(bool mine, int lane, int64_t& be, int64_t& bi, int& placed_e,
-                                            int& placed_i, int& dropped) const {
-    const uint64_t m = __ballot(mine);
-    be = bi = -1;
-    if (m == 0) return;
-    long long b0 = 0, b1 = 0;
+  // Slots of the newborn pairs (an electron and an ion) of the wave's `cnt`
+  // ionizations: issue() takes them from both counters (lane 0; the
+  // atomics go out together and their values are needed only by
+  // first_slots()), newborn r of the wave then has slot first + r.
+  __device__ __forceinline__ void issue_pair(int cnt, int lane, long long& a_e, long long& a_i) const {
+    a_e = a_i = 0;
     if (lane == 0) {
-      const int c = (int)__popcll(m);
       if (SMALL) {
-        b0 = atomicAdd(&lds[0], c);
-        b1 = atomicAdd(&lds[1], c);
+        a_e = atomicAdd(&lds[0], cnt);
+        a_i = atomicAdd(&lds[1], cnt);
       } else {
-        b0 = (long long)gl_fetch_add(glob[0], (unsigned long long)c);
-        b1 = (long long)gl_fetch_add(glob[1], (unsigned long long)c);
+        a_e = (long long)gl_fetch_add(glob[0], (unsigned long long)cnt);
+        a_i = (long long)gl_fetch_add(glob[1], (unsigned long long)cnt);
       }
     }
-    b0 = __shfl(b0, 0);
-    b1 = __shfl(b1, 0);
-    const int r = lane_rank(m);
-    const int64_t se = base[0] + (int64_t)b0 + r, si = base[1] + (int64_t)b1 + r;
-    const bool ok_e = se < cap[0], ok_i = si < cap[1];
-    placed_e += (int)__popcll(__ballot(mine && ok_e));
-    placed_i += (int)__popcll(__ballot(mine && ok_i));
-    dropped += (int)__popcll(__ballot(mine && !ok_e)) + (int)__popcll(__ballot(mine && !ok_i));
-    be = mine && ok_e ? se : -1;
-    bi = mine && ok_i ? si : -1;
+  }
+  __device__ __forceinline__ void first_slots(long long a_e, long long a_i, int64_t& f_e, int64_t& f_i) const {
+    f_e = base[0] + (int64_t)__shfl(a_e, 0);
+    f_i = base[1] + (int64_t)__shfl(a_i, 0);
   }
 };
 
@@ -878,6 +850,10 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   __shared__ double sVx[kPay][SP == 0 ? kSeg : 1];
   __shared__ uint64_t sUid[kPay][SP == 0 ? kSeg : 1];
   __shared__ int sTot[NB / kWave][kRec];
+  // entries of the overflow list, next pass over it
+  __shared__ int sOvf, sFin;
+  // lanes of a pass's ionizing colliders by rank (electrons)
+  __shared__ int sIon[SP == 0 ? NB / kWave : 1][SP == 0 ? kWave : 1];
   const int ng = C->ng;
   const int nsub = C->nsub;
   const int64_t kion = s / nsub;
@@ -904,10 +880,15 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
     }
   }
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x) sF[b] = 0;
+  constexpr int kWaves = NB / kWave;
+  if (threadIdx.x == 0) {
+    sOvf = 0;
+    sFin = 0;
+  }
   __syncthreads();
   EDP_GLOBAL double* __restrict__ X = G(C->sp[SP].x[cur]);
-  // this workgroup's overflow lists of candidates: its chunk range of the
-  // species' list, a quarter per wave
+  // this workgroup's overflow list of candidates: its chunk range of the
+  // species' list (as many entries as the range has slots)
   EDP_GLOBAL int64_t* __restrict__ CL = G(C->clist[SP]) + c_lo * NB;
   EDP_GLOBAL double* __restrict__ VX = G(C->sp[SP].vx[cur]);
   const EDP_GLOBAL double* __restrict__ VY = G(C->sp[SP].vy[cur]);
@@ -1034,46 +1015,60 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
     return proc;
   };
 
-  // A wave's full segment inside the streaming loop goes to the wave's
-  // overflow list (its quarter of the workgroup's range of the species'
-  // list, as many entries as the wave has slots) and is tested after the
+  // A wave's full segment inside the streaming loop goes to the
+  // workgroup's overflow list (entries taken from an LDS counter; the
+  // workgroup's candidates are at most its slots) and is tested after the
   // loop: the loop holds no table or transcendental code, so it keeps few
   // registers.
-  EDP_GLOBAL int64_t* __restrict__ CLw = CL + (int64_t)w * (c_hi - c_lo) * kWave;
-  int nov = 0;  // entries of this wave's overflow list
   auto spill_segment = [&](const int count) {
-    for (int k = lane; k < count; k += kWave) CLw[nov + k] = sSeg[w][k];
-    nov += count;
+    int off = 0;
+    if (lane == 0) off = atomicAdd(&sOvf, count);
+    off = __builtin_amdgcn_readfirstlane(__shfl(off, 0));
+    for (int k = lane; k < count; k += kWave) CL[off + k] = sSeg[w][k];
   };
 
-  // After the loop and the histogram's flush, each wave its own list, in
-  // rounds of 64 entries: its overflow list (state reloaded), then what is
-  // left in its segment.  Each round runs the exact test, moves the round's
+  // After the loop and the histogram's flush, in rounds of 64 entries: each
+  // wave what is left in its segment, then rounds of the workgroup's
+  // overflow list (state reloaded) from an LDS counter, until none is left.
+  // Each round runs the exact test, moves the round's
   // colliders with their state to the low lanes (one push permutation), and
   // gives each its scattering; an ionization also gets its newborns (slots
   // from the step's counters, charge at the parent's new position: the
   // electron a second share of this step's deposit, the ion the next ion
   // step's density).  No workgroup barrier: waves finish at their own pace.
   auto finish = [&]() {
-    const int count = nov + ncw;
-    for (int b0 = 0; b0 < count; b0 += kWave) {
+    const int npool = sOvf;  // written before the barrier after the loop
+    const int own = (ncw + kWave - 1) / kWave;
+    for (int round = 0;; ++round) {
+      bool pool = false;
+      int b0, count;
+      if (round < own) {
+        b0 = round * kWave;
+        count = ncw;
+      } else {
+        int g = 0;
+        if (lane == 0) g = atomicAdd(&sFin, 1);
+        b0 = __builtin_amdgcn_readfirstlane(__shfl(g, 0)) * kWave;
+        if (b0 >= npool) break;
+        pool = true;
+        count = npool;
+      }
       const int k = b0 + lane;
       int64_t i = 0;
       double vxn = 0.0, vy = 0.0, vz = 0.0;
       uint64_t uid = 0;
       int proc = -1;
       if (k < count) {
-        if (k < nov) {
-          i = CLw[k];
+        if (pool) {
+          i = CL[k];
           vxn = VX[i];
           uid = UID[i];
         } else {
-          const int kk = k - nov;
-          i = sSeg[w][kk];
+          i = sSeg[w][k];
           if (SP == 0) {
             // the pushed v_x and the uid from the segment
-            vxn = sVx[SP == 0 ? w : 0][SP == 0 ? kk : 0];
-            uid = sUid[SP == 0 ? w : 0][SP == 0 ? kk : 0];
+            vxn = sVx[SP == 0 ? w : 0][SP == 0 ? k : 0];
+            uid = sUid[SP == 0 ? w : 0][SP == 0 ? k : 0];
           } else {
             vxn = VX[i];
             uid = UID[i];
@@ -1105,12 +1100,55 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
       if (SP == 0) {
         const bool ioniz = coll && proc == 2;
         const uint64_t mi = __ballot(ioniz);
-        if (mi) {
-          t_ioniz += (int)__popcll(mi);
-          // the parent's new position loads while the slots are taken
+        if (mi == 0) {
+          if (coll) {
+            double ox, oy, oz;
+            electron_outgoing(C, P, false, proc, s, vxn, vy, vz, uid, ox, oy, oz);
+            store_electron_v(P, i, ox, oy, oz);
+          }
+        } else {
+          // Ionizations.  The parent's new position and the newborns' slots
+          // are loaded and taken first and used only at the stores; the
+          // ejected electrons are worked on the lanes the colliders leave
+          // free, beside the colliders, in rank order (more passes if they
+          // do not fit); the new ions on their parents' lanes after that.
+          const int ni = (int)__popcll(mi);
+          t_ioniz += ni;
+          const int ri = lane_rank(mi);
           const double xb = ioniz ? X[i] : 0.0;
-          int64_t be, bi;
-          B.take_pair(ioniz, lane, be, bi, t_be, t_bi, t_drop);
+          long long a_e, a_i;
+          B.issue_pair(ni, lane, a_e, a_i);
+          if (ioniz) sIon[SP == 0 ? w : 0][SP == 0 ? ri : 0] = lane;
+          int64_t f_e = 0, f_i = 0;
+          bool have_slots = false;
+          for (int e0 = 0, pass = 0; pass == 0 || e0 < ni; ++pass) {
+            const int lane0 = pass == 0 ? ncol : 0;
+            const int e = e0 + lane - lane0;  // the ejected electron of this lane, by rank
+            const bool ej = lane >= lane0 && e < ni;
+            const bool par = pass == 0 && coll;
+            const int src = ej ? sIon[SP == 0 ? w : 0][SP == 0 ? e : 0] : lane;
+            const double tvx = __shfl(vxn, src), tvy = __shfl(vy, src), tvz = __shfl(vz, src);
+            const uint64_t tuid = (uint64_t)__shfl((long long)uid, src);
+            double ox = 0.0, oy = 0.0, oz = 0.0;
+            if (par || ej) electron_outgoing(C, P, ej, ej ? 2 : proc, s, tvx, tvy, tvz, tuid, ox, oy, oz);
+            if (!have_slots) {
+              B.first_slots(a_e, a_i, f_e, f_i);
+              have_slots = true;
+            }
+            const double tx = __shfl(xb, src);
+            if (par) store_electron_v(P, i, ox, oy, oz);
+            const int64_t be = f_e + e;
+            if (ej && be < B.cap[0]) {
+              P.ex[be] = tx;
+              store_electron_v(P, be, ox, oy, oz);
+              P.euid[be] = child_uid(tuid, s, 1);
+            }
+            e0 += kWave - lane0;
+          }
+          const bool ok_e = f_e + ri < B.cap[0], ok_i = f_i + ri < B.cap[1];
+          t_be += (int)__popcll(__ballot(ioniz && ok_e));
+          t_bi += (int)__popcll(__ballot(ioniz && ok_i));
+          t_drop += (int)__popcll(__ballot(ioniz && !ok_e)) + (int)__popcll(__ballot(ioniz && !ok_i));
           if (ioniz) {
             long long r;
             const int q = deposit_split(xb, inv_dx, ng, r);
@@ -1118,26 +1156,26 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
             gl_add(&dst[q + 1], r);
             gl_add(&cnt_i_next[q], 4294967296LL - r);
             gl_add(&cnt_i_next[q + 1], r);
-            if (be >= 0) electron_eject_at(C, P, be, s, vxn, vy, vz, uid, xb);
-            if (bi >= 0) ion_birth_at(C, P, bi, s, uid, xb);
+            if (ok_i) ion_birth_at(C, P, f_i + ri, s, uid, xb);
           }
         }
-        if (coll) electron_scatter_at(C, P, i, proc, s, vxn, vy, vz, uid);
       } else if (coll) {
         ion_scatter_at(C, P, i, proc, s, vxn, vy, vz, uid);
       }
     }
   };
 
-  // The state of chunk c + 1 is loaded before chunk c is worked on, so each
-  // wave keeps two chunks' loads in flight (the loop is bound by memory
-  // latency, not by its arithmetic).
-  const int slot = w * kWave + lane;  // slot in the chunk
+  // The state of a wave's next slice is loaded before its current one is
+  // worked on, so each wave keeps two slices' loads in flight (the loop is
+  // bound by memory latency, not by its arithmetic).
+  const int64_t q_lo = c_lo * kWaves;
+  const int64_t q_end = (n + kWave - 1) / kWave;
+  const int64_t q_hi = c_hi * kWaves < q_end ? c_hi * kWaves : q_end;
   double nx = 0.0, nvx = 0.0, nvy = 0.0, nvz = 0.0;
   float nvp2 = 0.0f;
   uint64_t nuid = 0;
-  auto fetch = [&](const int64_t c) {
-    const int64_t i = c * NB + slot;
+  auto fetch = [&](const int64_t q) {
+    const int64_t i = q * kWave + lane;
     nx = __longlong_as_double(0x7FF8000000000000LL);
     nvx = nvy = nvz = 0.0;
     nvp2 = 0.0f;
@@ -1153,12 +1191,14 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
       nuid = UID[i];
     }
   };
-  if (c_lo < c_hi) fetch(c_lo);
-  for (int64_t c = c_lo; c < c_hi; ++c) {
-    const int64_t i = c * NB + slot;
+  int64_t q = q_lo + w;
+  if (q < q_hi) fetch(q);
+  while (q < q_hi) {
+    const int64_t i = q * kWave + lane;
     const double x = nx, vx = nvx, vy = nvy, vz = nvz, vp2 = (double)nvp2;
     const uint64_t uid = nuid;
-    if (c + 1 < c_hi) fetch(c + 1);
+    const int64_t qn = q + kWaves;
+    if (qn < q_hi) fetch(qn);
     bool live = x == x;  // past the end, or absorbed earlier (tombstone)
     t_live += (int)__popcll(__ballot(live));
     bool abs_pow = false, abs_gnd = false, surf = false, cand = false;
@@ -1302,6 +1342,7 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
     }
     t_pow += (int)__popcll(__ballot(abs_pow));
     t_gnd += (int)__popcll(__ballot(abs_gnd));
+    q = qn;
   }
   __syncthreads();
   // flush first (deposit for step s+1 and diagnostics of step s): the
@@ -1321,7 +1362,7 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   int64_t* hist = SP == 0 ? C->eepf : C->ifed;
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x)
     if (sF[b]) gl_add(&hist[b], (long long)sF[b]);
-  // this wave's overflow list and segment
+  // this wave's segment, then the workgroup's overflow list
   finish();
   if (lane == 0) {
     sTot[w][kRecColl] = t_coll;
@@ -1336,10 +1377,11 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   __syncthreads();
   SpTot T;
 #pragma unroll
-  for (int f = 0; f < kRec; ++f) {
-    T.v[f] = 0;
-    for (int u = 0; u < NB / kWave; ++u) T.v[f] += sTot[u][f];
-  }
+  for (int f = 0; f < kRec; ++f) T.v[f] = 0;
+#pragma unroll 1
+  for (int u = 0; u < NB / kWave; ++u)
+#pragma unroll
+    for (int f = 0; f < kRec; ++f) T.v[f] += sTot[u][f];
   __syncthreads();  // sTot, the segments and the histograms are free again
   return T;
 }
@@ -1366,7 +1408,7 @@ k_particles(const BlockRole* __restrict__ R, int dstep) {
   extern __shared__ double psm[];
   const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
   CaseDev* Cw = r->c;
-  const int ng = r->ng, nsub = r->nsub, j = r->j, nwg = r->n;
+  const int ng = r->ng, nsub = r->nsub, j = r->j;
   const int64_t s = r->step0 + dstep;
   if (SP == 1 && (s % nsub) != 0) return;  // ions move on ion steps only
   double* sE = psm;
@@ -1375,10 +1417,9 @@ k_particles(const BlockRole* __restrict__ R, int dstep) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   const int64_t n_e = step_slots(C, 0, s), n_i = step_slots(C, 1, s);
   const int64_t n = SP == 0 ? n_e : n_i;
-  const int64_t nch = (n + kPartBlock - 1) / kPartBlock;
-  const int64_t per = (nch + nwg - 1) / nwg;
-  const int64_t c_lo = (int64_t)j * per;
-  const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
+  const uint64_t nch = (uint64_t)((n + kPartBlock - 1) / kPartBlock);
+  const int64_t c_lo = (int64_t)((nch * r->f_lo) >> 31);
+  const int64_t c_hi = (int64_t)((nch * r->f_hi) >> 31);
   const int cur = C->cur[SP];
   solve_field<MODE, kPartBlock>(Cw, r->cnt_e, r->cnt_i, r->volt, ng, nsub, s, sE, reg, writer);
   if (writer && threadIdx.x == 0) {

@@ -25,6 +25,7 @@ OPT_MODE, OPT_SORT_EVERY, OPT_PROFILE, OPT_GRAPH_STEPS = 1, 2, 5, 6
 OPT_POISSON = 8
 OPT_PART_WG_PER_CU = 9
 OPT_GROUPS = 11
+OPT_PART_SKEW = 13
 OPT_SMALL_MAX = 12
 POISSON_FLUX, POISSON_THOMAS = 0, 1
 MODE_PLAIN, MODE_GRAPH = 0, 1

@@ -93,6 +93,37 @@ def test_batch_equals_alone(ctx, mode, groups):
             ctx.set_option(edupic.OPT_GROUPS, bad)
 
 
+def test_chunk_shares_change_nothing(ctx):
+    """A case with more chunks than the chip has resident particle
+    workgroups (so its workgroups span several dispatch layers): its result
+    is bit-identical whatever weighting of the workgroups' chunk shares
+    (EDP_OPT_PART_SKEW) and workgroups per CU the launches use."""
+    from paper_2103_09642_amd import edupic
+    say("test_chunk_shares_change_nothing")
+    n = 400_000
+    c = base_case(n_init_e=0, n_init_i=0, weight=1e3, n_grid=1000, pressure_pa=30.0, flags=["allow_unstable"],
+                  cap_e=2 * n, cap_i=2 * n, seed=31)
+    st = random_state(n, n, c["gap_m"], seed=31, te_ev=3.0, hot_frac=0.2, hot_ev=80.0)
+    ctx.set_option(edupic.OPT_SORT_EVERY, 10)
+    res = []
+    for skew, wg in ((0, 0), (-1, 0), (900, 0), (450, 3)):
+        ctx.set_option(edupic.OPT_PART_SKEW, skew)
+        ctx.set_option(edupic.OPT_PART_WG_PER_CU, wg)
+        g = _make(ctx, c, st, 7)
+        g.advance_steps(45)
+        res.append(_result(g))
+        g.destroy()
+    ctx.set_option(edupic.OPT_PART_SKEW, -1)
+    ctx.set_option(edupic.OPT_PART_WG_PER_CU, 0)
+    ctx.set_option(edupic.OPT_SORT_EVERY, 100)
+    for k in range(1, len(res)):
+        _same(res[0], res[k], f"schedule {k}")
+    assert res[0][3]["ioniz"] > 0 and res[0][3]["coll_e"] > 0
+    for bad in (-2, 901):
+        with pytest.raises(edupic.EdpError):
+            ctx.set_option(edupic.OPT_PART_SKEW, bad)
+
+
 def test_batch_matches_oracle(ctx, xs_default, orc):
     """Three cases advanced together for 40 steps against three oracle runs:
     counters exact, states to the one-step bar (with the flux solve's field
