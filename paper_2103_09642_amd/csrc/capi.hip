@@ -77,7 +77,11 @@ struct Case {
   int64_t arena_bytes = 0;
   int64_t step = 0;        // next step to run (host view)
   int64_t est[2] = {0, 0}; // estimate of the slots in use, for launch sizing
-  int64_t* est_pinned = nullptr;  // async read-back of alloc[]
+  int64_t* est_pinned = nullptr;  // async read-back of alloc[] .. ctr[] (kEstSpan bytes)
+  // collisions per particle step of each species over the last read-backs
+  // far enough apart (kRateSteps particle steps), and that read-back's counters
+  double coll_rate[2] = {0.0, 0.0};
+  int64_t rate_coll[2] = {0, 0}, rate_pst[2] = {0, 0};
   hipEvent_t est_ev = nullptr;
   bool est_pending = false;
   double* vstage = nullptr;  // pinned staging of V(t_s)
@@ -387,6 +391,21 @@ int blocks_for(const edp_ctx* ctx, int64_t n) {
 // Expected chunks of a species of a case (10% headroom over the estimate).
 int64_t est_chunks(const Case* c, int sp) { return (c->est[sp] + c->est[sp] / 10 + kChunk) / kChunk; }
 
+// Expected work of a case's electron share of a particle launch: its chunks
+// weighted by the collision work per particle step.  Timestamps of every
+// workgroup of batched launches (the 32 dual-frequency and the 64
+// heterogeneous cases) put a workgroup's time at about 10.5 ns per electron
+// of its range plus about 200 ns per collider (exact test and scattering):
+// a collider weighs as much as 20 electrons.  Ions are weighted by their
+// chunks alone (not measured).
+constexpr double kCollWeight[2] = {20.0, 0.0};
+double est_cost(const Case* c, int sp) {
+  return (double)est_chunks(c, sp) * (1.0 + kCollWeight[sp] * c->coll_rate[sp]);
+}
+// Bytes read back by request_estimate: CaseDev from alloc[] to the end of ctr[].
+constexpr size_t kEstSpan = offsetof(CaseDev, ctr) + sizeof(int64_t) * kNumCtr - offsetof(CaseDev, alloc);
+constexpr int64_t kRateSteps = 1 << 20;
+
 // Upload V(t_s) for steps [s0, s1) (s1 - s0 <= kVoltChunk) into the ring.
 int upload_volt(Case* c, int64_t s0, int64_t s1, hipStream_t st) {
   if (c->vev_pending) {
@@ -407,15 +426,35 @@ int upload_volt(Case* c, int64_t s0, int64_t s1, hipStream_t st) {
 
 void poll_estimate(Case* c) {
   if (c->est_pending && hipEventQuery(c->est_ev) == hipSuccess) {
-    c->est[0] = c->est_pinned[0];
-    c->est[1] = c->est_pinned[1];
+    const char* b = (const char*)c->est_pinned;
+    auto at = [&](size_t off) {
+      int64_t v;
+      std::memcpy(&v, b + off - offsetof(CaseDev, alloc), sizeof v);
+      return v;
+    };
+    c->est[0] = at(offsetof(CaseDev, alloc));
+    c->est[1] = at(offsetof(CaseDev, alloc) + 8);
+    const size_t ctr = offsetof(CaseDev, ctr);
+    const int64_t coll[2] = {at(ctr + 8 * kCollE), at(ctr + 8 * kCollI)};
+    const int64_t pst[2] = {at(ctr + 8 * kPstepE), at(ctr + 8 * kPstepI)};
+    for (int sp = 0; sp < 2; ++sp) {
+      const int64_t dp = pst[sp] - c->rate_pst[sp], dc = coll[sp] - c->rate_coll[sp];
+      if (dp < 0 || dc < 0) {  // counters restarted: a new baseline
+        c->rate_pst[sp] = pst[sp];
+        c->rate_coll[sp] = coll[sp];
+      } else if (dp >= kRateSteps) {
+        c->coll_rate[sp] = (double)dc / (double)dp;
+        c->rate_pst[sp] = pst[sp];
+        c->rate_coll[sp] = coll[sp];
+      }
+    }
     c->est_pending = false;
   }
 }
 
 int request_estimate(Case* c, hipStream_t st) {
   if (c->est_pending) return EDP_OK;
-  HIPCHK(hipMemcpyAsync(c->est_pinned, (char*)c->d + offsetof(CaseDev, alloc), 16, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(c->est_pinned, (char*)c->d + offsetof(CaseDev, alloc), kEstSpan, hipMemcpyDeviceToHost, st));
   HIPCHK(hipEventRecord(c->est_ev, st));
   c->est_pending = true;
   return EDP_OK;
@@ -559,9 +598,9 @@ int sort_blocks(const edp_ctx* ctx, const Case* c, int sp) { return std::max(1, 
 // Build the batch table for `cs` (in this order) and upload it.  Particle
 // workgroups: the chip's resident workgroups (at most part_wg_per_cu per CU
 // when that option is set) shared out in proportion to each case's expected
-// chunks, so every workgroup takes about the same
-// number of chunks (any count is still covered: the kernels split the live
-// chunks over whatever workgroups a case has).  The table is read by
+// work (est_cost), so every workgroup has about the same amount of it (any
+// count is still covered: the kernels split the live chunks over whatever
+// workgroups a case has).  The table is read by
 // kernels still in flight, so the stream is drained before it changes;
 // grids are rebuilt only when a case's estimate has moved by a quarter.
 int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
@@ -579,8 +618,8 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
     const int occ = particle_occupancy(sp, lds[sp]);
     const int per_cu = ctx->part_wg_per_cu > 0 ? std::min(ctx->part_wg_per_cu, occ) : occ;
     const int64_t slots = (int64_t)ctx->num_cu * per_cu;
-    int64_t total = 0;
-    for (const Case* c : cs) total += est_chunks(c, sp);
+    double total = 0.0;
+    for (const Case* c : cs) total += est_cost(c, sp);
     // every case at least one workgroup, the slots in proportion to the
     // chunks (largest remainders first), never more workgroups than chunks
     // and never more than the slots in all (unless the cases outnumber
@@ -591,7 +630,7 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
     int64_t used = 0;
     for (size_t k = 0; k < nc; ++k) {
       const int64_t ch = est_chunks(cs[k], sp);
-      const double ideal = (double)ch * (double)slots / (double)std::max<int64_t>(1, total);
+      const double ideal = est_cost(cs[k], sp) * (double)slots / std::max(1e-9, total);
       const int64_t w = std::max<int64_t>(1, std::min<int64_t>({(int64_t)ideal, ch, (int64_t)kMaxPartWG}));
       want[sp][k] = (int)w;
       frac[k] = ideal - (double)w;
@@ -610,12 +649,20 @@ int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
   std::vector<int> want_sort[2];
   for (int sp = 0; sp < 2; ++sp)
     for (size_t k = 0; k < nc; ++k) want_sort[sp].push_back(sort_blocks(ctx, cs[k], sp));
+  // rebuilt when a case's share has moved by a quarter, or the shares by a
+  // sixteenth of the workgroups in all
   auto near = [](int a, int a0) { return a <= a0 * 5 / 4 + 1 && a >= a0 * 3 / 4; };
   bool same = G.valid && B.cases == cs;
+  int64_t moved[2] = {0, 0};
   for (size_t k = 0; k < nc && same; ++k) {
-    for (int sp = 0; sp < 2 && same; ++sp) same = near(want[sp][k], B.h.part_off[sp][k + 1] - B.h.part_off[sp][k]);
+    for (int sp = 0; sp < 2 && same; ++sp) {
+      const int had = B.h.part_off[sp][k + 1] - B.h.part_off[sp][k];
+      same = near(want[sp][k], had);
+      moved[sp] += std::abs(want[sp][k] - had);
+    }
     for (int sp = 0; sp < 2 && same; ++sp) same = near(want_sort[sp][k], B.h.sort_off[sp][k + 1] - B.h.sort_off[sp][k]);
   }
+  for (int sp = 0; sp < 2 && same; ++sp) same = 16 * moved[sp] <= B.parts[sp];
   if (same) return EDP_OK;
   HIPCHK(hipStreamSynchronize(G.stream));
   drop_graph(G);
@@ -1286,7 +1333,7 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
     return code;
   };
   if (hipHostMalloc((void**)&c->vstage, kVoltChunk * 8, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->est_pinned, 16, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->est_pinned, kEstSpan, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&c->vev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->est_ev, hipEventDisableTiming) != hipSuccess)
     return cleanup(fail(EDP_EHIP, "host staging allocation failed"));
