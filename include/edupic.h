@@ -160,6 +160,14 @@ extern "C" {
                                  most 900, when the launch serves one case,
                                  else 0.  Results do not depend on it, speed
                                  does */
+#define EDP_OPT_PRETEST 14     /* the collision pre-test's bound of P (section
+                                 2.1.6, direct test): 0 (default) automatic,
+                                 1 the bound over the whole table, 2 the
+                                 bound by energy block (the tables' maximum
+                                 up to the particle's energy).  Either is a
+                                 bound, so decisions are those of the exact
+                                 test; results do not depend on it, speed
+                                 does */
 
 typedef struct edp_ctx edp_ctx; /* opaque */
 typedef int64_t edp_case;       /* case handle, > 0 */

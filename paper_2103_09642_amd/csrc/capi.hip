@@ -24,7 +24,7 @@
 #include "impl.hpp"
 
 namespace edp {
-hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, int mode, int dstep,
+hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, int mode, int dstep, int pretest,
                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_window_begin(BlockRole* roles, int nroles, const BlockRole* cases, int ncase, hipStream_t st);
 hipError_t launch_window_end(const BlockRole* cases, int ncase, int steps, hipStream_t st);
@@ -39,7 +39,8 @@ hipError_t launch_sort(const BlockRole* roles, const BlockRole* case_roles, int 
 hipError_t launch_fold(CaseDev* d, hipStream_t st);
 size_t small_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed);
 size_t small_static_lds();
-hipError_t launch_small(const BlockRole* roles, int ncase, size_t lds, int mode, int sort_every, hipStream_t st);
+hipError_t launch_small(const BlockRole* roles, int ncase, size_t lds, int mode, int sort_every, int pretest,
+                        hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 }  // namespace edp
 
@@ -171,6 +172,7 @@ struct edp_ctx {
   // options
   int mode = 0, sort_every = 100, profile = 0, graph_steps = 0, poisson = 0;
   int part_wg_per_cu = 0;  // 0: every resident slot
+  int pretest = 0;  // EDP_OPT_PRETEST
   int part_skew = kAutoSkew;  // per mille: the last layer's weight below the first's; -1 automatic
   int groups = 2;  // lockstep groups of a multi-case advance (1..kMaxGroups)
   // cases of at most this many slots per species (estimate) run in the
@@ -200,7 +202,7 @@ struct edp_ctx {
 namespace {
 
 struct Layout {
-  size_t off_case, off_part[2][2][5], off_vp2[2], off_cl[2], off_tab[7], off_rden, off_volt, off_cnt_e, off_cnt_i,
+  size_t off_case, off_part[2][2][5], off_vp2[2], off_cl[2], off_tab[7], off_pb[2], off_rden, off_volt, off_cnt_e, off_cnt_i,
       off_shard, off_rho, off_phi, off_ef, off_flux, off_sum[6], off_acc[7], off_eepf, off_xt, off_xtcnt, off_ifed,
       off_sort, total;
   int64_t cap[2];
@@ -269,6 +271,7 @@ Layout layout(const edp_case_desc* c, int nbins) {
     L.off_cl[sp] = take(chunks * kMaxChunk * 8);  // candidates (per-workgroup lists over its chunk range)
   }
   for (int t = 0; t < 7; ++t) L.off_tab[t] = take((size_t)nbins * 8);
+  for (int sp = 0; sp < 2; ++sp) L.off_pb[sp] = take((size_t)kMaxPb * 8);
   const size_t ng = (size_t)c->n_grid;
   L.off_rden = take(ng * 8);
   L.off_volt = take((size_t)kVoltChunk * 8);
@@ -315,6 +318,7 @@ void set_pointers(CaseDev& h, char* arena, const Layout& L) {
   h.sig_ion = tabs[4];
   h.sig_iso = tabs[5];
   h.sig_back = tabs[6];
+  for (int sp = 0; sp < 2; ++sp) h.pbound[sp] = (const double*)(arena + L.off_pb[sp]);
   h.rden = (double*)(arena + L.off_rden);
   h.volt = (double*)(arena + L.off_volt);
   h.cnt_e = (int64_t*)(arena + L.off_cnt_e);
@@ -348,14 +352,42 @@ double voltage(const edp_case_desc& c, int64_t s) {
 // n sigma_tot(E) g(E) with g at the upper end of each bin's energy range
 // (energies round to the nearest bin) and, for the last bin, which also holds
 // every higher energy, at four times the table's range.
-double nu_star(const std::vector<double>& nsig, double de_ev, double mass) {
+// Collision-frequency bound of table row i: n sigma_tot at the row's upper
+// energy (energies round to the nearest row), the last row (which also
+// holds every higher energy) taken at four times the table range.
+double row_nu(const std::vector<double>& nsig, int i, double de_ev, double mass) {
   const int nb = (int)nsig.size();
+  const double e_hi = i == nb - 1 ? 4.0 * (double)nb * de_ev : ((double)i + 0.5) * de_ev;
+  return nsig[i] * std::sqrt(2.0 * e_hi * kEvToJ / mass);
+}
+
+// Rows per block of the pre-test's bound table: a power of two giving at
+// most kMaxPb blocks.
+int pb_shift(int nbins) {
+  int s = 0;
+  while (((nbins - 1) >> s) >= kMaxPb) ++s;
+  return s;
+}
+
+// The pre-test's bound by energy (CaseDev::pbound): for block b the prefix
+// maximum of P = 1 - exp(-nu dt) over rows 0 .. the block's last, with the
+// relative margin of p_bound.
+std::vector<double> pbound_table(const std::vector<double>& nsig, double de_ev, double mass, double dt) {
+  const int nb = (int)nsig.size();
+  const int sh = pb_shift(nb);
+  std::vector<double> t((size_t)kMaxPb, 1.0);
   double m = 0.0;
   for (int i = 0; i < nb; ++i) {
-    const double e_hi = i == nb - 1 ? 4.0 * (double)nb * de_ev : ((double)i + 0.5) * de_ev;
-    const double nu = nsig[i] * std::sqrt(2.0 * e_hi * kEvToJ / mass);
-    m = std::max(m, nu);
+    m = std::max(m, row_nu(nsig, i, de_ev, mass));
+    if (i == nb - 1 || ((i + 1) >> sh) != (i >> sh))
+      t[(size_t)(i >> sh)] = std::min(1.0, (1.0 - std::exp(-m * dt)) * (1.0 + 1e-9));
   }
+  return t;
+}
+
+double nu_star(const std::vector<double>& nsig, double de_ev, double mass) {
+  double m = 0.0;
+  for (int i = 0; i < (int)nsig.size(); ++i) m = std::max(m, row_nu(nsig, i, de_ev, mass));
   return m;
 }
 
@@ -744,10 +776,12 @@ int enqueue_batch_step(edp_ctx* ctx, Group& G, const std::vector<int64_t>& s, in
     const int r = take_event_pair(ctx, e0, e1);
     if (r) return r;
   }
-  HIPCHK(launch_particles(G.roles_d + B.role_off[0], 0, B.parts[0], B.lds[0], ctx->poisson, dj, st, e0, e1));
+  HIPCHK(launch_particles(G.roles_d + B.role_off[0], 0, B.parts[0], B.lds[0], ctx->poisson, dj, ctx->pretest, st, e0,
+                          e1));
   if (e0) ctx->ev_pairs.emplace_back(e0, e1);
   if (any_ion)
-    HIPCHK(launch_particles(G.roles_d + B.role_off[1], 1, B.parts[1], B.lds[1], ctx->poisson, dj, st, nullptr, nullptr));
+    HIPCHK(launch_particles(G.roles_d + B.role_off[1], 1, B.parts[1], B.lds[1], ctx->poisson, dj, ctx->pretest, st,
+                            nullptr, nullptr));
   return EDP_OK;
 }
 
@@ -931,7 +965,7 @@ int run_small(edp_ctx* ctx, const std::vector<Case*>& cases, std::vector<int64_t
       r = upload_volt(c, c->step, c->step + roles[a].j, st);
     }
     if (r) break;
-    HIPCHK(launch_small(ctx->small_roles + lo, (int)(hi - lo), lds, ctx->poisson, ctx->sort_every, st));
+    HIPCHK(launch_small(ctx->small_roles + lo, (int)(hi - lo), lds, ctx->poisson, ctx->sort_every, ctx->pretest, st));
     for (size_t a = lo; a < hi && r == EDP_OK; ++a)
       for (Case* q : cases)
         if (q->d == roles[a].c) {
@@ -1292,6 +1326,8 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
     h.g2_lim_i = 2.0 * e_lim * kEvToJ / kMuArAr * (1.0 - 1e-12);
     const double amax = 12.2 * h.sigma_a;
     h.a2_i = amax * amax;
+    h.pb_shift = pb_shift(nb);
+    h.pb_n = ((nb - 1) >> h.pb_shift) + 1;
   }
   h.de_cs = ctx->de;
   h.thr_exc = ctx->thr_exc;
@@ -1345,6 +1381,10 @@ int edp_case_create(edp_ctx* ctx, const edp_case_desc* desc, void* dev_arena, in
   hipError_t e = hipSuccess;
   for (int t = 0; t < 7 && e == hipSuccess; ++t)
     e = hipMemcpyAsync(tabs[t], tsrc[t]->data(), (size_t)nb * 8, hipMemcpyHostToDevice, st);
+  const std::vector<double> pb[2] = {pbound_table(nsig_e, ctx->de, kEMass, h.dt_e),
+                                     pbound_table(nsig_i, ctx->de, kMuArAr, h.dt_i)};
+  for (int sp = 0; sp < 2 && e == hipSuccess; ++sp)
+    e = hipMemcpyAsync((void*)h.pbound[sp], pb[sp].data(), (size_t)kMaxPb * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync((void*)h.rden, rden.data(), (size_t)ng * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d, &h, sizeof(CaseDev), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -2021,6 +2061,10 @@ int edp_set_option(edp_ctx* ctx, int32_t key, int64_t value) {
     case EDP_OPT_PART_WG_PER_CU:
       if (value < 0 || value > 64) return fail(EDP_EINVAL, "workgroups per CU must be 0..64");
       ctx->part_wg_per_cu = (int)value;
+      break;
+    case EDP_OPT_PRETEST:
+      if (value < 0 || value > 2) return fail(EDP_EINVAL, "pre-test mode must be 0, 1 or 2");
+      ctx->pretest = (int)value;
       break;
     case EDP_OPT_PART_SKEW:
       if (value < -1 || value > 900) return fail(EDP_EINVAL, "workgroup share skew must be -1..900 (per mille)");

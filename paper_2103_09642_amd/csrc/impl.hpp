@@ -53,6 +53,7 @@ static_assert(kPartBlock % 256 == 0 && kPartBlock <= kMaxChunk, "particle workgr
 constexpr int kMaxApply = 1024;   // collision workgroups per case and application
 constexpr int kMaxPartWG = 8192;  // particle workgroups per case and species
 constexpr int kMaxNodes = 2048;                      // largest n_grid accepted
+constexpr int kMaxPb = 256;  // blocks of the collision pre-test's bound table
 constexpr int kVoltChunk = 1 << 16;  // steps of V(t) resident on the device
 
 // Flags (same values as EDP_* in edupic.h).
@@ -106,6 +107,12 @@ struct CaseDev {
   // 2 (v^2 + a2_i) > g2_lim_i (a2_i bounds the squared thermal target speed
   // the generator can give), i.e. beyond the energy range P* covers
   double p_bound_e, p_bound_i, v2_lim_e, g2_lim_i, a2_i;
+  // the same bound by energy: pbound[sp][b] bounds P over every table row
+  // up to the last of block b (rows r with r >> pb_shift <= b), a prefix
+  // maximum, so that the block of any upper bound of a particle's energy
+  // gives a bound of its P
+  const double* pbound[2];
+  int32_t pb_shift, pb_n;
   double kpois;       // dx*dx/eps0
   // surface processes, [0] powered electrode (x = 0), [1] grounded (x = L)
   double gamma_see[2];  // ion-induced secondary electron yield

@@ -842,7 +842,7 @@ template <int SP, bool SMALL, int NB>
 __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const double* sE, double* reg,
                                               const int64_t s, const int64_t n, const int64_t c_lo,
                                               const int64_t c_hi, const int cur, const int cur_o,
-                                              const Births<SMALL>& B) {
+                                              const Births<SMALL>& B, const int pretest) {
   const EDP_CONST CaseDev* __restrict__ C = KC(Cw);
   constexpr int kSeg = seg_len<SP>();
   constexpr int kPay = SP == 0 ? NB / kWave : 1;
@@ -852,6 +852,8 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   __shared__ int sTot[NB / kWave][kRec];
   // entries of the overflow list, next pass over it
   __shared__ int sOvf, sFin;
+  // the pre-test's bound of P by energy block (direct collision test)
+  __shared__ double sPB[kMaxPb];
   // lanes of a pass's ionizing colliders by rank (electrons)
   __shared__ int sIon[SP == 0 ? NB / kWave : 1][SP == 0 ? kWave : 1];
   const int ng = C->ng;
@@ -881,6 +883,26 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   }
   for (int b = threadIdx.x; b < n_hist; b += blockDim.x) sF[b] = 0;
   constexpr int kWaves = NB / kWave;
+  // candidate pre-test: R below a bound of P, or a speed beyond the bound's
+  // range.  The direct test's bound is P* (with its margin), or, when a
+  // wave's slots would give enough candidates by it, the
+  // bound by energy: the block of the table row of an upper bound of the
+  // particle's (relative) energy -- from g2u, a bound of its squared speed,
+  // times (1 + 1e-12) against the rounding of the exact test's own v^2 and
+  // energy -- in sPB.  The lookup costs every particle a few instructions
+  // and an LDS load, so it is taken when P* would give a wave more than a
+  // quarter round of candidates (measured: 2% slower on the large case with
+  // 8 per wave, 4-12% faster on the batched sets with 20-400).
+  const bool null_coll = (fl & kNullCollision) != 0;
+  const double p_null = SP == 0 ? C->p_null_e : C->p_null_i;
+  const double p_cand = null_coll ? p_null : (SP == 0 ? C->p_bound_e : C->p_bound_i);
+  const bool by_energy =
+      !null_coll && (pretest == 2 || (pretest == 0 && (double)(c_hi - c_lo) * kWave * p_cand > (double)(kWave / 4)));
+  if (by_energy) {
+    const int pb_n = C->pb_n;
+    const EDP_GLOBAL double* __restrict__ pbg = G(C->pbound[SP]);
+    for (int b = threadIdx.x; b < pb_n; b += blockDim.x) sPB[b] = pbg[b];
+  }
   if (threadIdx.x == 0) {
     sOvf = 0;
     sFin = 0;
@@ -916,17 +938,15 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
   const uint32_t st = (uint32_t)s;
   const double x_lo = C->x_lo, x_hi = C->x_hi, de_eepf = C->de_eepf, de_ifed = C->de_ifed;
   const double sa = C->sigma_a;
-  const bool null_coll = (fl & kNullCollision) != 0;
   // surface processes of this species' electrode hits
   const bool surf_on = SP == 0 ? C->refl_on != 0 : C->see_on != 0;
   const double p_surf0 = SP == 0 ? C->eta_refl[0] : C->gamma_see[0];
   const double p_surf1 = SP == 0 ? C->eta_refl[1] : C->gamma_see[1];
   const double n_gas = C->n_gas;
   const double nu_star = SP == 0 ? C->nu_star_e : C->nu_star_i;
-  const double p_null = SP == 0 ? C->p_null_e : C->p_null_i;
-  // candidate pre-test: R below this bound, or a speed beyond the bound's range
-  const double p_cand = null_coll ? p_null : (SP == 0 ? C->p_bound_e : C->p_bound_i);
   const double v2_cand = null_coll ? __builtin_huge_val() : (SP == 0 ? C->v2_lim_e : C->g2_lim_i);
+  const double rows_per_g2 = 0.5 * (SP == 0 ? kEMass : kMuArAr) / kEvToJ / C->de_cs * (1.0 + 1e-12);
+  const int pb_shift = C->pb_shift;
   const double a2_i = C->a2_i;
   const uint32_t r_tag = SP == 0 ? tag(0, 0, 0) : tag(1, 0, 2);
   const int w = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
@@ -1216,6 +1236,17 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
       const double e_here = sE[cell] * w_lo + sE[cell + 1] * w_hi;
       vxn = SP == 0 ? vx - e_here * kick : vx + e_here * kick;
       xn = x + vxn * dt;
+      // the pre-test's bound of P for this particle by energy, looked up now
+      // so that the LDS load is in flight during the wall test, the deposit
+      // and the Philox call (a reflection below keeps |v|)
+      double pc = p_cand, g2u = 0.0;
+      if (by_energy) {
+        v2 = SP == 0 ? vxn * vxn + vp2 : vxn * vxn + vy * vy + vz * vz;
+        g2u = SP == 0 ? v2 : 2.0 * (v2 + a2_i);
+        double rows = g2u * rows_per_g2 + 0.5;
+        rows = rows < (double)(nbins - 1) ? rows : (double)(nbins - 1);
+        pc = sPB[(int)rows >> pb_shift];
+      }
       if (pdiag) {
         // measurement at integer time: old position, mean of the half-step
         // velocities; the ionization rate as the expected n sigma_ion |v|
@@ -1304,8 +1335,11 @@ __device__ __forceinline__ SpTot species_pass(CaseDev* __restrict__ Cw, const do
         lds_add(&sH[q + 1], r);
         double r_coll, r_proc;
         uniform2(seed, uid, st, r_tag, r_coll, r_proc);
-        v2 = SP == 0 ? vxn * vxn + vp2 : vxn * vxn + vy * vy + vz * vz;
-        cand = r_coll < p_cand || (SP == 0 ? v2 : 2.0 * (v2 + a2_i)) > v2_cand;
+        if (!by_energy) {
+          v2 = SP == 0 ? vxn * vxn + vp2 : vxn * vxn + vy * vy + vz * vz;
+          g2u = SP == 0 ? v2 : 2.0 * (v2 + a2_i);
+        }
+        cand = r_coll < pc || g2u > v2_cand;
       }
     }
     if (i < n && x == x) {
@@ -1404,7 +1438,7 @@ __device__ __forceinline__ int64_t step_slots(const EDP_CONST CaseDev* __restric
 // adds its totals to its shard of the case's counters.
 template <int SP, int MODE>
 __global__ void __launch_bounds__(kPartBlock) __attribute__((amdgpu_waves_per_eu(4)))
-k_particles(const BlockRole* __restrict__ R, int dstep) {
+k_particles(const BlockRole* __restrict__ R, int dstep, int pretest) {
   extern __shared__ double psm[];
   const EDP_CONST BlockRole* r = KC(R) + blockIdx.x;
   CaseDev* Cw = r->c;
@@ -1437,7 +1471,7 @@ k_particles(const BlockRole* __restrict__ R, int dstep) {
   B.lds = nullptr;
   B.glob[0] = &Cw->born[0][s % 3];
   B.glob[1] = &Cw->born[1][s % 3];
-  const SpTot T = species_pass<SP, false, kPartBlock>(Cw, sE, reg, s, n, c_lo, c_hi, cur, C->cur[1 - SP], B);
+  const SpTot T = species_pass<SP, false, kPartBlock>(Cw, sE, reg, s, n, c_lo, c_hi, cur, C->cur[1 - SP], B, pretest);
   if (threadIdx.x == 0) {
     int64_t* sh = C->shard + ((int64_t)SP * kShards + j % kShards) * kRec;
 #pragma unroll
@@ -1614,7 +1648,7 @@ __device__ __forceinline__ int64_t small_sort(CaseDev* __restrict__ Cw, int sp, 
 // phase's histograms (also the field solve's scratch) and the sort's
 // counters.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ R, int sort_every) {
+__global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ R, int sort_every, int pretest) {
   extern __shared__ double ssm2[];
   __shared__ int64_t sState[5];  // step, n_e, n_i, cur_e, cur_i
   __shared__ int sBirth[2];
@@ -1659,9 +1693,9 @@ __global__ void __launch_bounds__(kBlock) k_small(const BlockRole* __restrict__ 
     B.lds = sBirth;
     B.glob[0] = B.glob[1] = nullptr;
     const int64_t nch_e = (n_e + kChunk - 1) / kChunk, nch_i = (n_i + kChunk - 1) / kChunk;
-    const SpTot te = species_pass<0, true, kBlock>(Cw, sE, reg, s, n_e, 0, nch_e, cur_e, cur_i, B);
+    const SpTot te = species_pass<0, true, kBlock>(Cw, sE, reg, s, n_e, 0, nch_e, cur_e, cur_i, B, pretest);
     SpTot ti{};
-    if (ion_step) ti = species_pass<1, true, kBlock>(Cw, sE, reg, s, n_i, 0, nch_i, cur_i, cur_e, B);
+    if (ion_step) ti = species_pass<1, true, kBlock>(Cw, sE, reg, s, n_i, 0, nch_i, cur_i, cur_e, B, pretest);
     if (threadIdx.x == 0) {
       int64_t* ctr = Cw->ctr;
       ctr[kCollE] += te.v[kRecColl];
@@ -1948,7 +1982,7 @@ __global__ void k_zero(int64_t* __restrict__ p, int64_t n) {
 // colliders and the field scan's scratch.
 size_t particle_static_lds(int sp) {
   const size_t waves = kPartBlock / kWave;
-  return sp == 0 ? waves * kSegE * (4 + 8 + 8) + 2048 : waves * kSegI * 4 + 2048;
+  return (sp == 0 ? waves * kSegE * (4 + 8 + 8) : waves * kSegI * 4) + kMaxPb * 8 + 2048;
 }
 
 size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp) {
@@ -1967,21 +2001,22 @@ size_t particle_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed, int sp
 // ev0/ev1 the launch records its own start and end (the dispatch's
 // timestamps, not those of separate event packets around it).
 template <int SP, int MODE>
-void launch_particles_t(const BlockRole* roles, int blocks, size_t lds, int dstep, hipStream_t st, hipEvent_t ev0,
+void launch_particles_t(const BlockRole* roles, int blocks, size_t lds, int dstep, int pretest, hipStream_t st, hipEvent_t ev0,
                         hipEvent_t ev1) {
   if (ev0)
-    hipExtLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kPartBlock), lds, st, ev0, ev1, 0, roles, dstep);
+    hipExtLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kPartBlock), lds, st, ev0, ev1, 0, roles, dstep,
+                          pretest);
   else
-    hipLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kPartBlock), lds, st, roles, dstep);
+    hipLaunchKernelGGL((k_particles<SP, MODE>), dim3(blocks), dim3(kPartBlock), lds, st, roles, dstep, pretest);
 }
 
-hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, int mode, int dstep,
+hipError_t launch_particles(const BlockRole* roles, int sp, int blocks, size_t lds, int mode, int dstep, int pretest,
                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   switch (sp * 2 + (mode == 1)) {
-    case 0: launch_particles_t<0, 0>(roles, blocks, lds, dstep, st, ev0, ev1); break;
-    case 1: launch_particles_t<0, 1>(roles, blocks, lds, dstep, st, ev0, ev1); break;
-    case 2: launch_particles_t<1, 0>(roles, blocks, lds, dstep, st, ev0, ev1); break;
-    default: launch_particles_t<1, 1>(roles, blocks, lds, dstep, st, ev0, ev1); break;
+    case 0: launch_particles_t<0, 0>(roles, blocks, lds, dstep, pretest, st, ev0, ev1); break;
+    case 1: launch_particles_t<0, 1>(roles, blocks, lds, dstep, pretest, st, ev0, ev1); break;
+    case 2: launch_particles_t<1, 0>(roles, blocks, lds, dstep, pretest, st, ev0, ev1); break;
+    default: launch_particles_t<1, 1>(roles, blocks, lds, dstep, pretest, st, ev0, ev1); break;
   }
   return hipGetLastError();
 }
@@ -2023,16 +2058,17 @@ size_t small_lds_bytes(int ng, uint32_t flags, int n_eepf, int n_ifed) {
 
 size_t small_static_lds() {
   const size_t waves = kBlock / kWave;
-  return waves * kSegE * (4 + 8 + 8) + waves * kSegI * 4 + 6144;
+  return waves * kSegE * (4 + 8 + 8) + waves * kSegI * 4 + 2 * kMaxPb * 8 + 6144;
 }
 
 // One window of the small cases: workgroup b runs the case of roles[b] for
 // roles[b].j steps.
-hipError_t launch_small(const BlockRole* roles, int ncase, size_t lds, int mode, int sort_every, hipStream_t st) {
+hipError_t launch_small(const BlockRole* roles, int ncase, size_t lds, int mode, int sort_every, int pretest,
+                        hipStream_t st) {
   if (mode == 1)
-    hipLaunchKernelGGL(k_small<1>, dim3(ncase), dim3(kBlock), lds, st, roles, sort_every);
+    hipLaunchKernelGGL(k_small<1>, dim3(ncase), dim3(kBlock), lds, st, roles, sort_every, pretest);
   else
-    hipLaunchKernelGGL(k_small<0>, dim3(ncase), dim3(kBlock), lds, st, roles, sort_every);
+    hipLaunchKernelGGL(k_small<0>, dim3(ncase), dim3(kBlock), lds, st, roles, sort_every, pretest);
   return hipGetLastError();
 }
 

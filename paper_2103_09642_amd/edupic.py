@@ -26,6 +26,7 @@ OPT_POISSON = 8
 OPT_PART_WG_PER_CU = 9
 OPT_GROUPS = 11
 OPT_PART_SKEW = 13
+OPT_PRETEST = 14
 OPT_SMALL_MAX = 12
 POISSON_FLUX, POISSON_THOMAS = 0, 1
 MODE_PLAIN, MODE_GRAPH = 0, 1

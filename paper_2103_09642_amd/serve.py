@@ -182,13 +182,17 @@ class Server:
             (self.failed if req.failed else self.done).append(req)
         return finished
 
-    def run(self, requests: List[Request], virtual: bool = False, max_wall: float = 0.0) -> List[Request]:
+    def run(self, requests: List[Request], virtual: bool = False, max_wall: float = 0.0,
+            progress: float = 0.0) -> List[Request]:
         """Serve a stream.  Wall clock: requests become visible at their
         arrival time; with max_wall the loop stops after that many seconds,
-        leaving the rest unserved.  Virtual clock (tests): arrival times are
-        iteration numbers, so admission is deterministic."""
+        leaving the rest unserved; with progress a status line goes to stderr
+        after an iteration at most every that many seconds.  Virtual clock
+        (tests): arrival times are iteration numbers, so admission is
+        deterministic."""
         pending = sorted(requests, key=lambda r: r.t_arrival)
         t0 = time.perf_counter()
+        last = 0.0
         if not virtual:
             self.clock = lambda: time.perf_counter() - t0  # same origin as the arrival times
         it = 0
@@ -206,6 +210,13 @@ class Server:
                 continue
             self.iterate(now)
             it += 1
+            if progress and not virtual:
+                t = time.perf_counter() - t0
+                if t - last >= progress:
+                    last = t
+                    print(f"[serve] {t:.0f} s: {len(requests) - len(pending)} arrived, {len(self.resident)} resident, "
+                          f"{len(self.waiting)} waiting, {len(self.done)} done, {len(self.failed)} failed, "
+                          f"{self.psteps / t:.3g} particle-steps/s served", file=sys.stderr, flush=True)
         self.unserved = pending + self.waiting + [e[0] for e in self.resident]
         return self.done
 
@@ -232,6 +243,8 @@ def main(argv=None):
     ap.add_argument("--groups", type=int, default=0, help="lockstep groups (0: the library's default)")
     ap.add_argument("--small-max", type=int, default=0,
                     help="cases up to this many slots per species run in the persistent small-case kernel")
+    ap.add_argument("--progress", type=float, default=30.0,
+                    help="seconds between status lines on stderr (0: none)")
     ap.add_argument("--max-wall", type=float, default=0.0,
                     help="stop serving after this many seconds (0: until every request is done)")
     args = ap.parse_args(argv)
@@ -253,7 +266,7 @@ def main(argv=None):
             for i, it in enumerate(stream)]
     srv = Server(ctx, budget, window=args.window)
     t0 = time.perf_counter()
-    done = srv.run(reqs, max_wall=args.max_wall)
+    done = srv.run(reqs, max_wall=args.max_wall, progress=args.progress)
     wall = time.perf_counter() - t0
     offered = sum(offered_psteps(r) for r in reqs) / args.duration
     out = {"requests": len(reqs), "completed": len(done), "failed": len(srv.failed),

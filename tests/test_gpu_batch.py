@@ -97,7 +97,9 @@ def test_chunk_shares_change_nothing(ctx):
     """A case with more chunks than the chip has resident particle
     workgroups (so its workgroups span several dispatch layers): its result
     is bit-identical whatever weighting of the workgroups' chunk shares
-    (EDP_OPT_PART_SKEW) and workgroups per CU the launches use."""
+    (EDP_OPT_PART_SKEW), workgroups per CU and collision pre-test bound
+    (EDP_OPT_PRETEST: P* over the table, or by energy block) the launches
+    use."""
     from paper_2103_09642_amd import edupic
     say("test_chunk_shares_change_nothing")
     n = 400_000
@@ -106,15 +108,17 @@ def test_chunk_shares_change_nothing(ctx):
     st = random_state(n, n, c["gap_m"], seed=31, te_ev=3.0, hot_frac=0.2, hot_ev=80.0)
     ctx.set_option(edupic.OPT_SORT_EVERY, 10)
     res = []
-    for skew, wg in ((0, 0), (-1, 0), (900, 0), (450, 3)):
+    for skew, wg, pre in ((0, 0, 1), (-1, 0, 0), (900, 0, 2), (450, 3, 2)):
         ctx.set_option(edupic.OPT_PART_SKEW, skew)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, wg)
+        ctx.set_option(edupic.OPT_PRETEST, pre)
         g = _make(ctx, c, st, 7)
         g.advance_steps(45)
         res.append(_result(g))
         g.destroy()
     ctx.set_option(edupic.OPT_PART_SKEW, -1)
     ctx.set_option(edupic.OPT_PART_WG_PER_CU, 0)
+    ctx.set_option(edupic.OPT_PRETEST, 0)
     ctx.set_option(edupic.OPT_SORT_EVERY, 100)
     for k in range(1, len(res)):
         _same(res[0], res[k], f"schedule {k}")
@@ -122,6 +126,9 @@ def test_chunk_shares_change_nothing(ctx):
     for bad in (-2, 901):
         with pytest.raises(edupic.EdpError):
             ctx.set_option(edupic.OPT_PART_SKEW, bad)
+    for bad in (-1, 3):
+        with pytest.raises(edupic.EdpError):
+            ctx.set_option(edupic.OPT_PRETEST, bad)
 
 
 def test_batch_matches_oracle(ctx, xs_default, orc):

@@ -70,8 +70,10 @@ def test_small_equals_lockstep(ctx, small, flags):
     c = _hot_case(flags=flags, gamma_see=(0.2, 0.1), eta_refl=(0.2, 0.3), see_te_ev=2.0, n_grid=300)
     st = _state(c, 81)
     res = []
-    for lim in (0, 10**9):
+    # the small-case kernel with the pre-test's bound by energy block forced
+    for lim, pre in ((0, 0), (10**9, 2)):
         small(lim)
+        ctx.set_option(edupic.OPT_PRETEST, pre)
         g = ctx.create_case(c)
         g.set_state(0, st["e"], 0)
         g.set_state(1, st["i"], 0)
@@ -82,6 +84,7 @@ def test_small_equals_lockstep(ctx, small, flags):
             extra = (g.density(), g.eepf()[1], g.currents(), g.mean_energy(), g.xt("ne"), g.ifed()[2])
         res.append((snap, extra))
         g.destroy()
+    ctx.set_option(edupic.OPT_PRETEST, 0)
     _same(res[0][0], res[1][0], "small vs lockstep")
     assert res[0][0][3]["coll_e"] > 1000 and res[0][0][3]["ioniz"] > 10
     for a, b in zip(res[0][1], res[1][1]):
