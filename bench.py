@@ -113,6 +113,8 @@ def main():
                     help="profiling aid: time this many PIC steps instead of --steps benchmark steps")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="profiling aid: first copy a device buffer of this size (counter calibration)")
+    ap.add_argument("--diag", action="store_true",
+                    help="large: time-averaged density and EEPF on, read every 10 RF cycles (as the plain line)")
     ap.add_argument("--null-collision", action="store_true",
                     help="select colliding particles by the null-collision method")
     ap.add_argument("--sequential", action="store_true",
@@ -493,7 +495,7 @@ def plain_large(args):
 
 def bench_large(args):
     ctx, g, case, tuned, wall, pe, pi, c1 = run_large(args, args.steps if not args.pic_steps else 0,
-                                                       args.warmup, False, args)
+                                                       args.warmup, args.diag, args)
     if args.pic_steps:
         wall, pe, pi, c1 = timed(ctx, [g], lambda: g.advance_steps(args.pic_steps))
     print(f"timed region: {wall:.3f} s, {pe} electron + {pi} ion particle-steps", file=sys.stderr, flush=True)
@@ -510,6 +512,7 @@ def bench_large(args):
     config = {"workload": "plain large single case: 1000 nodes, 8000 steps/RF cycle, 2e6+2e6 seeded uniform "
                           "1e15 m^-3, 10 Pa Ar, 250 V 13.56 MHz; step = 1 RF cycle",
               "collision_selection": "null collision" if args.null_collision else "direct",
+              "diagnostics": "time-averaged density and EEPF, read every 10 RF cycles" if args.diag else "none",
               **schedule_config(args, tuned),
               "electrons_live_end": c1[0]["n_e"], "ions_live_end": c1[0]["n_i"],
               "electron_psteps": pe, "ion_psteps": pi}
