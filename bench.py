@@ -49,6 +49,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particles_electrons_traffic.jso
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2103_09642_amd", "csrc", "kernels.hip")
 HF_STEPS = 2000  # one 27.12 MHz period of the dual-frequency cases
 MAX_CPU_WORKERS = 16  # the host-core share of one GPU
+# a batch of cases also tries sorting every 400 steps (its windows are then
+# longer than a graph holds, so it runs plain launches): the dual-frequency
+# set ran 1% faster there than at 200
+BATCH_SORT_EXTRA = 400
 
 
 def measured_traffic(electrons_per_launch, workload):
@@ -85,7 +89,10 @@ def main():
                     help="timed benchmark steps (dual32: 27.12 MHz periods; large, batch64, small: RF cycles)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed benchmark steps")
     ap.add_argument("--workload", choices=["dual32", "batch64", "large", "small", "small256"], default="dual32")
-    ap.add_argument("--mode", type=int, default=1, help="launch mode of the timed region: 0 plain, 1 graph")
+    ap.add_argument("--mode", type=int, default=-1, choices=(-1, 0, 1),
+                    help="launch mode of the timed region: 0 plain, 1 graph windows; -1 (default) the "
+                         "autotuner's choice for a batch of cases (several groups' graphs can overlap worse "
+                         "than their plain launches), graph windows otherwise")
     ap.add_argument("--plain-steps", type=int, default=10,
                     help="dual32: timed RF cycles of the plain large case reported beside it (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=0,
@@ -120,6 +127,11 @@ def main():
     ap.add_argument("--sequential", action="store_true",
                     help="batched workloads: advance the cases one after another instead of as one batch")
     args = ap.parse_args()
+    # the mode is tuned with the groups of a batch when the schedule is tuned
+    args.tune_mode = args.mode == -1 and args.workload in ("dual32", "batch64") and not (
+        args.sort_every and args.wg_per_cu >= 0 and args.groups)
+    if args.mode == -1:
+        args.mode = 1
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): independent cases shard "
               "across GPUs without communication, and one case's particles would need an int64 "
@@ -180,6 +192,7 @@ def choose_schedule(args, ctx, descs, warm):
     from paper_2103_09642_amd import edupic, tune
     if len(descs) == 1 and not args.groups:
         args.groups = tune.DEFAULTS["groups"]  # no effect on a single case
+    mode_candidates = (1, 0) if getattr(args, "tune_mode", False) else ()
     if args.sort_every and args.wg_per_cu >= 0 and args.groups:
         ctx.set_option(edupic.OPT_SORT_EVERY, args.sort_every)
         ctx.set_option(edupic.OPT_PART_WG_PER_CU, args.wg_per_cu)
@@ -191,22 +204,27 @@ def choose_schedule(args, ctx, descs, warm):
         warm(copies)
         choice, trials = tune.tune_schedule(ctx, copies,
                                             candidates=(args.sort_every,) if args.sort_every else
-                                            tune.DEFAULT_CANDIDATES,
+                                            tune.DEFAULT_CANDIDATES + ((BATCH_SORT_EXTRA,) if len(descs) > 1
+                                                                       else ()),
                                             wg_candidates=(args.wg_per_cu,) if args.wg_per_cu >= 0 else
                                             tune.DEFAULT_WG_CANDIDATES,
                                             restore_state=True,
                                             group_candidates=(args.groups,) if args.groups else
-                                            tune.DEFAULT_GROUP_CANDIDATES)
+                                            tune.DEFAULT_GROUP_CANDIDATES,
+                                            mode_candidates=mode_candidates)
     finally:
         for c in copies:
             c.destroy()
     args.sort_every, args.wg_per_cu = choice["sort_every"], choice["part_wg_per_cu"]
     args.groups = choice["groups"]
+    if "mode" in choice:
+        args.mode = choice["mode"]
     return {"seconds": round(time.perf_counter() - t0, 2),
             "on": "copies of the workload's cases advanced to the timed window's midpoint; "
                   "every trial starts from that state",
-            "trials": [[t.interval, t.wg_per_cu, t.groups, round(t.rate, 1)] for t in trials],
-            "trial_fields": ["sort_every", "wg_per_cu", "groups", "particle-steps/s"]}
+            "trials": [[t.interval, t.wg_per_cu, t.groups, t.mode, round(t.rate, 1)] for t in trials],
+            "trial_fields": ["sort_every", "wg_per_cu", "groups", "mode (1 graph, 0 plain, -1 as set)",
+                             "particle-steps/s"]}
 
 
 # ---------------------------------------------------------------------------

@@ -1,6 +1,7 @@
 """Autotuner for the batch runtime's schedule: the compaction + cell-sort
 interval, the particle workgroups per CU and, for a batch of several cases,
-the number of lockstep groups it runs as.
+the number of lockstep groups it runs as (and, when asked, the launch
+mode: graph windows or plain launches).
 
 * The sort every K steps trades its own cost (one pass over every particle
   array of the cases due) against the particle kernel's locality: between
@@ -72,6 +73,7 @@ class Trial:
     particle_steps: int
     wg_per_cu: int = 0   # the particle workgroups per CU of the trial
     groups: int = 2      # the lockstep groups the trial ran as (set by the tuner)
+    mode: int = -1       # the launch mode of the trial (1 graph, 0 plain; -1 as the context had it)
 
     @property
     def rate(self) -> float:
@@ -173,12 +175,15 @@ def _check(candidates, lo, what):
         raise ValueError(f"{what} candidates must be >= {lo}")
 
 
-def _apply(ctx, sort_every: int, wg: int, groups: int):
+def _apply(ctx, sort_every: int, wg: int, groups: int, mode: Optional[int] = None):
     from . import edupic
     ctx.set_option(edupic.OPT_SORT_EVERY, sort_every)
     ctx.set_option(edupic.OPT_PART_WG_PER_CU, wg)
     ctx.set_option(edupic.OPT_GROUPS, groups)
     _chosen[id(ctx)] = {"sort_every": sort_every, "part_wg_per_cu": wg, "groups": groups}
+    if mode is not None:
+        ctx.set_option(edupic.OPT_MODE, mode)
+        _chosen[id(ctx)]["mode"] = mode
 
 
 def snapshot(cases: Sequence) -> List:
@@ -196,7 +201,8 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
                   wg_candidates: Sequence[int] = DEFAULT_WG_CANDIDATES, cache_path: Optional[str] = None,
                   measure_fn: Optional[Callable[..., Trial]] = None,
                   restore_state: bool = False,
-                  group_candidates: Sequence[int] = DEFAULT_GROUP_CANDIDATES) -> Tuple[Dict[str, int], List[Trial]]:
+                  group_candidates: Sequence[int] = DEFAULT_GROUP_CANDIDATES,
+                  mode_candidates: Sequence[int] = ()) -> Tuple[Dict[str, int], List[Trial]]:
     """Pick the fastest sort interval, then the fastest particle workgroups
     per CU at that interval, then (a batch of several cases) the fastest
     lockstep groups, and set them on the context.  Returns ({"sort_every",
@@ -204,20 +210,26 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
     Empty `wg_candidates` leave the workgroups at all that fit, empty
     `group_candidates` (or a batch with fewer cases than two of them) the
     groups at 2.  Every trial
-    before the groups stage runs with 2 groups.  With restore_state every
-    trial starts from the cases' state at the call, and the cases end in
-    it."""
+    before the groups stage runs with 2 groups.  With `mode_candidates`
+    (launch modes: 1 graph windows, 0 plain launches) the last stage tries
+    every group count in every mode -- several groups' graphs can overlap
+    worse than their plain launches -- and the choice gains a "mode".  With
+    restore_state every trial starts from the cases' state at the call, and
+    the cases end in it."""
     from . import edupic
     _check(candidates, 1, "sort interval")
     if wg_candidates:
         _check(wg_candidates, 0, "workgroup")
     if group_candidates and any(int(g) not in (1, 2, 3, 4) for g in group_candidates):
         raise ValueError("group candidates must be 1..4")
+    if any(int(m) not in (0, 1) for m in mode_candidates):
+        raise ValueError("mode candidates must be 0 or 1")
     # more groups than cases run as one group per case: those candidates are
     # the same as the case count
     gs = sorted({min(int(g), len(cases)) for g in group_candidates})
     gs = gs if len(gs) > 1 else []
-    key = batch_key(cases) + (":wg" if wg_candidates else "") + (":groups" if gs else "")
+    ms = [int(m) for m in mode_candidates]
+    key = batch_key(cases) + (":wg" if wg_candidates else "") + (":groups" if gs else "") + (":mode" if ms else "")
     cache: Dict[str, Dict] = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -225,7 +237,7 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
         if key in cache:
             hit = cache[key]
             _apply(ctx, int(hit["sort_every"]), int(hit.get("part_wg_per_cu", 0)),
-                   int(hit.get("groups", DEFAULTS["groups"])))
+                   int(hit.get("groups", DEFAULTS["groups"])), hit.get("mode"))
             return dict(_chosen[id(ctx)]), []
     ctx.set_option(edupic.OPT_GROUPS, DEFAULTS["groups"])
     steps, base = trial_steps(cases, candidates)
@@ -269,7 +281,24 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
     # as one group per case)
     trials = [replace(t, groups=min(DEFAULTS["groups"], len(cases))) for t in trials]
     best_g = DEFAULTS["groups"]
-    if gs:
+    best_m = None
+    if ms:
+        # every group count (the default alone for a single case) in every mode
+        combos = [(g, m) for g in (gs or [best_g]) for m in ms]
+
+        def gm_trial(i):
+            g, m = combos[i]
+            ctx.set_option(edupic.OPT_GROUPS, g)
+            ctx.set_option(edupic.OPT_MODE, m)
+            t = run(ctx, cases, best_k, steps, min(base[best_k], MAX_TRIAL_STEPS), best_w)
+            return replace(t, groups=min(g, len(cases)), mode=m)
+        gt = _mirrored(list(range(len(combos))), gm_trial)
+        top = max(t.rate for t in gt)
+        near = [i for i, t in enumerate(gt) if t.rate >= top / (1.0 + MARGIN)]
+        # a tie goes to the default groups, then to graph windows
+        best_g, best_m = combos[min(near, key=lambda i: (_dist_groups(combos[i][0]), -combos[i][1]))]
+        trials += gt
+    elif gs:
         def group_trial(g):
             ctx.set_option(edupic.OPT_GROUPS, g)
             return replace(run(ctx, cases, best_k, steps, min(base[best_k], MAX_TRIAL_STEPS), best_w), groups=g)
@@ -278,10 +307,12 @@ def tune_schedule(ctx, cases: Sequence, candidates: Sequence[int] = DEFAULT_CAND
         trials += gt
     if snap is not None:
         restore(cases, snap)
-    _apply(ctx, best_k, best_w, best_g)
+    _apply(ctx, best_k, best_w, best_g, best_m)
     if cache_path:
         cache[key] = {"sort_every": best_k, "part_wg_per_cu": best_w, "groups": best_g,
                       "trials": [dict(asdict(t), rate=t.rate) for t in trials]}
+        if best_m is not None:
+            cache[key]["mode"] = best_m
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:
             json.dump(cache, f, indent=1)

@@ -216,3 +216,36 @@ def test_groups_are_tuned_last_for_a_batch_of_cases(tmp_path):
     assert [t.groups for t in trials] == [1] * 4
     with pytest.raises(ValueError):
         tune.tune_schedule(FakeCtx(), cases, group_candidates=(2, 5), measure_fn=run)
+
+
+def test_modes_are_tuned_with_the_groups():
+    """With mode candidates the last stage tries every group count in both
+    launch modes (graph windows and plain launches) and sets the fastest
+    pair; a tie goes to the default groups and then to graph windows."""
+    calls = []
+
+    def run(ctx, cases, k, steps, warm, wg=0):
+        g, m = ctx.options[edupic.OPT_GROUPS], ctx.options.get(edupic.OPT_MODE, 1)
+        calls.append((g, m))
+        # plain launches overlap better at 4 groups, graphs win below
+        rate = {(2, 1): 1.00, (2, 0): 0.99, (3, 1): 1.02, (3, 0): 1.01, (4, 1): 1.01, (4, 0): 1.06}[(g, m)]
+        return tune.Trial(k, steps, steps * 1e-6 / rate, steps, wg)
+    ctx = FakeCtx()
+    cases = [FakeCase(300_000, 1000, 20)] * 6
+    choice, trials = tune.tune_schedule(ctx, cases, candidates=(100,), wg_candidates=(), measure_fn=run,
+                                        mode_candidates=(1, 0))
+    assert choice == {"sort_every": 100, "part_wg_per_cu": 0, "groups": 4, "mode": 0}
+    assert ctx.options[edupic.OPT_MODE] == 0 and ctx.options[edupic.OPT_GROUPS] == 4
+    assert [(t.groups, t.mode) for t in trials[-6:]] == [(2, 1), (2, 0), (3, 1), (3, 0), (4, 1), (4, 0)]
+    # a tie keeps the default groups in graph windows
+    def flat(ctx, cases, k, steps, warm, wg=0):
+        return tune.Trial(k, steps, steps * 1e-6, steps, wg)
+    choice, _ = tune.tune_schedule(FakeCtx(), cases, candidates=(100,), wg_candidates=(), measure_fn=flat,
+                                   mode_candidates=(1, 0))
+    assert choice["groups"] == 2 and choice["mode"] == 1
+    # a single case: the modes alone
+    choice, trials = tune.tune_schedule(FakeCtx(), cases[:1], candidates=(100,), wg_candidates=(), measure_fn=flat,
+                                        mode_candidates=(1, 0))
+    assert "mode" in choice and [t.mode for t in trials[-2:]] == [1, 0]
+    with pytest.raises(ValueError):
+        tune.tune_schedule(FakeCtx(), cases, mode_candidates=(2,), measure_fn=flat)
