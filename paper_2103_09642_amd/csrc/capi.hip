@@ -1446,7 +1446,7 @@ int edp_case_resize(edp_ctx* ctx, edp_case id, int64_t cap_e, int64_t cap_i, voi
       HIPCHK(hipMemcpyAsync(na + Ln.off_vp2[0], c->arena + Lo.off_vp2[cur], n * 4, hipMemcpyDeviceToDevice, st));
   }
   // tables, V(t), deposit rings, fields and every diagnostic: the same
-  // layout after the particle and queue regions
+  // layout after the particle arrays and candidate lists
   const size_t tail = Lo.total - Lo.off_tab[0];
   if (tail != Ln.total - Ln.off_tab[0]) return fail(EDP_EHIP, "internal: layouts differ beyond the particles");
   HIPCHK(hipMemcpyAsync(na + Ln.off_tab[0], c->arena + Lo.off_tab[0], tail, hipMemcpyDeviceToDevice, st));

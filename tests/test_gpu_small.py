@@ -93,8 +93,9 @@ def test_small_equals_lockstep(ctx, small, flags):
 
 
 def test_switching_paths_and_mixed_batch(ctx, small):
-    """A case that switches lockstep -> small -> lockstep (a collision queue
-    pending at each switch) ends where a lockstep-only run ends, and a batch
+    """A case that switches lockstep -> small -> lockstep (the slot counts
+    and birth counters handed over at each switch) ends where a
+    lockstep-only run ends, and a batch
     mixing small cases (on their own stream) with a large lockstep case
     gives every case the bits it gets alone."""
     say("test_switching_paths_and_mixed_batch")
