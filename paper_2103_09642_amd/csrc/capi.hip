@@ -634,7 +634,8 @@ int sort_blocks(const edp_ctx* ctx, const Case* c, int sp) { return std::max(1, 
 // count is still covered: the kernels split the live chunks over whatever
 // workgroups a case has).  The table is read by
 // kernels still in flight, so the stream is drained before it changes;
-// grids are rebuilt only when a case's estimate has moved by a quarter.
+// grids are rebuilt only when a case's share has moved by a quarter or the
+// shares by a sixteenth of the workgroups in all.
 int set_batch(edp_ctx* ctx, Group& G, const std::vector<Case*>& cs) {
   Batch& B = G.batch;
   const size_t nc = cs.size();
