@@ -200,6 +200,13 @@ def choose_schedule(args, ctx, descs, warm):
         return None
     t0 = time.perf_counter()
     copies = [ctx.create_case(d) for d in descs]
+
+    def traced_measure(*a, **kw):
+        # one line per trial on stderr, so that a long tuning stage shows progress
+        t = tune.measure(*a, **kw)
+        print(f"tuning trial: sort every {t.interval}, {t.wg_per_cu} workgroups per CU: {t.rate:.4g} "
+              f"particle-steps/s", file=sys.stderr, flush=True)
+        return t
     try:
         warm(copies)
         choice, trials = tune.tune_schedule(ctx, copies,
@@ -211,7 +218,7 @@ def choose_schedule(args, ctx, descs, warm):
                                             restore_state=True,
                                             group_candidates=(args.groups,) if args.groups else
                                             tune.DEFAULT_GROUP_CANDIDATES,
-                                            mode_candidates=mode_candidates)
+                                            mode_candidates=mode_candidates, measure_fn=traced_measure)
     finally:
         for c in copies:
             c.destroy()
